@@ -1,0 +1,358 @@
+"""ctypes wrapper over the CPU oracle (test infrastructure only).
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
+import this module.  The product path never does.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from fractions import Fraction
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+
+class Graph(C.Structure):
+    _fields_ = [("n", C.c_int64), ("m", C.c_int64), ("off", C.POINTER(C.c_int64)),
+                ("nbr", C.POINTER(C.c_int32)), ("esrc", C.POINTER(C.c_int32)),
+                ("edst", C.POINTER(C.c_int32)), ("arow", C.POINTER(C.c_int32)),
+                ("perm", C.POINTER(C.c_int32))]
+
+
+class Plan(C.Structure):
+    _fields_ = [("k", C.c_int32), ("induced", C.c_int32), ("oriented", C.c_int32), ("aut", C.c_int32),
+                ("order", C.c_int32 * 8), ("connect", C.c_uint8 * 8), ("disconnect", C.c_uint8 * 8),
+                ("upper", C.c_uint8 * 8), ("lower", C.c_uint8 * 8)]
+
+
+class Rec(C.Structure):
+    _fields_ = [("s", C.c_uint64), ("v", C.c_int32 * 8), ("size", C.c_uint64 * 8), ("k", C.c_int32),
+                ("hit", C.c_int32), ("fail_step", C.c_int32), ("overflow", C.c_int32),
+                ("alpha_lo", C.c_uint64), ("alpha_hi", C.c_uint64), ("bytes", C.c_uint64)]
+
+    @property
+    def alpha(self) -> int:
+        return (self.alpha_hi << 64) | self.alpha_lo
+
+
+class NsOpts(C.Structure):
+    _fields_ = [("eps", C.c_double), ("confidence", C.c_double), ("seed", C.c_uint64), ("tag", C.c_uint32),
+                ("nthreads", C.c_int32), ("fixed_n", C.c_uint64), ("n_min", C.c_uint64), ("w_min", C.c_uint64),
+                ("quantum", C.c_uint64), ("max_samples", C.c_uint64), ("growth", C.c_double)]
+
+
+class NsResult(C.Structure):
+    _fields_ = [("estimate", C.c_double), ("eps_hat", C.c_double), ("z", C.c_double), ("n", C.c_uint64),
+                ("hits", C.c_uint64), ("checksum", C.c_uint64), ("bytes", C.c_uint64),
+                ("s1", C.c_uint32 * 8), ("s2", C.c_uint32 * 12), ("windows", C.c_int32),
+                ("converged", C.c_int32), ("overflow", C.c_int32)]
+
+    @property
+    def S1(self) -> int:
+        return sum(int(d) << (32 * i) for i, d in enumerate(self.s1))
+
+    @property
+    def S2(self) -> int:
+        return sum(int(d) << (32 * i) for i, d in enumerate(self.s2))
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        so = _build.SO
+        if not os.path.exists(so):
+            _build.build(force=False)
+        L = C.CDLL(so)
+        P = C.c_void_p
+        G = C.POINTER(Graph)
+        PL = C.POINTER(Plan)
+        L.orc_philox4x32_10.argtypes = [P, P, P]
+        L.orc_draw.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32]
+        L.orc_draw.restype = C.c_uint64
+        L.orc_mulhi.argtypes = [C.c_uint64, C.c_uint64]
+        L.orc_mulhi.restype = C.c_uint64
+        L.orc_canon.argtypes = [C.c_int64, P, P, G]
+        L.orc_from_canonical.argtypes = [C.c_int64, P, P, G]
+        L.orc_graph_free.argtypes = [G]
+        L.orc_compile.argtypes = [C.c_int, C.c_int, P, C.c_int, PL]
+        L.orc_automorphisms.argtypes = [C.c_int, C.c_int, P]
+        L.orc_brute_count.argtypes = [G, C.c_int, C.c_int, P, C.c_int, C.POINTER(C.c_uint64),
+                                      C.POINTER(C.c_uint64)]
+        L.orc_plan_count.argtypes = [G, PL, C.c_int, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
+        L.orc_candidates.argtypes = [G, PL, C.c_int, P, P]
+        L.orc_candidates.restype = C.c_uint64
+        L.orc_ns_sample.argtypes = [G, PL, C.c_uint64, C.c_uint32, C.c_uint64, P, C.POINTER(Rec)]
+        L.orc_rec_hash.argtypes = [C.POINTER(Rec)]
+        L.orc_rec_hash.restype = C.c_uint64
+        L.orc_ns_trace.argtypes = [G, PL, C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint64, C.c_int, P]
+        L.orc_ns_run.argtypes = [G, PL, C.POINTER(NsOpts), C.POINTER(NsResult), P, P, C.c_int]
+        L.orc_norm_ppf.argtypes = [C.c_double]
+        L.orc_norm_ppf.restype = C.c_double
+        L.orc_eps_hat.argtypes = [C.c_double, C.c_uint64, P, C.c_int, P, C.c_int]
+        L.orc_eps_hat.restype = C.c_double
+        L.orc_window_next.argtypes = [C.c_uint64, C.POINTER(NsOpts)]
+        L.orc_window_next.restype = C.c_uint64
+        L.orc_gs_colour.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_int64]
+        L.orc_gs_colour.restype = C.c_int32
+        L.orc_gs_sparsify.argtypes = [G, P, G]
+        L.orc_gs_count.argtypes = [G, PL, C.c_uint32, C.c_uint64, C.c_uint32, C.c_int,
+                                   C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
+        _lib = L
+    return _lib
+
+
+def nthreads() -> int:
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+# ------------------------------------------------------------------ Philox
+def philox(ctr, key):
+    c = np.asarray(ctr, dtype=np.uint32)
+    k = np.asarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox4x32_10(c.ctypes.data, k.ctypes.data, out.ctypes.data)
+    return [int(x) for x in out]
+
+
+def draw(seed, s, d, tag):
+    return int(lib().orc_draw(seed, s, d, tag))
+
+
+def mulhi(n, r):
+    return int(lib().orc_mulhi(n, r))
+
+
+# ------------------------------------------------------------------ graphs
+class OGraph:
+    """Oracle-owned canonical graph with numpy views of its arrays."""
+
+    def __init__(self, g: Graph):
+        self.g = g
+
+    @classmethod
+    def from_raw_csr(cls, n, off, nbr):
+        off = np.ascontiguousarray(off, dtype=np.int64)
+        nbr = np.ascontiguousarray(nbr, dtype=np.int32)
+        g = Graph()
+        rc = lib().orc_canon(n, off.ctypes.data, nbr.ctypes.data, C.byref(g))
+        if rc != 0:
+            raise ValueError(f"oracle canonicalisation failed ({rc})")
+        return cls(g)
+
+    @classmethod
+    def from_pairs(cls, n, pairs):
+        from paper_2405_03488_amd import synth
+        off, nbr = synth.pairs_to_csr(n, np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+        return cls.from_raw_csr(n, off, nbr)
+
+    @classmethod
+    def from_canonical(cls, n, off, nbr):
+        off = np.ascontiguousarray(off, dtype=np.int64)
+        nbr = np.ascontiguousarray(nbr, dtype=np.int32)
+        g = Graph()
+        rc = lib().orc_from_canonical(n, off.ctypes.data, nbr.ctypes.data, C.byref(g))
+        if rc != 0:
+            raise ValueError("oracle from_canonical failed")
+        return cls(g)
+
+    def __del__(self):
+        try:
+            lib().orc_graph_free(C.byref(self.g))
+        except Exception:
+            pass
+
+    @property
+    def n(self):
+        return int(self.g.n)
+
+    @property
+    def m(self):
+        return int(self.g.m)
+
+    def _arr(self, ptr, count):
+        if count == 0 or not ptr:
+            return np.zeros(0, dtype=np.int64 if ptr._type_ is C.c_int64 else np.int32)
+        return np.ctypeslib.as_array(ptr, shape=(count,)).copy()
+
+    @property
+    def off(self):
+        return self._arr(self.g.off, self.n + 1)
+
+    @property
+    def nbr(self):
+        return self._arr(self.g.nbr, 2 * self.m)
+
+    @property
+    def esrc(self):
+        return self._arr(self.g.esrc, self.m)
+
+    @property
+    def edst(self):
+        return self._arr(self.g.edst, self.m)
+
+    @property
+    def arow(self):
+        return self._arr(self.g.arow, 2 * self.m)
+
+    @property
+    def perm(self):
+        return self._arr(self.g.perm, self.n)
+
+    def ref(self):
+        return C.byref(self.g)
+
+
+# ------------------------------------------------------------------ patterns
+def compile_plan(k, edges, induced=False) -> Plan:
+    e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 2))
+    p = Plan()
+    rc = lib().orc_compile(k, len(e), e.ctypes.data, int(induced), C.byref(p))
+    if rc != 0:
+        raise ValueError(f"oracle compile failed ({rc})")
+    return p
+
+
+def automorphisms(k, edges) -> int:
+    e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 2))
+    return int(lib().orc_automorphisms(k, len(e), e.ctypes.data))
+
+
+def plan_dict(p: Plan) -> dict:
+    k = p.k
+    return {"k": k, "induced": p.induced, "oriented": p.oriented, "aut": p.aut,
+            "order": list(p.order)[:k], "connect": list(p.connect)[:k], "disconnect": list(p.disconnect)[:k],
+            "upper": list(p.upper)[:k], "lower": list(p.lower)[:k]}
+
+
+# ------------------------------------------------------------------ counting
+def brute_count(g: OGraph, k, edges, induced=False):
+    e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 2))
+    inj = C.c_uint64()
+    cnt = C.c_uint64()
+    lib().orc_brute_count(g.ref(), k, len(e), e.ctypes.data, int(induced), C.byref(inj), C.byref(cnt))
+    return int(inj.value), int(cnt.value)
+
+
+def plan_count(g: OGraph, p: Plan, threads=None) -> int:
+    lo = C.c_uint64()
+    hi = C.c_uint64()
+    lib().orc_plan_count(g.ref(), C.byref(p), threads or nthreads(), C.byref(lo), C.byref(hi))
+    return (int(hi.value) << 64) | int(lo.value)
+
+
+def candidates(g: OGraph, p: Plan, j, v):
+    vv = np.zeros(8, dtype=np.int32)
+    vv[:len(v)] = v
+    cnt = lib().orc_candidates(g.ref(), C.byref(p), j, vv.ctypes.data, None)
+    out = np.zeros(max(1, cnt), dtype=np.int32)
+    lib().orc_candidates(g.ref(), C.byref(p), j, vv.ctypes.data, out.ctypes.data)
+    return out[:cnt].tolist()
+
+
+# ------------------------------------------------------------------ NS
+def sample(g: OGraph, p: Plan, seed, tag, s, draws=None) -> Rec:
+    r = Rec()
+    if draws is not None:
+        d = np.zeros(8, dtype=np.uint64)
+        d[:len(draws)] = [int(x) for x in draws]
+        lib().orc_ns_sample(g.ref(), C.byref(p), seed, tag, s, d.ctypes.data, C.byref(r))
+    else:
+        lib().orc_ns_sample(g.ref(), C.byref(p), seed, tag, s, None, C.byref(r))
+    return r
+
+
+def rec_hash(r: Rec) -> int:
+    return int(lib().orc_rec_hash(C.byref(r)))
+
+
+def trace(g: OGraph, p: Plan, seed, tag, s0, count, threads=None):
+    arr = (Rec * count)()
+    lib().orc_ns_trace(g.ref(), C.byref(p), seed, tag, s0, count, threads or nthreads(), C.cast(arr, C.c_void_p))
+    return arr
+
+
+def make_opts(eps=0.01, confidence=0.95, seed=1, tag=0, threads=None, fixed_n=0, n_min=1 << 20,
+              w_min=1 << 20, quantum=1 << 16, max_samples=1 << 40, growth=0.10) -> NsOpts:
+    return NsOpts(eps, confidence, seed, tag, threads or nthreads(), fixed_n, n_min, w_min, quantum,
+                  max_samples, growth)
+
+
+def run(g: OGraph, p: Plan, opts: NsOpts, trace_cap=0):
+    r = NsResult()
+    if trace_cap:
+        et = np.zeros(trace_cap, dtype=np.float64)
+        nt = np.zeros(trace_cap, dtype=np.uint64)
+        lib().orc_ns_run(g.ref(), C.byref(p), C.byref(opts), C.byref(r), et.ctypes.data, nt.ctypes.data,
+                         trace_cap)
+        w = min(r.windows, trace_cap)
+        return r, et[:w].copy(), nt[:w].copy()
+    lib().orc_ns_run(g.ref(), C.byref(p), C.byref(opts), C.byref(r), None, None, 0)
+    return r
+
+
+def norm_ppf(p) -> float:
+    return float(lib().orc_norm_ppf(p))
+
+
+def eps_hat(z, n, S1: int, S2: int) -> float:
+    d1 = np.array([(S1 >> (32 * i)) & 0xFFFFFFFF for i in range(8)], dtype=np.uint32)
+    d2 = np.array([(S2 >> (32 * i)) & 0xFFFFFFFF for i in range(12)], dtype=np.uint32)
+    return float(lib().orc_eps_hat(z, n, d1.ctypes.data, 8, d2.ctypes.data, 12))
+
+
+def window_next(n_t, opts: NsOpts) -> int:
+    return int(lib().orc_window_next(n_t, C.byref(opts)))
+
+
+# ------------------------------------------------------------------ GS
+def gs_colour(seed, rep, c, v) -> int:
+    return int(lib().orc_gs_colour(seed, rep, c, v))
+
+
+def gs_sparsify(g: OGraph, colour) -> OGraph:
+    col = np.ascontiguousarray(colour, dtype=np.int32)
+    out = Graph()
+    rc = lib().orc_gs_sparsify(g.ref(), col.ctypes.data, C.byref(out))
+    if rc != 0:
+        raise ValueError("oracle sparsify failed")
+    return OGraph(out)
+
+
+def gs_count(g: OGraph, p: Plan, c, seed, rep, threads=None) -> int:
+    lo = C.c_uint64()
+    hi = C.c_uint64()
+    lib().orc_gs_count(g.ref(), C.byref(p), c, seed, rep, threads or nthreads(), C.byref(lo), C.byref(hi))
+    return (int(hi.value) << 64) | int(lo.value)
+
+
+def exact_expectation(g: OGraph, p: Plan) -> Fraction:
+    """Sum over every random walk of Pr(walk) * X(walk), enumerating index choices
+    by handing the sampler draws r = ceil(i * 2^64 / N) that select index i."""
+    k = p.k
+    M = g.m if p.oriented else 2 * g.m
+    if M == 0:
+        return Fraction(0)
+
+    def r_for(i, N):
+        return -((-i << 64) // N)
+
+    total = Fraction(0)
+
+    def walk(draws, depth, prob):
+        nonlocal total
+        rec = sample(g, p, 0, 0, 0, draws + [0] * (8 - len(draws)))
+        if depth == k:
+            if rec.hit:
+                total += prob * rec.alpha
+            return
+        N = int(rec.size[depth])  # |S_depth| given the chosen prefix
+        for i in range(N):
+            walk(draws + [r_for(i, N)], depth + 1, prob / N)
+
+    for e in range(M):
+        walk([r_for(e, M), 0], 2, Fraction(1, M))
+    return total

@@ -1,0 +1,104 @@
+"""Pins for the oracle's statistics and stop rule (Sec. 4.1, the NS-online
+algorithm and the error equation; Theorem on confidence)."""
+import math
+from decimal import Decimal, getcontext
+
+import numpy as np
+import pytest
+
+
+def test_norm_ppf_against_scipy(O):
+    from scipy.stats import norm
+    for conf in [0.5, 0.8, 0.9, 0.95, 0.98, 0.99, 0.995, 0.999, 0.9999]:
+        p = 1 - (1 - conf) / 2
+        assert abs(O.norm_ppf(p) - norm.ppf(p)) <= 5e-16 * norm.ppf(p)  # two ulps
+    assert abs(O.norm_ppf(0.975) - 1.959963984540054) < 1e-15
+    assert abs(O.norm_ppf(0.995) - 2.5758293035489004) < 1e-15
+
+
+def _paper_eps(z, xs):
+    """The paper's sequence of operations in 60-digit decimals:
+    mu = sum/n, var = squaredSum/n - mu^2, sigma = sqrt(var/n), eps = z*sigma/mu."""
+    getcontext().prec = 60
+    n = Decimal(len(xs))
+    s = Decimal(sum(xs))
+    ss = Decimal(sum(x * x for x in xs))
+    mu = s / n
+    var = ss / n - mu * mu
+    sigma = (var / n).sqrt()
+    return float(Decimal(z) * sigma / mu)
+
+
+@pytest.mark.parametrize("case", [
+    [1, 2, 3, 4, 5],
+    [0, 0, 0, 7, 0, 0, 9, 0],
+    [10**20, 3 * 10**20, 0, 5 * 10**19],
+    [2**100 + 17, 2**99, 0, 0, 2**101],
+    [123456789] * 9 + [123456790],
+])
+def test_eps_hat_matches_paper_formula(O, case):
+    z = 1.959963984540054
+    S1 = sum(case)
+    S2 = sum(x * x for x in case)
+    got = O.eps_hat(z, len(case), S1, S2)
+    want = _paper_eps(z, case)
+    assert abs(got - want) <= 1e-13 * want
+
+
+def test_eps_hat_against_numpy_population_std(O):
+    rng = np.random.default_rng(0)
+    xs = rng.integers(0, 1000, size=5000) * (rng.random(5000) < 0.3)
+    z = O.norm_ppf(0.975)
+    got = O.eps_hat(z, len(xs), int(xs.sum()), int((xs.astype(object) ** 2).sum()))
+    want = z * np.std(xs.astype(np.float64)) / math.sqrt(len(xs)) / np.mean(xs)
+    assert abs(got - want) < 1e-9 * want
+
+
+def test_eps_hat_special_cases(O):
+    assert O.eps_hat(1.96, 10, 0, 0) == float("inf")
+    assert O.eps_hat(1.96, 4, 20, 100) == 0.0  # all samples equal 5
+
+
+def test_window_schedule(O):
+    o = O.make_opts(n_min=1 << 20, w_min=1 << 20, quantum=1 << 16, max_samples=1 << 30, growth=0.10)
+    n = 0
+    seq = []
+    while True:
+        nx = O.window_next(n, o)
+        if nx <= n:
+            break
+        seq.append(nx)
+        n = nx
+    assert seq[0] == 1 << 20
+    assert all(x % (1 << 16) == 0 for x in seq)
+    for a, b in zip(seq, seq[1:]):
+        inc = max(1 << 20, math.ceil(0.1 * a))
+        assert b == min(1 << 30, -(-(a + inc) // (1 << 16)) * (1 << 16))
+    assert seq[-1] == 1 << 30
+
+
+def test_stop_rule_first_window_below_eps(O, synth):
+    g = O.OGraph.from_pairs(2000, synth.er_pairs(2000, 16000, 1))
+    k, e = synth.pattern("triangle")
+    p = O.compile_plan(k, e)
+    o = O.make_opts(eps=0.05, n_min=20000, w_min=20000, quantum=1000, seed=3)
+    r, et, nt = O.run(g, p, o, trace_cap=200)
+    assert r.converged == 1
+    assert et[-1] <= 0.05 and all(x > 0.05 for x in et[:-1])
+    assert nt[-1] == r.n
+
+
+def test_coverage(O, synth):
+    """Theorem (Sec. 4.1): P(|mu - C|/C < eps_hat) -> 1 - delta; check the
+    empirical coverage at fixed n over 200 seeds sits in the binomial 99% band."""
+    g = O.OGraph.from_pairs(500, synth.er_pairs(500, 5000, 2))
+    k, e = synth.pattern("triangle")
+    p = O.compile_plan(k, e)
+    C = O.plan_count(g, p)
+    R = 200
+    inside = 0
+    for seed in range(R):
+        r = O.run(g, p, O.make_opts(fixed_n=20000, seed=1000 + seed, confidence=0.95))
+        inside += abs(r.estimate - C) / C < r.eps_hat
+    # Binomial(200, 0.95): mean 190, sd 3.08; 99% band ~ [182, 198]
+    assert 180 <= inside <= 200, inside
