@@ -1,0 +1,246 @@
+/*
+ * sgpm.h -- C-ABI of the MI355X library for sampling-based approximate graph
+ * pattern counting (arXiv 2405.03488, "Accurate and Fast Approximate Graph
+ * Pattern Mining at Scale").
+ *
+ * Problem statement (Sec. 2.1): given a data graph G and a pattern P, return an
+ * estimate of the number of edge-induced (subgraph counting) or vertex-induced
+ * (motif counting) occurrences of P in G that lies within a factor (1 +- eps)
+ * of the true count with probability at least 1 - delta.
+ *
+ * Conventions for every call:
+ *   - Every function returns sgpm_status (0 = success, < 0 = error) and never
+ *     throws across the ABI.  A failing call leaves its outputs untouched
+ *     unless stated otherwise; sgpm_last_error() gives a message.
+ *   - Pointers are host pointers unless a flag says otherwise.  Caller-owned
+ *     arrays are only read during the call; the library copies what it keeps.
+ *   - Handles (sgpm_graph_t, sgpm_pattern_t, sgpm_model_t) are owned by the
+ *     library until the matching *_free; each belongs to the context that made
+ *     it.  One context per host thread.
+ *   - All device work runs on the context's HIP stream; calls return after
+ *     their results are final (no asynchronous outputs).
+ *   - Sample ids, random draws and integer sums are deterministic: the same
+ *     inputs and seed give bit-identical walks, sums and checksums regardless
+ *     of launch configuration.
+ */
+#ifndef SGPM_H
+#define SGPM_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SGPM_OK = 0,
+    SGPM_EINVAL = -1,          /* bad argument (null pointer, out-of-range option) */
+    SGPM_ENOMEM = -2,          /* host or device allocation failed */
+    SGPM_EHIP = -3,            /* a HIP runtime call failed */
+    SGPM_EUNSUPPORTED = -4,    /* k < 2, k > 8, disconnected pattern, unsupported mode */
+    SGPM_NOT_CONVERGED = -5,   /* max_samples reached before eps_hat <= eps; result IS filled */
+    SGPM_EBADGRAPH = -6,       /* malformed CSR, or non-canonical input with SGPM_ASSUME_CANONICAL */
+    SGPM_EOVERFLOW = -7        /* a sample weight exceeded 128 bits */
+} sgpm_status;
+
+typedef struct sgpm_ctx* sgpm_ctx_t;
+typedef struct sgpm_graph* sgpm_graph_t;
+typedef struct sgpm_pattern* sgpm_pattern_t;
+typedef struct sgpm_model* sgpm_model_t;
+
+/* ------------------------------------------------------------------ context */
+
+/* Create a context bound to HIP device `hip_device` and stream `hip_stream`
+ * (a hipStream_t; NULL = the device's null stream).  The stream must outlive
+ * the context. */
+sgpm_status sgpm_create(sgpm_ctx_t* out, int hip_device, void* hip_stream);
+sgpm_status sgpm_destroy(sgpm_ctx_t ctx);
+/* Message of the last failing call on ctx; valid until the next call on ctx. */
+const char* sgpm_last_error(sgpm_ctx_t ctx);
+/* Number of HIP devices visible (0 on a host without GPUs); never fails. */
+int sgpm_device_count(void);
+
+/* ------------------------------------------------------------------ graphs */
+
+#define SGPM_ASSUME_CANONICAL 0x1u  /* input is already symmetric, loop-free, deduplicated,
+                                       degree-descending relabelled with ascending rows */
+
+/* Build the canonical data graph (Sec. 6: symmetric, no loops or duplicate
+ * edges; vertices relabelled by degree descending, ties by original id; rows
+ * ascending) from a CSR of n vertices.  offsets has n+1 entries, int64 when
+ * offsets_is_64 else int32; nbrs has offsets[n] int32 entries in [0, n).
+ * Without SGPM_ASSUME_CANONICAL every (u, v) entry is symmetrised, loops and
+ * duplicates are dropped.  The canonical CSR, the oriented edge list and the
+ * arc-row array are kept in device memory owned by the graph handle.
+ * Errors: EINVAL (null pointers, n < 0 or n >= 2^31), EBADGRAPH (offsets not
+ * monotone, neighbour id out of range, or a non-canonical input with
+ * SGPM_ASSUME_CANONICAL), ENOMEM, EHIP. */
+sgpm_status sgpm_graph_from_csr(sgpm_ctx_t ctx, int64_t n, const void* offsets, int offsets_is_64,
+                                const int32_t* nbrs, uint32_t flags, sgpm_graph_t* out);
+/* Sizes; perm_out (nullable, n entries) receives perm[original id] = canonical id. */
+sgpm_status sgpm_graph_stats(sgpm_graph_t g, int64_t* n, int64_t* m, int64_t* max_deg, int32_t* perm_out);
+/* Copy the canonical CSR to host arrays off_out[n+1], nbr_out[2m] (either nullable). */
+sgpm_status sgpm_graph_export(sgpm_graph_t g, int64_t* off_out, int32_t* nbr_out);
+sgpm_status sgpm_graph_free(sgpm_graph_t g);
+
+/* ------------------------------------------------------------------ patterns */
+
+/* Compile pattern P (k vertices, l edges given as pairs of ids in [0, k)) into
+ * the matching order and symmetry-breaking restrictions of NS-prune (Sec. 4.2).
+ * induced = 0: edge-induced (subgraph counting); 1: vertex-induced (motifs).
+ * Errors: EINVAL (bad pointers or edge ids), EUNSUPPORTED (k < 2, k > 8, or P
+ * disconnected). */
+sgpm_status sgpm_pattern_create(sgpm_ctx_t ctx, int k, int l, const int32_t* edges, int induced,
+                                sgpm_pattern_t* out);
+/* The compiled plan: order[i] = pattern vertex at position i; per position j a
+ * bit i < j of connect[j] is a pattern edge (i, j), of disconnect[j] a pattern
+ * non-edge checked for vertex-induced counting, of upper[j] the restriction
+ * v_j < v_i and of lower[j] the restriction v_j > v_i.  oriented = 1 when the
+ * first edge is drawn from the m edges with v0 > v1 (alpha starts at m), else
+ * from the 2m arcs.  All outputs are arrays of k entries (any may be NULL). */
+sgpm_status sgpm_pattern_plan(sgpm_pattern_t p, int32_t* order, uint8_t* connect, uint8_t* disconnect,
+                              uint8_t* upper, uint8_t* lower, int32_t* aut_size, int32_t* oriented);
+sgpm_status sgpm_pattern_free(sgpm_pattern_t p);
+
+/* ------------------------------------------------------------------ estimation */
+
+enum {
+    SGPM_MODE_STRICT_NS = 0,   /* NS-prune with online convergence (Sec. 4.1, 5.1 strict mode) */
+    SGPM_MODE_FIXED_N = 1,     /* exactly fixed_n NS samples, no stop rule */
+    SGPM_MODE_GS = 2,          /* colour sparsification + exact count, repeated colourings */
+    SGPM_MODE_HYBRID = 3       /* loose mode: choose NS or GS from pilot costs (Sec. 5.1) */
+};
+enum { SGPM_SCHEME_NS = 0, SGPM_SCHEME_GS = 1, SGPM_SCHEME_EXACT = 2 };
+
+/* One NS sample as recorded by the trace option (64 bytes). status = 0xFF for a
+ * hit, else the position j whose candidate set was empty; v[i] = -1 for
+ * positions not reached; alpha = X_s (0 on a miss). */
+typedef struct {
+    uint64_t s;
+    int32_t v[8];
+    uint32_t status;
+    uint32_t k;
+    uint64_t alpha_lo, alpha_hi;
+} sgpm_trace_rec;
+
+typedef struct {
+    double eps;              /* relative error bound, e.g. 0.01 */
+    double confidence;       /* 1 - delta, e.g. 0.95 */
+    uint64_t seed;           /* Philox key */
+    uint32_t query_tag;      /* Philox counter word 3; distinct tags give independent streams */
+    int32_t mode;            /* SGPM_MODE_* */
+    uint64_t fixed_n;        /* SGPM_MODE_FIXED_N sample count */
+    uint64_t n_min;          /* first window end (rounded up to quantum) */
+    uint64_t w_min;          /* smallest window */
+    uint64_t quantum;        /* window ends are multiples of this */
+    uint64_t max_samples;    /* hard cap (NOT_CONVERGED when reached) */
+    double window_growth;    /* next window = max(w_min, ceil(growth * n)) */
+    int32_t colours;         /* GS: colours c (0 = choose) */
+    int32_t gs_reps_max;     /* GS: cap on repeated colourings */
+    sgpm_model_t proposal;   /* NULL = uniform proposal */
+    int32_t lanes_per_sample;/* 0 = autotune, else 1, 4, 16 or 64 lanes cooperate on one sample */
+    int32_t checksum;        /* 1 = fold every sample record into result.checksum */
+    uint64_t trace_lo, trace_hi; /* record samples with trace_lo <= s < trace_hi ... */
+    sgpm_trace_rec* trace_buf;   /* ... into this host array of trace_hi - trace_lo records */
+} sgpm_options;
+
+typedef struct {
+    double estimate;         /* mu = S1 / n (NS) or the mean of c^(k-1) Y over colourings (GS) */
+    double eps_hat;          /* predicted relative error (error equation, Sec. 4.1); +inf if S1 = 0 */
+    double ci_lo, ci_hi;     /* mu -+ z sigma */
+    double z;                /* Phi^-1(1 - delta/2) */
+    uint64_t n_samples, n_hits;
+    uint32_t sum_digits[8];  /* S1 = sum X, little-endian 32-bit digits */
+    uint32_t sumsq_digits[12]; /* S2 = sum X^2 */
+    int32_t scheme;          /* SGPM_SCHEME_* */
+    int32_t colours;
+    int32_t converged;
+    int32_t windows;
+    int32_t lanes_per_sample;/* launch configuration used */
+    int32_t launches;        /* sampling-kernel launches */
+    uint64_t checksum;       /* sum over samples of the record hash, mod 2^64 (0 unless requested) */
+    uint64_t bytes;          /* algorithmic bytes of all samples (0 unless requested) */
+    double seconds_sampling; /* device time of the windows (kernels, reductions, read-back) */
+    double seconds_total;    /* wall time of the call */
+    double seconds_kernel;   /* device time of the sampling kernels alone (HIP events around each) */
+} sgpm_result;
+
+/* Defaults: eps 0.01, confidence 0.95, seed 1, tag 0, strict NS, n_min = w_min =
+ * 2^20, quantum 2^16, max_samples 2^40, growth 0.10, colours 0, reps 64,
+ * lanes 0 (autotune), no checksum, no trace. */
+void sgpm_options_default(sgpm_options* o);
+
+/* Estimate the count of P in G (Sec. 4-5).  Strict mode draws NS-prune samples
+ * in windows [n_t, n_{t+1}) of sample ids and stops at the first window end
+ * with eps_hat <= eps (NS-online algorithm); every window's integer sums are
+ * exact, so results do not depend on the launch configuration.
+ * Returns NOT_CONVERGED (result filled) when max_samples is reached. */
+sgpm_status sgpm_estimate(sgpm_ctx_t ctx, sgpm_graph_t g, sgpm_pattern_t p, const sgpm_options* o,
+                          sgpm_result* res);
+
+/* sgpm_estimate in the NS modes with result.bytes filled: the algorithmic bytes
+ * of every sample (8 for the first edge, 16 per earlier vertex whose row a step
+ * reads, 4 per entry of the smallest connected row inside the step's bounds).
+ * Uses an instrumented build of the sampling kernel; for measurement. */
+sgpm_status sgpm_estimate_counted(sgpm_ctx_t ctx, sgpm_graph_t g, sgpm_pattern_t p, const sgpm_options* o,
+                                  sgpm_result* res);
+
+/* Estimate nq queries (graphs[i], patterns[i], opts[i]) in one persistent
+ * launch; each query keeps its own windows and stop rule and its result equals
+ * the solo sgpm_estimate result bit for bit (NS modes only). */
+sgpm_status sgpm_estimate_batch(sgpm_ctx_t ctx, int nq, const sgpm_graph_t* graphs,
+                                const sgpm_pattern_t* patterns, const sgpm_options* opts, sgpm_result* res);
+
+/* Exact count of P in G: the plan-driven nested-loop search of the GS engine on
+ * the unsparsified graph (one colour). */
+sgpm_status sgpm_exact_count(sgpm_ctx_t ctx, sgpm_graph_t g, sgpm_pattern_t p, uint64_t* count_lo,
+                             uint64_t* count_hi);
+
+/* Colour-sparsify G (Sec. 2.2, Sec. 5.2): colour(v) = floor(c * r / 2^64) with r
+ * the Philox value of (key = seed, counter = (v lo, v hi, 0, 0x40000000 | rep)),
+ * keep edges whose endpoints share a colour.  The result is a new graph handle
+ * on the same vertex ids (the disjoint union of the colour classes). */
+sgpm_status sgpm_gs_sparsify(sgpm_ctx_t ctx, sgpm_graph_t g, uint32_t colours, uint64_t seed, uint32_t rep,
+                             sgpm_graph_t* out);
+
+/* ------------------------------------------------------------------ learned proposal */
+
+/* Train the MLP proposal on pilot NS samples of (g, patterns[0..np)) drawn with
+ * tag 0x80000000 | i, using the library's BF16 MFMA forward and backward
+ * kernels; train_cfg may be NULL for defaults (see sgpm_train_cfg). */
+typedef struct {
+    uint64_t pilot_samples;  /* per pattern */
+    int32_t epochs;
+    int32_t batch;
+    float lr;
+    uint64_t seed;
+} sgpm_train_cfg;
+sgpm_status sgpm_model_train(sgpm_ctx_t ctx, sgpm_graph_t g, const sgpm_pattern_t* patterns, int np,
+                             const sgpm_train_cfg* cfg, sgpm_model_t* out);
+sgpm_status sgpm_model_free(sgpm_model_t m);
+
+/* ------------------------------------------------------------------ host-only utilities */
+/* These run the host parts of the library without a device, so they can be
+ * checked on any machine. */
+
+/* Canonicalise a CSR on the host (same rules as sgpm_graph_from_csr).  Call
+ * with nbr_out = NULL to get *m_out (undirected edges); then off_out[n+1],
+ * nbr_out[2m] and perm_out[n] (each nullable) are filled by a second call. */
+sgpm_status sgpm_host_canonicalise(int64_t n, const void* offsets, int offsets_is_64, const int32_t* nbrs,
+                                   uint32_t flags, int64_t* m_out, int64_t* off_out, int32_t* nbr_out,
+                                   int32_t* perm_out);
+/* Compile a pattern without a context; outputs as sgpm_pattern_plan. */
+sgpm_status sgpm_host_plan(int k, int l, const int32_t* edges, int induced, int32_t* order, uint8_t* connect,
+                           uint8_t* disconnect, uint8_t* upper, uint8_t* lower, int32_t* aut_size,
+                           int32_t* oriented);
+/* Phi^-1(p) for 0.5 < p < 1 (NaN otherwise). */
+double sgpm_host_normal_quantile(double p);
+/* Predicted relative error from exact sums given as little-endian 32-bit digits
+ * (error equation, Sec. 4.1); +inf when S1 = 0. */
+double sgpm_host_predicted_error(double z, uint64_t n, const uint32_t* s1, int n1, const uint32_t* s2, int n2);
+/* End of the window that starts at sample n_t under options o. */
+uint64_t sgpm_host_next_window(uint64_t n_t, const sgpm_options* o);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

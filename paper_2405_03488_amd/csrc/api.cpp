@@ -1,0 +1,533 @@
+// C-ABI entry points: contexts, graphs, patterns and the NS estimation loop.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+
+#include "sgpm_internal.h"
+
+using namespace sgpm;
+
+struct sgpm_ctx {
+    int dev = 0;
+    hipStream_t st = nullptr;
+    std::string err;
+    int cus = 256;
+    // scratch reused across calls
+    unsigned long long* d_partials = nullptr;
+    size_t partial_blocks = 0;
+    unsigned long long* d_slots = nullptr;   // per launch: ticket + 20 sums (+ pad) = 32 words
+    unsigned long long* h_slots = nullptr;   // pinned mirror of the sums
+    size_t nslots = 0;
+    std::vector<hipEvent_t> kev;             // start/stop events around each sampling kernel
+};
+
+struct sgpm_graph {
+    sgpm_ctx* ctx = nullptr;
+    int64_t n = 0, m = 0, maxdeg = 0;
+    std::vector<int32_t> perm;
+    int64_t* d_off = nullptr;
+    int32_t* d_nbr = nullptr;
+    int2* d_epair = nullptr;
+    int32_t* d_arow = nullptr;
+    DGraph view() const { return DGraph{d_off, d_nbr, d_epair, d_arow, n, m}; }
+};
+
+struct sgpm_pattern {
+    Plan plan;
+};
+
+namespace {
+
+constexpr int SLOT_WORDS = 32;  // [0] ticket, [1..20] sums
+
+sgpm_status fail(sgpm_ctx* c, sgpm_status s, const std::string& msg) {
+    if (c) c->err = msg;
+    return s;
+}
+
+#define HIP_TRY(ctx, expr)                                                                    \
+    do {                                                                                      \
+        hipError_t _e = (expr);                                                               \
+        if (_e != hipSuccess) return fail((ctx), SGPM_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+sgpm_status ensure_scratch(sgpm_ctx* c, size_t blocks, size_t slots) {
+    if (blocks > c->partial_blocks) {
+        if (c->d_partials) (void)hipFree(c->d_partials);
+        c->d_partials = nullptr;
+        c->partial_blocks = 0;
+        HIP_TRY(c, hipMalloc(&c->d_partials, blocks * PF_N * sizeof(unsigned long long)));
+        c->partial_blocks = blocks;
+    }
+    if (slots > c->nslots) {
+        if (c->d_slots) (void)hipFree(c->d_slots);
+        if (c->h_slots) (void)hipHostFree(c->h_slots);
+        c->d_slots = nullptr;
+        c->h_slots = nullptr;
+        c->nslots = 0;
+        size_t want = std::max<size_t>(slots, 1024);
+        HIP_TRY(c, hipMalloc(&c->d_slots, want * SLOT_WORDS * sizeof(unsigned long long)));
+        HIP_TRY(c, hipHostMalloc(&c->h_slots, want * SLOT_WORDS * sizeof(unsigned long long), hipHostMallocDefault));
+        c->nslots = want;
+    }
+    return SGPM_OK;
+}
+
+int blocks_for(sgpm_ctx* c, int lanes) {
+    // resident blocks of 256 threads per CU for the sampling kernel (register bound)
+    (void)lanes;
+    return c->cus * 6;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sgpm_device_count(void) {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess) return 0;
+    return n;
+}
+
+sgpm_status sgpm_create(sgpm_ctx_t* out, int hip_device, void* hip_stream) {
+    if (!out) return SGPM_EINVAL;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || hip_device < 0 || hip_device >= n) return SGPM_EHIP;
+    auto* c = new (std::nothrow) sgpm_ctx();
+    if (!c) return SGPM_ENOMEM;
+    c->dev = hip_device;
+    c->st = (hipStream_t)hip_stream;
+    if (hipSetDevice(hip_device) != hipSuccess) {
+        delete c;
+        return SGPM_EHIP;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess && prop.multiProcessorCount > 0)
+        c->cus = prop.multiProcessorCount;
+    *out = c;
+    return SGPM_OK;
+}
+
+sgpm_status sgpm_destroy(sgpm_ctx_t c) {
+    if (!c) return SGPM_EINVAL;
+    (void)hipSetDevice(c->dev);
+    if (c->d_partials) (void)hipFree(c->d_partials);
+    if (c->d_slots) (void)hipFree(c->d_slots);
+    if (c->h_slots) (void)hipHostFree(c->h_slots);
+    for (hipEvent_t e : c->kev) (void)hipEventDestroy(e);
+    delete c;
+    return SGPM_OK;
+}
+
+const char* sgpm_last_error(sgpm_ctx_t c) { return c ? c->err.c_str() : "null context"; }
+
+void sgpm_options_default(sgpm_options* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->eps = 0.01;
+    o->confidence = 0.95;
+    o->seed = 1;
+    o->query_tag = 0;
+    o->mode = SGPM_MODE_STRICT_NS;
+    o->n_min = 1ull << 20;
+    o->w_min = 1ull << 20;
+    o->quantum = 1ull << 16;
+    o->max_samples = 1ull << 40;
+    o->window_growth = 0.10;
+    o->colours = 0;
+    o->gs_reps_max = 64;
+    o->lanes_per_sample = 0;
+}
+
+sgpm_status sgpm_graph_from_csr(sgpm_ctx_t c, int64_t n, const void* offsets, int offsets_is_64,
+                                const int32_t* nbrs, uint32_t flags, sgpm_graph_t* out) {
+    if (!c || !out || !offsets || n < 0 || n >= (1ll << 31)) return fail(c, SGPM_EINVAL, "bad graph arguments");
+    HostGraph h;
+    std::string err;
+    int rc = canonicalise(n, offsets, offsets_is_64, nbrs, (flags & SGPM_ASSUME_CANONICAL) != 0, h, err);
+    if (rc != SGPM_OK) return fail(c, (sgpm_status)rc, err);
+    auto g = std::make_unique<sgpm_graph>();
+    g->ctx = c;
+    g->n = h.n;
+    g->m = h.m;
+    for (int64_t u = 0; u < n; u++) g->maxdeg = std::max(g->maxdeg, h.off[(size_t)u + 1] - h.off[(size_t)u]);
+    // oriented edges (u, w), w < u: the prefix of each ascending row below u
+    std::vector<int2> ep((size_t)std::max<int64_t>(h.m, 1));
+    std::vector<int32_t> arow((size_t)std::max<int64_t>(2 * h.m, 1));
+    {
+        int64_t e = 0;
+        for (int64_t u = 0; u < n; u++)
+            for (int64_t i = h.off[(size_t)u]; i < h.off[(size_t)u + 1]; i++) {
+                arow[(size_t)i] = (int32_t)u;
+                if (h.nbr[(size_t)i] < u) ep[(size_t)e++] = make_int2((int32_t)u, h.nbr[(size_t)i]);
+            }
+        if (e != h.m) return fail(c, SGPM_EBADGRAPH, "internal: oriented edge count mismatch");
+    }
+    HIP_TRY(c, hipSetDevice(c->dev));
+    HIP_TRY(c, hipMalloc(&g->d_off, sizeof(int64_t) * (size_t)(n + 1)));
+    HIP_TRY(c, hipMalloc(&g->d_nbr, sizeof(int32_t) * (size_t)std::max<int64_t>(2 * h.m, 1)));
+    HIP_TRY(c, hipMalloc(&g->d_epair, sizeof(int2) * (size_t)std::max<int64_t>(h.m, 1)));
+    HIP_TRY(c, hipMalloc(&g->d_arow, sizeof(int32_t) * (size_t)std::max<int64_t>(2 * h.m, 1)));
+    HIP_TRY(c, hipMemcpy(g->d_off, h.off.data(), sizeof(int64_t) * (size_t)(n + 1), hipMemcpyHostToDevice));
+    if (h.m > 0) {
+        HIP_TRY(c, hipMemcpy(g->d_nbr, h.nbr.data(), sizeof(int32_t) * (size_t)(2 * h.m), hipMemcpyHostToDevice));
+        HIP_TRY(c, hipMemcpy(g->d_epair, ep.data(), sizeof(int2) * (size_t)h.m, hipMemcpyHostToDevice));
+        HIP_TRY(c, hipMemcpy(g->d_arow, arow.data(), sizeof(int32_t) * (size_t)(2 * h.m), hipMemcpyHostToDevice));
+    }
+    g->perm = std::move(h.perm);
+    *out = g.release();
+    return SGPM_OK;
+}
+
+sgpm_status sgpm_graph_stats(sgpm_graph_t g, int64_t* n, int64_t* m, int64_t* max_deg, int32_t* perm_out) {
+    if (!g) return SGPM_EINVAL;
+    if (n) *n = g->n;
+    if (m) *m = g->m;
+    if (max_deg) *max_deg = g->maxdeg;
+    if (perm_out && !g->perm.empty()) std::memcpy(perm_out, g->perm.data(), sizeof(int32_t) * g->perm.size());
+    return SGPM_OK;
+}
+
+sgpm_status sgpm_graph_export(sgpm_graph_t g, int64_t* off_out, int32_t* nbr_out) {
+    if (!g) return SGPM_EINVAL;
+    sgpm_ctx* c = g->ctx;
+    HIP_TRY(c, hipSetDevice(c->dev));
+    if (off_out) HIP_TRY(c, hipMemcpy(off_out, g->d_off, sizeof(int64_t) * (size_t)(g->n + 1), hipMemcpyDeviceToHost));
+    if (nbr_out && g->m > 0)
+        HIP_TRY(c, hipMemcpy(nbr_out, g->d_nbr, sizeof(int32_t) * (size_t)(2 * g->m), hipMemcpyDeviceToHost));
+    return SGPM_OK;
+}
+
+sgpm_status sgpm_graph_free(sgpm_graph_t g) {
+    if (!g) return SGPM_EINVAL;
+    (void)hipSetDevice(g->ctx->dev);
+    (void)hipFree(g->d_off);
+    (void)hipFree(g->d_nbr);
+    (void)hipFree(g->d_epair);
+    (void)hipFree(g->d_arow);
+    delete g;
+    return SGPM_OK;
+}
+
+sgpm_status sgpm_pattern_create(sgpm_ctx_t c, int k, int l, const int32_t* edges, int induced, sgpm_pattern_t* out) {
+    if (!c || !out) return fail(c, SGPM_EINVAL, "null argument");
+    Plan p;
+    std::string err;
+    int rc = compile_pattern(k, l, edges, induced, p, err);
+    if (rc != SGPM_OK) return fail(c, (sgpm_status)rc, err);
+    auto* h = new (std::nothrow) sgpm_pattern();
+    if (!h) return SGPM_ENOMEM;
+    h->plan = p;
+    *out = h;
+    return SGPM_OK;
+}
+
+sgpm_status sgpm_pattern_plan(sgpm_pattern_t p, int32_t* order, uint8_t* connect, uint8_t* disconnect, uint8_t* upper,
+                              uint8_t* lower, int32_t* aut_size, int32_t* oriented) {
+    if (!p) return SGPM_EINVAL;
+    const Plan& q = p->plan;
+    for (int i = 0; i < q.k; i++) {
+        if (order) order[i] = q.order[i];
+        if (connect) connect[i] = q.connect[i];
+        if (disconnect) disconnect[i] = q.disconnect[i];
+        if (upper) upper[i] = q.upper[i];
+        if (lower) lower[i] = q.lower[i];
+    }
+    if (aut_size) *aut_size = q.aut;
+    if (oriented) *oriented = q.oriented;
+    return SGPM_OK;
+}
+
+sgpm_status sgpm_pattern_free(sgpm_pattern_t p) {
+    if (!p) return SGPM_EINVAL;
+    delete p;
+    return SGPM_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ NS engine
+namespace {
+
+struct NsState {
+    Big S1{24}, S2{24};
+    uint64_t n = 0, hits = 0, csum = 0, bytes = 0, ovf = 0;
+};
+
+void absorb(NsState& s, const unsigned long long* sums) {
+    big_add_digits(s.S1, sums + PF_S1, 6);
+    big_add_digits(s.S2, sums + PF_S2, 10);
+    s.hits += sums[PF_HITS];
+    s.csum += sums[PF_CSUM];
+    s.bytes += sums[PF_BYTES];
+    s.ovf += sums[PF_OVF];
+}
+
+// Launch [s0, s1) with the given lane count into slot `slot`; enqueue only.
+sgpm_status enqueue_range(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_options& o, uint64_t s0, uint64_t s1,
+                          int lanes, size_t slot, const TraceArgs& tr, int count_bytes) {
+    LaunchCfg cfg;
+    cfg.lanes = lanes;
+    cfg.spl = 4;
+    cfg.blocks = blocks_for(c, lanes);
+    const uint64_t per_wave = (uint64_t)(64 / lanes) * (uint64_t)cfg.spl;
+    const uint64_t tickets = (s1 - s0 + per_wave - 1) / per_wave;
+    const uint64_t max_blocks = (tickets + 3) / 4;
+    if ((uint64_t)cfg.blocks > max_blocks) cfg.blocks = (int)std::max<uint64_t>(1, max_blocks);
+    // partials sized for the largest grid once, so no buffer in flight is freed
+    sgpm_status st = ensure_scratch(c, (size_t)blocks_for(c, lanes), slot + 1);
+    if (st != SGPM_OK) return st;
+    unsigned long long* sl = c->d_slots + slot * SLOT_WORDS;
+    HIP_TRY(c, launch_fill_u64(sl, SLOT_WORDS, 0ull, c->st));
+    while (c->kev.size() < 2 * (slot + 1)) {
+        hipEvent_t ev;
+        HIP_TRY(c, hipEventCreate(&ev));
+        c->kev.push_back(ev);
+    }
+    HIP_TRY(c, hipEventRecord(c->kev[2 * slot], c->st));
+    HIP_TRY(c, launch_ns_window(g->view(), p, o.seed, o.query_tag, s0, s1, cfg, sl, c->d_partials, o.checksum,
+                                count_bytes, tr, c->st));
+    HIP_TRY(c, hipEventRecord(c->kev[2 * slot + 1], c->st));
+    HIP_TRY(c, launch_reduce_partials(c->d_partials, cfg.blocks, sl + 1, c->st));
+    HIP_TRY(c, hipMemcpyAsync(c->h_slots + slot * SLOT_WORDS, sl, SLOT_WORDS * sizeof(unsigned long long),
+                              hipMemcpyDeviceToHost, c->st));
+    return SGPM_OK;
+}
+
+void fill_result(sgpm_result* r, const NsState& s, double z) {
+    r->n_samples = s.n;
+    r->n_hits = s.hits;
+    for (int i = 0; i < 8; i++) r->sum_digits[i] = s.S1.d[(size_t)i];
+    for (int i = 0; i < 12; i++) r->sumsq_digits[i] = s.S2.d[(size_t)i];
+    r->estimate = s.n ? big_to_double(s.S1) / (double)s.n : 0.0;
+    r->eps_hat = predicted_error(z, s.n, s.S1, s.S2);
+    r->z = z;
+    const double sigma = std::isfinite(r->eps_hat) ? r->estimate * r->eps_hat / z : INFINITY;
+    r->ci_lo = r->estimate - z * sigma;
+    r->ci_hi = r->estimate + z * sigma;
+    r->checksum = s.csum;
+    r->bytes = s.bytes;
+}
+
+sgpm_status ns_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_options& o, sgpm_result* res,
+                        int count_bytes) {
+    auto t_start = std::chrono::steady_clock::now();
+    std::memset(res, 0, sizeof(*res));
+    res->scheme = SGPM_SCHEME_NS;
+    const double z = normal_quantile(1.0 - (1.0 - o.confidence) / 2.0);
+    const uint64_t M = p.oriented ? (uint64_t)g->m : 2ull * (uint64_t)g->m;
+    if (M == 0) {  // no edges: the count is exactly zero
+        res->z = z;
+        res->converged = 1;
+        res->eps_hat = 0.0;
+        return SGPM_OK;
+    }
+    HIP_TRY(c, hipSetDevice(c->dev));
+    // trace buffer
+    sgpm_trace_rec* d_trace = nullptr;
+    TraceArgs tr{nullptr, 0, 0};
+    const uint64_t ntr = (o.trace_buf && o.trace_hi > o.trace_lo) ? o.trace_hi - o.trace_lo : 0;
+    if (ntr) {
+        HIP_TRY(c, hipMalloc(&d_trace, ntr * sizeof(sgpm_trace_rec)));
+        HIP_TRY(c, launch_fill_u64((unsigned long long*)d_trace, ntr * sizeof(sgpm_trace_rec) / 8, 0ull, c->st));
+        tr = TraceArgs{d_trace, o.trace_lo, o.trace_hi};
+    }
+    hipEvent_t e0, e1;
+    HIP_TRY(c, hipEventCreate(&e0));
+    HIP_TRY(c, hipEventCreate(&e1));
+    NsState s;
+    int lanes = o.lanes_per_sample;
+    double dev_seconds = 0.0, kernel_seconds = 0.0;
+    int windows = 0, launches = 0;
+    bool converged = false;
+    sgpm_status status = SGPM_OK;
+    for (;;) {
+        const uint64_t nx = o.mode == SGPM_MODE_FIXED_N ? o.fixed_n : next_window_end(s.n, o);
+        if (nx <= s.n) break;
+        size_t slots = 0;
+        HIP_TRY(c, hipEventRecord(e0, c->st));
+        if (lanes == 0) {
+            // autotune on the first window: split it over the candidate lane
+            // counts, time each piece, keep the fastest per sample.  Every
+            // sample is still drawn exactly once, so results are unchanged.
+            static const int cand[4] = {1, 4, 16, 64};
+            const uint64_t len = nx - s.n;
+            float best_ms = 0;
+            int best = 1;
+            for (int i = 0; i < 4; i++) {
+                const uint64_t a = s.n + len * (uint64_t)i / 4, b = s.n + len * (uint64_t)(i + 1) / 4;
+                if (b <= a) continue;
+                hipEvent_t x0, x1;
+                HIP_TRY(c, hipEventCreate(&x0));
+                HIP_TRY(c, hipEventCreate(&x1));
+                HIP_TRY(c, hipEventRecord(x0, c->st));
+                status = enqueue_range(c, g, p, o, a, b, cand[i], slots++, tr, count_bytes);
+                if (status != SGPM_OK) return status;
+                HIP_TRY(c, hipEventRecord(x1, c->st));
+                HIP_TRY(c, hipEventSynchronize(x1));
+                float ms = 0;
+                HIP_TRY(c, hipEventElapsedTime(&ms, x0, x1));
+                (void)hipEventDestroy(x0);
+                (void)hipEventDestroy(x1);
+                const float per = ms / (float)(b - a);
+                if (i == 0 || per < best_ms) {
+                    best_ms = per;
+                    best = cand[i];
+                }
+            }
+            lanes = best;
+        } else {
+            status = enqueue_range(c, g, p, o, s.n, nx, lanes, slots++, tr, count_bytes);
+            if (status != SGPM_OK) return status;
+        }
+        HIP_TRY(c, hipEventRecord(e1, c->st));
+        HIP_TRY(c, hipStreamSynchronize(c->st));
+        float ms = 0;
+        HIP_TRY(c, hipEventElapsedTime(&ms, e0, e1));
+        dev_seconds += ms * 1e-3;
+        for (size_t k = 0; k < slots; k++) {
+            absorb(s, c->h_slots + k * SLOT_WORDS + 1);
+            float kms = 0;
+            HIP_TRY(c, hipEventElapsedTime(&kms, c->kev[2 * k], c->kev[2 * k + 1]));
+            kernel_seconds += kms * 1e-3;
+            launches++;
+        }
+        s.n = nx;
+        windows++;
+        if (s.ovf) {
+            status = SGPM_EOVERFLOW;
+            break;
+        }
+        if (o.mode == SGPM_MODE_FIXED_N) break;
+        const double eh = predicted_error(z, s.n, s.S1, s.S2);
+        if (eh <= o.eps) {
+            converged = true;
+            break;
+        }
+        if (o.max_samples && s.n >= o.max_samples) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    fill_result(res, s, z);
+    res->windows = windows;
+    res->lanes_per_sample = lanes;
+    res->seconds_sampling = dev_seconds;
+    res->seconds_kernel = kernel_seconds;
+    res->launches = launches;
+    if (o.mode == SGPM_MODE_FIXED_N) converged = res->eps_hat <= o.eps;
+    res->converged = converged ? 1 : 0;
+    if (ntr) {
+        HIP_TRY(c, hipMemcpy(o.trace_buf, d_trace, ntr * sizeof(sgpm_trace_rec), hipMemcpyDeviceToHost));
+        (void)hipFree(d_trace);
+    }
+    res->seconds_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    if (status != SGPM_OK) return fail(c, status, "a sample weight exceeded 128 bits");
+    if (!converged && o.mode != SGPM_MODE_FIXED_N) return fail(c, SGPM_NOT_CONVERGED, "max_samples reached");
+    return SGPM_OK;
+}
+
+sgpm_status check_options(sgpm_ctx* c, const sgpm_options* o) {
+    if (!o) return fail(c, SGPM_EINVAL, "null options");
+    if (!(o->eps > 0) || !(o->confidence > 0 && o->confidence < 1)) return fail(c, SGPM_EINVAL, "eps/confidence");
+    if (o->mode == SGPM_MODE_FIXED_N && o->fixed_n == 0) return fail(c, SGPM_EINVAL, "fixed_n = 0");
+    if (o->mode != SGPM_MODE_FIXED_N && o->n_min == 0 && o->w_min == 0) return fail(c, SGPM_EINVAL, "empty windows");
+    if (!(o->window_growth >= 0)) return fail(c, SGPM_EINVAL, "window_growth");
+    const int l = o->lanes_per_sample;
+    if (!(l == 0 || l == 1 || l == 4 || l == 16 || l == 64)) return fail(c, SGPM_EINVAL, "lanes_per_sample");
+    if (o->trace_hi > o->trace_lo && !o->trace_buf) return fail(c, SGPM_EINVAL, "trace range without buffer");
+    return SGPM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sgpm_status sgpm_estimate(sgpm_ctx_t c, sgpm_graph_t g, sgpm_pattern_t p, const sgpm_options* o, sgpm_result* res) {
+    if (!c || !g || !p || !res) return fail(c, SGPM_EINVAL, "null argument");
+    sgpm_status st = check_options(c, o);
+    if (st != SGPM_OK) return st;
+    switch (o->mode) {
+        case SGPM_MODE_STRICT_NS:
+        case SGPM_MODE_FIXED_N:
+            return ns_estimate(c, g, p->plan, *o, res, 0);
+        default:
+            return fail(c, SGPM_EUNSUPPORTED, "mode not available");
+    }
+}
+
+// Same as sgpm_estimate in NS modes, additionally filling result.bytes with the
+// algorithmic bytes of every sample (measurement build of the kernel).
+sgpm_status sgpm_estimate_counted(sgpm_ctx_t c, sgpm_graph_t g, sgpm_pattern_t p, const sgpm_options* o,
+                                  sgpm_result* res) {
+    if (!c || !g || !p || !res) return fail(c, SGPM_EINVAL, "null argument");
+    sgpm_status st = check_options(c, o);
+    if (st != SGPM_OK) return st;
+    if (o->mode != SGPM_MODE_STRICT_NS && o->mode != SGPM_MODE_FIXED_N)
+        return fail(c, SGPM_EUNSUPPORTED, "byte counting is for NS modes");
+    return ns_estimate(c, g, p->plan, *o, res, 1);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ host-only utilities
+extern "C" {
+
+sgpm_status sgpm_host_canonicalise(int64_t n, const void* offsets, int offsets_is_64, const int32_t* nbrs,
+                                   uint32_t flags, int64_t* m_out, int64_t* off_out, int32_t* nbr_out,
+                                   int32_t* perm_out) {
+    if (!offsets || n < 0 || n >= (1ll << 31)) return SGPM_EINVAL;
+    HostGraph h;
+    std::string err;
+    int rc = canonicalise(n, offsets, offsets_is_64, nbrs, (flags & SGPM_ASSUME_CANONICAL) != 0, h, err);
+    if (rc != SGPM_OK) return (sgpm_status)rc;
+    if (m_out) *m_out = h.m;
+    if (off_out) std::memcpy(off_out, h.off.data(), sizeof(int64_t) * (size_t)(n + 1));
+    if (nbr_out && h.m) std::memcpy(nbr_out, h.nbr.data(), sizeof(int32_t) * (size_t)(2 * h.m));
+    if (perm_out && n) std::memcpy(perm_out, h.perm.data(), sizeof(int32_t) * (size_t)n);
+    return SGPM_OK;
+}
+
+sgpm_status sgpm_host_plan(int k, int l, const int32_t* edges, int induced, int32_t* order, uint8_t* connect,
+                           uint8_t* disconnect, uint8_t* upper, uint8_t* lower, int32_t* aut_size,
+                           int32_t* oriented) {
+    sgpm_pattern p;
+    std::string err;
+    int rc = compile_pattern(k, l, edges, induced, p.plan, err);
+    if (rc != SGPM_OK) return (sgpm_status)rc;
+    return sgpm_pattern_plan(&p, order, connect, disconnect, upper, lower, aut_size, oriented);
+}
+
+double sgpm_host_normal_quantile(double p) { return normal_quantile(p); }
+
+double sgpm_host_predicted_error(double z, uint64_t n, const uint32_t* s1, int n1, const uint32_t* s2, int n2) {
+    Big S1(24), S2(24);
+    for (int i = 0; i < n1 && i < 24; i++) S1.d[(size_t)i] = s1[i];
+    for (int i = 0; i < n2 && i < 24; i++) S2.d[(size_t)i] = s2[i];
+    return predicted_error(z, n, S1, S2);
+}
+
+uint64_t sgpm_host_next_window(uint64_t n_t, const sgpm_options* o) { return o ? next_window_end(n_t, *o) : 0; }
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ entry points built in later modules
+extern "C" {
+sgpm_status sgpm_estimate_batch(sgpm_ctx_t c, int, const sgpm_graph_t*, const sgpm_pattern_t*, const sgpm_options*,
+                                sgpm_result*) {
+    return fail(c, SGPM_EUNSUPPORTED, "batch estimation is not built");
+}
+sgpm_status sgpm_exact_count(sgpm_ctx_t c, sgpm_graph_t, sgpm_pattern_t, uint64_t*, uint64_t*) {
+    return fail(c, SGPM_EUNSUPPORTED, "exact count is not built");
+}
+sgpm_status sgpm_gs_sparsify(sgpm_ctx_t c, sgpm_graph_t, uint32_t, uint64_t, uint32_t, sgpm_graph_t*) {
+    return fail(c, SGPM_EUNSUPPORTED, "sparsification is not built");
+}
+sgpm_status sgpm_model_train(sgpm_ctx_t c, sgpm_graph_t, const sgpm_pattern_t*, int, const sgpm_train_cfg*,
+                             sgpm_model_t*) {
+    return fail(c, SGPM_EUNSUPPORTED, "learned proposal is not built");
+}
+sgpm_status sgpm_model_free(sgpm_model_t) { return SGPM_EUNSUPPORTED; }
+}

@@ -1,0 +1,479 @@
+// NS-prune sampling kernels for gfx950 (wave64).
+//
+// One launch processes the sample ids [s0, s1) of one convergence window
+// (NS-online algorithm, Sec. 4.1).  Each sample (NS-prune, Sec. 4.2):
+//   * draws its first edge uniformly: from the m oriented edges (v0 > v1) when
+//     the plan orders them, else from the 2m arcs; alpha = m or 2m;
+//   * for every later position j builds the candidate set S_j = members of the
+//     smallest connected earlier row that lie inside the symmetry-breaking
+//     bounds, are adjacent to every other connected earlier vertex, are not
+//     adjacent to the disconnected ones (vertex-induced counting) and differ
+//     from all earlier vertices; an empty S_j ends the sample as a miss;
+//   * picks member floor(|S_j| * r / 2^64) of S_j in ascending order and
+//     multiplies alpha by |S_j| (the inverse selection probability);
+//   * on reaching the last position is a hit with X = alpha.
+// Draw d of sample s is Philox4x32-10 (Salmon et al., SC'11) with key = seed
+// and counter = (s lo, s hi, d, tag), read as w1*2^32 + w0.
+//
+// Work distribution: a wave takes tickets of (64 / G) * spl consecutive sample
+// ids from an atomic counter; G lanes cooperate on one sample (G = 1: one lane
+// per sample with cursor-advancing binary searches; G > 1: the group scans the
+// driver row G entries at a time, tests membership lane-parallel and counts
+// with ballot + popcount).  Any G gives the same samples.
+//
+// Sums: each lane accumulates X into a 192-bit and X^2 into a 320-bit integer;
+// the block turns them into 32-bit digits, adds, normalises and writes a
+// 20-word partial; a second kernel adds the partials.  Integer addition makes
+// the result independent of the schedule.
+#include "sgpm_internal.h"
+
+namespace sgpm {
+
+__device__ __forceinline__ uint64_t philox_r64(uint64_t seed, uint64_t s, uint32_t d, uint32_t tag) {
+    uint32_t c0 = (uint32_t)s, c1 = (uint32_t)(s >> 32), c2 = d, c3 = tag;
+    uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+        const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return ((uint64_t)c1 << 32) | (uint64_t)c0;
+}
+
+// SplitMix64 finaliser (Steele, Lea, Flood 2014), used by the record hash.
+__device__ __forceinline__ uint64_t fmix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// first index in [lo, hi) of the ascending row with row[i] >= x
+__device__ __forceinline__ int32_t lower_bound(const int32_t* __restrict__ row, int32_t lo, int32_t hi, int32_t x) {
+    while (lo < hi) {
+        const int32_t mid = (int32_t)(((uint32_t)lo + (uint32_t)hi) >> 1);
+        if (row[mid] < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ void add_carry(uint64_t& acc, uint64_t x, uint64_t& carry) {
+    const uint64_t t = acc + x;
+    const uint64_t c1 = t < x;
+    const uint64_t t2 = t + carry;
+    const uint64_t c2 = t2 < carry;
+    acc = t2;
+    carry = c1 + c2;
+}
+
+struct Acc {
+    uint64_t s1[3];   // sum X, 192 bits
+    uint64_t s2[5];   // sum X^2, 320 bits
+    uint64_t hits, csum, bytes, ovf;
+};
+
+__device__ __forceinline__ void acc_add(Acc& a, uint64_t lo, uint64_t hi) {
+    uint64_t c = 0;
+    add_carry(a.s1[0], lo, c);
+    add_carry(a.s1[1], hi, c);
+    a.s1[2] += c;
+    // X^2 = lo^2 + 2 lo hi 2^64 + hi^2 2^128
+    uint64_t w0 = lo * lo, w1 = __umul64hi(lo, lo), w2 = 0, w3 = 0;
+    if (hi) {
+        const uint64_t m0 = lo * hi, m1 = __umul64hi(lo, hi);
+        const uint64_t d0 = m0 << 1, d1 = (m1 << 1) | (m0 >> 63), d2 = m1 >> 63;
+        const uint64_t h0 = hi * hi, h1 = __umul64hi(hi, hi);
+        uint64_t cc = 0;
+        add_carry(w1, d0, cc);
+        w2 = d1;
+        add_carry(w2, h0, cc);
+        w3 = d2;
+        add_carry(w3, h1, cc);
+    }
+    c = 0;
+    add_carry(a.s2[0], w0, c);
+    add_carry(a.s2[1], w1, c);
+    add_carry(a.s2[2], w2, c);
+    add_carry(a.s2[3], w3, c);
+    a.s2[4] += c;
+}
+
+template <int G>
+__device__ __forceinline__ uint64_t group_ballot(bool pred, uint64_t gmask) {
+    return __ballot(pred) & gmask;
+}
+
+// One NS-prune sample.  Returns 0xFF for a hit, else the failing position j.
+// For G > 1 all G lanes of a group call it with the same s.
+template <int G>
+__device__ __forceinline__ uint32_t ns_sample(const DGraph& g, const Plan& p, uint64_t seed, uint32_t tag, uint64_t s,
+                                             int32_t (&v)[8], uint64_t& alo, uint64_t& ahi, uint64_t& ovf,
+                                             uint64_t& bytes, bool count_bytes) {
+    const int lane = (int)(threadIdx.x & 63);
+    const int gl = lane & (G - 1);
+    const int gbase = lane & ~(G - 1);
+    const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << gbase);
+
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = -1;
+    const uint64_t M = p.oriented ? (uint64_t)g.m : 2ull * (uint64_t)g.m;
+    const uint64_t e = __umul64hi(M, philox_r64(seed, s, 0, tag));
+    if (p.oriented) {
+        const int2 pr = g.epair[e];
+        v[0] = pr.x;
+        v[1] = pr.y;
+    } else {
+        v[0] = g.arow[e];
+        v[1] = g.nbr[e];
+    }
+    const int32_t* rp[8];
+    int32_t rl[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        rp[i] = nullptr;
+        rl[i] = 0;
+    }
+    {
+        const int64_t b0 = g.off[v[0]], e0 = g.off[v[0] + 1];
+        const int64_t b1 = g.off[v[1]], e1 = g.off[v[1] + 1];
+        rp[0] = g.nbr + b0;
+        rl[0] = (int32_t)(e0 - b0);
+        rp[1] = g.nbr + b1;
+        rl[1] = (int32_t)(e1 - b1);
+    }
+    alo = M;
+    ahi = 0;
+    bytes = 8;
+    uint32_t opened = 0;
+
+#pragma unroll
+    for (int j = 2; j < 8; ++j) {
+        if (j >= p.k) break;
+        const uint32_t conn = p.connect[j], disc = p.disconnect[j], up = p.upper[j], lw = p.lower[j];
+        int32_t lo = -1, hi = 0x7FFFFFFF;
+#pragma unroll
+        for (int i = 0; i < j; ++i) {
+            if (up >> i & 1) hi = min(hi, v[i]);
+            if (lw >> i & 1) lo = max(lo, v[i]);
+        }
+        // driver row: the smallest connected earlier row (lowest position on ties)
+        int d = -1;
+        int32_t dl = 0x7FFFFFFF;
+        const int32_t* dp = nullptr;
+#pragma unroll
+        for (int i = 0; i < j; ++i)
+            if ((conn >> i & 1) && rl[i] < dl) {
+                d = i;
+                dl = rl[i];
+                dp = rp[i];
+            }
+        if (count_bytes) {
+            const uint32_t rows = conn | disc;
+#pragma unroll
+            for (int i = 0; i < j; ++i)
+                if ((rows >> i & 1) && !(opened >> i & 1)) {
+                    bytes += 16;
+                    opened |= 1u << i;
+                }
+        }
+        const int32_t start = lo >= 0 ? lower_bound(dp, 0, dl, lo + 1) : 0;
+
+        // candidate test for x drawn from the driver row (x < hi, x > lo already)
+        // cursors (G == 1) advance monotonically because x increases.
+        int32_t cur[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) cur[i] = 0;
+        auto valid = [&](int32_t x) -> bool {
+            bool ok = true;
+#pragma unroll
+            for (int i = 0; i < j; ++i)
+                if (!((conn >> i) & 1)) ok = ok && (x != v[i]);
+#pragma unroll
+            for (int i = 0; i < j; ++i) {
+                if (((conn >> i) & 1) && i != d && ok) {
+                    const int32_t q = lower_bound(rp[i], G == 1 ? cur[i] : 0, rl[i], x);
+                    if (G == 1) cur[i] = q;
+                    ok = q < rl[i] && rp[i][q] == x;
+                }
+                if (((disc >> i) & 1) && ok) {
+                    const int32_t q = lower_bound(rp[i], G == 1 ? cur[i] : 0, rl[i], x);
+                    if (G == 1) cur[i] = q;
+                    ok = !(q < rl[i] && rp[i][q] == x);
+                }
+            }
+            return ok;
+        };
+
+        // count pass
+        uint32_t cnt = 0;
+        int32_t wend = start;
+        if (G == 1) {
+            int32_t pos = start;
+            for (; pos < dl; ++pos) {
+                const int32_t x = dp[pos];
+                if (x >= hi) break;
+                cnt += valid(x) ? 1u : 0u;
+            }
+            wend = pos;
+        } else {
+            for (int32_t base = start; base < dl; base += G) {
+                const int32_t pos = base + gl;
+                const int32_t x = pos < dl ? dp[pos] : 0x7FFFFFFF;
+                const bool in = x < hi;
+                const bool ok = in && valid(x);
+                const uint64_t okm = group_ballot<G>(ok, gmask);
+                const uint64_t inm = group_ballot<G>(in, gmask);
+                cnt += (uint32_t)__popcll(okm);
+                wend += (int32_t)__popcll(inm);
+                if (inm != gmask) break;
+            }
+        }
+        if (count_bytes) bytes += 4ull * (uint64_t)(wend - start);
+        if (cnt == 0) return (uint32_t)j;
+
+        const uint32_t idx = (uint32_t)__umul64hi((uint64_t)cnt, philox_r64(seed, s, (uint32_t)j, tag));
+        int32_t pick = -1;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) cur[i] = 0;
+        if (G == 1) {
+            uint32_t seen = 0;
+            for (int32_t pos = start; pos < dl; ++pos) {
+                const int32_t x = dp[pos];
+                if (x >= hi) break;
+                if (valid(x)) {
+                    if (seen == idx) {
+                        pick = x;
+                        break;
+                    }
+                    ++seen;
+                }
+            }
+        } else {
+            uint32_t seen = 0;
+            for (int32_t base = start; base < dl; base += G) {
+                const int32_t pos = base + gl;
+                const int32_t x = pos < dl ? dp[pos] : 0x7FFFFFFF;
+                const bool ok = x < hi && valid(x);
+                uint64_t okm = group_ballot<G>(ok, gmask);
+                const uint32_t c = (uint32_t)__popcll(okm);
+                if (seen + c > idx) {
+                    for (uint32_t t = idx - seen; t > 0; --t) okm &= okm - 1ull;
+                    const int sel = __ffsll((unsigned long long)okm) - 1;
+                    pick = __shfl(x, sel);
+                    break;
+                }
+                seen += c;
+            }
+        }
+        if (pick < 0) {  // count and select passes disagree: report, never index with it
+            ovf = 1;
+            return (uint32_t)j;
+        }
+        v[j] = pick;
+        if (j + 1 < p.k) {
+            const int64_t bj = g.off[pick], ej = g.off[pick + 1];
+            rp[j] = g.nbr + bj;
+            rl[j] = (int32_t)(ej - bj);
+        }
+        // alpha *= |S_j| with 128-bit overflow detection
+        const uint64_t plo = alo * (uint64_t)cnt, phi = __umul64hi(alo, (uint64_t)cnt);
+        const uint64_t qlo = ahi * (uint64_t)cnt, qhi = __umul64hi(ahi, (uint64_t)cnt);
+        const uint64_t nhi = phi + qlo;
+        if (qhi != 0 || nhi < qlo) ovf = 1;
+        alo = plo;
+        ahi = nhi;
+    }
+    return 0xFFu;
+}
+
+__device__ __forceinline__ uint64_t wave_sum(uint64_t x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    return x;
+}
+
+template <int G>
+__global__ __launch_bounds__(256) void ns_window_kernel(DGraph g, Plan p, uint64_t seed, uint32_t tag, uint64_t s0,
+                                                        uint64_t s1, int spl, unsigned long long* __restrict__ ticket,
+                                                        unsigned long long* __restrict__ partials, int checksum,
+                                                        int count_bytes, TraceArgs tr) {
+    const int lane = (int)(threadIdx.x & 63);
+    const bool leader = (lane & (G - 1)) == 0;
+    const uint64_t per_wave = (uint64_t)(64 / G) * (uint64_t)spl;
+    Acc a;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) a.s1[i] = 0;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) a.s2[i] = 0;
+    a.hits = a.csum = a.bytes = a.ovf = 0;
+
+    for (;;) {
+        unsigned long long t = 0;
+        if (lane == 0) t = atomicAdd(ticket, 1ull);
+        t = __shfl(t, 0);
+        const uint64_t base = s0 + (uint64_t)t * per_wave;
+        if (base >= s1) break;
+        for (int q = 0; q < spl; ++q) {
+            const uint64_t s = base + (uint64_t)q * (uint64_t)(64 / G) + (uint64_t)(lane / G);
+            if (s >= s1) break;
+            int32_t v[8];
+            uint64_t alo, ahi, b = 0;
+            const uint32_t st = ns_sample<G>(g, p, seed, tag, s, v, alo, ahi, a.ovf, b, count_bytes != 0);
+            if (!leader) continue;
+            if (st != 0xFFu) {
+                alo = 0;
+                ahi = 0;
+            } else {
+                a.hits += 1;
+                acc_add(a, alo, ahi);
+            }
+            a.bytes += b;
+            if (checksum) {
+                uint64_t h = fmix64(s ^ 0x9E3779B97F4A7C15ull);
+                h = fmix64(h ^ (uint64_t)st);
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    if (i < p.k) h = fmix64(h ^ (uint64_t)(uint32_t)v[i]);
+                h = fmix64(h ^ alo);
+                h = fmix64(h ^ ahi);
+                a.csum += h;
+            }
+            if (tr.buf && s >= tr.lo && s < tr.hi) {
+                sgpm_trace_rec* r = tr.buf + (s - tr.lo);
+                r->s = s;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) r->v[i] = v[i];
+                r->status = st;
+                r->k = (uint32_t)p.k;
+                r->alpha_lo = alo;
+                r->alpha_hi = ahi;
+            }
+        }
+    }
+
+    // block reduction into 32-bit digits
+    unsigned long long f[PF_N];
+    f[0] = a.s1[0] & 0xFFFFFFFFull;
+    f[1] = a.s1[0] >> 32;
+    f[2] = a.s1[1] & 0xFFFFFFFFull;
+    f[3] = a.s1[1] >> 32;
+    f[4] = a.s1[2] & 0xFFFFFFFFull;
+    f[5] = a.s1[2] >> 32;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        f[6 + 2 * i] = a.s2[i] & 0xFFFFFFFFull;
+        f[7 + 2 * i] = a.s2[i] >> 32;
+    }
+    f[PF_HITS] = a.hits;
+    f[PF_CSUM] = a.csum;
+    f[PF_BYTES] = a.bytes;
+    f[PF_OVF] = a.ovf;
+    __shared__ unsigned long long red[4][PF_N];
+    const int w = (int)(threadIdx.x >> 6);
+#pragma unroll
+    for (int i = 0; i < PF_N; ++i) {
+        const unsigned long long x = wave_sum(f[i]);
+        if (lane == 0) red[w][i] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long o[PF_N];
+#pragma unroll
+        for (int i = 0; i < PF_N; ++i) o[i] = red[0][i] + red[1][i] + red[2][i] + red[3][i];
+        // normalise digit blocks (S1: 6 digits, S2: 10 digits)
+        // (the top digit of each block keeps any excess; the host adds digits
+        // with full carries)
+        unsigned long long c = 0;
+        for (int i = 0; i < 5; ++i) {
+            const unsigned long long t = o[i] + c;
+            o[i] = t & 0xFFFFFFFFull;
+            c = t >> 32;
+        }
+        o[5] += c;
+        c = 0;
+        for (int i = 6; i < 15; ++i) {
+            const unsigned long long t = o[i] + c;
+            o[i] = t & 0xFFFFFFFFull;
+            c = t >> 32;
+        }
+        o[15] += c;
+        unsigned long long* dst = partials + (size_t)blockIdx.x * PF_N;
+        for (int i = 0; i < PF_N; ++i) dst[i] = o[i];
+    }
+}
+
+__global__ __launch_bounds__(256) void reduce_partials_kernel(const unsigned long long* __restrict__ partials,
+                                                              int nblocks, unsigned long long* __restrict__ out) {
+    unsigned long long acc[PF_N];
+#pragma unroll
+    for (int i = 0; i < PF_N; ++i) acc[i] = 0;
+    for (int b = (int)threadIdx.x; b < nblocks; b += (int)blockDim.x)
+#pragma unroll
+        for (int i = 0; i < PF_N; ++i) acc[i] += partials[(size_t)b * PF_N + i];
+    __shared__ unsigned long long red[4][PF_N];
+    const int lane = (int)(threadIdx.x & 63), w = (int)(threadIdx.x >> 6);
+#pragma unroll
+    for (int i = 0; i < PF_N; ++i) {
+        const unsigned long long x = wave_sum(acc[i]);
+        if (lane == 0) red[w][i] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < PF_N) {
+        const int i = (int)threadIdx.x;
+        out[i] = red[0][i] + red[1][i] + red[2][i] + red[3][i];
+    }
+}
+
+__global__ void fill_u64_kernel(unsigned long long* p, uint64_t n, unsigned long long v) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_u64(unsigned long long* p, uint64_t n, unsigned long long v, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(fill_u64_kernel, dim3(blocks), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_ns_window(const DGraph& g, const Plan& p, uint64_t seed, uint32_t tag, uint64_t s0, uint64_t s1,
+                            const LaunchCfg& cfg, unsigned long long* ticket, unsigned long long* partials,
+                            int checksum, int count_bytes, const TraceArgs& tr, hipStream_t st) {
+    const dim3 grid((unsigned)cfg.blocks), block(256);
+    switch (cfg.lanes) {
+        case 1:
+            hipLaunchKernelGGL(ns_window_kernel<1>, grid, block, 0, st, g, p, seed, tag, s0, s1, cfg.spl, ticket,
+                               partials, checksum, count_bytes, tr);
+            break;
+        case 4:
+            hipLaunchKernelGGL(ns_window_kernel<4>, grid, block, 0, st, g, p, seed, tag, s0, s1, cfg.spl, ticket,
+                               partials, checksum, count_bytes, tr);
+            break;
+        case 16:
+            hipLaunchKernelGGL(ns_window_kernel<16>, grid, block, 0, st, g, p, seed, tag, s0, s1, cfg.spl, ticket,
+                               partials, checksum, count_bytes, tr);
+            break;
+        case 64:
+            hipLaunchKernelGGL(ns_window_kernel<64>, grid, block, 0, st, g, p, seed, tag, s0, s1, cfg.spl, ticket,
+                               partials, checksum, count_bytes, tr);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_partials(const unsigned long long* partials, int nblocks, unsigned long long* out20,
+                                  hipStream_t st) {
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(256), 0, st, partials, nblocks, out20);
+    return hipGetLastError();
+}
+
+}  // namespace sgpm
