@@ -79,6 +79,13 @@ def lib():
     if _lib is None:
         if not os.path.exists(SO_PATH):
             raise RuntimeError(f"{SO_PATH} is missing: build it with __graft_entry__.build()")
+        # PyTorch ships its own HIP runtime; loading it first makes libsgpm bind to
+        # that same runtime (same soname), so torch streams and device pointers are
+        # valid inside the library and only one runtime owns the device.
+        try:
+            import torch  # noqa: F401
+        except Exception:
+            pass
         L = C.CDLL(SO_PATH)
         P = C.c_void_p
         PP = C.POINTER(C.c_void_p)

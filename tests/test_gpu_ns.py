@@ -69,6 +69,14 @@ def c1(S, O, synth, ctx):
     S.sgpm_graph_free(g)
 
 
+def test_torch_shares_the_hip_runtime(S, ctx):
+    import torch
+    assert torch.cuda.is_available()
+    x = torch.ones(1 << 20, device="cuda")
+    torch.cuda.synchronize()
+    assert float(x.sum()) == float(1 << 20)
+
+
 def test_graph_upload_matches_oracle(S, c1, ctx):
     g, og = c1
     off, nbr = S.sgpm_graph_export(ctx, g)
