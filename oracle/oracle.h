@@ -101,9 +101,19 @@ int orc_ns_run(const orc_graph* g, const orc_plan* p, const orc_ns_opts* o, orc_
                double* eps_trace, uint64_t* n_trace, int trace_cap);
 
 double orc_norm_ppf(double p);
+double orc_digits_to_double(const uint32_t* d, int nd);
 double orc_eps_hat(double z, uint64_t n, const uint32_t* s1, int n1, const uint32_t* s2, int n2);
 uint64_t orc_window_next(uint64_t n_t, const orc_ns_opts* o);
 
+typedef struct {
+    double estimate, eps_hat, z;
+    uint64_t reps, nonzero;
+    uint32_t s1[8], s2[12];
+    int32_t converged;
+} orc_gs_result;
+
+int orc_gs_run(const orc_graph* g, const orc_plan* p, uint32_t c, uint64_t seed, double eps, double confidence,
+               int reps_max, int nthreads, orc_gs_result* r, uint64_t* y_per_rep);
 int32_t orc_gs_colour(uint64_t seed, uint32_t rep, uint32_t c, int64_t v);
 int orc_gs_sparsify(const orc_graph* g, const int32_t* colour, orc_graph* out);
 void orc_gs_count(const orc_graph* g, const orc_plan* p, uint32_t c, uint64_t seed, uint32_t rep,

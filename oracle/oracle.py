@@ -60,6 +60,19 @@ class NsResult(C.Structure):
         return sum(int(d) << (32 * i) for i, d in enumerate(self.s2))
 
 
+class GsResult(C.Structure):
+    _fields_ = [("estimate", C.c_double), ("eps_hat", C.c_double), ("z", C.c_double), ("reps", C.c_uint64),
+                ("nonzero", C.c_uint64), ("s1", C.c_uint32 * 8), ("s2", C.c_uint32 * 12), ("converged", C.c_int32)]
+
+    @property
+    def S1(self) -> int:
+        return sum(int(d) << (32 * i) for i, d in enumerate(self.s1))
+
+    @property
+    def S2(self) -> int:
+        return sum(int(d) << (32 * i) for i, d in enumerate(self.s2))
+
+
 def lib():
     global _lib
     if _lib is None:
@@ -101,6 +114,10 @@ def lib():
         L.orc_gs_sparsify.argtypes = [G, P, G]
         L.orc_gs_count.argtypes = [G, PL, C.c_uint32, C.c_uint64, C.c_uint32, C.c_int,
                                    C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
+        L.orc_digits_to_double.argtypes = [P, C.c_int]
+        L.orc_digits_to_double.restype = C.c_double
+        L.orc_gs_run.argtypes = [G, PL, C.c_uint32, C.c_uint64, C.c_double, C.c_double, C.c_int, C.c_int,
+                                 C.POINTER(GsResult), P]
         _lib = L
     return _lib
 
@@ -356,3 +373,16 @@ def exact_expectation(g: OGraph, p: Plan) -> Fraction:
     for e in range(M):
         walk([r_for(e, M), 0], 2, Fraction(1, M))
     return total
+
+
+def gs_run(g: OGraph, p: Plan, c, seed, eps=0.01, confidence=0.95, reps_max=64, threads=None):
+    r = GsResult()
+    ys = np.zeros(reps_max, dtype=np.uint64)
+    lib().orc_gs_run(g.ref(), C.byref(p), c, seed, eps, confidence, reps_max, threads or nthreads(), C.byref(r),
+                     ys.ctypes.data)
+    return r, ys[:r.reps].tolist()
+
+
+def digits_to_double(x: int) -> float:
+    d = np.array([(x >> (32 * i)) & 0xFFFFFFFF for i in range(24)], dtype=np.uint32)
+    return float(lib().orc_digits_to_double(d.ctypes.data, 24))

@@ -54,3 +54,50 @@ void orc_gs_count(const orc_graph* g, const orc_plan* p, uint32_t c, uint64_t se
     orc_graph_free(&sp);
     free(colour);
 }
+
+/* GS estimate over repeated colourings: X_r = c^(k-1) * Y_r for rep r = 0, 1, ...
+ * treated as i.i.d. samples through the NS-online statistics (Sec. 4.1); stop
+ * at the first n >= 2 with eps_hat <= eps, or after reps_max colourings. */
+static void add_digits(uint32_t* acc, int nd, const uint64_t* cols, int nc) {
+    unsigned __int128 carry = 0;
+    for (int i = 0; i < nd; i++) {
+        unsigned __int128 t = carry + acc[i];
+        if (i < nc) t += cols[i];
+        acc[i] = (uint32_t)t;
+        carry = t >> 32;
+    }
+}
+
+int orc_gs_run(const orc_graph* g, const orc_plan* p, uint32_t c, uint64_t seed, double eps, double confidence,
+               int reps_max, int nthreads, orc_gs_result* r, uint64_t* y_per_rep) {
+    memset(r, 0, sizeof(*r));
+    double z = orc_norm_ppf(1.0 - (1.0 - confidence) / 2.0);
+    unsigned __int128 scale = 1;
+    for (int i = 0; i < p->k - 1; i++) scale *= c;
+    for (int rep = 0; rep < reps_max; rep++) {
+        uint64_t lo, hi;
+        orc_gs_count(g, p, c, seed, (uint32_t)rep, nthreads, &lo, &hi);
+        if (y_per_rep) y_per_rep[rep] = lo;
+        unsigned __int128 y = ((unsigned __int128)hi << 64) | lo;
+        unsigned __int128 x = y * scale;
+        uint64_t d[4], sq[8];
+        for (int i = 0; i < 4; i++) d[i] = (uint32_t)(x >> (32 * i));
+        memset(sq, 0, sizeof(sq));
+        for (int a = 0; a < 4; a++)
+            for (int b = 0; b < 4; b++) {
+                uint64_t pr = d[a] * d[b];
+                sq[a + b] += pr & 0xFFFFFFFFu;
+                if (a + b + 1 < 8) sq[a + b + 1] += pr >> 32;
+            }
+        add_digits(r->s1, 8, d, 4);
+        add_digits(r->s2, 12, sq, 8);
+        r->reps++;
+        if (y) r->nonzero++;
+        r->eps_hat = orc_eps_hat(z, r->reps, r->s1, 8, r->s2, 12);
+        if (r->reps >= 2 && r->eps_hat <= eps) { r->converged = 1; break; }
+    }
+    /* estimate = S1 / n with S1 rounded once */
+    r->estimate = orc_digits_to_double(r->s1, 8) / (double)r->reps;
+    r->z = z;
+    return 0;
+}

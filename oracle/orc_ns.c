@@ -297,6 +297,14 @@ double orc_norm_ppf(double p) {
     return (double)(0.5L * (lo + hi));
 }
 
+/* Correctly rounded double of a little-endian 32-bit digit integer. */
+double orc_digits_to_double(const uint32_t* d, int nd) {
+    obig a;
+    ob_zero(&a);
+    for (int i = 0; i < nd && i < OB; i++) a.d[i] = d[i];
+    return ob_to_double(&a);
+}
+
 double orc_eps_hat(double z, uint64_t n, const uint32_t* s1, int n1, const uint32_t* s2, int n2) {
     obig S1, S2, N, a, b;
     ob_zero(&S1); ob_zero(&S2); ob_zero(&N);

@@ -13,7 +13,8 @@ OUT = os.path.join(ROOT, "_build")
 SO = os.path.join(HERE, "libsgpm.so")
 ARCH = os.environ.get("SGPM_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["api.cpp", "host_graph.cpp", "host_pattern.cpp", "host_stats.cpp", "ns_kernels.hip"]
+SOURCES = ["api.cpp", "gs.cpp", "host_graph.cpp", "host_pattern.cpp", "host_stats.cpp", "ns_kernels.hip",
+           "gs_kernels.hip"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-ffp-contract=off", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

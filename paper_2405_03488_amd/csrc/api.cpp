@@ -2,6 +2,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -10,49 +12,14 @@
 
 using namespace sgpm;
 
-struct sgpm_ctx {
-    int dev = 0;
-    hipStream_t st = nullptr;
-    std::string err;
-    int cus = 256;
-    // scratch reused across calls
-    unsigned long long* d_partials = nullptr;
-    size_t partial_blocks = 0;
-    unsigned long long* d_slots = nullptr;   // per launch: ticket + 20 sums (+ pad) = 32 words
-    unsigned long long* h_slots = nullptr;   // pinned mirror of the sums
-    size_t nslots = 0;
-    std::vector<hipEvent_t> kev;             // start/stop events around each sampling kernel
-};
-
-struct sgpm_graph {
-    sgpm_ctx* ctx = nullptr;
-    int64_t n = 0, m = 0, maxdeg = 0;
-    std::vector<int32_t> perm;
-    int64_t* d_off = nullptr;
-    int32_t* d_nbr = nullptr;
-    int2* d_epair = nullptr;
-    int32_t* d_arow = nullptr;
-    DGraph view() const { return DGraph{d_off, d_nbr, d_epair, d_arow, n, m}; }
-};
-
-struct sgpm_pattern {
-    Plan plan;
-};
+namespace sgpm {
+sgpm_status gs_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_options& o, sgpm_result* res);
+}
 
 namespace {
 
 constexpr int SLOT_WORDS = 32;  // [0] ticket, [1..20] sums
 
-sgpm_status fail(sgpm_ctx* c, sgpm_status s, const std::string& msg) {
-    if (c) c->err = msg;
-    return s;
-}
-
-#define HIP_TRY(ctx, expr)                                                                    \
-    do {                                                                                      \
-        hipError_t _e = (expr);                                                               \
-        if (_e != hipSuccess) return fail((ctx), SGPM_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
-    } while (0)
 
 sgpm_status ensure_scratch(sgpm_ctx* c, size_t blocks, size_t slots) {
     if (blocks > c->partial_blocks) {
@@ -77,9 +44,14 @@ sgpm_status ensure_scratch(sgpm_ctx* c, size_t blocks, size_t slots) {
 }
 
 int blocks_for(sgpm_ctx* c, int lanes) {
-    // resident blocks of 256 threads per CU for the sampling kernel (register bound)
-    (void)lanes;
-    return c->cus * 6;
+    // enough 256-thread blocks to fill every CU at the kernel's occupancy
+    return c->cus * ns_blocks_per_cu(lanes);
+}
+
+int largest_grid(sgpm_ctx* c) {
+    int m = 1;
+    for (int l : {1, 4, 16, 64}) m = std::max(m, blocks_for(c, l));
+    return m;
 }
 
 }  // namespace
@@ -271,14 +243,24 @@ sgpm_status enqueue_range(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_
                           int lanes, size_t slot, const TraceArgs& tr, int count_bytes) {
     LaunchCfg cfg;
     cfg.lanes = lanes;
-    cfg.spl = 4;
     cfg.blocks = blocks_for(c, lanes);
+    // Tickets of about 1/16 of a wave's share: few enough that the single
+    // ticket counter is not the bottleneck, many enough to balance skewed
+    // per-sample work across waves.
+    {
+        const uint64_t waves = (uint64_t)cfg.blocks * 4, groups_per_wave = (uint64_t)(64 / lanes);
+        const uint64_t per_group = (s1 - s0) / (waves * groups_per_wave * 16);
+        cfg.spl = (int)std::min<uint64_t>(256, std::max<uint64_t>(1, per_group));
+    }
+    bool dynamic = true;
+    if (const char* e = std::getenv("SGPM_SPL")) cfg.spl = std::max(1, std::atoi(e));
+    if (const char* e = std::getenv("SGPM_DYNAMIC")) dynamic = std::atoi(e) != 0;
     const uint64_t per_wave = (uint64_t)(64 / lanes) * (uint64_t)cfg.spl;
     const uint64_t tickets = (s1 - s0 + per_wave - 1) / per_wave;
     const uint64_t max_blocks = (tickets + 3) / 4;
     if ((uint64_t)cfg.blocks > max_blocks) cfg.blocks = (int)std::max<uint64_t>(1, max_blocks);
     // partials sized for the largest grid once, so no buffer in flight is freed
-    sgpm_status st = ensure_scratch(c, (size_t)blocks_for(c, lanes), slot + 1);
+    sgpm_status st = ensure_scratch(c, (size_t)largest_grid(c), slot + 1);
     if (st != SGPM_OK) return st;
     unsigned long long* sl = c->d_slots + slot * SLOT_WORDS;
     HIP_TRY(c, launch_fill_u64(sl, SLOT_WORDS, 0ull, c->st));
@@ -288,8 +270,8 @@ sgpm_status enqueue_range(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_
         c->kev.push_back(ev);
     }
     HIP_TRY(c, hipEventRecord(c->kev[2 * slot], c->st));
-    HIP_TRY(c, launch_ns_window(g->view(), p, o.seed, o.query_tag, s0, s1, cfg, sl, c->d_partials, o.checksum,
-                                count_bytes, tr, c->st));
+    HIP_TRY(c, launch_ns_window(g->view(), p, o.seed, o.query_tag, s0, s1, cfg, dynamic ? sl : nullptr,
+                                c->d_partials, o.checksum, count_bytes, tr, c->st));
     HIP_TRY(c, hipEventRecord(c->kev[2 * slot + 1], c->st));
     HIP_TRY(c, launch_reduce_partials(c->d_partials, cfg.blocks, sl + 1, c->st));
     HIP_TRY(c, hipMemcpyAsync(c->h_slots + slot * SLOT_WORDS, sl, SLOT_WORDS * sizeof(unsigned long long),
@@ -373,6 +355,9 @@ sgpm_status ns_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_op
                 (void)hipEventDestroy(x0);
                 (void)hipEventDestroy(x1);
                 const float per = ms / (float)(b - a);
+                if (std::getenv("SGPM_DEBUG"))
+                    std::fprintf(stderr, "sgpm autotune: lanes=%d %.3f ms for %llu samples (%.4g samples/s)\n",
+                                 cand[i], ms, (unsigned long long)(b - a), (double)(b - a) / (ms * 1e-3));
                 if (i == 0 || per < best_ms) {
                     best_ms = per;
                     best = cand[i];
@@ -453,6 +438,8 @@ sgpm_status sgpm_estimate(sgpm_ctx_t c, sgpm_graph_t g, sgpm_pattern_t p, const 
         case SGPM_MODE_STRICT_NS:
         case SGPM_MODE_FIXED_N:
             return ns_estimate(c, g, p->plan, *o, res, 0);
+        case SGPM_MODE_GS:
+            return gs_estimate(c, g, p->plan, *o, res);
         default:
             return fail(c, SGPM_EUNSUPPORTED, "mode not available");
     }
@@ -518,12 +505,6 @@ extern "C" {
 sgpm_status sgpm_estimate_batch(sgpm_ctx_t c, int, const sgpm_graph_t*, const sgpm_pattern_t*, const sgpm_options*,
                                 sgpm_result*) {
     return fail(c, SGPM_EUNSUPPORTED, "batch estimation is not built");
-}
-sgpm_status sgpm_exact_count(sgpm_ctx_t c, sgpm_graph_t, sgpm_pattern_t, uint64_t*, uint64_t*) {
-    return fail(c, SGPM_EUNSUPPORTED, "exact count is not built");
-}
-sgpm_status sgpm_gs_sparsify(sgpm_ctx_t c, sgpm_graph_t, uint32_t, uint64_t, uint32_t, sgpm_graph_t*) {
-    return fail(c, SGPM_EUNSUPPORTED, "sparsification is not built");
 }
 sgpm_status sgpm_model_train(sgpm_ctx_t c, sgpm_graph_t, const sgpm_pattern_t*, int, const sgpm_train_cfg*,
                              sgpm_model_t*) {

@@ -1,0 +1,201 @@
+// GS engine host side: colour sparsification into a new graph handle, the
+// exact count, and the GS estimate over repeated colourings.
+//
+// Sec. 5.2: the estimate from one colouring with c colours is c^(k-1) * Y for a
+// connected k-vertex pattern (all k vertices must share a colour), Y the exact
+// count on the sparsified graph.  The paper gives GS no online confidence
+// test; here independent colourings (rep = 0, 1, ...) are treated as i.i.d.
+// samples X_r = c^(k-1) Y_r and run through the same exact-integer statistics
+// and stop rule as NS (Sec. 4.1), capped at gs_reps_max colourings.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+
+#include "sgpm_internal.h"
+
+namespace sgpm {
+
+namespace {
+
+struct DevBuf {
+    void* p = nullptr;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+}  // namespace
+
+sgpm_status sparsify(sgpm_ctx* c, sgpm_graph* g, uint32_t colours, uint64_t seed, uint32_t rep, sgpm_graph** out) {
+    if (colours < 1 || colours > 256) return fail(c, SGPM_EINVAL, "colours must be in [1, 256]");
+    HIP_TRY(c, hipSetDevice(c->dev));
+    const int64_t n = g->n;
+    DevBuf col, kept, klow, scratch;
+    HIP_TRY(c, hipMalloc(&col.p, (size_t)std::max<int64_t>(n, 1)));
+    HIP_TRY(c, hipMalloc(&kept.p, sizeof(int64_t) * (size_t)std::max<int64_t>(n, 1)));
+    HIP_TRY(c, hipMalloc(&klow.p, sizeof(int64_t) * (size_t)std::max<int64_t>(n, 1)));
+    HIP_TRY(c, hipMalloc(&scratch.p, sizeof(int64_t) * (size_t)scan_scratch_words(n)));
+    auto h = std::make_unique<sgpm_graph>();
+    h->ctx = c;
+    h->n = n;
+    h->perm = g->perm;
+    HIP_TRY(c, hipMalloc(&h->d_off, sizeof(int64_t) * (size_t)(n + 1)));
+    int64_t* d_eoff = nullptr;
+    HIP_TRY(c, hipMalloc(&d_eoff, sizeof(int64_t) * (size_t)(n + 1)));
+    std::unique_ptr<int64_t, void (*)(int64_t*)> eguard(d_eoff, [](int64_t* q) { (void)hipFree(q); });
+    const DGraph dg = g->view();
+    HIP_TRY(c, gs_colours(n, colours, seed, rep, (uint8_t*)col.p, c->st));
+    HIP_TRY(c, gs_row_counts(dg, (uint8_t*)col.p, (int64_t*)kept.p, (int64_t*)klow.p, c->st));
+    if (n > 0) {
+        HIP_TRY(c, exclusive_scan((int64_t*)kept.p, n, h->d_off, (int64_t*)scratch.p, c->st));
+        HIP_TRY(c, exclusive_scan((int64_t*)klow.p, n, d_eoff, (int64_t*)scratch.p, c->st));
+    } else {
+        HIP_TRY(c, hipMemsetAsync(h->d_off, 0, sizeof(int64_t), c->st));
+        HIP_TRY(c, hipMemsetAsync(d_eoff, 0, sizeof(int64_t), c->st));
+    }
+    int64_t arcs = 0, edges = 0;
+    HIP_TRY(c, hipMemcpyAsync(&arcs, h->d_off + n, sizeof(int64_t), hipMemcpyDeviceToHost, c->st));
+    HIP_TRY(c, hipMemcpyAsync(&edges, d_eoff + n, sizeof(int64_t), hipMemcpyDeviceToHost, c->st));
+    HIP_TRY(c, hipStreamSynchronize(c->st));
+    if (arcs != 2 * edges) return fail(c, SGPM_EHIP, "internal: sparsified graph is not symmetric");
+    h->m = edges;
+    HIP_TRY(c, hipMalloc(&h->d_nbr, sizeof(int32_t) * (size_t)std::max<int64_t>(arcs, 1)));
+    HIP_TRY(c, hipMalloc(&h->d_arow, sizeof(int32_t) * (size_t)std::max<int64_t>(arcs, 1)));
+    HIP_TRY(c, hipMalloc(&h->d_epair, sizeof(int2) * (size_t)std::max<int64_t>(edges, 1)));
+    HIP_TRY(c, gs_compact(dg, (uint8_t*)col.p, h->d_off, d_eoff, h->d_nbr, h->d_arow, h->d_epair, c->st));
+    unsigned long long* d_md = (unsigned long long*)kept.p;  // reuse as the max-degree cell
+    HIP_TRY(c, launch_fill_u64(d_md, 1, 0ull, c->st));
+    HIP_TRY(c, max_degree(h->d_off, n, d_md, c->st));
+    unsigned long long md = 0;
+    HIP_TRY(c, hipMemcpyAsync(&md, d_md, sizeof(md), hipMemcpyDeviceToHost, c->st));
+    HIP_TRY(c, hipStreamSynchronize(c->st));
+    h->maxdeg = (int64_t)md;
+    *out = h.release();
+    return SGPM_OK;
+}
+
+// exact count of the plan's tuples on g (the leaves of the pruned search tree)
+sgpm_status exact_count(sgpm_ctx* c, sgpm_graph* g, const Plan& p, unsigned __int128* out, double* seconds) {
+    HIP_TRY(c, hipSetDevice(c->dev));
+    const uint64_t nfirst = p.oriented ? (uint64_t)g->m : 2ull * (uint64_t)g->m;
+    *out = 0;
+    if (nfirst == 0) return SGPM_OK;
+    const int blocks = c->cus * exact_blocks_per_cu();
+    const uint64_t waves = (uint64_t)blocks * 4;
+    const int per_ticket = (int)std::min<uint64_t>(4096, std::max<uint64_t>(1, nfirst / (waves * 32)));
+    DevBuf part, cell;
+    HIP_TRY(c, hipMalloc(&part.p, sizeof(unsigned long long) * 2 * (size_t)blocks));
+    HIP_TRY(c, hipMalloc(&cell.p, sizeof(unsigned long long) * 4));
+    unsigned long long* d = (unsigned long long*)cell.p;
+    HIP_TRY(c, launch_fill_u64(d, 4, 0ull, c->st));
+    hipEvent_t e0, e1;
+    HIP_TRY(c, hipEventCreate(&e0));
+    HIP_TRY(c, hipEventCreate(&e1));
+    HIP_TRY(c, hipEventRecord(e0, c->st));
+    HIP_TRY(c, launch_exact_count(g->view(), p, nfirst, blocks, per_ticket, d, (unsigned long long*)part.p, d + 2,
+                                  c->st));
+    HIP_TRY(c, hipEventRecord(e1, c->st));
+    unsigned long long two[2];
+    HIP_TRY(c, hipMemcpyAsync(two, d + 2, sizeof(two), hipMemcpyDeviceToHost, c->st));
+    HIP_TRY(c, hipStreamSynchronize(c->st));
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (seconds) *seconds = ms * 1e-3;
+    *out = (unsigned __int128)two[0] + ((unsigned __int128)two[1] << 32);
+    return SGPM_OK;
+}
+
+sgpm_status gs_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_options& o, sgpm_result* res) {
+    auto t0 = std::chrono::steady_clock::now();
+    std::memset(res, 0, sizeof(*res));
+    res->scheme = SGPM_SCHEME_GS;
+    const uint32_t col = o.colours > 0 ? (uint32_t)o.colours : 8u;
+    if (col > 256) return fail(c, SGPM_EINVAL, "colours must be in [1, 256]");
+    const int reps = o.gs_reps_max > 0 ? o.gs_reps_max : 64;
+    const double z = normal_quantile(1.0 - (1.0 - o.confidence) / 2.0);
+    // c^(k-1) as an exact integer
+    unsigned __int128 scale = 1;
+    for (int i = 0; i < p.k - 1; i++) scale *= col;
+    Big S1(24), S2(24);
+    uint64_t n = 0, nonzero = 0;
+    double dev = 0.0;
+    bool converged = false;
+    for (int r = 0; r < reps; r++) {
+        sgpm_graph* sp = nullptr;
+        sgpm_status st = sparsify(c, g, col, o.seed, (uint32_t)r, &sp);
+        if (st != SGPM_OK) return st;
+        unsigned __int128 y = 0;
+        double secs = 0;
+        st = exact_count(c, sp, p, &y, &secs);
+        sgpm_graph_free(sp);
+        if (st != SGPM_OK) return st;
+        dev += secs;
+        const unsigned __int128 x = y * scale;
+        if (scale && x / scale != y) return fail(c, SGPM_EOVERFLOW, "GS estimate exceeds 128 bits");
+        unsigned long long d1[4], d2[8];
+        for (int i = 0; i < 4; i++) d1[i] = (unsigned long long)(uint32_t)(x >> (32 * i));
+        // x^2 as 32-bit digit columns (each < 2^35: low and high halves of the digit products)
+        for (int i = 0; i < 8; i++) d2[i] = 0;
+        for (int a = 0; a < 4; a++)
+            for (int b = 0; b < 4; b++) {
+                const unsigned long long pr = d1[a] * d1[b];
+                d2[a + b] += pr & 0xFFFFFFFFull;
+                if (a + b + 1 < 8) d2[a + b + 1] += pr >> 32;
+            }
+        big_add_digits(S1, d1, 4);
+        big_add_digits(S2, d2, 8);
+        n++;
+        if (y) nonzero++;
+        const double eh = predicted_error(z, n, S1, S2);
+        if (n >= 2 && eh <= o.eps) {
+            converged = true;
+            break;
+        }
+    }
+    res->n_samples = n;
+    res->n_hits = nonzero;
+    for (int i = 0; i < 8; i++) res->sum_digits[i] = S1.d[(size_t)i];
+    for (int i = 0; i < 12; i++) res->sumsq_digits[i] = S2.d[(size_t)i];
+    res->estimate = big_to_double(S1) / (double)n;
+    res->eps_hat = predicted_error(z, n, S1, S2);
+    res->z = z;
+    const double sigma = std::isfinite(res->eps_hat) ? res->estimate * res->eps_hat / z : INFINITY;
+    res->ci_lo = res->estimate - z * sigma;
+    res->ci_hi = res->estimate + z * sigma;
+    res->colours = (int32_t)col;
+    res->converged = converged ? 1 : 0;
+    res->windows = (int32_t)n;
+    res->seconds_kernel = dev;
+    res->seconds_sampling = dev;
+    res->seconds_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (!converged) return fail(c, SGPM_NOT_CONVERGED, "gs_reps_max colourings reached");
+    return SGPM_OK;
+}
+
+}  // namespace sgpm
+
+using namespace sgpm;
+
+extern "C" {
+
+sgpm_status sgpm_gs_sparsify(sgpm_ctx_t c, sgpm_graph_t g, uint32_t colours, uint64_t seed, uint32_t rep,
+                             sgpm_graph_t* out) {
+    if (!c || !g || !out) return fail(c, SGPM_EINVAL, "null argument");
+    return sparsify(c, g, colours, seed, rep, out);
+}
+
+sgpm_status sgpm_exact_count(sgpm_ctx_t c, sgpm_graph_t g, sgpm_pattern_t p, uint64_t* count_lo, uint64_t* count_hi) {
+    if (!c || !g || !p || !count_lo) return fail(c, SGPM_EINVAL, "null argument");
+    unsigned __int128 v = 0;
+    sgpm_status st = exact_count(c, g, p->plan, &v, nullptr);
+    if (st != SGPM_OK) return st;
+    *count_lo = (uint64_t)v;
+    if (count_hi) *count_hi = (uint64_t)(v >> 64);
+    return SGPM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,509 @@
+// Graph-sparsification (GS) engine for gfx950: colour sparsification and the
+// plan-driven exact count.
+//
+// Colour sparsification (Sec. 2.2 subgraph sampling, Sec. 5.2): every vertex
+// gets colour floor(c * r / 2^64), r the Philox4x32-10 value of key = seed and
+// counter = (v lo, v hi, 0, 0x40000000 | rep); an edge survives when both
+// endpoints share a colour.  The sparsified graph G' keeps the vertex ids, so
+// it is the disjoint union of the colour classes and counting on G' is
+// counting on every class (the paper's partition-parallel search, Sec. 5.4).
+// Passes: colours -> per-row kept counts -> exclusive scans -> compaction of
+// rows, arc rows and oriented edges.  Rows are streamed once per pass
+// (coalesced, 16 lanes per row); colours are one byte per vertex.
+//
+// Exact count (GS exact search, Sec. 4.4 nested loops): for every first edge
+// the nested loops of the same plan NS-prune samples from, enumerating every
+// candidate instead of one and counting the last level's candidates.  One wave
+// per first edge; the per-level loop state (chunk of 64 candidates, its valid
+// mask, merge cursors, walk vertices) lives in LDS so the depth is a runtime
+// value.
+#include "sgpm_internal.h"
+
+namespace sgpm {
+
+namespace {
+
+constexpr int32_t GBIG = 0x7FFFFFFF;
+
+__device__ __forceinline__ uint64_t philox_colour_r64(uint64_t seed, uint64_t v, uint32_t tag) {
+    uint32_t c0 = (uint32_t)v, c1 = (uint32_t)(v >> 32), c2 = 0u, c3 = tag;
+    uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+        const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return ((uint64_t)c1 << 32) | (uint64_t)c0;
+}
+
+__global__ void max_degree_kernel(const int64_t* __restrict__ off, int64_t n, unsigned long long* __restrict__ out) {
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long d = u < n ? (unsigned long long)(off[u + 1] - off[u]) : 0ull;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long t = __shfl_xor(d, o);
+        d = t > d ? t : d;
+    }
+    if ((threadIdx.x & 63) == 0 && d) atomicMax(out, d);
+}
+
+__global__ void colour_kernel(int64_t n, uint32_t c, uint64_t seed, uint32_t rep, uint8_t* __restrict__ col) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    col[v] = (uint8_t)__umul64hi((uint64_t)c, philox_colour_r64(seed, (uint64_t)v, 0x40000000u | rep));
+}
+
+// 16 lanes per row: kept[u] = same-colour neighbours, klow[u] = those below u
+__global__ __launch_bounds__(256) void row_count_kernel(DGraph g, const uint8_t* __restrict__ col,
+                                                        int64_t* __restrict__ kept, int64_t* __restrict__ klow) {
+    const int lane = (int)(threadIdx.x & 63), sub = lane & 15, gbase = lane & ~15;
+    const uint64_t gmask = 0xFFFFull << gbase;
+    const int64_t u = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+    if (u >= g.n) return;
+    const int64_t b = g.off[u], e = g.off[u + 1];
+    const uint8_t cu = col[u];
+    int64_t k = 0, kl = 0;
+    for (int64_t a = b + sub; a < e; a += 16) {
+        const int32_t w = g.nbr[a];
+        if (col[w] == cu) {
+            k++;
+            if (w < u) kl++;
+        }
+    }
+    // reduce within the 16-lane group
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) {
+        k += __shfl_xor(k, o, 16);
+        kl += __shfl_xor(kl, o, 16);
+    }
+    (void)gmask;
+    if (sub == 0) {
+        kept[u] = k;
+        klow[u] = kl;
+    }
+}
+
+__global__ __launch_bounds__(256) void compact_kernel(DGraph g, const uint8_t* __restrict__ col,
+                                                      const int64_t* __restrict__ noff,
+                                                      const int64_t* __restrict__ eoff, int32_t* __restrict__ nnbr,
+                                                      int32_t* __restrict__ narow, int2* __restrict__ nepair) {
+    const int lane = (int)(threadIdx.x & 63), sub = lane & 15, gbase = lane & ~15;
+    const uint64_t gmask = 0xFFFFull << gbase;
+    const uint64_t below = (1ull << lane) - 1ull;
+    const int64_t u = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+    if (u >= g.n) return;
+    const int64_t b = g.off[u], e = g.off[u + 1];
+    const uint8_t cu = col[u];
+    int64_t pos = noff[u], epos = eoff[u];
+    for (int64_t base = b; base < e; base += 16) {
+        const int64_t a = base + sub;
+        const int32_t w = a < e ? g.nbr[a] : GBIG;
+        const bool keep = a < e && col[w] == cu;
+        const uint64_t km = __ballot(keep) & gmask;
+        const uint64_t lm = __ballot(keep && w < u) & gmask;
+        if (keep) {
+            const int64_t at = pos + __popcll(km & below);
+            nnbr[at] = w;
+            narow[at] = (int32_t)u;
+            if (w < u) nepair[epos + __popcll(lm & below)] = make_int2((int32_t)u, w);
+        }
+        pos += __popcll(km);
+        epos += __popcll(lm);
+    }
+}
+
+// exclusive scan of int64 counts: out[0..n] with out[n] = total
+constexpr int SCAN_TILE = 2048;  // 256 threads x 8
+
+__global__ __launch_bounds__(256) void scan_block_sums(const int64_t* __restrict__ in, int64_t n,
+                                                       int64_t* __restrict__ bsum) {
+    const int64_t t0 = (int64_t)blockIdx.x * SCAN_TILE;
+    int64_t s = 0;
+    for (int i = 0; i < 8; ++i) {
+        const int64_t k = t0 + (int64_t)threadIdx.x * 8 + i;
+        if (k < n) s += in[k];
+    }
+    __shared__ int64_t red[256];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) bsum[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(1024) void scan_block_offsets(int64_t* __restrict__ bsum, int64_t nb) {
+    // exclusive scan of nb block sums in place by one block
+    __shared__ int64_t part[1024];
+    const int64_t per = (nb + 1023) / 1024;
+    const int64_t b0 = (int64_t)threadIdx.x * per, b1 = b0 + per < nb ? b0 + per : nb;
+    int64_t s = 0;
+    for (int64_t b = b0; b < b1; ++b) s += bsum[b];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t run = 0;
+        for (int i = 0; i < 1024; ++i) {
+            const int64_t t = part[i];
+            part[i] = run;
+            run += t;
+        }
+    }
+    __syncthreads();
+    int64_t run = part[threadIdx.x];
+    for (int64_t b = b0; b < b1; ++b) {
+        const int64_t t = bsum[b];
+        bsum[b] = run;
+        run += t;
+    }
+}
+
+__global__ __launch_bounds__(256) void scan_finish(const int64_t* __restrict__ in, int64_t n,
+                                                   const int64_t* __restrict__ boff, int64_t* __restrict__ out) {
+    const int64_t t0 = (int64_t)blockIdx.x * SCAN_TILE;
+    int64_t v[8];
+    int64_t s = 0;
+    for (int i = 0; i < 8; ++i) {
+        const int64_t k = t0 + (int64_t)threadIdx.x * 8 + i;
+        v[i] = k < n ? in[k] : 0;
+        s += v[i];
+    }
+    __shared__ int64_t part[256];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    // Hillis-Steele inclusive scan of the 256 thread sums
+    for (int st = 1; st < 256; st <<= 1) {
+        const int64_t add = (int)threadIdx.x >= st ? part[threadIdx.x - st] : 0;
+        __syncthreads();
+        part[threadIdx.x] += add;
+        __syncthreads();
+    }
+    int64_t run = boff[blockIdx.x] + part[threadIdx.x] - s;
+    for (int i = 0; i < 8; ++i) {
+        const int64_t k = t0 + (int64_t)threadIdx.x * 8 + i;
+        if (k < n) out[k] = run;
+        run += v[i];
+        if (k == n - 1) out[n] = run;
+    }
+}
+
+// ------------------------------------------------------------------ exact count
+__device__ __forceinline__ int32_t grfl(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// membership of each lane's x in an ascending row, 64-lane window merge (see the
+// NS kernels for the same scheme); c is the wave-uniform cursor
+__device__ __forceinline__ bool wave_member(const int32_t* __restrict__ R, int32_t rl, int32_t& c, int32_t x, bool act,
+                                            int32_t xmax, int lane) {
+    bool found = false, pending = act;
+    for (;;) {
+        const int32_t b = (c + lane < rl) ? R[c + lane] : GBIG;
+        const int32_t bmax = grfl(__shfl(b, 63));
+        int pos = 0;
+#pragma unroll
+        for (int st = 32; st >= 1; st >>= 1) {
+            const int32_t bv = __shfl(b, pos + st - 1);
+            if (bv < x) pos += st;
+        }
+        const int32_t bq = __shfl(b, pos < 64 ? pos : 63);
+        const bool res = pending && x <= bmax;
+        if (res) found = pos < 64 && bq == x;
+        pending = pending && !res;
+        if (__ballot(pending) == 0) {
+            c += (int32_t)__popcll(__ballot(b < xmax));
+            break;
+        }
+        c += 64;
+    }
+    return found;
+}
+
+// plan masks packed 8 bits per position, indexable by a runtime position
+struct PackedPlan {
+    uint64_t connect, disconnect, upper, lower;
+    int32_t k, oriented;
+};
+__device__ __forceinline__ uint32_t pk(uint64_t m, int j) { return (uint32_t)(m >> (8 * j)) & 0xFFu; }
+
+struct Level {          // per-wave, per-level loop state (LDS)
+    int32_t base;       // next chunk start in the driver row
+    int32_t ended;      // the driver window is exhausted
+    int32_t d;          // driver position
+    int32_t lo, hi;     // bounds
+    uint32_t pad;
+    unsigned long long mask;  // unvisited candidates of the current chunk
+    int32_t cur[8];     // merge cursors per constraint row
+    int32_t xs[64];     // current chunk's values
+};
+
+struct WaveState {
+    int32_t v[8];
+    int64_t rb[8];
+    int32_t rl[8];
+    Level lv[8];
+};
+
+// Evaluate the next chunk of level j's candidates; returns the valid mask and
+// stores the chunk in L.xs.
+__device__ __forceinline__ unsigned long long eval_level_chunk(const DGraph& g, const PackedPlan& p, int j,
+                                                               WaveState& W, Level& L, int lane, int32_t& x_out) {
+    const uint32_t conn = pk(p.connect, j), disc = pk(p.disconnect, j);
+    const int32_t* dp = g.nbr + W.rb[L.d];
+    const int32_t dl = W.rl[L.d];
+    const int32_t pos = L.base + lane;
+    const int32_t x = pos < dl ? dp[pos] : GBIG;
+    const bool act = x < L.hi;
+    const unsigned long long inm = __ballot(act);
+    bool ok = act && x > L.lo;
+    for (int i = 0; i < j; ++i)
+        if (!(conn >> i & 1)) ok = ok && x != W.v[i];
+    if (inm != 0) {
+        const int32_t xmax = grfl(__shfl(x, (int)__popcll(inm) - 1));
+        for (int i = 0; i < j; ++i) {
+            const bool isc = (conn >> i & 1) && i != L.d, isd = disc >> i & 1;
+            if (!isc && !isd) continue;
+            int32_t c = L.cur[i];
+            const bool f = wave_member(g.nbr + W.rb[i], W.rl[i], c, x, act, xmax, lane);
+            L.cur[i] = c;  // uniform: every lane stores the same value
+            ok = ok && (isc ? f : !f);
+        }
+    }
+    if (inm != ~0ull) L.ended = 1;
+    L.base += 64;
+    x_out = x;
+    return __ballot(ok);
+}
+
+__device__ __forceinline__ void init_level(const DGraph& g, const PackedPlan& p, int j, WaveState& W, Level& L,
+                                           int lane) {
+    const uint32_t conn = pk(p.connect, j), up = pk(p.upper, j), lw = pk(p.lower, j);
+    int32_t lo = -1, hi = GBIG, d = -1, dl = GBIG;
+    for (int i = 0; i < j; ++i) {
+        if (up >> i & 1) hi = min(hi, W.v[i]);
+        if (lw >> i & 1) lo = max(lo, W.v[i]);
+        if ((conn >> i & 1) && W.rl[i] < dl) {
+            d = i;
+            dl = W.rl[i];
+        }
+    }
+    int32_t start = 0;
+    if (lo >= 0) {
+        const int32_t* dp = g.nbr + W.rb[d];
+        int32_t a = 0, b = dl;
+        while (a < b) {
+            const int32_t mid = (a + b) >> 1;
+            if (dp[mid] < lo + 1) a = mid + 1;
+            else b = mid;
+        }
+        start = a;
+    }
+    // uniform values: every lane stores the same, so each lane's later reads
+    // follow its own writes in program order
+    L.base = start;
+    L.ended = 0;
+    L.d = d;
+    L.lo = lo;
+    L.hi = hi;
+    L.mask = 0;
+    for (int i = 0; i < 8; ++i) L.cur[i] = 0;
+}
+
+__global__ __launch_bounds__(256) void exact_count_kernel(DGraph g, PackedPlan p, uint64_t nfirst, int per_ticket,
+                                                          unsigned long long* __restrict__ ticket,
+                                                          unsigned long long* __restrict__ partials) {
+    const int lane = (int)(threadIdx.x & 63), w = (int)(threadIdx.x >> 6);
+    __shared__ WaveState ws[4];
+    WaveState& W = ws[w];
+    unsigned long long total = 0;
+    const int k = p.k;
+    for (;;) {
+        unsigned long long t = 0;
+        if (lane == 0) t = atomicAdd(ticket, 1ull);
+        t = __shfl(t, 0);
+        const uint64_t e0 = (uint64_t)t * (uint64_t)per_ticket;
+        if (e0 >= nfirst) break;
+        const uint64_t e1 = e0 + (uint64_t)per_ticket < nfirst ? e0 + (uint64_t)per_ticket : nfirst;
+        for (uint64_t e = e0; e < e1; ++e) {
+            int32_t v0, v1;
+            if (p.oriented) {
+                const int2 pr = g.epair[e];
+                v0 = pr.x;
+                v1 = pr.y;
+            } else {
+                v0 = g.arow[e];
+                v1 = g.nbr[e];
+            }
+            if (k == 2) {
+                total += 1;
+                continue;
+            }
+            {
+                const int64_t b0 = g.off[v0], b1 = g.off[v1];
+                const int32_t l0 = (int32_t)(g.off[v0 + 1] - b0), l1 = (int32_t)(g.off[v1 + 1] - b1);
+                W.v[0] = v0;
+                W.v[1] = v1;
+                W.rb[0] = b0;
+                W.rl[0] = l0;
+                W.rb[1] = b1;
+                W.rl[1] = l1;
+            }
+            __builtin_amdgcn_wave_barrier();
+            int j = 2;
+            init_level(g, p, 2, W, W.lv[2], lane);
+            __builtin_amdgcn_wave_barrier();
+            while (j >= 2) {
+                Level& L = W.lv[j];
+                if (j == k - 1) {
+                    // last level: count every candidate
+                    while (!L.ended) {
+                        int32_t x;
+                        const unsigned long long okm = eval_level_chunk(g, p, j, W, L, lane, x);
+                        __builtin_amdgcn_wave_barrier();
+                        total += (unsigned long long)__popcll(okm);
+                    }
+                    --j;
+                    continue;
+                }
+                if (L.mask == 0) {
+                    if (L.ended) {
+                        --j;
+                        continue;
+                    }
+                    int32_t x;
+                    const unsigned long long okm = eval_level_chunk(g, p, j, W, L, lane, x);
+                    L.xs[lane] = x;
+                    L.mask = okm;
+                    __builtin_amdgcn_wave_barrier();
+                    continue;
+                }
+                const unsigned long long m = L.mask;
+                const int bit = __ffsll(m) - 1;
+                const int32_t vj = grfl(L.xs[bit]);
+                {
+                    const int64_t bj = g.off[vj];
+                    const int32_t lj = (int32_t)(g.off[vj + 1] - bj);
+                    L.mask = m & (m - 1ull);
+                    W.v[j] = vj;
+                    W.rb[j] = bj;
+                    W.rl[j] = lj;
+                }
+                __builtin_amdgcn_wave_barrier();
+                ++j;
+                init_level(g, p, j, W, W.lv[j], lane);
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+    }
+    __shared__ unsigned long long red[4];
+    if (lane == 0) red[w] = total;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // two 32-bit halves so the final sum is exact in 64-bit words
+        unsigned long long lo = 0, hi = 0;
+        for (int i = 0; i < 4; ++i) {
+            lo += red[i] & 0xFFFFFFFFull;
+            hi += red[i] >> 32;
+        }
+        partials[2 * blockIdx.x] = lo;
+        partials[2 * blockIdx.x + 1] = hi;
+    }
+}
+
+__global__ void sum_pairs_kernel(const unsigned long long* __restrict__ partials, int nblocks,
+                                 unsigned long long* __restrict__ out2) {
+    __shared__ unsigned long long a[256], b[256];
+    unsigned long long lo = 0, hi = 0;
+    for (int i = (int)threadIdx.x; i < nblocks; i += (int)blockDim.x) {
+        lo += partials[2 * i];
+        hi += partials[2 * i + 1];
+    }
+    a[threadIdx.x] = lo;
+    b[threadIdx.x] = hi;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long L = 0, H = 0;
+        for (int i = 0; i < 256; ++i) {
+            L += a[i];
+            H += b[i];
+        }
+        out2[0] = L;  // sum of low halves
+        out2[1] = H;  // sum of high halves (weight 2^32)
+    }
+}
+
+}  // namespace
+
+hipError_t gs_colours(int64_t n, uint32_t c, uint64_t seed, uint32_t rep, uint8_t* col, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(colour_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, c, seed, rep, col);
+    return hipGetLastError();
+}
+
+hipError_t gs_row_counts(const DGraph& g, const uint8_t* col, int64_t* kept, int64_t* klow, hipStream_t st) {
+    if (g.n == 0) return hipSuccess;
+    const uint64_t threads = (uint64_t)g.n * 16;
+    hipLaunchKernelGGL(row_count_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, g, col, kept,
+                       klow);
+    return hipGetLastError();
+}
+
+hipError_t gs_compact(const DGraph& g, const uint8_t* col, const int64_t* noff, const int64_t* eoff, int32_t* nnbr,
+                      int32_t* narow, int2* nepair, hipStream_t st) {
+    if (g.n == 0) return hipSuccess;
+    const uint64_t threads = (uint64_t)g.n * 16;
+    hipLaunchKernelGGL(compact_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, g, col, noff, eoff,
+                       nnbr, narow, nepair);
+    return hipGetLastError();
+}
+
+hipError_t max_degree(const int64_t* off, int64_t n, unsigned long long* out, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(max_degree_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, off, n, out);
+    return hipGetLastError();
+}
+
+int64_t scan_scratch_words(int64_t n) { return (n + SCAN_TILE - 1) / SCAN_TILE + 1; }
+
+hipError_t exclusive_scan(const int64_t* in, int64_t n, int64_t* out, int64_t* scratch, hipStream_t st) {
+    const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    if (nb == 0) return hipMemcpyAsync(out, scratch, 0, hipMemcpyDeviceToDevice, st);
+    hipLaunchKernelGGL(scan_block_sums, dim3((unsigned)nb), dim3(256), 0, st, in, n, scratch);
+    hipLaunchKernelGGL(scan_block_offsets, dim3(1), dim3(1024), 0, st, scratch, nb);
+    hipLaunchKernelGGL(scan_finish, dim3((unsigned)nb), dim3(256), 0, st, in, n, scratch, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_exact_count(const DGraph& g, const Plan& p, uint64_t nfirst, int blocks, int per_ticket,
+                              unsigned long long* ticket, unsigned long long* partials, unsigned long long* out2,
+                              hipStream_t st) {
+    PackedPlan pp{};
+    for (int j = 0; j < 8; ++j) {
+        pp.connect |= (uint64_t)p.connect[j] << (8 * j);
+        pp.disconnect |= (uint64_t)p.disconnect[j] << (8 * j);
+        pp.upper |= (uint64_t)p.upper[j] << (8 * j);
+        pp.lower |= (uint64_t)p.lower[j] << (8 * j);
+    }
+    pp.k = p.k;
+    pp.oriented = p.oriented;
+    hipLaunchKernelGGL(exact_count_kernel, dim3((unsigned)blocks), dim3(256), 0, st, g, pp, nfirst, per_ticket, ticket,
+                       partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(sum_pairs_kernel, dim3(1), dim3(256), 0, st, partials, blocks, out2);
+    return hipGetLastError();
+}
+
+int exact_blocks_per_cu() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, exact_count_kernel, 256, 0) != hipSuccess || nb < 1) nb = 2;
+    return nb;
+}
+
+}  // namespace sgpm

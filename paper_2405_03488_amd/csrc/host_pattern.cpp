@@ -123,6 +123,13 @@ int compile_pattern(int k, int l, const int32_t* edges, int induced, Plan& out, 
             else if (induced) out.disconnect[j] |= (uint8_t)(1u << i);
         }
     out.oriented = (out.upper[1] & 1) ? 1 : 0;
+    // steps whose constraint set contains the previous step's can filter the
+    // previous candidate set instead of scanning a row again
+    for (int j = 3; j < k; j++) {
+        auto sub = [](uint8_t a, uint8_t b) { return (a & ~b) == 0; };
+        out.reuse[j] = sub(out.connect[j - 1], out.connect[j]) && sub(out.disconnect[j - 1], out.disconnect[j]) &&
+                       sub(out.upper[j - 1], out.upper[j]) && sub(out.lower[j - 1], out.lower[j]);
+    }
     return SGPM_OK;
 }
 

@@ -105,21 +105,89 @@ __device__ __forceinline__ void acc_add(Acc& a, uint64_t lo, uint64_t hi) {
     a.s2[4] += c;
 }
 
+constexpr int32_t BIG = 0x7FFFFFFF;
+
+// With one sample per wave (G = 64) every per-sample value is wave-uniform;
+// readfirstlane tells the compiler so, which keeps the walk state in SGPRs
+// and turns its branches into scalar branches.
+__device__ __forceinline__ int32_t rfl(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+template <int G>
+__device__ __forceinline__ int32_t uni(int32_t x) {
+    if constexpr (G == 64) return rfl(x);
+    else return x;
+}
+constexpr int LDS_WORDS = 4096;  // candidate lists per block (16 KB)
+
+// first index in [lo, hi) with row[i] >= x, galloping forward from lo
+__device__ __forceinline__ int32_t gallop(const int32_t* __restrict__ row, int32_t lo, int32_t hi, int32_t x) {
+    if (lo >= hi || row[lo] >= x) return lo;
+    int32_t prev = lo, step = 1;
+    for (;;) {
+        const int32_t nxt = prev + step;
+        if (nxt >= hi) return lower_bound(row, prev + 1, hi, x);
+        if (row[nxt] >= x) return lower_bound(row, prev + 1, nxt, x);
+        prev = nxt;
+        step <<= 1;
+    }
+}
+
 template <int G>
 __device__ __forceinline__ uint64_t group_ballot(bool pred, uint64_t gmask) {
     return __ballot(pred) & gmask;
 }
 
+// Membership of each lane's x in the ascending row R[0, rl) for a group whose
+// active lanes hold ascending values (xmax = the largest).  The group-uniform
+// cursor c only moves forward: entries before it are below every x still to
+// come.  G = 1: galloping search.  G > 1: the group loads G consecutive row
+// entries, every lane binary-searches its x among them through shuffles, and
+// the window slides until no active lane's x lies beyond it.
+template <int G>
+__device__ __forceinline__ bool member(const int32_t* __restrict__ R, int32_t rl, int32_t& c, int32_t x, bool act,
+                                       int32_t xmax, int gbase, int gl, uint64_t gmask) {
+    if constexpr (G == 1) {
+        if (!act) return false;
+        const int32_t q = gallop(R, c, rl, x);
+        c = q;
+        return q < rl && R[q] == x;
+    } else {
+        bool found = false, pending = act;
+        for (;;) {
+            const int32_t b = (c + gl < rl) ? R[c + gl] : BIG;
+            const int32_t bmax = uni<G>(__shfl(b, gbase + G - 1));
+            int pos = 0;
+#pragma unroll
+            for (int st = G / 2; st >= 1; st >>= 1) {
+                const int32_t bv = __shfl(b, gbase + pos + st - 1);
+                if (bv < x) pos += st;
+            }
+            const int32_t bq = __shfl(b, gbase + (pos < G ? pos : G - 1));
+            const bool res = pending && x <= bmax;
+            if (res) found = pos < G && bq == x;
+            pending = pending && !res;
+            if (group_ballot<G>(pending, gmask) == 0) {
+                c += (int32_t)__popcll(group_ballot<G>(b < xmax, gmask));
+                break;
+            }
+            c += G;
+        }
+        return found;
+    }
+}
+
 // One NS-prune sample.  Returns 0xFF for a hit, else the failing position j.
-// For G > 1 all G lanes of a group call it with the same s.
+// For G > 1 all G lanes of a group call it with the same s.  `list` is the
+// group's LDS area of CAP words holding the current candidate set.
 template <int G>
 __device__ __forceinline__ uint32_t ns_sample(const DGraph& g, const Plan& p, uint64_t seed, uint32_t tag, uint64_t s,
                                              int32_t (&v)[8], uint64_t& alo, uint64_t& ahi, uint64_t& ovf,
-                                             uint64_t& bytes, bool count_bytes) {
+                                             uint64_t& bytes, bool count_bytes, int32_t* list) {
+    constexpr int CAP = LDS_WORDS / (256 / G);
     const int lane = (int)(threadIdx.x & 63);
     const int gl = lane & (G - 1);
     const int gbase = lane & ~(G - 1);
     const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << gbase);
+    const uint64_t below = (1ull << lane) - 1ull;
 
 #pragma unroll
     for (int i = 0; i < 8; ++i) v[i] = -1;
@@ -152,20 +220,21 @@ __device__ __forceinline__ uint32_t ns_sample(const DGraph& g, const Plan& p, ui
     ahi = 0;
     bytes = 8;
     uint32_t opened = 0;
+    int32_t prevcnt = -1;  // |S_{j-1}| when the whole set sits in `list`
 
 #pragma unroll
     for (int j = 2; j < 8; ++j) {
         if (j >= p.k) break;
         const uint32_t conn = p.connect[j], disc = p.disconnect[j], up = p.upper[j], lw = p.lower[j];
-        int32_t lo = -1, hi = 0x7FFFFFFF;
+        int32_t lo = -1, hi = BIG;
 #pragma unroll
         for (int i = 0; i < j; ++i) {
             if (up >> i & 1) hi = min(hi, v[i]);
             if (lw >> i & 1) lo = max(lo, v[i]);
         }
-        // driver row: the smallest connected earlier row (lowest position on ties)
+        // smallest connected earlier row (lowest position on ties)
         int d = -1;
-        int32_t dl = 0x7FFFFFFF;
+        int32_t dl = BIG;
         const int32_t* dp = nullptr;
 #pragma unroll
         for (int i = 0; i < j; ++i)
@@ -182,95 +251,100 @@ __device__ __forceinline__ uint32_t ns_sample(const DGraph& g, const Plan& p, ui
                     bytes += 16;
                     opened |= 1u << i;
                 }
+            const int32_t w0 = lo >= 0 ? lower_bound(dp, 0, dl, lo + 1) : 0;
+            const int32_t w1 = hi < BIG ? lower_bound(dp, w0, dl, hi) : dl;
+            bytes += 4ull * (uint64_t)(w1 - w0);
         }
-        const int32_t start = lo >= 0 ? lower_bound(dp, 0, dl, lo + 1) : 0;
-
-        // candidate test for x drawn from the driver row (x < hi, x > lo already)
-        // cursors (G == 1) advance monotonically because x increases.
+        // Reuse: when step j's constraints contain step j-1's, S_j is the part
+        // of S_{j-1} (already in `list`) that meets the extra constraints.
+        const bool reuse = (j >= 3) && p.reuse[j] && prevcnt >= 0;
+        uint32_t need_conn, need_disc, excl;
+        const int32_t* src;
+        int32_t slen, start;
+        if (reuse) {
+            need_conn = conn & ~(uint32_t)p.connect[j - 1];
+            need_disc = disc & ~(uint32_t)p.disconnect[j - 1];
+            excl = (1u << (j - 1)) & ~conn;
+            src = list;
+            slen = prevcnt;
+            start = 0;
+        } else {
+            need_conn = conn & ~(1u << d);
+            need_disc = disc;
+            excl = ((1u << j) - 1u) & ~conn;
+            src = dp;
+            slen = dl;
+            start = lo >= 0 ? lower_bound(dp, 0, dl, lo + 1) : 0;
+        }
         int32_t cur[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) cur[i] = 0;
-        auto valid = [&](int32_t x) -> bool {
-            bool ok = true;
+        // candidates of one chunk of G source entries; advances the cursors
+        auto eval_chunk = [&](int32_t base, int32_t& x, uint64_t& inm) -> bool {
+            const int32_t pos = base + gl;
+            x = pos < slen ? src[pos] : BIG;
+            const bool act = x < hi;
+            inm = group_ballot<G>(act, gmask);
+            bool ok = act && x > lo;
 #pragma unroll
             for (int i = 0; i < j; ++i)
-                if (!((conn >> i) & 1)) ok = ok && (x != v[i]);
+                if (excl >> i & 1) ok = ok && (x != v[i]);
+            if (inm == 0) return false;
+            const int32_t xmax = uni<G>(__shfl(x, gbase + (int)__popcll(inm) - 1));
 #pragma unroll
             for (int i = 0; i < j; ++i) {
-                if (((conn >> i) & 1) && i != d && ok) {
-                    const int32_t q = lower_bound(rp[i], G == 1 ? cur[i] : 0, rl[i], x);
-                    if (G == 1) cur[i] = q;
-                    ok = q < rl[i] && rp[i][q] == x;
+                if (need_conn >> i & 1) {
+                    const bool f = member<G>(rp[i], rl[i], cur[i], x, act, xmax, gbase, gl, gmask);
+                    ok = ok && f;
                 }
-                if (((disc >> i) & 1) && ok) {
-                    const int32_t q = lower_bound(rp[i], G == 1 ? cur[i] : 0, rl[i], x);
-                    if (G == 1) cur[i] = q;
-                    ok = !(q < rl[i] && rp[i][q] == x);
+                if (need_disc >> i & 1) {
+                    const bool f = member<G>(rp[i], rl[i], cur[i], x, act, xmax, gbase, gl, gmask);
+                    ok = ok && !f;
                 }
             }
             return ok;
         };
 
-        // count pass
+        // count pass; candidates are appended to `list` while they fit (in place
+        // when reusing: a chunk is read before any of its slots is rewritten)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) cur[i] = 0;
         uint32_t cnt = 0;
-        int32_t wend = start;
-        if (G == 1) {
-            int32_t pos = start;
-            for (; pos < dl; ++pos) {
-                const int32_t x = dp[pos];
-                if (x >= hi) break;
-                cnt += valid(x) ? 1u : 0u;
-            }
-            wend = pos;
-        } else {
-            for (int32_t base = start; base < dl; base += G) {
-                const int32_t pos = base + gl;
-                const int32_t x = pos < dl ? dp[pos] : 0x7FFFFFFF;
-                const bool in = x < hi;
-                const bool ok = in && valid(x);
-                const uint64_t okm = group_ballot<G>(ok, gmask);
-                const uint64_t inm = group_ballot<G>(in, gmask);
-                cnt += (uint32_t)__popcll(okm);
-                wend += (int32_t)__popcll(inm);
-                if (inm != gmask) break;
-            }
+        for (int32_t base = start; base < slen; base += G) {
+            int32_t x;
+            uint64_t inm;
+            const bool ok = eval_chunk(base, x, inm);
+            const uint64_t okm = group_ballot<G>(ok, gmask);
+            const uint32_t rank = (uint32_t)__popcll(okm & below);
+            if (ok && cnt + rank < (uint32_t)CAP) list[cnt + rank] = x;
+            cnt += (uint32_t)__popcll(okm);
+            if (inm != gmask) break;
         }
-        if (count_bytes) bytes += 4ull * (uint64_t)(wend - start);
         if (cnt == 0) return (uint32_t)j;
 
         const uint32_t idx = (uint32_t)__umul64hi((uint64_t)cnt, philox_r64(seed, s, (uint32_t)j, tag));
         int32_t pick = -1;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) cur[i] = 0;
-        if (G == 1) {
-            uint32_t seen = 0;
-            for (int32_t pos = start; pos < dl; ++pos) {
-                const int32_t x = dp[pos];
-                if (x >= hi) break;
-                if (valid(x)) {
-                    if (seen == idx) {
-                        pick = x;
-                        break;
-                    }
-                    ++seen;
-                }
-            }
+        if (cnt <= (uint32_t)CAP) {
+            pick = uni<G>(list[idx]);
+            prevcnt = (int32_t)cnt;
         } else {
+            // the set overflowed the list (never when reusing): select by rescanning
+#pragma unroll
+            for (int i = 0; i < 8; ++i) cur[i] = 0;
             uint32_t seen = 0;
-            for (int32_t base = start; base < dl; base += G) {
-                const int32_t pos = base + gl;
-                const int32_t x = pos < dl ? dp[pos] : 0x7FFFFFFF;
-                const bool ok = x < hi && valid(x);
+            for (int32_t base = start; base < slen; base += G) {
+                int32_t x;
+                uint64_t inm;
+                const bool ok = eval_chunk(base, x, inm);
                 uint64_t okm = group_ballot<G>(ok, gmask);
                 const uint32_t c = (uint32_t)__popcll(okm);
                 if (seen + c > idx) {
                     for (uint32_t t = idx - seen; t > 0; --t) okm &= okm - 1ull;
-                    const int sel = __ffsll((unsigned long long)okm) - 1;
-                    pick = __shfl(x, sel);
+                    pick = uni<G>(__shfl(x, __ffsll((unsigned long long)okm) - 1));
                     break;
                 }
                 seen += c;
+                if (inm != gmask) break;
             }
+            prevcnt = -1;
         }
         if (pick < 0) {  // count and select passes disagree: report, never index with it
             ovf = 1;
@@ -307,6 +381,8 @@ __global__ __launch_bounds__(256) void ns_window_kernel(DGraph g, Plan p, uint64
     const int lane = (int)(threadIdx.x & 63);
     const bool leader = (lane & (G - 1)) == 0;
     const uint64_t per_wave = (uint64_t)(64 / G) * (uint64_t)spl;
+    __shared__ int32_t s_list[LDS_WORDS];
+    int32_t* list = s_list + (threadIdx.x / G) * (LDS_WORDS / (256 / G));
     Acc a;
 #pragma unroll
     for (int i = 0; i < 3; ++i) a.s1[i] = 0;
@@ -314,10 +390,18 @@ __global__ __launch_bounds__(256) void ns_window_kernel(DGraph g, Plan p, uint64
     for (int i = 0; i < 5; ++i) a.s2[i] = 0;
     a.hits = a.csum = a.bytes = a.ovf = 0;
 
+    // ticket == nullptr: static interleaving, wave w takes tickets w, w + W, ...
+    const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    uint64_t tstat = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     for (;;) {
         unsigned long long t = 0;
-        if (lane == 0) t = atomicAdd(ticket, 1ull);
-        t = __shfl(t, 0);
+        if (ticket) {
+            if (lane == 0) t = atomicAdd(ticket, 1ull);
+            t = __shfl(t, 0);
+        } else {
+            t = tstat;
+            tstat += nwaves;
+        }
         const uint64_t base = s0 + (uint64_t)t * per_wave;
         if (base >= s1) break;
         for (int q = 0; q < spl; ++q) {
@@ -325,7 +409,7 @@ __global__ __launch_bounds__(256) void ns_window_kernel(DGraph g, Plan p, uint64
             if (s >= s1) break;
             int32_t v[8];
             uint64_t alo, ahi, b = 0;
-            const uint32_t st = ns_sample<G>(g, p, seed, tag, s, v, alo, ahi, a.ovf, b, count_bytes != 0);
+            const uint32_t st = ns_sample<G>(g, p, seed, tag, s, v, alo, ahi, a.ovf, b, count_bytes != 0, list);
             if (!leader) continue;
             if (st != 0xFFu) {
                 alo = 0;
@@ -409,6 +493,122 @@ __global__ __launch_bounds__(256) void ns_window_kernel(DGraph g, Plan p, uint64
     }
 }
 
+// One sample per wave.  Exact sums live spread over the lanes: lanes 0-3 add
+// the 32-bit digits of X, lanes 8-15 the digit columns of X^2 (low and high
+// halves of the digit products), lane 20 hits, 21 the checksum, 22 bytes,
+// 23 the overflow flag.  Digit columns are normalised once per block.
+__global__ __launch_bounds__(256, 8) void ns_wave_kernel(DGraph g, Plan p, uint64_t seed, uint32_t tag, uint64_t s0,
+                                                      uint64_t s1, int spl, unsigned long long* __restrict__ ticket,
+                                                      unsigned long long* __restrict__ partials, int checksum,
+                                                      int count_bytes, TraceArgs tr) {
+    constexpr int G = 64;
+    const int lane = (int)(threadIdx.x & 63);
+    __shared__ int32_t s_list[LDS_WORDS];
+    int32_t* list = s_list + (threadIdx.x / G) * (LDS_WORDS / (256 / G));
+    uint64_t acc = 0;
+    uint64_t ovf = 0;
+    const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    uint64_t tstat = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    for (;;) {
+        uint64_t tt;
+        if (ticket) {
+            unsigned long long t = 0;
+            if (lane == 0) t = atomicAdd(ticket, 1ull);
+            tt = ((uint64_t)(uint32_t)rfl((int32_t)(__shfl(t, 0) >> 32)) << 32) | (uint32_t)rfl((int32_t)__shfl(t, 0));
+        } else {
+            tt = tstat;
+            tstat += nwaves;
+        }
+        const uint64_t base = s0 + tt * (uint64_t)spl;
+        if (base >= s1) break;
+        for (int q = 0; q < spl; ++q) {
+            const uint64_t s = base + (uint64_t)q;
+            if (s >= s1) break;
+            int32_t v[8];
+            uint64_t alo, ahi, b = 0, ov = 0;
+            const uint32_t st = ns_sample<G>(g, p, seed, tag, s, v, alo, ahi, ov, b, count_bytes != 0, list);
+            ovf |= ov;
+            if (st != 0xFFu) {
+                alo = 0;
+                ahi = 0;
+            }
+            uint64_t h = 0;
+            if (checksum) {
+                h = fmix64(s ^ 0x9E3779B97F4A7C15ull);
+                h = fmix64(h ^ (uint64_t)st);
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    if (i < p.k) h = fmix64(h ^ (uint64_t)(uint32_t)v[i]);
+                h = fmix64(h ^ alo);
+                h = fmix64(h ^ ahi);
+            }
+            // this lane's share of the sample
+            const uint32_t d[4] = {(uint32_t)alo, (uint32_t)(alo >> 32), (uint32_t)ahi, (uint32_t)(ahi >> 32)};
+            uint64_t add = 0;
+            if (lane < 4) {
+                add = d[lane & 3];
+            } else if (lane >= 8 && lane < 16 && (ahi | alo) != 0) {
+                const int col = lane - 8;
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        const uint64_t pr = (uint64_t)d[a] * (uint64_t)d[c];
+                        if (a + c == col) add += pr & 0xFFFFFFFFull;
+                        if (a + c + 1 == col) add += pr >> 32;
+                    }
+            } else if (lane == 20) {
+                add = st == 0xFFu ? 1 : 0;
+            } else if (lane == 21) {
+                add = h;
+            } else if (lane == 22) {
+                add = b;
+            }
+            acc += add;
+            if (tr.buf && s >= tr.lo && s < tr.hi && lane < 16) {
+                uint32_t w;
+                if (lane < 2) w = (uint32_t)(s >> (32 * lane));
+                else if (lane < 10) w = (uint32_t)v[lane - 2];
+                else if (lane == 10) w = st;
+                else if (lane == 11) w = (uint32_t)p.k;
+                else if (lane < 14) w = (uint32_t)(alo >> (32 * (lane - 12)));
+                else w = (uint32_t)(ahi >> (32 * (lane - 14)));
+                reinterpret_cast<uint32_t*>(tr.buf + (s - tr.lo))[lane] = w;
+            }
+        }
+    }
+    if (lane == 23) acc = ovf;
+    // block reduction: per wave the lane values are already the wave's sums
+    __shared__ unsigned long long red[4][24];
+    const int w = (int)(threadIdx.x >> 6);
+    if (lane < 24) red[w][lane] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long col[24];
+        for (int i = 0; i < 24; ++i) col[i] = red[0][i] + red[1][i] + red[2][i] + red[3][i];
+        unsigned long long o[PF_N];
+        for (int i = 0; i < PF_N; ++i) o[i] = 0;
+        unsigned long long c = 0;
+        for (int i = 0; i < 6; ++i) {  // S1: digit sums 0-3, carried into 6 digits
+            const unsigned long long t = (i < 4 ? col[i] : 0ull) + c;
+            o[PF_S1 + i] = i < 5 ? (t & 0xFFFFFFFFull) : t;
+            c = t >> 32;
+        }
+        c = 0;
+        for (int i = 0; i < 10; ++i) {  // S2: digit columns 0-7, carried into 10 digits
+            const unsigned long long t = (i < 8 ? col[8 + i] : 0ull) + c;
+            o[PF_S2 + i] = i < 9 ? (t & 0xFFFFFFFFull) : t;
+            c = t >> 32;
+        }
+        o[PF_HITS] = col[20];
+        o[PF_CSUM] = col[21];
+        o[PF_BYTES] = col[22];
+        o[PF_OVF] = col[23];
+        unsigned long long* dst = partials + (size_t)blockIdx.x * PF_N;
+        for (int i = 0; i < PF_N; ++i) dst[i] = o[i];
+    }
+}
+
 __global__ __launch_bounds__(256) void reduce_partials_kernel(const unsigned long long* __restrict__ partials,
                                                               int nblocks, unsigned long long* __restrict__ out) {
     unsigned long long acc[PF_N];
@@ -461,13 +661,32 @@ hipError_t launch_ns_window(const DGraph& g, const Plan& p, uint64_t seed, uint3
                                partials, checksum, count_bytes, tr);
             break;
         case 64:
-            hipLaunchKernelGGL(ns_window_kernel<64>, grid, block, 0, st, g, p, seed, tag, s0, s1, cfg.spl, ticket,
+            hipLaunchKernelGGL(ns_wave_kernel, grid, block, 0, st, g, p, seed, tag, s0, s1, cfg.spl, ticket,
                                partials, checksum, count_bytes, tr);
             break;
         default:
             return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+// Resident 256-thread blocks per CU for the sampling kernel of a lane count.
+int ns_blocks_per_cu(int lanes) {
+    static int cache[65] = {0};
+    if (lanes < 1 || lanes > 64) return 1;
+    if (cache[lanes]) return cache[lanes];
+    int nb = 0;
+    hipError_t e = hipErrorInvalidValue;
+    switch (lanes) {
+        case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ns_window_kernel<1>, 256, 0); break;
+        case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ns_window_kernel<4>, 256, 0); break;
+        case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ns_window_kernel<16>, 256, 0); break;
+        case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ns_wave_kernel, 256, 0); break;
+        default: break;
+    }
+    if (e != hipSuccess || nb < 1) nb = 2;
+    cache[lanes] = nb;
+    return nb;
 }
 
 hipError_t launch_reduce_partials(const unsigned long long* partials, int nblocks, unsigned long long* out20,

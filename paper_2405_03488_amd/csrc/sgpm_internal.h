@@ -14,6 +14,7 @@ struct Plan {
     int32_t k, oriented, induced, aut;
     int32_t order[8];
     uint8_t connect[8], disconnect[8], upper[8], lower[8];
+    uint8_t reuse[8];  // step j's constraints contain step j-1's: S_j is a subset of S_{j-1}
 };
 
 // Device-resident canonical graph.
@@ -53,6 +54,7 @@ hipError_t launch_ns_window(const DGraph& g, const Plan& p, uint64_t seed, uint3
                             int checksum, int count_bytes, const TraceArgs& tr, hipStream_t st);
 hipError_t launch_reduce_partials(const unsigned long long* partials, int nblocks, unsigned long long* out20,
                                   hipStream_t st);
+int ns_blocks_per_cu(int lanes);
 hipError_t launch_fill_u64(unsigned long long* p, uint64_t n, unsigned long long v, hipStream_t st);
 
 // host helpers
@@ -77,5 +79,64 @@ bool big_is_zero(const Big& a);
 double normal_quantile(double p);
 double predicted_error(double z, uint64_t n, const Big& S1, const Big& S2);
 uint64_t next_window_end(uint64_t n_t, const sgpm_options& o);
+
+// GS kernels (gs_kernels.hip)
+hipError_t gs_colours(int64_t n, uint32_t c, uint64_t seed, uint32_t rep, uint8_t* col, hipStream_t st);
+hipError_t gs_row_counts(const DGraph& g, const uint8_t* col, int64_t* kept, int64_t* klow, hipStream_t st);
+hipError_t gs_compact(const DGraph& g, const uint8_t* col, const int64_t* noff, const int64_t* eoff, int32_t* nnbr,
+                      int32_t* narow, int2* nepair, hipStream_t st);
+int64_t scan_scratch_words(int64_t n);
+hipError_t exclusive_scan(const int64_t* in, int64_t n, int64_t* out, int64_t* scratch, hipStream_t st);
+hipError_t max_degree(const int64_t* off, int64_t n, unsigned long long* out, hipStream_t st);
+hipError_t launch_exact_count(const DGraph& g, const Plan& p, uint64_t nfirst, int blocks, int per_ticket,
+                              unsigned long long* ticket, unsigned long long* partials, unsigned long long* out2,
+                              hipStream_t st);
+int exact_blocks_per_cu();
+
+}  // namespace sgpm
+
+// ------------------------------------------------------------------ library handles
+struct sgpm_ctx {
+    int dev = 0;
+    hipStream_t st = nullptr;
+    std::string err;
+    int cus = 256;
+    // scratch reused across calls
+    unsigned long long* d_partials = nullptr;
+    size_t partial_blocks = 0;
+    unsigned long long* d_slots = nullptr;   // per launch: ticket + 20 sums (+ pad) = 32 words
+    unsigned long long* h_slots = nullptr;   // pinned mirror of the sums
+    size_t nslots = 0;
+    std::vector<hipEvent_t> kev;             // start/stop events around each sampling kernel
+};
+
+struct sgpm_graph {
+    sgpm_ctx* ctx = nullptr;
+    int64_t n = 0, m = 0, maxdeg = 0;
+    std::vector<int32_t> perm;
+    int64_t* d_off = nullptr;
+    int32_t* d_nbr = nullptr;
+    int2* d_epair = nullptr;
+    int32_t* d_arow = nullptr;
+    sgpm::DGraph view() const { return sgpm::DGraph{d_off, d_nbr, d_epair, d_arow, n, m}; }
+};
+
+struct sgpm_pattern {
+    sgpm::Plan plan;
+};
+
+
+namespace sgpm {
+
+inline sgpm_status fail(sgpm_ctx* c, sgpm_status s, const std::string& msg) {
+    if (c) c->err = msg;
+    return s;
+}
+
+#define HIP_TRY(ctx, expr)                                                                                 \
+    do {                                                                                                   \
+        hipError_t _e = (expr);                                                                            \
+        if (_e != hipSuccess) return sgpm::fail((ctx), SGPM_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+    } while (0)
 
 }  // namespace sgpm

@@ -1,0 +1,147 @@
+"""GS engine on the GPU against the oracle: colour sparsification (bit-exact
+sparsified CSR), the plan-driven exact count (bit-exact counts) and the GS
+estimate over repeated colourings (identical per-colouring counts and sums)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+NAMES = ["edge", "triangle", "wedge", "4-clique", "5-clique", "4-cycle", "5-cycle", "4-path", "3-star",
+         "tailed-triangle", "diamond", "house", "dumbbell", "6-clique"]
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_2405_03488_amd import sgpm
+    return sgpm
+
+
+@pytest.fixture(scope="module")
+def ctx(S):
+    c = S.sgpm_create(0)
+    yield c
+    S.sgpm_destroy(c)
+
+
+def load(S, O, synth, ctx, n, pairs):
+    off, nbr = synth.pairs_to_csr(n, pairs)
+    return S.sgpm_graph_from_csr(ctx, n, off, nbr), O.OGraph.from_raw_csr(n, off, nbr)
+
+
+@pytest.fixture(scope="module")
+def cl(S, O, synth, ctx):
+    print("building Chung-Lu(4000, 14, 2.1)", flush=True)
+    g, og = load(S, O, synth, ctx, 4000, synth.chung_lu_pairs(4000, 14, 2.1, 6))
+    yield g, og
+    S.sgpm_graph_free(g)
+
+
+@pytest.mark.parametrize("c,seed,rep", [(1, 3, 0), (2, 3, 0), (4, 3, 1), (8, 99, 7), (256, 5, 2)])
+def test_sparsify_matches_oracle(S, O, ctx, cl, c, seed, rep):
+    g, og = cl
+    sp = S.sgpm_gs_sparsify(ctx, g, c, seed, rep)
+    off, nbr = S.sgpm_graph_export(ctx, sp)
+    n, m, maxdeg, _ = S.sgpm_graph_stats(sp)
+    col = np.array([O.gs_colour(seed, rep, c, v) for v in range(og.n)], dtype=np.int32)
+    osp = O.gs_sparsify(og, col)
+    assert m == osp.m and np.array_equal(off, osp.off) and np.array_equal(nbr, osp.nbr)
+    assert maxdeg == (int(np.diff(osp.off).max()) if osp.n else 0)
+    S.sgpm_graph_free(sp)
+
+
+@pytest.fixture(scope="module")
+def cl_small(S, O, synth, ctx):
+    g, og = load(S, O, synth, ctx, 1500, synth.chung_lu_pairs(1500, 10, 2.1, 6))
+    yield g, og
+    S.sgpm_graph_free(g)
+
+
+@pytest.fixture(scope="module")
+def er_small(S, O, synth, ctx):
+    g, og = load(S, O, synth, ctx, 400, synth.er_pairs(400, 3000, 6))
+    yield g, og
+    S.sgpm_graph_free(g)
+
+
+@pytest.mark.parametrize("induced", [False, True])
+@pytest.mark.parametrize("name", NAMES)
+def test_exact_count_matches_oracle(S, O, synth, ctx, cl_small, er_small, name, induced):
+    """Every pattern on a small power-law graph (the 6-vertex dumbbell, whose
+    edge-induced count is large there, on a small ER graph)."""
+    print(f"exact {name} induced={induced}", flush=True)
+    g, og = er_small if name == "dumbbell" else cl_small
+    k, e = synth.pattern(name)
+    p = S.sgpm_pattern_create(ctx, k, e, induced)
+    want = O.plan_count(og, O.compile_plan(k, e, induced))
+    assert S.sgpm_exact_count(ctx, g, p) == want
+    S.sgpm_pattern_free(p)
+
+
+def test_exact_count_closed_forms(S, O, synth, ctx):
+    import math
+    g, _ = load(S, O, synth, ctx, 12, synth.complete_pairs(12))
+    for kk, name in [(3, "triangle"), (4, "4-clique"), (5, "5-clique"), (6, "6-clique")]:
+        p = S.sgpm_pattern_create(ctx, *synth.pattern(name))
+        assert S.sgpm_exact_count(ctx, g, p) == math.comb(12, kk)
+        S.sgpm_pattern_free(p)
+    S.sgpm_graph_free(g)
+    g, _ = load(S, O, synth, ctx, 1 << 6, synth.hypercube_pairs(6))
+    p = S.sgpm_pattern_create(ctx, *synth.pattern("4-cycle"))
+    assert S.sgpm_exact_count(ctx, g, p) == math.comb(6, 2) * 2 ** 4
+    S.sgpm_pattern_free(p)
+    S.sgpm_graph_free(g)
+    g, _ = load(S, O, synth, ctx, 5, np.zeros((0, 2), dtype=np.int32))
+    p = S.sgpm_pattern_create(ctx, *synth.pattern("triangle"))
+    assert S.sgpm_exact_count(ctx, g, p) == 0
+    S.sgpm_pattern_free(p)
+    S.sgpm_graph_free(g)
+
+
+@pytest.mark.parametrize("name,c", [("triangle", 4), ("4-cycle", 3), ("diamond", 2)])
+def test_gs_estimate_matches_oracle(S, O, synth, ctx, cl, name, c):
+    g, og = cl
+    k, e = synth.pattern(name)
+    p = S.sgpm_pattern_create(ctx, k, e)
+    opts = S.sgpm_options_default(mode=S.MODE_GS, colours=c, seed=17, eps=0.05, gs_reps_max=40)
+    r, rc = S.sgpm_estimate(ctx, g, p, opts)
+    orr, ys = O.gs_run(og, O.compile_plan(k, e), c, 17, eps=0.05, confidence=0.95, reps_max=40)
+    assert r.scheme == S.SCHEME_GS and r.colours == c
+    assert r.n_samples == orr.reps and r.S1 == orr.S1 and r.S2 == orr.S2
+    assert r.estimate == orr.estimate and r.eps_hat == orr.eps_hat
+    assert r.converged == orr.converged
+    assert (rc == S.SGPM_OK) == bool(orr.converged)
+    S.sgpm_pattern_free(p)
+
+
+@pytest.fixture(scope="module")
+def rmat13(S, O, synth, ctx):
+    print("building R-MAT scale 13", flush=True)
+    g, og = load(S, O, synth, ctx, 1 << 13, synth.rmat_pairs(13, 16, seed=2))
+    yield g, og
+    S.sgpm_graph_free(g)
+
+
+@pytest.mark.parametrize("name", ["triangle", "4-clique", "5-clique", "diamond", "4-cycle"])
+def test_exact_count_rmat13(S, O, synth, ctx, rmat13, name):
+    """Skewed R-MAT degrees (hub rows spanning many 64-entry chunks)."""
+    g, og = rmat13
+    k, e = synth.pattern(name)
+    p = S.sgpm_pattern_create(ctx, k, e)
+    assert S.sgpm_exact_count(ctx, g, p) == O.plan_count(og, O.compile_plan(k, e))
+    S.sgpm_pattern_free(p)
+
+
+def test_sparsified_graph_supports_ns(S, O, synth, ctx, cl):
+    """NS on a sparsified handle equals the oracle's NS on its sparsified graph."""
+    g, og = cl
+    sp = S.sgpm_gs_sparsify(ctx, g, 2, 11, 0)
+    col = np.array([O.gs_colour(11, 0, 2, v) for v in range(og.n)], dtype=np.int32)
+    osp = O.gs_sparsify(og, col)
+    k, e = synth.pattern("triangle")
+    p = S.sgpm_pattern_create(ctx, k, e)
+    r, _ = S.sgpm_estimate(ctx, sp, p, S.sgpm_options_default(mode=S.MODE_FIXED_N, fixed_n=100000, seed=4,
+                                                               checksum=1))
+    orr = O.run(osp, O.compile_plan(k, e), O.make_opts(fixed_n=100000, seed=4))
+    assert r.S1 == orr.S1 and r.checksum == orr.checksum
+    S.sgpm_pattern_free(p)
+    S.sgpm_graph_free(sp)

@@ -102,3 +102,14 @@ def test_coverage(O, synth):
         inside += abs(r.estimate - C) / C < r.eps_hat
     # Binomial(200, 0.95): mean 190, sd 3.08; 99% band ~ [182, 198]
     assert 180 <= inside <= 200, inside
+
+
+def test_big_integer_to_double_is_correctly_rounded(O):
+    """Python's int -> float conversion rounds to nearest, ties to even."""
+    rng = np.random.default_rng(5)
+    cases = [0, 1, 2**53 - 1, 2**53, 2**53 + 1, 2**53 + 3, 2**64 + 2**11, 2**64 + 2**11 + 1, (2**53 + 1) << 70]
+    for _ in range(500):
+        bits = int(rng.integers(1, 700))
+        cases.append(int.from_bytes(rng.bytes(88), "little") >> (704 - bits))
+    for x in cases:
+        assert O.digits_to_double(x) == float(x), x
