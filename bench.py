@@ -46,6 +46,9 @@ def main():
     ap.add_argument("--eps", type=float, default=0.01)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-probes", action="store_true", help="skip the measured copy/gather rooflines")
+    ap.add_argument("--counters-run", action="store_true",
+                    help="short run for hardware counters: one 256 MiB copy, then one 4M-sample window per query")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding is a "
@@ -73,6 +76,15 @@ def main():
 
     queries = ["4-clique", "5-clique"]
     pats = {q: S.sgpm_pattern_create(ctx, *synth.pattern(q)) for q in queries}
+
+    if args.counters_run:
+        S.sgpm_probe_copy(ctx, 256 << 20, 1)
+        for q in queries:
+            o = S.sgpm_options_default(mode=S.MODE_FIXED_N, fixed_n=4 << 20, seed=1000, checksum=1,
+                                       lanes_per_sample=64)
+            r, _ = S.sgpm_estimate(ctx, g, pats[q], o)
+            log(f"{q}: {r.n_samples} samples, kernel {r.seconds_kernel * 1e3:.3f} ms over {r.launches} launch(es)")
+        return
 
     def opts_for(q, seed, lanes, trace):
         buf = S.trace_buffer(NTRACE) if trace else None
@@ -118,6 +130,15 @@ def main():
         bps[q] = r.bytes / max(1, r.n_samples)
     alg_bytes = sum(bps[x["q"]] * x["r"].n_samples for x in runs)
     achieved = alg_bytes / kernel_s / 1e9 if kernel_s > 0 else 0.0
+
+    probes = None
+    if not args.no_probes:
+        footprint = (gn + 1) * 8 + 2 * gm * 4 + gm * 8  # offsets + rows + oriented edge pairs
+        probes = {"hbm_copy_GBs": S.sgpm_probe_copy(ctx, 1 << 30, 5),
+                  "working_set_bytes": footprint}
+        for seg in (64, 256):
+            probes[f"gather_{seg}B_GBs"] = S.sgpm_probe_gather(ctx, footprint, seg, 16)
+        log(f"probes: {probes}")
 
     per_q = {}
     for q in queries:
@@ -176,7 +197,8 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "ns_window_kernel", "launches": launches,
                      "avg_launch_ms": kernel_s / max(1, launches) * 1e3,
-                     "alg_bytes_per_launch": alg_bytes / max(1, launches)},
+                     "alg_bytes_per_launch": alg_bytes / max(1, launches),
+                     "measured": probes},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -162,6 +162,8 @@ typedef struct {
     double seconds_sampling; /* device time of the windows (kernels, reductions, read-back) */
     double seconds_total;    /* wall time of the call */
     double seconds_kernel;   /* device time of the sampling kernels alone (HIP events around each) */
+    int32_t tile;            /* batch: samples per ticket picked by the autotuner */
+    int32_t pad;
 } sgpm_result;
 
 /* Defaults: eps 0.01, confidence 0.95, seed 1, tag 0, strict NS, n_min = w_min =
@@ -217,6 +219,15 @@ typedef struct {
 sgpm_status sgpm_model_train(sgpm_ctx_t ctx, sgpm_graph_t g, const sgpm_pattern_t* patterns, int np,
                              const sgpm_train_cfg* cfg, sgpm_model_t* out);
 sgpm_status sgpm_model_free(sgpm_model_t m);
+
+/* ------------------------------------------------------------------ measurement probes */
+/* Streaming copy of `bytes` (rounded down to 16) repeated iters times; *gbs =
+ * bytes read + written per second.  The measured HBM roofline. */
+sgpm_status sgpm_probe_copy(sgpm_ctx_t ctx, uint64_t bytes, int iters, double* gbs);
+/* Random reads of segment_bytes-long aligned segments (4..256, a power of two)
+ * from a working set of the given size, `rounds` dependent reads per segment
+ * group; *gbs = segment bytes read per second.  The measured gather roofline. */
+sgpm_status sgpm_probe_gather(sgpm_ctx_t ctx, uint64_t working_set_bytes, int segment_bytes, int rounds, double* gbs);
 
 /* ------------------------------------------------------------------ host-only utilities */
 /* These run the host parts of the library without a device, so they can be

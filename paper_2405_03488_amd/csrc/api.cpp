@@ -90,6 +90,11 @@ sgpm_status sgpm_destroy(sgpm_ctx_t c) {
     if (c->d_slots) (void)hipFree(c->d_slots);
     if (c->h_slots) (void)hipHostFree(c->h_slots);
     for (hipEvent_t e : c->kev) (void)hipEventDestroy(e);
+    if (c->batch_exec) (void)hipGraphExecDestroy(c->batch_exec);
+    if (c->batch_graph) (void)hipGraphDestroy(c->batch_graph);
+    if (c->batch_stream) (void)hipStreamDestroy(c->batch_stream);
+    if (c->d_bq) (void)hipFree(c->d_bq);
+    if (c->h_bq) (void)hipHostFree(c->h_bq);
     delete c;
     return SGPM_OK;
 }
@@ -414,6 +419,17 @@ sgpm_status ns_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_op
     return SGPM_OK;
 }
 
+}  // namespace
+
+namespace sgpm {
+sgpm_status ns_estimate_solo(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_options& o, sgpm_result* res,
+                             int count_bytes) {
+    return ns_estimate(c, g, p, o, res, count_bytes);
+}
+}  // namespace sgpm
+
+namespace {
+
 sgpm_status check_options(sgpm_ctx* c, const sgpm_options* o) {
     if (!o) return fail(c, SGPM_EINVAL, "null options");
     if (!(o->eps > 0) || !(o->confidence > 0 && o->confidence < 1)) return fail(c, SGPM_EINVAL, "eps/confidence");
@@ -502,13 +518,72 @@ uint64_t sgpm_host_next_window(uint64_t n_t, const sgpm_options* o) { return o ?
 
 // ------------------------------------------------------------------ entry points built in later modules
 extern "C" {
-sgpm_status sgpm_estimate_batch(sgpm_ctx_t c, int, const sgpm_graph_t*, const sgpm_pattern_t*, const sgpm_options*,
-                                sgpm_result*) {
-    return fail(c, SGPM_EUNSUPPORTED, "batch estimation is not built");
-}
 sgpm_status sgpm_model_train(sgpm_ctx_t c, sgpm_graph_t, const sgpm_pattern_t*, int, const sgpm_train_cfg*,
                              sgpm_model_t*) {
     return fail(c, SGPM_EUNSUPPORTED, "learned proposal is not built");
 }
 sgpm_status sgpm_model_free(sgpm_model_t) { return SGPM_EUNSUPPORTED; }
 }
+
+// ------------------------------------------------------------------ measurement probes
+extern "C" {
+
+sgpm_status sgpm_probe_copy(sgpm_ctx_t c, uint64_t bytes, int iters, double* gbs) {
+    if (!c || !gbs || bytes < 16 || iters < 1) return fail(c, SGPM_EINVAL, "bad probe arguments");
+    HIP_TRY(c, hipSetDevice(c->dev));
+    bytes &= ~15ull;
+    void *a = nullptr, *b = nullptr;
+    HIP_TRY(c, hipMalloc(&a, bytes));
+    HIP_TRY(c, hipMalloc(&b, bytes));
+    HIP_TRY(c, hipMemsetAsync(a, 1, bytes, c->st));
+    const int blocks = c->cus * 8;
+    HIP_TRY(c, probe_copy(a, b, bytes, blocks, c->st));  // warm
+    hipEvent_t e0, e1;
+    HIP_TRY(c, hipEventCreate(&e0));
+    HIP_TRY(c, hipEventCreate(&e1));
+    HIP_TRY(c, hipEventRecord(e0, c->st));
+    for (int i = 0; i < iters; i++) HIP_TRY(c, probe_copy(a, b, bytes, blocks, c->st));
+    HIP_TRY(c, hipEventRecord(e1, c->st));
+    HIP_TRY(c, hipEventSynchronize(e1));
+    float ms = 0;
+    HIP_TRY(c, hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(a);
+    (void)hipFree(b);
+    *gbs = 2.0 * (double)bytes * iters / (ms * 1e-3) / 1e9;
+    return SGPM_OK;
+}
+
+sgpm_status sgpm_probe_gather(sgpm_ctx_t c, uint64_t working_set_bytes, int segment_bytes, int rounds, double* gbs) {
+    if (!c || !gbs || segment_bytes < 4 || segment_bytes > 256 || (segment_bytes & (segment_bytes - 1)) ||
+        working_set_bytes < (uint64_t)segment_bytes || rounds < 1)
+        return fail(c, SGPM_EINVAL, "bad probe arguments");
+    HIP_TRY(c, hipSetDevice(c->dev));
+    const uint64_t words = working_set_bytes / 4;
+    int32_t* a = nullptr;
+    unsigned long long* sink = nullptr;
+    HIP_TRY(c, hipMalloc(&a, words * 4));
+    HIP_TRY(c, hipMalloc(&sink, 8));
+    HIP_TRY(c, hipMemsetAsync(a, 3, words * 4, c->st));
+    const int blocks = c->cus * 8;
+    HIP_TRY(c, probe_gather(a, words, segment_bytes, rounds, blocks, 1, sink, c->st));
+    hipEvent_t e0, e1;
+    HIP_TRY(c, hipEventCreate(&e0));
+    HIP_TRY(c, hipEventCreate(&e1));
+    HIP_TRY(c, hipEventRecord(e0, c->st));
+    HIP_TRY(c, probe_gather(a, words, segment_bytes, rounds, blocks, 2, sink, c->st));
+    HIP_TRY(c, hipEventRecord(e1, c->st));
+    HIP_TRY(c, hipEventSynchronize(e1));
+    float ms = 0;
+    HIP_TRY(c, hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(a);
+    (void)hipFree(sink);
+    const double segs = (double)blocks * 256.0 / (segment_bytes / 4) * rounds;
+    *gbs = segs * segment_bytes / (ms * 1e-3) / 1e9;
+    return SGPM_OK;
+}
+
+}  // extern "C"

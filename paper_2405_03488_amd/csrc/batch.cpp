@@ -1,0 +1,221 @@
+// Batched estimation: many (graph, pattern) NS queries in one persistent,
+// hipGraph-captured launch, one sample per wave at a time, with an autotuner
+// that sizes each query's tickets from timed pilot samples.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <tuple>
+
+#include "sgpm_internal.h"
+
+namespace sgpm {
+
+sgpm_status ns_estimate_solo(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_options& o, sgpm_result* res,
+                             int count_bytes);
+
+namespace {
+
+// Tile autotuner: time 2^16 pilot samples of the query (Philox tag
+// 0x80000000 | tag, so they never overlap estimation samples) and size the
+// query's tickets to about 50 us of wave time, so uneven queries hand out
+// tickets of similar cost and the persistent grid drains evenly.
+sgpm_status autotune_tile(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_options& o, int* tile) {
+    sgpm_options po = o;
+    po.mode = SGPM_MODE_FIXED_N;
+    po.fixed_n = 1 << 16;
+    po.query_tag = 0x80000000u | (o.query_tag & 0x7FFFFFFFu);
+    po.lanes_per_sample = 64;
+    po.checksum = 0;
+    po.trace_buf = nullptr;
+    po.trace_lo = po.trace_hi = 0;
+    sgpm_result r;
+    sgpm_status st = ns_estimate_solo(c, g, p, po, &r, 0);
+    if (st != SGPM_OK && st != SGPM_NOT_CONVERGED) return st;
+    const double waves = (double)c->cus * (double)ns_blocks_per_cu(64) * 4.0;
+    const double wave_time_per_sample = r.seconds_kernel * waves / (double)po.fixed_n;
+    double t = wave_time_per_sample > 0 ? 50e-6 / wave_time_per_sample : 1024.0;
+    int tl = 16;
+    while (tl < 1024 && tl * 2 <= t) tl *= 2;
+    *tile = tl;
+    if (std::getenv("SGPM_DEBUG"))
+        std::fprintf(stderr, "sgpm batch autotune: %.3g us wave time per sample -> tile %d\n",
+                     wave_time_per_sample * 1e6, tl);
+    return SGPM_OK;
+}
+
+}  // namespace
+
+sgpm_status batch_estimate(sgpm_ctx* c, int nq, const sgpm_graph_t* graphs, const sgpm_pattern_t* patterns,
+                           const sgpm_options* opts, sgpm_result* res) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (nq <= 0 || !graphs || !patterns || !opts || !res) return fail(c, SGPM_EINVAL, "bad batch arguments");
+    HIP_TRY(c, hipSetDevice(c->dev));
+    std::vector<BatchQuery> hq((size_t)nq);
+    std::vector<BatchState> hs((size_t)nq);
+    std::memset(hs.data(), 0, sizeof(BatchState) * (size_t)nq);
+    unsigned long long active = 0;
+    for (int i = 0; i < nq; i++) {
+        const sgpm_options& o = opts[i];
+        if (!graphs[i] || !patterns[i]) return fail(c, SGPM_EINVAL, "null graph or pattern in batch");
+        if (o.mode != SGPM_MODE_STRICT_NS && o.mode != SGPM_MODE_FIXED_N)
+            return fail(c, SGPM_EUNSUPPORTED, "batch queries must be NS (strict or fixed-n)");
+        if (o.trace_buf || o.proposal) return fail(c, SGPM_EUNSUPPORTED, "batch queries take no trace or proposal");
+        if (!(o.eps > 0) || !(o.confidence > 0 && o.confidence < 1)) return fail(c, SGPM_EINVAL, "eps/confidence");
+        if (o.mode == SGPM_MODE_FIXED_N && o.fixed_n == 0) return fail(c, SGPM_EINVAL, "fixed_n = 0");
+        // Window columns hold sums of 32-bit digits, so a window must stay
+        // below 2^32 samples: window_cap = the first window that would not.
+        int window_cap = 0x7FFFFFFF;
+        {
+            uint64_t n = 0;
+            for (int t = 0; t < 1000000; t++) {
+                const uint64_t nx = o.mode == SGPM_MODE_FIXED_N ? o.fixed_n : next_window_end(n, o);
+                if (nx <= n) break;
+                if (nx - n >= (1ull << 32)) {
+                    window_cap = t;
+                    break;
+                }
+                n = nx;
+                if (o.mode == SGPM_MODE_FIXED_N) break;
+            }
+            if (window_cap == 0) return fail(c, SGPM_EUNSUPPORTED, "batch windows must stay below 2^32 samples");
+        }
+        sgpm_graph* g = graphs[i];
+        const Plan& p = patterns[i]->plan;
+        BatchQuery& Q = hq[(size_t)i];
+        Q.g = g->view();
+        Q.p = p;
+        Q.seed = o.seed;
+        Q.tag = o.query_tag;
+        Q.mode = o.mode;
+        Q.fixed_n = o.fixed_n;
+        Q.n_min = o.n_min;
+        Q.w_min = o.w_min;
+        Q.quantum = o.quantum;
+        Q.max_samples = o.max_samples;
+        Q.growth = o.window_growth;
+        Q.eps = o.eps;
+        Q.z = normal_quantile(1.0 - (1.0 - o.confidence) / 2.0);
+        const uint64_t M = p.oriented ? (uint64_t)g->m : 2ull * (uint64_t)g->m;
+        int tile = 64;
+        if (M > 0) {
+            auto key = std::make_tuple((const void*)g, std::string((const char*)&p, sizeof(Plan)));
+            auto it = c->tuned.find(key);
+            if (it != c->tuned.end()) tile = it->second;
+            else {
+                sgpm_status st = autotune_tile(c, g, p, o, &tile);
+                if (st != SGPM_OK) return st;
+                c->tuned[key] = tile;
+            }
+        }
+        Q.lanes = 64;
+        Q.tile = tile;
+        Q.window_cap = window_cap;
+        if (M == 0) {
+            hs[(size_t)i].finished = 1;
+            hs[(size_t)i].converged = 1;
+        } else {
+            active++;
+        }
+    }
+    // device buffers and the captured graph, rebuilt when the batch shape changes
+    const size_t qbytes = sizeof(BatchQuery) * (size_t)nq, sbytes = sizeof(BatchState) * (size_t)nq;
+    if (c->batch_nq != nq) {
+        if (c->batch_exec) (void)hipGraphExecDestroy(c->batch_exec);
+        if (c->batch_graph) (void)hipGraphDestroy(c->batch_graph);
+        c->batch_exec = nullptr;
+        c->batch_graph = nullptr;
+        if (c->d_bq) (void)hipFree(c->d_bq);
+        if (c->h_bq) (void)hipHostFree(c->h_bq);
+        c->d_bq = c->h_bq = nullptr;
+        const size_t total = qbytes + sbytes + 64;
+        HIP_TRY(c, hipMalloc(&c->d_bq, total));
+        HIP_TRY(c, hipHostMalloc(&c->h_bq, total, hipHostMallocDefault));
+        if (!c->batch_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->batch_stream, hipStreamNonBlocking));
+        const int blocks = c->cus * batch_blocks_per_cu();
+        char* d = (char*)c->d_bq;
+        char* h = (char*)c->h_bq;
+        BatchQuery* dq = (BatchQuery*)d;
+        BatchState* ds = (BatchState*)(d + qbytes);
+        unsigned long long* dact = (unsigned long long*)(d + qbytes + sbytes);
+        HIP_TRY(c, hipStreamBeginCapture(c->batch_stream, hipStreamCaptureModeThreadLocal));
+        HIP_TRY(c, hipMemcpyAsync(d, h, qbytes + sbytes + 8, hipMemcpyHostToDevice, c->batch_stream));
+        HIP_TRY(c, launch_batch(dq, ds, nq, dact, blocks, c->batch_stream));
+        HIP_TRY(c, hipMemcpyAsync(h + qbytes, d + qbytes, sbytes, hipMemcpyDeviceToHost, c->batch_stream));
+        HIP_TRY(c, hipStreamEndCapture(c->batch_stream, &c->batch_graph));
+        HIP_TRY(c, hipGraphInstantiate(&c->batch_exec, c->batch_graph, nullptr, nullptr, 0));
+        c->batch_nq = nq;
+    }
+    char* h = (char*)c->h_bq;
+    std::memcpy(h, hq.data(), qbytes);
+    std::memcpy(h + qbytes, hs.data(), sbytes);
+    std::memcpy(h + qbytes + sbytes, &active, 8);
+    hipEvent_t e0, e1;
+    HIP_TRY(c, hipEventCreate(&e0));
+    HIP_TRY(c, hipEventCreate(&e1));
+    HIP_TRY(c, hipEventRecord(e0, c->batch_stream));
+    if (active > 0) HIP_TRY(c, hipGraphLaunch(c->batch_exec, c->batch_stream));
+    HIP_TRY(c, hipEventRecord(e1, c->batch_stream));
+    HIP_TRY(c, hipStreamSynchronize(c->batch_stream));
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    const BatchState* out = (const BatchState*)(h + qbytes);
+    const double wall = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    sgpm_status worst = SGPM_OK;
+    for (int i = 0; i < nq; i++) {
+        const BatchState& S = active > 0 ? out[i] : hs[(size_t)i];
+        const BatchQuery& Q = hq[(size_t)i];
+        sgpm_result* r = &res[i];
+        std::memset(r, 0, sizeof(*r));
+        r->scheme = SGPM_SCHEME_NS;
+        r->z = Q.z;
+        r->n_samples = S.n;
+        r->n_hits = S.hits;
+        Big S1(24), S2(24);
+        for (int k = 0; k < 8; k++) S1.d[(size_t)k] = (uint32_t)S.tot_s1[k];
+        for (int k = 0; k < 12; k++) S2.d[(size_t)k] = (uint32_t)S.tot_s2[k];
+        for (int k = 0; k < 8; k++) r->sum_digits[k] = S1.d[(size_t)k];
+        for (int k = 0; k < 12; k++) r->sumsq_digits[k] = S2.d[(size_t)k];
+        r->estimate = S.n ? big_to_double(S1) / (double)S.n : 0.0;
+        r->eps_hat = S.n ? predicted_error(Q.z, S.n, S1, S2) : 0.0;
+        const double sigma = std::isfinite(r->eps_hat) ? r->estimate * r->eps_hat / Q.z : INFINITY;
+        r->ci_lo = r->estimate - Q.z * sigma;
+        r->ci_hi = r->estimate + Q.z * sigma;
+        r->converged = S.converged;
+        r->windows = S.windows;
+        r->lanes_per_sample = Q.lanes;
+        r->tile = Q.tile;
+        r->launches = 1;
+        r->checksum = S.csum;
+        r->seconds_kernel = ms * 1e-3;
+        r->seconds_sampling = ms * 1e-3;
+        r->seconds_total = wall;
+        sgpm_status st = SGPM_OK;
+        if (S.status) st = (sgpm_status)S.status;
+        else if (S.n && memcmp(&r->eps_hat, &S.eps_hat, sizeof(double)) != 0 &&
+                 !(std::isinf(r->eps_hat) && std::isinf(S.eps_hat)))
+            st = SGPM_EHIP;  // the device's stop test disagrees with the host's arithmetic
+        else if (!S.converged && Q.mode != SGPM_MODE_FIXED_N)
+            st = SGPM_NOT_CONVERGED;
+        if (st != SGPM_OK && (worst == SGPM_OK || worst == SGPM_NOT_CONVERGED)) worst = st;
+    }
+    if (worst == SGPM_EHIP) return fail(c, worst, "device predicted error differs from the host's");
+    if (worst == SGPM_EUNSUPPORTED) return fail(c, worst, "a query needed a window of 2^32 samples or more");
+    if (worst == SGPM_EOVERFLOW) return fail(c, worst, "a sample weight exceeded 128 bits");
+    if (worst == SGPM_NOT_CONVERGED) return fail(c, worst, "a query reached max_samples");
+    return SGPM_OK;
+}
+
+}  // namespace sgpm
+
+extern "C" sgpm_status sgpm_estimate_batch(sgpm_ctx_t c, int nq, const sgpm_graph_t* graphs,
+                                           const sgpm_pattern_t* patterns, const sgpm_options* opts,
+                                           sgpm_result* res) {
+    if (!c) return SGPM_EINVAL;
+    return sgpm::batch_estimate(c, nq, graphs, patterns, opts, res);
+}

@@ -1,0 +1,320 @@
+// Persistent multi-query NS kernel with device-side convergence detection.
+//
+// Each query keeps the NS-online loop of Sec. 4.1: windows of sample ids
+// [n_t, n_{t+1}) and a stop test at every window end.  All queries share one
+// launch: waves pull (query, tile) tickets, sample the tile with the query's
+// own lane count, add the tile's exact sums into the query's window columns,
+// and count finished samples.  The wave whose samples complete a window folds
+// the columns into the query's totals, evaluates the predicted error exactly as
+// the host does (exact n*S2 - S1^2, correctly rounded conversions, IEEE
+// division and square root) and either finishes the query or opens the next
+// window by publishing a new epoch in the ticket word (epoch << 40 | tile).
+// Window bounds are a deterministic function of the epoch, recomputed by each
+// wave, so no wave ever reads bounds another wave is rewriting.  A query's
+// samples, sums and stop point are therefore identical to a solo run.
+#include "ns_device.h"
+
+namespace sgpm {
+
+namespace {
+
+constexpr unsigned long long TILE_MASK = (1ull << 40) - 1ull;
+
+__device__ __forceinline__ unsigned long long ld_acq(const unsigned long long* p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int ld_acq_i(const int* p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ uint64_t dev_next_window(uint64_t n_t, const BatchQuery& Q) {
+    auto up = [&](uint64_t x) { return Q.quantum ? (x + Q.quantum - 1) / Q.quantum * Q.quantum : x; };
+    uint64_t nx;
+    if (n_t == 0) {
+        nx = up(Q.n_min);
+    } else {
+        const double gr = ceil(__dmul_rn(Q.growth, (double)n_t));
+        uint64_t inc = (uint64_t)gr;
+        if (inc < Q.w_min) inc = Q.w_min;
+        nx = up(n_t + inc);
+    }
+    if (Q.max_samples && nx > Q.max_samples) nx = Q.max_samples;
+    return nx;
+}
+
+// window w = [start, end) of the query's schedule
+__device__ void dev_window(const BatchQuery& Q, int w, uint64_t& ws, uint64_t& we) {
+    if (Q.mode == SGPM_MODE_FIXED_N) {
+        ws = 0;
+        we = Q.fixed_n;
+        return;
+    }
+    uint64_t a = 0, b = dev_next_window(0, Q);
+    for (int t = 0; t < w; ++t) {
+        a = b;
+        b = dev_next_window(a, Q);
+    }
+    ws = a;
+    we = b;
+}
+
+// correctly rounded double of a little-endian 32-bit digit integer
+__device__ double dev_to_double(const uint32_t* d, int nd) {
+    int top = -1;
+    for (int i = nd - 1; i >= 0; --i)
+        if (d[i]) {
+            top = i;
+            break;
+        }
+    if (top < 0) return 0.0;
+    const int L = 32 * top + 32 - __clz(d[top]);
+    auto bit = [&](int i) -> uint32_t { return i < 0 ? 0u : (d[i >> 5] >> (i & 31)) & 1u; };
+    if (L <= 64) {
+        const uint64_t v = ((uint64_t)(top >= 1 ? d[1] : 0u) << 32) | d[0];
+        return (double)v;  // the conversion rounds to nearest even
+    }
+    const int shift = L - 64;
+    uint64_t topbits = 0;
+    for (int b = 63; b >= 0; --b) topbits = (topbits << 1) | bit(shift + b);
+    bool sticky = false;
+    for (int i = 0; i < shift && !sticky; ++i) sticky = bit(i);
+    uint64_t keep = topbits >> 11;
+    const uint64_t rem = topbits & 0x7FF;
+    if (rem > 0x400 || (rem == 0x400 && (sticky || (keep & 1)))) keep++;
+    return ldexp((double)keep, shift + 11);
+}
+
+// predicted relative error from exact totals (the host's formula and order)
+__device__ double dev_eps_hat(double z, uint64_t n, const uint32_t* s1, const uint32_t* s2) {
+    bool zero = true;
+    for (int i = 0; i < 8; ++i) zero = zero && s1[i] == 0;
+    if (n == 0 || zero) return __longlong_as_double(0x7FF0000000000000ll);
+    uint32_t D[24], T[24];
+    for (int i = 0; i < 24; ++i) D[i] = T[i] = 0;
+    const uint32_t N[2] = {(uint32_t)n, (uint32_t)(n >> 32)};
+    for (int i = 0; i < 2; ++i) {
+        uint64_t carry = 0;
+        for (int j = 0; j < 12 && i + j < 24; ++j) {
+            const uint64_t t = (uint64_t)N[i] * s2[j] + D[i + j] + carry;
+            D[i + j] = (uint32_t)t;
+            carry = t >> 32;
+        }
+        for (int k = i + 12; k < 24 && carry; ++k) {
+            const uint64_t t = (uint64_t)D[k] + carry;
+            D[k] = (uint32_t)t;
+            carry = t >> 32;
+        }
+    }
+    for (int i = 0; i < 8; ++i) {
+        uint64_t carry = 0;
+        for (int j = 0; j < 8 && i + j < 24; ++j) {
+            const uint64_t t = (uint64_t)s1[i] * s1[j] + T[i + j] + carry;
+            T[i + j] = (uint32_t)t;
+            carry = t >> 32;
+        }
+        for (int k = i + 8; k < 24 && carry; ++k) {
+            const uint64_t t = (uint64_t)T[k] + carry;
+            T[k] = (uint32_t)t;
+            carry = t >> 32;
+        }
+    }
+    int64_t borrow = 0;
+    for (int i = 0; i < 24; ++i) {
+        const int64_t t = (int64_t)D[i] - (int64_t)T[i] - borrow;
+        borrow = t < 0 ? 1 : 0;
+        D[i] = (uint32_t)(t & 0xFFFFFFFFll);
+    }
+    if (borrow) return __longlong_as_double(0x7FF8000000000000ll);
+    const double dD = dev_to_double(D, 24), dn = (double)n, dS1 = dev_to_double(s1, 8);
+    const double q = __ddiv_rn(dD, dn);
+    const double r = __dsqrt_rn(q);
+    const double t = __dmul_rn(z, r);
+    return __ddiv_rn(t, dS1);
+}
+
+// fold the window columns into the totals and decide (one lane)
+__device__ __attribute__((noinline)) void complete_window(const BatchQuery& Q, BatchState& S, int w, uint64_t we,
+                                unsigned long long* active) {
+    unsigned long long col[PF_N];
+    for (int i = 0; i < PF_N; ++i) col[i] = __hip_atomic_exchange(&S.win[i], 0ull, __ATOMIC_ACQ_REL,
+                                                                  __HIP_MEMORY_SCOPE_AGENT);
+    // S1 columns 0-5 into 8 digits, S2 columns 6-15 into 12 digits
+    unsigned long long c = 0;
+    for (int i = 0; i < 8; ++i) {
+        const unsigned long long t = S.tot_s1[i] + (i < 6 ? col[PF_S1 + i] : 0ull) + c;
+        S.tot_s1[i] = t & 0xFFFFFFFFull;
+        c = t >> 32;
+    }
+    c = 0;
+    for (int i = 0; i < 12; ++i) {
+        const unsigned long long t = S.tot_s2[i] + (i < 10 ? col[PF_S2 + i] : 0ull) + c;
+        S.tot_s2[i] = t & 0xFFFFFFFFull;
+        c = t >> 32;
+    }
+    S.hits += col[PF_HITS];
+    S.csum += col[PF_CSUM];
+    S.bytes += col[PF_BYTES];
+    S.ovf += col[PF_OVF];
+    S.n = we;
+    S.windows = w + 1;
+    uint32_t s1[8], s2[12];
+    for (int i = 0; i < 8; ++i) s1[i] = (uint32_t)S.tot_s1[i];
+    for (int i = 0; i < 12; ++i) s2[i] = (uint32_t)S.tot_s2[i];
+    const double eh = dev_eps_hat(Q.z, we, s1, s2);
+    S.eps_hat = eh;
+    bool stop = false;
+    if (S.ovf) {
+        stop = true;
+        S.status = SGPM_EOVERFLOW;
+    } else if (Q.mode == SGPM_MODE_FIXED_N) {
+        stop = true;
+        S.converged = eh <= Q.eps ? 1 : 0;
+    } else if (eh <= Q.eps) {
+        stop = true;
+        S.converged = 1;
+    } else if (Q.max_samples && we >= Q.max_samples) {
+        stop = true;
+    } else if (dev_next_window(we, Q) <= we) {
+        stop = true;
+    } else if (w + 1 >= Q.window_cap) {
+        stop = true;  // the next window is too large for 64-bit digit columns
+        S.status = SGPM_EUNSUPPORTED;
+    }
+    if (stop) {
+        __hip_atomic_store(&S.finished, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        atomicSub(active, 1ull);
+    } else {
+        __hip_atomic_store(&S.done, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        __hip_atomic_exchange(&S.ticket, (unsigned long long)(w + 1) << 40, __ATOMIC_RELEASE,
+                              __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// One tile of samples, one sample per wave at a time.  Exact sums are spread
+// over the lanes as in the window kernel (lanes 0-3: digit sums of X, 8-15: digit
+// columns of X^2, 20: hits, 21: checksum, 23: overflow); the lane's value
+// is returned together with the window column it belongs to (-1: none).
+__device__ __forceinline__ unsigned long long run_tile(const BatchQuery& Q, uint64_t s0, uint64_t s1, int32_t* list,
+                                                       int& field) {
+    const int lane = (int)(threadIdx.x & 63);
+    uint64_t acc = 0, ovf = 0;
+    for (uint64_t s = s0; s < s1; ++s) {
+        int32_t v[8];
+        uint64_t alo, ahi, b = 0, ov = 0;
+        const uint32_t st = ns_sample<64>(Q.g, Q.p, Q.seed, Q.tag, s, v, alo, ahi, ov, b, false, list);
+        ovf |= ov;
+        if (st != 0xFFu) {
+            alo = 0;
+            ahi = 0;
+        }
+        uint64_t h = fmix64(s ^ 0x9E3779B97F4A7C15ull);
+        h = fmix64(h ^ (uint64_t)st);
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            if (i < Q.p.k) h = fmix64(h ^ (uint64_t)(uint32_t)v[i]);
+        h = fmix64(h ^ alo);
+        h = fmix64(h ^ ahi);
+        const uint32_t d[4] = {(uint32_t)alo, (uint32_t)(alo >> 32), (uint32_t)ahi, (uint32_t)(ahi >> 32)};
+        uint64_t add = 0;
+        if (lane < 4) {
+            add = d[lane & 3];
+        } else if (lane >= 8 && lane < 16 && (ahi | alo) != 0) {
+            const int col = lane - 8;
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const uint64_t pr = (uint64_t)d[a] * (uint64_t)d[c];
+                    if (a + c == col) add += pr & 0xFFFFFFFFull;
+                    if (a + c + 1 == col) add += pr >> 32;
+                }
+        } else if (lane == 20) {
+            add = st == 0xFFu ? 1 : 0;
+        } else if (lane == 21) {
+            add = h;
+        }
+        acc += add;
+    }
+    if (lane == 23) acc = ovf;
+    field = lane < 4 ? PF_S1 + lane
+                     : (lane >= 8 && lane < 16) ? PF_S2 + (lane - 8)
+                     : lane == 20 ? PF_HITS : lane == 21 ? PF_CSUM : lane == 23 ? PF_OVF : -1;
+    return acc;
+}
+
+__global__ __launch_bounds__(256, 8) void batch_kernel(const BatchQuery* __restrict__ queries, BatchState* __restrict__ states,
+                                                    int nq, unsigned long long* __restrict__ active) {
+    const int lane = (int)(threadIdx.x & 63);
+    __shared__ int32_t s_list[LDS_WORDS];
+    const int wave = (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+    int start = wave % nq;
+    // per-wave cache of the last window bounds looked up
+    int cq = -1, cw = -1;
+    uint64_t cws = 0, cwe = 0;
+    for (;;) {
+        if (ld_acq(active) == 0) break;
+        int q = -1;
+        uint64_t t = 0;
+        for (int i = 0; i < nq; ++i) {
+            const int qq = (start + i) % nq;
+            if (ld_acq_i(&states[qq].finished)) continue;
+            const unsigned long long cur = ld_acq(&states[qq].ticket);
+            const int w = (int)(cur >> 40);
+            if (qq != cq || w != cw) {
+                dev_window(queries[qq], w, cws, cwe);
+                cq = qq;
+                cw = w;
+            }
+            const uint64_t T = (uint64_t)queries[qq].tile;
+            const uint64_t ntiles = (cwe - cws + T - 1) / T;
+            if ((cur & TILE_MASK) >= ntiles) continue;
+            unsigned long long got = 0;
+            if (lane == 0) got = atomicAdd(&states[qq].ticket, 1ull);
+            got = __shfl(got, 0);
+            if ((int)(got >> 40) != w || (got & TILE_MASK) >= ntiles) continue;
+            q = qq;
+            t = got & TILE_MASK;
+            break;
+        }
+        if (q < 0) {
+            __builtin_amdgcn_s_sleep(8);
+            start = (start + 1) % nq;
+            continue;
+        }
+        q = rfl(q);
+        t = ((uint64_t)(uint32_t)rfl((int32_t)(t >> 32)) << 32) | (uint32_t)rfl((int32_t)t);
+        start = q;
+        const BatchQuery& Q = queries[q];
+        const uint64_t T = (uint64_t)Q.tile;
+        const uint64_t s0 = cws + t * T, s1 = min(s0 + T, cwe);
+        int field = -1;
+        const unsigned long long val = run_tile(Q, s0, s1, s_list + (threadIdx.x >> 6) * (LDS_WORDS / 4), field);
+        BatchState& S = states[q];
+        if (field >= 0 && val) atomicAdd(&S.win[field], val);
+        __threadfence();
+        if (lane == 0) {
+            const unsigned long long old = atomicAdd(&S.done, (unsigned long long)(s1 - s0));
+            if (old + (s1 - s0) == cwe - cws) {
+                __threadfence();
+                complete_window(Q, S, cw, cwe, active);
+            }
+        }
+    }
+}
+
+}  // namespace
+
+int batch_blocks_per_cu() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_kernel, 256, 0) != hipSuccess || nb < 1) nb = 1;
+    return nb;
+}
+
+hipError_t launch_batch(const BatchQuery* q, BatchState* s, int nq, unsigned long long* active, int blocks,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(batch_kernel, dim3((unsigned)blocks), dim3(256), 0, st, q, s, nq, active);
+    return hipGetLastError();
+}
+
+}  // namespace sgpm

@@ -25,353 +25,9 @@
 // the block turns them into 32-bit digits, adds, normalises and writes a
 // 20-word partial; a second kernel adds the partials.  Integer addition makes
 // the result independent of the schedule.
-#include "sgpm_internal.h"
+#include "ns_device.h"
 
 namespace sgpm {
-
-__device__ __forceinline__ uint64_t philox_r64(uint64_t seed, uint64_t s, uint32_t d, uint32_t tag) {
-    uint32_t c0 = (uint32_t)s, c1 = (uint32_t)(s >> 32), c2 = d, c3 = tag;
-    uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
-        const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
-        c0 = n0;
-        c1 = lo1;
-        c2 = n2;
-        c3 = lo0;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-    return ((uint64_t)c1 << 32) | (uint64_t)c0;
-}
-
-// SplitMix64 finaliser (Steele, Lea, Flood 2014), used by the record hash.
-__device__ __forceinline__ uint64_t fmix64(uint64_t z) {
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
-
-// first index in [lo, hi) of the ascending row with row[i] >= x
-__device__ __forceinline__ int32_t lower_bound(const int32_t* __restrict__ row, int32_t lo, int32_t hi, int32_t x) {
-    while (lo < hi) {
-        const int32_t mid = (int32_t)(((uint32_t)lo + (uint32_t)hi) >> 1);
-        if (row[mid] < x) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
-}
-
-__device__ __forceinline__ void add_carry(uint64_t& acc, uint64_t x, uint64_t& carry) {
-    const uint64_t t = acc + x;
-    const uint64_t c1 = t < x;
-    const uint64_t t2 = t + carry;
-    const uint64_t c2 = t2 < carry;
-    acc = t2;
-    carry = c1 + c2;
-}
-
-struct Acc {
-    uint64_t s1[3];   // sum X, 192 bits
-    uint64_t s2[5];   // sum X^2, 320 bits
-    uint64_t hits, csum, bytes, ovf;
-};
-
-__device__ __forceinline__ void acc_add(Acc& a, uint64_t lo, uint64_t hi) {
-    uint64_t c = 0;
-    add_carry(a.s1[0], lo, c);
-    add_carry(a.s1[1], hi, c);
-    a.s1[2] += c;
-    // X^2 = lo^2 + 2 lo hi 2^64 + hi^2 2^128
-    uint64_t w0 = lo * lo, w1 = __umul64hi(lo, lo), w2 = 0, w3 = 0;
-    if (hi) {
-        const uint64_t m0 = lo * hi, m1 = __umul64hi(lo, hi);
-        const uint64_t d0 = m0 << 1, d1 = (m1 << 1) | (m0 >> 63), d2 = m1 >> 63;
-        const uint64_t h0 = hi * hi, h1 = __umul64hi(hi, hi);
-        uint64_t cc = 0;
-        add_carry(w1, d0, cc);
-        w2 = d1;
-        add_carry(w2, h0, cc);
-        w3 = d2;
-        add_carry(w3, h1, cc);
-    }
-    c = 0;
-    add_carry(a.s2[0], w0, c);
-    add_carry(a.s2[1], w1, c);
-    add_carry(a.s2[2], w2, c);
-    add_carry(a.s2[3], w3, c);
-    a.s2[4] += c;
-}
-
-constexpr int32_t BIG = 0x7FFFFFFF;
-
-// With one sample per wave (G = 64) every per-sample value is wave-uniform;
-// readfirstlane tells the compiler so, which keeps the walk state in SGPRs
-// and turns its branches into scalar branches.
-__device__ __forceinline__ int32_t rfl(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
-template <int G>
-__device__ __forceinline__ int32_t uni(int32_t x) {
-    if constexpr (G == 64) return rfl(x);
-    else return x;
-}
-constexpr int LDS_WORDS = 4096;  // candidate lists per block (16 KB)
-
-// first index in [lo, hi) with row[i] >= x, galloping forward from lo
-__device__ __forceinline__ int32_t gallop(const int32_t* __restrict__ row, int32_t lo, int32_t hi, int32_t x) {
-    if (lo >= hi || row[lo] >= x) return lo;
-    int32_t prev = lo, step = 1;
-    for (;;) {
-        const int32_t nxt = prev + step;
-        if (nxt >= hi) return lower_bound(row, prev + 1, hi, x);
-        if (row[nxt] >= x) return lower_bound(row, prev + 1, nxt, x);
-        prev = nxt;
-        step <<= 1;
-    }
-}
-
-template <int G>
-__device__ __forceinline__ uint64_t group_ballot(bool pred, uint64_t gmask) {
-    return __ballot(pred) & gmask;
-}
-
-// Membership of each lane's x in the ascending row R[0, rl) for a group whose
-// active lanes hold ascending values (xmax = the largest).  The group-uniform
-// cursor c only moves forward: entries before it are below every x still to
-// come.  G = 1: galloping search.  G > 1: the group loads G consecutive row
-// entries, every lane binary-searches its x among them through shuffles, and
-// the window slides until no active lane's x lies beyond it.
-template <int G>
-__device__ __forceinline__ bool member(const int32_t* __restrict__ R, int32_t rl, int32_t& c, int32_t x, bool act,
-                                       int32_t xmax, int gbase, int gl, uint64_t gmask) {
-    if constexpr (G == 1) {
-        if (!act) return false;
-        const int32_t q = gallop(R, c, rl, x);
-        c = q;
-        return q < rl && R[q] == x;
-    } else {
-        bool found = false, pending = act;
-        for (;;) {
-            const int32_t b = (c + gl < rl) ? R[c + gl] : BIG;
-            const int32_t bmax = uni<G>(__shfl(b, gbase + G - 1));
-            int pos = 0;
-#pragma unroll
-            for (int st = G / 2; st >= 1; st >>= 1) {
-                const int32_t bv = __shfl(b, gbase + pos + st - 1);
-                if (bv < x) pos += st;
-            }
-            const int32_t bq = __shfl(b, gbase + (pos < G ? pos : G - 1));
-            const bool res = pending && x <= bmax;
-            if (res) found = pos < G && bq == x;
-            pending = pending && !res;
-            if (group_ballot<G>(pending, gmask) == 0) {
-                c += (int32_t)__popcll(group_ballot<G>(b < xmax, gmask));
-                break;
-            }
-            c += G;
-        }
-        return found;
-    }
-}
-
-// One NS-prune sample.  Returns 0xFF for a hit, else the failing position j.
-// For G > 1 all G lanes of a group call it with the same s.  `list` is the
-// group's LDS area of CAP words holding the current candidate set.
-template <int G>
-__device__ __forceinline__ uint32_t ns_sample(const DGraph& g, const Plan& p, uint64_t seed, uint32_t tag, uint64_t s,
-                                             int32_t (&v)[8], uint64_t& alo, uint64_t& ahi, uint64_t& ovf,
-                                             uint64_t& bytes, bool count_bytes, int32_t* list) {
-    constexpr int CAP = LDS_WORDS / (256 / G);
-    const int lane = (int)(threadIdx.x & 63);
-    const int gl = lane & (G - 1);
-    const int gbase = lane & ~(G - 1);
-    const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << gbase);
-    const uint64_t below = (1ull << lane) - 1ull;
-
-#pragma unroll
-    for (int i = 0; i < 8; ++i) v[i] = -1;
-    const uint64_t M = p.oriented ? (uint64_t)g.m : 2ull * (uint64_t)g.m;
-    const uint64_t e = __umul64hi(M, philox_r64(seed, s, 0, tag));
-    if (p.oriented) {
-        const int2 pr = g.epair[e];
-        v[0] = pr.x;
-        v[1] = pr.y;
-    } else {
-        v[0] = g.arow[e];
-        v[1] = g.nbr[e];
-    }
-    const int32_t* rp[8];
-    int32_t rl[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        rp[i] = nullptr;
-        rl[i] = 0;
-    }
-    {
-        const int64_t b0 = g.off[v[0]], e0 = g.off[v[0] + 1];
-        const int64_t b1 = g.off[v[1]], e1 = g.off[v[1] + 1];
-        rp[0] = g.nbr + b0;
-        rl[0] = (int32_t)(e0 - b0);
-        rp[1] = g.nbr + b1;
-        rl[1] = (int32_t)(e1 - b1);
-    }
-    alo = M;
-    ahi = 0;
-    bytes = 8;
-    uint32_t opened = 0;
-    int32_t prevcnt = -1;  // |S_{j-1}| when the whole set sits in `list`
-
-#pragma unroll
-    for (int j = 2; j < 8; ++j) {
-        if (j >= p.k) break;
-        const uint32_t conn = p.connect[j], disc = p.disconnect[j], up = p.upper[j], lw = p.lower[j];
-        int32_t lo = -1, hi = BIG;
-#pragma unroll
-        for (int i = 0; i < j; ++i) {
-            if (up >> i & 1) hi = min(hi, v[i]);
-            if (lw >> i & 1) lo = max(lo, v[i]);
-        }
-        // smallest connected earlier row (lowest position on ties)
-        int d = -1;
-        int32_t dl = BIG;
-        const int32_t* dp = nullptr;
-#pragma unroll
-        for (int i = 0; i < j; ++i)
-            if ((conn >> i & 1) && rl[i] < dl) {
-                d = i;
-                dl = rl[i];
-                dp = rp[i];
-            }
-        if (count_bytes) {
-            const uint32_t rows = conn | disc;
-#pragma unroll
-            for (int i = 0; i < j; ++i)
-                if ((rows >> i & 1) && !(opened >> i & 1)) {
-                    bytes += 16;
-                    opened |= 1u << i;
-                }
-            const int32_t w0 = lo >= 0 ? lower_bound(dp, 0, dl, lo + 1) : 0;
-            const int32_t w1 = hi < BIG ? lower_bound(dp, w0, dl, hi) : dl;
-            bytes += 4ull * (uint64_t)(w1 - w0);
-        }
-        // Reuse: when step j's constraints contain step j-1's, S_j is the part
-        // of S_{j-1} (already in `list`) that meets the extra constraints.
-        const bool reuse = (j >= 3) && p.reuse[j] && prevcnt >= 0;
-        uint32_t need_conn, need_disc, excl;
-        const int32_t* src;
-        int32_t slen, start;
-        if (reuse) {
-            need_conn = conn & ~(uint32_t)p.connect[j - 1];
-            need_disc = disc & ~(uint32_t)p.disconnect[j - 1];
-            excl = (1u << (j - 1)) & ~conn;
-            src = list;
-            slen = prevcnt;
-            start = 0;
-        } else {
-            need_conn = conn & ~(1u << d);
-            need_disc = disc;
-            excl = ((1u << j) - 1u) & ~conn;
-            src = dp;
-            slen = dl;
-            start = lo >= 0 ? lower_bound(dp, 0, dl, lo + 1) : 0;
-        }
-        int32_t cur[8];
-        // candidates of one chunk of G source entries; advances the cursors
-        auto eval_chunk = [&](int32_t base, int32_t& x, uint64_t& inm) -> bool {
-            const int32_t pos = base + gl;
-            x = pos < slen ? src[pos] : BIG;
-            const bool act = x < hi;
-            inm = group_ballot<G>(act, gmask);
-            bool ok = act && x > lo;
-#pragma unroll
-            for (int i = 0; i < j; ++i)
-                if (excl >> i & 1) ok = ok && (x != v[i]);
-            if (inm == 0) return false;
-            const int32_t xmax = uni<G>(__shfl(x, gbase + (int)__popcll(inm) - 1));
-#pragma unroll
-            for (int i = 0; i < j; ++i) {
-                if (need_conn >> i & 1) {
-                    const bool f = member<G>(rp[i], rl[i], cur[i], x, act, xmax, gbase, gl, gmask);
-                    ok = ok && f;
-                }
-                if (need_disc >> i & 1) {
-                    const bool f = member<G>(rp[i], rl[i], cur[i], x, act, xmax, gbase, gl, gmask);
-                    ok = ok && !f;
-                }
-            }
-            return ok;
-        };
-
-        // count pass; candidates are appended to `list` while they fit (in place
-        // when reusing: a chunk is read before any of its slots is rewritten)
-#pragma unroll
-        for (int i = 0; i < 8; ++i) cur[i] = 0;
-        uint32_t cnt = 0;
-        for (int32_t base = start; base < slen; base += G) {
-            int32_t x;
-            uint64_t inm;
-            const bool ok = eval_chunk(base, x, inm);
-            const uint64_t okm = group_ballot<G>(ok, gmask);
-            const uint32_t rank = (uint32_t)__popcll(okm & below);
-            if (ok && cnt + rank < (uint32_t)CAP) list[cnt + rank] = x;
-            cnt += (uint32_t)__popcll(okm);
-            if (inm != gmask) break;
-        }
-        if (cnt == 0) return (uint32_t)j;
-
-        const uint32_t idx = (uint32_t)__umul64hi((uint64_t)cnt, philox_r64(seed, s, (uint32_t)j, tag));
-        int32_t pick = -1;
-        if (cnt <= (uint32_t)CAP) {
-            pick = uni<G>(list[idx]);
-            prevcnt = (int32_t)cnt;
-        } else {
-            // the set overflowed the list (never when reusing): select by rescanning
-#pragma unroll
-            for (int i = 0; i < 8; ++i) cur[i] = 0;
-            uint32_t seen = 0;
-            for (int32_t base = start; base < slen; base += G) {
-                int32_t x;
-                uint64_t inm;
-                const bool ok = eval_chunk(base, x, inm);
-                uint64_t okm = group_ballot<G>(ok, gmask);
-                const uint32_t c = (uint32_t)__popcll(okm);
-                if (seen + c > idx) {
-                    for (uint32_t t = idx - seen; t > 0; --t) okm &= okm - 1ull;
-                    pick = uni<G>(__shfl(x, __ffsll((unsigned long long)okm) - 1));
-                    break;
-                }
-                seen += c;
-                if (inm != gmask) break;
-            }
-            prevcnt = -1;
-        }
-        if (pick < 0) {  // count and select passes disagree: report, never index with it
-            ovf = 1;
-            return (uint32_t)j;
-        }
-        v[j] = pick;
-        if (j + 1 < p.k) {
-            const int64_t bj = g.off[pick], ej = g.off[pick + 1];
-            rp[j] = g.nbr + bj;
-            rl[j] = (int32_t)(ej - bj);
-        }
-        // alpha *= |S_j| with 128-bit overflow detection
-        const uint64_t plo = alo * (uint64_t)cnt, phi = __umul64hi(alo, (uint64_t)cnt);
-        const uint64_t qlo = ahi * (uint64_t)cnt, qhi = __umul64hi(ahi, (uint64_t)cnt);
-        const uint64_t nhi = phi + qlo;
-        if (qhi != 0 || nhi < qlo) ovf = 1;
-        alo = plo;
-        ahi = nhi;
-    }
-    return 0xFFu;
-}
-
-__device__ __forceinline__ uint64_t wave_sum(uint64_t x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-    return x;
-}
 
 template <int G>
 __global__ __launch_bounds__(256) void ns_window_kernel(DGraph g, Plan p, uint64_t seed, uint32_t tag, uint64_t s0,

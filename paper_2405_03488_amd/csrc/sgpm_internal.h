@@ -2,7 +2,9 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/sgpm.h"
@@ -57,6 +59,34 @@ hipError_t launch_reduce_partials(const unsigned long long* partials, int nblock
 int ns_blocks_per_cu(int lanes);
 hipError_t launch_fill_u64(unsigned long long* p, uint64_t n, unsigned long long v, hipStream_t st);
 
+// persistent batch (batch_kernels.hip)
+struct BatchQuery {
+    DGraph g;
+    Plan p;
+    uint64_t seed;
+    uint32_t tag;
+    int32_t lanes;  // 16 or 64
+    int32_t mode;   // SGPM_MODE_STRICT_NS or SGPM_MODE_FIXED_N
+    int32_t tile;   // samples per ticket
+    int32_t window_cap;  // first window index that would hold >= 2^32 samples
+    int32_t pad;
+    uint64_t fixed_n, n_min, w_min, quantum, max_samples;
+    double growth, eps, z;
+};
+struct BatchState {
+    unsigned long long ticket;  // window epoch << 40 | next tile
+    unsigned long long done;    // samples finished in the current window
+    int32_t finished, status, converged, windows;
+    unsigned long long win[PF_N];            // current window's sum columns
+    unsigned long long tot_s1[8], tot_s2[12];  // normalised 32-bit digits
+    unsigned long long hits, csum, bytes, ovf;
+    double eps_hat;
+    uint64_t n;
+};
+int batch_blocks_per_cu();
+hipError_t launch_batch(const BatchQuery* q, BatchState* s, int nq, unsigned long long* active, int blocks,
+                        hipStream_t st);
+
 // host helpers
 struct HostGraph {
     int64_t n = 0, m = 0;
@@ -92,6 +122,10 @@ hipError_t launch_exact_count(const DGraph& g, const Plan& p, uint64_t nfirst, i
                               unsigned long long* ticket, unsigned long long* partials, unsigned long long* out2,
                               hipStream_t st);
 int exact_blocks_per_cu();
+// probes (probe_kernels.hip)
+hipError_t probe_copy(const void* in, void* out, uint64_t bytes, int blocks, hipStream_t st);
+hipError_t probe_gather(const int32_t* a, uint64_t words, int seg_bytes, int rounds, int blocks, uint64_t seed,
+                        unsigned long long* sink, hipStream_t st);
 
 }  // namespace sgpm
 
@@ -108,6 +142,14 @@ struct sgpm_ctx {
     unsigned long long* h_slots = nullptr;   // pinned mirror of the sums
     size_t nslots = 0;
     std::vector<hipEvent_t> kev;             // start/stop events around each sampling kernel
+    // batch: autotuned lanes per (graph, plan), device/pinned tables, captured graph
+    std::map<std::tuple<const void*, std::string>, int> tuned;
+    int batch_nq = 0;
+    void* d_bq = nullptr;
+    void* h_bq = nullptr;
+    hipStream_t batch_stream = nullptr;
+    hipGraph_t batch_graph = nullptr;
+    hipGraphExec_t batch_exec = nullptr;
 };
 
 struct sgpm_graph {

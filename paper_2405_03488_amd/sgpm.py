@@ -54,7 +54,7 @@ class Result(C.Structure):
                 ("colours", C.c_int32), ("converged", C.c_int32), ("windows", C.c_int32),
                 ("lanes_per_sample", C.c_int32), ("launches", C.c_int32), ("checksum", C.c_uint64),
                 ("bytes", C.c_uint64), ("seconds_sampling", C.c_double), ("seconds_total", C.c_double),
-                ("seconds_kernel", C.c_double)]
+                ("seconds_kernel", C.c_double), ("tile", C.c_int32), ("pad", C.c_int32)]
 
     @property
     def S1(self) -> int:
@@ -110,6 +110,8 @@ def lib():
             "sgpm_gs_sparsify": ([P, P, C.c_uint32, C.c_uint64, C.c_uint32, PP], st),
             "sgpm_model_train": ([P, P, P, C.c_int, P, PP], st),
             "sgpm_model_free": ([P], st),
+            "sgpm_probe_copy": ([P, C.c_uint64, C.c_int, C.POINTER(C.c_double)], st),
+            "sgpm_probe_gather": ([P, C.c_uint64, C.c_int, C.c_int, C.POINTER(C.c_double)], st),
             "sgpm_host_canonicalise": ([C.c_int64, P, C.c_int, P, C.c_uint32, P, P, P, P], st),
             "sgpm_host_plan": ([C.c_int, C.c_int, P, C.c_int, P, P, P, P, P, P, P], st),
             "sgpm_host_normal_quantile": ([C.c_double], C.c_double),
@@ -129,7 +131,7 @@ EXPORTED = ["sgpm_create", "sgpm_destroy", "sgpm_last_error", "sgpm_device_count
             "sgpm_graph_stats", "sgpm_graph_export", "sgpm_graph_free", "sgpm_pattern_create", "sgpm_pattern_plan",
             "sgpm_pattern_free", "sgpm_options_default", "sgpm_estimate", "sgpm_estimate_counted",
             "sgpm_estimate_batch", "sgpm_exact_count", "sgpm_gs_sparsify", "sgpm_model_train", "sgpm_model_free",
-            "sgpm_host_canonicalise", "sgpm_host_plan", "sgpm_host_normal_quantile", "sgpm_host_predicted_error",
+            "sgpm_probe_copy", "sgpm_probe_gather", "sgpm_host_canonicalise", "sgpm_host_plan", "sgpm_host_normal_quantile", "sgpm_host_predicted_error",
             "sgpm_host_next_window"]
 
 
@@ -309,3 +311,15 @@ def sgpm_host_predicted_error(z, n, S1: int, S2: int):
 
 def sgpm_host_next_window(n_t, opts: Options):
     return int(lib().sgpm_host_next_window(n_t, C.byref(opts)))
+
+
+def sgpm_probe_copy(ctx, nbytes, iters=10) -> float:
+    v = C.c_double()
+    _check(ctx, lib().sgpm_probe_copy(ctx, nbytes, iters, C.byref(v)))
+    return v.value
+
+
+def sgpm_probe_gather(ctx, working_set_bytes, segment_bytes, rounds=8) -> float:
+    v = C.c_double()
+    _check(ctx, lib().sgpm_probe_gather(ctx, working_set_bytes, segment_bytes, rounds, C.byref(v)))
+    return v.value

@@ -1,0 +1,112 @@
+"""Persistent batched estimation: every query's result equals its solo run bit
+for bit (samples drawn, exact sums, hits, checksum, windows, stop point), the
+device's stop test agrees with the host arithmetic, and replays of the
+captured hipGraph with new seeds stay equal to solo runs."""
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_2405_03488_amd import sgpm
+    return sgpm
+
+
+@pytest.fixture(scope="module")
+def ctx(S):
+    c = S.sgpm_create(0)
+    yield c
+    S.sgpm_destroy(c)
+
+
+@pytest.fixture(scope="module")
+def graphs(S, synth, ctx):
+    print("building batch graphs", flush=True)
+    out = []
+    for n, pairs in [(3000, synth.chung_lu_pairs(3000, 12, 2.1, 1)), (1 << 14, synth.rmat_pairs(14, 16, seed=3)),
+                     (5000, synth.er_pairs(5000, 40000, 2))]:
+        off, nbr = synth.pairs_to_csr(n, pairs)
+        out.append(S.sgpm_graph_from_csr(ctx, n, off, nbr))
+    yield out
+    for g in out:
+        S.sgpm_graph_free(g)
+
+
+def same(a, b):
+    assert a.n_samples == b.n_samples
+    assert a.S1 == b.S1 and a.S2 == b.S2
+    assert a.n_hits == b.n_hits and a.checksum == b.checksum
+    assert a.windows == b.windows and a.converged == b.converged
+    assert a.estimate == b.estimate and a.eps_hat == b.eps_hat
+
+
+MOTIFS = [("3-star", True), ("4-path", True), ("tailed-triangle", True), ("4-cycle", True), ("diamond", True),
+          ("4-clique", True), ("wedge", True), ("triangle", False)]
+
+
+def make_queries(S, synth, ctx, graphs, seed0):
+    qs = []
+    for gi, g in enumerate(graphs):
+        for pi, (name, induced) in enumerate(MOTIFS):
+            k, e = synth.pattern(name)
+            p = S.sgpm_pattern_create(ctx, k, e, induced)
+            i = len(qs)
+            if i % 5 == 4:
+                o = S.sgpm_options_default(mode=S.MODE_FIXED_N, fixed_n=123457 + i, seed=seed0 + i, checksum=1)
+            else:
+                o = S.sgpm_options_default(eps=0.03, seed=seed0 + i, query_tag=i, n_min=1 << 16, w_min=1 << 15,
+                                           quantum=1 << 12, checksum=1, max_samples=1 << 24)
+            qs.append((g, p, o))
+    return qs
+
+
+def test_batch_equals_solo(S, synth, ctx, graphs):
+    qs = make_queries(S, synth, ctx, graphs, 100)
+    res = S.sgpm_estimate_batch(ctx, [q[0] for q in qs], [q[1] for q in qs], [q[2] for q in qs])
+    assert len(res) == 24
+    for (g, p, o), rb in zip(qs, res):
+        rs, _ = S.sgpm_estimate(ctx, g, p, o)
+        same(rb, rs)
+        assert rb.tile >= 16
+    for q in qs:
+        S.sgpm_pattern_free(q[1])
+
+
+def test_batch_replay_new_seeds(S, synth, ctx, graphs):
+    """The second and third calls with the same shape replay the captured graph."""
+    for seed0 in (500, 900):
+        qs = make_queries(S, synth, ctx, graphs, seed0)
+        res = S.sgpm_estimate_batch(ctx, [q[0] for q in qs], [q[1] for q in qs], [q[2] for q in qs])
+        for (g, p, o), rb in zip(qs, res):
+            rs, _ = S.sgpm_estimate(ctx, g, p, o)
+            same(rb, rs)
+        for q in qs:
+            S.sgpm_pattern_free(q[1])
+
+
+def test_batch_single_and_empty(S, O, synth, ctx, graphs):
+    off, nbr = synth.pairs_to_csr(7, synth.ring_pairs(7)[:0])
+    empty = S.sgpm_graph_from_csr(ctx, 7, off, nbr)
+    k, e = synth.pattern("triangle")
+    p = S.sgpm_pattern_create(ctx, k, e)
+    o = S.sgpm_options_default(eps=0.05, seed=3, n_min=1 << 14, w_min=1 << 14, quantum=1, checksum=1)
+    res = S.sgpm_estimate_batch(ctx, [empty, graphs[0]], [p, p], [o, o])
+    assert res[0].estimate == 0.0 and res[0].n_samples == 0 and res[0].converged == 1
+    rs, _ = S.sgpm_estimate(ctx, graphs[0], p, o)
+    same(res[1], rs)
+    res = S.sgpm_estimate_batch(ctx, [graphs[2]], [p], [o])
+    rs, _ = S.sgpm_estimate(ctx, graphs[2], p, o)
+    same(res[0], rs)
+    S.sgpm_pattern_free(p)
+    S.sgpm_graph_free(empty)
+
+
+def test_batch_rejects_unsupported(S, synth, ctx, graphs):
+    k, e = synth.pattern("triangle")
+    p = S.sgpm_pattern_create(ctx, k, e)
+    o = S.sgpm_options_default(mode=S.MODE_GS)
+    with pytest.raises(S.SgpmError) as ei:
+        S.sgpm_estimate_batch(ctx, [graphs[0]], [p], [o])
+    assert ei.value.status == S.SGPM_EUNSUPPORTED
+    S.sgpm_pattern_free(p)
