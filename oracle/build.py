@@ -4,7 +4,7 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SO = os.path.join(HERE, "liboracle.so")
-SOURCES = ["orc_graph.c", "orc_pattern.c", "orc_ns.c", "orc_gs.c"]
+SOURCES = ["orc_graph.c", "orc_pattern.c", "orc_ns.c", "orc_gs.c", "orc_learned.c"]
 
 
 def build(force: bool = True) -> str:

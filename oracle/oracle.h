@@ -119,6 +119,14 @@ int orc_gs_sparsify(const orc_graph* g, const int32_t* colour, orc_graph* out);
 void orc_gs_count(const orc_graph* g, const orc_plan* p, uint32_t c, uint64_t seed, uint32_t rep,
                   int nthreads, uint64_t* y_lo, uint64_t* y_hi);
 
+int32_t orc_bucket(const orc_graph* g, int64_t v);
+void orc_ns_sample_learned(const orc_graph* g, const orc_plan* p, const uint16_t* table, uint64_t seed,
+                           uint32_t tag, uint64_t s, const uint64_t* draws, orc_rec* r, double* alpha_f);
+double orc_bf16(double x);
+int orc_mlp_nparams(void);
+double orc_mlp(const float* params, const float* X, const float* y, int64_t N, int bf16, double* s_out,
+               double* grads);
+
 #ifdef __cplusplus
 }
 #endif

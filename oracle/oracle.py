@@ -114,6 +114,15 @@ def lib():
         L.orc_gs_sparsify.argtypes = [G, P, G]
         L.orc_gs_count.argtypes = [G, PL, C.c_uint32, C.c_uint64, C.c_uint32, C.c_int,
                                    C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
+        L.orc_bucket.argtypes = [G, C.c_int64]
+        L.orc_bucket.restype = C.c_int32
+        L.orc_ns_sample_learned.argtypes = [G, PL, P, C.c_uint64, C.c_uint32, C.c_uint64, P, C.POINTER(Rec),
+                                            C.POINTER(C.c_double)]
+        L.orc_bf16.argtypes = [C.c_double]
+        L.orc_bf16.restype = C.c_double
+        L.orc_mlp_nparams.restype = C.c_int
+        L.orc_mlp.argtypes = [P, P, P, C.c_int64, C.c_int, P, P]
+        L.orc_mlp.restype = C.c_double
         L.orc_digits_to_double.argtypes = [P, C.c_int]
         L.orc_digits_to_double.restype = C.c_double
         L.orc_gs_run.argtypes = [G, PL, C.c_uint32, C.c_uint64, C.c_double, C.c_double, C.c_int, C.c_int,
@@ -386,3 +395,95 @@ def gs_run(g: OGraph, p: Plan, c, seed, eps=0.01, confidence=0.95, reps_max=64, 
 def digits_to_double(x: int) -> float:
     d = np.array([(x >> (32 * i)) & 0xFFFFFFFF for i in range(24)], dtype=np.uint32)
     return float(lib().orc_digits_to_double(d.ctypes.data, 24))
+
+
+# ------------------------------------------------------------------ learned proposal
+TABLE_SHAPE = (8, 32, 32, 32)
+
+
+def bucket(g: OGraph, v) -> int:
+    return int(lib().orc_bucket(g.ref(), v))
+
+
+def sample_learned(g: OGraph, p: Plan, table, seed, tag, s, draws=None):
+    t = np.ascontiguousarray(table, dtype=np.uint16).reshape(-1)
+    assert t.size == 8 * 32 * 32 * 32
+    r = Rec()
+    a = C.c_double()
+    if draws is not None:
+        d = np.zeros(24, dtype=np.uint64)
+        for i, x in enumerate(draws):
+            d[i] = int(x)
+        lib().orc_ns_sample_learned(g.ref(), C.byref(p), t.ctypes.data, seed, tag, s, d.ctypes.data, C.byref(r),
+                                    C.byref(a))
+    else:
+        lib().orc_ns_sample_learned(g.ref(), C.byref(p), t.ctypes.data, seed, tag, s, None, C.byref(r), C.byref(a))
+    return r, a.value
+
+
+def bf16(x: float) -> float:
+    return float(lib().orc_bf16(x))
+
+
+def mlp_nparams() -> int:
+    return int(lib().orc_mlp_nparams())
+
+
+def mlp(params, X, y=None, bf16=True, grads=False):
+    pr = np.ascontiguousarray(params, dtype=np.float32)
+    Xa = np.ascontiguousarray(X, dtype=np.float32)
+    N = Xa.shape[0]
+    ya = np.ascontiguousarray(y, dtype=np.float32) if y is not None else None
+    s_out = np.zeros(N, dtype=np.float64)
+    g = np.zeros(mlp_nparams(), dtype=np.float64) if grads else None
+    loss = lib().orc_mlp(pr.ctypes.data, Xa.ctypes.data, ya.ctypes.data if ya is not None else None, N, int(bf16),
+                         s_out.ctypes.data, g.ctypes.data if g is not None else None)
+    return loss, s_out, g
+
+
+def exact_expectation_learned(g: OGraph, p: Plan, table):
+    """Sum over every walk of Pr(walk) * alpha'(walk), exact rationals for the
+    probabilities and the sampler's FP64 alpha' as the value."""
+    k = p.k
+    M = g.m if p.oriented else 2 * g.m
+    if M == 0:
+        return Fraction(0)
+    tab = np.asarray(table, dtype=np.int64).reshape(TABLE_SHAPE)
+
+    def r_for(i, N):
+        return -((-i << 64) // N)
+
+    total = Fraction(0)
+
+    def walk(draws, depth, prob):
+        nonlocal total
+        rec, af = sample_learned(g, p, table, 0, 0, 0, draws)
+        if depth == k:
+            if rec.hit:
+                total += prob * Fraction(af)
+            return
+        if int(rec.size[depth]) == 0:
+            return
+        cands = candidates(g, p, depth, list(rec.v)[:depth])
+        b0 = bucket(g, rec.v[0])
+        bp = bucket(g, rec.v[depth - 1])
+        w = tab[depth, b0, bp]
+        nb = np.zeros(32, dtype=np.int64)
+        for x in cands:
+            nb[bucket(g, x)] += 1
+        sigma = int((nb * w).sum())
+        run = 0
+        for b in range(32):
+            if nb[b] == 0:
+                continue
+            pb = Fraction(int(nb[b] * w[b]), sigma)
+            for i in range(int(nb[b])):
+                d = list(draws) + [0] * (24 - len(draws))
+                d[depth] = r_for(run, sigma)
+                d[16 + depth] = r_for(i, int(nb[b]))
+                walk(d, depth + 1, prob * pb / int(nb[b]))
+            run += int(nb[b] * w[b])
+
+    for e in range(M):
+        walk([r_for(e, M)] + [0] * 23, 2, Fraction(1, M))
+    return total
