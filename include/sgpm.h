@@ -163,7 +163,7 @@ typedef struct {
     double seconds_total;    /* wall time of the call */
     double seconds_kernel;   /* device time of the sampling kernels alone (HIP events around each) */
     int32_t tile;            /* batch: samples per ticket picked by the autotuner */
-    int32_t pad;
+    int32_t weight_shift;    /* sums are of X * 2^weight_shift (52 with a learned proposal, else 0) */
 } sgpm_result;
 
 /* Defaults: eps 0.01, confidence 0.95, seed 1, tag 0, strict NS, n_min = w_min =
@@ -219,6 +219,22 @@ typedef struct {
 sgpm_status sgpm_model_train(sgpm_ctx_t ctx, sgpm_graph_t g, const sgpm_pattern_t* patterns, int np,
                              const sgpm_train_cfg* cfg, sgpm_model_t* out);
 sgpm_status sgpm_model_free(sgpm_model_t m);
+/* A proposal from given weight tables (np patterns, np x [8][32][32][32]
+ * uint16 weights >= 1, indexed [step][bucket of v_0][bucket of v_{j-1}]
+ * [candidate bucket], bucket = floor(log2(1 + degree)) clipped to 31). */
+sgpm_status sgpm_model_from_tables(sgpm_ctx_t ctx, int np, const sgpm_pattern_t* patterns, const uint16_t* tables,
+                                   sgpm_model_t* out);
+/* Copy table i (8*32*32*32 uint16) out of a model. */
+sgpm_status sgpm_model_table(sgpm_model_t m, int i, uint16_t* out);
+/* Trained parameters (nullable; *nparams = 0 for table-only models) and
+ * stats4 = {pilot seconds, total training seconds, first loss, last loss}. */
+sgpm_status sgpm_model_info(sgpm_model_t m, float* params_out, int* nparams, double* stats4, uint64_t* tuples);
+/* The MLP on the GPU (MFMA BF16, FP32 accumulate): forward scores of N rows of
+ * 16 features, and the gradient of mean (s - y)^2 / 2 over them.  params is
+ * W1[16x64], b1[64], W2[64x64], b2[64], w3[64], b3 (5313 floats). */
+sgpm_status sgpm_mlp_forward(sgpm_ctx_t ctx, const float* params, const float* X, int64_t N, float* s_out);
+sgpm_status sgpm_mlp_grad(sgpm_ctx_t ctx, const float* params, const float* X, const float* y, int64_t N,
+                          float* grads_out);
 
 /* ------------------------------------------------------------------ measurement probes */
 /* Streaming copy of `bytes` (rounded down to 16) repeated iters times; *gbs =

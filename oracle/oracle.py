@@ -295,6 +295,7 @@ def rec_hash(r: Rec) -> int:
     return int(lib().orc_rec_hash(C.byref(r)))
 
 
+
 def trace(g: OGraph, p: Plan, seed, tag, s0, count, threads=None):
     arr = (Rec * count)()
     lib().orc_ns_trace(g.ref(), C.byref(p), seed, tag, s0, count, threads or nthreads(), C.cast(arr, C.c_void_p))

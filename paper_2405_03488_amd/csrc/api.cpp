@@ -14,6 +14,7 @@ using namespace sgpm;
 
 namespace sgpm {
 sgpm_status gs_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_options& o, sgpm_result* res);
+sgpm_status learn_args_for(sgpm_ctx* c, sgpm_graph* g, sgpm_pattern* p, sgpm_model* m, LearnArgs* la);
 }
 
 namespace {
@@ -154,6 +155,24 @@ sgpm_status sgpm_graph_from_csr(sgpm_ctx_t c, int64_t n, const void* offsets, in
         HIP_TRY(c, hipMemcpy(g->d_epair, ep.data(), sizeof(int2) * (size_t)h.m, hipMemcpyHostToDevice));
         HIP_TRY(c, hipMemcpy(g->d_arow, arow.data(), sizeof(int32_t) * (size_t)(2 * h.m), hipMemcpyHostToDevice));
     }
+    // degree buckets b = floor(log2(1 + deg)) are non-increasing in the canonical id
+    g->degree_ordered = true;
+    {
+        int64_t cntb[32] = {0};
+        for (int64_t u = 0; u < n; u++) {
+            const int64_t d = h.off[(size_t)u + 1] - h.off[(size_t)u];
+            int b = 0;
+            while (b < 31 && ((d + 1) >> (b + 1)) > 0) b++;
+            cntb[b]++;
+        }
+        int64_t above = 0;
+        for (int b = 31; b >= 0; b--) {
+            g->bthr[b] = (int32_t)above;  // vertices with bucket > b
+            above += cntb[b];
+        }
+        HIP_TRY(c, hipMalloc(&g->d_bthr, sizeof(int32_t) * 32));
+        HIP_TRY(c, hipMemcpy(g->d_bthr, g->bthr, sizeof(int32_t) * 32, hipMemcpyHostToDevice));
+    }
     g->perm = std::move(h.perm);
     *out = g.release();
     return SGPM_OK;
@@ -185,6 +204,7 @@ sgpm_status sgpm_graph_free(sgpm_graph_t g) {
     (void)hipFree(g->d_nbr);
     (void)hipFree(g->d_epair);
     (void)hipFree(g->d_arow);
+    if (g->d_bthr) (void)hipFree(g->d_bthr);
     delete g;
     return SGPM_OK;
 }
@@ -245,7 +265,7 @@ void absorb(NsState& s, const unsigned long long* sums) {
 
 // Launch [s0, s1) with the given lane count into slot `slot`; enqueue only.
 sgpm_status enqueue_range(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_options& o, uint64_t s0, uint64_t s1,
-                          int lanes, size_t slot, const TraceArgs& tr, int count_bytes) {
+                          int lanes, size_t slot, const TraceArgs& tr, int count_bytes, const LearnArgs& la) {
     LaunchCfg cfg;
     cfg.lanes = lanes;
     cfg.blocks = blocks_for(c, lanes);
@@ -276,7 +296,7 @@ sgpm_status enqueue_range(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_
     }
     HIP_TRY(c, hipEventRecord(c->kev[2 * slot], c->st));
     HIP_TRY(c, launch_ns_window(g->view(), p, o.seed, o.query_tag, s0, s1, cfg, dynamic ? sl : nullptr,
-                                c->d_partials, o.checksum, count_bytes, tr, c->st));
+                                c->d_partials, o.checksum, count_bytes, tr, la, c->st));
     HIP_TRY(c, hipEventRecord(c->kev[2 * slot + 1], c->st));
     HIP_TRY(c, launch_reduce_partials(c->d_partials, cfg.blocks, sl + 1, c->st));
     HIP_TRY(c, hipMemcpyAsync(c->h_slots + slot * SLOT_WORDS, sl, SLOT_WORDS * sizeof(unsigned long long),
@@ -284,12 +304,15 @@ sgpm_status enqueue_range(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_
     return SGPM_OK;
 }
 
-void fill_result(sgpm_result* r, const NsState& s, double z) {
+void fill_result(sgpm_result* r, const NsState& s, double z, int shift) {
     r->n_samples = s.n;
     r->n_hits = s.hits;
     for (int i = 0; i < 8; i++) r->sum_digits[i] = s.S1.d[(size_t)i];
     for (int i = 0; i < 12; i++) r->sumsq_digits[i] = s.S2.d[(size_t)i];
-    r->estimate = s.n ? big_to_double(s.S1) / (double)s.n : 0.0;
+    // learned proposal: the sums are of alpha' * 2^shift (exact integers); the
+    // predicted error is invariant to that power-of-two scale
+    r->estimate = s.n ? std::ldexp(big_to_double(s.S1) / (double)s.n, -shift) : 0.0;
+    r->weight_shift = shift;
     r->eps_hat = predicted_error(z, s.n, s.S1, s.S2);
     r->z = z;
     const double sigma = std::isfinite(r->eps_hat) ? r->estimate * r->eps_hat / z : INFINITY;
@@ -300,7 +323,10 @@ void fill_result(sgpm_result* r, const NsState& s, double z) {
 }
 
 sgpm_status ns_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_options& o, sgpm_result* res,
-                        int count_bytes) {
+                        int count_bytes, const NsExtra* ex = nullptr) {
+    LearnArgs la{nullptr, nullptr};
+    if (ex) la = ex->la;
+    const bool learned = la.table != nullptr;
     auto t_start = std::chrono::steady_clock::now();
     std::memset(res, 0, sizeof(*res));
     res->scheme = SGPM_SCHEME_NS;
@@ -315,18 +341,19 @@ sgpm_status ns_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_op
     HIP_TRY(c, hipSetDevice(c->dev));
     // trace buffer
     sgpm_trace_rec* d_trace = nullptr;
-    TraceArgs tr{nullptr, 0, 0};
+    TraceArgs tr{nullptr, 0, 0, nullptr};
     const uint64_t ntr = (o.trace_buf && o.trace_hi > o.trace_lo) ? o.trace_hi - o.trace_lo : 0;
     if (ntr) {
         HIP_TRY(c, hipMalloc(&d_trace, ntr * sizeof(sgpm_trace_rec)));
         HIP_TRY(c, launch_fill_u64((unsigned long long*)d_trace, ntr * sizeof(sgpm_trace_rec) / 8, 0ull, c->st));
-        tr = TraceArgs{d_trace, o.trace_lo, o.trace_hi};
+        tr = TraceArgs{d_trace, o.trace_lo, o.trace_hi, ex ? ex->d_sizes : nullptr};
     }
     hipEvent_t e0, e1;
     HIP_TRY(c, hipEventCreate(&e0));
     HIP_TRY(c, hipEventCreate(&e1));
     NsState s;
     int lanes = o.lanes_per_sample;
+    if (learned || tr.sizes) lanes = 64;  // the learned proposal and pilot sizes run one sample per wave
     double dev_seconds = 0.0, kernel_seconds = 0.0;
     int windows = 0, launches = 0;
     bool converged = false;
@@ -351,7 +378,7 @@ sgpm_status ns_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_op
                 HIP_TRY(c, hipEventCreate(&x0));
                 HIP_TRY(c, hipEventCreate(&x1));
                 HIP_TRY(c, hipEventRecord(x0, c->st));
-                status = enqueue_range(c, g, p, o, a, b, cand[i], slots++, tr, count_bytes);
+                status = enqueue_range(c, g, p, o, a, b, cand[i], slots++, tr, count_bytes, la);
                 if (status != SGPM_OK) return status;
                 HIP_TRY(c, hipEventRecord(x1, c->st));
                 HIP_TRY(c, hipEventSynchronize(x1));
@@ -370,7 +397,7 @@ sgpm_status ns_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_op
             }
             lanes = best;
         } else {
-            status = enqueue_range(c, g, p, o, s.n, nx, lanes, slots++, tr, count_bytes);
+            status = enqueue_range(c, g, p, o, s.n, nx, lanes, slots++, tr, count_bytes, la);
             if (status != SGPM_OK) return status;
         }
         HIP_TRY(c, hipEventRecord(e1, c->st));
@@ -401,7 +428,7 @@ sgpm_status ns_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_op
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    fill_result(res, s, z);
+    fill_result(res, s, z, learned ? 52 : 0);
     res->windows = windows;
     res->lanes_per_sample = lanes;
     res->seconds_sampling = dev_seconds;
@@ -423,8 +450,8 @@ sgpm_status ns_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_op
 
 namespace sgpm {
 sgpm_status ns_estimate_solo(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_options& o, sgpm_result* res,
-                             int count_bytes) {
-    return ns_estimate(c, g, p, o, res, count_bytes);
+                             int count_bytes, const NsExtra* ex) {
+    return ns_estimate(c, g, p, o, res, count_bytes, ex);
 }
 }  // namespace sgpm
 
@@ -452,8 +479,13 @@ sgpm_status sgpm_estimate(sgpm_ctx_t c, sgpm_graph_t g, sgpm_pattern_t p, const 
     if (st != SGPM_OK) return st;
     switch (o->mode) {
         case SGPM_MODE_STRICT_NS:
-        case SGPM_MODE_FIXED_N:
-            return ns_estimate(c, g, p->plan, *o, res, 0);
+        case SGPM_MODE_FIXED_N: {
+            if (!o->proposal) return ns_estimate(c, g, p->plan, *o, res, 0);
+            NsExtra ex{};
+            sgpm_status st2 = learn_args_for(c, g, p, o->proposal, &ex.la);
+            if (st2 != SGPM_OK) return st2;
+            return ns_estimate(c, g, p->plan, *o, res, 0, &ex);
+        }
         case SGPM_MODE_GS:
             return gs_estimate(c, g, p->plan, *o, res);
         default:
@@ -470,6 +502,7 @@ sgpm_status sgpm_estimate_counted(sgpm_ctx_t c, sgpm_graph_t g, sgpm_pattern_t p
     if (st != SGPM_OK) return st;
     if (o->mode != SGPM_MODE_STRICT_NS && o->mode != SGPM_MODE_FIXED_N)
         return fail(c, SGPM_EUNSUPPORTED, "byte counting is for NS modes");
+    if (o->proposal) return fail(c, SGPM_EUNSUPPORTED, "byte counting is for the uniform proposal");
     return ns_estimate(c, g, p->plan, *o, res, 1);
 }
 
@@ -518,11 +551,6 @@ uint64_t sgpm_host_next_window(uint64_t n_t, const sgpm_options* o) { return o ?
 
 // ------------------------------------------------------------------ entry points built in later modules
 extern "C" {
-sgpm_status sgpm_model_train(sgpm_ctx_t c, sgpm_graph_t, const sgpm_pattern_t*, int, const sgpm_train_cfg*,
-                             sgpm_model_t*) {
-    return fail(c, SGPM_EUNSUPPORTED, "learned proposal is not built");
-}
-sgpm_status sgpm_model_free(sgpm_model_t) { return SGPM_EUNSUPPORTED; }
 }
 
 // ------------------------------------------------------------------ measurement probes

@@ -15,7 +15,7 @@
 namespace sgpm {
 
 sgpm_status ns_estimate_solo(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_options& o, sgpm_result* res,
-                             int count_bytes);
+                             int count_bytes, const NsExtra* ex = nullptr);
 
 namespace {
 

@@ -154,10 +154,49 @@ __device__ __forceinline__ bool member(const int32_t* __restrict__ R, int32_t rl
 // One NS-prune sample.  Returns 0xFF for a hit, else the failing position j.
 // For G > 1 all G lanes of a group call it with the same s.  `list` is the
 // group's LDS area of CAP words holding the current candidate set.
+// b(x) = #{t < 31 : x < thr[t]}; thr is non-increasing, so a binary search
+__device__ __forceinline__ int32_t bucket_of(const LearnArgs& la, int32_t x) {
+    int32_t lo = 0, hi = 31;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (x < la.thr[mid]) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ uint64_t wave_incl_scan(uint64_t x) {
+    const int lane = (int)(threadIdx.x & 63);
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint64_t y = __shfl_up(x, (unsigned)o);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+
+// alpha' * 2^52 as an exact 128-bit integer (alpha' >= 1); false when alpha' >= 2^76
+__device__ __forceinline__ bool fixed52(double a, uint64_t& lo, uint64_t& hi) {
+    if (!(a < 75557863725914323419136.0)) return false;  // 2^76
+    const uint64_t bits = (uint64_t)__double_as_longlong(a);
+    const int e = (int)((bits >> 52) & 0x7FF) - 1023;
+    const uint64_t mant = (bits & ((1ull << 52) - 1ull)) | (1ull << 52);
+    if (e < 64) {
+        lo = mant << e;
+        hi = e == 0 ? 0ull : mant >> (64 - e);
+    } else {
+        lo = 0;
+        hi = mant << (e - 64);
+    }
+    return true;
+}
+
 template <int G>
 __device__ __forceinline__ uint32_t ns_sample(const DGraph& g, const Plan& p, uint64_t seed, uint32_t tag, uint64_t s,
                                              int32_t (&v)[8], uint64_t& alo, uint64_t& ahi, uint64_t& ovf,
-                                             uint64_t& bytes, bool count_bytes, int32_t* list) {
+                                             uint64_t& bytes, bool count_bytes, int32_t* list,
+                                             const LearnArgs* la = nullptr, uint32_t* hist = nullptr,
+                                             uint32_t* sz = nullptr) {
     constexpr int CAP = LDS_WORDS / (256 / G);
     const int lane = (int)(threadIdx.x & 63);
     const int gl = lane & (G - 1);
@@ -195,6 +234,10 @@ __device__ __forceinline__ uint32_t ns_sample(const DGraph& g, const Plan& p, ui
     alo = M;
     ahi = 0;
     bytes = 8;
+    const bool learned = (G == 64) && la != nullptr && la->table != nullptr;
+    double af = (double)M;
+    int32_t b0 = 0;
+    if (learned) b0 = bucket_of(*la, v[0]);
     uint32_t opened = 0;
     int32_t prevcnt = -1;  // |S_{j-1}| when the whole set sits in `list`
 
@@ -294,9 +337,46 @@ __device__ __forceinline__ uint32_t ns_sample(const DGraph& g, const Plan& p, ui
             cnt += (uint32_t)__popcll(okm);
             if (inm != gmask) break;
         }
+        if (sz) sz[j] = cnt;
         if (cnt == 0) return (uint32_t)j;
 
-        const uint32_t idx = (uint32_t)__umul64hi((uint64_t)cnt, philox_r64(seed, s, (uint32_t)j, tag));
+        uint32_t idx = 0;
+        if constexpr (G == 64) {
+            if (learned) {
+                // weighted bucket, then a uniform member of it (learned proposal)
+                if (lane < 32) hist[lane] = 0;
+                if (cnt <= (uint32_t)CAP) {
+                    for (uint32_t i = (uint32_t)lane; i < cnt; i += 64u) atomicAdd(&hist[bucket_of(*la, list[i])], 1u);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) cur[i] = 0;
+                    for (int32_t base = start; base < slen; base += G) {
+                        int32_t x;
+                        uint64_t inm;
+                        const bool ok = eval_chunk(base, x, inm);
+                        if (ok) atomicAdd(&hist[bucket_of(*la, x)], 1u);
+                        if (inm != gmask) break;
+                    }
+                }
+                const int32_t bp = bucket_of(*la, v[j - 1]);
+                const uint64_t nb = lane < 32 ? (uint64_t)hist[lane] : 0ull;
+                const uint64_t w =
+                    lane < 32 ? (uint64_t)la->table[(((size_t)j * 32 + (size_t)b0) * 32 + (size_t)bp) * 32 + lane] : 0ull;
+                const uint64_t cum = wave_incl_scan(nb * w);
+                const uint64_t cumn = wave_incl_scan(nb);
+                const uint64_t sigma = __shfl(cum, 63);
+                const uint64_t t = __umul64hi(sigma, philox_r64(seed, s, (uint32_t)j, tag));
+                const int bsel = __ffsll((unsigned long long)__ballot(lane < 32 && cum > t)) - 1;
+                const uint64_t nbs = __shfl(nb, bsel), wbs = __shfl(w, bsel), upto = __shfl(cumn, bsel);
+                const uint64_t inb = __umul64hi(nbs, philox_r64(seed, s, 16u + (uint32_t)j, tag));
+                idx = (uint32_t)((uint64_t)cnt - upto + inb);
+                af = __dmul_rn(af, __ddiv_rn((double)sigma, (double)wbs));
+            } else {
+                idx = (uint32_t)__umul64hi((uint64_t)cnt, philox_r64(seed, s, (uint32_t)j, tag));
+            }
+        } else {
+            idx = (uint32_t)__umul64hi((uint64_t)cnt, philox_r64(seed, s, (uint32_t)j, tag));
+        }
         int32_t pick = -1;
         if (cnt <= (uint32_t)CAP) {
             pick = uni<G>(list[idx]);
@@ -332,13 +412,21 @@ __device__ __forceinline__ uint32_t ns_sample(const DGraph& g, const Plan& p, ui
             rp[j] = g.nbr + bj;
             rl[j] = (int32_t)(ej - bj);
         }
-        // alpha *= |S_j| with 128-bit overflow detection
-        const uint64_t plo = alo * (uint64_t)cnt, phi = __umul64hi(alo, (uint64_t)cnt);
-        const uint64_t qlo = ahi * (uint64_t)cnt, qhi = __umul64hi(ahi, (uint64_t)cnt);
-        const uint64_t nhi = phi + qlo;
-        if (qhi != 0 || nhi < qlo) ovf = 1;
-        alo = plo;
-        ahi = nhi;
+        if (!learned) {
+            // alpha *= |S_j| with 128-bit overflow detection
+            const uint64_t plo = alo * (uint64_t)cnt, phi = __umul64hi(alo, (uint64_t)cnt);
+            const uint64_t qlo = ahi * (uint64_t)cnt, qhi = __umul64hi(ahi, (uint64_t)cnt);
+            const uint64_t nhi = phi + qlo;
+            if (qhi != 0 || nhi < qlo) ovf = 1;
+            alo = plo;
+            ahi = nhi;
+        }
+    }
+    if (learned) {
+        if (!fixed52(af, alo, ahi)) {
+            ovf = 1;
+            alo = ahi = 0;
+        }
     }
     return 0xFFu;
 }

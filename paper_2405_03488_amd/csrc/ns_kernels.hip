@@ -153,13 +153,18 @@ __global__ __launch_bounds__(256) void ns_window_kernel(DGraph g, Plan p, uint64
 // the 32-bit digits of X, lanes 8-15 the digit columns of X^2 (low and high
 // halves of the digit products), lane 20 hits, 21 the checksum, 22 bytes,
 // 23 the overflow flag.  Digit columns are normalised once per block.
+// MODE 0: uniform proposal; 1: learned proposal; 2: uniform with per-step set
+// sizes recorded for traced samples (training pilots)
+template <int MODE>
 __global__ __launch_bounds__(256, 8) void ns_wave_kernel(DGraph g, Plan p, uint64_t seed, uint32_t tag, uint64_t s0,
                                                       uint64_t s1, int spl, unsigned long long* __restrict__ ticket,
                                                       unsigned long long* __restrict__ partials, int checksum,
-                                                      int count_bytes, TraceArgs tr) {
+                                                      int count_bytes, TraceArgs tr, LearnArgs la) {
     constexpr int G = 64;
     const int lane = (int)(threadIdx.x & 63);
     __shared__ int32_t s_list[LDS_WORDS];
+    __shared__ uint32_t s_hist[4][32];
+    uint32_t* hist = s_hist[threadIdx.x >> 6];
     int32_t* list = s_list + (threadIdx.x / G) * (LDS_WORDS / (256 / G));
     uint64_t acc = 0;
     uint64_t ovf = 0;
@@ -182,7 +187,9 @@ __global__ __launch_bounds__(256, 8) void ns_wave_kernel(DGraph g, Plan p, uint6
             if (s >= s1) break;
             int32_t v[8];
             uint64_t alo, ahi, b = 0, ov = 0;
-            const uint32_t st = ns_sample<G>(g, p, seed, tag, s, v, alo, ahi, ov, b, count_bytes != 0, list);
+            uint32_t sz[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            const uint32_t st = ns_sample<G>(g, p, seed, tag, s, v, alo, ahi, ov, b, count_bytes != 0, list,
+                                             MODE == 1 ? &la : nullptr, hist, MODE == 2 ? sz : nullptr);
             ovf |= ov;
             if (st != 0xFFu) {
                 alo = 0;
@@ -230,6 +237,13 @@ __global__ __launch_bounds__(256, 8) void ns_wave_kernel(DGraph g, Plan p, uint6
                 else if (lane < 14) w = (uint32_t)(alo >> (32 * (lane - 12)));
                 else w = (uint32_t)(ahi >> (32 * (lane - 14)));
                 reinterpret_cast<uint32_t*>(tr.buf + (s - tr.lo))[lane] = w;
+                if (MODE == 2 && tr.sizes && lane < 8) {
+                    uint32_t z = 0;
+#pragma unroll
+                    for (int i = 0; i < 8; ++i)
+                        if (lane == i) z = sz[i];
+                    tr.sizes[(s - tr.lo) * 8 + (uint64_t)lane] = z;
+                }
             }
         }
     }
@@ -301,8 +315,10 @@ hipError_t launch_fill_u64(unsigned long long* p, uint64_t n, unsigned long long
 
 hipError_t launch_ns_window(const DGraph& g, const Plan& p, uint64_t seed, uint32_t tag, uint64_t s0, uint64_t s1,
                             const LaunchCfg& cfg, unsigned long long* ticket, unsigned long long* partials,
-                            int checksum, int count_bytes, const TraceArgs& tr, hipStream_t st) {
+                            int checksum, int count_bytes, const TraceArgs& tr, const LearnArgs& la,
+                            hipStream_t st) {
     const dim3 grid((unsigned)cfg.blocks), block(256);
+    if ((la.table || tr.sizes) && cfg.lanes != 64) return hipErrorInvalidValue;
     switch (cfg.lanes) {
         case 1:
             hipLaunchKernelGGL(ns_window_kernel<1>, grid, block, 0, st, g, p, seed, tag, s0, s1, cfg.spl, ticket,
@@ -317,8 +333,15 @@ hipError_t launch_ns_window(const DGraph& g, const Plan& p, uint64_t seed, uint3
                                partials, checksum, count_bytes, tr);
             break;
         case 64:
-            hipLaunchKernelGGL(ns_wave_kernel, grid, block, 0, st, g, p, seed, tag, s0, s1, cfg.spl, ticket,
-                               partials, checksum, count_bytes, tr);
+            if (la.table)
+                hipLaunchKernelGGL(ns_wave_kernel<1>, grid, block, 0, st, g, p, seed, tag, s0, s1, cfg.spl, ticket,
+                                   partials, checksum, count_bytes, tr, la);
+            else if (tr.sizes)
+                hipLaunchKernelGGL(ns_wave_kernel<2>, grid, block, 0, st, g, p, seed, tag, s0, s1, cfg.spl, ticket,
+                                   partials, checksum, count_bytes, tr, la);
+            else
+                hipLaunchKernelGGL(ns_wave_kernel<0>, grid, block, 0, st, g, p, seed, tag, s0, s1, cfg.spl, ticket,
+                                   partials, checksum, count_bytes, tr, la);
             break;
         default:
             return hipErrorInvalidValue;
@@ -337,7 +360,7 @@ int ns_blocks_per_cu(int lanes) {
         case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ns_window_kernel<1>, 256, 0); break;
         case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ns_window_kernel<4>, 256, 0); break;
         case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ns_window_kernel<16>, 256, 0); break;
-        case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ns_wave_kernel, 256, 0); break;
+        case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ns_wave_kernel<0>, 256, 0); break;
         default: break;
     }
     if (e != hipSuccess || nb < 1) nb = 2;

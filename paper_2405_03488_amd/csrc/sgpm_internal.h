@@ -42,6 +42,15 @@ enum {
 struct TraceArgs {
     sgpm_trace_rec* buf;  // device buffer
     uint64_t lo, hi;
+    uint32_t* sizes;      // optional: |S_j| for j < 8 per traced sample (training pilots)
+};
+
+// Learned proposal: bucket b(v) = floor(log2(1 + deg v)) clipped to 31 is
+// non-increasing in the canonical id, so b(v) = #{b < 31 : v < thr[b]} with
+// thr[b] = the number of vertices whose bucket exceeds b.
+struct LearnArgs {
+    const uint16_t* table;  // [8][32][32][32] weights for the pattern, nullptr = uniform proposal
+    const int32_t* thr;     // [32] device array, thr[31] = 0
 };
 
 struct LaunchCfg {
@@ -53,7 +62,8 @@ struct LaunchCfg {
 // kernels (ns_kernels.hip)
 hipError_t launch_ns_window(const DGraph& g, const Plan& p, uint64_t seed, uint32_t tag, uint64_t s0, uint64_t s1,
                             const LaunchCfg& cfg, unsigned long long* ticket, unsigned long long* partials,
-                            int checksum, int count_bytes, const TraceArgs& tr, hipStream_t st);
+                            int checksum, int count_bytes, const TraceArgs& tr, const LearnArgs& la,
+                            hipStream_t st);
 hipError_t launch_reduce_partials(const unsigned long long* partials, int nblocks, unsigned long long* out20,
                                   hipStream_t st);
 int ns_blocks_per_cu(int lanes);
@@ -86,6 +96,19 @@ struct BatchState {
 int batch_blocks_per_cu();
 hipError_t launch_batch(const BatchQuery* q, BatchState* s, int nq, unsigned long long* active, int blocks,
                         hipStream_t st);
+
+struct NsExtra {
+    LearnArgs la;        // learned proposal (table nullptr = uniform)
+    uint32_t* d_sizes;   // pilot traces: |S_j| per traced sample
+};
+
+// MLP (mlp_kernels.hip)
+int mlp_nparams();
+hipError_t mlp_forward(const float* P, const float* X, int64_t N, float* s_out, hipStream_t st);
+hipError_t mlp_grad(const float* P, const float* X, const float* y, int64_t N, float* gpart, float* g,
+                    hipStream_t st);
+hipError_t mlp_adam_step(float* P, const float* X, const float* y, int64_t B, float* gpart, float* m, float* v,
+                         float lr, int step, hipStream_t st);
 
 // host helpers
 struct HostGraph {
@@ -155,6 +178,9 @@ struct sgpm_ctx {
 struct sgpm_graph {
     sgpm_ctx* ctx = nullptr;
     int64_t n = 0, m = 0, maxdeg = 0;
+    bool degree_ordered = false;  // canonical ids: degree non-increasing (bucket thresholds valid)
+    int32_t bthr[32] = {0};
+    int32_t* d_bthr = nullptr;
     std::vector<int32_t> perm;
     int64_t* d_off = nullptr;
     int32_t* d_nbr = nullptr;
@@ -165,6 +191,17 @@ struct sgpm_graph {
 
 struct sgpm_pattern {
     sgpm::Plan plan;
+};
+
+struct sgpm_model {
+    sgpm_ctx* ctx = nullptr;
+    int np = 0;
+    std::vector<sgpm::Plan> plans;
+    std::vector<uint16_t> tables;  // np x [8][32][32][32]
+    uint16_t* d_tables = nullptr;
+    std::vector<float> params;     // trained MLP (empty for table-only models)
+    double train_seconds = 0.0, pilot_seconds = 0.0, loss_first = 0.0, loss_last = 0.0;
+    uint64_t tuples = 0;
 };
 
 

@@ -54,7 +54,7 @@ class Result(C.Structure):
                 ("colours", C.c_int32), ("converged", C.c_int32), ("windows", C.c_int32),
                 ("lanes_per_sample", C.c_int32), ("launches", C.c_int32), ("checksum", C.c_uint64),
                 ("bytes", C.c_uint64), ("seconds_sampling", C.c_double), ("seconds_total", C.c_double),
-                ("seconds_kernel", C.c_double), ("tile", C.c_int32), ("pad", C.c_int32)]
+                ("seconds_kernel", C.c_double), ("tile", C.c_int32), ("weight_shift", C.c_int32)]
 
     @property
     def S1(self) -> int:
@@ -110,6 +110,11 @@ def lib():
             "sgpm_gs_sparsify": ([P, P, C.c_uint32, C.c_uint64, C.c_uint32, PP], st),
             "sgpm_model_train": ([P, P, P, C.c_int, P, PP], st),
             "sgpm_model_free": ([P], st),
+            "sgpm_model_from_tables": ([P, C.c_int, P, P, PP], st),
+            "sgpm_model_table": ([P, C.c_int, P], st),
+            "sgpm_model_info": ([P, P, P, P, P], st),
+            "sgpm_mlp_forward": ([P, P, P, C.c_int64, P], st),
+            "sgpm_mlp_grad": ([P, P, P, P, C.c_int64, P], st),
             "sgpm_probe_copy": ([P, C.c_uint64, C.c_int, C.POINTER(C.c_double)], st),
             "sgpm_probe_gather": ([P, C.c_uint64, C.c_int, C.c_int, C.POINTER(C.c_double)], st),
             "sgpm_host_canonicalise": ([C.c_int64, P, C.c_int, P, C.c_uint32, P, P, P, P], st),
@@ -131,6 +136,7 @@ EXPORTED = ["sgpm_create", "sgpm_destroy", "sgpm_last_error", "sgpm_device_count
             "sgpm_graph_stats", "sgpm_graph_export", "sgpm_graph_free", "sgpm_pattern_create", "sgpm_pattern_plan",
             "sgpm_pattern_free", "sgpm_options_default", "sgpm_estimate", "sgpm_estimate_counted",
             "sgpm_estimate_batch", "sgpm_exact_count", "sgpm_gs_sparsify", "sgpm_model_train", "sgpm_model_free",
+            "sgpm_model_from_tables", "sgpm_model_table", "sgpm_model_info", "sgpm_mlp_forward", "sgpm_mlp_grad",
             "sgpm_probe_copy", "sgpm_probe_gather", "sgpm_host_canonicalise", "sgpm_host_plan", "sgpm_host_normal_quantile", "sgpm_host_predicted_error",
             "sgpm_host_next_window"]
 
@@ -323,3 +329,52 @@ def sgpm_probe_gather(ctx, working_set_bytes, segment_bytes, rounds=8) -> float:
     v = C.c_double()
     _check(ctx, lib().sgpm_probe_gather(ctx, working_set_bytes, segment_bytes, rounds, C.byref(v)))
     return v.value
+
+
+# ------------------------------------------------------------------ learned proposal
+TABLE_WORDS = 8 * 32 * 32 * 32
+MLP_NPARAMS = 16 * 64 + 64 + 64 * 64 + 64 + 64 + 1
+
+
+def sgpm_model_from_tables(ctx, patterns, tables):
+    t = np.ascontiguousarray(np.asarray(tables, dtype=np.uint16).reshape(len(patterns), TABLE_WORDS))
+    P = (C.c_void_p * len(patterns))(*[p.value for p in patterns])
+    h = C.c_void_p()
+    _check(ctx, lib().sgpm_model_from_tables(ctx, len(patterns), P, t.ctypes.data, C.byref(h)))
+    return h
+
+
+def sgpm_model_table(m, i):
+    out = np.zeros(TABLE_WORDS, dtype=np.uint16)
+    rc = lib().sgpm_model_table(m, i, out.ctypes.data)
+    if rc != SGPM_OK:
+        raise SgpmError(rc, "model table")
+    return out.reshape(8, 32, 32, 32)
+
+
+def sgpm_model_info(m):
+    n = C.c_int()
+    lib().sgpm_model_info(m, None, C.byref(n), None, None)
+    params = np.zeros(max(1, n.value), dtype=np.float32)
+    stats = np.zeros(4, dtype=np.float64)
+    tuples = C.c_uint64()
+    lib().sgpm_model_info(m, params.ctypes.data, None, stats.ctypes.data, C.byref(tuples))
+    return {"params": params[:n.value], "pilot_seconds": float(stats[0]), "train_seconds": float(stats[1]),
+            "loss_first": float(stats[2]), "loss_last": float(stats[3]), "tuples": int(tuples.value)}
+
+
+def sgpm_mlp_forward(ctx, params, X):
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    x = np.ascontiguousarray(X, dtype=np.float32)
+    out = np.zeros(x.shape[0], dtype=np.float32)
+    _check(ctx, lib().sgpm_mlp_forward(ctx, p.ctypes.data, x.ctypes.data, x.shape[0], out.ctypes.data))
+    return out
+
+
+def sgpm_mlp_grad(ctx, params, X, y):
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    x = np.ascontiguousarray(X, dtype=np.float32)
+    yy = np.ascontiguousarray(y, dtype=np.float32)
+    out = np.zeros(MLP_NPARAMS, dtype=np.float32)
+    _check(ctx, lib().sgpm_mlp_grad(ctx, p.ctypes.data, x.ctypes.data, yy.ctypes.data, x.shape[0], out.ctypes.data))
+    return out
