@@ -354,6 +354,12 @@ sgpm_status ns_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_op
     NsState s;
     int lanes = o.lanes_per_sample;
     if (learned || tr.sizes) lanes = 64;  // the learned proposal and pilot sizes run one sample per wave
+    // lane counts picked earlier for this (graph, plan) are reused
+    const auto tune_key = std::make_tuple((const void*)g, std::string((const char*)&p, sizeof(Plan)));
+    if (lanes == 0) {
+        auto it = c->ns_tuned.find(tune_key);
+        if (it != c->ns_tuned.end()) lanes = it->second;
+    }
     double dev_seconds = 0.0, kernel_seconds = 0.0;
     int windows = 0, launches = 0;
     bool converged = false;
@@ -367,25 +373,20 @@ sgpm_status ns_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_op
             // autotune on the first window: split it over the candidate lane
             // counts, time each piece, keep the fastest per sample.  Every
             // sample is still drawn exactly once, so results are unchanged.
-            static const int cand[4] = {1, 4, 16, 64};
+            static const int cand[4] = {64, 16, 4, 1};
             const uint64_t len = nx - s.n;
             float best_ms = 0;
-            int best = 1;
+            int best = 64;
             for (int i = 0; i < 4; i++) {
                 const uint64_t a = s.n + len * (uint64_t)i / 4, b = s.n + len * (uint64_t)(i + 1) / 4;
                 if (b <= a) continue;
-                hipEvent_t x0, x1;
-                HIP_TRY(c, hipEventCreate(&x0));
-                HIP_TRY(c, hipEventCreate(&x1));
-                HIP_TRY(c, hipEventRecord(x0, c->st));
-                status = enqueue_range(c, g, p, o, a, b, cand[i], slots++, tr, count_bytes, la);
+                const size_t slot = slots++;
+                status = enqueue_range(c, g, p, o, a, b, cand[i], slot, tr, count_bytes, la);
                 if (status != SGPM_OK) return status;
-                HIP_TRY(c, hipEventRecord(x1, c->st));
-                HIP_TRY(c, hipEventSynchronize(x1));
+                // sampling-kernel time alone (the events enqueue_range records around it)
+                HIP_TRY(c, hipEventSynchronize(c->kev[2 * slot + 1]));
                 float ms = 0;
-                HIP_TRY(c, hipEventElapsedTime(&ms, x0, x1));
-                (void)hipEventDestroy(x0);
-                (void)hipEventDestroy(x1);
+                HIP_TRY(c, hipEventElapsedTime(&ms, c->kev[2 * slot], c->kev[2 * slot + 1]));
                 const float per = ms / (float)(b - a);
                 if (std::getenv("SGPM_DEBUG"))
                     std::fprintf(stderr, "sgpm autotune: lanes=%d %.3f ms for %llu samples (%.4g samples/s)\n",
@@ -396,6 +397,7 @@ sgpm_status ns_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_op
                 }
             }
             lanes = best;
+            c->ns_tuned[tune_key] = best;
         } else {
             status = enqueue_range(c, g, p, o, s.n, nx, lanes, slots++, tr, count_bytes, la);
             if (status != SGPM_OK) return status;

@@ -191,7 +191,7 @@ __device__ __forceinline__ bool fixed52(double a, uint64_t& lo, uint64_t& hi) {
     return true;
 }
 
-template <int G>
+template <int G, int KMAX = 8>
 __device__ __forceinline__ uint32_t ns_sample(const DGraph& g, const Plan& p, uint64_t seed, uint32_t tag, uint64_t s,
                                              int32_t (&v)[8], uint64_t& alo, uint64_t& ahi, uint64_t& ovf,
                                              uint64_t& bytes, bool count_bytes, int32_t* list,
@@ -242,7 +242,7 @@ __device__ __forceinline__ uint32_t ns_sample(const DGraph& g, const Plan& p, ui
     int32_t prevcnt = -1;  // |S_{j-1}| when the whole set sits in `list`
 
 #pragma unroll
-    for (int j = 2; j < 8; ++j) {
+    for (int j = 2; j < KMAX; ++j) {
         if (j >= p.k) break;
         const uint32_t conn = p.connect[j], disc = p.disconnect[j], up = p.upper[j], lw = p.lower[j];
         int32_t lo = -1, hi = BIG;

@@ -155,7 +155,7 @@ __global__ __launch_bounds__(256) void ns_window_kernel(DGraph g, Plan p, uint64
 // 23 the overflow flag.  Digit columns are normalised once per block.
 // MODE 0: uniform proposal; 1: learned proposal; 2: uniform with per-step set
 // sizes recorded for traced samples (training pilots)
-template <int MODE>
+template <int MODE, int K>
 __global__ __launch_bounds__(256, 8) void ns_wave_kernel(DGraph g, Plan p, uint64_t seed, uint32_t tag, uint64_t s0,
                                                       uint64_t s1, int spl, unsigned long long* __restrict__ ticket,
                                                       unsigned long long* __restrict__ partials, int checksum,
@@ -188,8 +188,8 @@ __global__ __launch_bounds__(256, 8) void ns_wave_kernel(DGraph g, Plan p, uint6
             int32_t v[8];
             uint64_t alo, ahi, b = 0, ov = 0;
             uint32_t sz[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-            const uint32_t st = ns_sample<G>(g, p, seed, tag, s, v, alo, ahi, ov, b, count_bytes != 0, list,
-                                             MODE == 1 ? &la : nullptr, hist, MODE == 2 ? sz : nullptr);
+            const uint32_t st = ns_sample<G, K>(g, p, seed, tag, s, v, alo, ahi, ov, b, count_bytes != 0, list,
+                                                MODE == 1 ? &la : nullptr, hist, MODE == 2 ? sz : nullptr);
             ovf |= ov;
             if (st != 0xFFu) {
                 alo = 0;
@@ -313,6 +313,41 @@ hipError_t launch_fill_u64(unsigned long long* p, uint64_t n, unsigned long long
     return hipGetLastError();
 }
 
+// one-sample-per-wave kernels, specialised on the pattern size so only the
+// steps a pattern has are compiled into its kernel
+template <int MODE>
+hipError_t launch_wave_mode(const DGraph& g, const Plan& p, uint64_t seed, uint32_t tag, uint64_t s0, uint64_t s1,
+                            const LaunchCfg& cfg, unsigned long long* ticket, unsigned long long* partials,
+                            int checksum, int count_bytes, const TraceArgs& tr, const LearnArgs& la, hipStream_t st) {
+    const dim3 grid((unsigned)cfg.blocks), block(256);
+#define SGPM_WAVE_CASE(KK)                                                                                        \
+    case KK:                                                                                                      \
+        hipLaunchKernelGGL((ns_wave_kernel<MODE, KK>), grid, block, 0, st, g, p, seed, tag, s0, s1, cfg.spl, ticket, \
+                           partials, checksum, count_bytes, tr, la);                                              \
+        break;
+    switch (p.k) {
+        SGPM_WAVE_CASE(2)
+        SGPM_WAVE_CASE(3)
+        SGPM_WAVE_CASE(4)
+        SGPM_WAVE_CASE(5)
+        SGPM_WAVE_CASE(6)
+        SGPM_WAVE_CASE(7)
+        SGPM_WAVE_CASE(8)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef SGPM_WAVE_CASE
+    return hipGetLastError();
+}
+
+hipError_t launch_wave(const DGraph& g, const Plan& p, uint64_t seed, uint32_t tag, uint64_t s0, uint64_t s1,
+                       const LaunchCfg& cfg, unsigned long long* ticket, unsigned long long* partials, int checksum,
+                       int count_bytes, const TraceArgs& tr, const LearnArgs& la, hipStream_t st) {
+    if (la.table) return launch_wave_mode<1>(g, p, seed, tag, s0, s1, cfg, ticket, partials, checksum, count_bytes, tr, la, st);
+    if (tr.sizes) return launch_wave_mode<2>(g, p, seed, tag, s0, s1, cfg, ticket, partials, checksum, count_bytes, tr, la, st);
+    return launch_wave_mode<0>(g, p, seed, tag, s0, s1, cfg, ticket, partials, checksum, count_bytes, tr, la, st);
+}
+
 hipError_t launch_ns_window(const DGraph& g, const Plan& p, uint64_t seed, uint32_t tag, uint64_t s0, uint64_t s1,
                             const LaunchCfg& cfg, unsigned long long* ticket, unsigned long long* partials,
                             int checksum, int count_bytes, const TraceArgs& tr, const LearnArgs& la,
@@ -333,15 +368,7 @@ hipError_t launch_ns_window(const DGraph& g, const Plan& p, uint64_t seed, uint3
                                partials, checksum, count_bytes, tr);
             break;
         case 64:
-            if (la.table)
-                hipLaunchKernelGGL(ns_wave_kernel<1>, grid, block, 0, st, g, p, seed, tag, s0, s1, cfg.spl, ticket,
-                                   partials, checksum, count_bytes, tr, la);
-            else if (tr.sizes)
-                hipLaunchKernelGGL(ns_wave_kernel<2>, grid, block, 0, st, g, p, seed, tag, s0, s1, cfg.spl, ticket,
-                                   partials, checksum, count_bytes, tr, la);
-            else
-                hipLaunchKernelGGL(ns_wave_kernel<0>, grid, block, 0, st, g, p, seed, tag, s0, s1, cfg.spl, ticket,
-                                   partials, checksum, count_bytes, tr, la);
+            return launch_wave(g, p, seed, tag, s0, s1, cfg, ticket, partials, checksum, count_bytes, tr, la, st);
             break;
         default:
             return hipErrorInvalidValue;
@@ -360,7 +387,7 @@ int ns_blocks_per_cu(int lanes) {
         case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ns_window_kernel<1>, 256, 0); break;
         case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ns_window_kernel<4>, 256, 0); break;
         case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ns_window_kernel<16>, 256, 0); break;
-        case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ns_wave_kernel<0>, 256, 0); break;
+        case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ns_wave_kernel<0, 8>, 256, 0); break;
         default: break;
     }
     if (e != hipSuccess || nb < 1) nb = 2;

@@ -166,7 +166,8 @@ struct sgpm_ctx {
     size_t nslots = 0;
     std::vector<hipEvent_t> kev;             // start/stop events around each sampling kernel
     // batch: autotuned lanes per (graph, plan), device/pinned tables, captured graph
-    std::map<std::tuple<const void*, std::string>, int> tuned;
+    std::map<std::tuple<const void*, std::string>, int> tuned;     // batch tile per (graph, plan)
+    std::map<std::tuple<const void*, std::string>, int> ns_tuned;  // solo lanes per sample per (graph, plan)
     int batch_nq = 0;
     void* d_bq = nullptr;
     void* h_bq = nullptr;
