@@ -195,7 +195,9 @@ def main():
         "queries": per_q,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "ns_window_kernel", "launches": launches,
+                     "kernel": sorted({"ns_wave_kernel" if lanes[q] == 64 else f"ns_window_kernel<{lanes[q]}>"
+                                       for q in queries}),
+                     "launches": launches,
                      "avg_launch_ms": kernel_s / max(1, launches) * 1e3,
                      "alg_bytes_per_launch": alg_bytes / max(1, launches),
                      "measured": probes},

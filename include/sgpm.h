@@ -107,7 +107,8 @@ enum {
     SGPM_MODE_STRICT_NS = 0,   /* NS-prune with online convergence (Sec. 4.1, 5.1 strict mode) */
     SGPM_MODE_FIXED_N = 1,     /* exactly fixed_n NS samples, no stop rule */
     SGPM_MODE_GS = 2,          /* colour sparsification + exact count, repeated colourings */
-    SGPM_MODE_HYBRID = 3       /* loose mode: choose NS or GS from pilot costs (Sec. 5.1) */
+    SGPM_MODE_HYBRID = 3       /* loose mode: choose NS or GS from pilot costs (Sec. 5.1); the
+                                  result equals that engine's own result (same options) */
 };
 enum { SGPM_SCHEME_NS = 0, SGPM_SCHEME_GS = 1, SGPM_SCHEME_EXACT = 2 };
 
@@ -164,6 +165,11 @@ typedef struct {
     double seconds_kernel;   /* device time of the sampling kernels alone (HIP events around each) */
     int32_t tile;            /* batch: samples per ticket picked by the autotuner */
     int32_t weight_shift;    /* sums are of X * 2^weight_shift (52 with a learned proposal, else 0) */
+    int32_t reserved0;
+    /* hybrid mode: predicted NS time range (the pilot slices' min and max), the
+     * predicted GS time (+inf when GS cannot meet eps), and the pilots' wall time */
+    double pred_ns_lo, pred_ns_hi, pred_gs;
+    double seconds_pilot;
 } sgpm_result;
 
 /* Defaults: eps 0.01, confidence 0.95, seed 1, tag 0, strict NS, n_min = w_min =
@@ -266,6 +272,21 @@ double sgpm_host_normal_quantile(double p);
 double sgpm_host_predicted_error(double z, uint64_t n, const uint32_t* s1, int n1, const uint32_t* s2, int n2);
 /* End of the window that starts at sample n_t under options o. */
 uint64_t sgpm_host_next_window(uint64_t n_t, const sgpm_options* o);
+/* Hybrid selection from pilot figures (loose mode, Sec. 5.1 and the NS cost
+ * model of Sec. 4.3).  Pilot NS slice i took slice_seconds[i] and gave the
+ * predicted error slice_eps_hat[i]; by the error equation the samples needed
+ * scale with (eps_hat / eps)^2, so slice i predicts slice_seconds[i] *
+ * (slice_eps_hat[i] / eps)^2 and the slices' min and max form the NS cone
+ * (*ns_lo, *ns_hi; +inf for a slice without hits).  GS: gs_reps_run (1 or 2)
+ * pilot colourings took gs_rep_seconds each on average; with two, gs_eps_hat2
+ * is their predicted error and GS needs R = max(2, ceil(2 (gs_eps_hat2 /
+ * eps)^2)) colourings (+inf if R > gs_reps_max or gs_eps_hat2 = +inf); with
+ * one, only the lower bound 2 * gs_rep_seconds is known.  *gs_pred = R *
+ * gs_rep_seconds.  Returns SGPM_SCHEME_GS when GS lies entirely below the
+ * cone, else SGPM_SCHEME_NS (above or overlapping: NS keeps the guarantee). */
+int sgpm_host_hybrid_choice(int slices, const double* slice_seconds, const double* slice_eps_hat, double eps,
+                            int gs_reps_run, double gs_rep_seconds, double gs_eps_hat2, int gs_reps_max,
+                            double* ns_lo, double* ns_hi, double* gs_pred);
 
 #ifdef __cplusplus
 }

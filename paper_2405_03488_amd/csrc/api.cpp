@@ -13,8 +13,6 @@
 using namespace sgpm;
 
 namespace sgpm {
-sgpm_status gs_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_options& o, sgpm_result* res);
-sgpm_status learn_args_for(sgpm_ctx* c, sgpm_graph* g, sgpm_pattern* p, sgpm_model* m, LearnArgs* la);
 }
 
 namespace {
@@ -370,18 +368,22 @@ sgpm_status ns_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_op
         size_t slots = 0;
         HIP_TRY(c, hipEventRecord(e0, c->st));
         if (lanes == 0) {
-            // autotune on the first window: split it over the candidate lane
-            // counts, time each piece, keep the fastest per sample.  Every
+            // autotune on the first window: split it into two rounds over the
+            // candidate lane counts and keep the fastest per sample, each
+            // candidate judged by its better piece (the first launch of a
+            // kernel pays for loading its code and for cold caches).  Every
             // sample is still drawn exactly once, so results are unchanged.
             static const int cand[4] = {64, 16, 4, 1};
+            constexpr int kPieces = 8;
             const uint64_t len = nx - s.n;
-            float best_ms = 0;
-            int best = 64;
-            for (int i = 0; i < 4; i++) {
-                const uint64_t a = s.n + len * (uint64_t)i / 4, b = s.n + len * (uint64_t)(i + 1) / 4;
+            float best_per[4] = {0, 0, 0, 0};
+            bool seen[4] = {false, false, false, false};
+            for (int i = 0; i < kPieces; i++) {
+                const uint64_t a = s.n + len * (uint64_t)i / kPieces, b = s.n + len * (uint64_t)(i + 1) / kPieces;
                 if (b <= a) continue;
+                const int ci = i % 4;
                 const size_t slot = slots++;
-                status = enqueue_range(c, g, p, o, a, b, cand[i], slot, tr, count_bytes, la);
+                status = enqueue_range(c, g, p, o, a, b, cand[ci], slot, tr, count_bytes, la);
                 if (status != SGPM_OK) return status;
                 // sampling-kernel time alone (the events enqueue_range records around it)
                 HIP_TRY(c, hipEventSynchronize(c->kev[2 * slot + 1]));
@@ -390,12 +392,17 @@ sgpm_status ns_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_op
                 const float per = ms / (float)(b - a);
                 if (std::getenv("SGPM_DEBUG"))
                     std::fprintf(stderr, "sgpm autotune: lanes=%d %.3f ms for %llu samples (%.4g samples/s)\n",
-                                 cand[i], ms, (unsigned long long)(b - a), (double)(b - a) / (ms * 1e-3));
-                if (i == 0 || per < best_ms) {
-                    best_ms = per;
-                    best = cand[i];
-                }
+                                 cand[ci], ms, (unsigned long long)(b - a), (double)(b - a) / (ms * 1e-3));
+                if (!seen[ci] || per < best_per[ci]) best_per[ci] = per;
+                seen[ci] = true;
             }
+            int best = 64;
+            float best_ms = 0;
+            for (int ci = 0; ci < 4; ci++)
+                if (seen[ci] && (best_ms == 0 || best_per[ci] < best_ms)) {
+                    best_ms = best_per[ci];
+                    best = cand[ci];
+                }
             lanes = best;
             c->ns_tuned[tune_key] = best;
         } else {
@@ -455,6 +462,36 @@ sgpm_status ns_estimate_solo(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sg
                              int count_bytes, const NsExtra* ex) {
     return ns_estimate(c, g, p, o, res, count_bytes, ex);
 }
+
+sgpm_status ns_pilot(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_options& o, const LearnArgs& la,
+                     uint64_t n, int slices, double* seconds, double* eps_hat) {
+    HIP_TRY(c, hipSetDevice(c->dev));
+    const double z = normal_quantile(1.0 - (1.0 - o.confidence) / 2.0);
+    int lanes = o.lanes_per_sample;
+    if (la.table) lanes = 64;
+    if (lanes == 0) {
+        auto it = c->ns_tuned.find(std::make_tuple((const void*)g, std::string((const char*)&p, sizeof(Plan))));
+        lanes = it != c->ns_tuned.end() ? it->second : 64;
+    }
+    const TraceArgs tr{nullptr, 0, 0, nullptr};
+    for (int i = 0; i < slices; i++) {
+        const uint64_t a = n * (uint64_t)i / (uint64_t)slices, b = n * (uint64_t)(i + 1) / (uint64_t)slices;
+        sgpm_status st = enqueue_range(c, g, p, o, a, b, lanes, (size_t)i, tr, 0, la);
+        if (st != SGPM_OK) return st;
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->st));
+    for (int i = 0; i < slices; i++) {
+        const uint64_t a = n * (uint64_t)i / (uint64_t)slices, b = n * (uint64_t)(i + 1) / (uint64_t)slices;
+        NsState s;
+        absorb(s, c->h_slots + (size_t)i * SLOT_WORDS + 1);
+        s.n = b - a;
+        float ms = 0;
+        HIP_TRY(c, hipEventElapsedTime(&ms, c->kev[2 * (size_t)i], c->kev[2 * (size_t)i + 1]));
+        seconds[i] = ms * 1e-3;
+        eps_hat[i] = predicted_error(z, s.n, s.S1, s.S2);
+    }
+    return SGPM_OK;
+}
 }  // namespace sgpm
 
 namespace {
@@ -490,6 +527,8 @@ sgpm_status sgpm_estimate(sgpm_ctx_t c, sgpm_graph_t g, sgpm_pattern_t p, const 
         }
         case SGPM_MODE_GS:
             return gs_estimate(c, g, p->plan, *o, res);
+        case SGPM_MODE_HYBRID:
+            return hybrid_estimate(c, g, p, *o, res);
         default:
             return fail(c, SGPM_EUNSUPPORTED, "mode not available");
     }
@@ -548,6 +587,14 @@ double sgpm_host_predicted_error(double z, uint64_t n, const uint32_t* s1, int n
 }
 
 uint64_t sgpm_host_next_window(uint64_t n_t, const sgpm_options* o) { return o ? next_window_end(n_t, *o) : 0; }
+
+int sgpm_host_hybrid_choice(int slices, const double* slice_seconds, const double* slice_eps_hat, double eps,
+                            int gs_reps_run, double gs_rep_seconds, double gs_eps_hat2, int gs_reps_max,
+                            double* ns_lo, double* ns_hi, double* gs_pred) {
+    if (slices < 1 || !slice_seconds || !slice_eps_hat || !(eps > 0)) return SGPM_EINVAL;
+    return hybrid_choice(slices, slice_seconds, slice_eps_hat, eps, gs_reps_run, gs_rep_seconds, gs_eps_hat2,
+                         gs_reps_max, ns_lo, ns_hi, gs_pred);
+}
 
 }  // extern "C"
 

@@ -14,9 +14,6 @@
 
 namespace sgpm {
 
-sgpm_status ns_estimate_solo(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_options& o, sgpm_result* res,
-                             int count_bytes, const NsExtra* ex = nullptr);
-
 namespace {
 
 // Tile autotuner: time 2^16 pilot samples of the query (Philox tag

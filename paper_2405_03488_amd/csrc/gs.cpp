@@ -109,11 +109,24 @@ sgpm_status exact_count(sgpm_ctx* c, sgpm_graph* g, const Plan& p, unsigned __in
     return SGPM_OK;
 }
 
-sgpm_status gs_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_options& o, sgpm_result* res) {
+sgpm_status gs_rep(sgpm_ctx* c, sgpm_graph* g, const Plan& p, uint32_t colours, uint64_t seed, uint32_t rep,
+                   unsigned __int128* y, double* dev_seconds) {
+    sgpm_graph* sp = nullptr;
+    sgpm_status st = sparsify(c, g, colours, seed, rep, &sp);
+    if (st != SGPM_OK) return st;
+    st = exact_count(c, sp, p, y, dev_seconds);
+    sgpm_graph_free(sp);
+    return st;
+}
+
+uint32_t gs_colours_for(const sgpm_options& o) { return o.colours > 0 ? (uint32_t)o.colours : 8u; }
+
+sgpm_status gs_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_options& o, sgpm_result* res,
+                        const GsPrefix* pre) {
     auto t0 = std::chrono::steady_clock::now();
     std::memset(res, 0, sizeof(*res));
     res->scheme = SGPM_SCHEME_GS;
-    const uint32_t col = o.colours > 0 ? (uint32_t)o.colours : 8u;
+    const uint32_t col = gs_colours_for(o);
     if (col > 256) return fail(c, SGPM_EINVAL, "colours must be in [1, 256]");
     const int reps = o.gs_reps_max > 0 ? o.gs_reps_max : 64;
     const double z = normal_quantile(1.0 - (1.0 - o.confidence) / 2.0);
@@ -122,18 +135,18 @@ sgpm_status gs_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_op
     for (int i = 0; i < p.k - 1; i++) scale *= col;
     Big S1(24), S2(24);
     uint64_t n = 0, nonzero = 0;
-    double dev = 0.0;
+    double dev = pre ? pre->dev_seconds : 0.0;
     bool converged = false;
     for (int r = 0; r < reps; r++) {
-        sgpm_graph* sp = nullptr;
-        sgpm_status st = sparsify(c, g, col, o.seed, (uint32_t)r, &sp);
-        if (st != SGPM_OK) return st;
         unsigned __int128 y = 0;
-        double secs = 0;
-        st = exact_count(c, sp, p, &y, &secs);
-        sgpm_graph_free(sp);
-        if (st != SGPM_OK) return st;
-        dev += secs;
+        if (pre && r < pre->n) {
+            y = pre->y[r];
+        } else {
+            double secs = 0;
+            sgpm_status st = gs_rep(c, g, p, col, o.seed, (uint32_t)r, &y, &secs);
+            if (st != SGPM_OK) return st;
+            dev += secs;
+        }
         const unsigned __int128 x = y * scale;
         if (scale && x / scale != y) return fail(c, SGPM_EOVERFLOW, "GS estimate exceeds 128 bits");
         unsigned long long d1[4], d2[8];

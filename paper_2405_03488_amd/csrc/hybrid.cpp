@@ -1,0 +1,150 @@
+// Loose mode: choose the NS or the GS engine from short pilots (Sec. 5.1).
+//
+// The paper predicts NS time as work per sample times the number of samples
+// (NS cost model, Sec. 4.3), bounded by a cone whose slopes are the cheapest
+// (first step fails) and the dearest (no step fails) sample, and predicts GS
+// time from a cost model of sparsification plus the nested-loop search
+// (Sec. 4.4).  GS is chosen only when its prediction lies entirely below the
+// NS cone; above it, or overlapping it, NS runs, since only NS carries the
+// confidence guarantee.  Its profiler and GS cost formulas are not usable as
+// printed, so both predictions here come from measurements on this device:
+//
+//  * NS: a pilot of P samples on a separate Philox stream (tag 0x80000000 | q),
+//    in S equal slices.  By the error equation (Sec. 4.1) the samples needed for
+//    eps scale as (eps_hat / eps)^2, so slice i predicts t_i (eps_hat_i / eps)^2
+//    with t_i its kernel time; the slices' minimum and maximum are the cone.
+//  * GS: colourings 0 and 1 of the GS engine itself (timed end to end:
+//    sparsification and count).  Their predicted error gives the colourings
+//    needed, R = max(2, ceil(2 (eps_hat_2 / eps)^2)), and the prediction is R
+//    times the mean colouring time.  When one colouring already takes half the
+//    cone's lower end GS cannot lie below it and the second is skipped.
+//
+// The engine then runs exactly as in its own mode with the same options (GS
+// reuses the two pilot colourings, which are its first two), so a hybrid result
+// equals the strict-NS or GS result bit for bit.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "sgpm_internal.h"
+
+namespace sgpm {
+
+int hybrid_choice(int slices, const double* slice_seconds, const double* slice_eps_hat, double eps, int gs_reps_run,
+                  double gs_rep_seconds, double gs_eps_hat2, int gs_reps_max, double* ns_lo, double* ns_hi,
+                  double* gs_pred) {
+    double lo = INFINITY, hi = 0.0;
+    for (int i = 0; i < slices; i++) {
+        const double r = slice_eps_hat[i] / eps;
+        const double t = std::isfinite(r) ? slice_seconds[i] * r * r : INFINITY;
+        lo = std::min(lo, t);
+        hi = std::max(hi, t);
+    }
+    double gs = INFINITY;
+    if (gs_reps_run >= 2) {
+        if (std::isfinite(gs_eps_hat2)) {
+            const double r = gs_eps_hat2 / eps;
+            const double need = std::max(2.0, std::ceil(2.0 * r * r));
+            const double cap = gs_reps_max > 0 ? (double)gs_reps_max : 64.0;
+            if (need <= cap) gs = need * gs_rep_seconds;
+        }
+    } else if (gs_reps_run == 1) {
+        gs = 2.0 * gs_rep_seconds;  // a lower bound: GS needs two colourings at least
+    }
+    if (ns_lo) *ns_lo = lo;
+    if (ns_hi) *ns_hi = hi;
+    if (gs_pred) *gs_pred = gs;
+    // GS entirely below the cone; a one-colouring bound never selects GS
+    return (gs_reps_run >= 2 && gs < lo) ? SGPM_SCHEME_GS : SGPM_SCHEME_NS;
+}
+
+namespace {
+
+// predicted relative error of the first two colourings' values c^(k-1) y_r
+double gs_pilot_error(const GsPrefix& pre, const Plan& p, uint32_t col, double z) {
+    unsigned __int128 scale = 1;
+    for (int i = 0; i < p.k - 1; i++) scale *= col;
+    Big S1(24), S2(24);
+    for (int r = 0; r < pre.n; r++) {
+        const unsigned __int128 x = pre.y[r] * scale;
+        unsigned long long d1[4], d2[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int i = 0; i < 4; i++) d1[i] = (unsigned long long)(uint32_t)(x >> (32 * i));
+        for (int a = 0; a < 4; a++)
+            for (int b = 0; b < 4; b++) {
+                const unsigned long long pr = d1[a] * d1[b];
+                d2[a + b] += pr & 0xFFFFFFFFull;
+                if (a + b + 1 < 8) d2[a + b + 1] += pr >> 32;
+            }
+        big_add_digits(S1, d1, 4);
+        big_add_digits(S2, d2, 8);
+    }
+    return predicted_error(z, (uint64_t)pre.n, S1, S2);
+}
+
+}  // namespace
+
+sgpm_status hybrid_estimate(sgpm_ctx* c, sgpm_graph* g, sgpm_pattern* pat, const sgpm_options& o, sgpm_result* res) {
+    using clk = std::chrono::steady_clock;
+    const auto t0 = clk::now();
+    const Plan& p = pat->plan;
+    NsExtra ex{};
+    if (o.proposal) {
+        sgpm_status st = learn_args_for(c, g, pat, o.proposal, &ex.la);
+        if (st != SGPM_OK) return st;
+    }
+    const uint64_t M = p.oriented ? (uint64_t)g->m : 2ull * (uint64_t)g->m;
+    double ns_lo = INFINITY, ns_hi = INFINITY, gs_pred = INFINITY;
+    int scheme = SGPM_SCHEME_NS;
+    GsPrefix pre;
+    const uint32_t col = gs_colours_for(o);
+    if (col < 1 || col > 256) return fail(c, SGPM_EINVAL, "colours must be in [1, 256]");
+    if (M > 0) {
+        // NS pilot on its own stream of draws
+        constexpr int kSlices = 4;
+        sgpm_options po = o;
+        po.query_tag = 0x80000000u | o.query_tag;
+        po.checksum = 0;
+        po.trace_lo = po.trace_hi = 0;
+        po.trace_buf = nullptr;
+        const uint64_t n_pilot = std::max<uint64_t>(1ull << 16, o.n_min / 4);
+        double sec[kSlices], eh[kSlices];
+        sgpm_status st = ns_pilot(c, g, p, po, ex.la, n_pilot, kSlices, sec, eh);
+        if (st != SGPM_OK) return st;
+        (void)hybrid_choice(kSlices, sec, eh, o.eps, 0, 0.0, 0.0, o.gs_reps_max, &ns_lo, &ns_hi, nullptr);
+        // GS pilot: the GS engine's first colourings, timed end to end
+        const double z = normal_quantile(1.0 - (1.0 - o.confidence) / 2.0);
+        double rep_seconds = 0.0;
+        for (int r = 0; r < 2; r++) {
+            const auto a = clk::now();
+            double dev = 0.0;
+            st = gs_rep(c, g, p, col, o.seed, (uint32_t)r, &pre.y[r], &dev);
+            if (st != SGPM_OK) return st;
+            pre.dev_seconds += dev;
+            pre.n = r + 1;
+            rep_seconds += std::chrono::duration<double>(clk::now() - a).count();
+            if (r == 0 && 2.0 * rep_seconds >= ns_lo) break;  // GS cannot lie below the cone
+        }
+        rep_seconds /= pre.n;
+        const double e2 = pre.n >= 2 ? gs_pilot_error(pre, p, col, z) : INFINITY;
+        scheme = hybrid_choice(kSlices, sec, eh, o.eps, pre.n, rep_seconds, e2, o.gs_reps_max, &ns_lo, &ns_hi,
+                               &gs_pred);
+    }
+    const double pilot = std::chrono::duration<double>(clk::now() - t0).count();
+    sgpm_status st;
+    if (scheme == SGPM_SCHEME_GS) {
+        st = gs_estimate(c, g, p, o, res, &pre);
+    } else {
+        sgpm_options no = o;
+        no.mode = SGPM_MODE_STRICT_NS;
+        st = ns_estimate_solo(c, g, p, no, res, 0, o.proposal ? &ex : nullptr);
+    }
+    res->pred_ns_lo = ns_lo;
+    res->pred_ns_hi = ns_hi;
+    res->pred_gs = gs_pred;
+    res->seconds_pilot = pilot;
+    res->seconds_total += pilot;
+    return st;
+}
+
+}  // namespace sgpm

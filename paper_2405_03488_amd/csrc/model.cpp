@@ -23,9 +23,6 @@
 
 namespace sgpm {
 
-sgpm_status ns_estimate_solo(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_options& o, sgpm_result* res,
-                             int count_bytes, const NsExtra* ex);
-
 namespace {
 
 constexpr size_t TABLE = 8 * 32 * 32 * 32;

@@ -208,6 +208,29 @@ struct sgpm_model {
 
 namespace sgpm {
 
+// engines shared by the estimate entry points
+struct GsPrefix {              // colourings 0..n-1 already counted (hybrid pilots)
+    int n = 0;
+    unsigned __int128 y[2] = {0, 0};
+    double dev_seconds = 0.0;
+};
+sgpm_status gs_rep(sgpm_ctx* c, sgpm_graph* g, const Plan& p, uint32_t colours, uint64_t seed, uint32_t rep,
+                   unsigned __int128* y, double* dev_seconds);
+uint32_t gs_colours_for(const sgpm_options& o);
+sgpm_status gs_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_options& o, sgpm_result* res,
+                        const GsPrefix* pre = nullptr);
+sgpm_status ns_estimate_solo(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_options& o, sgpm_result* res,
+                             int count_bytes, const NsExtra* ex = nullptr);
+// NS pilot: `slices` equal consecutive id ranges of [0, n) under options o
+// (the caller sets the tag); per slice the kernel seconds and predicted error
+sgpm_status ns_pilot(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_options& o, const LearnArgs& la,
+                     uint64_t n, int slices, double* seconds, double* eps_hat);
+sgpm_status learn_args_for(sgpm_ctx* c, sgpm_graph* g, sgpm_pattern* p, sgpm_model* m, LearnArgs* la);
+sgpm_status hybrid_estimate(sgpm_ctx* c, sgpm_graph* g, sgpm_pattern* p, const sgpm_options& o, sgpm_result* res);
+int hybrid_choice(int slices, const double* slice_seconds, const double* slice_eps_hat, double eps, int gs_reps_run,
+                  double gs_rep_seconds, double gs_eps_hat2, int gs_reps_max, double* ns_lo, double* ns_hi,
+                  double* gs_pred);
+
 inline sgpm_status fail(sgpm_ctx* c, sgpm_status s, const std::string& msg) {
     if (c) c->err = msg;
     return s;

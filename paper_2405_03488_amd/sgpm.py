@@ -54,7 +54,9 @@ class Result(C.Structure):
                 ("colours", C.c_int32), ("converged", C.c_int32), ("windows", C.c_int32),
                 ("lanes_per_sample", C.c_int32), ("launches", C.c_int32), ("checksum", C.c_uint64),
                 ("bytes", C.c_uint64), ("seconds_sampling", C.c_double), ("seconds_total", C.c_double),
-                ("seconds_kernel", C.c_double), ("tile", C.c_int32), ("weight_shift", C.c_int32)]
+                ("seconds_kernel", C.c_double), ("tile", C.c_int32), ("weight_shift", C.c_int32),
+                ("reserved0", C.c_int32), ("pred_ns_lo", C.c_double), ("pred_ns_hi", C.c_double),
+                ("pred_gs", C.c_double), ("seconds_pilot", C.c_double)]
 
     @property
     def S1(self) -> int:
@@ -122,6 +124,8 @@ def lib():
             "sgpm_host_normal_quantile": ([C.c_double], C.c_double),
             "sgpm_host_predicted_error": ([C.c_double, C.c_uint64, P, C.c_int, P, C.c_int], C.c_double),
             "sgpm_host_next_window": ([C.c_uint64, C.POINTER(Options)], C.c_uint64),
+            "sgpm_host_hybrid_choice": ([C.c_int, P, P, C.c_double, C.c_int, C.c_double, C.c_double, C.c_int, P, P,
+                                         P], C.c_int),
         }
         for name, (args, res) in sig.items():
             if hasattr(L, name):
@@ -138,7 +142,7 @@ EXPORTED = ["sgpm_create", "sgpm_destroy", "sgpm_last_error", "sgpm_device_count
             "sgpm_estimate_batch", "sgpm_exact_count", "sgpm_gs_sparsify", "sgpm_model_train", "sgpm_model_free",
             "sgpm_model_from_tables", "sgpm_model_table", "sgpm_model_info", "sgpm_mlp_forward", "sgpm_mlp_grad",
             "sgpm_probe_copy", "sgpm_probe_gather", "sgpm_host_canonicalise", "sgpm_host_plan", "sgpm_host_normal_quantile", "sgpm_host_predicted_error",
-            "sgpm_host_next_window"]
+            "sgpm_host_next_window", "sgpm_host_hybrid_choice"]
 
 
 class SgpmError(RuntimeError):
@@ -317,6 +321,19 @@ def sgpm_host_predicted_error(z, n, S1: int, S2: int):
 
 def sgpm_host_next_window(n_t, opts: Options):
     return int(lib().sgpm_host_next_window(n_t, C.byref(opts)))
+
+
+def sgpm_host_hybrid_choice(slice_seconds, slice_eps_hat, eps, gs_reps_run, gs_rep_seconds, gs_eps_hat2,
+                            gs_reps_max=64):
+    """(scheme, ns_lo, ns_hi, gs_pred) from pilot figures; see include/sgpm.h."""
+    sec = np.ascontiguousarray(slice_seconds, dtype=np.float64)
+    eh = np.ascontiguousarray(slice_eps_hat, dtype=np.float64)
+    lo, hi, gs = C.c_double(), C.c_double(), C.c_double()
+    rc = lib().sgpm_host_hybrid_choice(len(sec), sec.ctypes.data, eh.ctypes.data, eps, gs_reps_run, gs_rep_seconds,
+                                       gs_eps_hat2, gs_reps_max, C.byref(lo), C.byref(hi), C.byref(gs))
+    if rc < 0:
+        raise SgpmError(rc, "invalid hybrid pilot figures")
+    return rc, lo.value, hi.value, gs.value
 
 
 def sgpm_probe_copy(ctx, nbytes, iters=10) -> float:

@@ -1,0 +1,104 @@
+"""Loose mode (hybrid NS/GS selection, Sec. 5.1) on the GPU.
+
+Whatever engine the pilots select, the hybrid result equals that engine's
+own result with the same options bit for bit (the NS pilot draws from its own
+Philox stream; the GS pilot colourings are the GS run's first two).  Two
+clear-cut cases check the choice itself: a common pattern on a power-law
+graph (NS), and a handful of planted 5-cliques in a large sparse graph, where
+NS pilots see almost no hits while one exact count is cheap (GS)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_2405_03488_amd import sgpm
+    return sgpm
+
+
+@pytest.fixture(scope="module")
+def ctx(S):
+    c = S.sgpm_create(0)
+    yield c
+    S.sgpm_destroy(c)
+
+
+def same(a, b):
+    assert a.scheme == b.scheme and a.n_samples == b.n_samples
+    assert a.S1 == b.S1 and a.S2 == b.S2 and a.n_hits == b.n_hits
+    assert a.checksum == b.checksum and a.converged == b.converged and a.windows == b.windows
+    assert a.estimate == b.estimate and a.eps_hat == b.eps_hat
+
+
+def run_pair(S, ctx, g, p, **kw):
+    oh = S.sgpm_options_default(mode=S.MODE_HYBRID, **kw)
+    rh, _ = S.sgpm_estimate(ctx, g, p, oh)
+    mode = S.MODE_GS if rh.scheme == S.SCHEME_GS else S.MODE_STRICT_NS
+    ro, _ = S.sgpm_estimate(ctx, g, p, S.sgpm_options_default(mode=mode, **kw))
+    same(rh, ro)
+    print("hybrid:", "GS" if rh.scheme == S.SCHEME_GS else "NS", "ns cone", rh.pred_ns_lo, rh.pred_ns_hi, "gs",
+          rh.pred_gs, "pilot s", rh.seconds_pilot, flush=True)
+    assert rh.pred_ns_lo <= rh.pred_ns_hi and rh.seconds_pilot > 0
+    return rh
+
+
+def test_hybrid_picks_ns_for_a_common_pattern(S, synth, ctx):
+    n = 20000
+    off, nbr = synth.pairs_to_csr(n, synth.chung_lu_pairs(n, 16, 2.1, 4))
+    g = S.sgpm_graph_from_csr(ctx, n, off, nbr)
+    p = S.sgpm_pattern_create(ctx, *synth.pattern("triangle"))
+    rh = run_pair(S, ctx, g, p, eps=0.02, seed=5, checksum=1, colours=2)
+    assert rh.scheme == S.SCHEME_NS and np.isfinite(rh.pred_ns_lo)
+    S.sgpm_pattern_free(p)
+    S.sgpm_graph_free(g)
+
+
+def planted(synth, n, m, cliques, k, seed):
+    rng = np.random.default_rng(seed)
+    pairs = [synth.er_pairs(n, m, seed)]
+    for _ in range(cliques):
+        vs = rng.choice(n, size=k, replace=False)
+        pairs.append(np.array([(a, b) for i, a in enumerate(vs) for b in vs[i + 1:]], dtype=np.int32))
+    return np.concatenate(pairs).astype(np.int32)
+
+
+def test_hybrid_picks_gs_for_rare_matches(S, O, synth, ctx):
+    n = 200000
+    pairs = planted(synth, n, 200000, 8, 5, 11)
+    off, nbr = synth.pairs_to_csr(n, pairs)
+    g = S.sgpm_graph_from_csr(ctx, n, off, nbr)
+    og = O.OGraph.from_raw_csr(n, off, nbr)
+    k, e = synth.pattern("5-clique")
+    p = S.sgpm_pattern_create(ctx, k, e)
+    exact = O.plan_count(og, O.compile_plan(k, e))
+    assert exact >= 8
+    # one colour: GS is the exact count, so two identical colourings converge
+    rh = run_pair(S, ctx, g, p, eps=0.02, seed=9, checksum=1, colours=1)
+    assert rh.scheme == S.SCHEME_GS and rh.converged == 1
+    assert rh.estimate == exact and rh.n_samples == 2
+    S.sgpm_pattern_free(p)
+    S.sgpm_graph_free(g)
+
+
+@pytest.mark.parametrize("name,colours", [("4-cycle", 2), ("diamond", 4), ("4-clique", 8)])
+def test_hybrid_equals_selected_engine(S, synth, ctx, name, colours):
+    n = 3000
+    off, nbr = synth.pairs_to_csr(n, synth.chung_lu_pairs(n, 12, 2.1, 8))
+    g = S.sgpm_graph_from_csr(ctx, n, off, nbr)
+    p = S.sgpm_pattern_create(ctx, *synth.pattern(name))
+    run_pair(S, ctx, g, p, eps=0.05, seed=17, checksum=1, colours=colours, gs_reps_max=200, n_min=1 << 16,
+             w_min=1 << 15, quantum=1 << 12)
+    S.sgpm_pattern_free(p)
+    S.sgpm_graph_free(g)
+
+
+def test_hybrid_on_an_edgeless_graph(S, synth, ctx):
+    off, nbr = synth.pairs_to_csr(9, np.zeros((0, 2), dtype=np.int32))
+    g = S.sgpm_graph_from_csr(ctx, 9, off, nbr)
+    p = S.sgpm_pattern_create(ctx, *synth.pattern("triangle"))
+    r, _ = S.sgpm_estimate(ctx, g, p, S.sgpm_options_default(mode=S.MODE_HYBRID))
+    assert r.scheme == S.SCHEME_NS and r.estimate == 0.0 and r.converged == 1
+    S.sgpm_pattern_free(p)
+    S.sgpm_graph_free(g)
