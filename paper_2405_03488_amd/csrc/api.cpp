@@ -17,7 +17,7 @@ namespace sgpm {
 
 namespace {
 
-constexpr int SLOT_WORDS = 32;  // [0] ticket, [1..20] sums
+constexpr int SLOT_WORDS = 32;  // [1..20] sums of one launch
 
 
 sgpm_status ensure_scratch(sgpm_ctx* c, size_t blocks, size_t slots) {
@@ -31,12 +31,15 @@ sgpm_status ensure_scratch(sgpm_ctx* c, size_t blocks, size_t slots) {
     if (slots > c->nslots) {
         if (c->d_slots) (void)hipFree(c->d_slots);
         if (c->h_slots) (void)hipHostFree(c->h_slots);
+        if (c->d_tickets) (void)hipFree(c->d_tickets);
         c->d_slots = nullptr;
         c->h_slots = nullptr;
+        c->d_tickets = nullptr;
         c->nslots = 0;
         size_t want = std::max<size_t>(slots, 1024);
         HIP_TRY(c, hipMalloc(&c->d_slots, want * SLOT_WORDS * sizeof(unsigned long long)));
         HIP_TRY(c, hipHostMalloc(&c->h_slots, want * SLOT_WORDS * sizeof(unsigned long long), hipHostMallocDefault));
+        HIP_TRY(c, hipMalloc(&c->d_tickets, want * NTK * TK_STRIDE * sizeof(unsigned long long)));
         c->nslots = want;
     }
     return SGPM_OK;
@@ -88,6 +91,7 @@ sgpm_status sgpm_destroy(sgpm_ctx_t c) {
     if (c->d_partials) (void)hipFree(c->d_partials);
     if (c->d_slots) (void)hipFree(c->d_slots);
     if (c->h_slots) (void)hipHostFree(c->h_slots);
+    if (c->d_tickets) (void)hipFree(c->d_tickets);
     for (hipEvent_t e : c->kev) (void)hipEventDestroy(e);
     if (c->batch_exec) (void)hipGraphExecDestroy(c->batch_exec);
     if (c->batch_graph) (void)hipGraphDestroy(c->batch_graph);
@@ -262,17 +266,23 @@ void absorb(NsState& s, const unsigned long long* sums) {
 }
 
 // Launch [s0, s1) with the given lane count into slot `slot`; enqueue only.
+// `span` is the length of the whole window the range belongs to: ticket sizes
+// follow it, so a window split into pieces (autotuning, pilots) is launched
+// as the whole window would be.
 sgpm_status enqueue_range(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_options& o, uint64_t s0, uint64_t s1,
-                          int lanes, size_t slot, const TraceArgs& tr, int count_bytes, const LearnArgs& la) {
+                          int lanes, size_t slot, const TraceArgs& tr, int count_bytes, const LearnArgs& la,
+                          uint64_t span = 0) {
     LaunchCfg cfg;
     cfg.lanes = lanes;
     cfg.blocks = blocks_for(c, lanes);
-    // Tickets of about 1/16 of a wave's share: few enough that the single
-    // ticket counter is not the bottleneck, many enough to balance skewed
+    // Tickets of about 1/16 of a wave's share of the window: few enough that
+    // the single ticket counter (a device-scope atomic, about 8e7 per second
+    // on one address) is not the bottleneck, many enough to balance skewed
     // per-sample work across waves.
     {
         const uint64_t waves = (uint64_t)cfg.blocks * 4, groups_per_wave = (uint64_t)(64 / lanes);
-        const uint64_t per_group = (s1 - s0) / (waves * groups_per_wave * 16);
+        const uint64_t len = std::max<uint64_t>(span, s1 - s0);
+        const uint64_t per_group = len / (waves * groups_per_wave * 16);
         cfg.spl = (int)std::min<uint64_t>(256, std::max<uint64_t>(1, per_group));
     }
     bool dynamic = true;
@@ -286,14 +296,16 @@ sgpm_status enqueue_range(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_
     sgpm_status st = ensure_scratch(c, (size_t)largest_grid(c), slot + 1);
     if (st != SGPM_OK) return st;
     unsigned long long* sl = c->d_slots + slot * SLOT_WORDS;
+    unsigned long long* tk = c->d_tickets + slot * NTK * TK_STRIDE;
     HIP_TRY(c, launch_fill_u64(sl, SLOT_WORDS, 0ull, c->st));
+    if (dynamic) HIP_TRY(c, launch_fill_u64(tk, (uint64_t)NTK * TK_STRIDE, 0ull, c->st));
     while (c->kev.size() < 2 * (slot + 1)) {
         hipEvent_t ev;
         HIP_TRY(c, hipEventCreate(&ev));
         c->kev.push_back(ev);
     }
     HIP_TRY(c, hipEventRecord(c->kev[2 * slot], c->st));
-    HIP_TRY(c, launch_ns_window(g->view(), p, o.seed, o.query_tag, s0, s1, cfg, dynamic ? sl : nullptr,
+    HIP_TRY(c, launch_ns_window(g->view(), p, o.seed, o.query_tag, s0, s1, cfg, dynamic ? tk : nullptr,
                                 c->d_partials, o.checksum, count_bytes, tr, la, c->st));
     HIP_TRY(c, hipEventRecord(c->kev[2 * slot + 1], c->st));
     HIP_TRY(c, launch_reduce_partials(c->d_partials, cfg.blocks, sl + 1, c->st));
@@ -383,7 +395,7 @@ sgpm_status ns_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_op
                 if (b <= a) continue;
                 const int ci = i % 4;
                 const size_t slot = slots++;
-                status = enqueue_range(c, g, p, o, a, b, cand[ci], slot, tr, count_bytes, la);
+                status = enqueue_range(c, g, p, o, a, b, cand[ci], slot, tr, count_bytes, la, len);
                 if (status != SGPM_OK) return status;
                 // sampling-kernel time alone (the events enqueue_range records around it)
                 HIP_TRY(c, hipEventSynchronize(c->kev[2 * slot + 1]));
@@ -476,7 +488,7 @@ sgpm_status ns_pilot(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_optio
     const TraceArgs tr{nullptr, 0, 0, nullptr};
     for (int i = 0; i < slices; i++) {
         const uint64_t a = n * (uint64_t)i / (uint64_t)slices, b = n * (uint64_t)(i + 1) / (uint64_t)slices;
-        sgpm_status st = enqueue_range(c, g, p, o, a, b, lanes, (size_t)i, tr, 0, la);
+        sgpm_status st = enqueue_range(c, g, p, o, a, b, lanes, (size_t)i, tr, 0, la, n);
         if (st != SGPM_OK) return st;
     }
     HIP_TRY(c, hipStreamSynchronize(c->st));

@@ -431,6 +431,29 @@ __device__ __forceinline__ uint32_t ns_sample(const DGraph& g, const Plan& p, ui
     return 0xFFu;
 }
 
+// Next ticket of a wave from the NTK counters at tk (wave-uniform result).
+// Blocks are dispatched round-robin over the 8 XCDs, so starting at counter
+// blockIdx % NTK keeps the counters' atomics apart; a wave whose counter has
+// run past `ntickets` moves on to the next one and stops after NTK dry
+// counters, so every wave ends after at most NTK failed fetches.
+__device__ __forceinline__ bool next_ticket(unsigned long long* __restrict__ tk, uint64_t ntickets, int& cur,
+                                            int& left, uint64_t& t) {
+    while (left > 0) {
+        unsigned long long got = 0;
+        if ((threadIdx.x & 63) == 0) got = atomicAdd(tk + (size_t)cur * TK_STRIDE, 1ull);
+        got = ((unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(__shfl(got, 0) >> 32)) << 32) |
+              (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)__shfl(got, 0));
+        const uint64_t tt = got * (uint64_t)NTK + (uint64_t)cur;
+        if (tt < ntickets) {
+            t = tt;
+            return true;
+        }
+        cur = cur + 1 == NTK ? 0 : cur + 1;
+        --left;
+    }
+    return false;
+}
+
 __device__ __forceinline__ uint64_t wave_sum(uint64_t x) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);

@@ -16,7 +16,7 @@
 // and counter = (s lo, s hi, d, tag), read as w1*2^32 + w0.
 //
 // Work distribution: a wave takes tickets of (64 / G) * spl consecutive sample
-// ids from an atomic counter; G lanes cooperate on one sample (G = 1: one lane
+// ids from NTK atomic counters (XCD-local first, then the others); G lanes cooperate on one sample (G = 1: one lane
 // per sample with cursor-advancing binary searches; G > 1: the group scans the
 // driver row G entries at a time, tests membership lane-parallel and counts
 // with ballot + popcount).  Any G gives the same samples.
@@ -49,16 +49,17 @@ __global__ __launch_bounds__(256) void ns_window_kernel(DGraph g, Plan p, uint64
     // ticket == nullptr: static interleaving, wave w takes tickets w, w + W, ...
     const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x >> 6);
     uint64_t tstat = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const uint64_t ntickets = (s1 - s0 + per_wave - 1) / per_wave;
+    int tk_cur = (int)(blockIdx.x % NTK), tk_left = NTK;
     for (;;) {
-        unsigned long long t = 0;
+        uint64_t t = 0;
         if (ticket) {
-            if (lane == 0) t = atomicAdd(ticket, 1ull);
-            t = __shfl(t, 0);
+            if (!next_ticket(ticket, ntickets, tk_cur, tk_left, t)) break;
         } else {
             t = tstat;
             tstat += nwaves;
         }
-        const uint64_t base = s0 + (uint64_t)t * per_wave;
+        const uint64_t base = s0 + t * per_wave;
         if (base >= s1) break;
         for (int q = 0; q < spl; ++q) {
             const uint64_t s = base + (uint64_t)q * (uint64_t)(64 / G) + (uint64_t)(lane / G);
@@ -170,12 +171,12 @@ __global__ __launch_bounds__(256, 8) void ns_wave_kernel(DGraph g, Plan p, uint6
     uint64_t ovf = 0;
     const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x >> 6);
     uint64_t tstat = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const uint64_t ntickets = (s1 - s0 + (uint64_t)spl - 1) / (uint64_t)spl;
+    int tk_cur = (int)(blockIdx.x % NTK), tk_left = NTK;
     for (;;) {
-        uint64_t tt;
+        uint64_t tt = 0;
         if (ticket) {
-            unsigned long long t = 0;
-            if (lane == 0) t = atomicAdd(ticket, 1ull);
-            tt = ((uint64_t)(uint32_t)rfl((int32_t)(__shfl(t, 0) >> 32)) << 32) | (uint32_t)rfl((int32_t)__shfl(t, 0));
+            if (!next_ticket(ticket, ntickets, tk_cur, tk_left, tt)) break;
         } else {
             tt = tstat;
             tstat += nwaves;

@@ -53,6 +53,11 @@ struct LearnArgs {
     const int32_t* thr;     // [32] device array, thr[31] = 0
 };
 
+// Dynamic work distribution of the sampling kernels: NTK ticket counters,
+// TK_STRIDE words apart, counter x handing out tickets x, x + NTK, ...
+constexpr int NTK = 8;
+constexpr int TK_STRIDE = 32;
+
 struct LaunchCfg {
     int lanes;     // lanes cooperating on one sample: 1, 4, 16, 64
     int spl;       // samples per group per ticket
@@ -163,6 +168,7 @@ struct sgpm_ctx {
     size_t partial_blocks = 0;
     unsigned long long* d_slots = nullptr;   // per launch: ticket + 20 sums (+ pad) = 32 words
     unsigned long long* h_slots = nullptr;   // pinned mirror of the sums
+    unsigned long long* d_tickets = nullptr; // per launch: NTK ticket counters, TK_STRIDE words apart
     size_t nslots = 0;
     std::vector<hipEvent_t> kev;             // start/stop events around each sampling kernel
     // batch: autotuned lanes per (graph, plan), device/pinned tables, captured graph
