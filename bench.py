@@ -37,6 +37,34 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def kernel_source_hash() -> str:
+    """Hash of the sampling kernel's sources; counter figures are only reported
+    while it matches the hash they were taken with."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("ns_kernels.hip", "ns_device.h", "sgpm_internal.h"):
+        with open(os.path.join(ROOT, "paper_2405_03488_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(runs, launches):
+    """HBM bytes per sampling launch from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE per sample, scaled by the copy-kernel
+    calibration), times the timed runs' samples per launch; None when the
+    summary is missing or was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "ns_wave_rmat20_hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    per_sample = t["hbm_bytes_per_sample"]
+    total = sum(per_sample[x["q"]] * x["r"].n_samples for x in runs)
+    return total / max(1, launches)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,11 +124,13 @@ def main():
 
     # warmup: also picks the lane count per query (autotuner on the first window)
     lanes = {q: 0 for q in queries}
+    warm_launches = 0
     for w in range(max(1, args.warmup)):
         for q in queries:
             o, _ = opts_for(q, 900 + w, lanes[q], False)
             r, _ = S.sgpm_estimate(ctx, g, pats[q], o)
             lanes[q] = r.lanes_per_sample
+            warm_launches += r.launches
             log(f"warmup {q}: n={r.n_samples} est={r.estimate:.6g} eps_hat={r.eps_hat:.4g} lanes={r.lanes_per_sample}"
                 f" t={r.seconds_total:.4f}s")
 
@@ -194,11 +224,13 @@ def main():
         "time_to_eps_s": {q: per_q[q]["time_to_eps_s"] for q in queries},
         "queries": per_q,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(runs, launches),
                      "kernel": sorted({"ns_wave_kernel" if lanes[q] == 64 else f"ns_window_kernel<{lanes[q]}>"
                                        for q in queries}),
                      "launches": launches,
                      "avg_launch_ms": kernel_s / max(1, launches) * 1e3,
+                     "sampling_launches_before_timed": warm_launches,
                      "alg_bytes_per_launch": alg_bytes / max(1, launches),
                      "measured": probes},
         "cpu_baseline": cpu,

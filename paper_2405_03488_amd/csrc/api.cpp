@@ -284,6 +284,9 @@ sgpm_status enqueue_range(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_
         const uint64_t len = std::max<uint64_t>(span, s1 - s0);
         const uint64_t per_group = len / (waves * groups_per_wave * 16);
         cfg.spl = (int)std::min<uint64_t>(256, std::max<uint64_t>(1, per_group));
+        // one sample per wave: whole groups of 16 samples (the kernel's draw and
+        // record groups)
+        if (lanes == 64) cfg.spl = (cfg.spl + 15) / 16 * 16;
     }
     bool dynamic = true;
     if (const char* e = std::getenv("SGPM_SPL")) cfg.spl = std::max(1, std::atoi(e));

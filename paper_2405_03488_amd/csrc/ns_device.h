@@ -87,6 +87,9 @@ constexpr int32_t BIG = 0x7FFFFFFF;
 // readfirstlane tells the compiler so, which keeps the walk state in SGPRs
 // and turns its branches into scalar branches.
 __device__ __forceinline__ int32_t rfl(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ int64_t rfl64(int64_t x) {
+    return (int64_t)(((uint64_t)(uint32_t)rfl((int32_t)((uint64_t)x >> 32)) << 32) | (uint32_t)rfl((int32_t)x));
+}
 template <int G>
 __device__ __forceinline__ int32_t uni(int32_t x) {
     if constexpr (G == 64) return rfl(x);
@@ -128,8 +131,8 @@ __device__ __forceinline__ bool member(const int32_t* __restrict__ R, int32_t rl
         return q < rl && R[q] == x;
     } else {
         bool found = false, pending = act;
+        int32_t b = (c + gl < rl) ? R[c + gl] : BIG;
         for (;;) {
-            const int32_t b = (c + gl < rl) ? R[c + gl] : BIG;
             const int32_t bmax = uni<G>(__shfl(b, gbase + G - 1));
             int pos = 0;
 #pragma unroll
@@ -146,6 +149,7 @@ __device__ __forceinline__ bool member(const int32_t* __restrict__ R, int32_t rl
                 break;
             }
             c += G;
+            b = (c + gl < rl) ? R[c + gl] : BIG;
         }
         return found;
     }
@@ -191,12 +195,30 @@ __device__ __forceinline__ bool fixed52(double a, uint64_t& lo, uint64_t& hi) {
     return true;
 }
 
+// Draws computed ahead, one per lane (the wave kernel evaluates all draws of a
+// group of samples at once).  Slot t of the current sample sits in lane
+// base + t: slots 0..k-2 hold draws 0, 2, .., k-1, slots k-1.. draws 18, 19, ..
+struct Draws {
+    uint32_t lo, hi;  // this lane's draw
+    int base;         // lane of slot 0 of the current sample
+    int k1;           // k - 1
+};
+
+// Draw d of sample s: read from the lanes holding it, or computed here.
+__device__ __forceinline__ uint64_t draw_at(const Draws* dr, uint64_t seed, uint64_t s, uint32_t d, uint32_t tag) {
+    if (!dr) return philox_r64(seed, s, d, tag);
+    const int slot = d == 0 ? 0 : d < 16 ? (int)d - 1 : dr->k1 + (int)d - 18;
+    const int l = dr->base + slot;
+    return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)dr->hi, l) << 32) |
+           (uint32_t)__builtin_amdgcn_readlane((int)dr->lo, l);
+}
+
 template <int G, int KMAX = 8>
 __device__ __forceinline__ uint32_t ns_sample(const DGraph& g, const Plan& p, uint64_t seed, uint32_t tag, uint64_t s,
                                              int32_t (&v)[8], uint64_t& alo, uint64_t& ahi, uint64_t& ovf,
                                              uint64_t& bytes, bool count_bytes, int32_t* list,
                                              const LearnArgs* la = nullptr, uint32_t* hist = nullptr,
-                                             uint32_t* sz = nullptr) {
+                                             uint32_t* sz = nullptr, const Draws* dr = nullptr) {
     constexpr int CAP = LDS_WORDS / (256 / G);
     const int lane = (int)(threadIdx.x & 63);
     const int gl = lane & (G - 1);
@@ -207,15 +229,6 @@ __device__ __forceinline__ uint32_t ns_sample(const DGraph& g, const Plan& p, ui
 #pragma unroll
     for (int i = 0; i < 8; ++i) v[i] = -1;
     const uint64_t M = p.oriented ? (uint64_t)g.m : 2ull * (uint64_t)g.m;
-    const uint64_t e = __umul64hi(M, philox_r64(seed, s, 0, tag));
-    if (p.oriented) {
-        const int2 pr = g.epair[e];
-        v[0] = pr.x;
-        v[1] = pr.y;
-    } else {
-        v[0] = g.arow[e];
-        v[1] = g.nbr[e];
-    }
     const int32_t* rp[8];
     int32_t rl[8];
 #pragma unroll
@@ -224,6 +237,15 @@ __device__ __forceinline__ uint32_t ns_sample(const DGraph& g, const Plan& p, ui
         rl[i] = 0;
     }
     {
+        const uint64_t e = __umul64hi(M, draw_at(dr, seed, s, 0, tag));
+        if (p.oriented) {
+            const int2 pr = g.epair[e];
+            v[0] = pr.x;
+            v[1] = pr.y;
+        } else {
+            v[0] = g.arow[e];
+            v[1] = g.nbr[e];
+        }
         const int64_t b0 = g.off[v[0]], e0 = g.off[v[0] + 1];
         const int64_t b1 = g.off[v[1]], e1 = g.off[v[1] + 1];
         rp[0] = g.nbr + b0;
@@ -298,6 +320,7 @@ __device__ __forceinline__ uint32_t ns_sample(const DGraph& g, const Plan& p, ui
         int32_t cur[8];
         // candidates of one chunk of G source entries; advances the cursors
         auto eval_chunk = [&](int32_t base, int32_t& x, uint64_t& inm) -> bool {
+            const uint32_t need = need_conn | need_disc;
             const int32_t pos = base + gl;
             x = pos < slen ? src[pos] : BIG;
             const bool act = x < hi;
@@ -310,13 +333,9 @@ __device__ __forceinline__ uint32_t ns_sample(const DGraph& g, const Plan& p, ui
             const int32_t xmax = uni<G>(__shfl(x, gbase + (int)__popcll(inm) - 1));
 #pragma unroll
             for (int i = 0; i < j; ++i) {
-                if (need_conn >> i & 1) {
+                if (need >> i & 1) {
                     const bool f = member<G>(rp[i], rl[i], cur[i], x, act, xmax, gbase, gl, gmask);
-                    ok = ok && f;
-                }
-                if (need_disc >> i & 1) {
-                    const bool f = member<G>(rp[i], rl[i], cur[i], x, act, xmax, gbase, gl, gmask);
-                    ok = ok && !f;
+                    ok = ok && ((need_conn >> i & 1) ? f : !f);
                 }
             }
             return ok;
@@ -365,17 +384,17 @@ __device__ __forceinline__ uint32_t ns_sample(const DGraph& g, const Plan& p, ui
                 const uint64_t cum = wave_incl_scan(nb * w);
                 const uint64_t cumn = wave_incl_scan(nb);
                 const uint64_t sigma = __shfl(cum, 63);
-                const uint64_t t = __umul64hi(sigma, philox_r64(seed, s, (uint32_t)j, tag));
+                const uint64_t t = __umul64hi(sigma, draw_at(dr, seed, s, (uint32_t)j, tag));
                 const int bsel = __ffsll((unsigned long long)__ballot(lane < 32 && cum > t)) - 1;
                 const uint64_t nbs = __shfl(nb, bsel), wbs = __shfl(w, bsel), upto = __shfl(cumn, bsel);
-                const uint64_t inb = __umul64hi(nbs, philox_r64(seed, s, 16u + (uint32_t)j, tag));
+                const uint64_t inb = __umul64hi(nbs, draw_at(dr, seed, s, 16u + (uint32_t)j, tag));
                 idx = (uint32_t)((uint64_t)cnt - upto + inb);
                 af = __dmul_rn(af, __ddiv_rn((double)sigma, (double)wbs));
             } else {
-                idx = (uint32_t)__umul64hi((uint64_t)cnt, philox_r64(seed, s, (uint32_t)j, tag));
+                idx = (uint32_t)__umul64hi((uint64_t)cnt, draw_at(dr, seed, s, (uint32_t)j, tag));
             }
         } else {
-            idx = (uint32_t)__umul64hi((uint64_t)cnt, philox_r64(seed, s, (uint32_t)j, tag));
+            idx = (uint32_t)__umul64hi((uint64_t)cnt, draw_at(dr, seed, s, (uint32_t)j, tag));
         }
         int32_t pick = -1;
         if (cnt <= (uint32_t)CAP) {

@@ -150,23 +150,54 @@ __global__ __launch_bounds__(256) void ns_window_kernel(DGraph g, Plan p, uint64
     }
 }
 
-// One sample per wave.  Exact sums live spread over the lanes: lanes 0-3 add
-// the 32-bit digits of X, lanes 8-15 the digit columns of X^2 (low and high
-// halves of the digit products), lane 20 hits, 21 the checksum, 22 bytes,
-// 23 the overflow flag.  Digit columns are normalised once per block.
+// One sample per wave, samples handled in groups of up to GMAX per wave:
+//  * prologue: the group's Philox draws are evaluated at once, one (sample,
+//    draw) pair per lane; a sample reads its draws back with readlane;
+//  * each sample leaves a record (walk, status, weight, bytes) in LDS;
+//  * epilogue: lane q hashes record q and forms the 32-bit digits of its
+//    weight and the digit columns of the weight's square; sums over the group
+//    are added to accumulators spread over the lanes (0-3 the digits of S1,
+//    8-15 the columns of S2, 20 hits, 21 checksum, 22 bytes, 23 the overflow
+//    flag), normalised once per block.
 // MODE 0: uniform proposal; 1: learned proposal; 2: uniform with per-step set
 // sizes recorded for traced samples (training pilots)
+#ifndef SGPM_WAVE_BLOCKS_PER_CU
+#define SGPM_WAVE_BLOCKS_PER_CU 7
+#endif
+constexpr int GMAX = 16;  // samples per group (records live in lanes 0..15)
+constexpr int REC = 16;   // words per sample record
+
+// draw index held in slot t of a sample's draws (slots 0..k-2: draws 0, 2, ..,
+// k-1; learned proposal: then draws 18, 19, ..)
+template <int K>
+__device__ __forceinline__ uint32_t draw_of_slot(int t) {
+    return t == 0 ? 0u : t <= K - 2 ? (uint32_t)(t + 1) : (uint32_t)(18 + (t - (K - 1)));
+}
+
+// sum over lanes 0..15 (the other lanes hold zeros), returned wave-uniform
+__device__ __forceinline__ uint64_t row_sum16(uint64_t x) {
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) x += __shfl_xor(x, o);
+    return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(x >> 32), 0) << 32) |
+           (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, 0);
+}
+
 template <int MODE, int K>
-__global__ __launch_bounds__(256, 8) void ns_wave_kernel(DGraph g, Plan p, uint64_t seed, uint32_t tag, uint64_t s0,
+__global__ __launch_bounds__(256, SGPM_WAVE_BLOCKS_PER_CU) void ns_wave_kernel(DGraph g, Plan p, uint64_t seed, uint32_t tag, uint64_t s0,
                                                       uint64_t s1, int spl, unsigned long long* __restrict__ ticket,
                                                       unsigned long long* __restrict__ partials, int checksum,
                                                       int count_bytes, TraceArgs tr, LearnArgs la) {
     constexpr int G = 64;
+    constexpr int D = (K - 1) + (MODE == 1 ? K - 2 : 0);  // draws per sample
+    constexpr int GS = (64 / D) < GMAX ? (64 / D) : GMAX;
     const int lane = (int)(threadIdx.x & 63);
+    const int wid = (int)(threadIdx.x >> 6);
     __shared__ int32_t s_list[LDS_WORDS];
     __shared__ uint32_t s_hist[4][32];
-    uint32_t* hist = s_hist[threadIdx.x >> 6];
-    int32_t* list = s_list + (threadIdx.x / G) * (LDS_WORDS / (256 / G));
+    __shared__ uint32_t s_rec[4][GMAX * REC];
+    uint32_t* hist = s_hist[wid];
+    uint32_t* rec = s_rec[wid];
+    int32_t* list = s_list + wid * (LDS_WORDS / 4);
     uint64_t acc = 0;
     uint64_t ovf = 0;
     const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x >> 6);
@@ -183,76 +214,125 @@ __global__ __launch_bounds__(256, 8) void ns_wave_kernel(DGraph g, Plan p, uint6
         }
         const uint64_t base = s0 + tt * (uint64_t)spl;
         if (base >= s1) break;
-        for (int q = 0; q < spl; ++q) {
-            const uint64_t s = base + (uint64_t)q;
-            if (s >= s1) break;
-            int32_t v[8];
-            uint64_t alo, ahi, b = 0, ov = 0;
-            uint32_t sz[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-            const uint32_t st = ns_sample<G, K>(g, p, seed, tag, s, v, alo, ahi, ov, b, count_bytes != 0, list,
-                                                MODE == 1 ? &la : nullptr, hist, MODE == 2 ? sz : nullptr);
-            ovf |= ov;
-            if (st != 0xFFu) {
-                alo = 0;
-                ahi = 0;
+        const uint64_t end = min(s1, base + (uint64_t)spl);
+        for (uint64_t gb = base; gb < end; gb += (uint64_t)GS) {
+            const int n = (int)min((uint64_t)GS, end - gb);
+            // prologue: every draw of the group, lane (q * D + t) holding draw slot t of sample gb + q
+            Draws dr;
+            {
+                const int q = lane / D, t = lane - q * D;
+                uint64_t r = 0;
+                if (q < n) r = philox_r64(seed, gb + (uint64_t)q, draw_of_slot<K>(t), tag);
+                dr.lo = (uint32_t)r;
+                dr.hi = (uint32_t)(r >> 32);
+                dr.k1 = K - 1;
+                dr.base = 0;
             }
-            uint64_t h = 0;
-            if (checksum) {
-                h = fmix64(s ^ 0x9E3779B97F4A7C15ull);
-                h = fmix64(h ^ (uint64_t)st);
+            for (int q = 0; q < n; ++q) {
+                const uint64_t s = gb + (uint64_t)q;
+                dr.base = q * D;
+                int32_t v[8];
+                uint64_t alo, ahi, b = 0, ov = 0;
+                uint32_t sz[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+                const uint32_t st = ns_sample<G, K>(g, p, seed, tag, s, v, alo, ahi, ov, b, count_bytes != 0, list,
+                                                    MODE == 1 ? &la : nullptr, hist, MODE == 2 ? sz : nullptr, &dr);
+                ovf |= ov;
+                if (st != 0xFFu) {
+                    alo = 0;
+                    ahi = 0;
+                }
+                // the sample's record: lanes 0-7 the walk, 8 the status, 9-12 X, 13-14 bytes
+                if (lane < REC - 1) {
+                    uint32_t w = 0;
 #pragma unroll
-                for (int i = 0; i < 8; ++i)
-                    if (i < p.k) h = fmix64(h ^ (uint64_t)(uint32_t)v[i]);
-                h = fmix64(h ^ alo);
-                h = fmix64(h ^ ahi);
+                    for (int i = 0; i < 8; ++i)
+                        if (lane == i) w = (uint32_t)v[i];
+                    if (lane == 8) w = st;
+                    if (lane == 9) w = (uint32_t)alo;
+                    if (lane == 10) w = (uint32_t)(alo >> 32);
+                    if (lane == 11) w = (uint32_t)ahi;
+                    if (lane == 12) w = (uint32_t)(ahi >> 32);
+                    if (lane == 13) w = (uint32_t)b;
+                    if (lane == 14) w = (uint32_t)(b >> 32);
+                    rec[q * REC + lane] = w;
+                }
+                if (tr.buf && s >= tr.lo && s < tr.hi && lane < 16) {
+                    uint32_t w = 0;
+                    if (lane < 2) {
+                        w = (uint32_t)(s >> (32 * lane));
+                    } else if (lane < 10) {
+#pragma unroll
+                        for (int i = 0; i < 8; ++i)
+                            if (lane - 2 == i) w = (uint32_t)v[i];
+                    } else if (lane == 10) w = st;
+                    else if (lane == 11) w = (uint32_t)p.k;
+                    else if (lane < 14) w = (uint32_t)(alo >> (32 * (lane - 12)));
+                    else w = (uint32_t)(ahi >> (32 * (lane - 14)));
+                    reinterpret_cast<uint32_t*>(tr.buf + (s - tr.lo))[lane] = w;
+                    if (MODE == 2 && tr.sizes && lane < 8) {
+                        uint32_t z = 0;
+#pragma unroll
+                        for (int i = 0; i < 8; ++i)
+                            if (lane == i) z = sz[i];
+                        tr.sizes[(s - tr.lo) * 8 + (uint64_t)lane] = z;
+                    }
+                }
             }
-            // this lane's share of the sample
-            const uint32_t d[4] = {(uint32_t)alo, (uint32_t)(alo >> 32), (uint32_t)ahi, (uint32_t)(ahi >> 32)};
-            uint64_t add = 0;
-            if (lane < 4) {
-                add = d[lane & 3];
-            } else if (lane >= 8 && lane < 16 && (ahi | alo) != 0) {
-                const int col = lane - 8;
+            // epilogue: lane q < n takes sample gb + q (LDS operations of a wave complete in order)
+            __builtin_amdgcn_wave_barrier();
+            {
+                const bool mine = lane < n;
+                const uint32_t* r = rec + (mine ? lane : 0) * REC;
+                const uint32_t st = mine ? r[8] : 0u;
+                uint32_t d[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) d[i] = mine ? r[9 + i] : 0u;
+                const uint64_t bytes = mine ? ((uint64_t)r[14] << 32 | r[13]) : 0ull;
+                uint64_t h = 0;
+                if (mine && checksum) {
+                    h = fmix64((gb + (uint64_t)lane) ^ 0x9E3779B97F4A7C15ull);
+                    h = fmix64(h ^ (uint64_t)st);
+#pragma unroll
+                    for (int i = 0; i < K; ++i) h = fmix64(h ^ (uint64_t)r[i]);
+                    h = fmix64(h ^ ((uint64_t)d[1] << 32 | d[0]));
+                    h = fmix64(h ^ ((uint64_t)d[3] << 32 | d[2]));
+                }
+                // digit columns of X^2: low and high halves of the digit products
+                uint64_t c2[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
                 for (int a = 0; a < 4; ++a)
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-                        const uint64_t pr = (uint64_t)d[a] * (uint64_t)d[c];
-                        if (a + c == col) add += pr & 0xFFFFFFFFull;
-                        if (a + c + 1 == col) add += pr >> 32;
+                    for (int e = 0; e < 4; ++e) {
+                        const uint64_t pr = (uint64_t)d[a] * (uint64_t)d[e];
+                        c2[a + e] += pr & 0xFFFFFFFFull;
+                        if (a + e + 1 < 8) c2[a + e + 1] += pr >> 32;
                     }
-            } else if (lane == 20) {
-                add = st == 0xFFu ? 1 : 0;
-            } else if (lane == 21) {
-                add = h;
-            } else if (lane == 22) {
-                add = b;
-            }
-            acc += add;
-            if (tr.buf && s >= tr.lo && s < tr.hi && lane < 16) {
-                uint32_t w;
-                if (lane < 2) w = (uint32_t)(s >> (32 * lane));
-                else if (lane < 10) w = (uint32_t)v[lane - 2];
-                else if (lane == 10) w = st;
-                else if (lane == 11) w = (uint32_t)p.k;
-                else if (lane < 14) w = (uint32_t)(alo >> (32 * (lane - 12)));
-                else w = (uint32_t)(ahi >> (32 * (lane - 14)));
-                reinterpret_cast<uint32_t*>(tr.buf + (s - tr.lo))[lane] = w;
-                if (MODE == 2 && tr.sizes && lane < 8) {
-                    uint32_t z = 0;
+                const uint64_t hits = (uint64_t)__popcll(__ballot(mine && st == 0xFFu));
+                uint64_t add = 0;
 #pragma unroll
-                    for (int i = 0; i < 8; ++i)
-                        if (lane == i) z = sz[i];
-                    tr.sizes[(s - tr.lo) * 8 + (uint64_t)lane] = z;
+                for (int i = 0; i < 4; ++i) {
+                    const uint64_t t = row_sum16(d[i]);
+                    if (lane == i) add = t;
                 }
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const uint64_t t = row_sum16(c2[i]);
+                    if (lane == 8 + i) add = t;
+                }
+                const uint64_t hs = row_sum16(h);
+                const uint64_t bs = row_sum16(bytes);
+                if (lane == 20) add = hits;
+                if (lane == 21) add = hs;
+                if (lane == 22) add = bs;
+                acc += add;
             }
+            __builtin_amdgcn_wave_barrier();
         }
     }
     if (lane == 23) acc = ovf;
     // block reduction: per wave the lane values are already the wave's sums
     __shared__ unsigned long long red[4][24];
-    const int w = (int)(threadIdx.x >> 6);
-    if (lane < 24) red[w][lane] = acc;
+    if (lane < 24) red[wid][lane] = acc;
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned long long col[24];
