@@ -155,10 +155,8 @@ __global__ __launch_bounds__(256) void ns_window_kernel(DGraph g, Plan p, uint64
 //    draw) pair per lane; a sample reads its draws back with readlane;
 //  * each sample leaves a record (walk, status, weight, bytes) in LDS;
 //  * epilogue: lane q hashes record q and forms the 32-bit digits of its
-//    weight and the digit columns of the weight's square; sums over the group
-//    are added to accumulators spread over the lanes (0-3 the digits of S1,
-//    8-15 the columns of S2, 20 hits, 21 checksum, 22 bytes, 23 the overflow
-//    flag), normalised once per block.
+//    weight and the digit columns of the weight's square, and adds them to the
+//    wave's sums in LDS (LDS atomics); the sums are normalised once per block.
 // MODE 0: uniform proposal; 1: learned proposal; 2: uniform with per-step set
 // sizes recorded for traced samples (training pilots)
 #ifndef SGPM_WAVE_BLOCKS_PER_CU
@@ -174,14 +172,6 @@ __device__ __forceinline__ uint32_t draw_of_slot(int t) {
     return t == 0 ? 0u : t <= K - 2 ? (uint32_t)(t + 1) : (uint32_t)(18 + (t - (K - 1)));
 }
 
-// sum over lanes 0..15 (the other lanes hold zeros), returned wave-uniform
-__device__ __forceinline__ uint64_t row_sum16(uint64_t x) {
-#pragma unroll
-    for (int o = 1; o < 16; o <<= 1) x += __shfl_xor(x, o);
-    return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(x >> 32), 0) << 32) |
-           (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, 0);
-}
-
 template <int MODE, int K>
 __global__ __launch_bounds__(256, SGPM_WAVE_BLOCKS_PER_CU) void ns_wave_kernel(DGraph g, Plan p, uint64_t seed, uint32_t tag, uint64_t s0,
                                                       uint64_t s1, int spl, unsigned long long* __restrict__ ticket,
@@ -195,10 +185,13 @@ __global__ __launch_bounds__(256, SGPM_WAVE_BLOCKS_PER_CU) void ns_wave_kernel(D
     __shared__ int32_t s_list[LDS_WORDS];
     __shared__ uint32_t s_hist[4][32];
     __shared__ uint32_t s_rec[4][GMAX * REC];
+    __shared__ unsigned long long s_wsum[4][16];
     uint32_t* hist = s_hist[wid];
     uint32_t* rec = s_rec[wid];
+    unsigned long long* wsum = s_wsum[wid];
     int32_t* list = s_list + wid * (LDS_WORDS / 4);
-    uint64_t acc = 0;
+    if (lane < 16) wsum[lane] = 0ull;
+    __builtin_amdgcn_wave_barrier();
     uint64_t ovf = 0;
     const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x >> 6);
     uint64_t tstat = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -278,65 +271,58 @@ __global__ __launch_bounds__(256, SGPM_WAVE_BLOCKS_PER_CU) void ns_wave_kernel(D
                     }
                 }
             }
-            // epilogue: lane q < n takes sample gb + q (LDS operations of a wave complete in order)
+            // epilogue: lane q < n takes sample gb + q (LDS operations of a wave
+            // complete in order) and adds its columns to the wave's LDS sums
             __builtin_amdgcn_wave_barrier();
-            {
-                const bool mine = lane < n;
-                const uint32_t* r = rec + (mine ? lane : 0) * REC;
-                const uint32_t st = mine ? r[8] : 0u;
+            if (lane < n) {
+                const uint32_t* r = rec + lane * REC;
+                const uint32_t st = r[8];
                 uint32_t d[4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) d[i] = mine ? r[9 + i] : 0u;
-                const uint64_t bytes = mine ? ((uint64_t)r[14] << 32 | r[13]) : 0ull;
-                uint64_t h = 0;
-                if (mine && checksum) {
-                    h = fmix64((gb + (uint64_t)lane) ^ 0x9E3779B97F4A7C15ull);
+                for (int i = 0; i < 4; ++i) d[i] = r[9 + i];
+                if (checksum) {
+                    uint64_t h = fmix64((gb + (uint64_t)lane) ^ 0x9E3779B97F4A7C15ull);
                     h = fmix64(h ^ (uint64_t)st);
 #pragma unroll
                     for (int i = 0; i < K; ++i) h = fmix64(h ^ (uint64_t)r[i]);
                     h = fmix64(h ^ ((uint64_t)d[1] << 32 | d[0]));
                     h = fmix64(h ^ ((uint64_t)d[3] << 32 | d[2]));
+                    atomicAdd(&wsum[12], (unsigned long long)h);
                 }
-                // digit columns of X^2: low and high halves of the digit products
-                uint64_t c2[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+                if (count_bytes) atomicAdd(&wsum[13], (unsigned long long)((uint64_t)r[14] << 32 | r[13]));
+                if (st == 0xFFu) {
+                    // digits of X and the digit columns of X^2 (low and high halves of the digit products)
+                    uint64_t c2[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
-                for (int a = 0; a < 4; ++a)
+                    for (int a = 0; a < 4; ++a)
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const uint64_t pr = (uint64_t)d[a] * (uint64_t)d[e];
-                        c2[a + e] += pr & 0xFFFFFFFFull;
-                        if (a + e + 1 < 8) c2[a + e + 1] += pr >> 32;
-                    }
-                const uint64_t hits = (uint64_t)__popcll(__ballot(mine && st == 0xFFu));
-                uint64_t add = 0;
+                        for (int e = 0; e < 4; ++e) {
+                            const uint64_t pr = (uint64_t)d[a] * (uint64_t)d[e];
+                            c2[a + e] += pr & 0xFFFFFFFFull;
+                            if (a + e + 1 < 8) c2[a + e + 1] += pr >> 32;
+                        }
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const uint64_t t = row_sum16(d[i]);
-                    if (lane == i) add = t;
+                    for (int i = 0; i < 4; ++i) atomicAdd(&wsum[i], (unsigned long long)d[i]);
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) atomicAdd(&wsum[4 + i], (unsigned long long)c2[i]);
+                    atomicAdd(&wsum[14], 1ull);
                 }
-#pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    const uint64_t t = row_sum16(c2[i]);
-                    if (lane == 8 + i) add = t;
-                }
-                const uint64_t hs = row_sum16(h);
-                const uint64_t bs = row_sum16(bytes);
-                if (lane == 20) add = hits;
-                if (lane == 21) add = hs;
-                if (lane == 22) add = bs;
-                acc += add;
             }
             __builtin_amdgcn_wave_barrier();
         }
     }
-    if (lane == 23) acc = ovf;
-    // block reduction: per wave the lane values are already the wave's sums
-    __shared__ unsigned long long red[4][24];
-    if (lane < 24) red[wid][lane] = acc;
+    __builtin_amdgcn_wave_barrier();
+    // per wave: lanes 0-3 the digit sums of S1, 4-11 the column sums of S2,
+    // 12 checksum, 13 bytes, 14 hits, 15 the overflow flag
+    uint64_t acc = lane < 15 ? (uint64_t)wsum[lane] : 0ull;
+    if (lane == 15) acc = ovf;
+    // block reduction of the waves' sums
+    __shared__ unsigned long long red[4][16];
+    if (lane < 16) red[wid][lane] = acc;
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned long long col[24];
-        for (int i = 0; i < 24; ++i) col[i] = red[0][i] + red[1][i] + red[2][i] + red[3][i];
+        unsigned long long col[16];
+        for (int i = 0; i < 16; ++i) col[i] = red[0][i] + red[1][i] + red[2][i] + red[3][i];
         unsigned long long o[PF_N];
         for (int i = 0; i < PF_N; ++i) o[i] = 0;
         unsigned long long c = 0;
@@ -347,14 +333,14 @@ __global__ __launch_bounds__(256, SGPM_WAVE_BLOCKS_PER_CU) void ns_wave_kernel(D
         }
         c = 0;
         for (int i = 0; i < 10; ++i) {  // S2: digit columns 0-7, carried into 10 digits
-            const unsigned long long t = (i < 8 ? col[8 + i] : 0ull) + c;
+            const unsigned long long t = (i < 8 ? col[4 + i] : 0ull) + c;
             o[PF_S2 + i] = i < 9 ? (t & 0xFFFFFFFFull) : t;
             c = t >> 32;
         }
-        o[PF_HITS] = col[20];
-        o[PF_CSUM] = col[21];
-        o[PF_BYTES] = col[22];
-        o[PF_OVF] = col[23];
+        o[PF_HITS] = col[14];
+        o[PF_CSUM] = col[12];
+        o[PF_BYTES] = col[13];
+        o[PF_OVF] = col[15];
         unsigned long long* dst = partials + (size_t)blockIdx.x * PF_N;
         for (int i = 0; i < PF_N; ++i) dst[i] = o[i];
     }
