@@ -11,13 +11,13 @@ value   = verified samples/s over the timed steps (all samples drawn / wall time
 roofline= the sampling kernel's algorithmic bytes (per-sample figure from the
           instrumented kernel x samples) / its HIP-event time, against the HBM peak
 cpu_baseline = the CPU oracle on a bounded sample of the same workload
-Walks of a traced id range of every timed run are checked against the oracle
-after timing ("verified").
+Every timed run is rerun by the CPU oracle after timing with the same
+options; stop point, exact sums and the checksum over all samples must match
+("verified").
 """
 from __future__ import annotations
 
 import argparse
-import ctypes as C
 import json
 import os
 import sys
@@ -30,7 +30,6 @@ sys.path.insert(0, ROOT)
 
 METRIC = "time-to-ε (ε=1%, 95% conf) & verified samples/s; learned vs uniform NS"
 HBM_PEAK_GBS = 8000.0
-NTRACE = 512
 
 
 def log(*a):
@@ -65,6 +64,46 @@ def measured_traffic(runs, launches):
     return total / max(1, launches)
 
 
+def learned_leg(S, ctx, g, pats, queries, eps, steps, lanes):
+    """Learned proposal against uniform NS on the same graph: train the MLP
+    proposal on the GPU (pilot samples of every query on their own Philox
+    stream), then run both proposals to eps with the same seeds.  Returns
+    time-to-eps and samples to the stop for each, and the training cost."""
+    t0 = time.perf_counter()
+    model = S.sgpm_model_train(ctx, g, [pats[q] for q in queries])
+    train_s = time.perf_counter() - t0
+    info = S.sgpm_model_info(model)
+    out = {"train_s": train_s, "pilot_s": info["pilot_seconds"], "tuples": info["tuples"],
+           "loss_first": info["loss_first"], "loss_last": info["loss_last"], "queries": {}}
+    for q in queries:
+        # warm both paths (the learned one runs one sample per wave)
+        for prop in (None, model):
+            o = S.sgpm_options_default(eps=eps, seed=800, lanes_per_sample=lanes[q] if prop is None else 64,
+                                       proposal=prop.value if prop is not None else None)
+            S.sgpm_estimate(ctx, g, pats[q], o)
+        res = {}
+        for name, prop in (("uniform", None), ("learned", model)):
+            ts, ns, est, eh = [], [], [], []
+            for step in range(steps):
+                o = S.sgpm_options_default(eps=eps, seed=2000 + step, checksum=1,
+                                           lanes_per_sample=lanes[q] if prop is None else 64,
+                                           proposal=prop.value if prop is not None else None)
+                r, _ = S.sgpm_estimate(ctx, g, pats[q], o)
+                ts.append(r.seconds_total)
+                ns.append(int(r.n_samples))
+                est.append(float(r.estimate))
+                eh.append(float(r.eps_hat))
+            res[name] = {"time_to_eps_s": float(np.mean(ts)), "n_stop": ns, "estimate": est, "eps_hat": eh,
+                         "samples_per_s": float(sum(ns) / sum(ts))}
+        res["time_ratio_learned_over_uniform"] = res["learned"]["time_to_eps_s"] / res["uniform"]["time_to_eps_s"]
+        out["queries"][q] = res
+        log(f"learned vs uniform {q}: {res['learned']['time_to_eps_s'] * 1e3:.2f} ms "
+            f"({np.mean(res['learned']['n_stop']):.0f} samples) vs {res['uniform']['time_to_eps_s'] * 1e3:.2f} ms "
+            f"({np.mean(res['uniform']['n_stop']):.0f} samples)")
+    S.sgpm_model_free(model)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,6 +114,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-probes", action="store_true", help="skip the measured copy/gather rooflines")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-uniform leg")
     ap.add_argument("--counters-run", action="store_true",
                     help="short run for hardware counters: one 256 MiB copy, then one 4M-sample window per query")
     args = ap.parse_args()
@@ -114,20 +154,16 @@ def main():
             log(f"{q}: {r.n_samples} samples, kernel {r.seconds_kernel * 1e3:.3f} ms over {r.launches} launch(es)")
         return
 
-    def opts_for(q, seed, lanes, trace):
-        buf = S.trace_buffer(NTRACE) if trace else None
-        o = S.sgpm_options_default(eps=args.eps, confidence=0.95, seed=seed, checksum=1, lanes_per_sample=lanes,
-                                   query_tag=0)
-        if trace:
-            o.trace_lo, o.trace_hi, o.trace_buf = 0, NTRACE, C.cast(buf, C.c_void_p).value
-        return o, buf
+    def opts_for(q, seed, lanes):
+        return S.sgpm_options_default(eps=args.eps, confidence=0.95, seed=seed, checksum=1, lanes_per_sample=lanes,
+                                      query_tag=0)
 
     # warmup: also picks the lane count per query (autotuner on the first window)
     lanes = {q: 0 for q in queries}
     warm_launches = 0
     for w in range(max(1, args.warmup)):
         for q in queries:
-            o, _ = opts_for(q, 900 + w, lanes[q], False)
+            o = opts_for(q, 900 + w, lanes[q])
             r, _ = S.sgpm_estimate(ctx, g, pats[q], o)
             lanes[q] = r.lanes_per_sample
             warm_launches += r.launches
@@ -140,9 +176,9 @@ def main():
     for step in range(args.steps):
         for q in queries:
             seed = 1000 + step
-            o, buf = opts_for(q, seed, lanes[q], True)
+            o = opts_for(q, seed, lanes[q])
             r, rc = S.sgpm_estimate(ctx, g, pats[q], o)
-            runs.append({"q": q, "seed": seed, "r": r, "buf": buf, "rc": rc})
+            runs.append({"q": q, "seed": seed, "r": r, "rc": rc, "opts": o})
     torch.cuda.synchronize()
     t_end = time.perf_counter()
     wall = t_end - t_begin
@@ -153,13 +189,15 @@ def main():
     # algorithmic bytes per sample, from the instrumented kernel on step 0's samples
     bps = {}
     for q in queries:
-        o, _ = opts_for(q, 1000, lanes[q], False)
+        o = opts_for(q, 1000, lanes[q])
         o.mode = S.MODE_FIXED_N
         o.fixed_n = int(next(x["r"].n_samples for x in runs if x["q"] == q))
         r, _ = S.sgpm_estimate(ctx, g, pats[q], o, counted=True)
         bps[q] = r.bytes / max(1, r.n_samples)
     alg_bytes = sum(bps[x["q"]] * x["r"].n_samples for x in runs)
     achieved = alg_bytes / kernel_s / 1e9 if kernel_s > 0 else 0.0
+
+    learned = None if args.no_learned else learned_leg(S, ctx, g, pats, queries, args.eps, args.steps, lanes)
 
     probes = None
     if not args.no_probes:
@@ -178,9 +216,12 @@ def main():
                     "eps_hat": [float(r.eps_hat) for r in rs], "hit_rate": float(np.mean([r.n_hits / r.n_samples
                                                                                           for r in rs])),
                     "converged": all(r.converged for r in rs), "lanes_per_sample": lanes[q],
+                    "windows": [int(r.windows) for r in rs],
+                    "device_span_s": float(np.mean([r.seconds_sampling for r in rs])),
+                    "kernel_s": float(np.mean([r.seconds_kernel for r in rs])),
                     "bytes_per_sample": bps[q]}
 
-    # CPU leg: oracle baseline and verification of the traced walks
+    # CPU leg: oracle baseline and verification of the timed runs
     cpu = None
     verified = None
     if not args.no_cpu:
@@ -188,15 +229,22 @@ def main():
         tc = time.time()
         og = O.OGraph.from_raw_csr(n, off, nbr)
         log(f"oracle graph built in {time.time() - tc:.1f}s")
+        # every timed run again in the oracle, same options: the stop point,
+        # the exact sums and the checksum over all samples must be identical
         verified = True
+        tv = time.perf_counter()
         for x in runs:
             k, e = synth.pattern(x["q"])
             op = O.compile_plan(k, e)
-            recs = O.trace(og, op, x["seed"], 0, 0, NTRACE)
-            for a, b in zip(x["buf"], recs):
-                st = 0xFF if b.hit else b.fail_step
-                if (a.s, a.status, list(a.v), a.alpha) != (b.s, st, list(b.v), b.alpha):
-                    verified = False
+            so = x["opts"]
+            orr = O.run(og, op, O.make_opts(eps=so.eps, confidence=so.confidence, seed=so.seed, tag=so.query_tag,
+                                            n_min=so.n_min, w_min=so.w_min, quantum=so.quantum,
+                                            max_samples=so.max_samples, growth=so.window_growth))
+            r = x["r"]
+            if (orr.n, orr.S1, orr.S2, orr.hits, orr.checksum) != (r.n_samples, r.S1, r.S2, r.n_hits, r.checksum):
+                verified = False
+                log(f"verification failed: {x['q']} seed {x['seed']}")
+        log(f"verified {len(runs)} timed runs against the oracle in {time.perf_counter() - tv:.1f}s")
         k, e = synth.pattern("4-clique")
         op = O.compile_plan(k, e)
         th = O.nthreads()
@@ -234,6 +282,7 @@ def main():
                      "alg_bytes_per_launch": alg_bytes / max(1, launches),
                      "measured": probes},
         "cpu_baseline": cpu,
+        "learned_vs_uniform": learned,
     }
     print(json.dumps(line), flush=True)
 

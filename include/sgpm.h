@@ -173,8 +173,10 @@ typedef struct {
 } sgpm_result;
 
 /* Defaults: eps 0.01, confidence 0.95, seed 1, tag 0, strict NS, n_min = w_min =
- * 2^20, quantum 2^16, max_samples 2^40, growth 0.10, colours 0, reps 64,
- * lanes 0 (autotune), no checksum, no trace. */
+ * 2^19 (a few passes of the device's waves, so that a window's slowest samples
+ * do not set its length), quantum 2^16, max_samples 2^40, growth 0.10, colours
+ * 0, reps 64, lanes 0 (autotuned on the first window of 2^19 samples or more;
+ * one sample per wave before that), no checksum, no trace. */
 void sgpm_options_default(sgpm_options* o);
 
 /* Estimate the count of P in G (Sec. 4-5).  Strict mode draws NS-prune samples

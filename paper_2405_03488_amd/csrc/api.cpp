@@ -1,5 +1,6 @@
 // C-ABI entry points: contexts, graphs, patterns and the NS estimation loop.
 #include <algorithm>
+#include <deque>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -17,7 +18,7 @@ namespace sgpm {
 
 namespace {
 
-constexpr int SLOT_WORDS = 32;  // [1..20] sums of one launch
+constexpr int SLOT_WORDS = 32;  // host slot of one launch: [1..20] its sums
 
 
 sgpm_status ensure_scratch(sgpm_ctx* c, size_t blocks, size_t slots) {
@@ -29,16 +30,18 @@ sgpm_status ensure_scratch(sgpm_ctx* c, size_t blocks, size_t slots) {
         c->partial_blocks = blocks;
     }
     if (slots > c->nslots) {
-        if (c->d_slots) (void)hipFree(c->d_slots);
         if (c->h_slots) (void)hipHostFree(c->h_slots);
         if (c->d_tickets) (void)hipFree(c->d_tickets);
-        c->d_slots = nullptr;
         c->h_slots = nullptr;
+        c->dh_slots = nullptr;
         c->d_tickets = nullptr;
         c->nslots = 0;
         size_t want = std::max<size_t>(slots, 1024);
-        HIP_TRY(c, hipMalloc(&c->d_slots, want * SLOT_WORDS * sizeof(unsigned long long)));
-        HIP_TRY(c, hipHostMalloc(&c->h_slots, want * SLOT_WORDS * sizeof(unsigned long long), hipHostMallocDefault));
+        // pinned host slots the reduction kernel writes into directly: no copy
+        // command follows a window, so queueing the next window never waits
+        HIP_TRY(c, hipHostMalloc(&c->h_slots, want * SLOT_WORDS * sizeof(unsigned long long),
+                                 hipHostMallocMapped | hipHostMallocCoherent));
+        HIP_TRY(c, hipHostGetDevicePointer((void**)&c->dh_slots, c->h_slots, 0));
         HIP_TRY(c, hipMalloc(&c->d_tickets, want * NTK * TK_STRIDE * sizeof(unsigned long long)));
         c->nslots = want;
     }
@@ -89,7 +92,6 @@ sgpm_status sgpm_destroy(sgpm_ctx_t c) {
     if (!c) return SGPM_EINVAL;
     (void)hipSetDevice(c->dev);
     if (c->d_partials) (void)hipFree(c->d_partials);
-    if (c->d_slots) (void)hipFree(c->d_slots);
     if (c->h_slots) (void)hipHostFree(c->h_slots);
     if (c->d_tickets) (void)hipFree(c->d_tickets);
     for (hipEvent_t e : c->kev) (void)hipEventDestroy(e);
@@ -112,8 +114,8 @@ void sgpm_options_default(sgpm_options* o) {
     o->seed = 1;
     o->query_tag = 0;
     o->mode = SGPM_MODE_STRICT_NS;
-    o->n_min = 1ull << 20;
-    o->w_min = 1ull << 20;
+    o->n_min = 1ull << 19;
+    o->w_min = 1ull << 19;
     o->quantum = 1ull << 16;
     o->max_samples = 1ull << 40;
     o->window_growth = 0.10;
@@ -298,22 +300,19 @@ sgpm_status enqueue_range(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_
     // partials sized for the largest grid once, so no buffer in flight is freed
     sgpm_status st = ensure_scratch(c, (size_t)largest_grid(c), slot + 1);
     if (st != SGPM_OK) return st;
-    unsigned long long* sl = c->d_slots + slot * SLOT_WORDS;
     unsigned long long* tk = c->d_tickets + slot * NTK * TK_STRIDE;
-    HIP_TRY(c, launch_fill_u64(sl, SLOT_WORDS, 0ull, c->st));
     if (dynamic) HIP_TRY(c, launch_fill_u64(tk, (uint64_t)NTK * TK_STRIDE, 0ull, c->st));
-    while (c->kev.size() < 2 * (slot + 1)) {
+    while (c->kev.size() < 3 * (slot + 1)) {
         hipEvent_t ev;
         HIP_TRY(c, hipEventCreate(&ev));
         c->kev.push_back(ev);
     }
-    HIP_TRY(c, hipEventRecord(c->kev[2 * slot], c->st));
+    HIP_TRY(c, hipEventRecord(c->kev[3 * slot], c->st));
     HIP_TRY(c, launch_ns_window(g->view(), p, o.seed, o.query_tag, s0, s1, cfg, dynamic ? tk : nullptr,
                                 c->d_partials, o.checksum, count_bytes, tr, la, c->st));
-    HIP_TRY(c, hipEventRecord(c->kev[2 * slot + 1], c->st));
-    HIP_TRY(c, launch_reduce_partials(c->d_partials, cfg.blocks, sl + 1, c->st));
-    HIP_TRY(c, hipMemcpyAsync(c->h_slots + slot * SLOT_WORDS, sl, SLOT_WORDS * sizeof(unsigned long long),
-                              hipMemcpyDeviceToHost, c->st));
+    HIP_TRY(c, hipEventRecord(c->kev[3 * slot + 1], c->st));
+    HIP_TRY(c, launch_reduce_partials(c->d_partials, cfg.blocks, c->dh_slots + slot * SLOT_WORDS + 1, c->st));
+    HIP_TRY(c, hipEventRecord(c->kev[3 * slot + 2], c->st));
     return SGPM_OK;
 }
 
@@ -377,66 +376,86 @@ sgpm_status ns_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_op
     int windows = 0, launches = 0;
     bool converged = false;
     sgpm_status status = SGPM_OK;
+    // One window at a time: the host's share of a window (launch, wait, exact
+    // statistics) is a few microseconds, so a window queued ahead would only
+    // add device work past the stop.  Windows use slot 0; autotune pieces 2..9.
+    struct Win {
+        uint64_t a, b;
+        size_t slot0, nslots;
+    };
+    std::deque<Win> inflight;
+    const size_t depth = 1;
+    uint64_t queued = 0;
+    size_t last_done = SIZE_MAX;
+    HIP_TRY(c, hipEventRecord(e0, c->st));
     for (;;) {
-        const uint64_t nx = o.mode == SGPM_MODE_FIXED_N ? o.fixed_n : next_window_end(s.n, o);
-        if (nx <= s.n) break;
-        size_t slots = 0;
-        HIP_TRY(c, hipEventRecord(e0, c->st));
-        if (lanes == 0) {
-            // autotune on the first window: split it into two rounds over the
-            // candidate lane counts and keep the fastest per sample, each
-            // candidate judged by its better piece (the first launch of a
-            // kernel pays for loading its code and for cold caches).  Every
-            // sample is still drawn exactly once, so results are unchanged.
-            static const int cand[4] = {64, 16, 4, 1};
-            constexpr int kPieces = 8;
-            const uint64_t len = nx - s.n;
-            float best_per[4] = {0, 0, 0, 0};
-            bool seen[4] = {false, false, false, false};
-            for (int i = 0; i < kPieces; i++) {
-                const uint64_t a = s.n + len * (uint64_t)i / kPieces, b = s.n + len * (uint64_t)(i + 1) / kPieces;
-                if (b <= a) continue;
-                const int ci = i % 4;
-                const size_t slot = slots++;
-                status = enqueue_range(c, g, p, o, a, b, cand[ci], slot, tr, count_bytes, la, len);
-                if (status != SGPM_OK) return status;
-                // sampling-kernel time alone (the events enqueue_range records around it)
-                HIP_TRY(c, hipEventSynchronize(c->kev[2 * slot + 1]));
-                float ms = 0;
-                HIP_TRY(c, hipEventElapsedTime(&ms, c->kev[2 * slot], c->kev[2 * slot + 1]));
-                const float per = ms / (float)(b - a);
-                if (std::getenv("SGPM_DEBUG"))
-                    std::fprintf(stderr, "sgpm autotune: lanes=%d %.3f ms for %llu samples (%.4g samples/s)\n",
-                                 cand[ci], ms, (unsigned long long)(b - a), (double)(b - a) / (ms * 1e-3));
-                if (!seen[ci] || per < best_per[ci]) best_per[ci] = per;
-                seen[ci] = true;
-            }
-            int best = 64;
-            float best_ms = 0;
-            for (int ci = 0; ci < 4; ci++)
-                if (seen[ci] && (best_ms == 0 || best_per[ci] < best_ms)) {
-                    best_ms = best_per[ci];
-                    best = cand[ci];
+        while (inflight.size() < depth) {
+            const uint64_t nx = o.mode == SGPM_MODE_FIXED_N ? o.fixed_n : next_window_end(queued, o);
+            if (nx <= queued || (o.mode == SGPM_MODE_FIXED_N && queued > 0)) break;
+            if (lanes == 0 && nx - queued >= (1ull << 19)) {
+                if (!inflight.empty()) break;  // tune once the queue has drained
+                // autotune on the first long window: split it into two rounds over the
+                // candidate lane counts and keep the fastest per sample, each
+                // candidate judged by its better piece (the first launch of a
+                // kernel pays for loading its code and for cold caches).  Every
+                // sample is still drawn exactly once, so results are unchanged.
+                static const int cand[4] = {64, 16, 4, 1};
+                constexpr int kPieces = 8;
+                const uint64_t len = nx - queued;
+                float best_per[4] = {0, 0, 0, 0};
+                bool seen[4] = {false, false, false, false};
+                size_t used = 0;
+                for (int i = 0; i < kPieces; i++) {
+                    const uint64_t a = queued + len * (uint64_t)i / kPieces, b = queued + len * (uint64_t)(i + 1) / kPieces;
+                    const int ci = i % 4;
+                    const size_t slot = 2 + used++;
+                    status = enqueue_range(c, g, p, o, a, b, cand[ci], slot, tr, count_bytes, la, len);
+                    if (status != SGPM_OK) return status;
+                    // sampling-kernel time alone (the events enqueue_range records around it)
+                    HIP_TRY(c, hipEventSynchronize(c->kev[3 * slot + 1]));
+                    float ms = 0;
+                    HIP_TRY(c, hipEventElapsedTime(&ms, c->kev[3 * slot], c->kev[3 * slot + 1]));
+                    const float per = ms / (float)(b - a);
+                    if (std::getenv("SGPM_DEBUG"))
+                        std::fprintf(stderr, "sgpm autotune: lanes=%d %.3f ms for %llu samples (%.4g samples/s)\n",
+                                     cand[ci], ms, (unsigned long long)(b - a), (double)(b - a) / (ms * 1e-3));
+                    if (!seen[ci] || per < best_per[ci]) best_per[ci] = per;
+                    seen[ci] = true;
                 }
-            lanes = best;
-            c->ns_tuned[tune_key] = best;
-        } else {
-            status = enqueue_range(c, g, p, o, s.n, nx, lanes, slots++, tr, count_bytes, la);
+                int best = 64;
+                float best_ms = 0;
+                for (int ci = 0; ci < 4; ci++)
+                    if (seen[ci] && (best_ms == 0 || best_per[ci] < best_ms)) {
+                        best_ms = best_per[ci];
+                        best = cand[ci];
+                    }
+                lanes = best;
+                c->ns_tuned[tune_key] = best;
+                inflight.push_back(Win{queued, nx, 2, used});
+                queued = nx;
+                break;
+            }
+            // short windows before tuning: one sample per wave, not remembered
+            const size_t slot = 0;
+            status = enqueue_range(c, g, p, o, queued, nx, lanes ? lanes : 64, slot, tr, count_bytes, la);
             if (status != SGPM_OK) return status;
+            inflight.push_back(Win{queued, nx, slot, 1});
+            queued = nx;
         }
-        HIP_TRY(c, hipEventRecord(e1, c->st));
-        HIP_TRY(c, hipStreamSynchronize(c->st));
-        float ms = 0;
-        HIP_TRY(c, hipEventElapsedTime(&ms, e0, e1));
-        dev_seconds += ms * 1e-3;
-        for (size_t k = 0; k < slots; k++) {
+        if (inflight.empty()) break;
+        const Win w = inflight.front();
+        inflight.pop_front();
+        const size_t lastslot = w.slot0 + w.nslots - 1;
+        HIP_TRY(c, hipEventSynchronize(c->kev[3 * lastslot + 2]));
+        for (size_t k = w.slot0; k <= lastslot; k++) {
             absorb(s, c->h_slots + k * SLOT_WORDS + 1);
             float kms = 0;
-            HIP_TRY(c, hipEventElapsedTime(&kms, c->kev[2 * k], c->kev[2 * k + 1]));
+            HIP_TRY(c, hipEventElapsedTime(&kms, c->kev[3 * k], c->kev[3 * k + 1]));
             kernel_seconds += kms * 1e-3;
             launches++;
         }
-        s.n = nx;
+        last_done = lastslot;
+        s.n = w.b;
         windows++;
         if (s.ovf) {
             status = SGPM_EOVERFLOW;
@@ -450,11 +469,16 @@ sgpm_status ns_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_op
         }
         if (o.max_samples && s.n >= o.max_samples) break;
     }
+    if (last_done != SIZE_MAX) {
+        float ms = 0;
+        HIP_TRY(c, hipEventElapsedTime(&ms, e0, c->kev[3 * last_done + 2]));
+        dev_seconds = ms * 1e-3;
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     fill_result(res, s, z, learned ? 52 : 0);
     res->windows = windows;
-    res->lanes_per_sample = lanes;
+    res->lanes_per_sample = lanes ? lanes : 64;
     res->seconds_sampling = dev_seconds;
     res->seconds_kernel = kernel_seconds;
     res->launches = launches;
@@ -501,7 +525,7 @@ sgpm_status ns_pilot(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_optio
         absorb(s, c->h_slots + (size_t)i * SLOT_WORDS + 1);
         s.n = b - a;
         float ms = 0;
-        HIP_TRY(c, hipEventElapsedTime(&ms, c->kev[2 * (size_t)i], c->kev[2 * (size_t)i + 1]));
+        HIP_TRY(c, hipEventElapsedTime(&ms, c->kev[3 * (size_t)i], c->kev[3 * (size_t)i + 1]));
         seconds[i] = ms * 1e-3;
         eps_hat[i] = predicted_error(z, s.n, s.S1, s.S2);
     }

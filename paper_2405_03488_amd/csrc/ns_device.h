@@ -273,6 +273,13 @@ __device__ __forceinline__ uint32_t ns_sample(const DGraph& g, const Plan& p, ui
             if (up >> i & 1) hi = min(hi, v[i]);
             if (lw >> i & 1) lo = max(lo, v[i]);
         }
+        // learned proposal: this step's weight-table row, loaded while the
+        // candidates are scanned
+        uint64_t wrow = 0;
+        if (learned && lane < 32) {
+            const int32_t bp = bucket_of(*la, v[j - 1]);
+            wrow = (uint64_t)la->table[(((size_t)j * 32 + (size_t)b0) * 32 + (size_t)bp) * 32 + lane];
+        }
         // smallest connected earlier row (lowest position on ties)
         int d = -1;
         int32_t dl = BIG;
@@ -361,26 +368,50 @@ __device__ __forceinline__ uint32_t ns_sample(const DGraph& g, const Plan& p, ui
 
         uint32_t idx = 0;
         if constexpr (G == 64) {
-            if (learned) {
-                // weighted bucket, then a uniform member of it (learned proposal)
+            // learned proposal with every candidate in one bucket (buckets follow
+            // the id order, so the first and the last candidate decide): the
+            // weighted choice reduces to a uniform member drawn with draw 16+j
+            // and the factor sum / w_b is exactly |S_j|
+            const bool one_bucket =
+                learned && cnt <= (uint32_t)CAP && bucket_of(*la, uni<G>(list[0])) == bucket_of(*la, uni<G>(list[cnt - 1]));
+            if (one_bucket) {
+                idx = (uint32_t)__umul64hi((uint64_t)cnt, draw_at(dr, seed, s, 16u + (uint32_t)j, tag));
+                af = __dmul_rn(af, (double)cnt);
+            } else if (learned && cnt <= (uint32_t)CAP) {
+                // weighted bucket, then a uniform member of it: counts n_b <= CAP
+                // and n_b w_b < 2^26, so (n_b w_b) << 32 | n_b scans as one word
                 if (lane < 32) hist[lane] = 0;
-                if (cnt <= (uint32_t)CAP) {
-                    for (uint32_t i = (uint32_t)lane; i < cnt; i += 64u) atomicAdd(&hist[bucket_of(*la, list[i])], 1u);
-                } else {
-#pragma unroll
-                    for (int i = 0; i < 8; ++i) cur[i] = 0;
-                    for (int32_t base = start; base < slen; base += G) {
-                        int32_t x;
-                        uint64_t inm;
-                        const bool ok = eval_chunk(base, x, inm);
-                        if (ok) atomicAdd(&hist[bucket_of(*la, x)], 1u);
-                        if (inm != gmask) break;
-                    }
-                }
-                const int32_t bp = bucket_of(*la, v[j - 1]);
+                for (uint32_t i = (uint32_t)lane; i < cnt; i += 64u) atomicAdd(&hist[bucket_of(*la, list[i])], 1u);
                 const uint64_t nb = lane < 32 ? (uint64_t)hist[lane] : 0ull;
-                const uint64_t w =
-                    lane < 32 ? (uint64_t)la->table[(((size_t)j * 32 + (size_t)b0) * 32 + (size_t)bp) * 32 + lane] : 0ull;
+                const uint64_t w = wrow;
+                uint64_t pk = (nb * w) << 32 | nb;
+#pragma unroll
+                for (int o = 1; o < 32; o <<= 1) {
+                    const uint64_t y = __shfl_up(pk, (unsigned)o);
+                    if (lane >= o) pk += y;
+                }
+                const uint64_t cum = pk >> 32, cumn = pk & 0xFFFFFFFFull;
+                const uint64_t sigma = __shfl(cum, 31);
+                const uint64_t t = __umul64hi(sigma, draw_at(dr, seed, s, (uint32_t)j, tag));
+                const int bsel = __ffsll((unsigned long long)__ballot(lane < 32 && cum > t)) - 1;
+                const uint64_t nbs = __shfl(nb, bsel), wbs = __shfl(w, bsel), upto = __shfl(cumn, bsel);
+                const uint64_t inb = __umul64hi(nbs, draw_at(dr, seed, s, 16u + (uint32_t)j, tag));
+                idx = (uint32_t)((uint64_t)cnt - upto + inb);
+                af = __dmul_rn(af, __ddiv_rn((double)sigma, (double)wbs));
+            } else if (learned) {
+                // the same when the set overflowed the list: histogram by rescanning
+                if (lane < 32) hist[lane] = 0;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) cur[i] = 0;
+                for (int32_t base = start; base < slen; base += G) {
+                    int32_t x;
+                    uint64_t inm;
+                    const bool ok = eval_chunk(base, x, inm);
+                    if (ok) atomicAdd(&hist[bucket_of(*la, x)], 1u);
+                    if (inm != gmask) break;
+                }
+                const uint64_t nb = lane < 32 ? (uint64_t)hist[lane] : 0ull;
+                const uint64_t w = wrow;
                 const uint64_t cum = wave_incl_scan(nb * w);
                 const uint64_t cumn = wave_incl_scan(nb);
                 const uint64_t sigma = __shfl(cum, 63);

@@ -191,6 +191,14 @@ __global__ __launch_bounds__(256, SGPM_WAVE_BLOCKS_PER_CU) void ns_wave_kernel(D
     unsigned long long* wsum = s_wsum[wid];
     int32_t* list = s_list + wid * (LDS_WORDS / 4);
     if (lane < 16) wsum[lane] = 0ull;
+    // learned proposal: the bucket thresholds, searched once per candidate chunk, in LDS
+    __shared__ int32_t s_thr[32];
+    LearnArgs lal = la;
+    if (MODE == 1) {
+        if (threadIdx.x < 32) s_thr[threadIdx.x] = la.thr[threadIdx.x];
+        __syncthreads();
+        lal.thr = s_thr;
+    }
     __builtin_amdgcn_wave_barrier();
     uint64_t ovf = 0;
     const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x >> 6);
@@ -228,7 +236,7 @@ __global__ __launch_bounds__(256, SGPM_WAVE_BLOCKS_PER_CU) void ns_wave_kernel(D
                 uint64_t alo, ahi, b = 0, ov = 0;
                 uint32_t sz[8] = {0, 0, 0, 0, 0, 0, 0, 0};
                 const uint32_t st = ns_sample<G, K>(g, p, seed, tag, s, v, alo, ahi, ov, b, count_bytes != 0, list,
-                                                    MODE == 1 ? &la : nullptr, hist, MODE == 2 ? sz : nullptr, &dr);
+                                                    MODE == 1 ? &lal : nullptr, hist, MODE == 2 ? sz : nullptr, &dr);
                 ovf |= ov;
                 if (st != 0xFFu) {
                     alo = 0;
@@ -366,6 +374,7 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(const unsigned lon
         const int i = (int)threadIdx.x;
         out[i] = red[0][i] + red[1][i] + red[2][i] + red[3][i];
     }
+    __threadfence_system();  // `out` may be host memory read after the stream's next event
 }
 
 __global__ void fill_u64_kernel(unsigned long long* p, uint64_t n, unsigned long long v) {

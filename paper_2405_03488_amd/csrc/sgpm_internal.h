@@ -166,8 +166,8 @@ struct sgpm_ctx {
     // scratch reused across calls
     unsigned long long* d_partials = nullptr;
     size_t partial_blocks = 0;
-    unsigned long long* d_slots = nullptr;   // per launch: ticket + 20 sums (+ pad) = 32 words
-    unsigned long long* h_slots = nullptr;   // pinned mirror of the sums
+    unsigned long long* h_slots = nullptr;   // pinned host slots: per launch its 20 sums (32 words a slot)
+    unsigned long long* dh_slots = nullptr;  // the same memory as seen from the device
     unsigned long long* d_tickets = nullptr; // per launch: NTK ticket counters, TK_STRIDE words apart
     size_t nslots = 0;
     std::vector<hipEvent_t> kev;             // start/stop events around each sampling kernel
