@@ -229,7 +229,10 @@ sgpm_status sgpm_model_train(sgpm_ctx_t ctx, sgpm_graph_t g, const sgpm_pattern_
 sgpm_status sgpm_model_free(sgpm_model_t m);
 /* A proposal from given weight tables (np patterns, np x [8][32][32][32]
  * uint16 weights >= 1, indexed [step][bucket of v_0][bucket of v_{j-1}]
- * [candidate bucket], bucket = floor(log2(1 + degree)) clipped to 31). */
+ * [candidate bucket], bucket = floor(log2(1 + degree)) clipped to 31).  Steps
+ * 2..k-2 choose a bucket in proportion to (members x weight) and a uniform
+ * member of it; the last step k-1 picks uniformly (every candidate there
+ * completes exactly one match), so its rows are not used. */
 sgpm_status sgpm_model_from_tables(sgpm_ctx_t ctx, int np, const sgpm_pattern_t* patterns, const uint16_t* tables,
                                    sgpm_model_t* out);
 /* Copy table i (8*32*32*32 uint16) out of a model. */

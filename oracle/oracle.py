@@ -466,6 +466,12 @@ def exact_expectation_learned(g: OGraph, p: Plan, table):
         if int(rec.size[depth]) == 0:
             return
         cands = candidates(g, p, depth, list(rec.v)[:depth])
+        if depth == k - 1:  # the last step picks uniformly
+            for i in range(len(cands)):
+                d = list(draws) + [0] * (24 - len(draws))
+                d[depth] = r_for(i, len(cands))
+                walk(d, depth + 1, prob / len(cands))
+            return
         b0 = bucket(g, rec.v[0])
         bp = bucket(g, rec.v[depth - 1])
         w = tab[depth, b0, bp]

@@ -5,13 +5,16 @@
  * Buckets: b(v) = floor(log2(1 + deg(v))) clipped to [0, 31], from degrees.
  * Weights: an integer table w[j][b0][bp][bc] in [1, 2^16] per pattern, indexed
  * by the step j, the buckets of v_0 and v_{j-1} and the candidate's bucket.
- * Step j: S_j as in NS-prune; n_b = members of S_j in bucket b; Sigma =
+ * Step j < k-1: S_j as in NS-prune; n_b = members of S_j in bucket b; Sigma =
  * sum_b n_b w_b; walking buckets in ascending b, the bucket is the first whose
  * running sum of n_b w_b exceeds floor(Sigma * r_j / 2^64); the member is the
  * floor(n_b * r_{16+j} / 2^64)-th member of that bucket in ascending id; the
- * weight factor is Sigma / w_b (one IEEE division) and alpha' = M times the
- * factors in step order (IEEE multiplications).  Any table with w >= 1 keeps
- * the estimator unbiased (importance sampling with full support).
+ * weight factor is Sigma / w_b (one IEEE division).  The last step j = k-1
+ * picks uniformly as NS-prune does (member floor(|S_j| * r_j / 2^64), factor
+ * |S_j|): there every candidate completes exactly one match, so the uniform
+ * pick is already the zero-variance choice.  alpha' = M times the factors in
+ * step order (IEEE multiplications).  Any table with w >= 1 keeps the
+ * estimator unbiased (importance sampling with full support).
  * Exact sums: X = alpha' * 2^52 is an integer for alpha' >= 1 (rejected when
  * alpha' >= 2^76), so the NS integer statistics apply unchanged; the predicted
  * error is scale invariant and the estimate is S1 / n / 2^52.
@@ -55,6 +58,11 @@ void orc_ns_sample_learned(const orc_graph* g, const orc_plan* p, const uint16_t
         if (cnt == 0) { r->fail_step = j; free(buf); return; }
         buf = (int32_t*)realloc(buf, sizeof(int32_t) * (size_t)cnt);
         orc_candidates(g, p, j, r->v, buf);
+        if (j == p->k - 1) {  /* last step: uniform pick */
+            r->v[j] = buf[orc_mulhi(cnt, DRAW(j))];
+            a = a * (double)cnt;
+            continue;
+        }
         int bp = orc_bucket(g, r->v[j - 1]);
         const uint16_t* w = table + ((((size_t)j * 32 + (size_t)b0) * 32 + (size_t)bp) * 32);
         uint64_t nb[32] = {0};

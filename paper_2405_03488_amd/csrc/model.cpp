@@ -113,7 +113,7 @@ sgpm_status build_table(sgpm_ctx* c, const float* d_params, int pi, int k, uint1
         for (int bc = 0; bc < 32; bc++) mx = std::max(mx, sc[row * 32 + bc]);
         for (int bc = 0; bc < 32; bc++) {
             uint16_t w = 1;
-            if (j >= 2 && j < k && std::isfinite(mx)) {
+            if (j >= 2 && j + 1 < k && std::isfinite(mx)) {  // the last step picks uniformly
                 const double e = std::exp2((double)sc[row * 32 + bc] - (double)mx + 15.0);
                 w = (uint16_t)std::min(65535.0, std::max(1.0, std::nearbyint(e)));
             }
@@ -141,9 +141,19 @@ sgpm_status train(sgpm_ctx* c, sgpm_graph* g, const sgpm_pattern_t* pats, int np
     auto m = std::make_unique<sgpm_model>();
     m->ctx = c;
     m->np = np;
-    // 1. pilots and tuples
+    // 1. pilots and tuples.  A tuple is one pilot step j of pattern i: its cell
+    // (i, j, bucket of v0, bucket of v_{j-1}, bucket of v_j) and C = the product
+    // of the later set sizes on a hit, 0 on a miss -- an unbiased estimate of the
+    // number of completions through v_j (the NS-prune argument applied to the
+    // rest of the walk).  The proposal that makes the weights least variable
+    // picks candidates in proportion to their completions, so the network
+    // regresses log2 of the cell's mean C (plus 1/16, which keeps cells without
+    // completions finite), every tuple of a cell carrying the cell's target.
     std::vector<float> X;
     std::vector<float> Y;
+    std::vector<uint32_t> cell_of;
+    std::vector<double> Csum((size_t)np * TABLE, 0.0);
+    std::vector<uint32_t> Ccnt((size_t)np * TABLE, 0);
     const uint64_t N = cfg.pilot_samples;
     std::vector<sgpm_trace_rec> rec((size_t)N);
     std::vector<uint32_t> sizes((size_t)N * 8);
@@ -181,13 +191,20 @@ sgpm_status train(sgpm_ctx* c, sgpm_graph* g, const sgpm_pattern_t* pats, int np
                     Yc = 1.0;
                     for (int t = j + 1; t < p.k; t++) Yc *= (double)sz[t];
                 }
+                const int bp = bucket_host(g, R.v[j - 1]), bc = bucket_host(g, R.v[j]);
                 float x[NFEAT];
-                features(x, i, j, b0, bucket_host(g, R.v[j - 1]), bucket_host(g, R.v[j]));
+                features(x, i, j, b0, bp, bc);
                 X.insert(X.end(), x, x + NFEAT);
-                Y.push_back((float)std::log2(1.0 + Yc));
+                const uint32_t cell = (uint32_t)((size_t)i * TABLE + ((((size_t)j * 32 + b0) * 32 + bp) * 32 + bc));
+                cell_of.push_back(cell);
+                Csum[cell] += Yc;
+                Ccnt[cell] += 1;
             }
         }
     }
+    Y.resize(cell_of.size());
+    for (size_t t = 0; t < cell_of.size(); t++)
+        Y[t] = (float)std::log2(Csum[cell_of[t]] / (double)Ccnt[cell_of[t]] + 0.0625);
     m->pilot_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     const int64_t T = (int64_t)Y.size();
     m->tuples = (uint64_t)T;

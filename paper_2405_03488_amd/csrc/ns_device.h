@@ -275,8 +275,10 @@ __device__ __forceinline__ uint32_t ns_sample(const DGraph& g, const Plan& p, ui
         }
         // learned proposal: this step's weight-table row, loaded while the
         // candidates are scanned
+        // (the last step picks uniformly: every candidate completes exactly one match)
+        const bool weighted = learned && j + 1 < p.k;
         uint64_t wrow = 0;
-        if (learned && lane < 32) {
+        if (weighted && lane < 32) {
             const int32_t bp = bucket_of(*la, v[j - 1]);
             wrow = (uint64_t)la->table[(((size_t)j * 32 + (size_t)b0) * 32 + (size_t)bp) * 32 + lane];
         }
@@ -373,11 +375,14 @@ __device__ __forceinline__ uint32_t ns_sample(const DGraph& g, const Plan& p, ui
             // weighted choice reduces to a uniform member drawn with draw 16+j
             // and the factor sum / w_b is exactly |S_j|
             const bool one_bucket =
-                learned && cnt <= (uint32_t)CAP && bucket_of(*la, uni<G>(list[0])) == bucket_of(*la, uni<G>(list[cnt - 1]));
-            if (one_bucket) {
+                weighted && cnt <= (uint32_t)CAP && bucket_of(*la, uni<G>(list[0])) == bucket_of(*la, uni<G>(list[cnt - 1]));
+            if (learned && !weighted) {
+                idx = (uint32_t)__umul64hi((uint64_t)cnt, draw_at(dr, seed, s, (uint32_t)j, tag));
+                af = __dmul_rn(af, (double)cnt);
+            } else if (one_bucket) {
                 idx = (uint32_t)__umul64hi((uint64_t)cnt, draw_at(dr, seed, s, 16u + (uint32_t)j, tag));
                 af = __dmul_rn(af, (double)cnt);
-            } else if (learned && cnt <= (uint32_t)CAP) {
+            } else if (weighted && cnt <= (uint32_t)CAP) {
                 // weighted bucket, then a uniform member of it: counts n_b <= CAP
                 // and n_b w_b < 2^26, so (n_b w_b) << 32 | n_b scans as one word
                 if (lane < 32) hist[lane] = 0;
@@ -398,7 +403,7 @@ __device__ __forceinline__ uint32_t ns_sample(const DGraph& g, const Plan& p, ui
                 const uint64_t inb = __umul64hi(nbs, draw_at(dr, seed, s, 16u + (uint32_t)j, tag));
                 idx = (uint32_t)((uint64_t)cnt - upto + inb);
                 af = __dmul_rn(af, __ddiv_rn((double)sigma, (double)wbs));
-            } else if (learned) {
+            } else if (weighted) {
                 // the same when the set overflowed the list: histogram by rescanning
                 if (lane < 32) hist[lane] = 0;
 #pragma unroll

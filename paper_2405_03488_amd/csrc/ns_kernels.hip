@@ -166,7 +166,7 @@ constexpr int GMAX = 16;  // samples per group (records live in lanes 0..15)
 constexpr int REC = 16;   // words per sample record
 
 // draw index held in slot t of a sample's draws (slots 0..k-2: draws 0, 2, ..,
-// k-1; learned proposal: then draws 18, 19, ..)
+// k-1; learned proposal: then draws 18, .., 16 + k-2 of its weighted steps)
 template <int K>
 __device__ __forceinline__ uint32_t draw_of_slot(int t) {
     return t == 0 ? 0u : t <= K - 2 ? (uint32_t)(t + 1) : (uint32_t)(18 + (t - (K - 1)));
@@ -178,7 +178,7 @@ __global__ __launch_bounds__(256, SGPM_WAVE_BLOCKS_PER_CU) void ns_wave_kernel(D
                                                       unsigned long long* __restrict__ partials, int checksum,
                                                       int count_bytes, TraceArgs tr, LearnArgs la) {
     constexpr int G = 64;
-    constexpr int D = (K - 1) + (MODE == 1 ? K - 2 : 0);  // draws per sample
+    constexpr int D = (K - 1) + (MODE == 1 && K > 3 ? K - 3 : 0);  // draws per sample
     constexpr int GS = (64 / D) < GMAX ? (64 / D) : GMAX;
     const int lane = (int)(threadIdx.x & 63);
     const int wid = (int)(threadIdx.x >> 6);

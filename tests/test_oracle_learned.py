@@ -62,20 +62,33 @@ def test_hand_trace_two_buckets(O, synth):
         b0, bp = O.bucket(g, r.v[0]), O.bucket(g, r.v[1])
         assert r.v[2] in cands
         assert af == float(2 * g.m * len(cands))
-    # weight the high bucket 1000x and check the factor Sigma / w_b of a pick
+    # the wedge's only step is its last: uniform whatever the table says
     t2 = np.ones((8, 32, 32, 32), dtype=np.uint16)
     t2[:, :, :, 4:] = 1000
-    seen = 0
     for s in range(300):
         r, af = O.sample_learned(g, p, t2, 9, 0, s)
+        if r.hit:
+            assert af == float(2 * g.m * len(O.candidates(g, p, 2, list(r.v)[:2])))
+    # a 3-star's step 2 is weighted: the low buckets 1000x, factor Sigma / w_b
+    # (centre 0: S_2 holds the hub and a low-degree vertex); its last step is
+    # uniform, factor |S_3|
+    t3 = np.ones((8, 32, 32, 32), dtype=np.uint16)
+    t3[:, :, :, :4] = 1000
+    k, e = synth.pattern("3-star")
+    p = O.compile_plan(k, e)
+    M = g.m if p.oriented else 2 * g.m
+    seen = 0
+    for s in range(4000):
+        r, af = O.sample_learned(g, p, t3, 9, 0, s)
         if not r.hit:
             continue
         cands = O.candidates(g, p, 2, list(r.v)[:2])
-        ws = [1000 if O.bucket(g, x) >= 4 else 1 for x in cands]
+        ws = [1 if O.bucket(g, x) >= 4 else 1000 for x in cands]
         sigma = sum(ws)
-        wb = 1000 if O.bucket(g, r.v[2]) >= 4 else 1
-        assert af == float(2 * g.m) * (sigma / wb)
-        seen += 1
+        wb = 1 if O.bucket(g, r.v[2]) >= 4 else 1000
+        last = len(O.candidates(g, p, 3, list(r.v)[:3]))
+        assert af == float(M) * (sigma / wb) * last
+        seen += 1 if len(set(ws)) > 1 else 0
     assert seen > 0
 
 
