@@ -394,20 +394,28 @@ sgpm_status ns_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_op
             if (nx <= queued || (o.mode == SGPM_MODE_FIXED_N && queued > 0)) break;
             if (lanes == 0 && nx - queued >= (1ull << 19)) {
                 if (!inflight.empty()) break;  // tune once the queue has drained
-                // autotune on the first long window: split it into two rounds over the
-                // candidate lane counts and keep the fastest per sample, each
+                // autotune on the first long window: pieces of it go to the
+                // candidate lane counts from wide to narrow, two rounds, each
                 // candidate judged by its better piece (the first launch of a
-                // kernel pays for loading its code and for cold caches).  Every
-                // sample is still drawn exactly once, so results are unchanged.
+                // kernel pays for loading its code and for cold caches); a
+                // narrower count is tried only while narrowing has paid off, so
+                // a slow one (one lane per sample at a hub's row) costs one
+                // small piece at most.  The rest of the window runs at the
+                // winner.  Every sample is still drawn exactly once, so results
+                // are unchanged.
                 static const int cand[4] = {64, 16, 4, 1};
-                constexpr int kPieces = 8;
+                constexpr int kPieces = 16;
                 const uint64_t len = nx - queued;
                 float best_per[4] = {0, 0, 0, 0};
                 bool seen[4] = {false, false, false, false};
                 size_t used = 0;
-                for (int i = 0; i < kPieces; i++) {
-                    const uint64_t a = queued + len * (uint64_t)i / kPieces, b = queued + len * (uint64_t)(i + 1) / kPieces;
+                int ntry = 2;  // candidates in play
+                uint64_t done_to = queued;
+                for (int i = 0; i < 8; i++) {
                     const int ci = i % 4;
+                    if (ci >= ntry) continue;
+                    const uint64_t a = done_to, b = queued + len * (uint64_t)(used + 1) / kPieces;
+                    done_to = b;
                     const size_t slot = 2 + used++;
                     status = enqueue_range(c, g, p, o, a, b, cand[ci], slot, tr, count_bytes, la, len);
                     if (status != SGPM_OK) return status;
@@ -421,6 +429,8 @@ sgpm_status ns_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_op
                                      cand[ci], ms, (unsigned long long)(b - a), (double)(b - a) / (ms * 1e-3));
                     if (!seen[ci] || per < best_per[ci]) best_per[ci] = per;
                     seen[ci] = true;
+                    // the narrower candidate won its first piece: try the next one too
+                    if (i < 4 && ci >= 1 && ci + 1 == ntry && ntry < 4 && best_per[ci] < best_per[ci - 1]) ntry++;
                 }
                 int best = 64;
                 float best_ms = 0;
@@ -431,6 +441,11 @@ sgpm_status ns_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_op
                     }
                 lanes = best;
                 c->ns_tuned[tune_key] = best;
+                if (done_to < nx) {  // the rest of the window at the winner
+                    const size_t slot = 2 + used++;
+                    status = enqueue_range(c, g, p, o, done_to, nx, best, slot, tr, count_bytes, la, len);
+                    if (status != SGPM_OK) return status;
+                }
                 inflight.push_back(Win{queued, nx, 2, used});
                 queued = nx;
                 break;

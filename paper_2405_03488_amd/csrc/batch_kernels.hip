@@ -191,62 +191,103 @@ __device__ __attribute__((noinline)) void complete_window(const BatchQuery& Q, B
     }
 }
 
-// One tile of samples, one sample per wave at a time.  Exact sums are spread
-// over the lanes as in the window kernel (lanes 0-3: digit sums of X, 8-15: digit
-// columns of X^2, 20: hits, 21: checksum, 23: overflow); the lane's value
-// is returned together with the window column it belongs to (-1: none).
-__device__ __forceinline__ unsigned long long run_tile(const BatchQuery& Q, uint64_t s0, uint64_t s1, int32_t* list,
-                                                       int& field) {
+// One tile of samples, one sample per wave at a time, in groups of up to 16
+// as in the window kernel: the group's Philox draws are evaluated in parallel
+// lanes and read back with readlane, each sample leaves a record in LDS, and
+// lane q of the group epilogue hashes record q and adds the digit columns of X
+// and X^2 to the wave's LDS sums (0-3 digits of S1, 4-11 columns of S2, 12
+// checksum, 14 hits), which the caller adds to the query's window columns.
+constexpr int BGMAX = 16, BREC = 16;
+
+__device__ __forceinline__ void run_tile(const BatchQuery& Q, uint64_t s0, uint64_t s1, int32_t* list, uint32_t* rec,
+                                         unsigned long long* wsum, uint64_t& ovf) {
     const int lane = (int)(threadIdx.x & 63);
-    uint64_t acc = 0, ovf = 0;
-    for (uint64_t s = s0; s < s1; ++s) {
-        int32_t v[8];
-        uint64_t alo, ahi, b = 0, ov = 0;
-        const uint32_t st = ns_sample<64>(Q.g, Q.p, Q.seed, Q.tag, s, v, alo, ahi, ov, b, false, list);
-        ovf |= ov;
-        if (st != 0xFFu) {
-            alo = 0;
-            ahi = 0;
+    const int K = Q.p.k;
+    const int D = K - 1;  // draws per sample: 0, 2, .., k-1
+    const int GS = (64 / D) < BGMAX ? (64 / D) : BGMAX;
+    for (uint64_t gb = s0; gb < s1; gb += (uint64_t)GS) {
+        const int n = (int)min((uint64_t)GS, s1 - gb);
+        Draws dr;
+        {
+            const int q = lane / D, t = lane - q * D;
+            uint64_t r = 0;
+            if (q < n) r = philox_r64(Q.seed, gb + (uint64_t)q, t == 0 ? 0u : (uint32_t)(t + 1), Q.tag);
+            dr.lo = (uint32_t)r;
+            dr.hi = (uint32_t)(r >> 32);
+            dr.k1 = K - 1;
+            dr.base = 0;
         }
-        uint64_t h = fmix64(s ^ 0x9E3779B97F4A7C15ull);
-        h = fmix64(h ^ (uint64_t)st);
+        for (int q = 0; q < n; ++q) {
+            const uint64_t s = gb + (uint64_t)q;
+            dr.base = q * D;
+            int32_t v[8];
+            uint64_t alo, ahi, b = 0, ov = 0;
+            const uint32_t st = ns_sample<64>(Q.g, Q.p, Q.seed, Q.tag, s, v, alo, ahi, ov, b, false, list, nullptr,
+                                              nullptr, nullptr, &dr);
+            ovf |= ov;
+            if (st != 0xFFu) {
+                alo = 0;
+                ahi = 0;
+            }
+            if (lane < 13) {  // record: 0-7 the walk, 8 the status, 9-12 X
+                uint32_t w = 0;
 #pragma unroll
-        for (int i = 0; i < 8; ++i)
-            if (i < Q.p.k) h = fmix64(h ^ (uint64_t)(uint32_t)v[i]);
-        h = fmix64(h ^ alo);
-        h = fmix64(h ^ ahi);
-        const uint32_t d[4] = {(uint32_t)alo, (uint32_t)(alo >> 32), (uint32_t)ahi, (uint32_t)(ahi >> 32)};
-        uint64_t add = 0;
-        if (lane < 4) {
-            add = d[lane & 3];
-        } else if (lane >= 8 && lane < 16 && (ahi | alo) != 0) {
-            const int col = lane - 8;
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    const uint64_t pr = (uint64_t)d[a] * (uint64_t)d[c];
-                    if (a + c == col) add += pr & 0xFFFFFFFFull;
-                    if (a + c + 1 == col) add += pr >> 32;
-                }
-        } else if (lane == 20) {
-            add = st == 0xFFu ? 1 : 0;
-        } else if (lane == 21) {
-            add = h;
+                for (int i = 0; i < 8; ++i)
+                    if (lane == i) w = (uint32_t)v[i];
+                if (lane == 8) w = st;
+                if (lane == 9) w = (uint32_t)alo;
+                if (lane == 10) w = (uint32_t)(alo >> 32);
+                if (lane == 11) w = (uint32_t)ahi;
+                if (lane == 12) w = (uint32_t)(ahi >> 32);
+                rec[q * BREC + lane] = w;
+            }
         }
-        acc += add;
+        __builtin_amdgcn_wave_barrier();
+        if (lane < n) {
+            const uint32_t* r = rec + lane * BREC;
+            const uint32_t st = r[8];
+            uint32_t d[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) d[i] = r[9 + i];
+            uint64_t h = fmix64((gb + (uint64_t)lane) ^ 0x9E3779B97F4A7C15ull);
+            h = fmix64(h ^ (uint64_t)st);
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                if (i < K) h = fmix64(h ^ (uint64_t)r[i]);
+            h = fmix64(h ^ ((uint64_t)d[1] << 32 | d[0]));
+            h = fmix64(h ^ ((uint64_t)d[3] << 32 | d[2]));
+            atomicAdd(&wsum[12], (unsigned long long)h);
+            if (st == 0xFFu) {
+                uint64_t c2[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const uint64_t pr = (uint64_t)d[a] * (uint64_t)d[e];
+                        c2[a + e] += pr & 0xFFFFFFFFull;
+                        if (a + e + 1 < 8) c2[a + e + 1] += pr >> 32;
+                    }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) atomicAdd(&wsum[i], (unsigned long long)d[i]);
+#pragma unroll
+                for (int i = 0; i < 8; ++i) atomicAdd(&wsum[4 + i], (unsigned long long)c2[i]);
+                atomicAdd(&wsum[14], 1ull);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
     }
-    if (lane == 23) acc = ovf;
-    field = lane < 4 ? PF_S1 + lane
-                     : (lane >= 8 && lane < 16) ? PF_S2 + (lane - 8)
-                     : lane == 20 ? PF_HITS : lane == 21 ? PF_CSUM : lane == 23 ? PF_OVF : -1;
-    return acc;
 }
 
 __global__ __launch_bounds__(256, 8) void batch_kernel(const BatchQuery* __restrict__ queries, BatchState* __restrict__ states,
                                                     int nq, unsigned long long* __restrict__ active) {
     const int lane = (int)(threadIdx.x & 63);
+    const int wid = (int)(threadIdx.x >> 6);
     __shared__ int32_t s_list[LDS_WORDS];
+    __shared__ uint32_t s_rec[4][BGMAX * BREC];
+    __shared__ unsigned long long s_wsum[4][16];
+    unsigned long long* wsum = s_wsum[wid];
+    if (lane < 16) wsum[lane] = 0ull;
+    __builtin_amdgcn_wave_barrier();
     const int wave = (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
     int start = wave % nq;
     // per-wave cache of the last window bounds looked up
@@ -288,10 +329,19 @@ __global__ __launch_bounds__(256, 8) void batch_kernel(const BatchQuery* __restr
         const BatchQuery& Q = queries[q];
         const uint64_t T = (uint64_t)Q.tile;
         const uint64_t s0 = cws + t * T, s1 = min(s0 + T, cwe);
-        int field = -1;
-        const unsigned long long val = run_tile(Q, s0, s1, s_list + (threadIdx.x >> 6) * (LDS_WORDS / 4), field);
+        uint64_t ovf = 0;
+        run_tile(Q, s0, s1, s_list + wid * (LDS_WORDS / 4), s_rec[wid], wsum, ovf);
         BatchState& S = states[q];
-        if (field >= 0 && val) atomicAdd(&S.win[field], val);
+        // the tile's sums into the query's window columns
+        if (lane < 15) {
+            const unsigned long long val = wsum[lane];
+            wsum[lane] = 0ull;
+            const int field = lane < 4 ? PF_S1 + lane : lane < 12 ? PF_S2 + (lane - 4) : lane == 12 ? PF_CSUM
+                            : lane == 14 ? PF_HITS : -1;
+            if (field >= 0 && val) atomicAdd(&S.win[field], val);
+        }
+        if (lane == 15 && ovf) atomicAdd(&S.win[PF_OVF], (unsigned long long)ovf);
+        __builtin_amdgcn_wave_barrier();
         __threadfence();
         if (lane == 0) {
             const unsigned long long old = atomicAdd(&S.done, (unsigned long long)(s1 - s0));

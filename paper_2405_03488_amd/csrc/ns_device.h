@@ -120,7 +120,8 @@ __device__ __forceinline__ uint64_t group_ballot(bool pred, uint64_t gmask) {
 // cursor c only moves forward: entries before it are below every x still to
 // come.  G = 1: galloping search.  G > 1: the group loads G consecutive row
 // entries, every lane binary-searches its x among them through shuffles, and
-// the window slides until no active lane's x lies beyond it.
+// the window slides until no active lane's x lies beyond it; across a long gap
+// (a hub's row against a few candidates) it jumps by a G-ary search.
 template <int G>
 __device__ __forceinline__ bool member(const int32_t* __restrict__ R, int32_t rl, int32_t& c, int32_t x, bool act,
                                        int32_t xmax, int gbase, int gl, uint64_t gmask) {
@@ -144,11 +145,29 @@ __device__ __forceinline__ bool member(const int32_t* __restrict__ R, int32_t rl
             const bool res = pending && x <= bmax;
             if (res) found = pos < G && bq == x;
             pending = pending && !res;
-            if (group_ballot<G>(pending, gmask) == 0) {
+            const uint64_t pend = group_ballot<G>(pending, gmask);
+            if (pend == 0) {
                 c += (int32_t)__popcll(group_ballot<G>(b < xmax, gmask));
                 break;
             }
+            const bool below = group_ballot<G>(res, gmask) == 0;  // the window lies below every pending x
             c += G;
+            if (below && rl - c > 4 * G) {
+                // G-ary search for the first entry >= the smallest pending x: each
+                // round probes G evenly spaced entries and keeps the gap that
+                // holds it, so a long row costs a few round trips, not one per
+                // G entries.  Entries skipped are below every x still pending.
+                const int32_t xmin = uni<G>(__shfl(x, __ffsll((unsigned long long)pend) - 1));
+                int32_t lo = c, hi = rl;  // the entry sought lies in [lo, hi]
+                while (hi - lo > G) {
+                    const int32_t step = (hi - lo) / G;
+                    const int32_t pv = R[lo + (gl + 1) * step - 1];
+                    const int nb = (int)__popcll(group_ballot<G>(pv < xmin, gmask));
+                    if (nb < G) hi = lo + (nb + 1) * step - 1;
+                    lo += nb * step;
+                }
+                c = lo;
+            }
             b = (c + gl < rl) ? R[c + gl] : BIG;
         }
         return found;
