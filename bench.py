@@ -64,6 +64,28 @@ def measured_traffic(runs, launches):
     return total / max(1, launches)
 
 
+def other_legs(S, ctx, g, pats, queries, eps):
+    """The rest of the hot path on the same graph: the GS engine (colour
+    sparsification + exact count, two colourings at c = 16), the loose-mode
+    choice between NS and GS at eps, and the MLP kernels' MFMA throughput."""
+    out = {"gs": {}, "hybrid": {}}
+    for q in queries:
+        t0 = time.perf_counter()
+        r, _ = S.sgpm_estimate(ctx, g, pats[q], S.sgpm_options_default(mode=S.MODE_GS, eps=eps, colours=16,
+                                                                        gs_reps_max=2, seed=5))
+        out["gs"][q] = {"colourings": int(r.n_samples), "estimate": r.estimate, "wall_s": time.perf_counter() - t0,
+                        "count_kernel_s": r.seconds_kernel}
+        r, _ = S.sgpm_estimate(ctx, g, pats[q], S.sgpm_options_default(mode=S.MODE_HYBRID, eps=eps, colours=16,
+                                                                        seed=6))
+        out["hybrid"][q] = {"scheme": "GS" if r.scheme == S.SCHEME_GS else "NS", "ns_cone_s": [r.pred_ns_lo,
+                                                                                             r.pred_ns_hi],
+                            "gs_pred_s": r.pred_gs, "pilot_s": r.seconds_pilot, "total_s": r.seconds_total}
+    out["mlp_forward_1M_rows"] = S.sgpm_probe_mlp(ctx, 1 << 20, 10)
+    out["mlp_train_batch_16K_rows"] = S.sgpm_probe_mlp(ctx, 1 << 14, 20)
+    log(f"gs/hybrid/mlp: {json.dumps(out)}")
+    return out
+
+
 def learned_leg(S, ctx, g, pats, queries, eps, steps, lanes):
     """Learned proposal against uniform NS on the same graph: train the MLP
     proposal on the GPU (pilot samples of every query on their own Philox
@@ -198,6 +220,7 @@ def main():
     achieved = alg_bytes / kernel_s / 1e9 if kernel_s > 0 else 0.0
 
     learned = None if args.no_learned else learned_leg(S, ctx, g, pats, queries, args.eps, args.steps, lanes)
+    other = None if args.no_learned else other_legs(S, ctx, g, pats, queries, args.eps)
 
     probes = None
     if not args.no_probes:
@@ -283,6 +306,7 @@ def main():
                      "measured": probes},
         "cpu_baseline": cpu,
         "learned_vs_uniform": learned,
+        "gs_hybrid_mlp": other,
     }
     print(json.dumps(line), flush=True)
 

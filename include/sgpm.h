@@ -256,6 +256,11 @@ sgpm_status sgpm_probe_copy(sgpm_ctx_t ctx, uint64_t bytes, int iters, double* g
  * group; *gbs = segment bytes read per second.  The measured gather roofline. */
 sgpm_status sgpm_probe_gather(sgpm_ctx_t ctx, uint64_t working_set_bytes, int segment_bytes, int rounds, double* gbs);
 
+/* The MLP kernels on N random device-resident rows, iters launches each:
+ * out4 = {forward ms, forward TFLOP/s, gradient ms, gradient TFLOP/s} (2 FLOPs
+ * per multiply-add of the three layers; 3x that for forward + backward). */
+sgpm_status sgpm_probe_mlp(sgpm_ctx_t ctx, int64_t N, int iters, double* out4);
+
 /* ------------------------------------------------------------------ host-only utilities */
 /* These run the host parts of the library without a device, so they can be
  * checked on any machine. */

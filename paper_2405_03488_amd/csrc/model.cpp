@@ -391,4 +391,54 @@ sgpm_status sgpm_mlp_grad(sgpm_ctx_t c, const float* params, const float* X, con
     return SGPM_OK;
 }
 
+// Times the MLP forward and gradient kernels on N device-resident rows
+// (iters launches each, HIP events): out4 = {forward ms, forward TFLOP/s,
+// gradient ms, gradient TFLOP/s}, FLOPs counted as 2 per multiply-add of the
+// three layers (x3 for forward + backward).
+sgpm_status sgpm_probe_mlp(sgpm_ctx_t c, int64_t N, int iters, double* out4) {
+    if (!c || N < 64 || iters < 1 || !out4) return fail(c, SGPM_EINVAL, "bad arguments");
+    HIP_TRY(c, hipSetDevice(c->dev));
+    const int NP = mlp_nparams();
+    const int64_t waves = ((N + 63) / 64 + 3) / 4 * 4;
+    std::vector<float> hp((size_t)NP), hx((size_t)N * NFEAT), hy((size_t)N);
+    uint64_t rs = 12345;
+    for (auto& v : hp) v = (float)(gauss(rs) * 0.1);
+    for (auto& v : hx) v = (float)gauss(rs);
+    for (auto& v : hy) v = (float)gauss(rs);
+    Dev dP, dX, dY, dS, dgp, dg;
+    HIP_TRY(c, hipMalloc(&dP.p, sizeof(float) * (size_t)NP));
+    HIP_TRY(c, hipMalloc(&dX.p, sizeof(float) * hx.size()));
+    HIP_TRY(c, hipMalloc(&dY.p, sizeof(float) * hy.size()));
+    HIP_TRY(c, hipMalloc(&dS.p, sizeof(float) * (size_t)N));
+    HIP_TRY(c, hipMalloc(&dgp.p, sizeof(float) * (size_t)NP * (size_t)waves));
+    HIP_TRY(c, hipMalloc(&dg.p, sizeof(float) * (size_t)NP));
+    HIP_TRY(c, hipMemcpy(dP.p, hp.data(), sizeof(float) * hp.size(), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(dX.p, hx.data(), sizeof(float) * hx.size(), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(dY.p, hy.data(), sizeof(float) * hy.size(), hipMemcpyHostToDevice));
+    hipEvent_t e[4];
+    for (auto& ev : e) HIP_TRY(c, hipEventCreate(&ev));
+    HIP_TRY(c, mlp_forward((const float*)dP.p, (const float*)dX.p, N, (float*)dS.p, c->st));  // warm
+    HIP_TRY(c, hipEventRecord(e[0], c->st));
+    for (int i = 0; i < iters; i++) HIP_TRY(c, mlp_forward((const float*)dP.p, (const float*)dX.p, N, (float*)dS.p, c->st));
+    HIP_TRY(c, hipEventRecord(e[1], c->st));
+    HIP_TRY(c, mlp_grad((const float*)dP.p, (const float*)dX.p, (const float*)dY.p, N, (float*)dgp.p, (float*)dg.p,
+                        c->st));
+    HIP_TRY(c, hipEventRecord(e[2], c->st));
+    for (int i = 0; i < iters; i++)
+        HIP_TRY(c, mlp_grad((const float*)dP.p, (const float*)dX.p, (const float*)dY.p, N, (float*)dgp.p,
+                            (float*)dg.p, c->st));
+    HIP_TRY(c, hipEventRecord(e[3], c->st));
+    HIP_TRY(c, hipStreamSynchronize(c->st));
+    float f = 0, b = 0;
+    HIP_TRY(c, hipEventElapsedTime(&f, e[0], e[1]));
+    HIP_TRY(c, hipEventElapsedTime(&b, e[2], e[3]));
+    for (auto& ev : e) (void)hipEventDestroy(ev);
+    const double flops_row = 2.0 * (16.0 * 64 + 64.0 * 64 + 64.0);
+    out4[0] = f / iters;
+    out4[1] = flops_row * (double)N / (out4[0] * 1e-3) / 1e12;
+    out4[2] = b / iters;
+    out4[3] = 3.0 * flops_row * (double)N / (out4[2] * 1e-3) / 1e12;
+    return SGPM_OK;
+}
+
 }  // extern "C"

@@ -119,6 +119,7 @@ def lib():
             "sgpm_mlp_grad": ([P, P, P, P, C.c_int64, P], st),
             "sgpm_probe_copy": ([P, C.c_uint64, C.c_int, C.POINTER(C.c_double)], st),
             "sgpm_probe_gather": ([P, C.c_uint64, C.c_int, C.c_int, C.POINTER(C.c_double)], st),
+            "sgpm_probe_mlp": ([P, C.c_int64, C.c_int, P], st),
             "sgpm_host_canonicalise": ([C.c_int64, P, C.c_int, P, C.c_uint32, P, P, P, P], st),
             "sgpm_host_plan": ([C.c_int, C.c_int, P, C.c_int, P, P, P, P, P, P, P], st),
             "sgpm_host_normal_quantile": ([C.c_double], C.c_double),
@@ -141,7 +142,7 @@ EXPORTED = ["sgpm_create", "sgpm_destroy", "sgpm_last_error", "sgpm_device_count
             "sgpm_pattern_free", "sgpm_options_default", "sgpm_estimate", "sgpm_estimate_counted",
             "sgpm_estimate_batch", "sgpm_exact_count", "sgpm_gs_sparsify", "sgpm_model_train", "sgpm_model_free",
             "sgpm_model_from_tables", "sgpm_model_table", "sgpm_model_info", "sgpm_mlp_forward", "sgpm_mlp_grad",
-            "sgpm_probe_copy", "sgpm_probe_gather", "sgpm_host_canonicalise", "sgpm_host_plan", "sgpm_host_normal_quantile", "sgpm_host_predicted_error",
+            "sgpm_probe_copy", "sgpm_probe_gather", "sgpm_probe_mlp", "sgpm_host_canonicalise", "sgpm_host_plan", "sgpm_host_normal_quantile", "sgpm_host_predicted_error",
             "sgpm_host_next_window", "sgpm_host_hybrid_choice"]
 
 
@@ -340,6 +341,14 @@ def sgpm_probe_copy(ctx, nbytes, iters=10) -> float:
     v = C.c_double()
     _check(ctx, lib().sgpm_probe_copy(ctx, nbytes, iters, C.byref(v)))
     return v.value
+
+
+def sgpm_probe_mlp(ctx, N, iters=20):
+    """{'fwd_ms', 'fwd_tflops', 'grad_ms', 'grad_tflops'} of the MLP kernels on N rows."""
+    out = np.zeros(4, dtype=np.float64)
+    _check(ctx, lib().sgpm_probe_mlp(ctx, N, iters, out.ctypes.data))
+    return {"fwd_ms": float(out[0]), "fwd_tflops": float(out[1]), "grad_ms": float(out[2]),
+            "grad_tflops": float(out[3])}
 
 
 def sgpm_probe_gather(ctx, working_set_bytes, segment_bytes, rounds=8) -> float:
