@@ -232,7 +232,11 @@ __device__ __forceinline__ uint64_t draw_at(const Draws* dr, uint64_t seed, uint
            (uint32_t)__builtin_amdgcn_readlane((int)dr->lo, l);
 }
 
-template <int G, int KMAX = 8>
+// CLQ: the plan is known to be the k-clique's (connect[j] = upper[j] = all
+// earlier positions, no disconnect or lower bounds, oriented first edge, S_j
+// filtered from S_{j-1} from j = 3 on), so every plan test folds at compile
+// time; the caller checks the plan before choosing it.
+template <int G, int KMAX = 8, bool CLQ = false>
 __device__ __forceinline__ uint32_t ns_sample(const DGraph& g, const Plan& p, uint64_t seed, uint32_t tag, uint64_t s,
                                              int32_t (&v)[8], uint64_t& alo, uint64_t& ahi, uint64_t& ovf,
                                              uint64_t& bytes, bool count_bytes, int32_t* list,
@@ -247,7 +251,9 @@ __device__ __forceinline__ uint32_t ns_sample(const DGraph& g, const Plan& p, ui
 
 #pragma unroll
     for (int i = 0; i < 8; ++i) v[i] = -1;
-    const uint64_t M = p.oriented ? (uint64_t)g.m : 2ull * (uint64_t)g.m;
+    const bool oriented = CLQ || p.oriented;
+    const int pk = CLQ ? KMAX : p.k;
+    const uint64_t M = oriented ? (uint64_t)g.m : 2ull * (uint64_t)g.m;
     const int32_t* rp[8];
     int32_t rl[8];
 #pragma unroll
@@ -257,7 +263,7 @@ __device__ __forceinline__ uint32_t ns_sample(const DGraph& g, const Plan& p, ui
     }
     {
         const uint64_t e = __umul64hi(M, draw_at(dr, seed, s, 0, tag));
-        if (p.oriented) {
+        if (oriented) {
             const int2 pr = g.epair[e];
             v[0] = pr.x;
             v[1] = pr.y;
@@ -284,8 +290,11 @@ __device__ __forceinline__ uint32_t ns_sample(const DGraph& g, const Plan& p, ui
 
 #pragma unroll
     for (int j = 2; j < KMAX; ++j) {
-        if (j >= p.k) break;
-        const uint32_t conn = p.connect[j], disc = p.disconnect[j], up = p.upper[j], lw = p.lower[j];
+        if (j >= pk) break;
+        const uint32_t conn = CLQ ? (1u << j) - 1u : (uint32_t)p.connect[j];
+        const uint32_t disc = CLQ ? 0u : (uint32_t)p.disconnect[j];
+        const uint32_t up = CLQ ? (1u << j) - 1u : (uint32_t)p.upper[j];
+        const uint32_t lw = CLQ ? 0u : (uint32_t)p.lower[j];
         int32_t lo = -1, hi = BIG;
 #pragma unroll
         for (int i = 0; i < j; ++i) {
@@ -295,7 +304,7 @@ __device__ __forceinline__ uint32_t ns_sample(const DGraph& g, const Plan& p, ui
         // learned proposal: this step's weight-table row, loaded while the
         // candidates are scanned
         // (the last step picks uniformly: every candidate completes exactly one match)
-        const bool weighted = learned && j + 1 < p.k;
+        const bool weighted = learned && j + 1 < pk;
         uint64_t wrow = 0;
         if (weighted && lane < 32) {
             const int32_t bp = bucket_of(*la, v[j - 1]);
@@ -326,13 +335,13 @@ __device__ __forceinline__ uint32_t ns_sample(const DGraph& g, const Plan& p, ui
         }
         // Reuse: when step j's constraints contain step j-1's, S_j is the part
         // of S_{j-1} (already in `list`) that meets the extra constraints.
-        const bool reuse = (j >= 3) && p.reuse[j] && prevcnt >= 0;
+        const bool reuse = (j >= 3) && (CLQ || p.reuse[j]) && prevcnt >= 0;
         uint32_t need_conn, need_disc, excl;
         const int32_t* src;
         int32_t slen, start;
         if (reuse) {
-            need_conn = conn & ~(uint32_t)p.connect[j - 1];
-            need_disc = disc & ~(uint32_t)p.disconnect[j - 1];
+            need_conn = conn & ~(CLQ ? (1u << (j - 1)) - 1u : (uint32_t)p.connect[j - 1]);
+            need_disc = CLQ ? 0u : disc & ~(uint32_t)p.disconnect[j - 1];
             excl = (1u << (j - 1)) & ~conn;
             src = list;
             slen = prevcnt;
@@ -481,7 +490,7 @@ __device__ __forceinline__ uint32_t ns_sample(const DGraph& g, const Plan& p, ui
             return (uint32_t)j;
         }
         v[j] = pick;
-        if (j + 1 < p.k) {
+        if (j + 1 < pk) {
             const int64_t bj = g.off[pick], ej = g.off[pick + 1];
             rp[j] = g.nbr + bj;
             rl[j] = (int32_t)(ej - bj);

@@ -172,7 +172,7 @@ __device__ __forceinline__ uint32_t draw_of_slot(int t) {
     return t == 0 ? 0u : t <= K - 2 ? (uint32_t)(t + 1) : (uint32_t)(18 + (t - (K - 1)));
 }
 
-template <int MODE, int K>
+template <int MODE, int K, bool CLQ>
 __global__ __launch_bounds__(256, SGPM_WAVE_BLOCKS_PER_CU) void ns_wave_kernel(DGraph g, Plan p, uint64_t seed, uint32_t tag, uint64_t s0,
                                                       uint64_t s1, int spl, unsigned long long* __restrict__ ticket,
                                                       unsigned long long* __restrict__ partials, int checksum,
@@ -235,8 +235,9 @@ __global__ __launch_bounds__(256, SGPM_WAVE_BLOCKS_PER_CU) void ns_wave_kernel(D
                 int32_t v[8];
                 uint64_t alo, ahi, b = 0, ov = 0;
                 uint32_t sz[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-                const uint32_t st = ns_sample<G, K>(g, p, seed, tag, s, v, alo, ahi, ov, b, count_bytes != 0, list,
-                                                    MODE == 1 ? &lal : nullptr, hist, MODE == 2 ? sz : nullptr, &dr);
+                const uint32_t st = ns_sample<G, K, CLQ>(g, p, seed, tag, s, v, alo, ahi, ov, b, count_bytes != 0,
+                                                         list, MODE == 1 ? &lal : nullptr, hist,
+                                                         MODE == 2 ? sz : nullptr, &dr);
                 ovf |= ov;
                 if (st != 0xFFu) {
                     alo = 0;
@@ -391,15 +392,33 @@ hipError_t launch_fill_u64(unsigned long long* p, uint64_t n, unsigned long long
 
 // one-sample-per-wave kernels, specialised on the pattern size so only the
 // steps a pattern has are compiled into its kernel
+
+// the plan is the k-clique's: every earlier position connected and above the
+// new one, no disconnect or lower bounds, S_j inside S_{j-1} from j = 3
+bool plan_is_clique(const Plan& p) {
+    if (!p.oriented || p.k < 3) return false;
+    for (int j = 1; j < p.k; ++j) {
+        const uint32_t all = (1u << j) - 1u;
+        if (p.connect[j] != all || p.upper[j] != all || p.disconnect[j] != 0 || p.lower[j] != 0) return false;
+        if (j >= 3 && !p.reuse[j]) return false;
+    }
+    return true;
+}
+
 template <int MODE>
 hipError_t launch_wave_mode(const DGraph& g, const Plan& p, uint64_t seed, uint32_t tag, uint64_t s0, uint64_t s1,
                             const LaunchCfg& cfg, unsigned long long* ticket, unsigned long long* partials,
                             int checksum, int count_bytes, const TraceArgs& tr, const LearnArgs& la, hipStream_t st) {
     const dim3 grid((unsigned)cfg.blocks), block(256);
+    const bool clq = MODE != 2 && plan_is_clique(p);
 #define SGPM_WAVE_CASE(KK)                                                                                        \
     case KK:                                                                                                      \
-        hipLaunchKernelGGL((ns_wave_kernel<MODE, KK>), grid, block, 0, st, g, p, seed, tag, s0, s1, cfg.spl, ticket, \
-                           partials, checksum, count_bytes, tr, la);                                              \
+        if (clq && KK >= 3 && KK <= 6)                                                                            \
+            hipLaunchKernelGGL((ns_wave_kernel<MODE, KK, KK >= 3 && KK <= 6>), grid, block, 0, st, g, p, seed, tag, s0, \
+                               s1, cfg.spl, ticket, partials, checksum, count_bytes, tr, la);                     \
+        else                                                                                                      \
+            hipLaunchKernelGGL((ns_wave_kernel<MODE, KK, false>), grid, block, 0, st, g, p, seed, tag, s0, s1,    \
+                               cfg.spl, ticket, partials, checksum, count_bytes, tr, la);                         \
         break;
     switch (p.k) {
         SGPM_WAVE_CASE(2)
@@ -463,7 +482,7 @@ int ns_blocks_per_cu(int lanes) {
         case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ns_window_kernel<1>, 256, 0); break;
         case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ns_window_kernel<4>, 256, 0); break;
         case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ns_window_kernel<16>, 256, 0); break;
-        case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ns_wave_kernel<0, 8>, 256, 0); break;
+        case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ns_wave_kernel<0, 8, false>, 256, 0); break;
         default: break;
     }
     if (e != hipSuccess || nb < 1) nb = 2;
