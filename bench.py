@@ -126,6 +126,120 @@ def learned_leg(S, ctx, g, pats, queries, eps, steps, lanes):
     return out
 
 
+def load_graph(S, synth, ctx, name, n, pairs_fn):
+    t0 = time.time()
+    pairs = pairs_fn()
+    log(f"{name}: {len(pairs)} generated pairs in {time.time() - t0:.1f}s")
+    off, nbr = synth.pairs_to_csr(n, pairs)
+    del pairs
+    g = S.sgpm_graph_from_csr(ctx, n, off, nbr)
+    gn, gm, md, _ = S.sgpm_graph_stats(g)
+    log(f"{name}: n={gn} m={gm} maxdeg={md}, resident after {time.time() - t0:.1f}s")
+    return g, {"name": name, "n": gn, "m": gm, "max_degree": md, "build_s": time.time() - t0}
+
+
+def workload_c3(S, synth, args):
+    """24 queries (the six vertex-induced 4-vertex motifs, the induced 3-path
+    and the triangle on three Chung-Lu graphs, gamma 2.1, average degree 32,
+    2^18, 2^20 and 2^22 vertices), each to eps at 95 %: the sum of solo runs
+    against one persistent batched launch (results must be identical)."""
+    ctx = S.sgpm_create(0)
+    graphs, info = [], []
+    for lg in (18, 20, 22):
+        g, gi = load_graph(S, synth, ctx, f"chung-lu 2^{lg}", 1 << lg,
+                           lambda lg=lg: synth.chung_lu_pairs(1 << lg, 32, 2.1, lg))
+        graphs.append(g)
+        info.append(gi)
+    motifs = [("3-star", 1), ("4-path", 1), ("tailed-triangle", 1), ("4-cycle", 1), ("diamond", 1), ("4-clique", 1),
+              ("wedge", 1), ("triangle", 0)]
+    qs = [(g, S.sgpm_pattern_create(ctx, *synth.pattern(m), ind), m, gi) for gi, g in enumerate(graphs)
+          for m, ind in motifs]
+    cap = 1 << 28
+
+    def opts(i, seed):
+        return S.sgpm_options_default(eps=args.eps, seed=seed + i, query_tag=i, checksum=1, max_samples=cap)
+
+    for i, (g, p, m, gi) in enumerate(qs):  # tune lanes per query (cached per graph and plan)
+        S.sgpm_estimate(ctx, g, p, opts(i, 7))
+    out = {"metric": "C3 batched motif queries: persistent-launch makespan vs sum of solo runs",
+           "eps": args.eps, "confidence": 0.95, "max_samples": cap, "graphs": info, "runs": []}
+    for seed in (100, 200):
+        torch_sync()
+        t0 = time.perf_counter()
+        solo = [S.sgpm_estimate(ctx, g, p, opts(i, seed))[0] for i, (g, p, _, _) in enumerate(qs)]
+        torch_sync()
+        t_solo = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        res = S.sgpm_estimate_batch(ctx, [q[0] for q in qs], [q[1] for q in qs], [opts(i, seed) for i in range(len(qs))])
+        torch_sync()
+        t_batch = time.perf_counter() - t0
+        same = all((a.n_samples, a.S1, a.S2, a.checksum) == (b.n_samples, b.S1, b.S2, b.checksum)
+                   for a, b in zip(solo, res))
+        run = {"seed": seed, "solo_s": t_solo, "batch_s": t_batch, "identical": same,
+               "samples": int(sum(r.n_samples for r in solo)),
+               "queries": [{"graph": gi, "motif": m, "n": int(r.n_samples), "converged": int(r.converged),
+                            "eps_hat": r.eps_hat, "solo_ms": r.seconds_total * 1e3} for (_, _, m, gi), r in zip(qs, solo)]}
+        out["runs"].append(run)
+        log(f"c3 seed {seed}: solo {t_solo:.2f}s batch {t_batch:.2f}s identical={same}")
+    return out
+
+
+def workload_c4(S, synth, args):
+    """R-MAT 24 (edge factor 16), 5-clique to eps at 95 %: the trained MLP
+    proposal against uniform NS-prune, same seeds and windows; training time
+    reported separately."""
+    ctx = S.sgpm_create(0)
+    g, gi = load_graph(S, synth, ctx, "rmat24", 1 << 24, lambda: synth.rmat_pairs(24, 16, 0.57, 0.19, 0.19, seed=1))
+    p = S.sgpm_pattern_create(ctx, *synth.pattern("5-clique"))
+    t0 = time.perf_counter()
+    model = S.sgpm_model_train(ctx, g, [p])
+    info = S.sgpm_model_info(model)
+    train_s = time.perf_counter() - t0
+    log(f"c4: trained in {train_s:.2f}s on {info['tuples']} tuples")
+    out = {"metric": "C4 learned vs uniform NS, time-to-eps", "graph": gi, "eps": args.eps, "train_s": train_s,
+           "tuples": info["tuples"], "runs": {}}
+    for name, prop in (("uniform", None), ("learned", model.value)):
+        S.sgpm_estimate(ctx, g, p, S.sgpm_options_default(eps=args.eps, seed=3, proposal=prop))
+        rs = []
+        for seed in range(10, 13):
+            r, _ = S.sgpm_estimate(ctx, g, p, S.sgpm_options_default(eps=args.eps, seed=seed, proposal=prop, checksum=1))
+            rs.append({"n": int(r.n_samples), "time_s": r.seconds_total, "estimate": r.estimate, "eps_hat": r.eps_hat,
+                       "kernel_samples_per_s": r.n_samples / max(r.seconds_kernel, 1e-12)})
+        out["runs"][name] = rs
+        log(f"c4 {name}: " + ", ".join(f"{x['n']} samples {x['time_s'] * 1e3:.2f} ms" for x in rs))
+    S.sgpm_model_free(model)
+    return out
+
+
+def workload_c5(S, synth, args):
+    """R-MAT 26 (edge factor 16, about a billion edges, int64 offsets): 6-clique,
+    5-cycle and diamond (edge-induced) in loose mode, where pilots choose
+    between NS-prune and colour sparsification with 16 colours."""
+    ctx = S.sgpm_create(0)
+    g, gi = load_graph(S, synth, ctx, "rmat26", 1 << 26, lambda: synth.rmat_pairs(26, 16, 0.57, 0.19, 0.19, seed=1))
+    out = {"metric": "C5 loose-mode estimates on R-MAT 26", "graph": gi, "eps": args.eps, "queries": {}}
+    for q in ("6-clique", "5-cycle", "diamond"):
+        p = S.sgpm_pattern_create(ctx, *synth.pattern(q))
+        log(f"c5 {q} ...")
+        r, rc = S.sgpm_estimate(ctx, g, p, S.sgpm_options_default(mode=S.MODE_HYBRID, eps=args.eps, colours=16,
+                                                                   gs_reps_max=8, seed=4, max_samples=1 << 30))
+        out["queries"][q] = {"scheme": "GS" if r.scheme == S.SCHEME_GS else "NS", "estimate": r.estimate,
+                             "eps_hat": r.eps_hat, "n": int(r.n_samples), "converged": int(r.converged),
+                             "ns_cone_s": [r.pred_ns_lo, r.pred_ns_hi], "gs_pred_s": r.pred_gs,
+                             "pilot_s": r.seconds_pilot, "total_s": r.seconds_total,
+                             "lanes": r.lanes_per_sample}
+        log(f"c5 {q}: {out['queries'][q]}")
+    return out
+
+
+def torch_sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+WORKLOADS = {"c3": workload_c3, "c4": workload_c4, "c5": workload_c5}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -137,6 +251,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-probes", action="store_true", help="skip the measured copy/gather rooflines")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-uniform leg")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"],
+                    help="c2 (default): R-MAT 20 4-/5-clique, the benchmark line; c3: 24 motif queries on three "
+                         "Chung-Lu graphs, batch vs solo; c4: R-MAT 24 5-clique, learned vs uniform; c5: R-MAT 26 "
+                         "6-clique, 5-cycle, diamond in loose (hybrid) mode")
     ap.add_argument("--counters-run", action="store_true",
                     help="short run for hardware counters: one 256 MiB copy, then one 4M-sample window per query")
     args = ap.parse_args()
@@ -153,6 +271,9 @@ def main():
         sys.exit(1)
     import torch  # device memory / stream plumbing only
     torch.cuda.init()
+    if args.workload != "c2":
+        print(json.dumps(WORKLOADS[args.workload](S, synth, args)), flush=True)
+        return
 
     t0 = time.time()
     scale = args.scale

@@ -518,7 +518,7 @@ sgpm_status ns_estimate_solo(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sg
 }
 
 sgpm_status ns_pilot(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_options& o, const LearnArgs& la,
-                     uint64_t n, int slices, double* seconds, double* eps_hat) {
+                     uint64_t n, int slices, double* seconds, double* eps_hat, double* mean) {
     HIP_TRY(c, hipSetDevice(c->dev));
     const double z = normal_quantile(1.0 - (1.0 - o.confidence) / 2.0);
     int lanes = o.lanes_per_sample;
@@ -534,16 +534,20 @@ sgpm_status ns_pilot(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_optio
         if (st != SGPM_OK) return st;
     }
     HIP_TRY(c, hipStreamSynchronize(c->st));
+    NsState all;
     for (int i = 0; i < slices; i++) {
         const uint64_t a = n * (uint64_t)i / (uint64_t)slices, b = n * (uint64_t)(i + 1) / (uint64_t)slices;
         NsState s;
         absorb(s, c->h_slots + (size_t)i * SLOT_WORDS + 1);
+        absorb(all, c->h_slots + (size_t)i * SLOT_WORDS + 1);
         s.n = b - a;
         float ms = 0;
         HIP_TRY(c, hipEventElapsedTime(&ms, c->kev[3 * (size_t)i], c->kev[3 * (size_t)i + 1]));
         seconds[i] = ms * 1e-3;
         eps_hat[i] = predicted_error(z, s.n, s.S1, s.S2);
     }
+    // the pilot's estimate of the count (learned: sums of alpha' * 2^52)
+    if (mean) *mean = n ? std::ldexp(big_to_double(all.S1) / (double)n, la.table ? -52 : 0) : 0.0;
     return SGPM_OK;
 }
 }  // namespace sgpm

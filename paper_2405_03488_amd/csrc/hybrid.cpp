@@ -17,7 +17,12 @@
 //    sparsification and count).  Their predicted error gives the colourings
 //    needed, R = max(2, ceil(2 (eps_hat_2 / eps)^2)), and the prediction is R
 //    times the mean colouring time.  When one colouring already takes half the
-//    cone's lower end GS cannot lie below it and the second is skipped.
+//    cone's lower end GS cannot lie below it and the second is skipped.  Before
+//    any colouring, the NS pilot's estimate C bounds GS from below: one
+//    colouring's search reaches about C / c^(k-1) leaves, and two colourings at
+//    an optimistic 1e10 leaves per second (several times the count kernel's
+//    measured rate) taking at least the cone's lower end rule GS out without
+//    running it (a large graph's exact count can take minutes).
 //
 // The engine then runs exactly as in its own mode with the same options (GS
 // reuses the two pilot colourings, which are its first two), so a hybrid result
@@ -108,14 +113,18 @@ sgpm_status hybrid_estimate(sgpm_ctx* c, sgpm_graph* g, sgpm_pattern* pat, const
         po.trace_lo = po.trace_hi = 0;
         po.trace_buf = nullptr;
         const uint64_t n_pilot = std::max<uint64_t>(1ull << 16, o.n_min / 4);
-        double sec[kSlices], eh[kSlices];
-        sgpm_status st = ns_pilot(c, g, p, po, ex.la, n_pilot, kSlices, sec, eh);
+        double sec[kSlices], eh[kSlices], mu = 0.0;
+        sgpm_status st = ns_pilot(c, g, p, po, ex.la, n_pilot, kSlices, sec, eh, &mu);
         if (st != SGPM_OK) return st;
         (void)hybrid_choice(kSlices, sec, eh, o.eps, 0, 0.0, 0.0, o.gs_reps_max, &ns_lo, &ns_hi, nullptr);
+        // lower bound of two colourings from the leaves they must reach
+        double leaves = mu;
+        for (int i = 0; i < p.k - 1; i++) leaves /= (double)col;
+        const double gs_floor = 2.0 * leaves / 1e10;
         // GS pilot: the GS engine's first colourings, timed end to end
         const double z = normal_quantile(1.0 - (1.0 - o.confidence) / 2.0);
         double rep_seconds = 0.0;
-        for (int r = 0; r < 2; r++) {
+        for (int r = 0; r < 2 && gs_floor < ns_lo; r++) {
             const auto a = clk::now();
             double dev = 0.0;
             st = gs_rep(c, g, p, col, o.seed, (uint32_t)r, &pre.y[r], &dev);
@@ -125,10 +134,14 @@ sgpm_status hybrid_estimate(sgpm_ctx* c, sgpm_graph* g, sgpm_pattern* pat, const
             rep_seconds += std::chrono::duration<double>(clk::now() - a).count();
             if (r == 0 && 2.0 * rep_seconds >= ns_lo) break;  // GS cannot lie below the cone
         }
-        rep_seconds /= pre.n;
-        const double e2 = pre.n >= 2 ? gs_pilot_error(pre, p, col, z) : INFINITY;
-        scheme = hybrid_choice(kSlices, sec, eh, o.eps, pre.n, rep_seconds, e2, o.gs_reps_max, &ns_lo, &ns_hi,
-                               &gs_pred);
+        if (pre.n == 0) {
+            gs_pred = gs_floor;  // a lower bound; GS was not run
+        } else {
+            rep_seconds /= pre.n;
+            const double e2 = pre.n >= 2 ? gs_pilot_error(pre, p, col, z) : INFINITY;
+            scheme = hybrid_choice(kSlices, sec, eh, o.eps, pre.n, rep_seconds, e2, o.gs_reps_max, &ns_lo, &ns_hi,
+                                   &gs_pred);
+        }
     }
     const double pilot = std::chrono::duration<double>(clk::now() - t0).count();
     sgpm_status st;

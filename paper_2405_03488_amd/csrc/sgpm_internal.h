@@ -228,9 +228,10 @@ sgpm_status gs_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_op
 sgpm_status ns_estimate_solo(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_options& o, sgpm_result* res,
                              int count_bytes, const NsExtra* ex = nullptr);
 // NS pilot: `slices` equal consecutive id ranges of [0, n) under options o
-// (the caller sets the tag); per slice the kernel seconds and predicted error
+// (the caller sets the tag); per slice the kernel seconds and predicted error,
+// and the estimate of the count over the whole pilot
 sgpm_status ns_pilot(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_options& o, const LearnArgs& la,
-                     uint64_t n, int slices, double* seconds, double* eps_hat);
+                     uint64_t n, int slices, double* seconds, double* eps_hat, double* mean);
 sgpm_status learn_args_for(sgpm_ctx* c, sgpm_graph* g, sgpm_pattern* p, sgpm_model* m, LearnArgs* la);
 sgpm_status hybrid_estimate(sgpm_ctx* c, sgpm_graph* g, sgpm_pattern* p, const sgpm_options& o, sgpm_result* res);
 int hybrid_choice(int slices, const double* slice_seconds, const double* slice_eps_hat, double eps, int gs_reps_run,
