@@ -110,3 +110,26 @@ def test_batch_rejects_unsupported(S, synth, ctx, graphs):
         S.sgpm_estimate_batch(ctx, [graphs[0]], [p], [o])
     assert ei.value.status == S.SGPM_EUNSUPPORTED
     S.sgpm_pattern_free(p)
+
+
+def test_batch_motifs_on_power_law_graph(S, synth, ctx):
+    """The batched motif set at the scale of the smallest motif-batch graph
+    (Chung-Lu, 2^18 vertices, average degree 32, gamma 2.1): hubs of ~1e5
+    neighbours, vertex-induced patterns; every query equals its solo run."""
+    n = 1 << 18
+    print("building Chung-Lu 2^18", flush=True)
+    off, nbr = synth.pairs_to_csr(n, synth.chung_lu_pairs(n, 32, 2.1, 18))
+    g = S.sgpm_graph_from_csr(ctx, n, off, nbr)
+    qs = []
+    for i, (name, induced) in enumerate(MOTIFS):
+        k, e = synth.pattern(name)
+        p = S.sgpm_pattern_create(ctx, k, e, induced)
+        o = S.sgpm_options_default(eps=0.05, seed=40 + i, query_tag=i, checksum=1, max_samples=1 << 24)
+        qs.append((g, p, o))
+    res = S.sgpm_estimate_batch(ctx, [q[0] for q in qs], [q[1] for q in qs], [q[2] for q in qs])
+    for (g_, p, o), rb in zip(qs, res):
+        rs, _ = S.sgpm_estimate(ctx, g_, p, o)
+        same(rb, rs)
+    for q in qs:
+        S.sgpm_pattern_free(q[1])
+    S.sgpm_graph_free(g)
