@@ -67,7 +67,8 @@ def measured_traffic(runs, launches):
 def other_legs(S, ctx, g, pats, queries, eps):
     """The rest of the hot path on the same graph: the GS engine (colour
     sparsification + exact count, two colourings at c = 16), the loose-mode
-    choice between NS and GS at eps, and the MLP kernels' MFMA throughput."""
+    choice between NS and GS at eps, the persistent batch against solo runs,
+    and the MLP kernels' MFMA throughput."""
     out = {"gs": {}, "hybrid": {}}
     for q in queries:
         t0 = time.perf_counter()
@@ -80,6 +81,19 @@ def other_legs(S, ctx, g, pats, queries, eps):
         out["hybrid"][q] = {"scheme": "GS" if r.scheme == S.SCHEME_GS else "NS", "ns_cone_s": [r.pred_ns_lo,
                                                                                              r.pred_ns_hi],
                             "gs_pred_s": r.pred_gs, "pilot_s": r.seconds_pilot, "total_s": r.seconds_total}
+    # the persistent batch: both queries x 4 seeds in one launch against the solo runs
+    qs = [(q, 3000 + i) for q in queries for i in range(4)]
+    bopts = [S.sgpm_options_default(eps=eps, seed=sd, query_tag=i, checksum=1) for i, (q, sd) in enumerate(qs)]
+    S.sgpm_estimate_batch(ctx, [g] * len(qs), [pats[q] for q, _ in qs], bopts)  # tunes and captures
+    t0 = time.perf_counter()
+    solo = [S.sgpm_estimate(ctx, g, pats[q], o)[0] for (q, _), o in zip(qs, bopts)]
+    t_solo = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    res = S.sgpm_estimate_batch(ctx, [g] * len(qs), [pats[q] for q, _ in qs], bopts)
+    t_batch = time.perf_counter() - t0
+    out["batch"] = {"queries": len(qs), "solo_s": t_solo, "batch_s": t_batch,
+                    "identical": all((a.n_samples, a.S1, a.S2, a.checksum) == (b.n_samples, b.S1, b.S2, b.checksum)
+                                     for a, b in zip(solo, res)), "tile": [int(r.tile) for r in res]}
     out["mlp_forward_1M_rows"] = S.sgpm_probe_mlp(ctx, 1 << 20, 10)
     out["mlp_train_batch_16K_rows"] = S.sgpm_probe_mlp(ctx, 1 << 14, 20)
     log(f"gs/hybrid/mlp: {json.dumps(out)}")

@@ -130,7 +130,7 @@ typedef struct {
     uint32_t query_tag;      /* Philox counter word 3; distinct tags give independent streams */
     int32_t mode;            /* SGPM_MODE_* */
     uint64_t fixed_n;        /* SGPM_MODE_FIXED_N sample count */
-    uint64_t n_min;          /* first window end (rounded up to quantum) */
+    uint64_t n_min;          /* first window end (rounded up to quantum); > 0 in NS and hybrid modes */
     uint64_t w_min;          /* smallest window */
     uint64_t quantum;        /* window ends are multiples of this */
     uint64_t max_samples;    /* hard cap (NOT_CONVERGED when reached) */

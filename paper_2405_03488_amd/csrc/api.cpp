@@ -290,9 +290,6 @@ sgpm_status enqueue_range(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_
         // record groups)
         if (lanes == 64) cfg.spl = (cfg.spl + 15) / 16 * 16;
     }
-    bool dynamic = true;
-    if (const char* e = std::getenv("SGPM_SPL")) cfg.spl = std::max(1, std::atoi(e));
-    if (const char* e = std::getenv("SGPM_DYNAMIC")) dynamic = std::atoi(e) != 0;
     const uint64_t per_wave = (uint64_t)(64 / lanes) * (uint64_t)cfg.spl;
     const uint64_t tickets = (s1 - s0 + per_wave - 1) / per_wave;
     const uint64_t max_blocks = (tickets + 3) / 4;
@@ -301,14 +298,14 @@ sgpm_status enqueue_range(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_
     sgpm_status st = ensure_scratch(c, (size_t)largest_grid(c), slot + 1);
     if (st != SGPM_OK) return st;
     unsigned long long* tk = c->d_tickets + slot * NTK * TK_STRIDE;
-    if (dynamic) HIP_TRY(c, launch_fill_u64(tk, (uint64_t)NTK * TK_STRIDE, 0ull, c->st));
+    HIP_TRY(c, launch_fill_u64(tk, (uint64_t)NTK * TK_STRIDE, 0ull, c->st));
     while (c->kev.size() < 3 * (slot + 1)) {
         hipEvent_t ev;
         HIP_TRY(c, hipEventCreate(&ev));
         c->kev.push_back(ev);
     }
     HIP_TRY(c, hipEventRecord(c->kev[3 * slot], c->st));
-    HIP_TRY(c, launch_ns_window(g->view(), p, o.seed, o.query_tag, s0, s1, cfg, dynamic ? tk : nullptr,
+    HIP_TRY(c, launch_ns_window(g->view(), p, o.seed, o.query_tag, s0, s1, cfg, tk,
                                 c->d_partials, o.checksum, count_bytes, tr, la, c->st));
     HIP_TRY(c, hipEventRecord(c->kev[3 * slot + 1], c->st));
     HIP_TRY(c, launch_reduce_partials(c->d_partials, cfg.blocks, c->dh_slots + slot * SLOT_WORDS + 1, c->st));
@@ -558,7 +555,8 @@ sgpm_status check_options(sgpm_ctx* c, const sgpm_options* o) {
     if (!o) return fail(c, SGPM_EINVAL, "null options");
     if (!(o->eps > 0) || !(o->confidence > 0 && o->confidence < 1)) return fail(c, SGPM_EINVAL, "eps/confidence");
     if (o->mode == SGPM_MODE_FIXED_N && o->fixed_n == 0) return fail(c, SGPM_EINVAL, "fixed_n = 0");
-    if (o->mode != SGPM_MODE_FIXED_N && o->n_min == 0 && o->w_min == 0) return fail(c, SGPM_EINVAL, "empty windows");
+    if ((o->mode == SGPM_MODE_STRICT_NS || o->mode == SGPM_MODE_HYBRID) && o->n_min == 0)
+        return fail(c, SGPM_EINVAL, "n_min = 0: the first window would be empty");
     if (!(o->window_growth >= 0)) return fail(c, SGPM_EINVAL, "window_growth");
     const int l = o->lanes_per_sample;
     if (!(l == 0 || l == 1 || l == 4 || l == 16 || l == 64)) return fail(c, SGPM_EINVAL, "lanes_per_sample");

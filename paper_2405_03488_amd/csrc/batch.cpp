@@ -16,14 +16,14 @@ namespace sgpm {
 
 namespace {
 
-// Tile autotuner: time 2^16 pilot samples of the query (Philox tag
+// Tile autotuner: time 2^18 pilot samples of the query (Philox tag
 // 0x80000000 | tag, so they never overlap estimation samples) and size the
-// query's tickets to about 50 us of wave time, so uneven queries hand out
+// query's tickets to about 200 us of wave time, so uneven queries hand out
 // tickets of similar cost and the persistent grid drains evenly.
 sgpm_status autotune_tile(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_options& o, int* tile) {
     sgpm_options po = o;
     po.mode = SGPM_MODE_FIXED_N;
-    po.fixed_n = 1 << 16;
+    po.fixed_n = 1 << 18;
     po.query_tag = 0x80000000u | (o.query_tag & 0x7FFFFFFFu);
     po.lanes_per_sample = 64;
     po.checksum = 0;
@@ -34,9 +34,12 @@ sgpm_status autotune_tile(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_
     if (st != SGPM_OK && st != SGPM_NOT_CONVERGED) return st;
     const double waves = (double)c->cus * (double)ns_blocks_per_cu(64) * 4.0;
     const double wave_time_per_sample = r.seconds_kernel * waves / (double)po.fixed_n;
-    double t = wave_time_per_sample > 0 ? 50e-6 / wave_time_per_sample : 1024.0;
+#ifndef SGPM_TILE_US
+#define SGPM_TILE_US 200
+#endif
+    double t = wave_time_per_sample > 0 ? SGPM_TILE_US * 1e-6 / wave_time_per_sample : 1024.0;
     int tl = 16;
-    while (tl < 1024 && tl * 2 <= t) tl *= 2;
+    while (tl < 1024 && tl * 2 <= 1.5 * t) tl *= 2;  // the power of two nearest t
     *tile = tl;
     if (std::getenv("SGPM_DEBUG"))
         std::fprintf(stderr, "sgpm batch autotune: %.3g us wave time per sample -> tile %d\n",
@@ -63,6 +66,9 @@ sgpm_status batch_estimate(sgpm_ctx* c, int nq, const sgpm_graph_t* graphs, cons
         if (o.trace_buf || o.proposal) return fail(c, SGPM_EUNSUPPORTED, "batch queries take no trace or proposal");
         if (!(o.eps > 0) || !(o.confidence > 0 && o.confidence < 1)) return fail(c, SGPM_EINVAL, "eps/confidence");
         if (o.mode == SGPM_MODE_FIXED_N && o.fixed_n == 0) return fail(c, SGPM_EINVAL, "fixed_n = 0");
+        // every window must hold a tile, or its query would never complete
+        if (o.mode == SGPM_MODE_STRICT_NS && o.n_min == 0)
+            return fail(c, SGPM_EINVAL, "n_min = 0: the first window would be empty");
         // Window columns hold sums of 32-bit digits, so a window must stay
         // below 2^32 samples: window_cap = the first window that would not.
         int window_cap = 0x7FFFFFFF;
@@ -120,7 +126,10 @@ sgpm_status batch_estimate(sgpm_ctx* c, int nq, const sgpm_graph_t* graphs, cons
     }
     // device buffers and the captured graph, rebuilt when the batch shape changes
     const size_t qbytes = sizeof(BatchQuery) * (size_t)nq, sbytes = sizeof(BatchState) * (size_t)nq;
-    if (c->batch_nq != nq) {
+    int kmax = 2;
+    for (int i = 0; i < nq; i++) kmax = std::max(kmax, patterns[i]->plan.k);
+    kmax = batch_kmax(kmax);
+    if (c->batch_nq != nq || c->batch_kmax != kmax) {
         if (c->batch_exec) (void)hipGraphExecDestroy(c->batch_exec);
         if (c->batch_graph) (void)hipGraphDestroy(c->batch_graph);
         c->batch_exec = nullptr;
@@ -132,7 +141,7 @@ sgpm_status batch_estimate(sgpm_ctx* c, int nq, const sgpm_graph_t* graphs, cons
         HIP_TRY(c, hipMalloc(&c->d_bq, total));
         HIP_TRY(c, hipHostMalloc(&c->h_bq, total, hipHostMallocDefault));
         if (!c->batch_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->batch_stream, hipStreamNonBlocking));
-        const int blocks = c->cus * batch_blocks_per_cu();
+        const int blocks = c->cus * batch_blocks_per_cu(kmax);
         char* d = (char*)c->d_bq;
         char* h = (char*)c->h_bq;
         BatchQuery* dq = (BatchQuery*)d;
@@ -140,11 +149,12 @@ sgpm_status batch_estimate(sgpm_ctx* c, int nq, const sgpm_graph_t* graphs, cons
         unsigned long long* dact = (unsigned long long*)(d + qbytes + sbytes);
         HIP_TRY(c, hipStreamBeginCapture(c->batch_stream, hipStreamCaptureModeThreadLocal));
         HIP_TRY(c, hipMemcpyAsync(d, h, qbytes + sbytes + 8, hipMemcpyHostToDevice, c->batch_stream));
-        HIP_TRY(c, launch_batch(dq, ds, nq, dact, blocks, c->batch_stream));
+        HIP_TRY(c, launch_batch(dq, ds, nq, dact, blocks, kmax, c->batch_stream));
         HIP_TRY(c, hipMemcpyAsync(h + qbytes, d + qbytes, sbytes, hipMemcpyDeviceToHost, c->batch_stream));
         HIP_TRY(c, hipStreamEndCapture(c->batch_stream, &c->batch_graph));
         HIP_TRY(c, hipGraphInstantiate(&c->batch_exec, c->batch_graph, nullptr, nullptr, 0));
         c->batch_nq = nq;
+        c->batch_kmax = kmax;
     }
     char* h = (char*)c->h_bq;
     std::memcpy(h, hq.data(), qbytes);

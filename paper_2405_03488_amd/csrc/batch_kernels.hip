@@ -20,11 +20,14 @@ namespace {
 
 constexpr unsigned long long TILE_MASK = (1ull << 40) - 1ull;
 
-__device__ __forceinline__ unsigned long long ld_acq(const unsigned long long* p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+// Polling reads are relaxed: the words polled (ticket, finished, active) carry
+// no data that a wave reads afterwards, and an acquire at agent scope would
+// invalidate the XCD's L2, which holds the graph's hot rows.
+__device__ __forceinline__ unsigned long long ld_rlx(const unsigned long long* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ int ld_acq_i(const int* p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ int ld_rlx_i(const int* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ uint64_t dev_next_window(uint64_t n_t, const BatchQuery& Q) {
@@ -136,8 +139,11 @@ __device__ double dev_eps_hat(double z, uint64_t n, const uint32_t* s1, const ui
 __device__ __attribute__((noinline)) void complete_window(const BatchQuery& Q, BatchState& S, int w, uint64_t we,
                                 unsigned long long* active) {
     unsigned long long col[PF_N];
-    for (int i = 0; i < PF_N; ++i) col[i] = __hip_atomic_exchange(&S.win[i], 0ull, __ATOMIC_ACQ_REL,
-                                                                  __HIP_MEMORY_SCOPE_AGENT);
+    for (int i = 0; i < PF_N; ++i) {
+        col[i] = 0;
+        for (int x = 0; x < 8; ++x)
+            col[i] += __hip_atomic_exchange(&S.win[x][i], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     // S1 columns 0-5 into 8 digits, S2 columns 6-15 into 12 digits
     unsigned long long c = 0;
     for (int i = 0; i < 8; ++i) {
@@ -186,8 +192,9 @@ __device__ __attribute__((noinline)) void complete_window(const BatchQuery& Q, B
     } else {
         __hip_atomic_store(&S.done, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __threadfence();
-        __hip_atomic_exchange(&S.ticket, (unsigned long long)(w + 1) << 40, __ATOMIC_RELEASE,
-                              __HIP_MEMORY_SCOPE_AGENT);
+        for (int c = 0; c < 8; ++c)
+            __hip_atomic_exchange(&S.ticket[c].v, (unsigned long long)(w + 1) << 40, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -199,6 +206,7 @@ __device__ __attribute__((noinline)) void complete_window(const BatchQuery& Q, B
 // checksum, 14 hits), which the caller adds to the query's window columns.
 constexpr int BGMAX = 16, BREC = 16;
 
+template <int KMAX>
 __device__ __forceinline__ void run_tile(const BatchQuery& Q, uint64_t s0, uint64_t s1, int32_t* list, uint32_t* rec,
                                          unsigned long long* wsum, uint64_t& ovf) {
     const int lane = (int)(threadIdx.x & 63);
@@ -222,7 +230,7 @@ __device__ __forceinline__ void run_tile(const BatchQuery& Q, uint64_t s0, uint6
             dr.base = q * D;
             int32_t v[8];
             uint64_t alo, ahi, b = 0, ov = 0;
-            const uint32_t st = ns_sample<64>(Q.g, Q.p, Q.seed, Q.tag, s, v, alo, ahi, ov, b, false, list, nullptr,
+            const uint32_t st = ns_sample<64, KMAX>(Q.g, Q.p, Q.seed, Q.tag, s, v, alo, ahi, ov, b, false, list, nullptr,
                                               nullptr, nullptr, &dr);
             ovf |= ov;
             if (st != 0xFFu) {
@@ -278,7 +286,55 @@ __device__ __forceinline__ void run_tile(const BatchQuery& Q, uint64_t s0, uint6
     }
 }
 
-__global__ __launch_bounds__(256, 8) void batch_kernel(const BatchQuery* __restrict__ queries, BatchState* __restrict__ states,
+#ifndef SGPM_BATCH_IDLE_SLEEP
+#define SGPM_BATCH_IDLE_SLEEP 8
+#endif
+// blocks per CU the kernel is compiled for: the most at which the sampling
+// loops of that pattern bound keep every value in registers
+constexpr int batch_occupancy(int kmax) { return kmax <= 5 ? 6 : kmax == 6 ? 5 : 4; }
+
+// The wave's sums of one window, held in its LDS columns across tiles, into the
+// query's window columns (the copy of this block's XCD: blocks are dispatched
+// round-robin over the 8 XCDs, so the copies split the atomics' contention);
+// then the held sample count into done, whose last adder completes the window.
+__device__ __forceinline__ void flush_held(const BatchQuery* queries, BatchState* states, int hq, int hw,
+                                           uint64_t hws, uint64_t hwe, uint64_t hn, uint64_t hovf,
+                                           unsigned long long* wsum, unsigned long long* active) {
+    const int lane = (int)(threadIdx.x & 63);
+    BatchState& S = states[hq];
+    unsigned long long* win = S.win[blockIdx.x & 7];
+    if (lane < 15) {
+        const unsigned long long val = wsum[lane];
+        wsum[lane] = 0ull;
+        const int field = lane < 4 ? PF_S1 + lane : lane < 12 ? PF_S2 + (lane - 4) : lane == 12 ? PF_CSUM
+                        : lane == 14 ? PF_HITS : -1;
+        if (field >= 0 && val) atomicAdd(&win[field], val);
+    }
+    if (lane == 15 && hovf) atomicAdd(&win[PF_OVF], (unsigned long long)hovf);
+    __builtin_amdgcn_wave_barrier();
+    // release only: the sums above before the count below
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (lane == 0) {
+        const unsigned long long old = atomicAdd(&S.done, (unsigned long long)hn);
+        if (old + hn == hwe - hws) {
+            __threadfence();
+            complete_window(queries[hq], S, hw, hwe, active);
+        }
+    }
+}
+
+// KMAX: the largest pattern size of the batch (the sampler is compiled for it).
+//
+// Scheduling: a wave takes tiles from the query it served last while that
+// query's window has tiles left, trying its own XCD's counter first and the
+// other seven after it, then moves on to the next query.  A tile belongs to the
+// window the counter's epoch names when the atomic returns it, not to the one
+// read before, so a tile handed out across a window change is never lost.  The
+// wave keeps its sums in LDS until it moves to another (query, window) or finds
+// no tile; a window cannot complete while a wave holds part of it, so every
+// wave holding sums of a finished window flushes at its next poll.
+template <int KMAX>
+__global__ __launch_bounds__(256, batch_occupancy(KMAX)) void batch_kernel(const BatchQuery* __restrict__ queries, BatchState* __restrict__ states,
                                                     int nq, unsigned long long* __restrict__ active) {
     const int lane = (int)(threadIdx.x & 63);
     const int wid = (int)(threadIdx.x >> 6);
@@ -288,82 +344,103 @@ __global__ __launch_bounds__(256, 8) void batch_kernel(const BatchQuery* __restr
     unsigned long long* wsum = s_wsum[wid];
     if (lane < 16) wsum[lane] = 0ull;
     __builtin_amdgcn_wave_barrier();
-    const int wave = (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+    const int wave = rfl((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+    const int xc = (int)(blockIdx.x & 7);
     int start = wave % nq;
-    // per-wave cache of the last window bounds looked up
+    // per-wave cache of the last window looked up: bounds and tile count
     int cq = -1, cw = -1;
-    uint64_t cws = 0, cwe = 0;
-    for (;;) {
-        if (ld_acq(active) == 0) break;
-        int q = -1;
-        uint64_t t = 0;
-        for (int i = 0; i < nq; ++i) {
-            const int qq = (start + i) % nq;
-            if (ld_acq_i(&states[qq].finished)) continue;
-            const unsigned long long cur = ld_acq(&states[qq].ticket);
-            const int w = (int)(cur >> 40);
-            if (qq != cq || w != cw) {
-                dev_window(queries[qq], w, cws, cwe);
-                cq = qq;
-                cw = w;
-            }
+    uint64_t cws = 0, cwe = 0, cnt = 0;
+    // the (query, window) whose sums the wave holds, and how many samples
+    int hq = -1, hw = -1;
+    uint64_t hws = 0, hwe = 0, hn = 0, hovf = 0;
+    auto lookup = [&](int qq, int e) {
+        if (qq != cq || e != cw) {
+            dev_window(queries[qq], e, cws, cwe);
             const uint64_t T = (uint64_t)queries[qq].tile;
-            const uint64_t ntiles = (cwe - cws + T - 1) / T;
-            if ((cur & TILE_MASK) >= ntiles) continue;
-            unsigned long long got = 0;
-            if (lane == 0) got = atomicAdd(&states[qq].ticket, 1ull);
-            got = __shfl(got, 0);
-            if ((int)(got >> 40) != w || (got & TILE_MASK) >= ntiles) continue;
-            q = qq;
-            t = got & TILE_MASK;
-            break;
+            cnt = (cwe - cws + T - 1) / T;
+            cq = qq;
+            cw = e;
+        }
+    };
+    for (;;) {
+        if (hn == 0 && ld_rlx(active) == 0) break;
+        int q = -1, w = 0;
+        uint64_t t = 0;
+        for (int i = 0; i < nq && q < 0; ++i) {
+            const int qq = (start + i) % nq;
+            if (rfl(ld_rlx_i(&states[qq].finished))) continue;
+            for (int j = 0; j < 8; ++j) {
+                const int c = (xc + j) & 7;
+                unsigned long long* tk = &states[qq].ticket[c].v;
+                const unsigned long long cur = (unsigned long long)rfl64((int64_t)ld_rlx(tk));
+                lookup(qq, (int)(cur >> 40));
+                if ((uint64_t)c + 8ull * (cur & TILE_MASK) >= cnt) continue;
+                unsigned long long got = 0;
+                if (lane == 0) got = atomicAdd(tk, 1ull);
+                got = (unsigned long long)rfl64((int64_t)__shfl(got, 0));
+                const int e = (int)(got >> 40);
+                lookup(qq, e);
+                const uint64_t tile = (uint64_t)c + 8ull * (got & TILE_MASK);
+                if (tile >= cnt) continue;
+                q = qq;
+                w = e;
+                t = tile;
+                break;
+            }
+        }
+        const bool flush = hn && (q < 0 || q != hq || w != hw);
+        if (flush) {
+            flush_held(queries, states, hq, hw, hws, hwe, hn, hovf, wsum, active);
+            hn = hovf = 0;
         }
         if (q < 0) {
-            __builtin_amdgcn_s_sleep(8);
+            if (!flush) __builtin_amdgcn_s_sleep(SGPM_BATCH_IDLE_SLEEP);
             start = (start + 1) % nq;
             continue;
         }
-        q = rfl(q);
-        t = ((uint64_t)(uint32_t)rfl((int32_t)(t >> 32)) << 32) | (uint32_t)rfl((int32_t)t);
         start = q;
         const BatchQuery& Q = queries[q];
         const uint64_t T = (uint64_t)Q.tile;
         const uint64_t s0 = cws + t * T, s1 = min(s0 + T, cwe);
         uint64_t ovf = 0;
-        run_tile(Q, s0, s1, s_list + wid * (LDS_WORDS / 4), s_rec[wid], wsum, ovf);
-        BatchState& S = states[q];
-        // the tile's sums into the query's window columns
-        if (lane < 15) {
-            const unsigned long long val = wsum[lane];
-            wsum[lane] = 0ull;
-            const int field = lane < 4 ? PF_S1 + lane : lane < 12 ? PF_S2 + (lane - 4) : lane == 12 ? PF_CSUM
-                            : lane == 14 ? PF_HITS : -1;
-            if (field >= 0 && val) atomicAdd(&S.win[field], val);
-        }
-        if (lane == 15 && ovf) atomicAdd(&S.win[PF_OVF], (unsigned long long)ovf);
-        __builtin_amdgcn_wave_barrier();
-        __threadfence();
-        if (lane == 0) {
-            const unsigned long long old = atomicAdd(&S.done, (unsigned long long)(s1 - s0));
-            if (old + (s1 - s0) == cwe - cws) {
-                __threadfence();
-                complete_window(Q, S, cw, cwe, active);
-            }
-        }
+        run_tile<KMAX>(Q, s0, s1, s_list + wid * (LDS_WORDS / 4), s_rec[wid], wsum, ovf);
+        hq = q;
+        hw = w;
+        hws = cws;
+        hwe = cwe;
+        hn += s1 - s0;
+        hovf |= ovf;
     }
 }
 
 }  // namespace
 
-int batch_blocks_per_cu() {
+// the compiled bound for a batch whose largest pattern has k vertices
+int batch_kmax(int k) { return k <= 3 ? 3 : k <= 6 ? k : 8; }
+
+int batch_blocks_per_cu(int kmax) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_kernel, 256, 0) != hipSuccess || nb < 1) nb = 1;
+    hipError_t e = hipErrorInvalidValue;
+    switch (batch_kmax(kmax)) {
+        case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_kernel<3>, 256, 0); break;
+        case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_kernel<4>, 256, 0); break;
+        case 5: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_kernel<5>, 256, 0); break;
+        case 6: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_kernel<6>, 256, 0); break;
+        default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_kernel<8>, 256, 0); break;
+    }
+    if (e != hipSuccess || nb < 1) nb = 1;
     return nb;
 }
 
 hipError_t launch_batch(const BatchQuery* q, BatchState* s, int nq, unsigned long long* active, int blocks,
-                        hipStream_t st) {
-    hipLaunchKernelGGL(batch_kernel, dim3((unsigned)blocks), dim3(256), 0, st, q, s, nq, active);
+                        int kmax, hipStream_t st) {
+    switch (batch_kmax(kmax)) {
+        case 3: hipLaunchKernelGGL(batch_kernel<3>, dim3((unsigned)blocks), dim3(256), 0, st, q, s, nq, active); break;
+        case 4: hipLaunchKernelGGL(batch_kernel<4>, dim3((unsigned)blocks), dim3(256), 0, st, q, s, nq, active); break;
+        case 5: hipLaunchKernelGGL(batch_kernel<5>, dim3((unsigned)blocks), dim3(256), 0, st, q, s, nq, active); break;
+        case 6: hipLaunchKernelGGL(batch_kernel<6>, dim3((unsigned)blocks), dim3(256), 0, st, q, s, nq, active); break;
+        default: hipLaunchKernelGGL(batch_kernel<8>, dim3((unsigned)blocks), dim3(256), 0, st, q, s, nq, active); break;
+    }
     return hipGetLastError();
 }
 

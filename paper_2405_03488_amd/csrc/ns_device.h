@@ -152,13 +152,15 @@ __device__ __forceinline__ bool member(const int32_t* __restrict__ R, int32_t rl
             }
             const bool below = group_ballot<G>(res, gmask) == 0;  // the window lies below every pending x
             c += G;
-            if (below && rl - c > 4 * G) {
-                // G-ary search for the first entry >= the smallest pending x: each
-                // round probes G evenly spaced entries and keeps the gap that
-                // holds it, so a long row costs a few round trips, not one per
-                // G entries.  Entries skipped are below every x still pending.
-                const int32_t xmin = uni<G>(__shfl(x, __ffsll((unsigned long long)pend) - 1));
-                int32_t lo = c, hi = rl;  // the entry sought lies in [lo, hi]
+            const int32_t xmin = below && rl - c > 8 * G ? uni<G>(__shfl(x, __ffsll((unsigned long long)pend) - 1)) : 0;
+            if (below && rl - c > 8 * G && uni<G>(R[c + 8 * G - 1]) < xmin) {
+                // more than 8 windows from the smallest pending x: a G-ary search
+                // for the first entry >= it, each round probing G evenly spaced
+                // entries and keeping the gap that holds it, so a long row costs
+                // a few round trips, not one per G entries.  Entries skipped are
+                // below every x still pending.  (A single probe 8 windows ahead
+                // keeps short gaps on the cheaper slide.)
+                int32_t lo = c + 8 * G, hi = rl;  // the entry sought lies in [lo, hi]
                 while (hi - lo > G) {
                     const int32_t step = (hi - lo) / G;
                     const int32_t pv = R[lo + (gl + 1) * step - 1];

@@ -88,19 +88,27 @@ struct BatchQuery {
     uint64_t fixed_n, n_min, w_min, quantum, max_samples;
     double growth, eps, z;
 };
+// one ticket counter per XCD, each in a cache line of its own: counter c hands
+// out tiles c, c + 8, c + 16, .. of the current window as epoch << 40 | k
+struct alignas(128) BatchTicket {
+    unsigned long long v;
+    unsigned long long pad[15];
+};
 struct BatchState {
-    unsigned long long ticket;  // window epoch << 40 | next tile
-    unsigned long long done;    // samples finished in the current window
+    BatchTicket ticket[8];
+    alignas(128) unsigned long long done;  // samples whose sums are in win[]
+    unsigned long long done_pad[15];
     int32_t finished, status, converged, windows;
-    unsigned long long win[PF_N];            // current window's sum columns
+    unsigned long long win[8][PF_N];         // current window's sum columns, one copy per XCD
     unsigned long long tot_s1[8], tot_s2[12];  // normalised 32-bit digits
     unsigned long long hits, csum, bytes, ovf;
     double eps_hat;
     uint64_t n;
 };
-int batch_blocks_per_cu();
+int batch_blocks_per_cu(int kmax);
+int batch_kmax(int k);
 hipError_t launch_batch(const BatchQuery* q, BatchState* s, int nq, unsigned long long* active, int blocks,
-                        hipStream_t st);
+                        int kmax, hipStream_t st);
 
 struct NsExtra {
     LearnArgs la;        // learned proposal (table nullptr = uniform)
@@ -175,6 +183,7 @@ struct sgpm_ctx {
     std::map<std::tuple<const void*, std::string>, int> tuned;     // batch tile per (graph, plan)
     std::map<std::tuple<const void*, std::string>, int> ns_tuned;  // solo lanes per sample per (graph, plan)
     int batch_nq = 0;
+    int batch_kmax = 0;
     void* d_bq = nullptr;
     void* h_bq = nullptr;
     hipStream_t batch_stream = nullptr;
