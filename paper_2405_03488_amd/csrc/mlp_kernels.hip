@@ -10,8 +10,10 @@
 // transpose and the B operand of itself: the weight gradients H1^T dZ2 and
 // X^T dZ1 need no data movement; H1 and dZ2 go through LDS once per tile to
 // become A operands of the next product.
-// Loss = mean over the minibatch of (s - y)^2 / 2.  Each wave writes its
-// partial gradient; the Adam kernel adds the partials in a fixed order.
+// Loss = mean over the minibatch of (s - y)^2 / 2.  The four waves of a block
+// add their gradients into one LDS copy in wave order, the block writes it as
+// its partial, and the partials are added in block order: the result does not
+// depend on scheduling.
 #include <hip/hip_runtime.h>
 
 #include "sgpm_internal.h"
@@ -71,10 +73,11 @@ __device__ __forceinline__ s4 frag_bt(const float* W2, int kb, int mb, int lane)
 }
 
 // Forward (and optionally backward) over rows [row0, row0 + nrows) of X, one
-// wave.  gout (BWD) receives this wave's gradient, NPARAM floats.
+// wave.  With BWD every wave of the block must call it (nrows may be 0): the
+// waves add their gradients into gacc (NPARAM floats of LDS) in wave order.
 template <bool BWD>
 __device__ void mlp_wave(const float* __restrict__ P, const float* __restrict__ X, const float* __restrict__ y,
-                         int64_t row0, int nrows, float inv_batch, float* __restrict__ s_out, float* __restrict__ gout,
+                         int64_t row0, int nrows, float inv_batch, float* __restrict__ s_out, float* gacc,
                          float* lds /* 16 x 64 floats */) {
     const int lane = (int)(threadIdx.x & 63), col = lane & 15, grp = lane >> 4;
     const float* W1 = P + OFF_W1;
@@ -199,24 +202,36 @@ __device__ void mlp_wave(const float* __restrict__ P, const float* __restrict__ 
         }
     }
     if (!BWD) return;
-    // write this wave's gradient (D layouts -> parameter indices)
-    for (int mb = 0; mb < 4; ++mb)
-        for (int i = 0; i < 4; ++i) gout[OFF_W1 + (4 * grp + i) * NH + 16 * mb + col] = gW1[mb][i];
-    for (int mb = 0; mb < 4; ++mb)
-        for (int nb = 0; nb < 4; ++nb)
-            for (int i = 0; i < 4; ++i) gout[OFF_W2 + (16 * mb + 4 * grp + i) * NH + 16 * nb + col] = gW2[mb][nb][i];
+    float gv1[4], gv2[4], gv3[4];
     for (int nb = 0; nb < 4; ++nb) {
-        const float a = across_groups(gb1[nb]), b = across_groups(gb2[nb]), c = across_groups(gw3[nb]);
-        if (grp == 0) {
-            gout[OFF_B1 + 16 * nb + col] = a;
-            gout[OFF_B2 + 16 * nb + col] = b;
-            gout[OFF_W3 + 16 * nb + col] = c;
-        }
+        gv1[nb] = across_groups(gb1[nb]);
+        gv2[nb] = across_groups(gb2[nb]);
+        gv3[nb] = across_groups(gw3[nb]);
     }
     float g3 = gb3;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) g3 += __shfl_xor(g3, o);
-    if (lane == 0) gout[OFF_B3] = g3;
+    // this wave's gradient (D layouts -> parameter indices) into gacc, wave 0
+    // storing and waves 1-3 adding, one wave per phase
+    const int wid = (int)(threadIdx.x >> 6);
+    for (int phase = 0; phase < 4; ++phase) {
+        if (wid == phase) {
+            auto put = [&](int idx, float v) { gacc[idx] = phase == 0 ? v : gacc[idx] + v; };
+            for (int mb = 0; mb < 4; ++mb)
+                for (int i = 0; i < 4; ++i) put(OFF_W1 + (4 * grp + i) * NH + 16 * mb + col, gW1[mb][i]);
+            for (int mb = 0; mb < 4; ++mb)
+                for (int nb = 0; nb < 4; ++nb)
+                    for (int i = 0; i < 4; ++i) put(OFF_W2 + (16 * mb + 4 * grp + i) * NH + 16 * nb + col, gW2[mb][nb][i]);
+            if (grp == 0)
+                for (int nb = 0; nb < 4; ++nb) {
+                    put(OFF_B1 + 16 * nb + col, gv1[nb]);
+                    put(OFF_B2 + 16 * nb + col, gv2[nb]);
+                    put(OFF_W3 + 16 * nb + col, gv3[nb]);
+                }
+            if (lane == 0) put(OFF_B3, g3);
+        }
+        __syncthreads();
+    }
 }
 
 // rows split over waves: wave w takes rows [w * per, (w + 1) * per)
@@ -231,37 +246,36 @@ __global__ __launch_bounds__(256) void mlp_forward_kernel(const float* __restric
     mlp_wave<false>(P, X, nullptr, r0, nrows, 0.f, s_out, nullptr, lds[w]);
 }
 
+// one partial gradient per block: its four waves' rows [r0, r0 + per_wave)
 __global__ __launch_bounds__(256) void mlp_grad_kernel(const float* __restrict__ P, const float* __restrict__ X,
                                                        const float* __restrict__ y, int64_t N, int per_wave,
                                                        float inv_batch, float* __restrict__ gpart) {
     __shared__ float lds[4][16 * NH];
+    __shared__ float gacc[NPARAM];
     const int w = (int)(threadIdx.x >> 6);
     const int64_t wave = (int64_t)blockIdx.x * 4 + w;
     const int64_t r0 = wave * per_wave;
-    float* gout = gpart + wave * NPARAM;
-    if (r0 >= N) {
-        for (int i = (int)(threadIdx.x & 63); i < NPARAM; i += 64) gout[i] = 0.f;
-        return;
-    }
-    const int nrows = (int)min((int64_t)per_wave, N - r0);
-    mlp_wave<true>(P, X, y, r0, nrows, inv_batch, nullptr, gout, lds[w]);
+    const int nrows = r0 < N ? (int)min((int64_t)per_wave, N - r0) : 0;
+    mlp_wave<true>(P, X, y, r0, nrows, inv_batch, nullptr, gacc, lds[w]);
+    float* gout = gpart + (int64_t)blockIdx.x * NPARAM;
+    for (int i = (int)threadIdx.x; i < NPARAM; i += 256) gout[i] = gacc[i];
 }
 
-// grads = sum of the partials in wave order (deterministic)
-__global__ void sum_partials_kernel(const float* __restrict__ gpart, int nwaves, float* __restrict__ g) {
+// grads = sum of the block partials in block order
+__global__ void sum_partials_kernel(const float* __restrict__ gpart, int nparts, float* __restrict__ g) {
     const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (i >= NPARAM) return;
     float a = 0.f;
-    for (int w = 0; w < nwaves; ++w) a += gpart[(int64_t)w * NPARAM + i];
+    for (int w = 0; w < nparts; ++w) a += gpart[(int64_t)w * NPARAM + i];
     g[i] = a;
 }
 
-__global__ void adam_kernel(float* __restrict__ P, const float* __restrict__ gpart, int nwaves, float* __restrict__ m,
+__global__ void adam_kernel(float* __restrict__ P, const float* __restrict__ gpart, int nparts, float* __restrict__ m,
                             float* __restrict__ v, float lr, float b1, float b2, float eps, float c1, float c2) {
     const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (i >= NPARAM) return;
     float g = 0.f;
-    for (int w = 0; w < nwaves; ++w) g += gpart[(int64_t)w * NPARAM + i];
+    for (int w = 0; w < nparts; ++w) g += gpart[(int64_t)w * NPARAM + i];
     const float mi = b1 * m[i] + (1.f - b1) * g;
     const float vi = b2 * v[i] + (1.f - b2) * g * g;
     m[i] = mi;
@@ -273,6 +287,18 @@ __global__ void adam_kernel(float* __restrict__ P, const float* __restrict__ gpa
 
 int mlp_nparams() { return NPARAM; }
 
+// Gradient launches: up to 1024 blocks (4 per CU at this kernel's LDS use, on
+// 256 CUs), each wave taking a run of rows that is a multiple of the 16-row tile.
+int64_t mlp_grad_blocks(int64_t N) {
+    const int64_t b = (N + 255) / 256;
+    return b < 1 ? 1 : b > 1024 ? 1024 : b;
+}
+static int grad_rows_per_wave(int64_t N) {
+    const int64_t waves = 4 * mlp_grad_blocks(N);
+    const int64_t per = (N + waves - 1) / waves;
+    return (int)((per + 15) / 16 * 16);
+}
+
 hipError_t mlp_forward(const float* P, const float* X, int64_t N, float* s_out, hipStream_t st) {
     if (N <= 0) return hipSuccess;
     const int per = 64;
@@ -283,28 +309,25 @@ hipError_t mlp_forward(const float* P, const float* X, int64_t N, float* s_out, 
 }
 
 // gradient of the mean loss over rows [0, N) into g (NPARAM floats); gpart holds
-// ceil(N / 64) rounded up to 4 waves x NPARAM floats
+// mlp_grad_blocks(N) x NPARAM floats
 hipError_t mlp_grad(const float* P, const float* X, const float* y, int64_t N, float* gpart, float* g,
                     hipStream_t st) {
-    const int per = 64;
-    const int64_t waves = (N + per - 1) / per;
-    const unsigned blocks = (unsigned)((waves + 3) / 4);
-    hipLaunchKernelGGL(mlp_grad_kernel, dim3(blocks), dim3(256), 0, st, P, X, y, N, per, 1.f / (float)N, gpart);
-    hipLaunchKernelGGL(sum_partials_kernel, dim3((NPARAM + 255) / 256), dim3(256), 0, st, gpart, (int)(blocks * 4),
-                       g);
+    const unsigned blocks = (unsigned)mlp_grad_blocks(N);
+    hipLaunchKernelGGL(mlp_grad_kernel, dim3(blocks), dim3(256), 0, st, P, X, y, N, grad_rows_per_wave(N),
+                       1.f / (float)N, gpart);
+    hipLaunchKernelGGL(sum_partials_kernel, dim3((NPARAM + 255) / 256), dim3(256), 0, st, gpart, (int)blocks, g);
     return hipGetLastError();
 }
 
 // one Adam step on the minibatch rows [0, B) of X, y
 hipError_t mlp_adam_step(float* P, const float* X, const float* y, int64_t B, float* gpart, float* m, float* v,
                          float lr, int step, hipStream_t st) {
-    const int per = 64;
-    const int64_t waves = (B + per - 1) / per;
-    const unsigned blocks = (unsigned)((waves + 3) / 4);
-    hipLaunchKernelGGL(mlp_grad_kernel, dim3(blocks), dim3(256), 0, st, P, X, y, B, per, 1.f / (float)B, gpart);
+    const unsigned blocks = (unsigned)mlp_grad_blocks(B);
+    hipLaunchKernelGGL(mlp_grad_kernel, dim3(blocks), dim3(256), 0, st, P, X, y, B, grad_rows_per_wave(B),
+                       1.f / (float)B, gpart);
     const float b1 = 0.9f, b2 = 0.999f;
     const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
-    hipLaunchKernelGGL(adam_kernel, dim3((NPARAM + 255) / 256), dim3(256), 0, st, P, gpart, (int)(blocks * 4), m, v,
+    hipLaunchKernelGGL(adam_kernel, dim3((NPARAM + 255) / 256), dim3(256), 0, st, P, gpart, (int)blocks, m, v,
                        lr, b1, b2, 1e-8f, c1, c2);
     return hipGetLastError();
 }

@@ -227,8 +227,8 @@ sgpm_status train(sgpm_ctx* c, sgpm_graph* g, const sgpm_pattern_t* pats, int np
     HIP_TRY(c, hipMalloc(&dv.p, sizeof(float) * (size_t)NP));
     HIP_TRY(c, hipMalloc(&dX.p, sizeof(float) * (size_t)(steps_per_epoch * B) * NFEAT));
     HIP_TRY(c, hipMalloc(&dY.p, sizeof(float) * (size_t)(steps_per_epoch * B)));
-    const int64_t waves = ((B + 63) / 64 + 3) / 4 * 4;
-    HIP_TRY(c, hipMalloc(&dg.p, sizeof(float) * (size_t)NP * (size_t)waves));
+    const int64_t parts = mlp_grad_blocks(B);
+    HIP_TRY(c, hipMalloc(&dg.p, sizeof(float) * (size_t)NP * (size_t)parts));
     HIP_TRY(c, hipMemcpy(dP.p, P.data(), sizeof(float) * (size_t)NP, hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemset(dm.p, 0, sizeof(float) * (size_t)NP));
     HIP_TRY(c, hipMemset(dv.p, 0, sizeof(float) * (size_t)NP));
@@ -374,12 +374,12 @@ sgpm_status sgpm_mlp_grad(sgpm_ctx_t c, const float* params, const float* X, con
     if (!c || !params || !X || !y || !grads_out || N < 1) return fail(c, SGPM_EINVAL, "bad arguments");
     HIP_TRY(c, hipSetDevice(c->dev));
     const int NP = mlp_nparams();
-    const int64_t waves = ((N + 63) / 64 + 3) / 4 * 4;
+    const int64_t parts = mlp_grad_blocks(N);
     Dev dP, dX, dY, dgp, dg;
     HIP_TRY(c, hipMalloc(&dP.p, sizeof(float) * (size_t)NP));
     HIP_TRY(c, hipMalloc(&dX.p, sizeof(float) * (size_t)N * NFEAT));
     HIP_TRY(c, hipMalloc(&dY.p, sizeof(float) * (size_t)N));
-    HIP_TRY(c, hipMalloc(&dgp.p, sizeof(float) * (size_t)NP * (size_t)waves));
+    HIP_TRY(c, hipMalloc(&dgp.p, sizeof(float) * (size_t)NP * (size_t)parts));
     HIP_TRY(c, hipMalloc(&dg.p, sizeof(float) * (size_t)NP));
     HIP_TRY(c, hipMemcpy(dP.p, params, sizeof(float) * (size_t)NP, hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy(dX.p, X, sizeof(float) * (size_t)N * NFEAT, hipMemcpyHostToDevice));
@@ -399,7 +399,7 @@ sgpm_status sgpm_probe_mlp(sgpm_ctx_t c, int64_t N, int iters, double* out4) {
     if (!c || N < 64 || iters < 1 || !out4) return fail(c, SGPM_EINVAL, "bad arguments");
     HIP_TRY(c, hipSetDevice(c->dev));
     const int NP = mlp_nparams();
-    const int64_t waves = ((N + 63) / 64 + 3) / 4 * 4;
+    const int64_t parts = mlp_grad_blocks(N);
     std::vector<float> hp((size_t)NP), hx((size_t)N * NFEAT), hy((size_t)N);
     uint64_t rs = 12345;
     for (auto& v : hp) v = (float)(gauss(rs) * 0.1);
@@ -410,7 +410,7 @@ sgpm_status sgpm_probe_mlp(sgpm_ctx_t c, int64_t N, int iters, double* out4) {
     HIP_TRY(c, hipMalloc(&dX.p, sizeof(float) * hx.size()));
     HIP_TRY(c, hipMalloc(&dY.p, sizeof(float) * hy.size()));
     HIP_TRY(c, hipMalloc(&dS.p, sizeof(float) * (size_t)N));
-    HIP_TRY(c, hipMalloc(&dgp.p, sizeof(float) * (size_t)NP * (size_t)waves));
+    HIP_TRY(c, hipMalloc(&dgp.p, sizeof(float) * (size_t)NP * (size_t)parts));
     HIP_TRY(c, hipMalloc(&dg.p, sizeof(float) * (size_t)NP));
     HIP_TRY(c, hipMemcpy(dP.p, hp.data(), sizeof(float) * hp.size(), hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy(dX.p, hx.data(), sizeof(float) * hx.size(), hipMemcpyHostToDevice));

@@ -117,6 +117,7 @@ struct NsExtra {
 
 // MLP (mlp_kernels.hip)
 int mlp_nparams();
+int64_t mlp_grad_blocks(int64_t N);  // partial gradients mlp_grad / mlp_adam_step write
 hipError_t mlp_forward(const float* P, const float* X, int64_t N, float* s_out, hipStream_t st);
 hipError_t mlp_grad(const float* P, const float* X, const float* y, int64_t N, float* gpart, float* g,
                     hipStream_t st);

@@ -60,7 +60,7 @@ def test_mlp_forward_matches_oracle(S, O, ctx, N):
     assert err <= 1e-2 and cos >= 0.999, (err, cos)
 
 
-@pytest.mark.parametrize("N", [64, 256, 777])
+@pytest.mark.parametrize("N", [64, 256, 777, 70001])
 def test_mlp_gradients_match_oracle(S, O, ctx, N):
     rng = np.random.default_rng(100 + N)
     p = rand_params(rng, O)
