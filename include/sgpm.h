@@ -246,6 +246,18 @@ sgpm_status sgpm_model_info(sgpm_model_t m, float* params_out, int* nparams, dou
 sgpm_status sgpm_mlp_forward(sgpm_ctx_t ctx, const float* params, const float* X, int64_t N, float* s_out);
 sgpm_status sgpm_mlp_grad(sgpm_ctx_t ctx, const float* params, const float* X, const float* y, int64_t N,
                           float* grads_out);
+/* Adam (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) on the same loss
+ * over nsteps consecutive minibatches of B rows: step s takes rows [s B, (s+1) B)
+ * of X (nsteps * B x 16, row-major) and y.  params, m, v (5313 floats each) and
+ * beta_pow = {0.9^t, 0.999^t} before the first step ({1, 1} at the start of
+ * training) are host arrays, updated in place.  Each step equals
+ * sgpm_mlp_grad on its rows followed by the FP32 update
+ * m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g g, c = 1 - beta^t,
+ * params -= lr (m / c1) / (sqrt(v / c2) + eps); for B <= 256 all steps run in
+ * one launch (weights in LDS), else two launches per step.  This is the
+ * training step sgpm_model_train runs per epoch. */
+sgpm_status sgpm_mlp_adam_steps(sgpm_ctx_t ctx, float* params, float* m, float* v, const float* X, const float* y,
+                                int64_t nsteps, int64_t B, float lr, float* beta_pow);
 
 /* ------------------------------------------------------------------ measurement probes */
 /* Streaming copy of `bytes` (rounded down to 16) repeated iters times; *gbs =

@@ -283,6 +283,44 @@ __global__ void adam_kernel(float* __restrict__ P, const float* __restrict__ gpa
     P[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
+// Adam over nsteps consecutive minibatches of B rows in one workgroup, for
+// minibatches one gradient block covers (B <= 256): the weights stay in LDS
+// between steps, the moments in global memory (each thread owns the same
+// parameters every step), so a step costs no launch.  The arithmetic is that of
+// mlp_grad_kernel + adam_kernel step by step: the gradient rows split over the
+// four waves as grad_rows_per_wave gives them, the bias corrections from the
+// running products beta^t, carried in from the caller as pb1, pb2.
+__global__ __launch_bounds__(256) void mlp_train_kernel(float* __restrict__ P, float* __restrict__ m,
+                                                        float* __restrict__ v, const float* __restrict__ X,
+                                                        const float* __restrict__ y, int64_t nsteps, int B,
+                                                        int per_wave, float lr, float pb1, float pb2) {
+    __shared__ float lds[4][16 * NH];
+    __shared__ float gacc[NPARAM];
+    __shared__ float Pl[NPARAM];
+    const int tid = (int)threadIdx.x, w = tid >> 6;
+    for (int i = tid; i < NPARAM; i += 256) Pl[i] = P[i];
+    __syncthreads();
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f, inv = 1.f / (float)B;
+    const int64_t r0 = (int64_t)w * per_wave;
+    const int nrows = r0 < B ? (int)min((int64_t)per_wave, (int64_t)B - r0) : 0;
+    for (int64_t s = 0; s < nsteps; ++s) {
+        mlp_wave<true>(Pl, X + s * B * NIN, y + s * B, r0, nrows, inv, nullptr, gacc, lds[w]);
+        pb1 *= b1;
+        pb2 *= b2;
+        const float c1 = 1.f - pb1, c2 = 1.f - pb2;
+        for (int i = tid; i < NPARAM; i += 256) {
+            const float g = gacc[i];
+            const float mi = b1 * m[i] + (1.f - b1) * g;
+            const float vi = b2 * v[i] + (1.f - b2) * g * g;
+            m[i] = mi;
+            v[i] = vi;
+            Pl[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+        }
+        __syncthreads();
+    }
+    for (int i = tid; i < NPARAM; i += 256) P[i] = Pl[i];
+}
+
 }  // namespace
 
 int mlp_nparams() { return NPARAM; }
@@ -319,16 +357,34 @@ hipError_t mlp_grad(const float* P, const float* X, const float* y, int64_t N, f
     return hipGetLastError();
 }
 
-// one Adam step on the minibatch rows [0, B) of X, y
-hipError_t mlp_adam_step(float* P, const float* X, const float* y, int64_t B, float* gpart, float* m, float* v,
-                         float lr, int step, hipStream_t st) {
-    const unsigned blocks = (unsigned)mlp_grad_blocks(B);
-    hipLaunchKernelGGL(mlp_grad_kernel, dim3(blocks), dim3(256), 0, st, P, X, y, B, grad_rows_per_wave(B),
-                       1.f / (float)B, gpart);
+// Adam steps on nsteps consecutive minibatches of B rows (step s takes rows
+// [s B, (s + 1) B) of X, y).  bpow = {0.9^t, 0.999^t} before the first step,
+// host memory, advanced by nsteps.  One launch in all when a minibatch fits one
+// gradient block, else a gradient and an update launch per step (gpart holds
+// mlp_grad_blocks(B) x NPARAM floats).
+hipError_t mlp_adam_steps(float* P, float* m, float* v, const float* X, const float* y, int64_t nsteps, int64_t B,
+                          float lr, float* bpow, float* gpart, hipStream_t st) {
     const float b1 = 0.9f, b2 = 0.999f;
-    const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
-    hipLaunchKernelGGL(adam_kernel, dim3((NPARAM + 255) / 256), dim3(256), 0, st, P, gpart, (int)blocks, m, v,
-                       lr, b1, b2, 1e-8f, c1, c2);
+    const unsigned blocks = (unsigned)mlp_grad_blocks(B);
+    if (nsteps <= 0) return hipSuccess;
+    if (blocks == 1) {
+        hipLaunchKernelGGL(mlp_train_kernel, dim3(1), dim3(256), 0, st, P, m, v, X, y, nsteps, (int)B,
+                           grad_rows_per_wave(B), lr, bpow[0], bpow[1]);
+        for (int64_t s = 0; s < nsteps; ++s) {
+            bpow[0] *= b1;
+            bpow[1] *= b2;
+        }
+        return hipGetLastError();
+    }
+    for (int64_t s = 0; s < nsteps; ++s) {
+        hipLaunchKernelGGL(mlp_grad_kernel, dim3(blocks), dim3(256), 0, st, P, X + s * B * NIN, y + s * B, B,
+                           grad_rows_per_wave(B), 1.f / (float)B, gpart);
+        bpow[0] *= b1;
+        bpow[1] *= b2;
+        const float c1 = 1.f - bpow[0], c2 = 1.f - bpow[1];
+        hipLaunchKernelGGL(adam_kernel, dim3((NPARAM + 255) / 256), dim3(256), 0, st, P, gpart, (int)blocks, m, v,
+                           lr, b1, b2, 1e-8f, c1, c2);
+    }
     return hipGetLastError();
 }
 

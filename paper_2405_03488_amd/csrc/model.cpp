@@ -236,7 +236,7 @@ sgpm_status train(sgpm_ctx* c, sgpm_graph* g, const sgpm_pattern_t* pats, int np
     for (int64_t i = 0; i < T; i++) perm[(size_t)i] = i;
     std::vector<float> Xs((size_t)(steps_per_epoch * B) * NFEAT), Ys((size_t)(steps_per_epoch * B));
     uint64_t ps = cfg.seed ^ 0xA11CEull;
-    int step = 0;
+    float bpow[2] = {1.f, 1.f};  // Adam's beta1^t, beta2^t
     Dev dloss;
     HIP_TRY(c, hipMalloc(&dloss.p, sizeof(float) * (size_t)T));
     auto eval_loss = [&](double* loss) -> sgpm_status {
@@ -262,12 +262,8 @@ sgpm_status train(sgpm_ctx* c, sgpm_graph* g, const sgpm_pattern_t* pats, int np
             sgpm_status st = eval_loss(&m->loss_first);
             if (st != SGPM_OK) return st;
         }
-        for (int64_t b = 0; b < steps_per_epoch; b++) {
-            ++step;
-            HIP_TRY(c, mlp_adam_step((float*)dP.p, (const float*)dX.p + (size_t)(b * B) * NFEAT,
-                                     (const float*)dY.p + (size_t)(b * B), B, (float*)dg.p, (float*)dm.p, (float*)dv.p,
-                                     cfg.lr, step, c->st));
-        }
+        HIP_TRY(c, mlp_adam_steps((float*)dP.p, (float*)dm.p, (float*)dv.p, (const float*)dX.p, (const float*)dY.p,
+                                  steps_per_epoch, B, cfg.lr, bpow, (float*)dg.p, c->st));
     }
     {
         sgpm_status st = eval_loss(&m->loss_last);
@@ -387,6 +383,34 @@ sgpm_status sgpm_mlp_grad(sgpm_ctx_t c, const float* params, const float* X, con
     HIP_TRY(c, mlp_grad((const float*)dP.p, (const float*)dX.p, (const float*)dY.p, N, (float*)dgp.p, (float*)dg.p,
                         c->st));
     HIP_TRY(c, hipMemcpyAsync(grads_out, dg.p, sizeof(float) * (size_t)NP, hipMemcpyDeviceToHost, c->st));
+    HIP_TRY(c, hipStreamSynchronize(c->st));
+    return SGPM_OK;
+}
+
+sgpm_status sgpm_mlp_adam_steps(sgpm_ctx_t c, float* params, float* m, float* v, const float* X, const float* y,
+                                int64_t nsteps, int64_t B, float lr, float* beta_pow) {
+    if (!c || !params || !m || !v || !X || !y || !beta_pow || nsteps < 1 || B < 1 || !(lr > 0))
+        return fail(c, SGPM_EINVAL, "bad arguments");
+    HIP_TRY(c, hipSetDevice(c->dev));
+    const int NP = mlp_nparams();
+    const size_t rows = (size_t)nsteps * (size_t)B;
+    Dev dP, dm, dv, dX, dY, dgp;
+    HIP_TRY(c, hipMalloc(&dP.p, sizeof(float) * (size_t)NP));
+    HIP_TRY(c, hipMalloc(&dm.p, sizeof(float) * (size_t)NP));
+    HIP_TRY(c, hipMalloc(&dv.p, sizeof(float) * (size_t)NP));
+    HIP_TRY(c, hipMalloc(&dX.p, sizeof(float) * rows * NFEAT));
+    HIP_TRY(c, hipMalloc(&dY.p, sizeof(float) * rows));
+    HIP_TRY(c, hipMalloc(&dgp.p, sizeof(float) * (size_t)NP * (size_t)mlp_grad_blocks(B)));
+    HIP_TRY(c, hipMemcpy(dP.p, params, sizeof(float) * (size_t)NP, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(dm.p, m, sizeof(float) * (size_t)NP, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(dv.p, v, sizeof(float) * (size_t)NP, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(dX.p, X, sizeof(float) * rows * NFEAT, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(dY.p, y, sizeof(float) * rows, hipMemcpyHostToDevice));
+    HIP_TRY(c, mlp_adam_steps((float*)dP.p, (float*)dm.p, (float*)dv.p, (const float*)dX.p, (const float*)dY.p, nsteps,
+                              B, lr, beta_pow, (float*)dgp.p, c->st));
+    HIP_TRY(c, hipMemcpyAsync(params, dP.p, sizeof(float) * (size_t)NP, hipMemcpyDeviceToHost, c->st));
+    HIP_TRY(c, hipMemcpyAsync(m, dm.p, sizeof(float) * (size_t)NP, hipMemcpyDeviceToHost, c->st));
+    HIP_TRY(c, hipMemcpyAsync(v, dv.p, sizeof(float) * (size_t)NP, hipMemcpyDeviceToHost, c->st));
     HIP_TRY(c, hipStreamSynchronize(c->st));
     return SGPM_OK;
 }

@@ -117,12 +117,12 @@ struct NsExtra {
 
 // MLP (mlp_kernels.hip)
 int mlp_nparams();
-int64_t mlp_grad_blocks(int64_t N);  // partial gradients mlp_grad / mlp_adam_step write
+int64_t mlp_grad_blocks(int64_t N);  // partial gradients mlp_grad / mlp_adam_steps write
 hipError_t mlp_forward(const float* P, const float* X, int64_t N, float* s_out, hipStream_t st);
 hipError_t mlp_grad(const float* P, const float* X, const float* y, int64_t N, float* gpart, float* g,
                     hipStream_t st);
-hipError_t mlp_adam_step(float* P, const float* X, const float* y, int64_t B, float* gpart, float* m, float* v,
-                         float lr, int step, hipStream_t st);
+hipError_t mlp_adam_steps(float* P, float* m, float* v, const float* X, const float* y, int64_t nsteps, int64_t B,
+                          float lr, float* bpow, float* gpart, hipStream_t st);
 
 // host helpers
 struct HostGraph {

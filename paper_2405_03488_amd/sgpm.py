@@ -117,6 +117,7 @@ def lib():
             "sgpm_model_info": ([P, P, P, P, P], st),
             "sgpm_mlp_forward": ([P, P, P, C.c_int64, P], st),
             "sgpm_mlp_grad": ([P, P, P, P, C.c_int64, P], st),
+            "sgpm_mlp_adam_steps": ([P, P, P, P, P, P, C.c_int64, C.c_int64, C.c_float, P], st),
             "sgpm_probe_copy": ([P, C.c_uint64, C.c_int, C.POINTER(C.c_double)], st),
             "sgpm_probe_gather": ([P, C.c_uint64, C.c_int, C.c_int, C.POINTER(C.c_double)], st),
             "sgpm_probe_mlp": ([P, C.c_int64, C.c_int, P], st),
@@ -142,6 +143,7 @@ EXPORTED = ["sgpm_create", "sgpm_destroy", "sgpm_last_error", "sgpm_device_count
             "sgpm_pattern_free", "sgpm_options_default", "sgpm_estimate", "sgpm_estimate_counted",
             "sgpm_estimate_batch", "sgpm_exact_count", "sgpm_gs_sparsify", "sgpm_model_train", "sgpm_model_free",
             "sgpm_model_from_tables", "sgpm_model_table", "sgpm_model_info", "sgpm_mlp_forward", "sgpm_mlp_grad",
+            "sgpm_mlp_adam_steps",
             "sgpm_probe_copy", "sgpm_probe_gather", "sgpm_probe_mlp", "sgpm_host_canonicalise", "sgpm_host_plan", "sgpm_host_normal_quantile", "sgpm_host_predicted_error",
             "sgpm_host_next_window", "sgpm_host_hybrid_choice"]
 
@@ -404,3 +406,18 @@ def sgpm_mlp_grad(ctx, params, X, y):
     out = np.zeros(MLP_NPARAMS, dtype=np.float32)
     _check(ctx, lib().sgpm_mlp_grad(ctx, p.ctypes.data, x.ctypes.data, yy.ctypes.data, x.shape[0], out.ctypes.data))
     return out
+
+
+def sgpm_mlp_adam_steps(ctx, params, m, v, X, y, nsteps, B, lr, beta_pow):
+    """Adam on nsteps minibatches of B rows; returns new (params, m, v, beta_pow)."""
+    p = np.array(params, dtype=np.float32)
+    mm = np.array(m, dtype=np.float32)
+    vv = np.array(v, dtype=np.float32)
+    bp = np.array(beta_pow, dtype=np.float32)
+    x = np.ascontiguousarray(X, dtype=np.float32)
+    yy = np.ascontiguousarray(y, dtype=np.float32)
+    if x.shape != (nsteps * B, 16) or yy.shape != (nsteps * B,) or p.shape != (MLP_NPARAMS,) or bp.shape != (2,):
+        raise ValueError("sgpm_mlp_adam_steps: shapes")
+    _check(ctx, lib().sgpm_mlp_adam_steps(ctx, p.ctypes.data, mm.ctypes.data, vv.ctypes.data, x.ctypes.data,
+                                          yy.ctypes.data, nsteps, B, lr, bp.ctypes.data))
+    return p, mm, vv, bp

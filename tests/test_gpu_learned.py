@@ -75,6 +75,36 @@ def test_mlp_gradients_match_oracle(S, O, ctx, N):
         assert err <= 1e-2 and (cos >= 0.999 or name == "b3"), (name, err, cos)
 
 
+@pytest.mark.parametrize("B", [200, 256, 1000])
+def test_adam_steps_equal_gradient_then_update(S, O, ctx, B):
+    """Each training step is the gradient kernel followed by the FP32 Adam update:
+    the fused launch (B <= 256) and the per-step launches (B > 256) both equal
+    sgpm_mlp_grad per minibatch plus the update written out in numpy float32,
+    bit for bit; the gradients themselves are checked against the oracle above."""
+    nsteps = 5
+    rng = np.random.default_rng(7 + B)
+    p0 = rand_params(rng, O)
+    X = rng.standard_normal((nsteps * B, 16)).astype(np.float32)
+    y = rng.standard_normal(nsteps * B).astype(np.float32)
+    z = np.zeros(S.MLP_NPARAMS, dtype=np.float32)
+    lr = np.float32(3e-3)
+    got_p, got_m, got_v, got_b = S.sgpm_mlp_adam_steps(ctx, p0, z, z, X, y, nsteps, B, lr, [1.0, 1.0])
+    f = np.float32
+    b1, b2, eps = f(0.9), f(0.999), f(1e-8)
+    P, m, v, bp = p0.astype(np.float32), z.copy(), z.copy(), np.ones(2, dtype=np.float32)
+    for s in range(nsteps):
+        g = S.sgpm_mlp_grad(ctx, P, X[s * B:(s + 1) * B], y[s * B:(s + 1) * B])
+        bp = bp * np.array([b1, b2], dtype=np.float32)
+        c1, c2 = f(1) - bp[0], f(1) - bp[1]
+        m = b1 * m + (f(1) - b1) * g
+        v = b2 * v + (f(1) - b2) * g * g
+        P = P - lr * (m / c1) / (np.sqrt(v / c2) + eps)
+    assert np.array_equal(got_b, bp)
+    assert np.array_equal(got_m, m) and np.array_equal(got_v, v)
+    assert np.array_equal(got_p, P), float(np.abs(got_p - P).max())
+    assert not np.array_equal(got_p, p0)
+
+
 @pytest.fixture(scope="module")
 def cl(S, O, synth, ctx):
     n = 5000
