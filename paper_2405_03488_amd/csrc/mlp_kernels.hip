@@ -76,7 +76,7 @@ __device__ __forceinline__ s4 frag_bt(const float* W2, int kb, int mb, int lane)
 // wave.  With BWD every wave of the block must call it (nrows may be 0): the
 // waves add their gradients into gacc (NPARAM floats of LDS) in wave order.
 template <bool BWD>
-__device__ void mlp_wave(const float* __restrict__ P, const float* __restrict__ X, const float* __restrict__ y,
+__device__ __forceinline__ void mlp_wave(const float* __restrict__ P, const float* __restrict__ X, const float* __restrict__ y,
                          int64_t row0, int nrows, float inv_batch, float* __restrict__ s_out, float* gacc,
                          float* lds /* 16 x 64 floats */) {
     const int lane = (int)(threadIdx.x & 63), col = lane & 15, grp = lane >> 4;
@@ -285,8 +285,9 @@ __global__ void adam_kernel(float* __restrict__ P, const float* __restrict__ gpa
 
 // Adam over nsteps consecutive minibatches of B rows in one workgroup, for
 // minibatches one gradient block covers (B <= 256): the weights stay in LDS
-// between steps, the moments in global memory (each thread owns the same
-// parameters every step), so a step costs no launch.  The arithmetic is that of
+// between steps and the moments in registers (thread t owns parameters
+// t + 256 k every step), so a step costs no launch and no global access but
+// its rows.  The arithmetic is that of
 // mlp_grad_kernel + adam_kernel step by step: the gradient rows split over the
 // four waves as grad_rows_per_wave gives them, the bias corrections from the
 // running products beta^t, carried in from the caller as pb1, pb2.
@@ -297,8 +298,16 @@ __global__ __launch_bounds__(256) void mlp_train_kernel(float* __restrict__ P, f
     __shared__ float lds[4][16 * NH];
     __shared__ float gacc[NPARAM];
     __shared__ float Pl[NPARAM];
+    constexpr int PPT = (NPARAM + 255) / 256;
     const int tid = (int)threadIdx.x, w = tid >> 6;
-    for (int i = tid; i < NPARAM; i += 256) Pl[i] = P[i];
+    float mr[PPT], vr[PPT];
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int i = tid + 256 * k;
+        mr[k] = i < NPARAM ? m[i] : 0.f;
+        vr[k] = i < NPARAM ? v[i] : 0.f;
+        if (i < NPARAM) Pl[i] = P[i];
+    }
     __syncthreads();
     const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f, inv = 1.f / (float)B;
     const int64_t r0 = (int64_t)w * per_wave;
@@ -308,17 +317,27 @@ __global__ __launch_bounds__(256) void mlp_train_kernel(float* __restrict__ P, f
         pb1 *= b1;
         pb2 *= b2;
         const float c1 = 1.f - pb1, c2 = 1.f - pb2;
-        for (int i = tid; i < NPARAM; i += 256) {
-            const float g = gacc[i];
-            const float mi = b1 * m[i] + (1.f - b1) * g;
-            const float vi = b2 * v[i] + (1.f - b2) * g * g;
-            m[i] = mi;
-            v[i] = vi;
-            Pl[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int i = tid + 256 * k;
+            if (i < NPARAM) {
+                const float g = gacc[i];
+                mr[k] = b1 * mr[k] + (1.f - b1) * g;
+                vr[k] = b2 * vr[k] + (1.f - b2) * g * g;
+                Pl[i] -= lr * (mr[k] / c1) / (sqrtf(vr[k] / c2) + eps);
+            }
         }
         __syncthreads();
     }
-    for (int i = tid; i < NPARAM; i += 256) P[i] = Pl[i];
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int i = tid + 256 * k;
+        if (i < NPARAM) {
+            P[i] = Pl[i];
+            m[i] = mr[k];
+            v[i] = vr[k];
+        }
+    }
 }
 
 }  // namespace
