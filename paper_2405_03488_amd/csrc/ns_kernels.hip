@@ -158,7 +158,10 @@ __global__ __launch_bounds__(256) void ns_window_kernel(DGraph g, Plan p, uint64
 //    weight and the digit columns of the weight's square, and adds them to the
 //    wave's sums in LDS (LDS atomics); the sums are normalised once per block.
 // MODE 0: uniform proposal; 1: learned proposal; 2: uniform with per-step set
-// sizes recorded for traced samples (training pilots)
+// sizes recorded for traced samples (training pilots).  CLQ: the plan is the
+// K-clique's, so every plan test folds at compile time; this build also leaves
+// out the trace and byte-count code, which halves the per-sample loop's
+// uniform-register spills to vector lanes.
 #ifndef SGPM_WAVE_BLOCKS_PER_CU
 #define SGPM_WAVE_BLOCKS_PER_CU 7
 #endif
@@ -235,7 +238,7 @@ __global__ __launch_bounds__(256, SGPM_WAVE_BLOCKS_PER_CU) void ns_wave_kernel(D
                 int32_t v[8];
                 uint64_t alo, ahi, b = 0, ov = 0;
                 uint32_t sz[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-                const uint32_t st = ns_sample<G, K, CLQ>(g, p, seed, tag, s, v, alo, ahi, ov, b, count_bytes != 0,
+                const uint32_t st = ns_sample<G, K, CLQ>(g, p, seed, tag, s, v, alo, ahi, ov, b, !CLQ && count_bytes != 0,
                                                          list, MODE == 1 ? &lal : nullptr, hist,
                                                          MODE == 2 ? sz : nullptr, &dr);
                 ovf |= ov;
@@ -258,7 +261,7 @@ __global__ __launch_bounds__(256, SGPM_WAVE_BLOCKS_PER_CU) void ns_wave_kernel(D
                     if (lane == 14) w = (uint32_t)(b >> 32);
                     rec[q * REC + lane] = w;
                 }
-                if (tr.buf && s >= tr.lo && s < tr.hi && lane < 16) {
+                if (!CLQ && tr.buf && s >= tr.lo && s < tr.hi && lane < 16) {
                     uint32_t w = 0;
                     if (lane < 2) {
                         w = (uint32_t)(s >> (32 * lane));
@@ -298,7 +301,7 @@ __global__ __launch_bounds__(256, SGPM_WAVE_BLOCKS_PER_CU) void ns_wave_kernel(D
                     h = fmix64(h ^ ((uint64_t)d[3] << 32 | d[2]));
                     atomicAdd(&wsum[12], (unsigned long long)h);
                 }
-                if (count_bytes) atomicAdd(&wsum[13], (unsigned long long)((uint64_t)r[14] << 32 | r[13]));
+                if (!CLQ && count_bytes) atomicAdd(&wsum[13], (unsigned long long)((uint64_t)r[14] << 32 | r[13]));
                 if (st == 0xFFu) {
                     // digits of X and the digit columns of X^2 (low and high halves of the digit products)
                     uint64_t c2[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -410,7 +413,9 @@ hipError_t launch_wave_mode(const DGraph& g, const Plan& p, uint64_t seed, uint3
                             const LaunchCfg& cfg, unsigned long long* ticket, unsigned long long* partials,
                             int checksum, int count_bytes, const TraceArgs& tr, const LearnArgs& la, hipStream_t st) {
     const dim3 grid((unsigned)cfg.blocks), block(256);
-    const bool clq = MODE != 2 && plan_is_clique(p);
+    // the clique specialisation carries no trace or byte count (the generic
+    // kernel computes the same walks and serves those requests)
+    const bool clq = MODE != 2 && plan_is_clique(p) && !tr.buf && !count_bytes;
 #define SGPM_WAVE_CASE(KK)                                                                                        \
     case KK:                                                                                                      \
         if (clq && KK >= 3 && KK <= 6)                                                                            \
