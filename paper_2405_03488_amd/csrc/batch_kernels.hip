@@ -237,18 +237,8 @@ __device__ __forceinline__ void run_tile(const BatchQuery& Q, uint64_t s0, uint6
                 alo = 0;
                 ahi = 0;
             }
-            if (lane < 13) {  // record: 0-7 the walk, 8 the status, 9-12 X
-                uint32_t w = 0;
-#pragma unroll
-                for (int i = 0; i < 8; ++i)
-                    if (lane == i) w = (uint32_t)v[i];
-                if (lane == 8) w = st;
-                if (lane == 9) w = (uint32_t)alo;
-                if (lane == 10) w = (uint32_t)(alo >> 32);
-                if (lane == 11) w = (uint32_t)ahi;
-                if (lane == 12) w = (uint32_t)(ahi >> 32);
-                rec[q * BREC + lane] = w;
-            }
+            // record: 0-7 the walk, 8 the status, 9-12 X
+            if (lane == 0) write_record<KMAX>(rec + q * BREC, v, st, alo, ahi, 0);
         }
         __builtin_amdgcn_wave_barrier();
         if (lane < n) {
@@ -339,7 +329,7 @@ __global__ __launch_bounds__(256, batch_occupancy(KMAX)) void batch_kernel(const
     const int lane = (int)(threadIdx.x & 63);
     const int wid = (int)(threadIdx.x >> 6);
     __shared__ int32_t s_list[LDS_WORDS];
-    __shared__ uint32_t s_rec[4][BGMAX * BREC];
+    __shared__ __align__(16) uint32_t s_rec[4][BGMAX * BREC];
     __shared__ unsigned long long s_wsum[4][16];
     unsigned long long* wsum = s_wsum[wid];
     if (lane < 16) wsum[lane] = 0ull;

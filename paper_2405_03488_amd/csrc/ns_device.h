@@ -539,6 +539,21 @@ __device__ __forceinline__ bool next_ticket(unsigned long long* __restrict__ tk,
     return false;
 }
 
+// A sample's 16-word LDS record from wave-uniform values, four 16-byte
+// stores by one lane: words 0..K-1 the walk, 8 the status, 9-12 the weight
+// X (four 32-bit digits), 13-14 the bytes read, 15 zero.  rec is 16-byte aligned.
+template <int K>
+__device__ __forceinline__ void write_record(uint32_t* rec, const int32_t* v, uint32_t st, uint64_t alo,
+                                             uint64_t ahi, uint64_t b) {
+    uint4* r4 = reinterpret_cast<uint4*>(rec);
+    r4[0] = make_uint4((uint32_t)v[0], (uint32_t)v[1], K > 2 ? (uint32_t)v[2] : 0u, K > 3 ? (uint32_t)v[3] : 0u);
+    if (K > 4)
+        r4[1] = make_uint4((uint32_t)v[4], K > 5 ? (uint32_t)v[5] : 0u, K > 6 ? (uint32_t)v[6] : 0u,
+                           K > 7 ? (uint32_t)v[7] : 0u);
+    r4[2] = make_uint4(st, (uint32_t)alo, (uint32_t)(alo >> 32), (uint32_t)ahi);
+    r4[3] = make_uint4((uint32_t)(ahi >> 32), (uint32_t)b, (uint32_t)(b >> 32), 0u);
+}
+
 __device__ __forceinline__ uint64_t wave_sum(uint64_t x) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);

@@ -187,7 +187,7 @@ __global__ __launch_bounds__(256, SGPM_WAVE_BLOCKS_PER_CU) void ns_wave_kernel(D
     const int wid = (int)(threadIdx.x >> 6);
     __shared__ int32_t s_list[LDS_WORDS];
     __shared__ uint32_t s_hist[4][32];
-    __shared__ uint32_t s_rec[4][GMAX * REC];
+    __shared__ __align__(16) uint32_t s_rec[4][GMAX * REC];
     __shared__ unsigned long long s_wsum[4][16];
     uint32_t* hist = s_hist[wid];
     uint32_t* rec = s_rec[wid];
@@ -246,21 +246,9 @@ __global__ __launch_bounds__(256, SGPM_WAVE_BLOCKS_PER_CU) void ns_wave_kernel(D
                     alo = 0;
                     ahi = 0;
                 }
-                // the sample's record: lanes 0-7 the walk, 8 the status, 9-12 X, 13-14 bytes
-                if (lane < REC - 1) {
-                    uint32_t w = 0;
-#pragma unroll
-                    for (int i = 0; i < 8; ++i)
-                        if (lane == i) w = (uint32_t)v[i];
-                    if (lane == 8) w = st;
-                    if (lane == 9) w = (uint32_t)alo;
-                    if (lane == 10) w = (uint32_t)(alo >> 32);
-                    if (lane == 11) w = (uint32_t)ahi;
-                    if (lane == 12) w = (uint32_t)(ahi >> 32);
-                    if (lane == 13) w = (uint32_t)b;
-                    if (lane == 14) w = (uint32_t)(b >> 32);
-                    rec[q * REC + lane] = w;
-                }
+                // the sample's record (words 0-7 the walk, 8 the status, 9-12 X,
+                // 13-14 bytes), written by lane 0 from the uniform registers
+                if (lane == 0) write_record<K>(rec + q * REC, v, st, alo, ahi, b);
                 if (!CLQ && tr.buf && s >= tr.lo && s < tr.hi && lane < 16) {
                     uint32_t w = 0;
                     if (lane < 2) {
