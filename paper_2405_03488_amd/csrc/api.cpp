@@ -48,13 +48,13 @@ sgpm_status ensure_scratch(sgpm_ctx* c, size_t blocks, size_t slots) {
     return SGPM_OK;
 }
 
-int blocks_for(sgpm_ctx* c, int lanes) {
+int blocks_for(sgpm_ctx* c, int lanes, bool clique_kernel = false) {
     // enough 256-thread blocks to fill every CU at the kernel's occupancy
-    return c->cus * ns_blocks_per_cu(lanes);
+    return c->cus * (clique_kernel ? ns_clique_blocks_per_cu() : ns_blocks_per_cu(lanes));
 }
 
 int largest_grid(sgpm_ctx* c) {
-    int m = 1;
+    int m = blocks_for(c, 64, true);
     for (int l : {1, 4, 16, 64}) m = std::max(m, blocks_for(c, l));
     return m;
 }
@@ -276,7 +276,7 @@ sgpm_status enqueue_range(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_
                           uint64_t span = 0) {
     LaunchCfg cfg;
     cfg.lanes = lanes;
-    cfg.blocks = blocks_for(c, lanes);
+    cfg.blocks = blocks_for(c, lanes, lanes == 64 && !la.table && wave_uses_clique_kernel(p, tr, la, count_bytes));
     // Tickets of about 1/16 of a wave's share of the window: few enough that
     // the single ticket counter (a device-scope atomic, about 8e7 per second
     // on one address) is not the bottleneck, many enough to balance skewed

@@ -32,7 +32,8 @@ sgpm_status autotune_tile(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_
     sgpm_result r;
     sgpm_status st = ns_estimate_solo(c, g, p, po, &r, 0);
     if (st != SGPM_OK && st != SGPM_NOT_CONVERGED) return st;
-    const double waves = (double)c->cus * (double)ns_blocks_per_cu(64) * 4.0;
+    const bool clq = wave_uses_clique_kernel(p, TraceArgs{}, LearnArgs{}, 0);
+    const double waves = (double)c->cus * (double)(clq ? ns_clique_blocks_per_cu() : ns_blocks_per_cu(64)) * 4.0;
     const double wave_time_per_sample = r.seconds_kernel * waves / (double)po.fixed_n;
 #ifndef SGPM_TILE_US
 #define SGPM_TILE_US 200

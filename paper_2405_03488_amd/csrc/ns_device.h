@@ -95,7 +95,9 @@ __device__ __forceinline__ int32_t uni(int32_t x) {
     if constexpr (G == 64) return rfl(x);
     else return x;
 }
-constexpr int LDS_WORDS = 4096;  // candidate lists per block (16 KB)
+// candidate lists per block (14 KB): with the records and sums, eight
+// one-sample-per-wave blocks fit a CU's 160 KB of LDS
+constexpr int LDS_WORDS = 3584;
 
 // first index in [lo, hi) with row[i] >= x, galloping forward from lo
 __device__ __forceinline__ int32_t gallop(const int32_t* __restrict__ row, int32_t lo, int32_t hi, int32_t x) {

@@ -162,9 +162,10 @@ __global__ __launch_bounds__(256) void ns_window_kernel(DGraph g, Plan p, uint64
 // K-clique's, so every plan test folds at compile time; this build also leaves
 // out the trace and byte-count code, which halves the per-sample loop's
 // uniform-register spills to vector lanes.
-#ifndef SGPM_WAVE_BLOCKS_PER_CU
-#define SGPM_WAVE_BLOCKS_PER_CU 7
-#endif
+// Blocks per CU each one-sample-per-wave kernel is compiled for: the uniform
+// clique kernels fit 64 VGPRs with their per-sample loop free of spills, and
+// eight blocks keep 8 % more samples in flight; the others need 72 VGPRs.
+constexpr int wave_occupancy(int mode, bool clq) { return clq && mode == 0 ? 8 : 7; }
 constexpr int GMAX = 16;  // samples per group (records live in lanes 0..15)
 constexpr int REC = 16;   // words per sample record
 
@@ -176,7 +177,7 @@ __device__ __forceinline__ uint32_t draw_of_slot(int t) {
 }
 
 template <int MODE, int K, bool CLQ>
-__global__ __launch_bounds__(256, SGPM_WAVE_BLOCKS_PER_CU) void ns_wave_kernel(DGraph g, Plan p, uint64_t seed, uint32_t tag, uint64_t s0,
+__global__ __launch_bounds__(256, wave_occupancy(MODE, CLQ)) void ns_wave_kernel(DGraph g, Plan p, uint64_t seed, uint32_t tag, uint64_t s0,
                                                       uint64_t s1, int spl, unsigned long long* __restrict__ ticket,
                                                       unsigned long long* __restrict__ partials, int checksum,
                                                       int count_bytes, TraceArgs tr, LearnArgs la) {
@@ -396,14 +397,19 @@ bool plan_is_clique(const Plan& p) {
     return true;
 }
 
+// whether a one-sample-per-wave launch takes the clique specialisation: a
+// clique plan, no trace or byte count (the generic kernel computes the same
+// walks and serves those requests), not the pilots' set-size mode
+bool wave_uses_clique_kernel(const Plan& p, const TraceArgs& tr, const LearnArgs& la, int count_bytes) {
+    return plan_is_clique(p) && p.k <= 6 && !tr.buf && !count_bytes && (la.table || !tr.sizes);
+}
+
 template <int MODE>
 hipError_t launch_wave_mode(const DGraph& g, const Plan& p, uint64_t seed, uint32_t tag, uint64_t s0, uint64_t s1,
                             const LaunchCfg& cfg, unsigned long long* ticket, unsigned long long* partials,
                             int checksum, int count_bytes, const TraceArgs& tr, const LearnArgs& la, hipStream_t st) {
     const dim3 grid((unsigned)cfg.blocks), block(256);
-    // the clique specialisation carries no trace or byte count (the generic
-    // kernel computes the same walks and serves those requests)
-    const bool clq = MODE != 2 && plan_is_clique(p) && !tr.buf && !count_bytes;
+    const bool clq = MODE != 2 && wave_uses_clique_kernel(p, tr, la, count_bytes);
 #define SGPM_WAVE_CASE(KK)                                                                                        \
     case KK:                                                                                                      \
         if (clq && KK >= 3 && KK <= 6)                                                                            \
@@ -462,6 +468,17 @@ hipError_t launch_ns_window(const DGraph& g, const Plan& p, uint64_t seed, uint3
             return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+// Resident 256-thread blocks per CU of the uniform clique kernels.
+int ns_clique_blocks_per_cu() {
+    static int cache = 0;
+    if (cache) return cache;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ns_wave_kernel<0, 4, true>, 256, 0) != hipSuccess || nb < 1)
+        nb = 1;
+    cache = nb;
+    return nb;
 }
 
 // Resident 256-thread blocks per CU for the sampling kernel of a lane count.

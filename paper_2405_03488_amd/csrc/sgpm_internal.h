@@ -72,6 +72,8 @@ hipError_t launch_ns_window(const DGraph& g, const Plan& p, uint64_t seed, uint3
 hipError_t launch_reduce_partials(const unsigned long long* partials, int nblocks, unsigned long long* out20,
                                   hipStream_t st);
 int ns_blocks_per_cu(int lanes);
+int ns_clique_blocks_per_cu();  // the uniform clique kernels (compiled for more blocks)
+bool wave_uses_clique_kernel(const Plan& p, const TraceArgs& tr, const LearnArgs& la, int count_bytes);
 hipError_t launch_fill_u64(unsigned long long* p, uint64_t n, unsigned long long v, hipStream_t st);
 
 // persistent batch (batch_kernels.hip)
