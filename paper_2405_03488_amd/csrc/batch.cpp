@@ -130,7 +130,11 @@ sgpm_status batch_estimate(sgpm_ctx* c, int nq, const sgpm_graph_t* graphs, cons
     int kmax = 2;
     for (int i = 0; i < nq; i++) kmax = std::max(kmax, patterns[i]->plan.k);
     kmax = batch_kmax(kmax);
-    if (c->batch_nq != nq || c->batch_kmax != kmax) {
+    // every query a clique of at most 6 vertices: tiles run the clique sampler
+    bool clq = kmax <= 6;
+    for (int i = 0; i < nq; i++)
+        clq = clq && plan_is_clique(patterns[i]->plan) && patterns[i]->plan.k >= 3 && patterns[i]->plan.k <= kmax;
+    if (c->batch_nq != nq || c->batch_kmax != kmax || c->batch_clq != clq) {
         if (c->batch_exec) (void)hipGraphExecDestroy(c->batch_exec);
         if (c->batch_graph) (void)hipGraphDestroy(c->batch_graph);
         c->batch_exec = nullptr;
@@ -142,7 +146,7 @@ sgpm_status batch_estimate(sgpm_ctx* c, int nq, const sgpm_graph_t* graphs, cons
         HIP_TRY(c, hipMalloc(&c->d_bq, total));
         HIP_TRY(c, hipHostMalloc(&c->h_bq, total, hipHostMallocDefault));
         if (!c->batch_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->batch_stream, hipStreamNonBlocking));
-        const int blocks = c->cus * batch_blocks_per_cu(kmax);
+        const int blocks = c->cus * batch_blocks_per_cu(kmax, clq);
         char* d = (char*)c->d_bq;
         char* h = (char*)c->h_bq;
         BatchQuery* dq = (BatchQuery*)d;
@@ -150,12 +154,13 @@ sgpm_status batch_estimate(sgpm_ctx* c, int nq, const sgpm_graph_t* graphs, cons
         unsigned long long* dact = (unsigned long long*)(d + qbytes + sbytes);
         HIP_TRY(c, hipStreamBeginCapture(c->batch_stream, hipStreamCaptureModeThreadLocal));
         HIP_TRY(c, hipMemcpyAsync(d, h, qbytes + sbytes + 8, hipMemcpyHostToDevice, c->batch_stream));
-        HIP_TRY(c, launch_batch(dq, ds, nq, dact, blocks, kmax, c->batch_stream));
+        HIP_TRY(c, launch_batch(dq, ds, nq, dact, blocks, kmax, clq, c->batch_stream));
         HIP_TRY(c, hipMemcpyAsync(h + qbytes, d + qbytes, sbytes, hipMemcpyDeviceToHost, c->batch_stream));
         HIP_TRY(c, hipStreamEndCapture(c->batch_stream, &c->batch_graph));
         HIP_TRY(c, hipGraphInstantiate(&c->batch_exec, c->batch_graph, nullptr, nullptr, 0));
         c->batch_nq = nq;
         c->batch_kmax = kmax;
+        c->batch_clq = clq;
     }
     char* h = (char*)c->h_bq;
     std::memcpy(h, hq.data(), qbytes);

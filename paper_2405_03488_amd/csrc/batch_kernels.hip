@@ -206,11 +206,13 @@ __device__ __attribute__((noinline)) void complete_window(const BatchQuery& Q, B
 // checksum, 14 hits), which the caller adds to the query's window columns.
 constexpr int BGMAX = 16, BREC = 16;
 
-template <int KMAX>
+// CLQ: the query is the KMAX-clique (its compiled plan is the clique's), and the
+// sampler is the clique specialisation of the solo kernels
+template <int KMAX, bool CLQ>
 __device__ __forceinline__ void run_tile(const BatchQuery& Q, uint64_t s0, uint64_t s1, int32_t* list, uint32_t* rec,
                                          unsigned long long* wsum, uint64_t& ovf) {
     const int lane = (int)(threadIdx.x & 63);
-    const int K = Q.p.k;
+    const int K = CLQ ? KMAX : Q.p.k;
     const int D = K - 1;  // draws per sample: 0, 2, .., k-1
     const int GS = (64 / D) < BGMAX ? (64 / D) : BGMAX;
     for (uint64_t gb = s0; gb < s1; gb += (uint64_t)GS) {
@@ -230,8 +232,8 @@ __device__ __forceinline__ void run_tile(const BatchQuery& Q, uint64_t s0, uint6
             dr.base = q * D;
             int32_t v[8];
             uint64_t alo, ahi, b = 0, ov = 0;
-            const uint32_t st = ns_sample<64, KMAX>(Q.g, Q.p, Q.seed, Q.tag, s, v, alo, ahi, ov, b, false, list, nullptr,
-                                              nullptr, nullptr, &dr);
+            const uint32_t st = ns_sample<64, KMAX, CLQ>(Q.g, Q.p, Q.seed, Q.tag, s, v, alo, ahi, ov, b, false, list,
+                                                         nullptr, nullptr, nullptr, &dr);
             ovf |= ov;
             if (st != 0xFFu) {
                 alo = 0;
@@ -280,8 +282,20 @@ __device__ __forceinline__ void run_tile(const BatchQuery& Q, uint64_t s0, uint6
 #define SGPM_BATCH_IDLE_SLEEP 8
 #endif
 // blocks per CU the kernel is compiled for: the most at which the sampling
-// loops of that pattern bound keep every value in registers
-constexpr int batch_occupancy(int kmax) { return kmax <= 5 ? 6 : kmax == 6 ? 5 : 4; }
+// loops of that pattern bound keep every value in registers (the all-clique
+// build inlines one sampler per clique size, so it needs more of them)
+constexpr int batch_occupancy(int kmax, bool clq) { return clq ? (kmax <= 4 ? 6 : 5) : kmax <= 5 ? 6 : kmax == 6 ? 5 : 4; }
+
+// a tile of a k-clique query (3 <= k <= KMAX) with the sampler compiled for k
+template <int KMAX>
+__device__ __forceinline__ void clique_tile(int k, const BatchQuery& Q, uint64_t s0, uint64_t s1, int32_t* list,
+                                            uint32_t* rec, unsigned long long* wsum, uint64_t& ovf) {
+    if (k == KMAX) {
+        run_tile<KMAX, true>(Q, s0, s1, list, rec, wsum, ovf);
+    } else if constexpr (KMAX > 3) {
+        clique_tile<KMAX - 1>(k, Q, s0, s1, list, rec, wsum, ovf);
+    }
+}
 
 // The wave's sums of one window, held in its LDS columns across tiles, into the
 // query's window columns (the copy of this block's XCD: blocks are dispatched
@@ -314,6 +328,8 @@ __device__ __forceinline__ void flush_held(const BatchQuery* queries, BatchState
 }
 
 // KMAX: the largest pattern size of the batch (the sampler is compiled for it).
+// ALLCLQ: every query is a clique of at most KMAX vertices, and each tile runs
+// the clique sampler compiled for its query's size.
 //
 // Scheduling: a wave takes tiles from the query it served last while that
 // query's window has tiles left, trying its own XCD's counter first and the
@@ -323,8 +339,8 @@ __device__ __forceinline__ void flush_held(const BatchQuery* queries, BatchState
 // wave keeps its sums in LDS until it moves to another (query, window) or finds
 // no tile; a window cannot complete while a wave holds part of it, so every
 // wave holding sums of a finished window flushes at its next poll.
-template <int KMAX>
-__global__ __launch_bounds__(256, batch_occupancy(KMAX)) void batch_kernel(const BatchQuery* __restrict__ queries, BatchState* __restrict__ states,
+template <int KMAX, bool ALLCLQ>
+__global__ __launch_bounds__(256, batch_occupancy(KMAX, ALLCLQ)) void batch_kernel(const BatchQuery* __restrict__ queries, BatchState* __restrict__ states,
                                                     int nq, unsigned long long* __restrict__ active) {
     const int lane = (int)(threadIdx.x & 63);
     const int wid = (int)(threadIdx.x >> 6);
@@ -393,7 +409,10 @@ __global__ __launch_bounds__(256, batch_occupancy(KMAX)) void batch_kernel(const
         const uint64_t T = (uint64_t)Q.tile;
         const uint64_t s0 = cws + t * T, s1 = min(s0 + T, cwe);
         uint64_t ovf = 0;
-        run_tile<KMAX>(Q, s0, s1, s_list + wid * (LDS_WORDS / 4), s_rec[wid], wsum, ovf);
+        if constexpr (ALLCLQ)
+            clique_tile<KMAX>(Q.p.k, Q, s0, s1, s_list + wid * (LDS_WORDS / 4), s_rec[wid], wsum, ovf);
+        else
+            run_tile<KMAX, false>(Q, s0, s1, s_list + wid * (LDS_WORDS / 4), s_rec[wid], wsum, ovf);
         hq = q;
         hw = w;
         hws = cws;
@@ -408,29 +427,34 @@ __global__ __launch_bounds__(256, batch_occupancy(KMAX)) void batch_kernel(const
 // the compiled bound for a batch whose largest pattern has k vertices
 int batch_kmax(int k) { return k <= 3 ? 3 : k <= 6 ? k : 8; }
 
-int batch_blocks_per_cu(int kmax) {
+int batch_blocks_per_cu(int kmax, bool clq) {
     int nb = 0;
     hipError_t e = hipErrorInvalidValue;
+#define SGPM_BATCH_OCC(KK, CC) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_kernel<KK, CC>, 256, 0)
     switch (batch_kmax(kmax)) {
-        case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_kernel<3>, 256, 0); break;
-        case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_kernel<4>, 256, 0); break;
-        case 5: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_kernel<5>, 256, 0); break;
-        case 6: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_kernel<6>, 256, 0); break;
-        default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_kernel<8>, 256, 0); break;
+        case 3: if (clq) SGPM_BATCH_OCC(3, true); else SGPM_BATCH_OCC(3, false); break;
+        case 4: if (clq) SGPM_BATCH_OCC(4, true); else SGPM_BATCH_OCC(4, false); break;
+        case 5: if (clq) SGPM_BATCH_OCC(5, true); else SGPM_BATCH_OCC(5, false); break;
+        case 6: if (clq) SGPM_BATCH_OCC(6, true); else SGPM_BATCH_OCC(6, false); break;
+        default: SGPM_BATCH_OCC(8, false); break;
     }
+#undef SGPM_BATCH_OCC
     if (e != hipSuccess || nb < 1) nb = 1;
     return nb;
 }
 
 hipError_t launch_batch(const BatchQuery* q, BatchState* s, int nq, unsigned long long* active, int blocks,
-                        int kmax, hipStream_t st) {
+                        int kmax, bool clq, hipStream_t st) {
+#define SGPM_BATCH_LAUNCH(KK, CC) \
+    hipLaunchKernelGGL((batch_kernel<KK, CC>), dim3((unsigned)blocks), dim3(256), 0, st, q, s, nq, active)
     switch (batch_kmax(kmax)) {
-        case 3: hipLaunchKernelGGL(batch_kernel<3>, dim3((unsigned)blocks), dim3(256), 0, st, q, s, nq, active); break;
-        case 4: hipLaunchKernelGGL(batch_kernel<4>, dim3((unsigned)blocks), dim3(256), 0, st, q, s, nq, active); break;
-        case 5: hipLaunchKernelGGL(batch_kernel<5>, dim3((unsigned)blocks), dim3(256), 0, st, q, s, nq, active); break;
-        case 6: hipLaunchKernelGGL(batch_kernel<6>, dim3((unsigned)blocks), dim3(256), 0, st, q, s, nq, active); break;
-        default: hipLaunchKernelGGL(batch_kernel<8>, dim3((unsigned)blocks), dim3(256), 0, st, q, s, nq, active); break;
+        case 3: if (clq) SGPM_BATCH_LAUNCH(3, true); else SGPM_BATCH_LAUNCH(3, false); break;
+        case 4: if (clq) SGPM_BATCH_LAUNCH(4, true); else SGPM_BATCH_LAUNCH(4, false); break;
+        case 5: if (clq) SGPM_BATCH_LAUNCH(5, true); else SGPM_BATCH_LAUNCH(5, false); break;
+        case 6: if (clq) SGPM_BATCH_LAUNCH(6, true); else SGPM_BATCH_LAUNCH(6, false); break;
+        default: SGPM_BATCH_LAUNCH(8, false); break;
     }
+#undef SGPM_BATCH_LAUNCH
     return hipGetLastError();
 }
 

@@ -73,6 +73,7 @@ hipError_t launch_reduce_partials(const unsigned long long* partials, int nblock
                                   hipStream_t st);
 int ns_blocks_per_cu(int lanes);
 int ns_clique_blocks_per_cu();  // the uniform clique kernels (compiled for more blocks)
+bool plan_is_clique(const Plan& p);
 bool wave_uses_clique_kernel(const Plan& p, const TraceArgs& tr, const LearnArgs& la, int count_bytes);
 hipError_t launch_fill_u64(unsigned long long* p, uint64_t n, unsigned long long v, hipStream_t st);
 
@@ -107,10 +108,10 @@ struct BatchState {
     double eps_hat;
     uint64_t n;
 };
-int batch_blocks_per_cu(int kmax);
+int batch_blocks_per_cu(int kmax, bool clq);
 int batch_kmax(int k);
 hipError_t launch_batch(const BatchQuery* q, BatchState* s, int nq, unsigned long long* active, int blocks,
-                        int kmax, hipStream_t st);
+                        int kmax, bool clq, hipStream_t st);
 
 struct NsExtra {
     LearnArgs la;        // learned proposal (table nullptr = uniform)
@@ -187,6 +188,7 @@ struct sgpm_ctx {
     std::map<std::tuple<const void*, std::string>, int> ns_tuned;  // solo lanes per sample per (graph, plan)
     int batch_nq = 0;
     int batch_kmax = 0;
+    bool batch_clq = false;
     void* d_bq = nullptr;
     void* h_bq = nullptr;
     hipStream_t batch_stream = nullptr;
