@@ -24,11 +24,14 @@ constexpr int SLOT_WORDS = 32;  // host slot of one launch: [1..20] its sums
 sgpm_status ensure_scratch(sgpm_ctx* c, size_t blocks, size_t slots) {
     if (blocks > c->partial_blocks) {
         if (c->d_partials) (void)hipFree(c->d_partials);
-        c->d_partials = nullptr;
+        if (c->d_partials2) (void)hipFree(c->d_partials2);
+        c->d_partials = c->d_partials2 = nullptr;
         c->partial_blocks = 0;
         HIP_TRY(c, hipMalloc(&c->d_partials, blocks * PF_N * sizeof(unsigned long long)));
+        HIP_TRY(c, hipMalloc(&c->d_partials2, blocks * PF_N * sizeof(unsigned long long)));
         c->partial_blocks = blocks;
     }
+    if (!c->st2) HIP_TRY(c, hipStreamCreateWithFlags(&c->st2, hipStreamNonBlocking));
     if (slots > c->nslots) {
         if (c->h_slots) (void)hipHostFree(c->h_slots);
         if (c->d_tickets) (void)hipFree(c->d_tickets);
@@ -91,7 +94,10 @@ sgpm_status sgpm_create(sgpm_ctx_t* out, int hip_device, void* hip_stream) {
 sgpm_status sgpm_destroy(sgpm_ctx_t c) {
     if (!c) return SGPM_EINVAL;
     (void)hipSetDevice(c->dev);
+    if (c->st2) (void)hipStreamSynchronize(c->st2);
     if (c->d_partials) (void)hipFree(c->d_partials);
+    if (c->d_partials2) (void)hipFree(c->d_partials2);
+    if (c->st2) (void)hipStreamDestroy(c->st2);
     if (c->h_slots) (void)hipHostFree(c->h_slots);
     if (c->d_tickets) (void)hipFree(c->d_tickets);
     for (hipEvent_t e : c->kev) (void)hipEventDestroy(e);
@@ -273,7 +279,7 @@ void absorb(NsState& s, const unsigned long long* sums) {
 // as the whole window would be.
 sgpm_status enqueue_range(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_options& o, uint64_t s0, uint64_t s1,
                           int lanes, size_t slot, const TraceArgs& tr, int count_bytes, const LearnArgs& la,
-                          uint64_t span = 0) {
+                          uint64_t span = 0, bool second_stream = false) {
     LaunchCfg cfg;
     cfg.lanes = lanes;
     cfg.blocks = blocks_for(c, lanes, lanes == 64 && !la.table && wave_uses_clique_kernel(p, tr, la, count_bytes));
@@ -297,19 +303,21 @@ sgpm_status enqueue_range(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_
     // partials sized for the largest grid once, so no buffer in flight is freed
     sgpm_status st = ensure_scratch(c, (size_t)largest_grid(c), slot + 1);
     if (st != SGPM_OK) return st;
+    hipStream_t sq = second_stream ? c->st2 : c->st;
+    unsigned long long* parts = second_stream ? c->d_partials2 : c->d_partials;
     unsigned long long* tk = c->d_tickets + slot * NTK * TK_STRIDE;
-    HIP_TRY(c, launch_fill_u64(tk, (uint64_t)NTK * TK_STRIDE, 0ull, c->st));
+    HIP_TRY(c, launch_fill_u64(tk, (uint64_t)NTK * TK_STRIDE, 0ull, sq));
     while (c->kev.size() < 3 * (slot + 1)) {
         hipEvent_t ev;
         HIP_TRY(c, hipEventCreate(&ev));
         c->kev.push_back(ev);
     }
-    HIP_TRY(c, hipEventRecord(c->kev[3 * slot], c->st));
-    HIP_TRY(c, launch_ns_window(g->view(), p, o.seed, o.query_tag, s0, s1, cfg, tk,
-                                c->d_partials, o.checksum, count_bytes, tr, la, c->st));
-    HIP_TRY(c, hipEventRecord(c->kev[3 * slot + 1], c->st));
-    HIP_TRY(c, launch_reduce_partials(c->d_partials, cfg.blocks, c->dh_slots + slot * SLOT_WORDS + 1, c->st));
-    HIP_TRY(c, hipEventRecord(c->kev[3 * slot + 2], c->st));
+    HIP_TRY(c, hipEventRecord(c->kev[3 * slot], sq));
+    HIP_TRY(c, launch_ns_window(g->view(), p, o.seed, o.query_tag, s0, s1, cfg, tk, parts, o.checksum, count_bytes,
+                                tr, la, sq));
+    HIP_TRY(c, hipEventRecord(c->kev[3 * slot + 1], sq));
+    HIP_TRY(c, launch_reduce_partials(parts, cfg.blocks, c->dh_slots + slot * SLOT_WORDS + 1, sq));
+    HIP_TRY(c, hipEventRecord(c->kev[3 * slot + 2], sq));
     return SGPM_OK;
 }
 
@@ -373,15 +381,23 @@ sgpm_status ns_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_op
     int windows = 0, launches = 0;
     bool converged = false;
     sgpm_status status = SGPM_OK;
-    // One window at a time: the host's share of a window (launch, wait, exact
-    // statistics) is a few microseconds, so a window queued ahead would only
-    // add device work past the stop.  Windows use slot 0; autotune pieces 2..9.
+    // Windows are decided in order, one at a time.  A launch ends with a tail
+    // (its last tickets finish at different times) and the next one starts
+    // with a ramp, about 0.1 ms together; so when the error of the windows so
+    // far predicts that the next window cannot stop either (the samples needed,
+    // n (eps_hat / eps)^2, exceed its end by 10 %), the window after it is
+    // queued at once on the second stream, where it fills the CUs the first
+    // one's tail leaves idle.  The stop rule is unchanged: a window queued
+    // ahead is absorbed only if every earlier one missed, and otherwise waited
+    // for and dropped.  Windows use slots 0 (stream st) and 1 (st2);
+    // autotune pieces 2..9 (st).
     struct Win {
         uint64_t a, b;
         size_t slot0, nslots;
     };
     std::deque<Win> inflight;
-    const size_t depth = 1;
+    size_t depth = 1;
+    const bool may_queue_ahead = o.mode != SGPM_MODE_FIXED_N && !ntr && !count_bytes;
     uint64_t queued = 0;
     size_t last_done = SIZE_MAX;
     HIP_TRY(c, hipEventRecord(e0, c->st));
@@ -447,9 +463,12 @@ sgpm_status ns_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_op
                 queued = nx;
                 break;
             }
-            // short windows before tuning: one sample per wave, not remembered
-            const size_t slot = 0;
-            status = enqueue_range(c, g, p, o, queued, nx, lanes ? lanes : 64, slot, tr, count_bytes, la);
+            // short windows before tuning: one sample per wave, not remembered;
+            // the slot (and stream) no window in flight holds
+            bool busy0 = false;
+            for (const Win& w : inflight) busy0 = busy0 || w.slot0 == 0;
+            const size_t slot = busy0 ? 1 : 0;
+            status = enqueue_range(c, g, p, o, queued, nx, lanes ? lanes : 64, slot, tr, count_bytes, la, 0, slot == 1);
             if (status != SGPM_OK) return status;
             inflight.push_back(Win{queued, nx, slot, 1});
             queued = nx;
@@ -480,7 +499,16 @@ sgpm_status ns_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_op
             break;
         }
         if (o.max_samples && s.n >= o.max_samples) break;
+        depth = 1;
+        if (may_queue_ahead && std::isfinite(eh) && eh > 0) {
+            const uint64_t next_end = inflight.empty() ? next_window_end(s.n, o) : inflight.back().b;
+            const double r = eh / o.eps, need = (double)s.n * r * r;
+            if (need > 1.1 * (double)next_end) depth = 2;
+        }
     }
+    // windows queued ahead past the stop: wait for them (their slots and the
+    // second stream are reused by the next call) and drop their sums
+    for (const Win& w : inflight) HIP_TRY(c, hipEventSynchronize(c->kev[3 * (w.slot0 + w.nslots - 1) + 2]));
     if (last_done != SIZE_MAX) {
         float ms = 0;
         HIP_TRY(c, hipEventElapsedTime(&ms, e0, c->kev[3 * last_done + 2]));

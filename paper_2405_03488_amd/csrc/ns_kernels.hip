@@ -209,10 +209,22 @@ __global__ __launch_bounds__(256, wave_occupancy(MODE, CLQ)) void ns_wave_kernel
     uint64_t tstat = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const uint64_t ntickets = (s1 - s0 + (uint64_t)spl - 1) / (uint64_t)spl;
     int tk_cur = (int)(blockIdx.x % NTK), tk_left = NTK;
+    // tickets 0 .. nwaves-1 go to the waves by index, without an atomic (the
+    // launch's first fetches would all hit the counters at once); the rest
+    // come from the counters
+    bool first = true;
+    const uint64_t ndyn = ntickets > nwaves ? ntickets - nwaves : 0;
     for (;;) {
         uint64_t tt = 0;
         if (ticket) {
-            if (!next_ticket(ticket, ntickets, tk_cur, tk_left, tt)) break;
+            if (first) {
+                first = false;
+                tt = tstat;
+            } else {
+                uint64_t td = 0;
+                if (ndyn == 0 || !next_ticket(ticket, ndyn, tk_cur, tk_left, td)) break;
+                tt = nwaves + td;
+            }
         } else {
             tt = tstat;
             tstat += nwaves;

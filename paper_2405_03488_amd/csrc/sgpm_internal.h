@@ -177,7 +177,9 @@ struct sgpm_ctx {
     int cus = 256;
     // scratch reused across calls
     unsigned long long* d_partials = nullptr;
+    unsigned long long* d_partials2 = nullptr;  // the second stream's
     size_t partial_blocks = 0;
+    hipStream_t st2 = nullptr;  // a window queued ahead runs here, beside the one on st
     unsigned long long* h_slots = nullptr;   // pinned host slots: per launch its 20 sums (32 words a slot)
     unsigned long long* dh_slots = nullptr;  // the same memory as seen from the device
     unsigned long long* d_tickets = nullptr; // per launch: NTK ticket counters, TK_STRIDE words apart
