@@ -165,6 +165,25 @@ def test_strict_mode_matches_oracle(S, O, synth, ctx, cl_graph, name):
     S.sgpm_pattern_free(p)
 
 
+@pytest.mark.parametrize("name,seed", [("triangle", 3), ("4-cycle", 4), ("diamond", 5)])
+def test_windows_queued_ahead_keep_the_stop_rule(S, O, synth, ctx, cl_graph, name, seed):
+    """Many short windows: after each window whose error predicts two more, the
+    library queues the window after next on a second stream.  The stop point,
+    window count and exact sums must still be the oracle's (a window queued
+    past the stop is dropped)."""
+    g, og = cl_graph
+    k, e = synth.pattern(name)
+    p = S.sgpm_pattern_create(ctx, k, e)
+    kw = dict(n_min=2000, w_min=2000, quantum=100)
+    opts = S.sgpm_options_default(eps=0.01, confidence=0.95, seed=seed, checksum=1, lanes_per_sample=64,
+                                  window_growth=0.0, **kw)
+    r, rc = S.sgpm_estimate(ctx, g, p, opts)
+    orr = O.run(og, O.compile_plan(k, e), O.make_opts(eps=0.01, confidence=0.95, seed=seed, growth=0.0, **kw))
+    check_run(S, O, r, orr)
+    assert r.windows == orr.windows and r.windows >= 4 and r.converged == orr.converged
+    S.sgpm_pattern_free(p)
+
+
 def test_not_converged_is_reported(S, O, synth, ctx, cl_graph):
     g, og = cl_graph
     k, e = synth.pattern("5-clique")
