@@ -67,6 +67,7 @@ typedef struct {
     uint64_t fixed_n;      /* >0: one window of exactly fixed_n samples */
     uint64_t n_min, w_min, quantum, max_samples;
     double growth;
+    int32_t sampler;       /* 0: NS-prune, 1: NS-base */
 } orc_ns_opts;
 
 typedef struct {
@@ -95,6 +96,11 @@ uint64_t orc_candidates(const orc_graph* g, const orc_plan* p, int j, const int3
 void orc_ns_sample(const orc_graph* g, const orc_plan* p, uint64_t seed, uint32_t tag, uint64_t s,
                    const uint64_t* draws, orc_rec* r);
 uint64_t orc_rec_hash(const orc_rec* r);
+uint64_t orc_union_candidates(const orc_graph* g, const orc_plan* p, int j, const int32_t* v, int32_t* out);
+void orc_ns_base_sample(const orc_graph* g, const orc_plan* p, uint64_t seed, uint32_t tag, uint64_t s,
+                        const uint64_t* draws, orc_rec* r);
+int orc_ns_base_trace(const orc_graph* g, const orc_plan* p, uint64_t seed, uint32_t tag,
+                      uint64_t s0, uint64_t count, int nthreads, orc_rec* out);
 int orc_ns_trace(const orc_graph* g, const orc_plan* p, uint64_t seed, uint32_t tag,
                  uint64_t s0, uint64_t count, int nthreads, orc_rec* out);
 int orc_ns_run(const orc_graph* g, const orc_plan* p, const orc_ns_opts* o, orc_ns_result* r,

@@ -42,7 +42,8 @@ class Rec(C.Structure):
 class NsOpts(C.Structure):
     _fields_ = [("eps", C.c_double), ("confidence", C.c_double), ("seed", C.c_uint64), ("tag", C.c_uint32),
                 ("nthreads", C.c_int32), ("fixed_n", C.c_uint64), ("n_min", C.c_uint64), ("w_min", C.c_uint64),
-                ("quantum", C.c_uint64), ("max_samples", C.c_uint64), ("growth", C.c_double)]
+                ("quantum", C.c_uint64), ("max_samples", C.c_uint64), ("growth", C.c_double),
+                ("sampler", C.c_int32)]
 
 
 class NsResult(C.Structure):
@@ -102,6 +103,10 @@ def lib():
         L.orc_rec_hash.argtypes = [C.POINTER(Rec)]
         L.orc_rec_hash.restype = C.c_uint64
         L.orc_ns_trace.argtypes = [G, PL, C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint64, C.c_int, P]
+        L.orc_union_candidates.argtypes = [G, PL, C.c_int, P, P]
+        L.orc_union_candidates.restype = C.c_uint64
+        L.orc_ns_base_sample.argtypes = [G, PL, C.c_uint64, C.c_uint32, C.c_uint64, P, C.POINTER(Rec)]
+        L.orc_ns_base_trace.argtypes = [G, PL, C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint64, C.c_int, P]
         L.orc_ns_run.argtypes = [G, PL, C.POINTER(NsOpts), C.POINTER(NsResult), P, P, C.c_int]
         L.orc_norm_ppf.argtypes = [C.c_double]
         L.orc_norm_ppf.restype = C.c_double
@@ -291,6 +296,35 @@ def sample(g: OGraph, p: Plan, seed, tag, s, draws=None) -> Rec:
     return r
 
 
+def sample_base(g: OGraph, p: Plan, seed, tag, s, draws=None) -> Rec:
+    """One NS-base sample (lazy verification; see orc_ns_base_sample)."""
+    r = Rec()
+    if draws is not None:
+        d = np.zeros(8, dtype=np.uint64)
+        d[:len(draws)] = [int(x) for x in draws]
+        lib().orc_ns_base_sample(g.ref(), C.byref(p), seed, tag, s, d.ctypes.data, C.byref(r))
+    else:
+        lib().orc_ns_base_sample(g.ref(), C.byref(p), seed, tag, s, None, C.byref(r))
+    return r
+
+
+def union_candidates(g: OGraph, p: Plan, j, v):
+    """U_j of NS-base in its enumeration order, for the walk prefix v[0..j-1]."""
+    vv = np.full(8, -1, dtype=np.int32)
+    vv[:len(v)] = v
+    n = int(lib().orc_union_candidates(g.ref(), C.byref(p), j, vv.ctypes.data, None))
+    out = np.zeros(max(n, 1), dtype=np.int32)
+    lib().orc_union_candidates(g.ref(), C.byref(p), j, vv.ctypes.data, out.ctypes.data)
+    return out[:n]
+
+
+def trace_base(g: OGraph, p: Plan, seed, tag, s0, count, threads=None):
+    arr = (Rec * count)()
+    lib().orc_ns_base_trace(g.ref(), C.byref(p), seed, tag, s0, count, threads or nthreads(),
+                            C.cast(arr, C.c_void_p))
+    return arr
+
+
 def rec_hash(r: Rec) -> int:
     return int(lib().orc_rec_hash(C.byref(r)))
 
@@ -303,9 +337,10 @@ def trace(g: OGraph, p: Plan, seed, tag, s0, count, threads=None):
 
 
 def make_opts(eps=0.01, confidence=0.95, seed=1, tag=0, threads=None, fixed_n=0, n_min=1 << 20,
-              w_min=1 << 20, quantum=1 << 16, max_samples=1 << 40, growth=0.10) -> NsOpts:
+              w_min=1 << 20, quantum=1 << 16, max_samples=1 << 40, growth=0.10, sampler=0) -> NsOpts:
+    """sampler 0: NS-prune; 1: NS-base (lazy verification)."""
     return NsOpts(eps, confidence, seed, tag, threads or nthreads(), fixed_n, n_min, w_min, quantum,
-                  max_samples, growth)
+                  max_samples, growth, sampler)
 
 
 def run(g: OGraph, p: Plan, opts: NsOpts, trace_cap=0):
@@ -356,33 +391,38 @@ def gs_count(g: OGraph, p: Plan, c, seed, rep, threads=None) -> int:
     return (int(hi.value) << 64) | int(lo.value)
 
 
-def exact_expectation(g: OGraph, p: Plan) -> Fraction:
+def exact_expectation(g: OGraph, p: Plan, base=False, with_hit_prob=False):
     """Sum over every random walk of Pr(walk) * X(walk), enumerating index choices
-    by handing the sampler draws r = ceil(i * 2^64 / N) that select index i."""
+    by handing the sampler draws r = ceil(i * 2^64 / N) that select index i.
+    base: the NS-base sampler instead of NS-prune.  with_hit_prob: also return
+    Pr(hit), both as exact rationals."""
     k = p.k
     M = g.m if p.oriented else 2 * g.m
     if M == 0:
-        return Fraction(0)
+        return (Fraction(0), Fraction(0)) if with_hit_prob else Fraction(0)
+    draw = sample_base if base else sample
 
     def r_for(i, N):
         return -((-i << 64) // N)
 
     total = Fraction(0)
+    hit = Fraction(0)
 
     def walk(draws, depth, prob):
-        nonlocal total
-        rec = sample(g, p, 0, 0, 0, draws + [0] * (8 - len(draws)))
+        nonlocal total, hit
+        rec = draw(g, p, 0, 0, 0, draws + [0] * (8 - len(draws)))
         if depth == k:
             if rec.hit:
                 total += prob * rec.alpha
+                hit += prob
             return
-        N = int(rec.size[depth])  # |S_depth| given the chosen prefix
+        N = int(rec.size[depth])  # the candidate set's size given the chosen prefix
         for i in range(N):
             walk(draws + [r_for(i, N)], depth + 1, prob / N)
 
     for e in range(M):
         walk([r_for(e, M), 0], 2, Fraction(1, M))
-    return total
+    return (total, hit) if with_hit_prob else total
 
 
 def gs_run(g: OGraph, p: Plan, c, seed, eps=0.01, confidence=0.95, reps_max=64, threads=None):

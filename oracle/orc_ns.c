@@ -196,6 +196,99 @@ void orc_ns_sample(const orc_graph* g, const orc_plan* p, uint64_t seed, uint32_
     r->alpha_hi = (uint64_t)(alpha >> 64);
 }
 
+/* ------------------------------------------------------------------ NS-base
+ *
+ * The neighbour sampler the paper measures NS-prune against (Sec. 4.2, the
+ * neighbour-sampling algorithm and its lazy verification; the comparison of
+ * hit rates and convergence in the evaluation): after the same first edge,
+ * position j is drawn uniformly from the UNION of the neighbourhoods of the
+ * earlier positions joined to j by a pattern edge, with no other test, and
+ * alpha is multiplied by the union's size; once every position is drawn, the
+ * closure check tests what NS-prune tests step by step (distinct vertices, the
+ * symmetry-breaking bounds, every pattern edge present and, for vertex-induced
+ * counting, every non-edge absent).  A sample failing it is a miss.  Each match
+ * is produced by exactly one sequence of draws, with probability 1/alpha, so
+ * E[X] is the count.
+ *
+ * Order of the union (the index r selects into): the earlier positions joined
+ * to j in ascending position, each row ascending, an entry kept at its first
+ * occurrence (dropped from a later row that repeats an earlier one).
+ * Status of a miss: j for an empty union at position j, k for a failed closure. */
+uint64_t orc_union_candidates(const orc_graph* g, const orc_plan* p, int j, const int32_t* v, int32_t* out) {
+    uint64_t cnt = 0;
+    for (int i = 0; i < j; i++) {
+        if (!(p->connect[j] >> i & 1)) continue;
+        for (int64_t e = g->off[v[i]]; e < g->off[v[i] + 1]; e++) {
+            int32_t x = g->nbr[e];
+            int seen = 0;
+            for (int h = 0; h < i && !seen; h++)
+                if ((p->connect[j] >> h & 1) && has_edge(g, v[h], x)) seen = 1;
+            if (seen) continue;
+            if (out) out[cnt] = x;
+            cnt++;
+        }
+    }
+    return cnt;
+}
+
+static int closure_holds(const orc_graph* g, const orc_plan* p, const int32_t* v) {
+    for (int j = 2; j < p->k; j++) {
+        int64_t lo = -1, hi = g->n;
+        for (int i = 0; i < j; i++) {
+            if (p->upper[j] >> i & 1) { if (v[i] < hi) hi = v[i]; }
+            if (p->lower[j] >> i & 1) { if (v[i] > lo) lo = v[i]; }
+        }
+        if (v[j] <= lo || v[j] >= hi) return 0;
+        for (int i = 0; i < j; i++) {
+            if (v[j] == v[i]) return 0;
+            if ((p->connect[j] >> i & 1) && !has_edge(g, v[i], v[j])) return 0;
+            if ((p->disconnect[j] >> i & 1) && has_edge(g, v[i], v[j])) return 0;
+        }
+    }
+    return 1;
+}
+
+void orc_ns_base_sample(const orc_graph* g, const orc_plan* p, uint64_t seed, uint32_t tag, uint64_t s,
+                        const uint64_t* draws, orc_rec* r) {
+    memset(r, 0, sizeof(*r));
+    r->s = s;
+    r->k = p->k;
+    for (int i = 0; i < 8; i++) r->v[i] = -1;
+    uint64_t M = p->oriented ? (uint64_t)g->m : 2 * (uint64_t)g->m;
+    r->size[0] = M;
+    if (M == 0) { r->fail_step = 1; return; }
+    uint64_t r0 = draws ? draws[0] : orc_draw(seed, s, 0, tag);
+    uint64_t e = orc_mulhi(M, r0);
+    if (p->oriented) { r->v[0] = g->esrc[e]; r->v[1] = g->edst[e]; }
+    else { r->v[0] = g->arow[e]; r->v[1] = g->nbr[e]; }
+    unsigned __int128 alpha = M;
+    int32_t* buf = NULL;
+    for (int j = 2; j < p->k; j++) {
+        uint64_t cnt = orc_union_candidates(g, p, j, r->v, NULL);
+        r->size[j] = cnt;
+        if (cnt == 0) {
+            r->fail_step = j;
+            free(buf);
+            return;
+        }
+        buf = (int32_t*)realloc(buf, sizeof(int32_t) * (size_t)cnt);
+        orc_union_candidates(g, p, j, r->v, buf);
+        uint64_t rj = draws ? draws[j] : orc_draw(seed, s, (uint32_t)j, tag);
+        r->v[j] = buf[orc_mulhi(cnt, rj)];
+        unsigned __int128 next = alpha * cnt;
+        if (next / cnt != alpha) r->overflow = 1;
+        alpha = next;
+    }
+    free(buf);
+    if (!closure_holds(g, p, r->v)) {
+        r->fail_step = p->k;
+        return;
+    }
+    r->hit = 1;
+    r->alpha_lo = (uint64_t)alpha;
+    r->alpha_hi = (uint64_t)(alpha >> 64);
+}
+
 /* SplitMix64 finaliser (Steele, Lea, Flood 2014). */
 static uint64_t mix64(uint64_t z) {
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
@@ -220,7 +313,7 @@ uint64_t orc_rec_hash(const orc_rec* r) {
 
 typedef struct {
     const orc_graph* g; const orc_plan* p; uint64_t seed; uint32_t tag;
-    uint64_t s0, s1; orc_rec* out;
+    uint64_t s0, s1; orc_rec* out; int base; /* 1: NS-base, else NS-prune */
     obig S1, S2; uint64_t hits, checksum, bytes; int overflow;
 } ns_job;
 
@@ -230,7 +323,8 @@ static void* ns_worker(void* arg) {
     J->hits = 0; J->checksum = 0; J->bytes = 0; J->overflow = 0;
     orc_rec r;
     for (uint64_t s = J->s0; s < J->s1; s++) {
-        orc_ns_sample(J->g, J->p, J->seed, J->tag, s, NULL, &r);
+        if (J->base) orc_ns_base_sample(J->g, J->p, J->seed, J->tag, s, NULL, &r);
+        else orc_ns_sample(J->g, J->p, J->seed, J->tag, s, NULL, &r);
         if (J->out) J->out[s - J->s0] = r;
         J->checksum += orc_rec_hash(&r);
         J->bytes += r.bytes;
@@ -249,7 +343,7 @@ static void* ns_worker(void* arg) {
 }
 
 static void run_range(const orc_graph* g, const orc_plan* p, uint64_t seed, uint32_t tag, uint64_t s0,
-                      uint64_t count, int nthreads, orc_rec* out, ns_job* total) {
+                      uint64_t count, int nthreads, orc_rec* out, ns_job* total, int base) {
     if (nthreads < 1) nthreads = 1;
     if (nthreads > 64) nthreads = 64;
     pthread_t th[64];
@@ -259,6 +353,7 @@ static void run_range(const orc_graph* g, const orc_plan* p, uint64_t seed, uint
         jobs[t].s0 = s0 + count * (uint64_t)t / (uint64_t)nthreads;
         jobs[t].s1 = s0 + count * (uint64_t)(t + 1) / (uint64_t)nthreads;
         jobs[t].out = out ? out + (jobs[t].s0 - s0) : NULL;
+        jobs[t].base = base;
         pthread_create(&th[t], NULL, ns_worker, &jobs[t]);
     }
     ob_zero(&total->S1); ob_zero(&total->S2);
@@ -277,7 +372,14 @@ static void run_range(const orc_graph* g, const orc_plan* p, uint64_t seed, uint
 int orc_ns_trace(const orc_graph* g, const orc_plan* p, uint64_t seed, uint32_t tag, uint64_t s0,
                  uint64_t count, int nthreads, orc_rec* out) {
     ns_job total;
-    run_range(g, p, seed, tag, s0, count, nthreads, out, &total);
+    run_range(g, p, seed, tag, s0, count, nthreads, out, &total, 0);
+    return 0;
+}
+
+int orc_ns_base_trace(const orc_graph* g, const orc_plan* p, uint64_t seed, uint32_t tag, uint64_t s0,
+                      uint64_t count, int nthreads, orc_rec* out) {
+    ns_job total;
+    run_range(g, p, seed, tag, s0, count, nthreads, out, &total, 1);
     return 0;
 }
 
@@ -360,7 +462,7 @@ int orc_ns_run(const orc_graph* g, const orc_plan* p, const orc_ns_opts* o, orc_
         uint64_t nx = o->fixed_n ? o->fixed_n : orc_window_next(n, o);
         if (nx <= n) break;
         ns_job part;
-        run_range(g, p, o->seed, o->tag, n, nx - n, o->nthreads, NULL, &part);
+        run_range(g, p, o->seed, o->tag, n, nx - n, o->nthreads, NULL, &part, o->sampler == 1);
         ob_add(&S1, &part.S1);
         ob_add(&S2, &part.S2);
         res->hits += part.hits;
