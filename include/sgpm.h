@@ -111,6 +111,14 @@ enum {
                                   result equals that engine's own result (same options) */
 };
 enum { SGPM_SCHEME_NS = 0, SGPM_SCHEME_GS = 1, SGPM_SCHEME_EXACT = 2 };
+enum {
+    SGPM_SAMPLER_PRUNE = 0,    /* NS-prune: eager verification, candidate sets filtered at every step (Sec. 4.2) */
+    SGPM_SAMPLER_BASE = 1      /* NS-base: the sampler the paper compares against (Sec. 4.2): position j drawn
+                                  from the union of the joined positions' rows (alpha *= its size, union
+                                  enumerated by ascending position, each row ascending, first occurrences),
+                                  every test deferred to a closure check after the last draw; a failed closure
+                                  is a miss with status k */
+};
 
 /* One NS sample as recorded by the trace option (64 bytes). status = 0xFF for a
  * hit, else the position j whose candidate set was empty; v[i] = -1 for
@@ -142,6 +150,9 @@ typedef struct {
     int32_t checksum;        /* 1 = fold every sample record into result.checksum */
     uint64_t trace_lo, trace_hi; /* record samples with trace_lo <= s < trace_hi ... */
     sgpm_trace_rec* trace_buf;   /* ... into this host array of trace_hi - trace_lo records */
+    int32_t sampler;         /* SGPM_SAMPLER_*: NS-prune (default) or NS-base; NS-base runs in the strict
+                                and fixed-n modes only, with the uniform proposal and no byte count */
+    int32_t reserved1;
 } sgpm_options;
 
 typedef struct {

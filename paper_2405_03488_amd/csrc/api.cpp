@@ -282,7 +282,8 @@ sgpm_status enqueue_range(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_
                           uint64_t span = 0, bool second_stream = false) {
     LaunchCfg cfg;
     cfg.lanes = lanes;
-    cfg.blocks = blocks_for(c, lanes, lanes == 64 && !la.table && wave_uses_clique_kernel(p, tr, la, count_bytes));
+    cfg.base = o.sampler == SGPM_SAMPLER_BASE ? 1 : 0;
+    cfg.blocks = blocks_for(c, lanes, lanes == 64 && !la.table && !cfg.base && wave_uses_clique_kernel(p, tr, la, count_bytes));
     // Tickets of about 1/16 of a wave's share of the window: few enough that
     // the single ticket counter (a device-scope atomic, about 8e7 per second
     // on one address) is not the bottleneck, many enough to balance skewed
@@ -370,7 +371,8 @@ sgpm_status ns_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_op
     HIP_TRY(c, hipEventCreate(&e1));
     NsState s;
     int lanes = o.lanes_per_sample;
-    if (learned || tr.sizes) lanes = 64;  // the learned proposal and pilot sizes run one sample per wave
+    // the learned proposal, pilot sizes and NS-base run one sample per wave
+    if (learned || tr.sizes || o.sampler == SGPM_SAMPLER_BASE) lanes = 64;
     // lane counts picked earlier for this (graph, plan) are reused
     const auto tune_key = std::make_tuple((const void*)g, std::string((const char*)&p, sizeof(Plan)));
     if (lanes == 0) {
@@ -589,6 +591,10 @@ sgpm_status check_options(sgpm_ctx* c, const sgpm_options* o) {
     const int l = o->lanes_per_sample;
     if (!(l == 0 || l == 1 || l == 4 || l == 16 || l == 64)) return fail(c, SGPM_EINVAL, "lanes_per_sample");
     if (o->trace_hi > o->trace_lo && !o->trace_buf) return fail(c, SGPM_EINVAL, "trace range without buffer");
+    if (o->sampler != SGPM_SAMPLER_PRUNE && o->sampler != SGPM_SAMPLER_BASE) return fail(c, SGPM_EINVAL, "sampler");
+    if (o->sampler == SGPM_SAMPLER_BASE &&
+        ((o->mode != SGPM_MODE_STRICT_NS && o->mode != SGPM_MODE_FIXED_N) || o->proposal))
+        return fail(c, SGPM_EUNSUPPORTED, "NS-base runs in the strict and fixed-n modes with the uniform proposal");
     return SGPM_OK;
 }
 
@@ -628,6 +634,7 @@ sgpm_status sgpm_estimate_counted(sgpm_ctx_t c, sgpm_graph_t g, sgpm_pattern_t p
     if (o->mode != SGPM_MODE_STRICT_NS && o->mode != SGPM_MODE_FIXED_N)
         return fail(c, SGPM_EUNSUPPORTED, "byte counting is for NS modes");
     if (o->proposal) return fail(c, SGPM_EUNSUPPORTED, "byte counting is for the uniform proposal");
+    if (o->sampler == SGPM_SAMPLER_BASE) return fail(c, SGPM_EUNSUPPORTED, "byte counting is for NS-prune");
     return ns_estimate(c, g, p->plan, *o, res, 1);
 }
 

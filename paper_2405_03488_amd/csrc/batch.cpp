@@ -65,6 +65,7 @@ sgpm_status batch_estimate(sgpm_ctx* c, int nq, const sgpm_graph_t* graphs, cons
         if (o.mode != SGPM_MODE_STRICT_NS && o.mode != SGPM_MODE_FIXED_N)
             return fail(c, SGPM_EUNSUPPORTED, "batch queries must be NS (strict or fixed-n)");
         if (o.trace_buf || o.proposal) return fail(c, SGPM_EUNSUPPORTED, "batch queries take no trace or proposal");
+        if (o.sampler != SGPM_SAMPLER_PRUNE) return fail(c, SGPM_EUNSUPPORTED, "batch queries use NS-prune");
         if (!(o.eps > 0) || !(o.confidence > 0 && o.confidence < 1)) return fail(c, SGPM_EINVAL, "eps/confidence");
         if (o.mode == SGPM_MODE_FIXED_N && o.fixed_n == 0) return fail(c, SGPM_EINVAL, "fixed_n = 0");
         // every window must hold a tile, or its query would never complete

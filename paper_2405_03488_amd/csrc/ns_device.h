@@ -518,6 +518,174 @@ __device__ __forceinline__ uint32_t ns_sample(const DGraph& g, const Plan& p, ui
     return 0xFFu;
 }
 
+// Whether x is in the ascending row R[0, L), by the whole wave: G-ary rounds
+// (64 probes, keep the gap that holds x) until one window of 64 remains.
+__device__ __forceinline__ bool wave_row_has(const int32_t* __restrict__ R, int32_t L, int32_t x) {
+    const int lane = (int)(threadIdx.x & 63);
+    int32_t lo = 0, hi = L;
+    while (hi - lo > 64) {
+        const int32_t step = (hi - lo) / 64;
+        const int32_t pv = R[lo + (lane + 1) * step - 1];
+        const int nb = (int)__popcll(__ballot(pv < x));
+        if (nb < 64) hi = lo + (nb + 1) * step;
+        lo += nb * step;
+    }
+    const int32_t y = lo + lane < hi ? R[lo + lane] : BIG;
+    return __ballot(y == x) != 0ull;
+}
+
+// One NS-base sample (lazy verification), one sample per wave: the sampler the
+// paper measures NS-prune against (Sec. 4.2).  After the first edge, position
+// j is drawn uniformly from the union U_j of the rows of the earlier positions
+// joined to j by a pattern edge, enumerated row by row in ascending position,
+// each row ascending, an entry kept at its first occurrence; alpha *= |U_j|.
+// No other test runs until every position is drawn; the closure check then
+// tests distinctness, the symmetry-breaking bounds, every pattern edge and
+// (vertex-induced) every non-edge.  Returns 0xFF for a hit, j for an empty
+// union at position j, k for a failed closure check.  `list` (CAP words) keeps
+// the first CAP members of U_j; a draw beyond them rescans the rows.
+template <int KMAX>
+__device__ __forceinline__ uint32_t ns_base_sample(const DGraph& g, const Plan& p, uint64_t seed, uint32_t tag,
+                                                  uint64_t s, int32_t (&v)[8], uint64_t& alo, uint64_t& ahi,
+                                                  uint64_t& ovf, int32_t* list, const Draws* dr) {
+    constexpr int CAP = LDS_WORDS / 4;
+    const int lane = (int)(threadIdx.x & 63);
+    const uint64_t below = (1ull << lane) - 1ull;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = -1;
+    const int pk = p.k;
+    const uint64_t M = p.oriented ? (uint64_t)g.m : 2ull * (uint64_t)g.m;
+    const int32_t* rp[8];
+    int32_t rl[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        rp[i] = nullptr;
+        rl[i] = 0;
+    }
+    {
+        const uint64_t e = __umul64hi(M, draw_at(dr, seed, s, 0, tag));
+        if (p.oriented) {
+            const int2 pr = g.epair[e];
+            v[0] = pr.x;
+            v[1] = pr.y;
+        } else {
+            v[0] = g.arow[e];
+            v[1] = g.nbr[e];
+        }
+        const int64_t b0 = g.off[v[0]], e0 = g.off[v[0] + 1];
+        const int64_t b1 = g.off[v[1]], e1 = g.off[v[1] + 1];
+        rp[0] = g.nbr + b0;
+        rl[0] = (int32_t)(e0 - b0);
+        rp[1] = g.nbr + b1;
+        rl[1] = (int32_t)(e1 - b1);
+    }
+    alo = M;
+    ahi = 0;
+#pragma unroll
+    for (int j = 2; j < KMAX; ++j) {
+        if (j >= pk) break;
+        const uint32_t conn = (uint32_t)p.connect[j];
+        // one chunk of row i: x and whether it is a first occurrence (absent
+        // from every earlier joined row); cursors only move forward along row i
+        int32_t cur[8];
+        auto chunk = [&](int i, int32_t base, int32_t& x) -> bool {
+            const bool act = base + lane < rl[i];
+            x = act ? rp[i][base + lane] : BIG;
+            const uint64_t am = __ballot(act);
+            const int32_t xmax = rfl(__shfl(x, (int)__popcll(am) - 1));
+            bool fresh = act;
+#pragma unroll
+            for (int h = 0; h < i; ++h)
+                if (conn >> h & 1) {
+                    const bool f = member<64>(rp[h], rl[h], cur[h], x, act, xmax, 0, lane, ~0ull);
+                    fresh = fresh && !f;
+                }
+            return fresh;
+        };
+        // count pass, keeping the first CAP members
+        uint64_t cnt = 0;
+#pragma unroll
+        for (int i = 0; i < KMAX - 1; ++i) {
+            if (i >= j || !(conn >> i & 1)) continue;
+#pragma unroll
+            for (int h = 0; h < 8; ++h) cur[h] = 0;
+            for (int32_t base = 0; base < rl[i]; base += 64) {
+                int32_t x;
+                const bool ok = chunk(i, base, x);
+                const uint64_t okm = __ballot(ok);
+                const uint64_t rank = (uint64_t)__popcll(okm & below);
+                if (ok && cnt + rank < (uint64_t)CAP) list[cnt + rank] = x;
+                cnt += (uint64_t)__popcll(okm);
+            }
+        }
+        if (cnt == 0) return (uint32_t)j;
+        const uint64_t idx = __umul64hi(cnt, draw_at(dr, seed, s, (uint32_t)j, tag));
+        int32_t pick = -1;
+        if (idx < (uint64_t)CAP) {
+            pick = rfl(list[idx]);
+        } else {
+            // beyond the kept members: enumerate again up to member idx
+            uint64_t seen = 0;
+#pragma unroll
+            for (int i = 0; i < KMAX - 1; ++i) {
+                if (i >= j || !(conn >> i & 1) || pick >= 0) continue;
+#pragma unroll
+                for (int h = 0; h < 8; ++h) cur[h] = 0;
+                for (int32_t base = 0; base < rl[i]; base += 64) {
+                    int32_t x;
+                    const bool ok = chunk(i, base, x);
+                    uint64_t okm = __ballot(ok);
+                    const uint64_t c = (uint64_t)__popcll(okm);
+                    if (seen + c > idx) {
+                        for (uint64_t t = idx - seen; t > 0; --t) okm &= okm - 1ull;
+                        pick = rfl(__shfl(x, __ffsll((unsigned long long)okm) - 1));
+                        break;
+                    }
+                    seen += c;
+                }
+            }
+        }
+        if (pick < 0) {  // the two passes disagree: report, never index with it
+            ovf = 1;
+            return (uint32_t)j;
+        }
+        v[j] = pick;
+        if (j + 1 < pk) {
+            const int64_t bj = g.off[pick], ej = g.off[pick + 1];
+            rp[j] = g.nbr + bj;
+            rl[j] = (int32_t)(ej - bj);
+        }
+        // alpha *= |U_j| with 128-bit overflow detection
+        const uint64_t plo = alo * cnt, phi = __umul64hi(alo, cnt);
+        const uint64_t qlo = ahi * cnt, qhi = __umul64hi(ahi, cnt);
+        const uint64_t nhi = phi + qlo;
+        if (qhi != 0 || nhi < qlo) ovf = 1;
+        alo = plo;
+        ahi = nhi;
+    }
+    // closure check: what NS-prune tests at every step, tested once at the end
+#pragma unroll
+    for (int j = 2; j < KMAX; ++j) {
+        if (j >= pk) break;
+        const uint32_t conn = (uint32_t)p.connect[j], disc = (uint32_t)p.disconnect[j];
+        const uint32_t up = (uint32_t)p.upper[j], lw = (uint32_t)p.lower[j];
+#pragma unroll
+        for (int i = 0; i < KMAX - 1; ++i) {
+            if (i >= j) continue;
+            if (v[j] == v[i]) return (uint32_t)pk;
+            if ((up >> i & 1) && !(v[j] < v[i])) return (uint32_t)pk;
+            if ((lw >> i & 1) && !(v[j] > v[i])) return (uint32_t)pk;
+        }
+#pragma unroll
+        for (int i = 0; i < KMAX - 1; ++i) {
+            if (i >= j || !((conn | disc) >> i & 1)) continue;
+            const bool has = wave_row_has(rp[i], rl[i], v[j]);
+            if ((conn >> i & 1) ? !has : has) return (uint32_t)pk;
+        }
+    }
+    return 0xFFu;
+}
+
 // Next ticket of a wave from the NTK counters at tk (wave-uniform result).
 // Blocks are dispatched round-robin over the 8 XCDs, so starting at counter
 // blockIdx % NTK keeps the counters' atomics apart; a wave whose counter has

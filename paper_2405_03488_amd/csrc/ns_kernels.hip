@@ -158,7 +158,8 @@ __global__ __launch_bounds__(256) void ns_window_kernel(DGraph g, Plan p, uint64
 //    weight and the digit columns of the weight's square, and adds them to the
 //    wave's sums in LDS (LDS atomics); the sums are normalised once per block.
 // MODE 0: uniform proposal; 1: learned proposal; 2: uniform with per-step set
-// sizes recorded for traced samples (training pilots).  CLQ: the plan is the
+// sizes recorded for traced samples (training pilots); 3: the NS-base sampler
+// (lazy verification), which the paper measures NS-prune against.  CLQ: the plan is the
 // K-clique's, so every plan test folds at compile time; this build also leaves
 // out the trace and byte-count code, which halves the per-sample loop's
 // uniform-register spills to vector lanes.
@@ -251,9 +252,12 @@ __global__ __launch_bounds__(256, wave_occupancy(MODE, CLQ)) void ns_wave_kernel
                 int32_t v[8];
                 uint64_t alo, ahi, b = 0, ov = 0;
                 uint32_t sz[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-                const uint32_t st = ns_sample<G, K, CLQ>(g, p, seed, tag, s, v, alo, ahi, ov, b, !CLQ && count_bytes != 0,
-                                                         list, MODE == 1 ? &lal : nullptr, hist,
-                                                         MODE == 2 ? sz : nullptr, &dr);
+                uint32_t st;
+                if constexpr (MODE == 3)
+                    st = ns_base_sample<K>(g, p, seed, tag, s, v, alo, ahi, ov, list, &dr);
+                else
+                    st = ns_sample<G, K, CLQ>(g, p, seed, tag, s, v, alo, ahi, ov, b, !CLQ && count_bytes != 0, list,
+                                              MODE == 1 ? &lal : nullptr, hist, MODE == 2 ? sz : nullptr, &dr);
                 ovf |= ov;
                 if (st != 0xFFu) {
                     alo = 0;
@@ -421,12 +425,12 @@ hipError_t launch_wave_mode(const DGraph& g, const Plan& p, uint64_t seed, uint3
                             const LaunchCfg& cfg, unsigned long long* ticket, unsigned long long* partials,
                             int checksum, int count_bytes, const TraceArgs& tr, const LearnArgs& la, hipStream_t st) {
     const dim3 grid((unsigned)cfg.blocks), block(256);
-    const bool clq = MODE != 2 && wave_uses_clique_kernel(p, tr, la, count_bytes);
+    const bool clq = MODE < 2 && wave_uses_clique_kernel(p, tr, la, count_bytes);
 #define SGPM_WAVE_CASE(KK)                                                                                        \
     case KK:                                                                                                      \
-        if (clq && KK >= 3 && KK <= 6)                                                                            \
-            hipLaunchKernelGGL((ns_wave_kernel<MODE, KK, KK >= 3 && KK <= 6>), grid, block, 0, st, g, p, seed, tag, s0, \
-                               s1, cfg.spl, ticket, partials, checksum, count_bytes, tr, la);                     \
+        if (MODE < 2 && clq && KK >= 3 && KK <= 6)                                                                \
+            hipLaunchKernelGGL((ns_wave_kernel<MODE, KK, MODE < 2 && KK >= 3 && KK <= 6>), grid, block, 0, st, g, p, \
+                               seed, tag, s0, s1, cfg.spl, ticket, partials, checksum, count_bytes, tr, la);      \
         else                                                                                                      \
             hipLaunchKernelGGL((ns_wave_kernel<MODE, KK, false>), grid, block, 0, st, g, p, seed, tag, s0, s1,    \
                                cfg.spl, ticket, partials, checksum, count_bytes, tr, la);                         \
@@ -449,6 +453,7 @@ hipError_t launch_wave_mode(const DGraph& g, const Plan& p, uint64_t seed, uint3
 hipError_t launch_wave(const DGraph& g, const Plan& p, uint64_t seed, uint32_t tag, uint64_t s0, uint64_t s1,
                        const LaunchCfg& cfg, unsigned long long* ticket, unsigned long long* partials, int checksum,
                        int count_bytes, const TraceArgs& tr, const LearnArgs& la, hipStream_t st) {
+    if (cfg.base) return launch_wave_mode<3>(g, p, seed, tag, s0, s1, cfg, ticket, partials, checksum, 0, tr, la, st);
     if (la.table) return launch_wave_mode<1>(g, p, seed, tag, s0, s1, cfg, ticket, partials, checksum, count_bytes, tr, la, st);
     if (tr.sizes) return launch_wave_mode<2>(g, p, seed, tag, s0, s1, cfg, ticket, partials, checksum, count_bytes, tr, la, st);
     return launch_wave_mode<0>(g, p, seed, tag, s0, s1, cfg, ticket, partials, checksum, count_bytes, tr, la, st);
@@ -459,7 +464,7 @@ hipError_t launch_ns_window(const DGraph& g, const Plan& p, uint64_t seed, uint3
                             int checksum, int count_bytes, const TraceArgs& tr, const LearnArgs& la,
                             hipStream_t st) {
     const dim3 grid((unsigned)cfg.blocks), block(256);
-    if ((la.table || tr.sizes) && cfg.lanes != 64) return hipErrorInvalidValue;
+    if ((la.table || tr.sizes || cfg.base) && cfg.lanes != 64) return hipErrorInvalidValue;
     switch (cfg.lanes) {
         case 1:
             hipLaunchKernelGGL(ns_window_kernel<1>, grid, block, 0, st, g, p, seed, tag, s0, s1, cfg.spl, ticket,

@@ -62,6 +62,7 @@ struct LaunchCfg {
     int lanes;     // lanes cooperating on one sample: 1, 4, 16, 64
     int spl;       // samples per group per ticket
     int blocks;    // grid size
+    int base = 0;  // 1: the NS-base sampler (one sample per wave only)
 };
 
 // kernels (ns_kernels.hip)

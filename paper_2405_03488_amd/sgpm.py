@@ -26,6 +26,7 @@ SGPM_EOVERFLOW = -7
 SGPM_ASSUME_CANONICAL = 0x1
 
 MODE_STRICT_NS, MODE_FIXED_N, MODE_GS, MODE_HYBRID = 0, 1, 2, 3
+SAMPLER_PRUNE, SAMPLER_BASE = 0, 1
 SCHEME_NS, SCHEME_GS, SCHEME_EXACT = 0, 1, 2
 
 
@@ -44,7 +45,8 @@ class Options(C.Structure):
                 ("quantum", C.c_uint64), ("max_samples", C.c_uint64), ("window_growth", C.c_double),
                 ("colours", C.c_int32), ("gs_reps_max", C.c_int32), ("proposal", C.c_void_p),
                 ("lanes_per_sample", C.c_int32), ("checksum", C.c_int32), ("trace_lo", C.c_uint64),
-                ("trace_hi", C.c_uint64), ("trace_buf", C.c_void_p)]
+                ("trace_hi", C.c_uint64), ("trace_buf", C.c_void_p), ("sampler", C.c_int32),
+                ("reserved1", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -181,7 +183,10 @@ def sgpm_destroy(ctx):
 def sgpm_options_default(**kw) -> Options:
     o = Options()
     lib().sgpm_options_default(C.byref(o))
+    names = {f[0] for f in Options._fields_}
     for k, v in kw.items():
+        if k not in names:
+            raise AttributeError(f"sgpm_options has no field {k!r}")
         setattr(o, k, v)
     return o
 
