@@ -68,7 +68,7 @@ def other_legs(S, ctx, g, pats, queries, eps):
     """The rest of the hot path on the same graph: the GS engine (colour
     sparsification + exact count, two colourings at c = 16), the loose-mode
     choice between NS and GS at eps, the persistent batch against solo runs,
-    and the MLP kernels' MFMA throughput."""
+    NS-base against NS-prune, and the MLP kernels' MFMA throughput."""
     out = {"gs": {}, "hybrid": {}}
     for q in queries:
         t0 = time.perf_counter()
@@ -94,6 +94,22 @@ def other_legs(S, ctx, g, pats, queries, eps):
     out["batch"] = {"queries": len(qs), "solo_s": t_solo, "batch_s": t_batch,
                     "identical": all((a.n_samples, a.S1, a.S2, a.checksum) == (b.n_samples, b.S1, b.S2, b.checksum)
                                      for a, b in zip(solo, res)), "tile": [int(r.tile) for r in res]}
+    # NS-base (lazy verification, the paper's baseline sampler) against NS-prune
+    # at equal samples: hit rate, predicted error, kernel rate, and the samples
+    # and time to eps that the error predicts (n (eps_hat / eps)^2)
+    out["ns_base_vs_prune"] = {}
+    for q in queries:
+        row = {}
+        for name, smp in (("prune", S.SAMPLER_PRUNE), ("base", S.SAMPLER_BASE)):
+            N = 1 << 20
+            r, _ = S.sgpm_estimate(ctx, g, pats[q], S.sgpm_options_default(mode=S.MODE_FIXED_N, fixed_n=N, seed=7,
+                                                                            sampler=smp, lanes_per_sample=64))
+            rate = N / r.seconds_kernel
+            need = N * (r.eps_hat / eps) ** 2 if r.eps_hat < float("inf") else None
+            row[name] = {"samples": N, "hits": int(r.n_hits), "hit_rate": r.n_hits / N, "eps_hat": r.eps_hat
+                         if r.eps_hat < float("inf") else None, "estimate": r.estimate, "samples_per_s": rate,
+                         "pred_samples_to_eps": need, "pred_seconds_to_eps": need / rate if need else None}
+        out["ns_base_vs_prune"][q] = row
     out["mlp_forward_1M_rows"] = S.sgpm_probe_mlp(ctx, 1 << 20, 10)
     out["mlp_train_batch_16K_rows"] = S.sgpm_probe_mlp(ctx, 1 << 14, 20)
     log(f"gs/hybrid/mlp: {json.dumps(out)}")
