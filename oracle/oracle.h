@@ -121,6 +121,13 @@ typedef struct {
 int orc_gs_run(const orc_graph* g, const orc_plan* p, uint32_t c, uint64_t seed, double eps, double confidence,
                int reps_max, int nthreads, orc_gs_result* r, uint64_t* y_per_rep);
 int32_t orc_gs_colour(uint64_t seed, uint32_t rep, uint32_t c, int64_t v);
+int orc_bes_keep(uint64_t seed, uint32_t rep, uint32_t c, int32_t u, int32_t w);
+int orc_bes_sparsify(const orc_graph* g, uint32_t c, uint64_t seed, uint32_t rep, orc_graph* out);
+void orc_bes_count(const orc_graph* g, const orc_plan* p, uint32_t c, uint64_t seed, uint32_t rep,
+                   int nthreads, uint64_t* y_lo, uint64_t* y_hi);
+int orc_plan_edges(const orc_plan* p);
+int orc_bes_run(const orc_graph* g, const orc_plan* p, uint32_t c, uint64_t seed, double eps, double confidence,
+                int reps_max, int nthreads, orc_gs_result* r, uint64_t* y_per_rep);
 int orc_gs_sparsify(const orc_graph* g, const int32_t* colour, orc_graph* out);
 void orc_gs_count(const orc_graph* g, const orc_plan* p, uint32_t c, uint64_t seed, uint32_t rep,
                   int nthreads, uint64_t* y_lo, uint64_t* y_hi);

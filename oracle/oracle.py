@@ -132,6 +132,14 @@ def lib():
         L.orc_digits_to_double.restype = C.c_double
         L.orc_gs_run.argtypes = [G, PL, C.c_uint32, C.c_uint64, C.c_double, C.c_double, C.c_int, C.c_int,
                                  C.POINTER(GsResult), P]
+        L.orc_bes_keep.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_int32, C.c_int32]
+        L.orc_bes_keep.restype = C.c_int
+        L.orc_bes_sparsify.argtypes = [G, C.c_uint32, C.c_uint64, C.c_uint32, G]
+        L.orc_bes_count.argtypes = [G, PL, C.c_uint32, C.c_uint64, C.c_uint32, C.c_int,
+                                    C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
+        L.orc_plan_edges.argtypes = [PL]
+        L.orc_bes_run.argtypes = [G, PL, C.c_uint32, C.c_uint64, C.c_double, C.c_double, C.c_int, C.c_int,
+                                  C.POINTER(GsResult), P]
         _lib = L
     return _lib
 
@@ -389,6 +397,30 @@ def gs_count(g: OGraph, p: Plan, c, seed, rep, threads=None) -> int:
     hi = C.c_uint64()
     lib().orc_gs_count(g.ref(), C.byref(p), c, seed, rep, threads or nthreads(), C.byref(lo), C.byref(hi))
     return (int(hi.value) << 64) | int(lo.value)
+
+
+def bes_keep(seed, rep, c, u, w) -> bool:
+    """Bernoulli edge sparsification: whether edge {u, w} survives repetition rep."""
+    return bool(lib().orc_bes_keep(seed, rep, c, u, w))
+
+
+def bes_sparsify(g: OGraph, c, seed, rep) -> OGraph:
+    out = Graph()
+    if lib().orc_bes_sparsify(g.ref(), c, seed, rep, C.byref(out)) != 0:
+        raise ValueError("oracle BES sparsify failed")
+    return OGraph(out)
+
+
+def plan_edges(p: Plan) -> int:
+    return int(lib().orc_plan_edges(C.byref(p)))
+
+
+def bes_run(g: OGraph, p: Plan, c, seed, eps=0.01, confidence=0.95, reps_max=64, threads=None):
+    r = GsResult()
+    ys = np.zeros(reps_max, dtype=np.uint64)
+    lib().orc_bes_run(g.ref(), C.byref(p), c, seed, eps, confidence, reps_max, threads or nthreads(), C.byref(r),
+                      ys.ctypes.data)
+    return r, ys[:r.reps].tolist()
 
 
 def exact_expectation(g: OGraph, p: Plan, base=False, with_hit_prob=False):

@@ -55,6 +55,55 @@ void orc_gs_count(const orc_graph* g, const orc_plan* p, uint32_t c, uint64_t se
     free(colour);
 }
 
+/* Bernoulli edge sparsification (Sec. 2.2, the edge-sparsification algorithm
+ * and the GS trade-off section): every edge is kept independently with
+ * probability p = 1/c, so a match with l pattern edges survives with
+ * probability p^l and the estimate is c^l * Y.  Non-edges are not preserved,
+ * so only edge-induced patterns (no disconnect constraint) qualify.
+ * keep({a, b}) with a > b: floor(c * r / 2^64) == 0, r the Philox value of
+ * key = seed, counter = (a, b, 0, 0x20000000 | rep). */
+int orc_bes_keep(uint64_t seed, uint32_t rep, uint32_t c, int32_t u, int32_t w) {
+    uint32_t a = (uint32_t)(u > w ? u : w), b = (uint32_t)(u > w ? w : u);
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t ctr[4] = {a, b, 0u, 0x20000000u | rep};
+    uint32_t out[4];
+    orc_philox4x32_10(ctr, key, out);
+    uint64_t r = ((uint64_t)out[1] << 32) | out[0];
+    return orc_mulhi(c, r) == 0;
+}
+
+int orc_bes_sparsify(const orc_graph* g, uint32_t c, uint64_t seed, uint32_t rep, orc_graph* out) {
+    int64_t n = g->n;
+    int64_t* off = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
+    int32_t* nbr = (int32_t*)malloc(sizeof(int32_t) * (size_t)(2 * g->m + 1));
+    if (!off || !nbr) return -2;
+    int64_t w = 0;
+    for (int64_t u = 0; u < n; u++) {
+        for (int64_t e = g->off[u]; e < g->off[u + 1]; e++)
+            if (orc_bes_keep(seed, rep, c, (int32_t)u, g->nbr[e])) nbr[w++] = g->nbr[e];
+        off[u + 1] = w;
+    }
+    int rc = orc_from_canonical(n, off, nbr, out);
+    free(off);
+    free(nbr);
+    return rc;
+}
+
+void orc_bes_count(const orc_graph* g, const orc_plan* p, uint32_t c, uint64_t seed, uint32_t rep,
+                   int nthreads, uint64_t* y_lo, uint64_t* y_hi) {
+    orc_graph sp;
+    orc_bes_sparsify(g, c, seed, rep, &sp);
+    orc_plan_count(&sp, p, nthreads, y_lo, y_hi);
+    orc_graph_free(&sp);
+}
+
+/* pattern edges of a compiled plan */
+int orc_plan_edges(const orc_plan* p) {
+    int l = 0;
+    for (int j = 1; j < p->k; j++) l += __builtin_popcount(p->connect[j]);
+    return l;
+}
+
 /* GS estimate over repeated colourings: X_r = c^(k-1) * Y_r for rep r = 0, 1, ...
  * treated as i.i.d. samples through the NS-online statistics (Sec. 4.1); stop
  * at the first n >= 2 with eps_hat <= eps, or after reps_max colourings. */
@@ -68,15 +117,18 @@ static void add_digits(uint32_t* acc, int nd, const uint64_t* cols, int nc) {
     }
 }
 
-int orc_gs_run(const orc_graph* g, const orc_plan* p, uint32_t c, uint64_t seed, double eps, double confidence,
-               int reps_max, int nthreads, orc_gs_result* r, uint64_t* y_per_rep) {
+static int gs_run_scheme(const orc_graph* g, const orc_plan* p, uint32_t c, uint64_t seed, double eps,
+                         double confidence, int reps_max, int nthreads, orc_gs_result* r, uint64_t* y_per_rep,
+                         int bes) {
     memset(r, 0, sizeof(*r));
     double z = orc_norm_ppf(1.0 - (1.0 - confidence) / 2.0);
     unsigned __int128 scale = 1;
-    for (int i = 0; i < p->k - 1; i++) scale *= c;
+    int expo = bes ? orc_plan_edges(p) : p->k - 1;
+    for (int i = 0; i < expo; i++) scale *= c;
     for (int rep = 0; rep < reps_max; rep++) {
         uint64_t lo, hi;
-        orc_gs_count(g, p, c, seed, (uint32_t)rep, nthreads, &lo, &hi);
+        if (bes) orc_bes_count(g, p, c, seed, (uint32_t)rep, nthreads, &lo, &hi);
+        else orc_gs_count(g, p, c, seed, (uint32_t)rep, nthreads, &lo, &hi);
         if (y_per_rep) y_per_rep[rep] = lo;
         unsigned __int128 y = ((unsigned __int128)hi << 64) | lo;
         unsigned __int128 x = y * scale;
@@ -100,4 +152,15 @@ int orc_gs_run(const orc_graph* g, const orc_plan* p, uint32_t c, uint64_t seed,
     r->estimate = orc_digits_to_double(r->s1, 8) / (double)r->reps;
     r->z = z;
     return 0;
+}
+
+int orc_gs_run(const orc_graph* g, const orc_plan* p, uint32_t c, uint64_t seed, double eps, double confidence,
+               int reps_max, int nthreads, orc_gs_result* r, uint64_t* y_per_rep) {
+    return gs_run_scheme(g, p, c, seed, eps, confidence, reps_max, nthreads, r, y_per_rep, 0);
+}
+
+/* The same over repeated Bernoulli edge sparsifications: X_r = c^l * Y_r. */
+int orc_bes_run(const orc_graph* g, const orc_plan* p, uint32_t c, uint64_t seed, double eps, double confidence,
+                int reps_max, int nthreads, orc_gs_result* r, uint64_t* y_per_rep) {
+    return gs_run_scheme(g, p, c, seed, eps, confidence, reps_max, nthreads, r, y_per_rep, 1);
 }
