@@ -112,6 +112,13 @@ enum {
 };
 enum { SGPM_SCHEME_NS = 0, SGPM_SCHEME_GS = 1, SGPM_SCHEME_EXACT = 2 };
 enum {
+    SGPM_GS_COLOUR = 0,        /* colour sparsification, estimate c^(k-1) Y (Sec. 2.2, 5.2) */
+    SGPM_GS_BERNOULLI = 1      /* Bernoulli edge sparsification (Sec. 2.2): every edge kept with probability
+                                  1/c, decided per undirected edge {a > b} by Philox(key seed, counter
+                                  (a, b, 0, 0x20000000 | rep)); estimate c^l Y with l pattern edges;
+                                  edge-induced patterns only (EUNSUPPORTED otherwise); SGPM_MODE_GS only */
+};
+enum {
     SGPM_SAMPLER_PRUNE = 0,    /* NS-prune: eager verification, candidate sets filtered at every step (Sec. 4.2) */
     SGPM_SAMPLER_BASE = 1      /* NS-base: the sampler the paper compares against (Sec. 4.2): position j drawn
                                   from the union of the joined positions' rows (alpha *= its size, union
@@ -152,7 +159,7 @@ typedef struct {
     sgpm_trace_rec* trace_buf;   /* ... into this host array of trace_hi - trace_lo records */
     int32_t sampler;         /* SGPM_SAMPLER_*: NS-prune (default) or NS-base; NS-base runs in the strict
                                 and fixed-n modes only, with the uniform proposal and no byte count */
-    int32_t reserved1;
+    int32_t gs_scheme;       /* SGPM_GS_*: the sparsifier of SGPM_MODE_GS */
 } sgpm_options;
 
 typedef struct {
@@ -222,6 +229,12 @@ sgpm_status sgpm_exact_count(sgpm_ctx_t ctx, sgpm_graph_t g, sgpm_pattern_t p, u
  * on the same vertex ids (the disjoint union of the colour classes). */
 sgpm_status sgpm_gs_sparsify(sgpm_ctx_t ctx, sgpm_graph_t g, uint32_t colours, uint64_t seed, uint32_t rep,
                              sgpm_graph_t* out);
+/* Bernoulli edge sparsification of g (every edge kept with probability 1/inv_p,
+ * inv_p in [1, 256], the keep rule of SGPM_GS_BERNOULLI for repetition rep)
+ * into a new graph handle with the same vertex ids; free it with
+ * sgpm_graph_free. */
+sgpm_status sgpm_bes_sparsify(sgpm_ctx_t ctx, sgpm_graph_t g, uint32_t inv_p, uint64_t seed, uint32_t rep,
+                              sgpm_graph_t* out);
 
 /* ------------------------------------------------------------------ learned proposal */
 

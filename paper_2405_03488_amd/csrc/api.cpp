@@ -592,6 +592,9 @@ sgpm_status check_options(sgpm_ctx* c, const sgpm_options* o) {
     if (!(l == 0 || l == 1 || l == 4 || l == 16 || l == 64)) return fail(c, SGPM_EINVAL, "lanes_per_sample");
     if (o->trace_hi > o->trace_lo && !o->trace_buf) return fail(c, SGPM_EINVAL, "trace range without buffer");
     if (o->sampler != SGPM_SAMPLER_PRUNE && o->sampler != SGPM_SAMPLER_BASE) return fail(c, SGPM_EINVAL, "sampler");
+    if (o->gs_scheme != SGPM_GS_COLOUR && o->gs_scheme != SGPM_GS_BERNOULLI) return fail(c, SGPM_EINVAL, "gs_scheme");
+    if (o->gs_scheme == SGPM_GS_BERNOULLI && o->mode != SGPM_MODE_GS)
+        return fail(c, SGPM_EUNSUPPORTED, "Bernoulli edge sparsification runs in the GS mode");
     if (o->sampler == SGPM_SAMPLER_BASE &&
         ((o->mode != SGPM_MODE_STRICT_NS && o->mode != SGPM_MODE_FIXED_N) || o->proposal))
         return fail(c, SGPM_EUNSUPPORTED, "NS-base runs in the strict and fixed-n modes with the uniform proposal");

@@ -1,5 +1,5 @@
-// GS engine host side: colour sparsification into a new graph handle, the
-// exact count, and the GS estimate over repeated colourings.
+// GS engine host side: colour or Bernoulli edge sparsification into a new
+// graph handle, the exact count, and the GS estimate over repetitions.
 //
 // Sec. 5.2: the estimate from one colouring with c colours is c^(k-1) * Y for a
 // connected k-vertex pattern (all k vertices must share a colour), Y the exact
@@ -28,7 +28,9 @@ struct DevBuf {
 
 }  // namespace
 
-sgpm_status sparsify(sgpm_ctx* c, sgpm_graph* g, uint32_t colours, uint64_t seed, uint32_t rep, sgpm_graph** out) {
+// colours: c of colour sparsification, or (bes) the inverse keep probability
+sgpm_status sparsify(sgpm_ctx* c, sgpm_graph* g, uint32_t colours, uint64_t seed, uint32_t rep, sgpm_graph** out,
+                     bool bes = false) {
     if (colours < 1 || colours > 256) return fail(c, SGPM_EINVAL, "colours must be in [1, 256]");
     HIP_TRY(c, hipSetDevice(c->dev));
     const int64_t n = g->n;
@@ -46,8 +48,9 @@ sgpm_status sparsify(sgpm_ctx* c, sgpm_graph* g, uint32_t colours, uint64_t seed
     HIP_TRY(c, hipMalloc(&d_eoff, sizeof(int64_t) * (size_t)(n + 1)));
     std::unique_ptr<int64_t, void (*)(int64_t*)> eguard(d_eoff, [](int64_t* q) { (void)hipFree(q); });
     const DGraph dg = g->view();
-    HIP_TRY(c, gs_colours(n, colours, seed, rep, (uint8_t*)col.p, c->st));
-    HIP_TRY(c, gs_row_counts(dg, (uint8_t*)col.p, (int64_t*)kept.p, (int64_t*)klow.p, c->st));
+    const uint8_t* colp = bes ? nullptr : (const uint8_t*)col.p;
+    if (!bes) HIP_TRY(c, gs_colours(n, colours, seed, rep, (uint8_t*)col.p, c->st));
+    HIP_TRY(c, gs_row_counts(dg, colp, colours, seed, rep, (int64_t*)kept.p, (int64_t*)klow.p, c->st));
     if (n > 0) {
         HIP_TRY(c, exclusive_scan((int64_t*)kept.p, n, h->d_off, (int64_t*)scratch.p, c->st));
         HIP_TRY(c, exclusive_scan((int64_t*)klow.p, n, d_eoff, (int64_t*)scratch.p, c->st));
@@ -64,7 +67,7 @@ sgpm_status sparsify(sgpm_ctx* c, sgpm_graph* g, uint32_t colours, uint64_t seed
     HIP_TRY(c, hipMalloc(&h->d_nbr, sizeof(int32_t) * (size_t)std::max<int64_t>(arcs, 1)));
     HIP_TRY(c, hipMalloc(&h->d_arow, sizeof(int32_t) * (size_t)std::max<int64_t>(arcs, 1)));
     HIP_TRY(c, hipMalloc(&h->d_epair, sizeof(int2) * (size_t)std::max<int64_t>(edges, 1)));
-    HIP_TRY(c, gs_compact(dg, (uint8_t*)col.p, h->d_off, d_eoff, h->d_nbr, h->d_arow, h->d_epair, c->st));
+    HIP_TRY(c, gs_compact(dg, colp, colours, seed, rep, h->d_off, d_eoff, h->d_nbr, h->d_arow, h->d_epair, c->st));
     unsigned long long* d_md = (unsigned long long*)kept.p;  // reuse as the max-degree cell
     HIP_TRY(c, launch_fill_u64(d_md, 1, 0ull, c->st));
     HIP_TRY(c, max_degree(h->d_off, n, d_md, c->st));
@@ -110,9 +113,9 @@ sgpm_status exact_count(sgpm_ctx* c, sgpm_graph* g, const Plan& p, unsigned __in
 }
 
 sgpm_status gs_rep(sgpm_ctx* c, sgpm_graph* g, const Plan& p, uint32_t colours, uint64_t seed, uint32_t rep,
-                   unsigned __int128* y, double* dev_seconds) {
+                   unsigned __int128* y, double* dev_seconds, bool bes) {
     sgpm_graph* sp = nullptr;
-    sgpm_status st = sparsify(c, g, colours, seed, rep, &sp);
+    sgpm_status st = sparsify(c, g, colours, seed, rep, &sp, bes);
     if (st != SGPM_OK) return st;
     st = exact_count(c, sp, p, y, dev_seconds);
     sgpm_graph_free(sp);
@@ -130,9 +133,24 @@ sgpm_status gs_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_op
     if (col > 256) return fail(c, SGPM_EINVAL, "colours must be in [1, 256]");
     const int reps = o.gs_reps_max > 0 ? o.gs_reps_max : 64;
     const double z = normal_quantile(1.0 - (1.0 - o.confidence) / 2.0);
-    // c^(k-1) as an exact integer
+    // Bernoulli edge sparsification keeps every edge with probability 1/c, so
+    // a match survives with c^-l (l pattern edges); it does not preserve
+    // non-edges, so vertex-induced constraints are refused
+    const bool bes = o.gs_scheme == SGPM_GS_BERNOULLI;
+    int expo = p.k - 1;
+    if (bes) {
+        expo = 0;
+        for (int j = 1; j < p.k; j++) {
+            if (p.disconnect[j]) return fail(c, SGPM_EUNSUPPORTED, "Bernoulli edge sparsification is edge-induced");
+            expo += __builtin_popcount((unsigned)p.connect[j]);
+        }
+    }
+    // c^(k-1) (colours) or c^l (Bernoulli) as an exact integer
     unsigned __int128 scale = 1;
-    for (int i = 0; i < p.k - 1; i++) scale *= col;
+    for (int i = 0; i < expo; i++) {
+        if (scale > ~(unsigned __int128)0 / col) return fail(c, SGPM_EOVERFLOW, "GS scale exceeds 128 bits");
+        scale *= col;
+    }
     Big S1(24), S2(24);
     uint64_t n = 0, nonzero = 0;
     double dev = pre ? pre->dev_seconds : 0.0;
@@ -143,7 +161,7 @@ sgpm_status gs_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_op
             y = pre->y[r];
         } else {
             double secs = 0;
-            sgpm_status st = gs_rep(c, g, p, col, o.seed, (uint32_t)r, &y, &secs);
+            sgpm_status st = gs_rep(c, g, p, col, o.seed, (uint32_t)r, &y, &secs, bes);
             if (st != SGPM_OK) return st;
             dev += secs;
         }
@@ -199,6 +217,12 @@ sgpm_status sgpm_gs_sparsify(sgpm_ctx_t c, sgpm_graph_t g, uint32_t colours, uin
                              sgpm_graph_t* out) {
     if (!c || !g || !out) return fail(c, SGPM_EINVAL, "null argument");
     return sparsify(c, g, colours, seed, rep, out);
+}
+
+sgpm_status sgpm_bes_sparsify(sgpm_ctx_t c, sgpm_graph_t g, uint32_t inv_p, uint64_t seed, uint32_t rep,
+                              sgpm_graph_t* out) {
+    if (!c || !g || !out) return fail(c, SGPM_EINVAL, "null argument");
+    return sparsify(c, g, inv_p, seed, rep, out, true);
 }
 
 sgpm_status sgpm_exact_count(sgpm_ctx_t c, sgpm_graph_t g, sgpm_pattern_t p, uint64_t* count_lo, uint64_t* count_hi) {

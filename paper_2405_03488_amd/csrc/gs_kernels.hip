@@ -1,5 +1,5 @@
-// Graph-sparsification (GS) engine for gfx950: colour sparsification and the
-// plan-driven exact count.
+// Graph-sparsification (GS) engine for gfx950: colour sparsification,
+// Bernoulli edge sparsification and the plan-driven exact count.
 //
 // Colour sparsification (Sec. 2.2 subgraph sampling, Sec. 5.2): every vertex
 // gets colour floor(c * r / 2^64), r the Philox4x32-10 value of key = seed and
@@ -60,19 +60,43 @@ __global__ void colour_kernel(int64_t n, uint32_t c, uint64_t seed, uint32_t rep
     col[v] = (uint8_t)__umul64hi((uint64_t)c, philox_colour_r64(seed, (uint64_t)v, 0x40000000u | rep));
 }
 
-// 16 lanes per row: kept[u] = same-colour neighbours, klow[u] = those below u
-__global__ __launch_bounds__(256) void row_count_kernel(DGraph g, const uint8_t* __restrict__ col,
-                                                        int64_t* __restrict__ kept, int64_t* __restrict__ klow) {
+// Which arcs survive.  Colour sparsification: both endpoints share a colour.
+// Bernoulli edge sparsification (Sec. 2.2, the edge-sparsification
+// algorithm): edge {a, b}, a > b, survives repetition rep when
+// floor(c * r / 2^64) == 0, r the Philox4x32-10 value of key = seed and
+// counter = (a, b, 0, 0x20000000 | rep) -- probability 1/c, decided per
+// undirected edge, so both arcs agree.
+struct KeepRule {
+    const uint8_t* col;  // colour sparsification (nullptr: Bernoulli)
+    uint64_t seed;
+    uint32_t rep, c;
+};
+
+template <bool BES>
+__device__ __forceinline__ bool keep_arc(const KeepRule& k, int64_t u, uint8_t cu, int32_t w) {
+    if constexpr (BES) {
+        const uint32_t a = (uint32_t)(u > w ? u : w), b = (uint32_t)(u > w ? w : u);
+        const uint64_t r = philox_colour_r64(k.seed, ((uint64_t)b << 32) | a, 0x20000000u | k.rep);
+        return __umul64hi((uint64_t)k.c, r) == 0ull;
+    } else {
+        return k.col[w] == cu;
+    }
+}
+
+// 16 lanes per row: kept[u] = surviving neighbours, klow[u] = those below u
+template <bool BES>
+__global__ __launch_bounds__(256) void row_count_kernel(DGraph g, KeepRule kr, int64_t* __restrict__ kept,
+                                                        int64_t* __restrict__ klow) {
     const int lane = (int)(threadIdx.x & 63), sub = lane & 15, gbase = lane & ~15;
     const uint64_t gmask = 0xFFFFull << gbase;
     const int64_t u = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
     if (u >= g.n) return;
     const int64_t b = g.off[u], e = g.off[u + 1];
-    const uint8_t cu = col[u];
+    const uint8_t cu = BES ? 0 : kr.col[u];
     int64_t k = 0, kl = 0;
     for (int64_t a = b + sub; a < e; a += 16) {
         const int32_t w = g.nbr[a];
-        if (col[w] == cu) {
+        if (keep_arc<BES>(kr, u, cu, w)) {
             k++;
             if (w < u) kl++;
         }
@@ -90,8 +114,8 @@ __global__ __launch_bounds__(256) void row_count_kernel(DGraph g, const uint8_t*
     }
 }
 
-__global__ __launch_bounds__(256) void compact_kernel(DGraph g, const uint8_t* __restrict__ col,
-                                                      const int64_t* __restrict__ noff,
+template <bool BES>
+__global__ __launch_bounds__(256) void compact_kernel(DGraph g, KeepRule kr, const int64_t* __restrict__ noff,
                                                       const int64_t* __restrict__ eoff, int32_t* __restrict__ nnbr,
                                                       int32_t* __restrict__ narow, int2* __restrict__ nepair) {
     const int lane = (int)(threadIdx.x & 63), sub = lane & 15, gbase = lane & ~15;
@@ -100,12 +124,12 @@ __global__ __launch_bounds__(256) void compact_kernel(DGraph g, const uint8_t* _
     const int64_t u = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
     if (u >= g.n) return;
     const int64_t b = g.off[u], e = g.off[u + 1];
-    const uint8_t cu = col[u];
+    const uint8_t cu = BES ? 0 : kr.col[u];
     int64_t pos = noff[u], epos = eoff[u];
     for (int64_t base = b; base < e; base += 16) {
         const int64_t a = base + sub;
         const int32_t w = a < e ? g.nbr[a] : GBIG;
-        const bool keep = a < e && col[w] == cu;
+        const bool keep = a < e && keep_arc<BES>(kr, u, cu, w);
         const uint64_t km = __ballot(keep) & gmask;
         const uint64_t lm = __ballot(keep && w < u) & gmask;
         if (keep) {
@@ -446,20 +470,34 @@ hipError_t gs_colours(int64_t n, uint32_t c, uint64_t seed, uint32_t rep, uint8_
     return hipGetLastError();
 }
 
-hipError_t gs_row_counts(const DGraph& g, const uint8_t* col, int64_t* kept, int64_t* klow, hipStream_t st) {
+// col != nullptr: colour sparsification by col; else Bernoulli edge
+// sparsification with probability 1/c for repetition rep
+hipError_t gs_row_counts(const DGraph& g, const uint8_t* col, uint32_t c, uint64_t seed, uint32_t rep, int64_t* kept,
+                         int64_t* klow, hipStream_t st) {
     if (g.n == 0) return hipSuccess;
     const uint64_t threads = (uint64_t)g.n * 16;
-    hipLaunchKernelGGL(row_count_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, g, col, kept,
-                       klow);
+    const KeepRule kr{col, seed, rep, c};
+    if (col)
+        hipLaunchKernelGGL(row_count_kernel<false>, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, g, kr,
+                           kept, klow);
+    else
+        hipLaunchKernelGGL(row_count_kernel<true>, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, g, kr,
+                           kept, klow);
     return hipGetLastError();
 }
 
-hipError_t gs_compact(const DGraph& g, const uint8_t* col, const int64_t* noff, const int64_t* eoff, int32_t* nnbr,
-                      int32_t* narow, int2* nepair, hipStream_t st) {
+hipError_t gs_compact(const DGraph& g, const uint8_t* col, uint32_t c, uint64_t seed, uint32_t rep,
+                      const int64_t* noff, const int64_t* eoff, int32_t* nnbr, int32_t* narow, int2* nepair,
+                      hipStream_t st) {
     if (g.n == 0) return hipSuccess;
     const uint64_t threads = (uint64_t)g.n * 16;
-    hipLaunchKernelGGL(compact_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, g, col, noff, eoff,
-                       nnbr, narow, nepair);
+    const KeepRule kr{col, seed, rep, c};
+    if (col)
+        hipLaunchKernelGGL(compact_kernel<false>, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, g, kr,
+                           noff, eoff, nnbr, narow, nepair);
+    else
+        hipLaunchKernelGGL(compact_kernel<true>, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, g, kr,
+                           noff, eoff, nnbr, narow, nepair);
     return hipGetLastError();
 }
 

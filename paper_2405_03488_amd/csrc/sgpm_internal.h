@@ -153,9 +153,11 @@ uint64_t next_window_end(uint64_t n_t, const sgpm_options& o);
 
 // GS kernels (gs_kernels.hip)
 hipError_t gs_colours(int64_t n, uint32_t c, uint64_t seed, uint32_t rep, uint8_t* col, hipStream_t st);
-hipError_t gs_row_counts(const DGraph& g, const uint8_t* col, int64_t* kept, int64_t* klow, hipStream_t st);
-hipError_t gs_compact(const DGraph& g, const uint8_t* col, const int64_t* noff, const int64_t* eoff, int32_t* nnbr,
-                      int32_t* narow, int2* nepair, hipStream_t st);
+hipError_t gs_row_counts(const DGraph& g, const uint8_t* col, uint32_t c, uint64_t seed, uint32_t rep, int64_t* kept,
+                         int64_t* klow, hipStream_t st);
+hipError_t gs_compact(const DGraph& g, const uint8_t* col, uint32_t c, uint64_t seed, uint32_t rep,
+                      const int64_t* noff, const int64_t* eoff, int32_t* nnbr, int32_t* narow, int2* nepair,
+                      hipStream_t st);
 int64_t scan_scratch_words(int64_t n);
 hipError_t exclusive_scan(const int64_t* in, int64_t n, int64_t* out, int64_t* scratch, hipStream_t st);
 hipError_t max_degree(const int64_t* off, int64_t n, unsigned long long* out, hipStream_t st);
@@ -238,7 +240,7 @@ struct GsPrefix {              // colourings 0..n-1 already counted (hybrid pilo
     double dev_seconds = 0.0;
 };
 sgpm_status gs_rep(sgpm_ctx* c, sgpm_graph* g, const Plan& p, uint32_t colours, uint64_t seed, uint32_t rep,
-                   unsigned __int128* y, double* dev_seconds);
+                   unsigned __int128* y, double* dev_seconds, bool bes = false);
 uint32_t gs_colours_for(const sgpm_options& o);
 sgpm_status gs_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_options& o, sgpm_result* res,
                         const GsPrefix* pre = nullptr);

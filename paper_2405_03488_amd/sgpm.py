@@ -27,6 +27,7 @@ SGPM_ASSUME_CANONICAL = 0x1
 
 MODE_STRICT_NS, MODE_FIXED_N, MODE_GS, MODE_HYBRID = 0, 1, 2, 3
 SAMPLER_PRUNE, SAMPLER_BASE = 0, 1
+GS_COLOUR, GS_BERNOULLI = 0, 1
 SCHEME_NS, SCHEME_GS, SCHEME_EXACT = 0, 1, 2
 
 
@@ -46,7 +47,7 @@ class Options(C.Structure):
                 ("colours", C.c_int32), ("gs_reps_max", C.c_int32), ("proposal", C.c_void_p),
                 ("lanes_per_sample", C.c_int32), ("checksum", C.c_int32), ("trace_lo", C.c_uint64),
                 ("trace_hi", C.c_uint64), ("trace_buf", C.c_void_p), ("sampler", C.c_int32),
-                ("reserved1", C.c_int32)]
+                ("gs_scheme", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -112,6 +113,7 @@ def lib():
             "sgpm_estimate_batch": ([P, C.c_int, P, P, P, P], st),
             "sgpm_exact_count": ([P, P, P, P, P], st),
             "sgpm_gs_sparsify": ([P, P, C.c_uint32, C.c_uint64, C.c_uint32, PP], st),
+            "sgpm_bes_sparsify": ([P, P, C.c_uint32, C.c_uint64, C.c_uint32, PP], st),
             "sgpm_model_train": ([P, P, P, C.c_int, P, PP], st),
             "sgpm_model_free": ([P], st),
             "sgpm_model_from_tables": ([P, C.c_int, P, P, PP], st),
@@ -143,7 +145,8 @@ def lib():
 EXPORTED = ["sgpm_create", "sgpm_destroy", "sgpm_last_error", "sgpm_device_count", "sgpm_graph_from_csr",
             "sgpm_graph_stats", "sgpm_graph_export", "sgpm_graph_free", "sgpm_pattern_create", "sgpm_pattern_plan",
             "sgpm_pattern_free", "sgpm_options_default", "sgpm_estimate", "sgpm_estimate_counted",
-            "sgpm_estimate_batch", "sgpm_exact_count", "sgpm_gs_sparsify", "sgpm_model_train", "sgpm_model_free",
+            "sgpm_estimate_batch", "sgpm_exact_count", "sgpm_gs_sparsify", "sgpm_bes_sparsify",
+            "sgpm_model_train", "sgpm_model_free",
             "sgpm_model_from_tables", "sgpm_model_table", "sgpm_model_info", "sgpm_mlp_forward", "sgpm_mlp_grad",
             "sgpm_mlp_adam_steps",
             "sgpm_probe_copy", "sgpm_probe_gather", "sgpm_probe_mlp", "sgpm_host_canonicalise", "sgpm_host_plan", "sgpm_host_normal_quantile", "sgpm_host_predicted_error",
@@ -272,6 +275,12 @@ def sgpm_exact_count(ctx, g, p) -> int:
 def sgpm_gs_sparsify(ctx, g, colours, seed, rep):
     h = C.c_void_p()
     _check(ctx, lib().sgpm_gs_sparsify(ctx, g, colours, seed, rep, C.byref(h)))
+    return h
+
+
+def sgpm_bes_sparsify(ctx, g, inv_p, seed, rep):
+    h = C.c_void_p()
+    _check(ctx, lib().sgpm_bes_sparsify(ctx, g, inv_p, seed, rep, C.byref(h)))
     return h
 
 

@@ -1,4 +1,4 @@
-"""GS engine on the GPU against the oracle: colour sparsification (bit-exact
+"""GS engine on the GPU against the oracle: colour and Bernoulli edge sparsification (bit-exact
 sparsified CSR), the plan-driven exact count (bit-exact counts) and the GS
 estimate over repeated colourings (identical per-colouring counts and sums)."""
 import numpy as np
@@ -145,3 +145,46 @@ def test_sparsified_graph_supports_ns(S, O, synth, ctx, cl):
     assert r.S1 == orr.S1 and r.checksum == orr.checksum
     S.sgpm_pattern_free(p)
     S.sgpm_graph_free(sp)
+
+
+# ------------------------------------------------------------------ Bernoulli edge sparsification
+@pytest.mark.parametrize("c,seed,rep", [(1, 3, 0), (2, 3, 0), (3, 8, 1), (16, 99, 7), (256, 5, 2)])
+def test_bes_sparsify_matches_oracle(S, O, ctx, cl, c, seed, rep):
+    g, og = cl
+    sp = S.sgpm_bes_sparsify(ctx, g, c, seed, rep)
+    off, nbr = S.sgpm_graph_export(ctx, sp)
+    n, m, maxdeg, _ = S.sgpm_graph_stats(sp)
+    osp = O.bes_sparsify(og, c, seed, rep)
+    assert m == osp.m and np.array_equal(off, osp.off) and np.array_equal(nbr, osp.nbr)
+    assert maxdeg == (int(np.diff(osp.off).max()) if osp.m else 0)
+    S.sgpm_graph_free(sp)
+
+
+@pytest.mark.parametrize("name,c", [("triangle", 2), ("4-cycle", 2), ("diamond", 2), ("tailed-triangle", 3)])
+def test_bes_estimate_matches_oracle(S, O, synth, ctx, cl, name, c):
+    g, og = cl
+    k, e = synth.pattern(name)
+    p = S.sgpm_pattern_create(ctx, k, e)
+    opts = S.sgpm_options_default(mode=S.MODE_GS, gs_scheme=S.GS_BERNOULLI, colours=c, seed=23, eps=0.05,
+                                  gs_reps_max=30)
+    r, rc = S.sgpm_estimate(ctx, g, p, opts)
+    orr, ys = O.bes_run(og, O.compile_plan(k, e), c, 23, eps=0.05, confidence=0.95, reps_max=30)
+    assert r.scheme == S.SCHEME_GS and r.colours == c
+    assert r.n_samples == orr.reps and r.S1 == orr.S1 and r.S2 == orr.S2
+    assert r.estimate == orr.estimate and r.eps_hat == orr.eps_hat and r.converged == orr.converged
+    S.sgpm_pattern_free(p)
+
+
+def test_bes_refuses_what_it_cannot_estimate(S, O, synth, ctx, cl):
+    g, og = cl
+    k, e = synth.pattern("4-cycle")
+    p = S.sgpm_pattern_create(ctx, k, e, True)  # vertex-induced: non-edges are not preserved
+    with pytest.raises(S.SgpmError):
+        S.sgpm_estimate(ctx, g, p, S.sgpm_options_default(mode=S.MODE_GS, gs_scheme=S.GS_BERNOULLI, colours=2))
+    S.sgpm_pattern_free(p)
+    k, e = synth.pattern("triangle")
+    p = S.sgpm_pattern_create(ctx, k, e)
+    for kw in (dict(mode=S.MODE_STRICT_NS), dict(mode=S.MODE_HYBRID), dict(gs_scheme=5)):
+        with pytest.raises(S.SgpmError):
+            S.sgpm_estimate(ctx, g, p, S.sgpm_options_default(**{"gs_scheme": S.GS_BERNOULLI, **kw}))
+    S.sgpm_pattern_free(p)
