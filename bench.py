@@ -66,9 +66,10 @@ def measured_traffic(runs, launches):
 
 def other_legs(S, ctx, g, pats, queries, eps):
     """The rest of the hot path on the same graph: the GS engine (colour
-    sparsification + exact count, two colourings at c = 16), the loose-mode
-    choice between NS and GS at eps, the persistent batch against solo runs,
-    NS-base against NS-prune, and the MLP kernels' MFMA throughput."""
+    sparsification + exact count, two colourings at c = 16; two Bernoulli edge
+    sparsifications at p = 1/16), the loose-mode choice between NS and GS at
+    eps, the persistent batch against solo runs, NS-base against NS-prune, and
+    the MLP kernels' MFMA throughput."""
     out = {"gs": {}, "hybrid": {}}
     for q in queries:
         t0 = time.perf_counter()
@@ -76,6 +77,12 @@ def other_legs(S, ctx, g, pats, queries, eps):
                                                                         gs_reps_max=2, seed=5))
         out["gs"][q] = {"colourings": int(r.n_samples), "estimate": r.estimate, "wall_s": time.perf_counter() - t0,
                         "count_kernel_s": r.seconds_kernel}
+        t0 = time.perf_counter()
+        r, _ = S.sgpm_estimate(ctx, g, pats[q], S.sgpm_options_default(mode=S.MODE_GS, eps=eps, colours=16,
+                                                                        gs_reps_max=2, seed=5,
+                                                                        gs_scheme=S.GS_BERNOULLI))
+        out.setdefault("gs_bernoulli", {})[q] = {"reps": int(r.n_samples), "estimate": r.estimate,
+                                                 "wall_s": time.perf_counter() - t0, "count_kernel_s": r.seconds_kernel}
         r, _ = S.sgpm_estimate(ctx, g, pats[q], S.sgpm_options_default(mode=S.MODE_HYBRID, eps=eps, colours=16,
                                                                         seed=6))
         out["hybrid"][q] = {"scheme": "GS" if r.scheme == S.SCHEME_GS else "NS", "ns_cone_s": [r.pred_ns_lo,
