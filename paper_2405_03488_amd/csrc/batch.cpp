@@ -210,7 +210,8 @@ sgpm_status batch_estimate(sgpm_ctx* c, int nq, const sgpm_graph_t* graphs, cons
         r->seconds_sampling = ms * 1e-3;
         r->seconds_total = wall;
         sgpm_status st = SGPM_OK;
-        if (S.status) st = (sgpm_status)S.status;
+        if (active > 0 && !S.finished) st = SGPM_EHIP;  // the launch's watchdog ended it
+        else if (S.status) st = (sgpm_status)S.status;
         else if (S.n && memcmp(&r->eps_hat, &S.eps_hat, sizeof(double)) != 0 &&
                  !(std::isinf(r->eps_hat) && std::isinf(S.eps_hat)))
             st = SGPM_EHIP;  // the device's stop test disagrees with the host's arithmetic
@@ -218,7 +219,7 @@ sgpm_status batch_estimate(sgpm_ctx* c, int nq, const sgpm_graph_t* graphs, cons
             st = SGPM_NOT_CONVERGED;
         if (st != SGPM_OK && (worst == SGPM_OK || worst == SGPM_NOT_CONVERGED)) worst = st;
     }
-    if (worst == SGPM_EHIP) return fail(c, worst, "device predicted error differs from the host's");
+    if (worst == SGPM_EHIP) return fail(c, worst, "device stop test differs from the host's, or the batch watchdog fired");
     if (worst == SGPM_EUNSUPPORTED) return fail(c, worst, "a query needed a window of 2^32 samples or more");
     if (worst == SGPM_EOVERFLOW) return fail(c, worst, "a sample weight exceeded 128 bits");
     if (worst == SGPM_NOT_CONVERGED) return fail(c, worst, "a query reached max_samples");

@@ -281,6 +281,9 @@ __device__ __forceinline__ void run_tile(const BatchQuery& Q, uint64_t s0, uint6
 #ifndef SGPM_BATCH_IDLE_SLEEP
 #define SGPM_BATCH_IDLE_SLEEP 8
 #endif
+#ifndef SGPM_BATCH_WATCHDOG_S
+#define SGPM_BATCH_WATCHDOG_S 60
+#endif
 // blocks per CU the kernel is compiled for: the most at which the sampling
 // loops of that pattern bound keep every value in registers (the all-clique
 // build inlines one sampler per clique size, so it needs more of them)
@@ -368,6 +371,12 @@ __global__ __launch_bounds__(256, batch_occupancy(KMAX, ALLCLQ)) void batch_kern
             cw = e;
         }
     };
+    // Watchdog: a wave that has found no tile for SGPM_BATCH_WATCHDOG_S seconds
+    // of the 100 MHz real-time counter leaves (holding no sums: it flushed when
+    // it first found nothing).  A healthy batch never idles that long -- a wave
+    // idles only while other waves finish a window -- so this ends a launch
+    // whose invariants broke; the host reports the unfinished queries.
+    uint64_t idle_since = 0;
     for (;;) {
         if (hn == 0 && ld_rlx(active) == 0) break;
         int q = -1, w = 0;
@@ -400,10 +409,16 @@ __global__ __launch_bounds__(256, batch_occupancy(KMAX, ALLCLQ)) void batch_kern
             hn = hovf = 0;
         }
         if (q < 0) {
-            if (!flush) __builtin_amdgcn_s_sleep(SGPM_BATCH_IDLE_SLEEP);
+            if (!flush) {
+                const uint64_t now = __builtin_amdgcn_s_memrealtime();
+                if (idle_since == 0) idle_since = now;
+                else if (now - idle_since > (uint64_t)SGPM_BATCH_WATCHDOG_S * 100000000ull) break;
+                __builtin_amdgcn_s_sleep(SGPM_BATCH_IDLE_SLEEP);
+            }
             start = (start + 1) % nq;
             continue;
         }
+        idle_since = 0;
         start = q;
         const BatchQuery& Q = queries[q];
         const uint64_t T = (uint64_t)Q.tile;
