@@ -221,6 +221,14 @@ __device__ __forceinline__ bool fixed52(double a, uint64_t& lo, uint64_t& hi) {
 // Draws computed ahead, one per lane (the wave kernel evaluates all draws of a
 // group of samples at once).  Slot t of the current sample sits in lane
 // base + t: slots 0..k-2 hold draws 0, 2, .., k-1, slots k-1.. draws 18, 19, ..
+// A sample's first edge and the bounds of its two rows, loaded ahead by the
+// group prologue (one lane per sample, so the group's loads overlap).
+struct Head {
+    int32_t v0, v1;
+    int64_t b0, b1;
+    int32_t l0, l1;
+};
+
 struct Draws {
     uint32_t lo, hi;  // this lane's draw
     int base;         // lane of slot 0 of the current sample
@@ -245,7 +253,8 @@ __device__ __forceinline__ uint32_t ns_sample(const DGraph& g, const Plan& p, ui
                                              int32_t (&v)[8], uint64_t& alo, uint64_t& ahi, uint64_t& ovf,
                                              uint64_t& bytes, bool count_bytes, int32_t* list,
                                              const LearnArgs* la = nullptr, uint32_t* hist = nullptr,
-                                             uint32_t* sz = nullptr, const Draws* dr = nullptr) {
+                                             uint32_t* sz = nullptr, const Draws* dr = nullptr,
+                                             const Head* hd = nullptr) {
     constexpr int CAP = LDS_WORDS / (256 / G);
     const int lane = (int)(threadIdx.x & 63);
     const int gl = lane & (G - 1);
@@ -265,7 +274,14 @@ __device__ __forceinline__ uint32_t ns_sample(const DGraph& g, const Plan& p, ui
         rp[i] = nullptr;
         rl[i] = 0;
     }
-    {
+    if (hd) {
+        v[0] = hd->v0;
+        v[1] = hd->v1;
+        rp[0] = g.nbr + hd->b0;
+        rl[0] = hd->l0;
+        rp[1] = g.nbr + hd->b1;
+        rl[1] = hd->l1;
+    } else {
         const uint64_t e = __umul64hi(M, draw_at(dr, seed, s, 0, tag));
         if (oriented) {
             const int2 pr = g.epair[e];
