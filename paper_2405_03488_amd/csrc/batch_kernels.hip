@@ -227,13 +227,15 @@ __device__ __forceinline__ void run_tile(const BatchQuery& Q, uint64_t s0, uint6
             dr.k1 = K - 1;
             dr.base = 0;
         }
+        prefetch_heads(Q.g, CLQ || Q.p.oriented, dr, D, n, rec, BREC);
         for (int q = 0; q < n; ++q) {
             const uint64_t s = gb + (uint64_t)q;
             dr.base = q * D;
             int32_t v[8];
             uint64_t alo, ahi, b = 0, ov = 0;
+            const Head hd = read_head(rec + q * BREC);
             const uint32_t st = ns_sample<64, KMAX, CLQ>(Q.g, Q.p, Q.seed, Q.tag, s, v, alo, ahi, ov, b, false, list,
-                                                         nullptr, nullptr, nullptr, &dr);
+                                                         nullptr, nullptr, nullptr, &dr, &hd);
             ovf |= ov;
             if (st != 0xFFu) {
                 alo = 0;
@@ -287,7 +289,7 @@ __device__ __forceinline__ void run_tile(const BatchQuery& Q, uint64_t s0, uint6
 // blocks per CU the kernel is compiled for: the most at which the sampling
 // loops of that pattern bound keep every value in registers (the all-clique
 // build inlines one sampler per clique size, so it needs more of them)
-constexpr int batch_occupancy(int kmax, bool clq) { return clq ? (kmax <= 4 ? 6 : 5) : kmax <= 5 ? 6 : kmax == 6 ? 5 : 4; }
+constexpr int batch_occupancy(int kmax, bool clq) { return clq ? (kmax == 4 ? 6 : 5) : kmax <= 5 ? 6 : kmax == 6 ? 5 : 4; }
 
 // a tile of a k-clique query (3 <= k <= KMAX) with the sampler compiled for k
 template <int KMAX>

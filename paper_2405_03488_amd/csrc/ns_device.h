@@ -534,6 +534,47 @@ __device__ __forceinline__ uint32_t ns_sample(const DGraph& g, const Plan& p, ui
     return 0xFFu;
 }
 
+// Group prologue: lane q < n takes its sample's first draw (held by lane q D),
+// loads the first edge and both row bounds, and parks them in the sample's
+// record slot (words 0-7 of a 16-byte aligned slot of `stride` words); the
+// sample reads them back with read_head before it writes its record there.
+__device__ __forceinline__ void prefetch_heads(const DGraph& g, bool oriented, const Draws& dr, int D, int n,
+                                               uint32_t* rec, int stride) {
+    const int lane = (int)(threadIdx.x & 63);
+    const uint32_t rlo = __shfl(dr.lo, lane * D), rhi = __shfl(dr.hi, lane * D);
+    if (lane < n) {
+        const uint64_t M = oriented ? (uint64_t)g.m : 2ull * (uint64_t)g.m;
+        const uint64_t e = __umul64hi(M, ((uint64_t)rhi << 32) | rlo);
+        int32_t h0, h1;
+        if (oriented) {
+            const int2 pr = g.epair[e];
+            h0 = pr.x;
+            h1 = pr.y;
+        } else {
+            h0 = g.arow[e];
+            h1 = g.nbr[e];
+        }
+        const int64_t b0 = g.off[h0], e0 = g.off[h0 + 1], b1 = g.off[h1], e1 = g.off[h1 + 1];
+        uint4* h4 = reinterpret_cast<uint4*>(rec + lane * stride);
+        h4[0] = make_uint4((uint32_t)h0, (uint32_t)h1, (uint32_t)(e0 - b0), (uint32_t)(e1 - b1));
+        h4[1] = make_uint4((uint32_t)b0, (uint32_t)((uint64_t)b0 >> 32), (uint32_t)b1, (uint32_t)((uint64_t)b1 >> 32));
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ Head read_head(const uint32_t* slot) {
+    const uint4 a4 = reinterpret_cast<const uint4*>(slot)[0];
+    const uint4 b4 = reinterpret_cast<const uint4*>(slot)[1];
+    Head h;
+    h.v0 = rfl((int32_t)a4.x);
+    h.v1 = rfl((int32_t)a4.y);
+    h.l0 = rfl((int32_t)a4.z);
+    h.l1 = rfl((int32_t)a4.w);
+    h.b0 = rfl64((int64_t)(((uint64_t)b4.y << 32) | b4.x));
+    h.b1 = rfl64((int64_t)(((uint64_t)b4.w << 32) | b4.z));
+    return h;
+}
+
 // Whether x is in the ascending row R[0, L), by the whole wave: G-ary rounds
 // (64 probes, keep the gap that holds x) until one window of 64 remains.
 __device__ __forceinline__ bool wave_row_has(const int32_t* __restrict__ R, int32_t L, int32_t x) {

@@ -246,46 +246,13 @@ __global__ __launch_bounds__(256, wave_occupancy(MODE, CLQ)) void ns_wave_kernel
                 dr.k1 = K - 1;
                 dr.base = 0;
             }
-            // heads: lane q < n takes sample gb + q's first draw, loads its first
-            // edge and both row bounds, and parks them in the sample's record
-            // slot (words 0-7), which the sample reads before it writes its record
-            if constexpr (MODE != 3) {
-                const uint32_t rlo = __shfl(dr.lo, lane * D), rhi = __shfl(dr.hi, lane * D);
-                if (lane < n) {
-                    const bool oriented = CLQ || p.oriented;
-                    const uint64_t M = oriented ? (uint64_t)g.m : 2ull * (uint64_t)g.m;
-                    const uint64_t e = __umul64hi(M, ((uint64_t)rhi << 32) | rlo);
-                    int32_t h0, h1;
-                    if (oriented) {
-                        const int2 pr = g.epair[e];
-                        h0 = pr.x;
-                        h1 = pr.y;
-                    } else {
-                        h0 = g.arow[e];
-                        h1 = g.nbr[e];
-                    }
-                    const int64_t b0 = g.off[h0], e0 = g.off[h0 + 1], b1 = g.off[h1], e1 = g.off[h1 + 1];
-                    uint4* h4 = reinterpret_cast<uint4*>(rec + lane * REC);
-                    h4[0] = make_uint4((uint32_t)h0, (uint32_t)h1, (uint32_t)(e0 - b0), (uint32_t)(e1 - b1));
-                    h4[1] = make_uint4((uint32_t)b0, (uint32_t)((uint64_t)b0 >> 32), (uint32_t)b1,
-                                       (uint32_t)((uint64_t)b1 >> 32));
-                }
-                __builtin_amdgcn_wave_barrier();
-            }
+            // heads: every sample's first edge and row bounds, loaded at once
+            if constexpr (MODE != 3) prefetch_heads(g, CLQ || p.oriented, dr, D, n, rec, REC);
             for (int q = 0; q < n; ++q) {
                 const uint64_t s = gb + (uint64_t)q;
                 dr.base = q * D;
                 Head hd;
-                if constexpr (MODE != 3) {
-                    const uint4 a4 = reinterpret_cast<const uint4*>(rec + q * REC)[0];
-                    const uint4 b4 = reinterpret_cast<const uint4*>(rec + q * REC)[1];
-                    hd.v0 = rfl((int32_t)a4.x);
-                    hd.v1 = rfl((int32_t)a4.y);
-                    hd.l0 = rfl((int32_t)a4.z);
-                    hd.l1 = rfl((int32_t)a4.w);
-                    hd.b0 = rfl64((int64_t)(((uint64_t)b4.y << 32) | b4.x));
-                    hd.b1 = rfl64((int64_t)(((uint64_t)b4.w << 32) | b4.z));
-                }
+                if constexpr (MODE != 3) hd = read_head(rec + q * REC);
                 int32_t v[8];
                 uint64_t alo, ahi, b = 0, ov = 0;
                 uint32_t sz[8] = {0, 0, 0, 0, 0, 0, 0, 0};
