@@ -269,12 +269,39 @@ def workload_c5(S, synth, args):
     return out
 
 
+def workload_coverage(S, synth, args):
+    """R-MAT 20, 4-clique and 5-clique: the exact counts (the GS exact count with
+    one colour class, i.e. the whole graph), then 100 strict NS runs to eps with
+    different seeds: the fraction of 95 % intervals that contain the exact count
+    and the stop points reached (the stop rule's coverage)."""
+    ctx = S.sgpm_create(0)
+    g, gi = load_graph(S, synth, ctx, "rmat20", 1 << 20, lambda: synth.rmat_pairs(20, 16, 0.57, 0.19, 0.19, seed=1))
+    out = {"metric": "95 % interval coverage over 100 seeds, R-MAT 20", "graph": gi, "eps": args.eps, "queries": {}}
+    for q in ("4-clique", "5-clique"):
+        p = S.sgpm_pattern_create(ctx, *synth.pattern(q))
+        t0 = time.perf_counter()
+        exact = S.sgpm_exact_count(ctx, g, p)
+        te = time.perf_counter() - t0
+        log(f"coverage {q}: exact {exact} in {te:.2f} s")
+        cover, ns, errs = 0, [], []
+        for seed in range(100):
+            r, _ = S.sgpm_estimate(ctx, g, p, S.sgpm_options_default(eps=args.eps, seed=1000 + seed))
+            cover += int(r.ci_lo <= exact <= r.ci_hi)
+            ns.append(int(r.n_samples))
+            errs.append(abs(r.estimate - exact) / exact)
+        out["queries"][q] = {"exact": exact, "exact_count_s": te, "coverage": cover / 100,
+                             "n_stop": sorted(set(ns)), "mean_rel_err": sum(errs) / len(errs),
+                             "max_rel_err": max(errs)}
+        log(f"coverage {q}: {out['queries'][q]}")
+    return out
+
+
 def torch_sync():
     import torch
     torch.cuda.synchronize()
 
 
-WORKLOADS = {"c3": workload_c3, "c4": workload_c4, "c5": workload_c5}
+WORKLOADS = {"c3": workload_c3, "c4": workload_c4, "c5": workload_c5, "coverage": workload_coverage}
 
 
 def main():
@@ -288,10 +315,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-probes", action="store_true", help="skip the measured copy/gather rooflines")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-uniform leg")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "coverage"],
                     help="c2 (default): R-MAT 20 4-/5-clique, the benchmark line; c3: 24 motif queries on three "
                          "Chung-Lu graphs, batch vs solo; c4: R-MAT 24 5-clique, learned vs uniform; c5: R-MAT 26 "
-                         "6-clique, 5-cycle, diamond in loose (hybrid) mode")
+                         "6-clique, 5-cycle, diamond in loose (hybrid) mode; coverage: exact counts and the 95 %% "
+                         "intervals of 100 seeds on R-MAT 20")
     ap.add_argument("--counters-run", action="store_true",
                     help="short run for hardware counters: one 256 MiB copy, then one 4M-sample window per query")
     args = ap.parse_args()
