@@ -471,6 +471,9 @@ def main():
         log(f"cpu oracle: {N / dt:.4g} samples/s ({N} samples, {dt:.1f}s, {th} threads)")
 
     value = total_samples / wall
+    traffic = measured_traffic(runs, launches)
+    avg_launch_s = kernel_s / max(1, launches)
+    gather = (probes or {}).get("gather_64B_GBs")
     line = {
         "metric": METRIC, "value": value, "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
@@ -482,7 +485,13 @@ def main():
         "queries": per_q,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(runs, launches),
+                     "traffic": traffic,
+                     # the counted HBM traffic as a rate, and the algorithmic and traffic rates against the
+                     # measured random 64-B gather rate over the same working set (the bound that applies)
+                     "traffic_GBs": traffic / avg_launch_s / 1e9 if traffic else None,
+                     "frac_of_gather_probe": achieved / gather if gather else None,
+                     "traffic_frac_of_gather_probe": traffic / avg_launch_s / 1e9 / gather
+                     if (traffic and gather) else None,
                      "kernel": sorted({"ns_wave_kernel" if lanes[q] == 64 else f"ns_window_kernel<{lanes[q]}>"
                                        for q in queries}),
                      "launches": launches,
