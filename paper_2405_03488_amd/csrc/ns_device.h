@@ -227,6 +227,7 @@ struct Head {
     int32_t v0, v1;
     int64_t b0, b1;
     int32_t l0, l1;
+    int32_t k0, k1;  // learned proposal: degree buckets of v0 and v1
 };
 
 struct Draws {
@@ -304,7 +305,7 @@ __device__ __forceinline__ uint32_t ns_sample(const DGraph& g, const Plan& p, ui
     const bool learned = (G == 64) && la != nullptr && la->table != nullptr;
     double af = (double)M;
     int32_t b0 = 0;
-    if (learned) b0 = bucket_of(*la, v[0]);
+    if (learned) b0 = hd ? hd->k0 : bucket_of(*la, v[0]);
     uint32_t opened = 0;
     int32_t prevcnt = -1;  // |S_{j-1}| when the whole set sits in `list`
 
@@ -327,7 +328,7 @@ __device__ __forceinline__ uint32_t ns_sample(const DGraph& g, const Plan& p, ui
         const bool weighted = learned && j + 1 < pk;
         uint64_t wrow = 0;
         if (weighted && lane < 32) {
-            const int32_t bp = bucket_of(*la, v[j - 1]);
+            const int32_t bp = (j == 2 && hd) ? hd->k1 : bucket_of(*la, v[j - 1]);
             wrow = (uint64_t)la->table[(((size_t)j * 32 + (size_t)b0) * 32 + (size_t)bp) * 32 + lane];
         }
         // smallest connected earlier row (lowest position on ties)
@@ -539,7 +540,7 @@ __device__ __forceinline__ uint32_t ns_sample(const DGraph& g, const Plan& p, ui
 // record slot (words 0-7 of a 16-byte aligned slot of `stride` words); the
 // sample reads them back with read_head before it writes its record there.
 __device__ __forceinline__ void prefetch_heads(const DGraph& g, bool oriented, const Draws& dr, int D, int n,
-                                               uint32_t* rec, int stride) {
+                                               uint32_t* rec, int stride, const LearnArgs* la = nullptr) {
     const int lane = (int)(threadIdx.x & 63);
     const uint32_t rlo = __shfl(dr.lo, lane * D), rhi = __shfl(dr.hi, lane * D);
     if (lane < n) {
@@ -558,14 +559,24 @@ __device__ __forceinline__ void prefetch_heads(const DGraph& g, bool oriented, c
         uint4* h4 = reinterpret_cast<uint4*>(rec + lane * stride);
         h4[0] = make_uint4((uint32_t)h0, (uint32_t)h1, (uint32_t)(e0 - b0), (uint32_t)(e1 - b1));
         h4[1] = make_uint4((uint32_t)b0, (uint32_t)((uint64_t)b0 >> 32), (uint32_t)b1, (uint32_t)((uint64_t)b1 >> 32));
+        if (la) {  // words 8-9: the buckets of the first edge's ends (learned proposal)
+            uint2* k2 = reinterpret_cast<uint2*>(rec + lane * stride + 8);
+            k2[0] = make_uint2((uint32_t)bucket_of(*la, h0), (uint32_t)bucket_of(*la, h1));
+        }
     }
     __builtin_amdgcn_wave_barrier();
 }
 
-__device__ __forceinline__ Head read_head(const uint32_t* slot) {
+__device__ __forceinline__ Head read_head(const uint32_t* slot, bool learned = false) {
     const uint4 a4 = reinterpret_cast<const uint4*>(slot)[0];
     const uint4 b4 = reinterpret_cast<const uint4*>(slot)[1];
     Head h;
+    h.k0 = h.k1 = 0;
+    if (learned) {
+        const uint2 k2 = reinterpret_cast<const uint2*>(slot + 8)[0];
+        h.k0 = rfl((int32_t)k2.x);
+        h.k1 = rfl((int32_t)k2.y);
+    }
     h.v0 = rfl((int32_t)a4.x);
     h.v1 = rfl((int32_t)a4.y);
     h.l0 = rfl((int32_t)a4.z);

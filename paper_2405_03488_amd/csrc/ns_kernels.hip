@@ -247,12 +247,12 @@ __global__ __launch_bounds__(256, wave_occupancy(MODE, CLQ)) void ns_wave_kernel
                 dr.base = 0;
             }
             // heads: every sample's first edge and row bounds, loaded at once
-            if constexpr (MODE != 3) prefetch_heads(g, CLQ || p.oriented, dr, D, n, rec, REC);
+            if constexpr (MODE != 3) prefetch_heads(g, CLQ || p.oriented, dr, D, n, rec, REC, MODE == 1 ? &lal : nullptr);
             for (int q = 0; q < n; ++q) {
                 const uint64_t s = gb + (uint64_t)q;
                 dr.base = q * D;
                 Head hd;
-                if constexpr (MODE != 3) hd = read_head(rec + q * REC);
+                if constexpr (MODE != 3) hd = read_head(rec + q * REC, MODE == 1);
                 int32_t v[8];
                 uint64_t alo, ahi, b = 0, ov = 0;
                 uint32_t sz[8] = {0, 0, 0, 0, 0, 0, 0, 0};
