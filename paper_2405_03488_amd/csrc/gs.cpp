@@ -34,11 +34,16 @@ sgpm_status sparsify(sgpm_ctx* c, sgpm_graph* g, uint32_t colours, uint64_t seed
     if (colours < 1 || colours > 256) return fail(c, SGPM_EINVAL, "colours must be in [1, 256]");
     HIP_TRY(c, hipSetDevice(c->dev));
     const int64_t n = g->n;
-    DevBuf col, kept, klow, scratch;
+    const int64_t nt = arc_tiles(2 * g->m);
+    DevBuf col, rstart, rlow, tk, tl, tko, tlo, scratch;
     HIP_TRY(c, hipMalloc(&col.p, (size_t)std::max<int64_t>(n, 1)));
-    HIP_TRY(c, hipMalloc(&kept.p, sizeof(int64_t) * (size_t)std::max<int64_t>(n, 1)));
-    HIP_TRY(c, hipMalloc(&klow.p, sizeof(int64_t) * (size_t)std::max<int64_t>(n, 1)));
-    HIP_TRY(c, hipMalloc(&scratch.p, sizeof(int64_t) * (size_t)scan_scratch_words(n)));
+    HIP_TRY(c, hipMalloc(&rstart.p, sizeof(int64_t) * (size_t)std::max<int64_t>(n, 1)));
+    HIP_TRY(c, hipMalloc(&rlow.p, sizeof(int64_t) * (size_t)std::max<int64_t>(n, 1)));
+    HIP_TRY(c, hipMalloc(&tk.p, sizeof(int64_t) * (size_t)(nt + 1)));
+    HIP_TRY(c, hipMalloc(&tl.p, sizeof(int64_t) * (size_t)(nt + 1)));
+    HIP_TRY(c, hipMalloc(&tko.p, sizeof(int64_t) * (size_t)(nt + 1)));
+    HIP_TRY(c, hipMalloc(&tlo.p, sizeof(int64_t) * (size_t)(nt + 1)));
+    HIP_TRY(c, hipMalloc(&scratch.p, sizeof(int64_t) * (size_t)scan_scratch_words(nt)));
     auto h = std::make_unique<sgpm_graph>();
     h->ctx = c;
     h->n = n;
@@ -50,25 +55,27 @@ sgpm_status sparsify(sgpm_ctx* c, sgpm_graph* g, uint32_t colours, uint64_t seed
     const DGraph dg = g->view();
     const uint8_t* colp = bes ? nullptr : (const uint8_t*)col.p;
     if (!bes) HIP_TRY(c, gs_colours(n, colours, seed, rep, (uint8_t*)col.p, c->st));
-    HIP_TRY(c, gs_row_counts(dg, colp, colours, seed, rep, (int64_t*)kept.p, (int64_t*)klow.p, c->st));
-    if (n > 0) {
-        HIP_TRY(c, exclusive_scan((int64_t*)kept.p, n, h->d_off, (int64_t*)scratch.p, c->st));
-        HIP_TRY(c, exclusive_scan((int64_t*)klow.p, n, d_eoff, (int64_t*)scratch.p, c->st));
-    } else {
-        HIP_TRY(c, hipMemsetAsync(h->d_off, 0, sizeof(int64_t), c->st));
-        HIP_TRY(c, hipMemsetAsync(d_eoff, 0, sizeof(int64_t), c->st));
-    }
+    // arcs surviving per tile, their exclusive scans, then the totals
     int64_t arcs = 0, edges = 0;
-    HIP_TRY(c, hipMemcpyAsync(&arcs, h->d_off + n, sizeof(int64_t), hipMemcpyDeviceToHost, c->st));
-    HIP_TRY(c, hipMemcpyAsync(&edges, d_eoff + n, sizeof(int64_t), hipMemcpyDeviceToHost, c->st));
-    HIP_TRY(c, hipStreamSynchronize(c->st));
+    if (nt > 0) {
+        HIP_TRY(c, gs_arc_counts(dg, colp, colours, seed, rep, (int64_t*)tk.p, (int64_t*)tl.p, c->st));
+        HIP_TRY(c, exclusive_scan((int64_t*)tk.p, nt, (int64_t*)tko.p, (int64_t*)scratch.p, c->st));
+        HIP_TRY(c, exclusive_scan((int64_t*)tl.p, nt, (int64_t*)tlo.p, (int64_t*)scratch.p, c->st));
+        HIP_TRY(c, hipMemcpyAsync(&arcs, (int64_t*)tko.p + nt, sizeof(int64_t), hipMemcpyDeviceToHost, c->st));
+        HIP_TRY(c, hipMemcpyAsync(&edges, (int64_t*)tlo.p + nt, sizeof(int64_t), hipMemcpyDeviceToHost, c->st));
+        HIP_TRY(c, hipStreamSynchronize(c->st));
+    } else {
+        HIP_TRY(c, launch_fill_u64((unsigned long long*)tko.p, 1, 0ull, c->st));
+        HIP_TRY(c, launch_fill_u64((unsigned long long*)tlo.p, 1, 0ull, c->st));
+    }
     if (arcs != 2 * edges) return fail(c, SGPM_EHIP, "internal: sparsified graph is not symmetric");
     h->m = edges;
     HIP_TRY(c, hipMalloc(&h->d_nbr, sizeof(int32_t) * (size_t)std::max<int64_t>(arcs, 1)));
     HIP_TRY(c, hipMalloc(&h->d_arow, sizeof(int32_t) * (size_t)std::max<int64_t>(arcs, 1)));
     HIP_TRY(c, hipMalloc(&h->d_epair, sizeof(int2) * (size_t)std::max<int64_t>(edges, 1)));
-    HIP_TRY(c, gs_compact(dg, colp, colours, seed, rep, h->d_off, d_eoff, h->d_nbr, h->d_arow, h->d_epair, c->st));
-    unsigned long long* d_md = (unsigned long long*)kept.p;  // reuse as the max-degree cell
+    HIP_TRY(c, gs_arc_write(dg, colp, colours, seed, rep, (int64_t*)tko.p, (int64_t*)tlo.p, h->d_nbr, h->d_arow,
+                            h->d_epair, (int64_t*)rstart.p, (int64_t*)rlow.p, h->d_off, d_eoff, c->st));
+    unsigned long long* d_md = (unsigned long long*)rstart.p;  // reuse as the max-degree cell
     HIP_TRY(c, launch_fill_u64(d_md, 1, 0ull, c->st));
     HIP_TRY(c, max_degree(h->d_off, n, d_md, c->st));
     unsigned long long md = 0;

@@ -83,63 +83,119 @@ __device__ __forceinline__ bool keep_arc(const KeepRule& k, int64_t u, uint8_t c
     }
 }
 
-// 16 lanes per row: kept[u] = surviving neighbours, klow[u] = those below u
+// Arc-parallel sparsification: arcs in CSR order, tiles of ARC_TILE
+// consecutive arcs per block (coalesced reads of the arc's row and neighbour,
+// no per-row loop, so a hub's row costs what its arcs cost).  Pass 1 counts the
+// surviving arcs (and those with w < u, the oriented edges) per tile; after an
+// exclusive scan of the tile counts, pass 2 writes every surviving arc at its
+// global rank (the order of arcs is kept, so rows stay ascending) and, at each
+// row's first arc, the ranks before it; pass 3 turns those into row offsets
+// (an empty row takes the offset of the next non-empty one).
+constexpr int ARC_TILE = 2048;  // 256 threads x 8
+
 template <bool BES>
-__global__ __launch_bounds__(256) void row_count_kernel(DGraph g, KeepRule kr, int64_t* __restrict__ kept,
-                                                        int64_t* __restrict__ klow) {
-    const int lane = (int)(threadIdx.x & 63), sub = lane & 15, gbase = lane & ~15;
-    const uint64_t gmask = 0xFFFFull << gbase;
-    const int64_t u = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
-    if (u >= g.n) return;
-    const int64_t b = g.off[u], e = g.off[u + 1];
-    const uint8_t cu = BES ? 0 : kr.col[u];
-    int64_t k = 0, kl = 0;
-    for (int64_t a = b + sub; a < e; a += 16) {
-        const int32_t w = g.nbr[a];
-        if (keep_arc<BES>(kr, u, cu, w)) {
-            k++;
-            if (w < u) kl++;
+__global__ __launch_bounds__(256) void arc_count_kernel(DGraph g, KeepRule kr, int64_t narcs,
+                                                        int64_t* __restrict__ tk, int64_t* __restrict__ tl) {
+    const int64_t t0 = (int64_t)blockIdx.x * ARC_TILE;
+    int k = 0, l = 0;
+#pragma unroll
+    for (int i = 0; i < ARC_TILE / 256; ++i) {
+        const int64_t a = t0 + i * 256 + (int64_t)threadIdx.x;
+        if (a < narcs) {
+            const int32_t u = g.arow[a], w = g.nbr[a];
+            if (keep_arc<BES>(kr, u, BES ? (uint8_t)0 : kr.col[u], w)) {
+                k++;
+                if (w < u) l++;
+            }
         }
     }
-    // reduce within the 16-lane group
 #pragma unroll
-    for (int o = 8; o > 0; o >>= 1) {
-        k += __shfl_xor(k, o, 16);
-        kl += __shfl_xor(kl, o, 16);
+    for (int o = 32; o > 0; o >>= 1) {
+        k += __shfl_xor(k, o);
+        l += __shfl_xor(l, o);
     }
-    (void)gmask;
-    if (sub == 0) {
-        kept[u] = k;
-        klow[u] = kl;
+    __shared__ int sk[4], sl[4];
+    if ((threadIdx.x & 63) == 0) {
+        sk[threadIdx.x >> 6] = k;
+        sl[threadIdx.x >> 6] = l;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        tk[blockIdx.x] = (int64_t)(sk[0] + sk[1] + sk[2] + sk[3]);
+        tl[blockIdx.x] = (int64_t)(sl[0] + sl[1] + sl[2] + sl[3]);
     }
 }
 
 template <bool BES>
-__global__ __launch_bounds__(256) void compact_kernel(DGraph g, KeepRule kr, const int64_t* __restrict__ noff,
-                                                      const int64_t* __restrict__ eoff, int32_t* __restrict__ nnbr,
-                                                      int32_t* __restrict__ narow, int2* __restrict__ nepair) {
-    const int lane = (int)(threadIdx.x & 63), sub = lane & 15, gbase = lane & ~15;
-    const uint64_t gmask = 0xFFFFull << gbase;
+__global__ __launch_bounds__(256) void arc_write_kernel(DGraph g, KeepRule kr, int64_t narcs,
+                                                        const int64_t* __restrict__ tko,
+                                                        const int64_t* __restrict__ tlo, int32_t* __restrict__ nnbr,
+                                                        int32_t* __restrict__ narow, int2* __restrict__ nepair,
+                                                        int64_t* __restrict__ rstart, int64_t* __restrict__ rlow) {
+    const int lane = (int)(threadIdx.x & 63), wid = (int)(threadIdx.x >> 6);
     const uint64_t below = (1ull << lane) - 1ull;
-    const int64_t u = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
-    if (u >= g.n) return;
-    const int64_t b = g.off[u], e = g.off[u + 1];
-    const uint8_t cu = BES ? 0 : kr.col[u];
-    int64_t pos = noff[u], epos = eoff[u];
-    for (int64_t base = b; base < e; base += 16) {
-        const int64_t a = base + sub;
-        const int32_t w = a < e ? g.nbr[a] : GBIG;
-        const bool keep = a < e && keep_arc<BES>(kr, u, cu, w);
-        const uint64_t km = __ballot(keep) & gmask;
-        const uint64_t lm = __ballot(keep && w < u) & gmask;
-        if (keep) {
-            const int64_t at = pos + __popcll(km & below);
-            nnbr[at] = w;
-            narow[at] = (int32_t)u;
-            if (w < u) nepair[epos + __popcll(lm & below)] = make_int2((int32_t)u, w);
+    __shared__ int sk[4], sl[4];
+    const int64_t t0 = (int64_t)blockIdx.x * ARC_TILE;
+    int64_t pos = tko[blockIdx.x], lpos = tlo[blockIdx.x];
+    for (int i = 0; i < ARC_TILE / 256; ++i) {
+        const int64_t a = t0 + i * 256 + (int64_t)threadIdx.x;
+        bool keep = false, low = false, first = false;
+        int32_t u = 0, w = 0;
+        if (a < narcs) {
+            u = g.arow[a];
+            w = g.nbr[a];
+            keep = keep_arc<BES>(kr, u, BES ? (uint8_t)0 : kr.col[u], w);
+            low = keep && w < u;
+            first = a == 0 || g.arow[a - 1] != u;
         }
-        pos += __popcll(km);
-        epos += __popcll(lm);
+        const uint64_t km = __ballot(keep), lm = __ballot(low);
+        if (lane == 0) {
+            sk[wid] = (int)__popcll(km);
+            sl[wid] = (int)__popcll(lm);
+        }
+        __syncthreads();
+        int kb = 0, lb = 0, kt = 0, lt = 0;
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+            if (x < wid) {
+                kb += sk[x];
+                lb += sl[x];
+            }
+            kt += sk[x];
+            lt += sl[x];
+        }
+        const int64_t p = pos + kb + (int64_t)__popcll(km & below);
+        const int64_t lp = lpos + lb + (int64_t)__popcll(lm & below);
+        if (keep) {
+            nnbr[p] = w;
+            narow[p] = u;
+            if (low) nepair[lp] = make_int2(u, w);
+        }
+        if (first) {
+            rstart[u] = p;
+            rlow[u] = lp;
+        }
+        pos += kt;
+        lpos += lt;
+        __syncthreads();
+    }
+}
+
+__global__ void arc_row_offsets_kernel(const int64_t* __restrict__ off, int64_t n, int64_t narcs,
+                                       const int32_t* __restrict__ arow, const int64_t* __restrict__ rstart,
+                                       const int64_t* __restrict__ rlow, const int64_t* __restrict__ ktot,
+                                       const int64_t* __restrict__ ltot, int64_t* __restrict__ noff,
+                                       int64_t* __restrict__ neoff) {
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u > n) return;
+    const int64_t a = u < n ? off[u] : narcs;
+    if (a < narcs) {
+        const int32_t v = arow[a];  // the row that owns arc a: u itself, or the next non-empty row
+        noff[u] = rstart[v];
+        neoff[u] = rlow[v];
+    } else {
+        noff[u] = *ktot;
+        neoff[u] = *ltot;
     }
 }
 
@@ -470,34 +526,38 @@ hipError_t gs_colours(int64_t n, uint32_t c, uint64_t seed, uint32_t rep, uint8_
     return hipGetLastError();
 }
 
-// col != nullptr: colour sparsification by col; else Bernoulli edge
-// sparsification with probability 1/c for repetition rep
-hipError_t gs_row_counts(const DGraph& g, const uint8_t* col, uint32_t c, uint64_t seed, uint32_t rep, int64_t* kept,
-                         int64_t* klow, hipStream_t st) {
-    if (g.n == 0) return hipSuccess;
-    const uint64_t threads = (uint64_t)g.n * 16;
+int64_t arc_tiles(int64_t narcs) { return (narcs + ARC_TILE - 1) / ARC_TILE; }
+
+// pass 1: per-tile counts of surviving arcs and oriented edges (tk, tl: arc_tiles entries)
+hipError_t gs_arc_counts(const DGraph& g, const uint8_t* col, uint32_t c, uint64_t seed, uint32_t rep, int64_t* tk,
+                         int64_t* tl, hipStream_t st) {
+    const int64_t narcs = 2 * g.m, nt = arc_tiles(narcs);
+    if (nt == 0) return hipSuccess;
     const KeepRule kr{col, seed, rep, c};
-    if (col)
-        hipLaunchKernelGGL(row_count_kernel<false>, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, g, kr,
-                           kept, klow);
-    else
-        hipLaunchKernelGGL(row_count_kernel<true>, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, g, kr,
-                           kept, klow);
+    if (col) hipLaunchKernelGGL(arc_count_kernel<false>, dim3((unsigned)nt), dim3(256), 0, st, g, kr, narcs, tk, tl);
+    else hipLaunchKernelGGL(arc_count_kernel<true>, dim3((unsigned)nt), dim3(256), 0, st, g, kr, narcs, tk, tl);
     return hipGetLastError();
 }
 
-hipError_t gs_compact(const DGraph& g, const uint8_t* col, uint32_t c, uint64_t seed, uint32_t rep,
-                      const int64_t* noff, const int64_t* eoff, int32_t* nnbr, int32_t* narow, int2* nepair,
-                      hipStream_t st) {
-    if (g.n == 0) return hipSuccess;
-    const uint64_t threads = (uint64_t)g.n * 16;
+// passes 2 and 3: tko, tlo the exclusive scans of the tile counts (arc_tiles + 1
+// entries each, the last ones the totals); rstart, rlow n words of scratch;
+// noff, neoff n + 1 offsets of the new rows and oriented edges
+hipError_t gs_arc_write(const DGraph& g, const uint8_t* col, uint32_t c, uint64_t seed, uint32_t rep,
+                        const int64_t* tko, const int64_t* tlo, int32_t* nnbr, int32_t* narow,
+                        int2* nepair, int64_t* rstart, int64_t* rlow, int64_t* noff, int64_t* neoff,
+                        hipStream_t st) {
+    const int64_t narcs = 2 * g.m, nt = arc_tiles(narcs);
     const KeepRule kr{col, seed, rep, c};
-    if (col)
-        hipLaunchKernelGGL(compact_kernel<false>, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, g, kr,
-                           noff, eoff, nnbr, narow, nepair);
-    else
-        hipLaunchKernelGGL(compact_kernel<true>, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, g, kr,
-                           noff, eoff, nnbr, narow, nepair);
+    if (nt > 0) {
+        if (col)
+            hipLaunchKernelGGL(arc_write_kernel<false>, dim3((unsigned)nt), dim3(256), 0, st, g, kr, narcs, tko, tlo,
+                               nnbr, narow, nepair, rstart, rlow);
+        else
+            hipLaunchKernelGGL(arc_write_kernel<true>, dim3((unsigned)nt), dim3(256), 0, st, g, kr, narcs, tko, tlo,
+                               nnbr, narow, nepair, rstart, rlow);
+    }
+    hipLaunchKernelGGL(arc_row_offsets_kernel, dim3((unsigned)((g.n + 1 + 255) / 256)), dim3(256), 0, st, g.off, g.n,
+                       narcs, g.arow, rstart, rlow, tko + nt, tlo + nt, noff, neoff);
     return hipGetLastError();
 }
 

@@ -153,11 +153,14 @@ uint64_t next_window_end(uint64_t n_t, const sgpm_options& o);
 
 // GS kernels (gs_kernels.hip)
 hipError_t gs_colours(int64_t n, uint32_t c, uint64_t seed, uint32_t rep, uint8_t* col, hipStream_t st);
-hipError_t gs_row_counts(const DGraph& g, const uint8_t* col, uint32_t c, uint64_t seed, uint32_t rep, int64_t* kept,
-                         int64_t* klow, hipStream_t st);
-hipError_t gs_compact(const DGraph& g, const uint8_t* col, uint32_t c, uint64_t seed, uint32_t rep,
-                      const int64_t* noff, const int64_t* eoff, int32_t* nnbr, int32_t* narow, int2* nepair,
-                      hipStream_t st);
+int64_t arc_tiles(int64_t narcs);
+// col != nullptr: colour sparsification by col; else Bernoulli edge
+// sparsification with probability 1/c for repetition rep
+hipError_t gs_arc_counts(const DGraph& g, const uint8_t* col, uint32_t c, uint64_t seed, uint32_t rep, int64_t* tk,
+                         int64_t* tl, hipStream_t st);
+hipError_t gs_arc_write(const DGraph& g, const uint8_t* col, uint32_t c, uint64_t seed, uint32_t rep,
+                        const int64_t* tko, const int64_t* tlo, int32_t* nnbr, int32_t* narow, int2* nepair,
+                        int64_t* rstart, int64_t* rlow, int64_t* noff, int64_t* neoff, hipStream_t st);
 int64_t scan_scratch_words(int64_t n);
 hipError_t exclusive_scan(const int64_t* in, int64_t n, int64_t* out, int64_t* scratch, hipStream_t st);
 hipError_t max_degree(const int64_t* off, int64_t n, unsigned long long* out, hipStream_t st);
