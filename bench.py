@@ -37,13 +37,18 @@ def log(*a):
 
 
 def kernel_source_hash() -> str:
-    """Hash of the sampling kernel's sources; counter figures are only reported
-    while it matches the hash they were taken with."""
+    """Hash of the sampling kernel's sources (its two files and the types it
+    takes, the part of sgpm_internal.h before the kernel declarations);
+    counter figures are only reported while it matches the hash they were
+    taken with."""
     import hashlib
     h = hashlib.sha256()
-    for name in ("ns_kernels.hip", "ns_device.h", "sgpm_internal.h"):
-        with open(os.path.join(ROOT, "paper_2405_03488_amd", "csrc", name), "rb") as f:
+    csrc = os.path.join(ROOT, "paper_2405_03488_amd", "csrc")
+    for name in ("ns_kernels.hip", "ns_device.h"):
+        with open(os.path.join(csrc, name), "rb") as f:
             h.update(f.read())
+    with open(os.path.join(csrc, "sgpm_internal.h"), "rb") as f:
+        h.update(f.read().split(b"// kernels (ns_kernels.hip)")[0])
     return h.hexdigest()[:16]
 
 
