@@ -274,6 +274,27 @@ def workload_c5(S, synth, args):
     return out
 
 
+def workload_c1(S, synth, args):
+    """ER G(10,000, 80,000) (L2-resident), triangle: 2^30 samples for throughput
+    in each lane configuration (its parity with the oracle is a test case)."""
+    ctx = S.sgpm_create(0)
+    n = 10000
+    off, nbr = synth.pairs_to_csr(n, synth.er_pairs(n, 80000, 1))
+    g = S.sgpm_graph_from_csr(ctx, n, off, nbr)
+    k, e = synth.pattern("triangle")
+    p = S.sgpm_pattern_create(ctx, k, e)
+    out = {"metric": "C1 ER(10000, 80000) triangle samples/s", "throughput": {}}
+    for lanes in (64, 16, 4, 1):
+        NT = 1 << 30
+        r, _ = S.sgpm_estimate(ctx, g, p, S.sgpm_options_default(mode=S.MODE_FIXED_N, fixed_n=NT, seed=2,
+                                                                   lanes_per_sample=lanes))
+        out["throughput"][lanes] = {"samples": NT, "estimate": r.estimate, "hits": int(r.n_hits),
+                                    "kernel_samples_per_s": NT / r.seconds_kernel,
+                                    "wall_samples_per_s": NT / r.seconds_total}
+        log(f"c1 lanes {lanes}: {out['throughput'][lanes]}")
+    return out
+
+
 def workload_coverage(S, synth, args):
     """R-MAT 20, 4-clique and 5-clique: the exact counts (the GS exact count with
     one colour class, i.e. the whole graph), then 100 strict NS runs to eps with
@@ -306,7 +327,8 @@ def torch_sync():
     torch.cuda.synchronize()
 
 
-WORKLOADS = {"c3": workload_c3, "c4": workload_c4, "c5": workload_c5, "coverage": workload_coverage}
+WORKLOADS = {"c1": workload_c1, "c3": workload_c3, "c4": workload_c4, "c5": workload_c5,
+             "coverage": workload_coverage}
 
 
 def main():
@@ -320,8 +342,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-probes", action="store_true", help="skip the measured copy/gather rooflines")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-uniform leg")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "coverage"],
-                    help="c2 (default): R-MAT 20 4-/5-clique, the benchmark line; c3: 24 motif queries on three "
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "coverage"],
+                    help="c1: ER triangle throughput; "
+                         "c2 (default): R-MAT 20 4-/5-clique, the benchmark line; c3: 24 motif queries on three "
                          "Chung-Lu graphs, batch vs solo; c4: R-MAT 24 5-clique, learned vs uniform; c5: R-MAT 26 "
                          "6-clique, 5-cycle, diamond in loose (hybrid) mode; coverage: exact counts and the 95 %% "
                          "intervals of 100 seeds on R-MAT 20")
