@@ -276,7 +276,8 @@ def workload_c5(S, synth, args):
 
 def workload_c1(S, synth, args):
     """ER G(10,000, 80,000) (L2-resident), triangle: 2^30 samples for throughput
-    in each lane configuration (its parity with the oracle is a test case)."""
+    in each lane configuration, then with the lane count autotuned (0); its
+    parity with the oracle is a test case."""
     ctx = S.sgpm_create(0)
     n = 10000
     off, nbr = synth.pairs_to_csr(n, synth.er_pairs(n, 80000, 1))
@@ -284,13 +285,14 @@ def workload_c1(S, synth, args):
     k, e = synth.pattern("triangle")
     p = S.sgpm_pattern_create(ctx, k, e)
     out = {"metric": "C1 ER(10000, 80000) triangle samples/s", "throughput": {}}
-    for lanes in (64, 16, 4, 1):
+    for lanes in (64, 16, 4, 1, 0):
         NT = 1 << 30
         r, _ = S.sgpm_estimate(ctx, g, p, S.sgpm_options_default(mode=S.MODE_FIXED_N, fixed_n=NT, seed=2,
                                                                    lanes_per_sample=lanes))
         out["throughput"][lanes] = {"samples": NT, "estimate": r.estimate, "hits": int(r.n_hits),
                                     "kernel_samples_per_s": NT / r.seconds_kernel,
-                                    "wall_samples_per_s": NT / r.seconds_total}
+                                    "wall_samples_per_s": NT / r.seconds_total,
+                                    "lanes_used": int(r.lanes_per_sample)}
         log(f"c1 lanes {lanes}: {out['throughput'][lanes]}")
     return out
 

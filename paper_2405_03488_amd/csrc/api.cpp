@@ -64,6 +64,13 @@ int largest_grid(sgpm_ctx* c) {
 
 }  // namespace
 
+sgpm_graph::~sgpm_graph() {
+    if (!d_off && !d_nbr && !d_epair && !d_arow && !d_bthr) return;
+    if (ctx) (void)hipSetDevice(ctx->dev);
+    for (void* q : {(void*)d_off, (void*)d_nbr, (void*)d_epair, (void*)d_arow, (void*)d_bthr})
+        if (q) (void)hipFree(q);
+}
+
 extern "C" {
 
 int sgpm_device_count(void) {
@@ -209,12 +216,6 @@ sgpm_status sgpm_graph_export(sgpm_graph_t g, int64_t* off_out, int32_t* nbr_out
 
 sgpm_status sgpm_graph_free(sgpm_graph_t g) {
     if (!g) return SGPM_EINVAL;
-    (void)hipSetDevice(g->ctx->dev);
-    (void)hipFree(g->d_off);
-    (void)hipFree(g->d_nbr);
-    (void)hipFree(g->d_epair);
-    (void)hipFree(g->d_arow);
-    if (g->d_bthr) (void)hipFree(g->d_bthr);
     delete g;
     return SGPM_OK;
 }

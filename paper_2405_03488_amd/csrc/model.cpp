@@ -341,10 +341,6 @@ sgpm_status sgpm_model_info(sgpm_model_t m, float* params_out, int* nparams, dou
 
 sgpm_status sgpm_model_free(sgpm_model_t m) {
     if (!m) return SGPM_EINVAL;
-    if (m->d_tables) {
-        (void)hipSetDevice(m->ctx->dev);
-        (void)hipFree(m->d_tables);
-    }
     delete m;
     return SGPM_OK;
 }

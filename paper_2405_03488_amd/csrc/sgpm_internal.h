@@ -216,6 +216,11 @@ struct sgpm_graph {
     int2* d_epair = nullptr;
     int32_t* d_arow = nullptr;
     sgpm::DGraph view() const { return sgpm::DGraph{d_off, d_nbr, d_epair, d_arow, n, m}; }
+    sgpm_graph() = default;
+    sgpm_graph(const sgpm_graph&) = delete;
+    sgpm_graph& operator=(const sgpm_graph&) = delete;
+    // owns its device arrays, so a build that fails part way frees what it took
+    ~sgpm_graph();
 };
 
 struct sgpm_pattern {
@@ -231,6 +236,10 @@ struct sgpm_model {
     std::vector<float> params;     // trained MLP (empty for table-only models)
     double train_seconds = 0.0, pilot_seconds = 0.0, loss_first = 0.0, loss_last = 0.0;
     uint64_t tuples = 0;
+    sgpm_model() = default;
+    sgpm_model(const sgpm_model&) = delete;
+    sgpm_model& operator=(const sgpm_model&) = delete;
+    ~sgpm_model();  // frees d_tables
 };
 
 
