@@ -291,6 +291,12 @@ sgpm_status train(sgpm_ctx* c, sgpm_graph* g, const sgpm_pattern_t* pats, int np
 
 using namespace sgpm;
 
+sgpm_model::~sgpm_model() {
+    if (!d_tables) return;
+    if (ctx) (void)hipSetDevice(ctx->dev);
+    (void)hipFree(d_tables);
+}
+
 extern "C" {
 
 sgpm_status sgpm_model_train(sgpm_ctx_t c, sgpm_graph_t g, const sgpm_pattern_t* patterns, int np,
