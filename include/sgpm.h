@@ -219,7 +219,10 @@ sgpm_status sgpm_estimate_batch(sgpm_ctx_t ctx, int nq, const sgpm_graph_t* grap
                                 const sgpm_pattern_t* patterns, const sgpm_options* opts, sgpm_result* res);
 
 /* Exact count of P in G: the plan-driven nested-loop search of the GS engine on
- * the unsparsified graph (one colour). */
+ * the unsparsified graph (one colour).  The count is (count_hi << 64) | count_lo.
+ * The search runs 8, 16 or 64 lanes per first edge, chosen from the pattern and
+ * the graph's mean degree; the environment variable SGPM_EXACT_GROUP (8, 16 or
+ * 64) fixes it.  The count does not depend on the width. */
 sgpm_status sgpm_exact_count(sgpm_ctx_t ctx, sgpm_graph_t g, sgpm_pattern_t p, uint64_t* count_lo,
                              uint64_t* count_hi);
 

@@ -7,9 +7,11 @@
 // test; here independent colourings (rep = 0, 1, ...) are treated as i.i.d.
 // samples X_r = c^(k-1) Y_r and run through the same exact-integer statistics
 // and stop rule as NS (Sec. 4.1), capped at gs_reps_max colourings.
+#include <cstdlib>
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <memory>
 
@@ -86,34 +88,65 @@ sgpm_status sparsify(sgpm_ctx* c, sgpm_graph* g, uint32_t colours, uint64_t seed
     return SGPM_OK;
 }
 
+// Lanes per first edge of the exact count.  Narrow groups keep 64 / G first
+// edges in flight per wave, which pays where every row the search reads is
+// short; the whole wave pays where deeper levels scan long rows.  In the clique
+// search every candidate row is a degree-ordered out-row, so on a sparse graph
+// (mean degree below 16, as after colour sparsification) a triangle takes 8
+// lanes and a 4-clique 16; every other case, and any graph of mean degree 16 or
+// more, the whole wave.  R-MAT 20 sparsified with c = 16, ms at 8 / 16 / 64
+// lanes: triangle 0.51 / 0.86 / 3.07, 4-clique 1.65 / 1.25 / 3.20, 5-clique
+// 17.0 / 8.0 / 6.7, diamond 384 / 182 / 25, 4-cycle 40 / 42 / 56.
+// SGPM_EXACT_GROUP = 8, 16 or 64 fixes the width (tuning, and tests that run
+// every width on one graph).
+int exact_group(const sgpm_graph* g, const Plan& p) {
+    if (const char* e = std::getenv("SGPM_EXACT_GROUP")) {
+        const int v = std::atoi(e);
+        if (v == 8 || v == 16 || v == 64) return v;
+    }
+    if (2.0 * (double)g->m >= 16.0 * (double)g->n || !plan_is_clique(p)) return 64;
+    return p.k == 3 ? 8 : p.k == 4 ? 16 : 64;
+}
+
 // exact count of the plan's tuples on g (the leaves of the pruned search tree)
 sgpm_status exact_count(sgpm_ctx* c, sgpm_graph* g, const Plan& p, unsigned __int128* out, double* seconds) {
     HIP_TRY(c, hipSetDevice(c->dev));
     const uint64_t nfirst = p.oriented ? (uint64_t)g->m : 2ull * (uint64_t)g->m;
     *out = 0;
+    if (seconds) *seconds = 0.0;
     if (nfirst == 0) return SGPM_OK;
-    const int blocks = c->cus * exact_blocks_per_cu();
-    const uint64_t waves = (uint64_t)blocks * 4;
-    const int per_ticket = (int)std::min<uint64_t>(4096, std::max<uint64_t>(1, nfirst / (waves * 32)));
+    const int group = exact_group(g, p);
+    const int blocks = c->cus * exact_blocks_per_cu(group);
+    const uint64_t groups = (uint64_t)blocks * 4 * (uint64_t)(64 / group);
+    // about 32 tickets per group; at least 4 edges each for narrow groups, so
+    // the one ticket counter is not the limit on a graph of short rows
+    const int per_ticket =
+        (int)std::min<uint64_t>(4096, std::max<uint64_t>(group == 64 ? 1 : 4, nfirst / (groups * 32)));
     DevBuf part, cell;
     HIP_TRY(c, hipMalloc(&part.p, sizeof(unsigned long long) * 2 * (size_t)blocks));
     HIP_TRY(c, hipMalloc(&cell.p, sizeof(unsigned long long) * 4));
-    unsigned long long* d = (unsigned long long*)cell.p;
+    unsigned long long* d = (unsigned long long*)cell.p;  // ticket, spare, low sum, high sum
     HIP_TRY(c, launch_fill_u64(d, 4, 0ull, c->st));
-    hipEvent_t e0, e1;
-    HIP_TRY(c, hipEventCreate(&e0));
-    HIP_TRY(c, hipEventCreate(&e1));
-    HIP_TRY(c, hipEventRecord(e0, c->st));
-    HIP_TRY(c, launch_exact_count(g->view(), p, nfirst, blocks, per_ticket, d, (unsigned long long*)part.p, d + 2,
-                                  c->st));
-    HIP_TRY(c, hipEventRecord(e1, c->st));
+    struct Events {
+        hipEvent_t e[2] = {};
+        int n = 0;
+        ~Events() {
+            for (int i = 0; i < n; i++) (void)hipEventDestroy(e[i]);
+        }
+    } ev;
+    for (int i = 0; i < 2; i++) {
+        HIP_TRY(c, hipEventCreate(&ev.e[i]));
+        ev.n++;
+    }
+    HIP_TRY(c, hipEventRecord(ev.e[0], c->st));
+    HIP_TRY(c, launch_exact_count(g->view(), p, nfirst, group, blocks, per_ticket, d, (unsigned long long*)part.p,
+                                  d + 2, c->st));
+    HIP_TRY(c, hipEventRecord(ev.e[1], c->st));
     unsigned long long two[2];
     HIP_TRY(c, hipMemcpyAsync(two, d + 2, sizeof(two), hipMemcpyDeviceToHost, c->st));
     HIP_TRY(c, hipStreamSynchronize(c->st));
     float ms = 0;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    (void)hipEventElapsedTime(&ms, ev.e[0], ev.e[1]);
     if (seconds) *seconds = ms * 1e-3;
     *out = (unsigned __int128)two[0] + ((unsigned __int128)two[1] << 32);
     return SGPM_OK;

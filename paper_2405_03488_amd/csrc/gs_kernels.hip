@@ -278,29 +278,52 @@ __global__ __launch_bounds__(256) void scan_finish(const int64_t* __restrict__ i
 // ------------------------------------------------------------------ exact count
 __device__ __forceinline__ int32_t grfl(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 
-// membership of each lane's x in an ascending row, 64-lane window merge (see the
-// NS kernels for the same scheme); c is the wave-uniform cursor
-__device__ __forceinline__ bool wave_member(const int32_t* __restrict__ R, int32_t rl, int32_t& c, int32_t x, bool act,
-                                            int32_t xmax, int lane) {
+// Lanes [base, base + G) of a wave enumerate the search tree of one first edge
+// together (G = 64: the whole wave).  A colour-sparsified graph has rows of a
+// few entries, where a whole wave per edge leaves most lanes idle; narrower
+// groups keep 64 / G edges in flight per wave.  Every value the helpers return
+// is uniform over the group, and control flow is uniform per group.
+template <int G>
+struct Lanes {
+    int sub, base;
+    static constexpr unsigned long long full = G == 64 ? ~0ull : (1ull << G) - 1ull;
+    __device__ __forceinline__ unsigned long long ballot(bool q) const {
+        const unsigned long long b = __ballot(q);
+        if constexpr (G == 64) return b;
+        else return (b >> base) & full;
+    }
+    // x of the group's lane i
+    __device__ __forceinline__ int32_t at(int32_t x, int i) const {
+        if constexpr (G == 64) return grfl(__shfl(x, i));
+        else return __shfl(x, base + i);
+    }
+};
+
+// membership of each lane's x in an ascending row by a G-entry window merge:
+// the window R[c, c + G) is searched by bisection over lanes; c (uniform) only
+// moves forward, past entries below the chunk's largest x when it is done
+template <int G>
+__device__ __forceinline__ bool grp_member(const int32_t* __restrict__ R, int32_t rl, int32_t& c, int32_t x, bool act,
+                                           int32_t xmax, const Lanes<G>& ln) {
     bool found = false, pending = act;
     for (;;) {
-        const int32_t b = (c + lane < rl) ? R[c + lane] : GBIG;
-        const int32_t bmax = grfl(__shfl(b, 63));
-        int pos = 0;
+        const int32_t b = (c + ln.sub < rl) ? R[c + ln.sub] : GBIG;
+        const int32_t bmax = ln.at(b, G - 1);
+        int pos = 0;  // entries of the window below x, at most G - 1
 #pragma unroll
-        for (int st = 32; st >= 1; st >>= 1) {
-            const int32_t bv = __shfl(b, pos + st - 1);
+        for (int st = G / 2; st >= 1; st >>= 1) {
+            const int32_t bv = __shfl(b, ln.base + pos + st - 1);
             if (bv < x) pos += st;
         }
-        const int32_t bq = __shfl(b, pos < 64 ? pos : 63);
+        const int32_t bq = __shfl(b, ln.base + pos);
         const bool res = pending && x <= bmax;
-        if (res) found = pos < 64 && bq == x;
+        if (res) found = bq == x;
         pending = pending && !res;
-        if (__ballot(pending) == 0) {
-            c += (int32_t)__popcll(__ballot(b < xmax));
+        if (ln.ballot(pending) == 0) {
+            c += (int32_t)__popcll(ln.ballot(b < xmax));
             break;
         }
-        c += 64;
+        c += G;
     }
     return found;
 }
@@ -312,7 +335,8 @@ struct PackedPlan {
 };
 __device__ __forceinline__ uint32_t pk(uint64_t m, int j) { return (uint32_t)(m >> (8 * j)) & 0xFFu; }
 
-struct Level {          // per-wave, per-level loop state (LDS)
+template <int G>
+struct Level {          // per-group, per-level loop state (LDS)
     int32_t base;       // next chunk start in the driver row
     int32_t ended;      // the driver window is exhausted
     int32_t d;          // driver position
@@ -320,49 +344,53 @@ struct Level {          // per-wave, per-level loop state (LDS)
     uint32_t pad;
     unsigned long long mask;  // unvisited candidates of the current chunk
     int32_t cur[8];     // merge cursors per constraint row
-    int32_t xs[64];     // current chunk's values
+    int32_t xs[G];      // current chunk's values
 };
 
-struct WaveState {
+template <int G>
+struct GroupState {
     int32_t v[8];
     int64_t rb[8];
     int32_t rl[8];
-    Level lv[8];
+    Level<G> lv[6];     // levels 2 .. 7
 };
 
 // Evaluate the next chunk of level j's candidates; returns the valid mask and
 // stores the chunk in L.xs.
+template <int G>
 __device__ __forceinline__ unsigned long long eval_level_chunk(const DGraph& g, const PackedPlan& p, int j,
-                                                               WaveState& W, Level& L, int lane, int32_t& x_out) {
+                                                               GroupState<G>& W, Level<G>& L, const Lanes<G>& ln,
+                                                               int32_t& x_out) {
     const uint32_t conn = pk(p.connect, j), disc = pk(p.disconnect, j);
     const int32_t* dp = g.nbr + W.rb[L.d];
     const int32_t dl = W.rl[L.d];
-    const int32_t pos = L.base + lane;
+    const int32_t pos = L.base + ln.sub;
     const int32_t x = pos < dl ? dp[pos] : GBIG;
     const bool act = x < L.hi;
-    const unsigned long long inm = __ballot(act);
+    const unsigned long long inm = ln.ballot(act);  // a prefix of the group
     bool ok = act && x > L.lo;
     for (int i = 0; i < j; ++i)
         if (!(conn >> i & 1)) ok = ok && x != W.v[i];
     if (inm != 0) {
-        const int32_t xmax = grfl(__shfl(x, (int)__popcll(inm) - 1));
+        const int32_t xmax = ln.at(x, (int)__popcll(inm) - 1);
         for (int i = 0; i < j; ++i) {
             const bool isc = (conn >> i & 1) && i != L.d, isd = disc >> i & 1;
             if (!isc && !isd) continue;
             int32_t c = L.cur[i];
-            const bool f = wave_member(g.nbr + W.rb[i], W.rl[i], c, x, act, xmax, lane);
-            L.cur[i] = c;  // uniform: every lane stores the same value
+            const bool f = grp_member<G>(g.nbr + W.rb[i], W.rl[i], c, x, act, xmax, ln);
+            L.cur[i] = c;  // uniform: every lane of the group stores the same value
             ok = ok && (isc ? f : !f);
         }
     }
-    if (inm != ~0ull) L.ended = 1;
-    L.base += 64;
+    if (inm != Lanes<G>::full) L.ended = 1;
+    L.base += G;
     x_out = x;
-    return __ballot(ok);
+    return ln.ballot(ok);
 }
 
-__device__ __forceinline__ void init_level(const DGraph& g, const PackedPlan& p, int j, WaveState& W, Level& L,
-                                           int lane) {
+template <int G>
+__device__ __forceinline__ void init_level(const DGraph& g, const PackedPlan& p, int j, GroupState<G>& W,
+                                           Level<G>& L) {
     const uint32_t conn = pk(p.connect, j), up = pk(p.upper, j), lw = pk(p.lower, j);
     int32_t lo = -1, hi = GBIG, d = -1, dl = GBIG;
     for (int i = 0; i < j; ++i) {
@@ -384,8 +412,8 @@ __device__ __forceinline__ void init_level(const DGraph& g, const PackedPlan& p,
         }
         start = a;
     }
-    // uniform values: every lane stores the same, so each lane's later reads
-    // follow its own writes in program order
+    // uniform values: every lane of the group stores the same, so each lane's
+    // later reads follow its own writes in program order
     L.base = start;
     L.ended = 0;
     L.d = d;
@@ -395,18 +423,22 @@ __device__ __forceinline__ void init_level(const DGraph& g, const PackedPlan& p,
     for (int i = 0; i < 8; ++i) L.cur[i] = 0;
 }
 
+template <int G>
 __global__ __launch_bounds__(256) void exact_count_kernel(DGraph g, PackedPlan p, uint64_t nfirst, int per_ticket,
                                                           unsigned long long* __restrict__ ticket,
                                                           unsigned long long* __restrict__ partials) {
+    constexpr int NG = 64 / G;  // groups per wave
     const int lane = (int)(threadIdx.x & 63), w = (int)(threadIdx.x >> 6);
-    __shared__ WaveState ws[4];
-    WaveState& W = ws[w];
-    unsigned long long total = 0;
+    const int grp = lane / G;
+    const Lanes<G> ln{lane % G, grp * G};
+    __shared__ GroupState<G> ws[4 * NG];
+    GroupState<G>& W = ws[w * NG + grp];
+    unsigned long long total = 0;  // uniform over the group
     const int k = p.k;
     for (;;) {
         unsigned long long t = 0;
-        if (lane == 0) t = atomicAdd(ticket, 1ull);
-        t = __shfl(t, 0);
+        if (ln.sub == 0) t = atomicAdd(ticket, 1ull);
+        t = __shfl(t, ln.base);
         const uint64_t e0 = (uint64_t)t * (uint64_t)per_ticket;
         if (e0 >= nfirst) break;
         const uint64_t e1 = e0 + (uint64_t)per_ticket < nfirst ? e0 + (uint64_t)per_ticket : nfirst;
@@ -436,15 +468,15 @@ __global__ __launch_bounds__(256) void exact_count_kernel(DGraph g, PackedPlan p
             }
             __builtin_amdgcn_wave_barrier();
             int j = 2;
-            init_level(g, p, 2, W, W.lv[2], lane);
+            init_level<G>(g, p, 2, W, W.lv[0]);
             __builtin_amdgcn_wave_barrier();
             while (j >= 2) {
-                Level& L = W.lv[j];
+                Level<G>& L = W.lv[j - 2];
                 if (j == k - 1) {
                     // last level: count every candidate
                     while (!L.ended) {
                         int32_t x;
-                        const unsigned long long okm = eval_level_chunk(g, p, j, W, L, lane, x);
+                        const unsigned long long okm = eval_level_chunk<G>(g, p, j, W, L, ln, x);
                         __builtin_amdgcn_wave_barrier();
                         total += (unsigned long long)__popcll(okm);
                     }
@@ -457,15 +489,16 @@ __global__ __launch_bounds__(256) void exact_count_kernel(DGraph g, PackedPlan p
                         continue;
                     }
                     int32_t x;
-                    const unsigned long long okm = eval_level_chunk(g, p, j, W, L, lane, x);
-                    L.xs[lane] = x;
+                    const unsigned long long okm = eval_level_chunk<G>(g, p, j, W, L, ln, x);
+                    L.xs[ln.sub] = x;
                     L.mask = okm;
                     __builtin_amdgcn_wave_barrier();
                     continue;
                 }
                 const unsigned long long m = L.mask;
                 const int bit = __ffsll(m) - 1;
-                const int32_t vj = grfl(L.xs[bit]);
+                int32_t vj = L.xs[bit];
+                if constexpr (G == 64) vj = grfl(vj);
                 {
                     const int64_t bj = g.off[vj];
                     const int32_t lj = (int32_t)(g.off[vj + 1] - bj);
@@ -476,18 +509,18 @@ __global__ __launch_bounds__(256) void exact_count_kernel(DGraph g, PackedPlan p
                 }
                 __builtin_amdgcn_wave_barrier();
                 ++j;
-                init_level(g, p, j, W, W.lv[j], lane);
+                init_level<G>(g, p, j, W, W.lv[j - 2]);
                 __builtin_amdgcn_wave_barrier();
             }
         }
     }
-    __shared__ unsigned long long red[4];
-    if (lane == 0) red[w] = total;
+    __shared__ unsigned long long red[4 * NG];
+    if (ln.sub == 0) red[w * NG + grp] = total;
     __syncthreads();
     if (threadIdx.x == 0) {
         // two 32-bit halves so the final sum is exact in 64-bit words
         unsigned long long lo = 0, hi = 0;
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < 4 * NG; ++i) {
             lo += red[i] & 0xFFFFFFFFull;
             hi += red[i] >> 32;
         }
@@ -578,7 +611,7 @@ hipError_t exclusive_scan(const int64_t* in, int64_t n, int64_t* out, int64_t* s
     return hipGetLastError();
 }
 
-hipError_t launch_exact_count(const DGraph& g, const Plan& p, uint64_t nfirst, int blocks, int per_ticket,
+hipError_t launch_exact_count(const DGraph& g, const Plan& p, uint64_t nfirst, int group, int blocks, int per_ticket,
                               unsigned long long* ticket, unsigned long long* partials, unsigned long long* out2,
                               hipStream_t st) {
     PackedPlan pp{};
@@ -590,17 +623,29 @@ hipError_t launch_exact_count(const DGraph& g, const Plan& p, uint64_t nfirst, i
     }
     pp.k = p.k;
     pp.oriented = p.oriented;
-    hipLaunchKernelGGL(exact_count_kernel, dim3((unsigned)blocks), dim3(256), 0, st, g, pp, nfirst, per_ticket, ticket,
-                       partials);
+    if (group == 8)
+        hipLaunchKernelGGL(exact_count_kernel<8>, dim3((unsigned)blocks), dim3(256), 0, st, g, pp, nfirst, per_ticket,
+                           ticket, partials);
+    else if (group == 16)
+        hipLaunchKernelGGL(exact_count_kernel<16>, dim3((unsigned)blocks), dim3(256), 0, st, g, pp, nfirst, per_ticket,
+                           ticket, partials);
+    else if (group == 64)
+        hipLaunchKernelGGL(exact_count_kernel<64>, dim3((unsigned)blocks), dim3(256), 0, st, g, pp, nfirst, per_ticket,
+                           ticket, partials);
+    else
+        return hipErrorInvalidValue;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(sum_pairs_kernel, dim3(1), dim3(256), 0, st, partials, blocks, out2);
     return hipGetLastError();
 }
 
-int exact_blocks_per_cu() {
+int exact_blocks_per_cu(int group) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, exact_count_kernel, 256, 0) != hipSuccess || nb < 1) nb = 2;
+    hipError_t e = group == 8    ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, exact_count_kernel<8>, 256, 0)
+                   : group == 16 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, exact_count_kernel<16>, 256, 0)
+                                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, exact_count_kernel<64>, 256, 0);
+    if (e != hipSuccess || nb < 1) nb = 2;
     return nb;
 }
 

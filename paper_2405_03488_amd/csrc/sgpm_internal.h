@@ -164,10 +164,11 @@ hipError_t gs_arc_write(const DGraph& g, const uint8_t* col, uint32_t c, uint64_
 int64_t scan_scratch_words(int64_t n);
 hipError_t exclusive_scan(const int64_t* in, int64_t n, int64_t* out, int64_t* scratch, hipStream_t st);
 hipError_t max_degree(const int64_t* off, int64_t n, unsigned long long* out, hipStream_t st);
-hipError_t launch_exact_count(const DGraph& g, const Plan& p, uint64_t nfirst, int blocks, int per_ticket,
+// group: lanes per first edge (8, 16 or 64)
+hipError_t launch_exact_count(const DGraph& g, const Plan& p, uint64_t nfirst, int group, int blocks, int per_ticket,
                               unsigned long long* ticket, unsigned long long* partials, unsigned long long* out2,
                               hipStream_t st);
-int exact_blocks_per_cu();
+int exact_blocks_per_cu(int group);
 // probes (probe_kernels.hip)
 hipError_t probe_copy(const void* in, void* out, uint64_t bytes, int blocks, hipStream_t st);
 hipError_t probe_gather(const int32_t* a, uint64_t words, int seg_bytes, int rounds, int blocks, uint64_t seed,

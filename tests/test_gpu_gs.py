@@ -127,7 +127,44 @@ def test_exact_count_rmat13(S, O, synth, ctx, rmat13, name):
     g, og = rmat13
     k, e = synth.pattern(name)
     p = S.sgpm_pattern_create(ctx, k, e)
-    assert S.sgpm_exact_count(ctx, g, p) == O.plan_count(og, O.compile_plan(k, e))
+    want = O.plan_count(og, O.compile_plan(k, e))
+    assert S.sgpm_exact_count(ctx, g, p) == want
+    S.sgpm_pattern_free(p)
+
+
+@pytest.mark.parametrize("name,c", [("triangle", 1), ("4-clique", 1), ("4-cycle", 2)])
+def test_gs_estimate_rmat13_matches_oracle(S, O, synth, ctx, rmat13, name, c):
+    """GS on R-MAT (hub rows) against the oracle: per-colouring counts of a
+    sparse triangle and 4-clique search take 8 and 16 lanes per first edge,
+    the 4-cycle the whole wave."""
+    g, og = rmat13
+    k, e = synth.pattern(name)
+    p = S.sgpm_pattern_create(ctx, k, e)
+    opts = S.sgpm_options_default(mode=S.MODE_GS, colours=c, seed=23, eps=0.02, gs_reps_max=4)
+    r, rc = S.sgpm_estimate(ctx, g, p, opts)
+    orr, ys = O.gs_run(og, O.compile_plan(k, e), c, 23, eps=0.02, confidence=0.95, reps_max=4)
+    assert r.n_samples == orr.reps and r.S1 == orr.S1 and r.S2 == orr.S2
+    assert r.estimate == orr.estimate and r.converged == orr.converged
+    S.sgpm_pattern_free(p)
+
+
+_want = {}
+
+
+@pytest.mark.parametrize("group", ["8", "16", "64"])
+@pytest.mark.parametrize("name", ["triangle", "4-clique", "5-clique", "diamond", "4-cycle"])
+def test_exact_count_every_group_width(S, O, synth, ctx, cl_small, rmat13, monkeypatch, name, group):
+    """Each lane-group width of the count (8, 16 or 64 lanes per first edge,
+    forced) gives the oracle's count, on a power-law graph and on R-MAT (hub
+    rows spanning many group-wide windows)."""
+    monkeypatch.setenv("SGPM_EXACT_GROUP", group)
+    print(f"exact {name} group={group}", flush=True)
+    k, e = synth.pattern(name)
+    p = S.sgpm_pattern_create(ctx, k, e)
+    for gname, (g, og) in (("cl", cl_small), ("rmat13", rmat13)):
+        if (gname, name) not in _want:
+            _want[(gname, name)] = O.plan_count(og, O.compile_plan(k, e))
+        assert S.sgpm_exact_count(ctx, g, p) == _want[(gname, name)]
     S.sgpm_pattern_free(p)
 
 
