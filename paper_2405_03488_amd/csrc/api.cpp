@@ -364,17 +364,19 @@ sgpm_status ns_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_op
     }
     HIP_TRY(c, hipSetDevice(c->dev));
     // trace buffer
+    DeviceBuffer trace_buf;
     sgpm_trace_rec* d_trace = nullptr;
     TraceArgs tr{nullptr, 0, 0, nullptr};
     const uint64_t ntr = (o.trace_buf && o.trace_hi > o.trace_lo) ? o.trace_hi - o.trace_lo : 0;
     if (ntr) {
-        HIP_TRY(c, hipMalloc(&d_trace, ntr * sizeof(sgpm_trace_rec)));
+        HIP_TRY(c, hipMalloc(&trace_buf.p, ntr * sizeof(sgpm_trace_rec)));
+        d_trace = (sgpm_trace_rec*)trace_buf.p;
         HIP_TRY(c, launch_fill_u64((unsigned long long*)d_trace, ntr * sizeof(sgpm_trace_rec) / 8, 0ull, c->st));
         tr = TraceArgs{d_trace, o.trace_lo, o.trace_hi, ex ? ex->d_sizes : nullptr};
     }
-    hipEvent_t e0, e1;
-    HIP_TRY(c, hipEventCreate(&e0));
-    HIP_TRY(c, hipEventCreate(&e1));
+    ScopedEvents<1> ev;
+    HIP_TRY(c, ev.create());
+    const hipEvent_t e0 = ev[0];  // start of the first window
     NsState s;
     int lanes = o.lanes_per_sample;
     // the learned proposal, pilot sizes and NS-base run one sample per wave
@@ -522,8 +524,6 @@ sgpm_status ns_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_op
         HIP_TRY(c, hipEventElapsedTime(&ms, e0, c->kev[3 * last_done + 2]));
         dev_seconds = ms * 1e-3;
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     fill_result(res, s, z, learned ? 52 : 0);
     res->windows = windows;
     res->lanes_per_sample = lanes ? lanes : 64;
@@ -534,7 +534,6 @@ sgpm_status ns_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_op
     res->converged = converged ? 1 : 0;
     if (ntr) {
         HIP_TRY(c, hipMemcpy(o.trace_buf, d_trace, ntr * sizeof(sgpm_trace_rec), hipMemcpyDeviceToHost));
-        (void)hipFree(d_trace);
     }
     res->seconds_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
     if (status != SGPM_OK) return fail(c, status, "a sample weight exceeded 128 bits");
@@ -709,25 +708,20 @@ sgpm_status sgpm_probe_copy(sgpm_ctx_t c, uint64_t bytes, int iters, double* gbs
     if (!c || !gbs || bytes < 16 || iters < 1) return fail(c, SGPM_EINVAL, "bad probe arguments");
     HIP_TRY(c, hipSetDevice(c->dev));
     bytes &= ~15ull;
-    void *a = nullptr, *b = nullptr;
-    HIP_TRY(c, hipMalloc(&a, bytes));
-    HIP_TRY(c, hipMalloc(&b, bytes));
-    HIP_TRY(c, hipMemsetAsync(a, 1, bytes, c->st));
+    DeviceBuffer a, b;
+    HIP_TRY(c, hipMalloc(&a.p, bytes));
+    HIP_TRY(c, hipMalloc(&b.p, bytes));
+    HIP_TRY(c, hipMemsetAsync(a.p, 1, bytes, c->st));
     const int blocks = c->cus * 8;
-    HIP_TRY(c, probe_copy(a, b, bytes, blocks, c->st));  // warm
-    hipEvent_t e0, e1;
-    HIP_TRY(c, hipEventCreate(&e0));
-    HIP_TRY(c, hipEventCreate(&e1));
-    HIP_TRY(c, hipEventRecord(e0, c->st));
-    for (int i = 0; i < iters; i++) HIP_TRY(c, probe_copy(a, b, bytes, blocks, c->st));
-    HIP_TRY(c, hipEventRecord(e1, c->st));
-    HIP_TRY(c, hipEventSynchronize(e1));
+    HIP_TRY(c, probe_copy(a.p, b.p, bytes, blocks, c->st));  // warm
+    ScopedEvents<2> ev;
+    HIP_TRY(c, ev.create());
+    HIP_TRY(c, hipEventRecord(ev[0], c->st));
+    for (int i = 0; i < iters; i++) HIP_TRY(c, probe_copy(a.p, b.p, bytes, blocks, c->st));
+    HIP_TRY(c, hipEventRecord(ev[1], c->st));
+    HIP_TRY(c, hipEventSynchronize(ev[1]));
     float ms = 0;
-    HIP_TRY(c, hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    (void)hipFree(a);
-    (void)hipFree(b);
+    HIP_TRY(c, hipEventElapsedTime(&ms, ev[0], ev[1]));
     *gbs = 2.0 * (double)bytes * iters / (ms * 1e-3) / 1e9;
     return SGPM_OK;
 }
@@ -738,26 +732,22 @@ sgpm_status sgpm_probe_gather(sgpm_ctx_t c, uint64_t working_set_bytes, int segm
         return fail(c, SGPM_EINVAL, "bad probe arguments");
     HIP_TRY(c, hipSetDevice(c->dev));
     const uint64_t words = working_set_bytes / 4;
-    int32_t* a = nullptr;
-    unsigned long long* sink = nullptr;
-    HIP_TRY(c, hipMalloc(&a, words * 4));
-    HIP_TRY(c, hipMalloc(&sink, 8));
+    DeviceBuffer ab, sb;
+    HIP_TRY(c, hipMalloc(&ab.p, words * 4));
+    HIP_TRY(c, hipMalloc(&sb.p, 8));
+    int32_t* a = (int32_t*)ab.p;
+    unsigned long long* sink = (unsigned long long*)sb.p;
     HIP_TRY(c, hipMemsetAsync(a, 3, words * 4, c->st));
     const int blocks = c->cus * 8;
     HIP_TRY(c, probe_gather(a, words, segment_bytes, rounds, blocks, 1, sink, c->st));
-    hipEvent_t e0, e1;
-    HIP_TRY(c, hipEventCreate(&e0));
-    HIP_TRY(c, hipEventCreate(&e1));
-    HIP_TRY(c, hipEventRecord(e0, c->st));
+    ScopedEvents<2> ev;
+    HIP_TRY(c, ev.create());
+    HIP_TRY(c, hipEventRecord(ev[0], c->st));
     HIP_TRY(c, probe_gather(a, words, segment_bytes, rounds, blocks, 2, sink, c->st));
-    HIP_TRY(c, hipEventRecord(e1, c->st));
-    HIP_TRY(c, hipEventSynchronize(e1));
+    HIP_TRY(c, hipEventRecord(ev[1], c->st));
+    HIP_TRY(c, hipEventSynchronize(ev[1]));
     float ms = 0;
-    HIP_TRY(c, hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    (void)hipFree(a);
-    (void)hipFree(sink);
+    HIP_TRY(c, hipEventElapsedTime(&ms, ev[0], ev[1]));
     const double segs = (double)blocks * 256.0 / (segment_bytes / 4) * rounds;
     *gbs = segs * segment_bytes / (ms * 1e-3) / 1e9;
     return SGPM_OK;

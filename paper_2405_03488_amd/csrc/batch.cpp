@@ -167,17 +167,14 @@ sgpm_status batch_estimate(sgpm_ctx* c, int nq, const sgpm_graph_t* graphs, cons
     std::memcpy(h, hq.data(), qbytes);
     std::memcpy(h + qbytes, hs.data(), sbytes);
     std::memcpy(h + qbytes + sbytes, &active, 8);
-    hipEvent_t e0, e1;
-    HIP_TRY(c, hipEventCreate(&e0));
-    HIP_TRY(c, hipEventCreate(&e1));
-    HIP_TRY(c, hipEventRecord(e0, c->batch_stream));
+    ScopedEvents<2> ev;
+    HIP_TRY(c, ev.create());
+    HIP_TRY(c, hipEventRecord(ev[0], c->batch_stream));
     if (active > 0) HIP_TRY(c, hipGraphLaunch(c->batch_exec, c->batch_stream));
-    HIP_TRY(c, hipEventRecord(e1, c->batch_stream));
+    HIP_TRY(c, hipEventRecord(ev[1], c->batch_stream));
     HIP_TRY(c, hipStreamSynchronize(c->batch_stream));
     float ms = 0;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    (void)hipEventElapsedTime(&ms, ev[0], ev[1]);
     const BatchState* out = (const BatchState*)(h + qbytes);
     const double wall = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     sgpm_status worst = SGPM_OK;

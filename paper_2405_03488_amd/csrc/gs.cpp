@@ -19,16 +19,6 @@
 
 namespace sgpm {
 
-namespace {
-
-struct DevBuf {
-    void* p = nullptr;
-    ~DevBuf() {
-        if (p) (void)hipFree(p);
-    }
-};
-
-}  // namespace
 
 // colours: c of colour sparsification, or (bes) the inverse keep probability
 sgpm_status sparsify(sgpm_ctx* c, sgpm_graph* g, uint32_t colours, uint64_t seed, uint32_t rep, sgpm_graph** out,
@@ -37,7 +27,7 @@ sgpm_status sparsify(sgpm_ctx* c, sgpm_graph* g, uint32_t colours, uint64_t seed
     HIP_TRY(c, hipSetDevice(c->dev));
     const int64_t n = g->n;
     const int64_t nt = arc_tiles(2 * g->m);
-    DevBuf col, rstart, rlow, tk, tl, tko, tlo, scratch;
+    DeviceBuffer col, rstart, rlow, tk, tl, tko, tlo, scratch;
     HIP_TRY(c, hipMalloc(&col.p, (size_t)std::max<int64_t>(n, 1)));
     HIP_TRY(c, hipMalloc(&rstart.p, sizeof(int64_t) * (size_t)std::max<int64_t>(n, 1)));
     HIP_TRY(c, hipMalloc(&rlow.p, sizeof(int64_t) * (size_t)std::max<int64_t>(n, 1)));
@@ -122,22 +112,13 @@ sgpm_status exact_count(sgpm_ctx* c, sgpm_graph* g, const Plan& p, unsigned __in
     // the one ticket counter is not the limit on a graph of short rows
     const int per_ticket =
         (int)std::min<uint64_t>(4096, std::max<uint64_t>(group == 64 ? 1 : 4, nfirst / (groups * 32)));
-    DevBuf part, cell;
+    DeviceBuffer part, cell;
     HIP_TRY(c, hipMalloc(&part.p, sizeof(unsigned long long) * 2 * (size_t)blocks));
     HIP_TRY(c, hipMalloc(&cell.p, sizeof(unsigned long long) * 4));
     unsigned long long* d = (unsigned long long*)cell.p;  // ticket, spare, low sum, high sum
     HIP_TRY(c, launch_fill_u64(d, 4, 0ull, c->st));
-    struct Events {
-        hipEvent_t e[2] = {};
-        int n = 0;
-        ~Events() {
-            for (int i = 0; i < n; i++) (void)hipEventDestroy(e[i]);
-        }
-    } ev;
-    for (int i = 0; i < 2; i++) {
-        HIP_TRY(c, hipEventCreate(&ev.e[i]));
-        ev.n++;
-    }
+    ScopedEvents<2> ev;
+    HIP_TRY(c, ev.create());
     HIP_TRY(c, hipEventRecord(ev.e[0], c->st));
     HIP_TRY(c, launch_exact_count(g->view(), p, nfirst, group, blocks, per_ticket, d, (unsigned long long*)part.p,
                                   d + 2, c->st));

@@ -64,13 +64,6 @@ double gauss(uint64_t& st) {
     return std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586 * u2);
 }
 
-struct Dev {
-    void* p = nullptr;
-    ~Dev() {
-        if (p) (void)hipFree(p);
-    }
-};
-
 sgpm_status upload_tables(sgpm_ctx* c, sgpm_model* m) {
     HIP_TRY(c, hipMalloc(&m->d_tables, sizeof(uint16_t) * m->tables.size()));
     HIP_TRY(c, hipMemcpy(m->d_tables, m->tables.data(), sizeof(uint16_t) * m->tables.size(), hipMemcpyHostToDevice));
@@ -99,7 +92,7 @@ sgpm_status build_table(sgpm_ctx* c, const float* d_params, int pi, int k, uint1
             for (int bp = 0; bp < 32; bp++)
                 for (int bc = 0; bc < 32; bc++)
                     features(&X[((((size_t)j * 32 + b0) * 32 + bp) * 32 + bc) * NFEAT], pi, j, b0, bp, bc);
-    Dev dX, dS;
+    DeviceBuffer dX, dS;
     HIP_TRY(c, hipMalloc(&dX.p, sizeof(float) * X.size()));
     HIP_TRY(c, hipMalloc(&dS.p, sizeof(float) * TABLE));
     HIP_TRY(c, hipMemcpy(dX.p, X.data(), sizeof(float) * X.size(), hipMemcpyHostToDevice));
@@ -157,7 +150,7 @@ sgpm_status train(sgpm_ctx* c, sgpm_graph* g, const sgpm_pattern_t* pats, int np
     const uint64_t N = cfg.pilot_samples;
     std::vector<sgpm_trace_rec> rec((size_t)N);
     std::vector<uint32_t> sizes((size_t)N * 8);
-    Dev dsz;
+    DeviceBuffer dsz;
     HIP_TRY(c, hipMalloc(&dsz.p, sizeof(uint32_t) * 8 * (size_t)N));
     for (int i = 0; i < np; i++) {
         if (!pats[i]) return fail(c, SGPM_EINVAL, "null pattern");
@@ -221,7 +214,7 @@ sgpm_status train(sgpm_ctx* c, sgpm_graph* g, const sgpm_pattern_t* pats, int np
     P[(size_t)NP - 1] = (float)(ymean / (double)T);
     // 3. Adam epochs over shuffled minibatches (rows permuted on the host per epoch)
     const int64_t B = cfg.batch, steps_per_epoch = T / B;
-    Dev dP, dX, dY, dm, dv, dg;
+    DeviceBuffer dP, dX, dY, dm, dv, dg;
     HIP_TRY(c, hipMalloc(&dP.p, sizeof(float) * (size_t)NP));
     HIP_TRY(c, hipMalloc(&dm.p, sizeof(float) * (size_t)NP));
     HIP_TRY(c, hipMalloc(&dv.p, sizeof(float) * (size_t)NP));
@@ -237,7 +230,7 @@ sgpm_status train(sgpm_ctx* c, sgpm_graph* g, const sgpm_pattern_t* pats, int np
     std::vector<float> Xs((size_t)(steps_per_epoch * B) * NFEAT), Ys((size_t)(steps_per_epoch * B));
     uint64_t ps = cfg.seed ^ 0xA11CEull;
     float bpow[2] = {1.f, 1.f};  // Adam's beta1^t, beta2^t
-    Dev dloss;
+    DeviceBuffer dloss;
     HIP_TRY(c, hipMalloc(&dloss.p, sizeof(float) * (size_t)T));
     auto eval_loss = [&](double* loss) -> sgpm_status {
         // mean squared error over the first epoch's rows (forward only)
@@ -355,7 +348,7 @@ sgpm_status sgpm_mlp_forward(sgpm_ctx_t c, const float* params, const float* X, 
     if (!c || !params || !X || !s_out || N < 1) return fail(c, SGPM_EINVAL, "bad arguments");
     HIP_TRY(c, hipSetDevice(c->dev));
     const int NP = mlp_nparams();
-    Dev dP, dX, dS;
+    DeviceBuffer dP, dX, dS;
     HIP_TRY(c, hipMalloc(&dP.p, sizeof(float) * (size_t)NP));
     HIP_TRY(c, hipMalloc(&dX.p, sizeof(float) * (size_t)N * NFEAT));
     HIP_TRY(c, hipMalloc(&dS.p, sizeof(float) * (size_t)N));
@@ -373,7 +366,7 @@ sgpm_status sgpm_mlp_grad(sgpm_ctx_t c, const float* params, const float* X, con
     HIP_TRY(c, hipSetDevice(c->dev));
     const int NP = mlp_nparams();
     const int64_t parts = mlp_grad_blocks(N);
-    Dev dP, dX, dY, dgp, dg;
+    DeviceBuffer dP, dX, dY, dgp, dg;
     HIP_TRY(c, hipMalloc(&dP.p, sizeof(float) * (size_t)NP));
     HIP_TRY(c, hipMalloc(&dX.p, sizeof(float) * (size_t)N * NFEAT));
     HIP_TRY(c, hipMalloc(&dY.p, sizeof(float) * (size_t)N));
@@ -396,7 +389,7 @@ sgpm_status sgpm_mlp_adam_steps(sgpm_ctx_t c, float* params, float* m, float* v,
     HIP_TRY(c, hipSetDevice(c->dev));
     const int NP = mlp_nparams();
     const size_t rows = (size_t)nsteps * (size_t)B;
-    Dev dP, dm, dv, dX, dY, dgp;
+    DeviceBuffer dP, dm, dv, dX, dY, dgp;
     HIP_TRY(c, hipMalloc(&dP.p, sizeof(float) * (size_t)NP));
     HIP_TRY(c, hipMalloc(&dm.p, sizeof(float) * (size_t)NP));
     HIP_TRY(c, hipMalloc(&dv.p, sizeof(float) * (size_t)NP));
@@ -431,7 +424,7 @@ sgpm_status sgpm_probe_mlp(sgpm_ctx_t c, int64_t N, int iters, double* out4) {
     for (auto& v : hp) v = (float)(gauss(rs) * 0.1);
     for (auto& v : hx) v = (float)gauss(rs);
     for (auto& v : hy) v = (float)gauss(rs);
-    Dev dP, dX, dY, dS, dgp, dg;
+    DeviceBuffer dP, dX, dY, dS, dgp, dg;
     HIP_TRY(c, hipMalloc(&dP.p, sizeof(float) * (size_t)NP));
     HIP_TRY(c, hipMalloc(&dX.p, sizeof(float) * hx.size()));
     HIP_TRY(c, hipMalloc(&dY.p, sizeof(float) * hy.size()));
@@ -441,8 +434,8 @@ sgpm_status sgpm_probe_mlp(sgpm_ctx_t c, int64_t N, int iters, double* out4) {
     HIP_TRY(c, hipMemcpy(dP.p, hp.data(), sizeof(float) * hp.size(), hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy(dX.p, hx.data(), sizeof(float) * hx.size(), hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy(dY.p, hy.data(), sizeof(float) * hy.size(), hipMemcpyHostToDevice));
-    hipEvent_t e[4];
-    for (auto& ev : e) HIP_TRY(c, hipEventCreate(&ev));
+    ScopedEvents<4> e;
+    HIP_TRY(c, e.create());
     HIP_TRY(c, mlp_forward((const float*)dP.p, (const float*)dX.p, N, (float*)dS.p, c->st));  // warm
     HIP_TRY(c, hipEventRecord(e[0], c->st));
     for (int i = 0; i < iters; i++) HIP_TRY(c, mlp_forward((const float*)dP.p, (const float*)dX.p, N, (float*)dS.p, c->st));
@@ -458,7 +451,6 @@ sgpm_status sgpm_probe_mlp(sgpm_ctx_t c, int64_t N, int iters, double* out4) {
     float f = 0, b = 0;
     HIP_TRY(c, hipEventElapsedTime(&f, e[0], e[1]));
     HIP_TRY(c, hipEventElapsedTime(&b, e[2], e[3]));
-    for (auto& ev : e) (void)hipEventDestroy(ev);
     const double flops_row = 2.0 * (16.0 * 64 + 64.0 * 64 + 64.0);
     out4[0] = f / iters;
     out4[1] = flops_row * (double)N / (out4[0] * 1e-3) / 1e12;

@@ -281,4 +281,38 @@ inline sgpm_status fail(sgpm_ctx* c, sgpm_status s, const std::string& msg) {
         if (_e != hipSuccess) return sgpm::fail((ctx), SGPM_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
     } while (0)
 
+// Device memory owned by a scope: freed on every return path (hipFree waits for
+// the work still using it).
+struct DeviceBuffer {
+    void* p = nullptr;
+    DeviceBuffer() = default;
+    DeviceBuffer(const DeviceBuffer&) = delete;
+    DeviceBuffer& operator=(const DeviceBuffer&) = delete;
+    ~DeviceBuffer() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+// N HIP events owned by a scope: create() makes them, the destructor releases
+// those made, on every return path.
+template <int N>
+struct ScopedEvents {
+    hipEvent_t e[N] = {};
+    int made = 0;
+    ScopedEvents() = default;
+    ScopedEvents(const ScopedEvents&) = delete;
+    ScopedEvents& operator=(const ScopedEvents&) = delete;
+    hipError_t create() {
+        for (; made < N; made++) {
+            const hipError_t r = hipEventCreate(&e[made]);
+            if (r != hipSuccess) return r;
+        }
+        return hipSuccess;
+    }
+    ~ScopedEvents() {
+        for (int i = 0; i < made; i++) (void)hipEventDestroy(e[i]);
+    }
+    hipEvent_t operator[](int i) const { return e[i]; }
+};
+
 }  // namespace sgpm
