@@ -20,9 +20,11 @@
 //    cone's lower end GS cannot lie below it and the second is skipped.  Before
 //    any colouring, the NS pilot's estimate C bounds GS from below: one
 //    colouring's search reaches about C / c^(k-1) leaves, and two colourings at
-//    an optimistic 1e10 leaves per second (several times the count kernel's
-//    measured rate) taking at least the cone's lower end rule GS out without
-//    running it (a large graph's exact count can take minutes).
+//    an optimistic rate taking at least the cone's lower end rule GS out without
+//    running it (a large graph's exact count can take minutes).  The rate is
+//    1e10 leaves per second when the sparsified graph is sparse (mean degree
+//    2m / (n c) below 16; the count kernel measures 1.4e9 to 3.7e9 there) and
+//    1e11 otherwise (long rows: 4.1e10 measured for the 4-clique on R-MAT 20).
 //
 // The engine then runs exactly as in its own mode with the same options (GS
 // reuses the two pilot colourings, which are its first two), so a hybrid result
@@ -120,7 +122,8 @@ sgpm_status hybrid_estimate(sgpm_ctx* c, sgpm_graph* g, sgpm_pattern* pat, const
         // lower bound of two colourings from the leaves they must reach
         double leaves = mu;
         for (int i = 0; i < p.k - 1; i++) leaves /= (double)col;
-        const double gs_floor = 2.0 * leaves / 1e10;
+        const double sparse_deg = g->n > 0 ? 2.0 * (double)g->m / ((double)g->n * (double)col) : 0.0;
+        const double gs_floor = 2.0 * leaves / (sparse_deg < 16.0 ? 1e10 : 1e11);
         // GS pilot: the GS engine's first colourings, timed end to end
         const double z = normal_quantile(1.0 - (1.0 - o.confidence) / 2.0);
         double rep_seconds = 0.0;
