@@ -237,6 +237,27 @@ def c2(S, O, synth, ctx):
     S.sgpm_graph_free(g)
 
 
+@pytest.mark.parametrize("name,seed", [("4-clique", 3), ("5-clique", 4)])
+def test_c2_strict_run_matches_oracle(S, O, synth, ctx, c2, name, seed):
+    """Full-size R-MAT-20 at the benchmark's options (strict, eps 1 %, 95 %,
+    default windows, autotuned lanes: the clique kernel the benchmark times,
+    which has no trace path): stop point, windows, exact sums, hits and the
+    checksum over every sample equal the oracle's run."""
+    print(f"C2 strict {name}", flush=True)
+    g, og = c2
+    k, e = synth.pattern(name)
+    p = S.sgpm_pattern_create(ctx, k, e)
+    so = S.sgpm_options_default(eps=0.01, confidence=0.95, seed=seed, checksum=1)
+    r, rc = S.sgpm_estimate(ctx, g, p, so)
+    orr = O.run(og, O.compile_plan(k, e), O.make_opts(eps=so.eps, confidence=so.confidence, seed=so.seed,
+                                                       tag=so.query_tag, n_min=so.n_min, w_min=so.w_min,
+                                                       quantum=so.quantum, max_samples=so.max_samples,
+                                                       growth=so.window_growth))
+    check_run(S, O, r, orr)
+    assert r.windows == orr.windows and r.converged == orr.converged == 1 and rc == S.SGPM_OK
+    S.sgpm_pattern_free(p)
+
+
 @pytest.mark.parametrize("name", ["4-clique", "5-clique"])
 def test_c2_sampled_walks(S, O, synth, ctx, c2, name):
     """Full-size R-MAT-20 in the benchmark's launch configuration (autotuned
