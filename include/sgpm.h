@@ -63,17 +63,25 @@ int sgpm_device_count(void);
 
 #define SGPM_ASSUME_CANONICAL 0x1u  /* input is already symmetric, loop-free, deduplicated,
                                        degree-descending relabelled with ascending rows */
+#define SGPM_DEVICE_PTRS 0x2u       /* offsets and nbrs are device pointers (e.g. torch tensors'
+                                       data) on the context's device */
+#define SGPM_SYMMETRIZE 0x4u        /* the default made explicit: symmetrise and clean the input;
+                                       not with SGPM_ASSUME_CANONICAL */
 
 /* Build the canonical data graph (Sec. 6: symmetric, no loops or duplicate
  * edges; vertices relabelled by degree descending, ties by original id; rows
  * ascending) from a CSR of n vertices.  offsets has n+1 entries, int64 when
  * offsets_is_64 else int32; nbrs has offsets[n] int32 entries in [0, n).
  * Without SGPM_ASSUME_CANONICAL every (u, v) entry is symmetrised, loops and
- * duplicates are dropped.  The canonical CSR, the oriented edge list and the
- * arc-row array are kept in device memory owned by the graph handle.
- * Errors: EINVAL (null pointers, n < 0 or n >= 2^31), EBADGRAPH (offsets not
+ * duplicates are dropped.  With SGPM_DEVICE_PTRS the arrays are read from
+ * device memory (the caller keeps them alive during the call): they are copied
+ * to the host, where the canonicalisation runs, and the result is uploaded as
+ * for host arrays.  The canonical CSR, the oriented edge list and the arc-row
+ * array are kept in device memory owned by the graph handle.
+ * Errors: EINVAL (null pointers, n < 0 or n >= 2^31, unknown flags, or
+ * SGPM_SYMMETRIZE with SGPM_ASSUME_CANONICAL), EBADGRAPH (offsets not
  * monotone, neighbour id out of range, or a non-canonical input with
- * SGPM_ASSUME_CANONICAL), ENOMEM, EHIP. */
+ * SGPM_ASSUME_CANONICAL), ENOMEM, EHIP (a device copy failed). */
 sgpm_status sgpm_graph_from_csr(sgpm_ctx_t ctx, int64_t n, const void* offsets, int offsets_is_64,
                                 const int32_t* nbrs, uint32_t flags, sgpm_graph_t* out);
 /* Sizes; perm_out (nullable, n entries) receives perm[original id] = canonical id. */
@@ -304,9 +312,10 @@ sgpm_status sgpm_probe_mlp(sgpm_ctx_t ctx, int64_t N, int iters, double* out4);
 /* These run the host parts of the library without a device, so they can be
  * checked on any machine. */
 
-/* Canonicalise a CSR on the host (same rules as sgpm_graph_from_csr).  Call
- * with nbr_out = NULL to get *m_out (undirected edges); then off_out[n+1],
- * nbr_out[2m] and perm_out[n] (each nullable) are filled by a second call. */
+/* Canonicalise a CSR on the host (same rules as sgpm_graph_from_csr; host
+ * arrays only, so SGPM_DEVICE_PTRS gives EINVAL).  Call with nbr_out = NULL to
+ * get *m_out (undirected edges); then off_out[n+1], nbr_out[2m] and
+ * perm_out[n] (each nullable) are filled by a second call. */
 sgpm_status sgpm_host_canonicalise(int64_t n, const void* offsets, int offsets_is_64, const int32_t* nbrs,
                                    uint32_t flags, int64_t* m_out, int64_t* off_out, int32_t* nbr_out,
                                    int32_t* perm_out);

@@ -145,6 +145,26 @@ void sgpm_options_default(sgpm_options* o) {
 sgpm_status sgpm_graph_from_csr(sgpm_ctx_t c, int64_t n, const void* offsets, int offsets_is_64,
                                 const int32_t* nbrs, uint32_t flags, sgpm_graph_t* out) {
     if (!c || !out || !offsets || n < 0 || n >= (1ll << 31)) return fail(c, SGPM_EINVAL, "bad graph arguments");
+    if (flags & ~(SGPM_ASSUME_CANONICAL | SGPM_DEVICE_PTRS | SGPM_SYMMETRIZE))
+        return fail(c, SGPM_EINVAL, "unknown graph flags");
+    if ((flags & SGPM_ASSUME_CANONICAL) && (flags & SGPM_SYMMETRIZE))
+        return fail(c, SGPM_EINVAL, "SGPM_SYMMETRIZE contradicts SGPM_ASSUME_CANONICAL");
+    // device arrays: staged to the host, where the canonicalisation runs
+    std::vector<unsigned char> h_off;
+    std::vector<int32_t> h_nbr;
+    if (flags & SGPM_DEVICE_PTRS) {
+        HIP_TRY(c, hipSetDevice(c->dev));
+        const size_t w = offsets_is_64 ? 8 : 4;
+        h_off.resize(w * (size_t)(n + 1));
+        HIP_TRY(c, hipMemcpy(h_off.data(), offsets, h_off.size(), hipMemcpyDefault));
+        const int64_t cnt = offsets_is_64 ? ((const int64_t*)h_off.data())[n] : ((const int32_t*)h_off.data())[n];
+        if (cnt < 0) return fail(c, SGPM_EBADGRAPH, "offsets[n] < 0");
+        if (cnt > 0 && !nbrs) return fail(c, SGPM_EINVAL, "null neighbour array");
+        h_nbr.resize((size_t)cnt);
+        if (cnt > 0) HIP_TRY(c, hipMemcpy(h_nbr.data(), nbrs, sizeof(int32_t) * (size_t)cnt, hipMemcpyDefault));
+        offsets = h_off.data();
+        nbrs = h_nbr.data();
+    }
     HostGraph h;
     std::string err;
     int rc = canonicalise(n, offsets, offsets_is_64, nbrs, (flags & SGPM_ASSUME_CANONICAL) != 0, h, err);
@@ -655,6 +675,8 @@ sgpm_status sgpm_host_canonicalise(int64_t n, const void* offsets, int offsets_i
                                    uint32_t flags, int64_t* m_out, int64_t* off_out, int32_t* nbr_out,
                                    int32_t* perm_out) {
     if (!offsets || n < 0 || n >= (1ll << 31)) return SGPM_EINVAL;
+    if (flags & ~(SGPM_ASSUME_CANONICAL | SGPM_SYMMETRIZE)) return SGPM_EINVAL;  // host arrays only
+    if ((flags & SGPM_ASSUME_CANONICAL) && (flags & SGPM_SYMMETRIZE)) return SGPM_EINVAL;
     HostGraph h;
     std::string err;
     int rc = canonicalise(n, offsets, offsets_is_64, nbrs, (flags & SGPM_ASSUME_CANONICAL) != 0, h, err);

@@ -24,6 +24,8 @@ SGPM_NOT_CONVERGED = -5
 SGPM_EBADGRAPH = -6
 SGPM_EOVERFLOW = -7
 SGPM_ASSUME_CANONICAL = 0x1
+SGPM_DEVICE_PTRS = 0x2
+SGPM_SYMMETRIZE = 0x4
 
 MODE_STRICT_NS, MODE_FIXED_N, MODE_GS, MODE_HYBRID = 0, 1, 2, 3
 SAMPLER_PRUNE, SAMPLER_BASE = 0, 1
@@ -195,9 +197,21 @@ def sgpm_options_default(**kw) -> Options:
 
 
 def sgpm_graph_from_csr(ctx, n, off, nbr, flags=0):
+    """off, nbr: host arrays, or device tensors (torch, on the context's
+    device: int32 or int64 offsets, int32 neighbours), passed with
+    SGPM_DEVICE_PTRS."""
+    h = C.c_void_p()
+    if hasattr(off, "data_ptr") and getattr(off, "is_cuda", False):
+        import torch
+        if nbr.dtype != torch.int32 or off.dtype not in (torch.int32, torch.int64):
+            raise TypeError("device CSR: offsets int32/int64, neighbours int32")
+        off, nbr = off.contiguous(), nbr.contiguous()
+        _check(ctx, lib().sgpm_graph_from_csr(ctx, n, C.c_void_p(off.data_ptr()), int(off.dtype == torch.int64),
+                                              C.c_void_p(nbr.data_ptr()) if nbr.numel() else None,
+                                              flags | SGPM_DEVICE_PTRS, C.byref(h)))
+        return h
     off = np.ascontiguousarray(off, dtype=np.int64)
     nbr = np.ascontiguousarray(nbr, dtype=np.int32)
-    h = C.c_void_p()
     _check(ctx, lib().sgpm_graph_from_csr(ctx, n, off.ctypes.data, 1, nbr.ctypes.data if len(nbr) else None,
                                           flags, C.byref(h)))
     return h

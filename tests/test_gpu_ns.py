@@ -86,6 +86,23 @@ def test_graph_upload_matches_oracle(S, c1, ctx):
     assert maxdeg == int(np.diff(og.off).max())
 
 
+@pytest.mark.parametrize("off_dtype", ["int32", "int64"])
+def test_graph_from_device_tensors(S, O, synth, ctx, c1, off_dtype):
+    """The raw (unsymmetrised, duplicated) C1 CSR handed over as torch device
+    tensors builds the same canonical graph as the host path and the oracle."""
+    import torch
+    _, og = c1
+    off, nbr = synth.pairs_to_csr(10000, synth.er_pairs(10000, 80000, 1))
+    d_off = torch.from_numpy(np.asarray(off).astype(off_dtype)).cuda()
+    d_nbr = torch.from_numpy(np.asarray(nbr, dtype=np.int32)).cuda()
+    g = S.sgpm_graph_from_csr(ctx, 10000, d_off, d_nbr)
+    goff, gnbr = S.sgpm_graph_export(ctx, g)
+    n, m, _, perm = S.sgpm_graph_stats(g)
+    assert (n, m) == (og.n, og.m)
+    assert np.array_equal(goff, og.off) and np.array_equal(gnbr, og.nbr) and np.array_equal(perm, og.perm)
+    S.sgpm_graph_free(g)
+
+
 @pytest.mark.parametrize("lanes", [1, 4, 16, 64])
 def test_c1_triangle_full_run(S, O, synth, ctx, c1, lanes):
     """Triangles on the ER graph, 1e6 samples, Philox seed 1: sums, hits and

@@ -44,6 +44,19 @@ def test_assume_canonical_rejects_raw_input(S, synth):
     assert ei.value.status == S.SGPM_EBADGRAPH
 
 
+def test_graph_flags_checked(S, synth):
+    """Host canonicalisation takes host arrays only; unknown flags and the
+    contradictory SYMMETRIZE | ASSUME_CANONICAL are rejected."""
+    off, nbr = synth.pairs_to_csr(50, synth.er_pairs(50, 100, 1))
+    for flags in (S.SGPM_DEVICE_PTRS, 0x100, S.SGPM_SYMMETRIZE | S.SGPM_ASSUME_CANONICAL):
+        with pytest.raises(S.SgpmError) as ei:
+            S.sgpm_host_canonicalise(50, off, nbr, flags)
+        assert ei.value.status == S.SGPM_EINVAL
+    a = S.sgpm_host_canonicalise(50, off, nbr, S.SGPM_SYMMETRIZE)
+    b = S.sgpm_host_canonicalise(50, off, nbr, 0)
+    assert all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
 def test_bad_csr_rejected(S):
     with pytest.raises(S.SgpmError) as ei:
         S.sgpm_host_canonicalise(3, np.array([0, 1, 1, 1]), np.array([5], dtype=np.int32))
