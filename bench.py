@@ -350,6 +350,9 @@ def main():
                          "Chung-Lu graphs, batch vs solo; c4: R-MAT 24 5-clique, learned vs uniform; c5: R-MAT 26 "
                          "6-clique, 5-cycle, diamond in loose (hybrid) mode; coverage: exact counts and the 95 %% "
                          "intervals of 100 seeds on R-MAT 20")
+    ap.add_argument("--counters-run-gs", action="store_true",
+                    help="for counter runs: the 256 MiB calibration copy, then one exact count of the 4-clique, "
+                         "5-clique and diamond on R-MAT 20 colour-sparsified with c = 16 (seed 11, colouring 0)")
     ap.add_argument("--counters-run", action="store_true",
                     help="short run for hardware counters: one 256 MiB copy, then one 4M-sample window per query")
     args = ap.parse_args()
@@ -382,6 +385,17 @@ def main():
 
     queries = ["4-clique", "5-clique"]
     pats = {q: S.sgpm_pattern_create(ctx, *synth.pattern(q)) for q in queries}
+
+    if args.counters_run_gs:
+        S.sgpm_probe_copy(ctx, 256 << 20, 1)
+        sp = S.sgpm_gs_sparsify(ctx, g, 16, 11, 0)
+        for q in ("4-clique", "5-clique", "diamond"):
+            pq = pats[q] if q in pats else S.sgpm_pattern_create(ctx, *synth.pattern(q))
+            tc = time.perf_counter()
+            cnt = S.sgpm_exact_count(ctx, sp, pq)
+            log(f"{q}: exact count {cnt} on the sparsified graph in {1e3 * (time.perf_counter() - tc):.2f} ms")
+        S.sgpm_graph_free(sp)
+        return
 
     if args.counters_run:
         S.sgpm_probe_copy(ctx, 256 << 20, 1)
