@@ -43,15 +43,30 @@ __device__ __forceinline__ uint64_t philox_colour_r64(uint64_t seed, uint64_t v,
     return ((uint64_t)c1 << 32) | (uint64_t)c0;
 }
 
-__global__ void max_degree_kernel(const int64_t* __restrict__ off, int64_t n, unsigned long long* __restrict__ out) {
-    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    unsigned long long d = u < n ? (unsigned long long)(off[u + 1] - off[u]) : 0ull;
+// Largest row length.  Grid-stride over a bounded grid and one atomic per
+// block: atomics on one word serialise, so one per wave (16k of them on R-MAT
+// 20) cost as much as a full pass over the arcs.
+constexpr int MAXDEG_BLOCKS = 1024;
+__global__ __launch_bounds__(256) void max_degree_kernel(const int64_t* __restrict__ off, int64_t n,
+                                                         unsigned long long* __restrict__ out) {
+    unsigned long long d = 0;
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x) {
+        const unsigned long long x = (unsigned long long)(off[u + 1] - off[u]);
+        d = x > d ? x : d;
+    }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         const unsigned long long t = __shfl_xor(d, o);
         d = t > d ? t : d;
     }
-    if ((threadIdx.x & 63) == 0 && d) atomicMax(out, d);
+    __shared__ unsigned long long wmax[4];
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = d;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long m = wmax[0];
+        for (int i = 1; i < 4; ++i) m = wmax[i] > m ? wmax[i] : m;
+        if (m) atomicMax(out, m);
+    }
 }
 
 __global__ void colour_kernel(int64_t n, uint32_t c, uint64_t seed, uint32_t rep, uint8_t* __restrict__ col) {
@@ -596,7 +611,8 @@ hipError_t gs_arc_write(const DGraph& g, const uint8_t* col, uint32_t c, uint64_
 
 hipError_t max_degree(const int64_t* off, int64_t n, unsigned long long* out, hipStream_t st) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(max_degree_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, off, n, out);
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, MAXDEG_BLOCKS);
+    hipLaunchKernelGGL(max_degree_kernel, dim3((unsigned)blocks), dim3(256), 0, st, off, n, out);
     return hipGetLastError();
 }
 
