@@ -118,6 +118,8 @@ sgpm_status sgpm_destroy(sgpm_ctx_t c) {
     if (c->batch_stream) (void)hipStreamDestroy(c->batch_stream);
     if (c->d_bq) (void)hipFree(c->d_bq);
     if (c->h_bq) (void)hipHostFree(c->h_bq);
+    for (auto& b : c->gs_scratch)
+        if (b.first) (void)hipFree(b.first);
     delete c;
     return SGPM_OK;
 }

@@ -20,6 +20,32 @@
 namespace sgpm {
 
 
+// Slot i of the context's GS scratch, at least `bytes` long (grown by a
+// quarter when it must grow, so colourings of slightly different sizes reuse it).
+sgpm_status gs_scratch(sgpm_ctx* c, size_t i, size_t bytes, void** out) {
+    if (c->gs_scratch.size() <= i) c->gs_scratch.resize(i + 1, {nullptr, 0});
+    auto& b = c->gs_scratch[i];
+    if (b.second < bytes) {
+        if (b.first) HIP_TRY(c, hipFree(b.first));
+        b = {nullptr, 0};
+        const size_t want = bytes + bytes / 4;
+        HIP_TRY(c, hipMalloc(&b.first, want));
+        b.second = want;
+    }
+    *out = b.first;
+    return SGPM_OK;
+}
+
+enum GsSlot : size_t { GS_COL, GS_RSTART, GS_RLOW, GS_TK, GS_TL, GS_TKO, GS_TLO, GS_SCAN, GS_EOFF, GS_PART, GS_CELL };
+
+#define GS_SCRATCH(ctx, slot, bytes, ptr)                                        \
+    do {                                                                         \
+        void* _p = nullptr;                                                      \
+        sgpm_status _s = gs_scratch((ctx), (slot), (bytes), &_p);               \
+        if (_s != SGPM_OK) return _s;                                            \
+        (ptr) = decltype(ptr)(_p);                                               \
+    } while (0)
+
 // colours: c of colour sparsification, or (bes) the inverse keep probability
 sgpm_status sparsify(sgpm_ctx* c, sgpm_graph* g, uint32_t colours, uint64_t seed, uint32_t rep, sgpm_graph** out,
                      bool bes = false) {
@@ -27,47 +53,49 @@ sgpm_status sparsify(sgpm_ctx* c, sgpm_graph* g, uint32_t colours, uint64_t seed
     HIP_TRY(c, hipSetDevice(c->dev));
     const int64_t n = g->n;
     const int64_t nt = arc_tiles(2 * g->m);
-    DeviceBuffer col, rstart, rlow, tk, tl, tko, tlo, scratch;
-    HIP_TRY(c, hipMalloc(&col.p, (size_t)std::max<int64_t>(n, 1)));
-    HIP_TRY(c, hipMalloc(&rstart.p, sizeof(int64_t) * (size_t)std::max<int64_t>(n, 1)));
-    HIP_TRY(c, hipMalloc(&rlow.p, sizeof(int64_t) * (size_t)std::max<int64_t>(n, 1)));
-    HIP_TRY(c, hipMalloc(&tk.p, sizeof(int64_t) * (size_t)(nt + 1)));
-    HIP_TRY(c, hipMalloc(&tl.p, sizeof(int64_t) * (size_t)(nt + 1)));
-    HIP_TRY(c, hipMalloc(&tko.p, sizeof(int64_t) * (size_t)(nt + 1)));
-    HIP_TRY(c, hipMalloc(&tlo.p, sizeof(int64_t) * (size_t)(nt + 1)));
-    HIP_TRY(c, hipMalloc(&scratch.p, sizeof(int64_t) * (size_t)scan_scratch_words(nt)));
+    // temporaries from the context's scratch (no allocation once it has grown)
+    const size_t nv = (size_t)std::max<int64_t>(n, 1), ntw = sizeof(int64_t) * (size_t)(nt + 1);
+    uint8_t* col = nullptr;
+    int64_t *rstart = nullptr, *rlow = nullptr, *tk = nullptr, *tl = nullptr, *tko = nullptr, *tlo = nullptr;
+    int64_t *scan = nullptr, *d_eoff = nullptr;
+    GS_SCRATCH(c, GS_COL, nv, col);
+    GS_SCRATCH(c, GS_RSTART, sizeof(int64_t) * nv, rstart);
+    GS_SCRATCH(c, GS_RLOW, sizeof(int64_t) * nv, rlow);
+    GS_SCRATCH(c, GS_TK, ntw, tk);
+    GS_SCRATCH(c, GS_TL, ntw, tl);
+    GS_SCRATCH(c, GS_TKO, ntw, tko);
+    GS_SCRATCH(c, GS_TLO, ntw, tlo);
+    GS_SCRATCH(c, GS_SCAN, sizeof(int64_t) * (size_t)scan_scratch_words(nt), scan);
+    GS_SCRATCH(c, GS_EOFF, sizeof(int64_t) * (size_t)(n + 1), d_eoff);
     auto h = std::make_unique<sgpm_graph>();
     h->ctx = c;
     h->n = n;
     h->perm = g->perm;
     HIP_TRY(c, hipMalloc(&h->d_off, sizeof(int64_t) * (size_t)(n + 1)));
-    int64_t* d_eoff = nullptr;
-    HIP_TRY(c, hipMalloc(&d_eoff, sizeof(int64_t) * (size_t)(n + 1)));
-    std::unique_ptr<int64_t, void (*)(int64_t*)> eguard(d_eoff, [](int64_t* q) { (void)hipFree(q); });
     const DGraph dg = g->view();
-    const uint8_t* colp = bes ? nullptr : (const uint8_t*)col.p;
-    if (!bes) HIP_TRY(c, gs_colours(n, colours, seed, rep, (uint8_t*)col.p, c->st));
+    const uint8_t* colp = bes ? nullptr : col;
+    if (!bes) HIP_TRY(c, gs_colours(n, colours, seed, rep, col, c->st));
     // arcs surviving per tile, their exclusive scans, then the totals
     int64_t arcs = 0, edges = 0;
     if (nt > 0) {
-        HIP_TRY(c, gs_arc_counts(dg, colp, colours, seed, rep, (int64_t*)tk.p, (int64_t*)tl.p, c->st));
-        HIP_TRY(c, exclusive_scan((int64_t*)tk.p, nt, (int64_t*)tko.p, (int64_t*)scratch.p, c->st));
-        HIP_TRY(c, exclusive_scan((int64_t*)tl.p, nt, (int64_t*)tlo.p, (int64_t*)scratch.p, c->st));
-        HIP_TRY(c, hipMemcpyAsync(&arcs, (int64_t*)tko.p + nt, sizeof(int64_t), hipMemcpyDeviceToHost, c->st));
-        HIP_TRY(c, hipMemcpyAsync(&edges, (int64_t*)tlo.p + nt, sizeof(int64_t), hipMemcpyDeviceToHost, c->st));
+        HIP_TRY(c, gs_arc_counts(dg, colp, colours, seed, rep, tk, tl, c->st));
+        HIP_TRY(c, exclusive_scan(tk, nt, tko, scan, c->st));
+        HIP_TRY(c, exclusive_scan(tl, nt, tlo, scan, c->st));
+        HIP_TRY(c, hipMemcpyAsync(&arcs, tko + nt, sizeof(int64_t), hipMemcpyDeviceToHost, c->st));
+        HIP_TRY(c, hipMemcpyAsync(&edges, tlo + nt, sizeof(int64_t), hipMemcpyDeviceToHost, c->st));
         HIP_TRY(c, hipStreamSynchronize(c->st));
     } else {
-        HIP_TRY(c, launch_fill_u64((unsigned long long*)tko.p, 1, 0ull, c->st));
-        HIP_TRY(c, launch_fill_u64((unsigned long long*)tlo.p, 1, 0ull, c->st));
+        HIP_TRY(c, launch_fill_u64((unsigned long long*)tko, 1, 0ull, c->st));
+        HIP_TRY(c, launch_fill_u64((unsigned long long*)tlo, 1, 0ull, c->st));
     }
     if (arcs != 2 * edges) return fail(c, SGPM_EHIP, "internal: sparsified graph is not symmetric");
     h->m = edges;
     HIP_TRY(c, hipMalloc(&h->d_nbr, sizeof(int32_t) * (size_t)std::max<int64_t>(arcs, 1)));
     HIP_TRY(c, hipMalloc(&h->d_arow, sizeof(int32_t) * (size_t)std::max<int64_t>(arcs, 1)));
     HIP_TRY(c, hipMalloc(&h->d_epair, sizeof(int2) * (size_t)std::max<int64_t>(edges, 1)));
-    HIP_TRY(c, gs_arc_write(dg, colp, colours, seed, rep, (int64_t*)tko.p, (int64_t*)tlo.p, h->d_nbr, h->d_arow,
-                            h->d_epair, (int64_t*)rstart.p, (int64_t*)rlow.p, h->d_off, d_eoff, c->st));
-    unsigned long long* d_md = (unsigned long long*)rstart.p;  // reuse as the max-degree cell
+    HIP_TRY(c, gs_arc_write(dg, colp, colours, seed, rep, tko, tlo, h->d_nbr, h->d_arow,
+                            h->d_epair, rstart, rlow, h->d_off, d_eoff, c->st));
+    unsigned long long* d_md = (unsigned long long*)rstart;  // reuse as the max-degree cell
     HIP_TRY(c, launch_fill_u64(d_md, 1, 0ull, c->st));
     HIP_TRY(c, max_degree(h->d_off, n, d_md, c->st));
     unsigned long long md = 0;
@@ -112,16 +140,14 @@ sgpm_status exact_count(sgpm_ctx* c, sgpm_graph* g, const Plan& p, unsigned __in
     // the one ticket counter is not the limit on a graph of short rows
     const int per_ticket =
         (int)std::min<uint64_t>(4096, std::max<uint64_t>(group == 64 ? 1 : 4, nfirst / (groups * 32)));
-    DeviceBuffer part, cell;
-    HIP_TRY(c, hipMalloc(&part.p, sizeof(unsigned long long) * 2 * (size_t)blocks));
-    HIP_TRY(c, hipMalloc(&cell.p, sizeof(unsigned long long) * 4));
-    unsigned long long* d = (unsigned long long*)cell.p;  // ticket, spare, low sum, high sum
+    unsigned long long *part = nullptr, *d = nullptr;  // d: ticket, spare, low sum, high sum
+    GS_SCRATCH(c, GS_PART, sizeof(unsigned long long) * 2 * (size_t)blocks, part);
+    GS_SCRATCH(c, GS_CELL, sizeof(unsigned long long) * 4, d);
     HIP_TRY(c, launch_fill_u64(d, 4, 0ull, c->st));
     ScopedEvents<2> ev;
     HIP_TRY(c, ev.create());
     HIP_TRY(c, hipEventRecord(ev.e[0], c->st));
-    HIP_TRY(c, launch_exact_count(g->view(), p, nfirst, group, blocks, per_ticket, d, (unsigned long long*)part.p,
-                                  d + 2, c->st));
+    HIP_TRY(c, launch_exact_count(g->view(), p, nfirst, group, blocks, per_ticket, d, part, d + 2, c->st));
     HIP_TRY(c, hipEventRecord(ev.e[1], c->st));
     unsigned long long two[2];
     HIP_TRY(c, hipMemcpyAsync(two, d + 2, sizeof(two), hipMemcpyDeviceToHost, c->st));

@@ -203,6 +203,11 @@ struct sgpm_ctx {
     hipStream_t batch_stream = nullptr;
     hipGraph_t batch_graph = nullptr;
     hipGraphExec_t batch_exec = nullptr;
+    // grow-only device scratch of the GS engine (sparsification temporaries,
+    // count partials), reused by every colouring; freed with the context.  GS
+    // calls finish (stream synchronised) before they return, so calls on one
+    // context never share it in flight.
+    std::vector<std::pair<void*, size_t>> gs_scratch;
 };
 
 struct sgpm_graph {
