@@ -51,8 +51,14 @@ typedef struct sgpm_model* sgpm_model_t;
 
 /* Create a context bound to HIP device `hip_device` and stream `hip_stream`
  * (a hipStream_t; NULL = the device's null stream).  The stream must outlive
- * the context. */
+ * the context.  One context per host thread: calls on a context must not
+ * overlap. */
 sgpm_status sgpm_create(sgpm_ctx_t* out, int hip_device, void* hip_stream);
+/* Release the context and the device memory it keeps between calls: the NS
+ * engine's partial-sum and ticket buffers, the batch's capture and query
+ * table, and the GS engine's grow-only scratch (about 25 bytes per vertex of
+ * the largest graph sparsified, plus 32 bytes per 2,048 arcs).  Free the
+ * context's graphs, patterns and models first. */
 sgpm_status sgpm_destroy(sgpm_ctx_t ctx);
 /* Message of the last failing call on ctx; valid until the next call on ctx. */
 const char* sgpm_last_error(sgpm_ctx_t ctx);
