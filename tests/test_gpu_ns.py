@@ -103,6 +103,18 @@ def test_graph_from_device_tensors(S, O, synth, ctx, c1, off_dtype):
     S.sgpm_graph_free(g)
 
 
+def test_empty_graph_from_device_tensors(S, ctx):
+    """Device input with no edges (and with no vertices): nothing to copy for
+    the neighbours, and the graph is empty."""
+    import torch
+    for n in (5, 0):
+        d_off = torch.zeros(n + 1, dtype=torch.int64, device="cuda")
+        d_nbr = torch.zeros(0, dtype=torch.int32, device="cuda")
+        g = S.sgpm_graph_from_csr(ctx, n, d_off, d_nbr)
+        assert S.sgpm_graph_stats(g)[:3] == (n, 0, 0)
+        S.sgpm_graph_free(g)
+
+
 @pytest.mark.parametrize("lanes", [1, 4, 16, 64])
 def test_c1_triangle_full_run(S, O, synth, ctx, c1, lanes):
     """Triangles on the ER graph, 1e6 samples, Philox seed 1: sums, hits and
