@@ -108,22 +108,55 @@ __device__ __forceinline__ bool keep_arc(const KeepRule& k, int64_t u, uint8_t c
 // (an empty row takes the offset of the next non-empty one).
 constexpr int ARC_TILE = 2048;  // 256 threads x 8
 
+// This thread's arcs of a tile, a_i = t0 + 256 i + threadIdx.x for i < 8, with
+// their keep bits (bit i: arc i survives; low: it survives and w < u, an
+// oriented edge).  Every load is issued before any is used -- arc rows and
+// neighbours, then the colour gathers -- so a wave keeps the whole tile's loads
+// in flight instead of one arc's at a time; indexes past the last arc are
+// clamped to arc 0, read, and dropped.  prev (nullable): the row of arc a_i - 1.
+template <bool BES>
+__device__ __forceinline__ void tile_arcs(const DGraph& g, const KeepRule& kr, int64_t t0, int64_t narcs,
+                                          int32_t (&u)[ARC_TILE / 256], int32_t (&w)[ARC_TILE / 256],
+                                          int32_t* prev, uint32_t& keep, uint32_t& low) {
+    constexpr int NA = ARC_TILE / 256;
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+        const int64_t a = t0 + i * 256 + (int64_t)threadIdx.x;
+        const int64_t ac = a < narcs ? a : 0;
+        u[i] = g.arow[ac];
+        w[i] = g.nbr[ac];
+        if (prev) prev[i] = g.arow[ac > 0 ? ac - 1 : 0];
+    }
+    uint8_t cu[NA], cw[NA];
+    if constexpr (!BES) {
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            cu[i] = kr.col[u[i]];
+            cw[i] = kr.col[w[i]];
+        }
+    }
+    keep = 0;
+    low = 0;
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+        const int64_t a = t0 + i * 256 + (int64_t)threadIdx.x;
+        bool k;
+        if constexpr (BES) k = keep_arc<true>(kr, u[i], (uint8_t)0, w[i]);
+        else k = cu[i] == cw[i];
+        k = k && a < narcs;
+        keep |= (uint32_t)k << i;
+        low |= (uint32_t)(k && w[i] < u[i]) << i;
+    }
+}
+
 template <bool BES>
 __global__ __launch_bounds__(256) void arc_count_kernel(DGraph g, KeepRule kr, int64_t narcs,
                                                         int64_t* __restrict__ tk, int64_t* __restrict__ tl) {
     const int64_t t0 = (int64_t)blockIdx.x * ARC_TILE;
-    int k = 0, l = 0;
-#pragma unroll
-    for (int i = 0; i < ARC_TILE / 256; ++i) {
-        const int64_t a = t0 + i * 256 + (int64_t)threadIdx.x;
-        if (a < narcs) {
-            const int32_t u = g.arow[a], w = g.nbr[a];
-            if (keep_arc<BES>(kr, u, BES ? (uint8_t)0 : kr.col[u], w)) {
-                k++;
-                if (w < u) l++;
-            }
-        }
-    }
+    int32_t u[ARC_TILE / 256], w[ARC_TILE / 256];
+    uint32_t keep, low;
+    tile_arcs<BES>(g, kr, t0, narcs, u, w, nullptr, keep, low);
+    int k = __popc(keep), l = __popc(low);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         k += __shfl_xor(k, o);
@@ -152,17 +185,15 @@ __global__ __launch_bounds__(256) void arc_write_kernel(DGraph g, KeepRule kr, i
     __shared__ int sk[4], sl[4];
     const int64_t t0 = (int64_t)blockIdx.x * ARC_TILE;
     int64_t pos = tko[blockIdx.x], lpos = tlo[blockIdx.x];
+    int32_t uu[ARC_TILE / 256], ww[ARC_TILE / 256], pu[ARC_TILE / 256];
+    uint32_t keepm, lowm;
+    tile_arcs<BES>(g, kr, t0, narcs, uu, ww, pu, keepm, lowm);
+#pragma unroll
     for (int i = 0; i < ARC_TILE / 256; ++i) {
         const int64_t a = t0 + i * 256 + (int64_t)threadIdx.x;
-        bool keep = false, low = false, first = false;
-        int32_t u = 0, w = 0;
-        if (a < narcs) {
-            u = g.arow[a];
-            w = g.nbr[a];
-            keep = keep_arc<BES>(kr, u, BES ? (uint8_t)0 : kr.col[u], w);
-            low = keep && w < u;
-            first = a == 0 || g.arow[a - 1] != u;
-        }
+        const int32_t u = uu[i], w = ww[i];
+        const bool keep = (keepm >> i) & 1u, low = (lowm >> i) & 1u;
+        const bool first = a < narcs && (a == 0 || pu[i] != u);
         const uint64_t km = __ballot(keep), lm = __ballot(low);
         if (lane == 0) {
             sk[wid] = (int)__popcll(km);
