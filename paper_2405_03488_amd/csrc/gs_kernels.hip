@@ -180,38 +180,47 @@ __global__ __launch_bounds__(256) void arc_write_kernel(DGraph g, KeepRule kr, i
                                                         const int64_t* __restrict__ tlo, int32_t* __restrict__ nnbr,
                                                         int32_t* __restrict__ narow, int2* __restrict__ nepair,
                                                         int64_t* __restrict__ rstart, int64_t* __restrict__ rlow) {
+    constexpr int NA = ARC_TILE / 256;
     const int lane = (int)(threadIdx.x & 63), wid = (int)(threadIdx.x >> 6);
     const uint64_t below = (1ull << lane) - 1ull;
-    __shared__ int sk[4], sl[4];
+    // surviving arcs and oriented edges per (group of 256 arcs, wave): the rank
+    // of an arc in the tile is the count over earlier groups, then over the
+    // earlier waves of its group, then over the earlier lanes of its wave
+    __shared__ int sk[NA][4], sl[NA][4];
     const int64_t t0 = (int64_t)blockIdx.x * ARC_TILE;
-    int64_t pos = tko[blockIdx.x], lpos = tlo[blockIdx.x];
-    int32_t uu[ARC_TILE / 256], ww[ARC_TILE / 256], pu[ARC_TILE / 256];
+    int32_t uu[NA], ww[NA], pu[NA];
     uint32_t keepm, lowm;
     tile_arcs<BES>(g, kr, t0, narcs, uu, ww, pu, keepm, lowm);
+    uint64_t km[NA], lm[NA];
 #pragma unroll
-    for (int i = 0; i < ARC_TILE / 256; ++i) {
+    for (int i = 0; i < NA; ++i) {
+        km[i] = __ballot((keepm >> i) & 1u);
+        lm[i] = __ballot((lowm >> i) & 1u);
+        if (lane == 0) {
+            sk[i][wid] = (int)__popcll(km[i]);
+            sl[i][wid] = (int)__popcll(lm[i]);
+        }
+    }
+    __syncthreads();
+    int64_t pos = tko[blockIdx.x], lpos = tlo[blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
         const int64_t a = t0 + i * 256 + (int64_t)threadIdx.x;
         const int32_t u = uu[i], w = ww[i];
         const bool keep = (keepm >> i) & 1u, low = (lowm >> i) & 1u;
         const bool first = a < narcs && (a == 0 || pu[i] != u);
-        const uint64_t km = __ballot(keep), lm = __ballot(low);
-        if (lane == 0) {
-            sk[wid] = (int)__popcll(km);
-            sl[wid] = (int)__popcll(lm);
-        }
-        __syncthreads();
         int kb = 0, lb = 0, kt = 0, lt = 0;
 #pragma unroll
         for (int x = 0; x < 4; ++x) {
             if (x < wid) {
-                kb += sk[x];
-                lb += sl[x];
+                kb += sk[i][x];
+                lb += sl[i][x];
             }
-            kt += sk[x];
-            lt += sl[x];
+            kt += sk[i][x];
+            lt += sl[i][x];
         }
-        const int64_t p = pos + kb + (int64_t)__popcll(km & below);
-        const int64_t lp = lpos + lb + (int64_t)__popcll(lm & below);
+        const int64_t p = pos + kb + (int64_t)__popcll(km[i] & below);
+        const int64_t lp = lpos + lb + (int64_t)__popcll(lm[i] & below);
         if (keep) {
             nnbr[p] = w;
             narow[p] = u;
@@ -223,7 +232,6 @@ __global__ __launch_bounds__(256) void arc_write_kernel(DGraph g, KeepRule kr, i
         }
         pos += kt;
         lpos += lt;
-        __syncthreads();
     }
 }
 
