@@ -516,6 +516,14 @@ def main():
                "sample": f"4-clique NS-prune on the same rmat{scale} graph, fixed {N} samples (seed 6), "
                          f"{dt:.1f}s on {th} threads"}
         log(f"cpu oracle: {N / dt:.4g} samples/s ({N} samples, {dt:.1f}s, {th} threads)")
+        # the same oracle on one core, on a sample of about a tenth of the time
+        N1 = max(20000, int(N / max(1, th) / 10))
+        tc = time.perf_counter()
+        O.run(og, op, O.make_opts(fixed_n=N1, seed=7, threads=1))
+        dt1 = time.perf_counter() - tc
+        cpu["single_core"] = {"value": N1 / dt1, "unit": "samples/s", "cores": 1,
+                              "sample": f"fixed {N1} samples (seed 7), {dt1:.1f}s on 1 thread"}
+        log(f"cpu oracle, one core: {N1 / dt1:.4g} samples/s ({N1} samples, {dt1:.1f}s)")
 
     value = total_samples / wall
     traffic = measured_traffic(runs, launches)
