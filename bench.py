@@ -479,6 +479,7 @@ def main():
 
     # CPU leg: oracle baseline and verification of the timed runs
     cpu = None
+    cpu_bytes = None
     verified = None
     if not args.no_cpu:
         from oracle import oracle as O
@@ -524,6 +525,24 @@ def main():
         cpu["single_core"] = {"value": N1 / dt1, "unit": "samples/s", "cores": 1,
                               "sample": f"fixed {N1} samples (seed 7), {dt1:.1f}s on 1 thread"}
         log(f"cpu oracle, one core: {N1 / dt1:.4g} samples/s ({N1} samples, {dt1:.1f}s)")
+        # algorithmic bytes per sample (the measurement definition the roofline
+        # uses), by the step at which the sample ended, from the oracle's records
+        bdist = {}
+        for q in queries:
+            kq, eq = synth.pattern(q)
+            opq = O.compile_plan(kq, eq)
+            ends = {}
+            allb = []
+            for sid in range(20000):
+                rec = O.sample(og, opq, 1, 0, sid)
+                key = "hit" if rec.hit else f"ended at step {rec.fail_step}"
+                ends.setdefault(key, []).append(int(rec.bytes))
+                allb.append(int(rec.bytes))
+            a = np.array(allb, dtype=np.float64)
+            bdist[q] = {"samples": len(allb), "mean": float(a.mean()), "p50": float(np.percentile(a, 50)),
+                        "p90": float(np.percentile(a, 90)), "p99": float(np.percentile(a, 99)), "max": float(a.max()),
+                        "by_end": {k2: {"samples": len(v), "mean": float(np.mean(v))} for k2, v in sorted(ends.items())}}
+        cpu_bytes = bdist
 
     value = total_samples / wall
     traffic = measured_traffic(runs, launches)
@@ -555,6 +574,7 @@ def main():
                      "alg_bytes_per_launch": alg_bytes / max(1, launches),
                      "measured": probes},
         "cpu_baseline": cpu,
+        "bytes_per_sample": cpu_bytes,
         "learned_vs_uniform": learned,
         "gs_hybrid_mlp": other,
     }
