@@ -171,6 +171,17 @@ def learned_leg(S, ctx, g, pats, queries, eps, steps, lanes):
     return out
 
 
+def host_cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def load_graph(S, synth, ctx, name, n, pairs_fn):
     t0 = time.time()
     pairs = pairs_fn()
@@ -524,6 +535,7 @@ def main():
         dt1 = time.perf_counter() - tc
         cpu["single_core"] = {"value": N1 / dt1, "unit": "samples/s", "cores": 1,
                               "sample": f"fixed {N1} samples (seed 7), {dt1:.1f}s on 1 thread"}
+        cpu["host"] = {"nproc": os.cpu_count(), "cpu_model": host_cpu_model()}
         log(f"cpu oracle, one core: {N1 / dt1:.4g} samples/s ({N1} samples, {dt1:.1f}s)")
         # algorithmic bytes per sample (the measurement definition the roofline
         # uses), by the step at which the sample ended, from the oracle's records
