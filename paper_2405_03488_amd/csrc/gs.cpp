@@ -111,8 +111,10 @@ sgpm_status sparsify(sgpm_ctx* c, sgpm_graph* g, uint32_t colours, uint64_t seed
 // short; the whole wave pays where deeper levels scan long rows.  In the clique
 // search every candidate row is a degree-ordered out-row, so on a sparse graph
 // (mean degree below 16, as after colour sparsification) a triangle takes 8
-// lanes and a 4-clique 16; every other case, and any graph of mean degree 16 or
-// more, the whole wave.  R-MAT 20 sparsified with c = 16, ms at 8 / 16 / 64
+// lanes and a 4-clique 16.  A 3-vertex pattern's search is one counted level
+// per first edge, so the wedge is narrow too (16 lanes: 1.8 against 3.1 ms at
+// c = 16).  Every other case, and any graph of mean degree 16 or more, takes
+// the whole wave.  R-MAT 20 sparsified with c = 16, ms at 8 / 16 / 64
 // lanes: triangle 0.51 / 0.86 / 3.07, 4-clique 1.65 / 1.25 / 3.20, 5-clique
 // 17.0 / 8.0 / 6.7, diamond 384 / 182 / 25, 4-cycle 40 / 42 / 56.
 // SGPM_EXACT_GROUP = 8, 16 or 64 fixes the width (tuning, and tests that run
@@ -122,8 +124,9 @@ int exact_group(const sgpm_graph* g, const Plan& p) {
         const int v = std::atoi(e);
         if (v == 8 || v == 16 || v == 64) return v;
     }
-    if (2.0 * (double)g->m >= 16.0 * (double)g->n || !plan_is_clique(p)) return 64;
-    return p.k == 3 ? 8 : p.k == 4 ? 16 : 64;
+    if (2.0 * (double)g->m >= 16.0 * (double)g->n) return 64;
+    if (p.k == 3) return plan_is_clique(p) ? 8 : 16;  // one counted level per first edge
+    return plan_is_clique(p) && p.k == 4 ? 16 : 64;
 }
 
 // exact count of the plan's tuples on g (the leaves of the pruned search tree)
