@@ -90,7 +90,11 @@ int sgpm_device_count(void);
  * SGPM_ASSUME_CANONICAL), ENOMEM, EHIP (a device copy failed). */
 sgpm_status sgpm_graph_from_csr(sgpm_ctx_t ctx, int64_t n, const void* offsets, int offsets_is_64,
                                 const int32_t* nbrs, uint32_t flags, sgpm_graph_t* out);
-/* Sizes; perm_out (nullable, n entries) receives perm[original id] = canonical id. */
+/* Sizes of the canonical graph (Sec. 6, the data-graph table: |V|, |E| of the
+ * symmetrised, loop-free graph, and the maximum degree that the sampling cost
+ * depends on, Sec. 4.3): *n vertices, *m undirected edges, *max_deg (each
+ * nullable); perm_out (nullable, n entries) receives perm[original id] =
+ * canonical id.  EINVAL for a null graph. */
 sgpm_status sgpm_graph_stats(sgpm_graph_t g, int64_t* n, int64_t* m, int64_t* max_deg, int32_t* perm_out);
 /* Copy the canonical CSR to host arrays off_out[n+1], nbr_out[2m] (either nullable). */
 sgpm_status sgpm_graph_export(sgpm_graph_t g, int64_t* off_out, int32_t* nbr_out);
@@ -164,7 +168,9 @@ typedef struct {
     uint64_t quantum;        /* window ends are multiples of this */
     uint64_t max_samples;    /* hard cap (NOT_CONVERGED when reached) */
     double window_growth;    /* next window = max(w_min, ceil(growth * n)) */
-    int32_t colours;         /* GS: colours c (0 = choose) */
+    int32_t colours;         /* GS: colours c in [1, 256], or 0 = choose c in 4..16 from one probe colouring
+                                (see sgpm_host_colours_choice; the Bernoulli scheme takes 8); < 0 or > 256
+                                is EINVAL */
     int32_t gs_reps_max;     /* GS: cap on repeated colourings */
     sgpm_model_t proposal;   /* NULL = uniform proposal */
     int32_t lanes_per_sample;/* 0 = autotune, else 1, 4, 16 or 64 lanes cooperate on one sample */
@@ -178,9 +184,11 @@ typedef struct {
 
 typedef struct {
     double estimate;         /* mu = S1 / n (NS) or the mean of c^(k-1) Y over colourings (GS) */
-    double eps_hat;          /* predicted relative error (error equation, Sec. 4.1); +inf if S1 = 0 */
+    double eps_hat;          /* predicted relative error (error equation, Sec. 4.1); +inf if S1 = 0.  GS:
+                                t_{n-1} sqrt((n S2 - S1^2) / (n - 1)) / S1 over the n sparsifications */
     double ci_lo, ci_hi;     /* mu -+ z sigma */
-    double z;                /* Phi^-1(1 - delta/2) */
+    double z;                /* NS: Phi^-1(1 - delta/2); GS: the Student t quantile with n - 1 degrees of
+                                freedom at the same two-sided confidence */
     uint64_t n_samples, n_hits;
     uint32_t sum_digits[8];  /* S1 = sum X, little-endian 32-bit digits */
     uint32_t sumsq_digits[12]; /* S2 = sum X^2 */
@@ -232,8 +240,12 @@ sgpm_status sgpm_estimate_counted(sgpm_ctx_t ctx, sgpm_graph_t g, sgpm_pattern_t
 sgpm_status sgpm_estimate_batch(sgpm_ctx_t ctx, int nq, const sgpm_graph_t* graphs,
                                 const sgpm_pattern_t* patterns, const sgpm_options* opts, sgpm_result* res);
 
-/* Exact count of P in G: the plan-driven nested-loop search of the GS engine on
- * the unsparsified graph (one colour).  The count is (count_hi << 64) | count_lo.
+/* Exact count of P in G: the plan-driven nested-loop search of the GS engine
+ * (Sec. 4.4: one loop per pattern vertex over its candidate set, formed by set
+ * intersections; Sec. 5.2: the exact search that runs on each sparsified
+ * graph) on the unsparsified graph, which is colour sparsification with one
+ * colour.  The count is (count_hi << 64) | count_lo (count_hi nullable).
+ * Errors: EINVAL (null ctx, graph, pattern or count_lo), EHIP.
  * The search runs 8, 16 or 64 lanes per first edge, chosen from the pattern and
  * the graph's mean degree; the environment variable SGPM_EXACT_GROUP (8, 16 or
  * 64) fixes it.  The count does not depend on the width. */
@@ -334,6 +346,22 @@ double sgpm_host_normal_quantile(double p);
 /* Predicted relative error from exact sums given as little-endian 32-bit digits
  * (error equation, Sec. 4.1); +inf when S1 = 0. */
 double sgpm_host_predicted_error(double z, uint64_t n, const uint32_t* s1, int n1, const uint32_t* s2, int n2);
+/* Two-sided Student t quantile: t with P(|T| <= t) = conf for nu >= 1 degrees
+ * of freedom (NaN outside 0 < conf < 1 or for nu < 1). */
+double sgpm_host_t_quantile(double conf, int nu);
+/* Predicted relative error of the GS estimate (the mean of n repeated
+ * sparsifications) from its exact sums: t * sqrt((n S2 - S1^2) / (n - 1)) / S1,
+ * the unbiased-variance form; +inf when n < 2 or S1 = 0. */
+double sgpm_host_predicted_error_t(double t, uint64_t n, const uint32_t* s1, int n1, const uint32_t* s2, int n2);
+/* Colour count chosen for colours = 0 (Sec. 4.4: GS time is insensitive to c
+ * inside a stabilisation window, so the fewest colours inside it give the best
+ * accuracy).  A probe colouring at c = 16 (repetition 0x3FFFFFFF) of a graph
+ * with m edges found leaves16 matches of a k-vertex pattern; a colouring at c
+ * is predicted to take 2m / 1e11 + 3e-4 + leaves16 (16 / c)^(k-1) / 3e9
+ * seconds (sparsification, then a search whose leaves scale as c^-(k-1)), and
+ * the result is the smallest c of 4, 5, 6, 8, 10, 12, 16 predicted within 25 %
+ * of the time at 16.  SGPM_EINVAL for m < 0, k outside [2, 8] or leaves16 < 0. */
+int sgpm_host_colours_choice(int64_t m, int k, double leaves16);
 /* End of the window that starts at sample n_t under options o. */
 uint64_t sgpm_host_next_window(uint64_t n_t, const sgpm_options* o);
 /* Hybrid selection from pilot figures (loose mode, Sec. 5.1 and the NS cost
@@ -342,14 +370,16 @@ uint64_t sgpm_host_next_window(uint64_t n_t, const sgpm_options* o);
  * scale with (eps_hat / eps)^2, so slice i predicts slice_seconds[i] *
  * (slice_eps_hat[i] / eps)^2 and the slices' min and max form the NS cone
  * (*ns_lo, *ns_hi; +inf for a slice without hits).  GS: gs_reps_run (1 or 2)
- * pilot colourings took gs_rep_seconds each on average; with two, gs_eps_hat2
- * is their predicted error and GS needs R = max(2, ceil(2 (gs_eps_hat2 /
- * eps)^2)) colourings (+inf if R > gs_reps_max or gs_eps_hat2 = +inf); with
- * one, only the lower bound 2 * gs_rep_seconds is known.  *gs_pred = R *
- * gs_rep_seconds.  Returns SGPM_SCHEME_GS when GS lies entirely below the
- * cone, else SGPM_SCHEME_NS (above or overlapping: NS keeps the guarantee). */
+ * pilot colourings took gs_rep_seconds each on average; with two, gs_cv is the
+ * relative standard deviation of one colouring's estimate (unbiased variance
+ * over the squared mean) and GS needs the smallest R in [3, gs_reps_max] with
+ * t_{R-1} gs_cv / sqrt(R) <= eps (t: two-sided Student t quantile at
+ * `confidence`), +inf if there is none; with one, only the lower bound
+ * 2 * gs_rep_seconds is known.  *gs_pred = R * gs_rep_seconds.  Returns
+ * SGPM_SCHEME_GS when GS lies entirely below the cone, else SGPM_SCHEME_NS
+ * (above or overlapping: NS keeps the guarantee); SGPM_EINVAL for bad inputs. */
 int sgpm_host_hybrid_choice(int slices, const double* slice_seconds, const double* slice_eps_hat, double eps,
-                            int gs_reps_run, double gs_rep_seconds, double gs_eps_hat2, int gs_reps_max,
+                            double confidence, int gs_reps_run, double gs_rep_seconds, double gs_cv, int gs_reps_max,
                             double* ns_lo, double* ns_hi, double* gs_pred);
 
 #ifdef __cplusplus

@@ -56,7 +56,8 @@ typedef struct {
     uint64_t size[8];      /* |S_j| for the steps that ran (size[0] = M) */
     int32_t k, hit, fail_step, overflow;
     uint64_t alpha_lo, alpha_hi;   /* X_s as a 128-bit integer (0 on a miss) */
-    uint64_t bytes;        /* algorithmic bytes of this sample (measurement definition) */
+    uint64_t bytes;        /* algorithmic bytes of this sample (measurement definition: every row merged) */
+    uint64_t bytes_min;    /* the same with only the smallest connected row's entries (lower bound) */
 } orc_rec;
 
 typedef struct {
@@ -109,6 +110,8 @@ int orc_ns_run(const orc_graph* g, const orc_plan* p, const orc_ns_opts* o, orc_
 double orc_norm_ppf(double p);
 double orc_digits_to_double(const uint32_t* d, int nd);
 double orc_eps_hat(double z, uint64_t n, const uint32_t* s1, int n1, const uint32_t* s2, int n2);
+double orc_t_ppf(double conf, int nu);
+double orc_eps_hat_t(double t, uint64_t n, const uint32_t* s1, int n1, const uint32_t* s2, int n2);
 uint64_t orc_window_next(uint64_t n_t, const orc_ns_opts* o);
 
 typedef struct {

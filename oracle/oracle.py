@@ -32,7 +32,8 @@ class Plan(C.Structure):
 class Rec(C.Structure):
     _fields_ = [("s", C.c_uint64), ("v", C.c_int32 * 8), ("size", C.c_uint64 * 8), ("k", C.c_int32),
                 ("hit", C.c_int32), ("fail_step", C.c_int32), ("overflow", C.c_int32),
-                ("alpha_lo", C.c_uint64), ("alpha_hi", C.c_uint64), ("bytes", C.c_uint64)]
+                ("alpha_lo", C.c_uint64), ("alpha_hi", C.c_uint64), ("bytes", C.c_uint64),
+                ("bytes_min", C.c_uint64)]
 
     @property
     def alpha(self) -> int:
@@ -112,6 +113,10 @@ def lib():
         L.orc_norm_ppf.restype = C.c_double
         L.orc_eps_hat.argtypes = [C.c_double, C.c_uint64, P, C.c_int, P, C.c_int]
         L.orc_eps_hat.restype = C.c_double
+        L.orc_t_ppf.argtypes = [C.c_double, C.c_int]
+        L.orc_t_ppf.restype = C.c_double
+        L.orc_eps_hat_t.argtypes = [C.c_double, C.c_uint64, P, C.c_int, P, C.c_int]
+        L.orc_eps_hat_t.restype = C.c_double
         L.orc_window_next.argtypes = [C.c_uint64, C.POINTER(NsOpts)]
         L.orc_window_next.restype = C.c_uint64
         L.orc_gs_colour.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_int64]
@@ -372,6 +377,16 @@ def eps_hat(z, n, S1: int, S2: int) -> float:
     d1 = np.array([(S1 >> (32 * i)) & 0xFFFFFFFF for i in range(8)], dtype=np.uint32)
     d2 = np.array([(S2 >> (32 * i)) & 0xFFFFFFFF for i in range(12)], dtype=np.uint32)
     return float(lib().orc_eps_hat(z, n, d1.ctypes.data, 8, d2.ctypes.data, 12))
+
+
+def t_ppf(conf, nu) -> float:
+    return float(lib().orc_t_ppf(conf, nu))
+
+
+def eps_hat_t(t, n, S1: int, S2: int) -> float:
+    d1 = np.array([(S1 >> (32 * i)) & 0xFFFFFFFF for i in range(8)], dtype=np.uint32)
+    d2 = np.array([(S2 >> (32 * i)) & 0xFFFFFFFF for i in range(12)], dtype=np.uint32)
+    return float(lib().orc_eps_hat_t(t, n, d1.ctypes.data, 8, d2.ctypes.data, 12))
 
 
 def window_next(n_t, opts: NsOpts) -> int:

@@ -105,8 +105,15 @@ int orc_plan_edges(const orc_plan* p) {
 }
 
 /* GS estimate over repeated colourings: X_r = c^(k-1) * Y_r for rep r = 0, 1, ...
- * treated as i.i.d. samples through the NS-online statistics (Sec. 4.1); stop
- * at the first n >= 2 with eps_hat <= eps, or after reps_max colourings. */
+ * are i.i.d. unbiased estimates of the count.  The paper gives GS no online
+ * confidence interval (Sec. 4.4 bounds its variance; Sec. 5.1 gives loose mode
+ * no guarantee), and n is small here (a few colourings), so the interval is the
+ * Student t interval of their mean: eps_hat = t_{n-1} sqrt(D / (n - 1)) / S1
+ * with D = n S2 - S1^2, the unbiased variance and t_{n-1} the two-sided
+ * quantile at the requested confidence.  Stop at the first n >= 3 with
+ * eps_hat <= eps, or after reps_max colourings: two colourings of a small or
+ * skewed count often give equal values, a zero variance and an interval of
+ * width zero, so the test starts at the third. */
 static void add_digits(uint32_t* acc, int nd, const uint64_t* cols, int nc) {
     unsigned __int128 carry = 0;
     for (int i = 0; i < nd; i++) {
@@ -121,7 +128,7 @@ static int gs_run_scheme(const orc_graph* g, const orc_plan* p, uint32_t c, uint
                          double confidence, int reps_max, int nthreads, orc_gs_result* r, uint64_t* y_per_rep,
                          int bes) {
     memset(r, 0, sizeof(*r));
-    double z = orc_norm_ppf(1.0 - (1.0 - confidence) / 2.0);
+    double z = orc_t_ppf(confidence, 1);
     unsigned __int128 scale = 1;
     int expo = bes ? orc_plan_edges(p) : p->k - 1;
     for (int i = 0; i < expo; i++) scale *= c;
@@ -145,8 +152,9 @@ static int gs_run_scheme(const orc_graph* g, const orc_plan* p, uint32_t c, uint
         add_digits(r->s2, 12, sq, 8);
         r->reps++;
         if (y) r->nonzero++;
-        r->eps_hat = orc_eps_hat(z, r->reps, r->s1, 8, r->s2, 12);
-        if (r->reps >= 2 && r->eps_hat <= eps) { r->converged = 1; break; }
+        if (r->reps >= 2) z = orc_t_ppf(confidence, (int)r->reps - 1);
+        r->eps_hat = orc_eps_hat_t(z, r->reps, r->s1, 8, r->s2, 12);
+        if (r->reps >= 3 && r->eps_hat <= eps) { r->converged = 1; break; }
     }
     /* estimate = S1 / n with S1 rounded once */
     r->estimate = orc_digits_to_double(r->s1, 8) / (double)r->reps;

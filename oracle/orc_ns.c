@@ -131,28 +131,41 @@ uint64_t orc_candidates(const orc_graph* g, const orc_plan* p, int j, const int3
     return cnt;
 }
 
-/* Measurement definition of a sample's algorithmic bytes: 8 for the first
- * edge, 16 (an int64 offset pair) for each distinct earlier vertex whose row a
- * step reads, and 4 per entry of the smallest such connected row that lies
- * strictly inside the step's bounds. */
-static uint64_t step_bytes(const orc_graph* g, const orc_plan* p, int j, const int32_t* v, uint32_t* opened) {
+/* Measurement definition of a sample's algorithmic bytes (the work a merge
+ * of sorted rows must read, independent of how a kernel does it): 8 for the
+ * first edge, 16 (an int64 offset pair) for each distinct earlier vertex whose
+ * row a step reads (a pattern edge or, vertex-induced, a non-edge to position
+ * j), and 4 per entry of EACH such row that lies strictly inside the step's
+ * symmetry-breaking bounds, for every step up to and including the first empty
+ * one.  *min_b receives the same sum with only the smallest connected row's
+ * entries counted (a lower bound: what a scan of the shortest row alone must
+ * read). */
+static uint64_t step_bytes(const orc_graph* g, const orc_plan* p, int j, const int32_t* v, uint32_t* opened,
+                           uint64_t* min_b) {
     int64_t lo = -1, hi = g->n;
     for (int i = 0; i < j; i++) {
         if (p->upper[j] >> i & 1) { if (v[i] < hi) hi = v[i]; }
         if (p->lower[j] >> i & 1) { if (v[i] > lo) lo = v[i]; }
     }
-    uint64_t b = 0;
+    uint64_t b = 0, small = 0;
     uint32_t rows = (uint32_t)(p->connect[j] | p->disconnect[j]);
     for (int i = 0; i < j; i++)
         if ((rows >> i & 1) && !(*opened >> i & 1)) { b += 16; *opened |= 1u << i; }
+    uint64_t head = b;
     int best = -1;
-    for (int i = 0; i < j; i++)
-        if (p->connect[j] >> i & 1) {
-            int64_t d = g->off[v[i] + 1] - g->off[v[i]];
-            if (best < 0 || d < g->off[v[best] + 1] - g->off[v[best]]) best = i;
+    for (int i = 0; i < j; i++) {
+        if (!(rows >> i & 1)) continue;
+        uint64_t in = 0;
+        for (int64_t e = g->off[v[i]]; e < g->off[v[i] + 1]; e++)
+            if (g->nbr[e] > lo && g->nbr[e] < hi) in += 4;
+        b += in;
+        if ((p->connect[j] >> i & 1) &&
+            (best < 0 || g->off[v[i] + 1] - g->off[v[i]] < g->off[v[best] + 1] - g->off[v[best]])) {
+            best = i;
+            small = in;
         }
-    for (int64_t e = g->off[v[best]]; e < g->off[v[best] + 1]; e++)
-        if (g->nbr[e] > lo && g->nbr[e] < hi) b += 4;
+    }
+    *min_b += head + small;
     return b;
 }
 
@@ -170,11 +183,12 @@ void orc_ns_sample(const orc_graph* g, const orc_plan* p, uint64_t seed, uint32_
     if (p->oriented) { r->v[0] = g->esrc[e]; r->v[1] = g->edst[e]; }
     else { r->v[0] = g->arow[e]; r->v[1] = g->nbr[e]; }
     r->bytes = 8;
+    r->bytes_min = 8;
     uint32_t opened = 0;
     unsigned __int128 alpha = M;
     int32_t* buf = NULL;
     for (int j = 2; j < p->k; j++) {
-        r->bytes += step_bytes(g, p, j, r->v, &opened);
+        r->bytes += step_bytes(g, p, j, r->v, &opened, &r->bytes_min);
         uint64_t cnt = orc_candidates(g, p, j, r->v, NULL);
         r->size[j] = cnt;
         if (cnt == 0) {
@@ -422,6 +436,72 @@ double orc_eps_hat(double z, uint64_t n, const uint32_t* s1, int n1, const uint3
     double r = sqrt(q);
     double t = z * r;
     return t / dS1;
+}
+
+/* Student's t distribution with nu degrees of freedom: P(|T| <= t) by the
+ * closed forms for integer nu (Abramowitz and Stegun 26.7.3 for odd nu,
+ * 26.7.4 for even nu), with theta = atan(t / sqrt(nu)):
+ *   odd nu:  (2/pi) [theta + sin(theta) (cos + (2/3) cos^3 + (2*4)/(3*5) cos^5
+ *            + ... up to cos^(nu-2))]   (theta alone for nu = 1)
+ *   even nu: sin(theta) [1 + (1/2) cos^2 + (1*3)/(2*4) cos^4 + ... up to cos^(nu-2)]
+ * evaluated in x87 extended precision. */
+static long double t_central(long double t, int nu) {
+    long double th = atanl(t / sqrtl((long double)nu)), s = sinl(th), c = cosl(th);
+    if (nu % 2) {
+        long double sum = 0.0L;
+        if (nu > 1) {
+            long double term = c;   /* cos^1 */
+            sum = term;
+            for (int i = 3; i <= nu - 2; i += 2) {
+                term *= c * c * (long double)(i - 1) / (long double)i;
+                sum += term;
+            }
+        }
+        return 2.0L / 3.14159265358979323846264338327950288L * (th + s * sum);
+    }
+    long double term = 1.0L, sum = 1.0L;
+    for (int i = 2; i <= nu - 2; i += 2) {
+        term *= c * c * (long double)(i - 1) / (long double)i;
+        sum += term;
+    }
+    return s * sum;
+}
+
+/* t with P(|T| <= t) = conf for nu degrees of freedom (the two-sided quantile,
+ * t_{nu}(1 - delta/2) with conf = 1 - delta), by bisection in extended
+ * precision, then rounded to double. */
+double orc_t_ppf(double conf, int nu) {
+    if (!(conf > 0.0 && conf < 1.0) || nu < 1) return NAN;
+    long double lo = 0.0L, hi = 1.0L, C = (long double)conf;
+    while (t_central(hi, nu) < C) hi *= 2.0L;
+    for (int it = 0; it < 20000; it++) {
+        long double mid = 0.5L * (lo + hi);
+        if (mid == lo || mid == hi) break;
+        if (t_central(mid, nu) < C) lo = mid; else hi = mid;
+    }
+    return (double)(0.5L * (lo + hi));
+}
+
+/* Predicted relative error of the mean of n i.i.d. values from their exact
+ * sums with the unbiased sample variance s^2 = (S2 - S1^2/n) / (n - 1): the
+ * standard error over the mean is sqrt(D / (n - 1)) / S1 with D = n S2 - S1^2,
+ * scaled by the t quantile.  +inf while n < 2 or S1 = 0.  Used for the repeated
+ * sparsifications of the GS path, where n is small. */
+double orc_eps_hat_t(double t, uint64_t n, const uint32_t* s1, int n1, const uint32_t* s2, int n2) {
+    obig S1, S2, N, a, b;
+    ob_zero(&S1); ob_zero(&S2); ob_zero(&N);
+    for (int i = 0; i < n1 && i < OB; i++) S1.d[i] = s1[i];
+    for (int i = 0; i < n2 && i < OB; i++) S2.d[i] = s2[i];
+    if (ob_is_zero(&S1) || n < 2) return INFINITY;
+    N.d[0] = (uint32_t)n; N.d[1] = (uint32_t)(n >> 32);
+    ob_mul(&N, &S2, &a);
+    ob_mul(&S1, &S1, &b);
+    if (ob_sub(&a, &b)) return NAN;
+    double D = ob_to_double(&a), dn1 = (double)(n - 1), dS1 = ob_to_double(&S1);
+    double q = D / dn1;
+    double r = sqrt(q);
+    double u = t * r;
+    return u / dS1;
 }
 
 static uint64_t round_up(uint64_t x, uint64_t q) { return q ? (x + q - 1) / q * q : x; }

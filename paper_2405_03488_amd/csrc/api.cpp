@@ -709,13 +709,28 @@ double sgpm_host_predicted_error(double z, uint64_t n, const uint32_t* s1, int n
     return predicted_error(z, n, S1, S2);
 }
 
+double sgpm_host_t_quantile(double conf, int nu) { return student_t_quantile(conf, nu); }
+
+double sgpm_host_predicted_error_t(double t, uint64_t n, const uint32_t* s1, int n1, const uint32_t* s2, int n2) {
+    Big S1(24), S2(24);
+    for (int i = 0; i < n1 && i < 24; i++) S1.d[(size_t)i] = s1[i];
+    for (int i = 0; i < n2 && i < 24; i++) S2.d[(size_t)i] = s2[i];
+    return predicted_error_t(t, n, S1, S2);
+}
+
 uint64_t sgpm_host_next_window(uint64_t n_t, const sgpm_options* o) { return o ? next_window_end(n_t, *o) : 0; }
 
+int sgpm_host_colours_choice(int64_t m, int k, double leaves16) {
+    if (m < 0 || k < 2 || k > 8 || !(leaves16 >= 0)) return SGPM_EINVAL;
+    return (int)colours_from_probe(m, k, leaves16);
+}
+
 int sgpm_host_hybrid_choice(int slices, const double* slice_seconds, const double* slice_eps_hat, double eps,
-                            int gs_reps_run, double gs_rep_seconds, double gs_eps_hat2, int gs_reps_max,
+                            double confidence, int gs_reps_run, double gs_rep_seconds, double gs_cv, int gs_reps_max,
                             double* ns_lo, double* ns_hi, double* gs_pred) {
-    if (slices < 1 || !slice_seconds || !slice_eps_hat || !(eps > 0)) return SGPM_EINVAL;
-    return hybrid_choice(slices, slice_seconds, slice_eps_hat, eps, gs_reps_run, gs_rep_seconds, gs_eps_hat2,
+    if (slices < 1 || !slice_seconds || !slice_eps_hat || !(eps > 0) || !(confidence > 0 && confidence < 1))
+        return SGPM_EINVAL;
+    return hybrid_choice(slices, slice_seconds, slice_eps_hat, eps, confidence, gs_reps_run, gs_rep_seconds, gs_cv,
                          gs_reps_max, ns_lo, ns_hi, gs_pred);
 }
 

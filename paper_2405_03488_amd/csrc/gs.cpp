@@ -4,9 +4,14 @@
 // Sec. 5.2: the estimate from one colouring with c colours is c^(k-1) * Y for a
 // connected k-vertex pattern (all k vertices must share a colour), Y the exact
 // count on the sparsified graph.  The paper gives GS no online confidence
-// test; here independent colourings (rep = 0, 1, ...) are treated as i.i.d.
-// samples X_r = c^(k-1) Y_r and run through the same exact-integer statistics
-// and stop rule as NS (Sec. 4.1), capped at gs_reps_max colourings.
+// test; here independent colourings (rep = 0, 1, ...) are i.i.d. unbiased
+// estimates X_r = c^(k-1) Y_r whose exact sums give the mean and a Student t
+// interval: with few colourings the normal quantile and the 1/n variance of
+// the NS rule would give far too narrow an interval, so the predicted error is
+// t_{n-1} sqrt(D / (n - 1)) / S1 (unbiased variance, t quantile of n - 1
+// degrees of freedom).  Stop at the first n >= 3 with that at most eps (two
+// colourings of a small or skewed count often agree exactly, which would give
+// an interval of width zero), capped at gs_reps_max colourings.
 #include <cstdlib>
 #include <algorithm>
 #include <chrono>
@@ -172,17 +177,72 @@ sgpm_status gs_rep(sgpm_ctx* c, sgpm_graph* g, const Plan& p, uint32_t colours, 
     return st;
 }
 
-uint32_t gs_colours_for(const sgpm_options& o) { return o.colours > 0 ? (uint32_t)o.colours : 8u; }
+// colours = 0: choose c in 4..16 (Sec. 4.4, the colour-count figure, and
+// Sec. 5.2).  A colouring's time is sparsification (one pass over the arcs,
+// nearly independent of c) plus the exact search, whose leaves shrink as
+// c^-(k-1) (a match survives when its k vertices share a colour).  Past some c
+// the sparsification dominates and the time stops falling (the paper's
+// stabilisation window), so the fewest colours -- the largest keep probability,
+// hence the lowest variance -- inside that window are the best choice.  One
+// probe colouring at c = 16 (repetition id kColourProbeRep, outside the ids the
+// estimate uses) counts its leaves Y16; with the device rates of the two parts
+// (sparsification 1e11 arcs/s plus 0.3 ms of launches per colouring; the
+// search 3e9 leaves/s, measured 1.4e9 to 3.7e9 on a sparsified power-law
+// graph) a colouring at c is predicted to take 2m / 1e11 + 3e-4 +
+// Y16 (16 / c)^(k-1) / 3e9 seconds, and c is the smallest of 4, 5, 6, 8, 10,
+// 12, 16 predicted within 25 % of the time at 16.  The choice depends only on
+// the graph, the pattern and the seed, so runs repeat exactly.
+constexpr uint32_t kColourProbeRep = 0x3FFFFFFFu;
+
+uint32_t colours_from_probe(int64_t m, int k, double leaves16) {
+    static const uint32_t cands[] = {4, 5, 6, 8, 10, 12, 16};
+    const double t_sp = 2.0 * (double)m / 1e11 + 3e-4;
+    const double at16 = t_sp + leaves16 / 3e9;
+    for (uint32_t cc : cands)
+        if (t_sp + leaves16 * std::pow(16.0 / (double)cc, (double)(k - 1)) / 3e9 <= 1.25 * at16) return cc;
+    return 16;
+}
+
+sgpm_status gs_choose_colours(sgpm_ctx* c, sgpm_graph* g, const Plan& p, uint64_t seed, uint32_t* out) {
+    sgpm_graph* sp = nullptr;
+    sgpm_status st = sparsify(c, g, 16, seed, kColourProbeRep, &sp);
+    if (st != SGPM_OK) return st;
+    unsigned __int128 y = 0;
+    st = exact_count(c, sp, p, &y, nullptr);
+    sgpm_graph_free(sp);
+    if (st != SGPM_OK) return st;
+    *out = colours_from_probe(g->m, p.k, (double)y);
+    return SGPM_OK;
+}
+
+sgpm_status gs_resolve_colours(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_options& o, uint32_t* col) {
+    if (o.colours < 0 || o.colours > 256) return fail(c, SGPM_EINVAL, "colours must be 0 (choose) or in [1, 256]");
+    if (o.colours > 0) {
+        *col = (uint32_t)o.colours;
+        return SGPM_OK;
+    }
+    if (o.gs_scheme == SGPM_GS_BERNOULLI) {
+        *col = 8;  // the choice follows the colour scheme's survival law; Bernoulli takes c = 8
+        return SGPM_OK;
+    }
+    return gs_choose_colours(c, g, p, o.seed, col);
+}
 
 sgpm_status gs_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_options& o, sgpm_result* res,
                         const GsPrefix* pre) {
     auto t0 = std::chrono::steady_clock::now();
     std::memset(res, 0, sizeof(*res));
     res->scheme = SGPM_SCHEME_GS;
-    const uint32_t col = gs_colours_for(o);
-    if (col > 256) return fail(c, SGPM_EINVAL, "colours must be in [1, 256]");
+    uint32_t col = 0;
+    if (pre) {
+        col = (uint32_t)o.colours;  // the hybrid resolved it before its pilot colourings
+    } else {
+        sgpm_status st = gs_resolve_colours(c, g, p, o, &col);
+        if (st != SGPM_OK) return st;
+    }
+    if (col < 1 || col > 256) return fail(c, SGPM_EINVAL, "colours must be 0 (choose) or in [1, 256]");
     const int reps = o.gs_reps_max > 0 ? o.gs_reps_max : 64;
-    const double z = normal_quantile(1.0 - (1.0 - o.confidence) / 2.0);
+    double z = student_t_quantile(o.confidence, 1);
     // Bernoulli edge sparsification keeps every edge with probability 1/c, so
     // a match survives with c^-l (l pattern edges); it does not preserve
     // non-edges, so vertex-induced constraints are refused
@@ -231,8 +291,9 @@ sgpm_status gs_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_op
         big_add_digits(S2, d2, 8);
         n++;
         if (y) nonzero++;
-        const double eh = predicted_error(z, n, S1, S2);
-        if (n >= 2 && eh <= o.eps) {
+        if (n >= 2) z = student_t_quantile(o.confidence, (int)(n - 1));
+        const double eh = predicted_error_t(z, n, S1, S2);
+        if (n >= kGsMinReps && eh <= o.eps) {
             converged = true;
             break;
         }
@@ -242,7 +303,7 @@ sgpm_status gs_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_op
     for (int i = 0; i < 8; i++) res->sum_digits[i] = S1.d[(size_t)i];
     for (int i = 0; i < 12; i++) res->sumsq_digits[i] = S2.d[(size_t)i];
     res->estimate = big_to_double(S1) / (double)n;
-    res->eps_hat = predicted_error(z, n, S1, S2);
+    res->eps_hat = predicted_error_t(z, n, S1, S2);
     res->z = z;
     const double sigma = std::isfinite(res->eps_hat) ? res->estimate * res->eps_hat / z : INFINITY;
     res->ci_lo = res->estimate - z * sigma;

@@ -101,6 +101,80 @@ double normal_quantile(double p) {
     return (double)x;
 }
 
+// Regularised incomplete beta I_x(a, b) in extended precision: the continued
+// fraction of Abramowitz and Stegun 26.5.8, evaluated by the modified Lentz
+// method, on the side of the symmetry I_x(a, b) = 1 - I_{1-x}(b, a) where it
+// converges quickly (x < (a + 1) / (a + b + 2)).
+static long double incomplete_beta(long double x, long double a, long double b) {
+    if (x <= 0.0L) return 0.0L;
+    if (x >= 1.0L) return 1.0L;
+    if (x > (a + 1.0L) / (a + b + 2.0L)) return 1.0L - incomplete_beta(1.0L - x, b, a);
+    const long double tiny = 1e-4000L;
+    const long double lead =
+        expl(a * logl(x) + b * log1pl(-x) + lgammal(a + b) - lgammal(a) - lgammal(b)) / a;
+    long double f = 1.0L, C = 1.0L, D = 0.0L;
+    for (int i = 1; i < 100000; i++) {
+        const int m = i / 2;
+        long double d;
+        if (i % 2) d = -(a + m) * (a + b + m) * x / ((a + 2 * m) * (a + 2 * m + 1));
+        else d = m * (b - m) * x / ((a + 2 * m - 1) * (a + 2 * m));
+        D = 1.0L + d * D;
+        if (fabsl(D) < tiny) D = tiny;
+        C = 1.0L + d / C;
+        if (fabsl(C) < tiny) C = tiny;
+        D = 1.0L / D;
+        const long double step = C * D;
+        f *= step;
+        if (fabsl(step - 1.0L) < 1e-21L) break;
+    }
+    // the fraction's leading term 1 / (1 + d1 / (1 + ...)) with f = 1 + d1/(1 + ...)
+    return lead / f;
+}
+
+// Two-sided Student t quantile: t with P(|T| <= t) = conf for nu degrees of
+// freedom, where P(|T| <= t) = 1 - I_{nu / (nu + t^2)}(nu / 2, 1 / 2).  Newton's
+// method from the normal quantile, with the density 2 f(t) as the derivative,
+// kept inside a bracket that halves whenever a Newton step leaves it.
+double student_t_quantile(double conf, int nu) {
+    if (!(conf > 0.0 && conf < 1.0) || nu < 1) return NAN;
+    const long double v = nu, C = conf;
+    auto central = [&](long double t) { return 1.0L - incomplete_beta(v / (v + t * t), v / 2.0L, 0.5L); };
+    const long double logc = lgammal((v + 1.0L) / 2.0L) - lgammal(v / 2.0L) - 0.5L * logl(v * 3.14159265358979323846L);
+    auto dens2 = [&](long double t) { return 2.0L * expl(logc - (v + 1.0L) / 2.0L * log1pl(t * t / v)); };
+    long double lo = 0.0L, hi = 1.0L;
+    while (central(hi) < C) hi *= 2.0L;
+    long double t = normal_quantile(0.5 + conf / 2.0);
+    if (!(t > lo && t < hi)) t = 0.5L * (lo + hi);
+    for (int it = 0; it < 400; it++) {
+        const long double f = central(t) - C;
+        if (f < 0) lo = t; else hi = t;
+        long double nt = t - f / dens2(t);
+        if (!(nt > lo && nt < hi)) nt = 0.5L * (lo + hi);
+        if (nt == t || hi - lo <= 0.0L) break;
+        t = nt;
+    }
+    return (double)t;
+}
+
+// Predicted relative error of the mean of n i.i.d. values with the unbiased
+// sample variance: t * sqrt(D / (n - 1)) / S1, D = n S2 - S1^2 (exact); +inf
+// while n < 2 or S1 = 0.  The GS path's repeated sparsifications use it with
+// the Student t quantile of n - 1 degrees of freedom.
+double predicted_error_t(double t, uint64_t n, const Big& S1, const Big& S2) {
+    if (n < 2 || big_is_zero(S1)) return INFINITY;
+    Big N(S2.d.size());
+    N.d[0] = (uint32_t)n;
+    N.d[1] = (uint32_t)(n >> 32);
+    Big D = big_mul(N, S2);
+    Big S1sq = big_mul(S1, S1);
+    if (!big_sub(D, S1sq)) return NAN;
+    double dD = big_to_double(D), dn1 = (double)(n - 1), dS1 = big_to_double(S1);
+    double q = dD / dn1;
+    double r = std::sqrt(q);
+    double u = t * r;
+    return u / dS1;
+}
+
 double predicted_error(double z, uint64_t n, const Big& S1, const Big& S2) {
     if (n == 0 || big_is_zero(S1)) return INFINITY;
     Big N(S2.d.size());

@@ -14,9 +14,11 @@
 //    eps scale as (eps_hat / eps)^2, so slice i predicts t_i (eps_hat_i / eps)^2
 //    with t_i its kernel time; the slices' minimum and maximum are the cone.
 //  * GS: colourings 0 and 1 of the GS engine itself (timed end to end:
-//    sparsification and count).  Their predicted error gives the colourings
-//    needed, R = max(2, ceil(2 (eps_hat_2 / eps)^2)), and the prediction is R
-//    times the mean colouring time.  When one colouring already takes half the
+//    sparsification and count).  Their relative spread (the unbiased standard
+//    deviation of one colouring's estimate over their mean, cv) gives the
+//    colourings needed under the GS stop rule: the smallest R >= 3 with
+//    t_{R-1} cv / sqrt(R) <= eps (t the two-sided Student t quantile), and the
+//    prediction is R times the mean colouring time.  When one colouring already takes half the
 //    cone's lower end GS cannot lie below it and the second is skipped.  Before
 //    any colouring, the NS pilot's estimate C bounds GS from below: one
 //    colouring's search reaches about C / c^(k-1) leaves, and two colourings at
@@ -38,8 +40,18 @@
 
 namespace sgpm {
 
-int hybrid_choice(int slices, const double* slice_seconds, const double* slice_eps_hat, double eps, int gs_reps_run,
-                  double gs_rep_seconds, double gs_eps_hat2, int gs_reps_max, double* ns_lo, double* ns_hi,
+// colourings the GS stop rule needs when one colouring's estimate has relative
+// standard deviation cv: the smallest R in [3, cap] with t_{R-1} cv / sqrt(R)
+// <= eps, or 0 when none is
+int gs_reps_needed(double cv, double eps, double confidence, int cap) {
+    if (!std::isfinite(cv) || !(eps > 0)) return 0;
+    for (int R = (int)kGsMinReps; R <= cap; R++)
+        if (student_t_quantile(confidence, R - 1) * cv / std::sqrt((double)R) <= eps) return R;
+    return 0;
+}
+
+int hybrid_choice(int slices, const double* slice_seconds, const double* slice_eps_hat, double eps, double confidence,
+                  int gs_reps_run, double gs_rep_seconds, double gs_cv, int gs_reps_max, double* ns_lo, double* ns_hi,
                   double* gs_pred) {
     double lo = INFINITY, hi = 0.0;
     for (int i = 0; i < slices; i++) {
@@ -50,12 +62,8 @@ int hybrid_choice(int slices, const double* slice_seconds, const double* slice_e
     }
     double gs = INFINITY;
     if (gs_reps_run >= 2) {
-        if (std::isfinite(gs_eps_hat2)) {
-            const double r = gs_eps_hat2 / eps;
-            const double need = std::max(2.0, std::ceil(2.0 * r * r));
-            const double cap = gs_reps_max > 0 ? (double)gs_reps_max : 64.0;
-            if (need <= cap) gs = need * gs_rep_seconds;
-        }
+        const int need = gs_reps_needed(gs_cv, eps, confidence, gs_reps_max > 0 ? gs_reps_max : 64);
+        if (need > 0) gs = need * gs_rep_seconds;
     } else if (gs_reps_run == 1) {
         gs = 2.0 * gs_rep_seconds;  // a lower bound: GS needs two colourings at least
     }
@@ -68,13 +76,19 @@ int hybrid_choice(int slices, const double* slice_seconds, const double* slice_e
 
 namespace {
 
-// predicted relative error of the first two colourings' values c^(k-1) y_r
-double gs_pilot_error(const GsPrefix& pre, const Plan& p, uint32_t col, double z) {
+// relative standard deviation of one colouring's estimate c^(k-1) y_r from the
+// pilot colourings (unbiased variance over the squared mean); +inf when their
+// values are all zero or c^(k-1) y_r leaves 128 bits (then GS is not usable)
+double gs_pilot_cv(const GsPrefix& pre, const Plan& p, uint32_t col) {
     unsigned __int128 scale = 1;
-    for (int i = 0; i < p.k - 1; i++) scale *= col;
+    for (int i = 0; i < p.k - 1; i++) {
+        if (scale > ~(unsigned __int128)0 / col) return INFINITY;
+        scale *= col;
+    }
     Big S1(24), S2(24);
     for (int r = 0; r < pre.n; r++) {
         const unsigned __int128 x = pre.y[r] * scale;
+        if (x / scale != pre.y[r]) return INFINITY;
         unsigned long long d1[4], d2[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         for (int i = 0; i < 4; i++) d1[i] = (unsigned long long)(uint32_t)(x >> (32 * i));
         for (int a = 0; a < 4; a++)
@@ -86,7 +100,7 @@ double gs_pilot_error(const GsPrefix& pre, const Plan& p, uint32_t col, double z
         big_add_digits(S1, d1, 4);
         big_add_digits(S2, d2, 8);
     }
-    return predicted_error(z, (uint64_t)pre.n, S1, S2);
+    return std::sqrt((double)pre.n) * predicted_error_t(1.0, (uint64_t)pre.n, S1, S2);
 }
 
 }  // namespace
@@ -104,8 +118,11 @@ sgpm_status hybrid_estimate(sgpm_ctx* c, sgpm_graph* g, sgpm_pattern* pat, const
     double ns_lo = INFINITY, ns_hi = INFINITY, gs_pred = INFINITY;
     int scheme = SGPM_SCHEME_NS;
     GsPrefix pre;
-    const uint32_t col = gs_colours_for(o);
-    if (col < 1 || col > 256) return fail(c, SGPM_EINVAL, "colours must be in [1, 256]");
+    uint32_t col = 0;
+    {
+        sgpm_status st = gs_resolve_colours(c, g, p, o, &col);
+        if (st != SGPM_OK) return st;
+    }
     if (M > 0) {
         // NS pilot on its own stream of draws
         constexpr int kSlices = 4;
@@ -118,14 +135,14 @@ sgpm_status hybrid_estimate(sgpm_ctx* c, sgpm_graph* g, sgpm_pattern* pat, const
         double sec[kSlices], eh[kSlices], mu = 0.0;
         sgpm_status st = ns_pilot(c, g, p, po, ex.la, n_pilot, kSlices, sec, eh, &mu);
         if (st != SGPM_OK) return st;
-        (void)hybrid_choice(kSlices, sec, eh, o.eps, 0, 0.0, 0.0, o.gs_reps_max, &ns_lo, &ns_hi, nullptr);
+        (void)hybrid_choice(kSlices, sec, eh, o.eps, o.confidence, 0, 0.0, 0.0, o.gs_reps_max, &ns_lo, &ns_hi,
+                            nullptr);
         // lower bound of two colourings from the leaves they must reach
         double leaves = mu;
         for (int i = 0; i < p.k - 1; i++) leaves /= (double)col;
         const double sparse_deg = g->n > 0 ? 2.0 * (double)g->m / ((double)g->n * (double)col) : 0.0;
         const double gs_floor = 2.0 * leaves / (sparse_deg < 16.0 ? 1e10 : 1e11);
         // GS pilot: the GS engine's first colourings, timed end to end
-        const double z = normal_quantile(1.0 - (1.0 - o.confidence) / 2.0);
         double rep_seconds = 0.0;
         for (int r = 0; r < 2 && gs_floor < ns_lo; r++) {
             const auto a = clk::now();
@@ -141,15 +158,17 @@ sgpm_status hybrid_estimate(sgpm_ctx* c, sgpm_graph* g, sgpm_pattern* pat, const
             gs_pred = gs_floor;  // a lower bound; GS was not run
         } else {
             rep_seconds /= pre.n;
-            const double e2 = pre.n >= 2 ? gs_pilot_error(pre, p, col, z) : INFINITY;
-            scheme = hybrid_choice(kSlices, sec, eh, o.eps, pre.n, rep_seconds, e2, o.gs_reps_max, &ns_lo, &ns_hi,
-                                   &gs_pred);
+            const double cv = pre.n >= 2 ? gs_pilot_cv(pre, p, col) : INFINITY;
+            scheme = hybrid_choice(kSlices, sec, eh, o.eps, o.confidence, pre.n, rep_seconds, cv, o.gs_reps_max,
+                                   &ns_lo, &ns_hi, &gs_pred);
         }
     }
     const double pilot = std::chrono::duration<double>(clk::now() - t0).count();
     sgpm_status st;
     if (scheme == SGPM_SCHEME_GS) {
-        st = gs_estimate(c, g, p, o, res, &pre);
+        sgpm_options go = o;
+        go.colours = (int32_t)col;
+        st = gs_estimate(c, g, p, go, res, &pre);
     } else {
         sgpm_options no = o;
         no.mode = SGPM_MODE_STRICT_NS;

@@ -343,16 +343,20 @@ __device__ __forceinline__ uint32_t ns_sample(const DGraph& g, const Plan& p, ui
                 dp = rp[i];
             }
         if (count_bytes) {
+            // 16 per newly opened row, 4 per entry inside (lo, hi) of every row
+            // the step merges (connected and, vertex-induced, disconnected)
             const uint32_t rows = conn | disc;
 #pragma unroll
             for (int i = 0; i < j; ++i)
-                if ((rows >> i & 1) && !(opened >> i & 1)) {
-                    bytes += 16;
-                    opened |= 1u << i;
+                if (rows >> i & 1) {
+                    if (!(opened >> i & 1)) {
+                        bytes += 16;
+                        opened |= 1u << i;
+                    }
+                    const int32_t w0 = lo >= 0 ? lower_bound(rp[i], 0, rl[i], lo + 1) : 0;
+                    const int32_t w1 = hi < BIG ? lower_bound(rp[i], w0, rl[i], hi) : rl[i];
+                    bytes += 4ull * (uint64_t)(w1 - w0);
                 }
-            const int32_t w0 = lo >= 0 ? lower_bound(dp, 0, dl, lo + 1) : 0;
-            const int32_t w1 = hi < BIG ? lower_bound(dp, w0, dl, hi) : dl;
-            bytes += 4ull * (uint64_t)(w1 - w0);
         }
         // Reuse: when step j's constraints contain step j-1's, S_j is the part
         // of S_{j-1} (already in `list`) that meets the extra constraints.

@@ -149,6 +149,8 @@ double big_to_double(const Big& a);
 bool big_is_zero(const Big& a);
 double normal_quantile(double p);
 double predicted_error(double z, uint64_t n, const Big& S1, const Big& S2);
+double student_t_quantile(double conf, int nu);
+double predicted_error_t(double t, uint64_t n, const Big& S1, const Big& S2);
 uint64_t next_window_end(uint64_t n_t, const sgpm_options& o);
 
 // GS kernels (gs_kernels.hip)
@@ -259,7 +261,8 @@ struct GsPrefix {              // colourings 0..n-1 already counted (hybrid pilo
 };
 sgpm_status gs_rep(sgpm_ctx* c, sgpm_graph* g, const Plan& p, uint32_t colours, uint64_t seed, uint32_t rep,
                    unsigned __int128* y, double* dev_seconds, bool bes = false);
-uint32_t gs_colours_for(const sgpm_options& o);
+uint32_t colours_from_probe(int64_t m, int k, double leaves16);
+sgpm_status gs_resolve_colours(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_options& o, uint32_t* col);
 sgpm_status gs_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_options& o, sgpm_result* res,
                         const GsPrefix* pre = nullptr);
 sgpm_status ns_estimate_solo(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_options& o, sgpm_result* res,
@@ -271,9 +274,12 @@ sgpm_status ns_pilot(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_optio
                      uint64_t n, int slices, double* seconds, double* eps_hat, double* mean);
 sgpm_status learn_args_for(sgpm_ctx* c, sgpm_graph* g, sgpm_pattern* p, sgpm_model* m, LearnArgs* la);
 sgpm_status hybrid_estimate(sgpm_ctx* c, sgpm_graph* g, sgpm_pattern* p, const sgpm_options& o, sgpm_result* res);
-int hybrid_choice(int slices, const double* slice_seconds, const double* slice_eps_hat, double eps, int gs_reps_run,
-                  double gs_rep_seconds, double gs_eps_hat2, int gs_reps_max, double* ns_lo, double* ns_hi,
+int hybrid_choice(int slices, const double* slice_seconds, const double* slice_eps_hat, double eps, double confidence,
+                  int gs_reps_run, double gs_rep_seconds, double gs_cv, int gs_reps_max, double* ns_lo, double* ns_hi,
                   double* gs_pred);
+int gs_reps_needed(double cv, double eps, double confidence, int cap);
+// the GS stop rule tests its interval from the third sparsification on
+constexpr uint64_t kGsMinReps = 3;
 
 inline sgpm_status fail(sgpm_ctx* c, sgpm_status s, const std::string& msg) {
     if (c) c->err = msg;

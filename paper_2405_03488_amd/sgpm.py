@@ -132,8 +132,11 @@ def lib():
             "sgpm_host_normal_quantile": ([C.c_double], C.c_double),
             "sgpm_host_predicted_error": ([C.c_double, C.c_uint64, P, C.c_int, P, C.c_int], C.c_double),
             "sgpm_host_next_window": ([C.c_uint64, C.POINTER(Options)], C.c_uint64),
-            "sgpm_host_hybrid_choice": ([C.c_int, P, P, C.c_double, C.c_int, C.c_double, C.c_double, C.c_int, P, P,
-                                         P], C.c_int),
+            "sgpm_host_t_quantile": ([C.c_double, C.c_int], C.c_double),
+            "sgpm_host_colours_choice": ([C.c_int64, C.c_int, C.c_double], C.c_int),
+            "sgpm_host_predicted_error_t": ([C.c_double, C.c_uint64, P, C.c_int, P, C.c_int], C.c_double),
+            "sgpm_host_hybrid_choice": ([C.c_int, P, P, C.c_double, C.c_double, C.c_int, C.c_double, C.c_double,
+                                         C.c_int, P, P, P], C.c_int),
         }
         for name, (args, res) in sig.items():
             if hasattr(L, name):
@@ -152,7 +155,7 @@ EXPORTED = ["sgpm_create", "sgpm_destroy", "sgpm_last_error", "sgpm_device_count
             "sgpm_model_from_tables", "sgpm_model_table", "sgpm_model_info", "sgpm_mlp_forward", "sgpm_mlp_grad",
             "sgpm_mlp_adam_steps",
             "sgpm_probe_copy", "sgpm_probe_gather", "sgpm_probe_mlp", "sgpm_host_canonicalise", "sgpm_host_plan", "sgpm_host_normal_quantile", "sgpm_host_predicted_error",
-            "sgpm_host_next_window", "sgpm_host_hybrid_choice"]
+            "sgpm_host_t_quantile", "sgpm_host_predicted_error_t", "sgpm_host_colours_choice", "sgpm_host_next_window", "sgpm_host_hybrid_choice"]
 
 
 class SgpmError(RuntimeError):
@@ -350,18 +353,32 @@ def sgpm_host_predicted_error(z, n, S1: int, S2: int):
     return float(lib().sgpm_host_predicted_error(z, n, d1.ctypes.data, 8, d2.ctypes.data, 12))
 
 
+def sgpm_host_t_quantile(conf, nu):
+    return float(lib().sgpm_host_t_quantile(conf, nu))
+
+
+def sgpm_host_predicted_error_t(t, n, S1: int, S2: int):
+    d1 = np.array([(S1 >> (32 * i)) & 0xFFFFFFFF for i in range(8)], dtype=np.uint32)
+    d2 = np.array([(S2 >> (32 * i)) & 0xFFFFFFFF for i in range(12)], dtype=np.uint32)
+    return float(lib().sgpm_host_predicted_error_t(t, n, d1.ctypes.data, 8, d2.ctypes.data, 12))
+
+
+def sgpm_host_colours_choice(m, k, leaves16):
+    return int(lib().sgpm_host_colours_choice(m, k, leaves16))
+
+
 def sgpm_host_next_window(n_t, opts: Options):
     return int(lib().sgpm_host_next_window(n_t, C.byref(opts)))
 
 
-def sgpm_host_hybrid_choice(slice_seconds, slice_eps_hat, eps, gs_reps_run, gs_rep_seconds, gs_eps_hat2,
-                            gs_reps_max=64):
+def sgpm_host_hybrid_choice(slice_seconds, slice_eps_hat, eps, gs_reps_run, gs_rep_seconds, gs_cv,
+                            gs_reps_max=64, confidence=0.95):
     """(scheme, ns_lo, ns_hi, gs_pred) from pilot figures; see include/sgpm.h."""
     sec = np.ascontiguousarray(slice_seconds, dtype=np.float64)
     eh = np.ascontiguousarray(slice_eps_hat, dtype=np.float64)
     lo, hi, gs = C.c_double(), C.c_double(), C.c_double()
-    rc = lib().sgpm_host_hybrid_choice(len(sec), sec.ctypes.data, eh.ctypes.data, eps, gs_reps_run, gs_rep_seconds,
-                                       gs_eps_hat2, gs_reps_max, C.byref(lo), C.byref(hi), C.byref(gs))
+    rc = lib().sgpm_host_hybrid_choice(len(sec), sec.ctypes.data, eh.ctypes.data, eps, confidence, gs_reps_run,
+                                       gs_rep_seconds, gs_cv, gs_reps_max, C.byref(lo), C.byref(hi), C.byref(gs))
     if rc < 0:
         raise SgpmError(rc, "invalid hybrid pilot figures")
     return rc, lo.value, hi.value, gs.value

@@ -107,7 +107,10 @@ def test_gs_estimate_matches_oracle(S, O, synth, ctx, cl, name, c):
     orr, ys = O.gs_run(og, O.compile_plan(k, e), c, 17, eps=0.05, confidence=0.95, reps_max=40)
     assert r.scheme == S.SCHEME_GS and r.colours == c
     assert r.n_samples == orr.reps and r.S1 == orr.S1 and r.S2 == orr.S2
-    assert r.estimate == orr.estimate and r.eps_hat == orr.eps_hat
+    assert r.estimate == orr.estimate
+    # the t quantile is computed by different methods on the two sides and may
+    # round one unit in the last place apart
+    assert r.eps_hat == pytest.approx(orr.eps_hat, rel=1e-15, abs=0) and r.z == pytest.approx(orr.z, rel=1e-15)
     assert r.converged == orr.converged
     assert (rc == S.SGPM_OK) == bool(orr.converged)
     S.sgpm_pattern_free(p)
@@ -208,7 +211,8 @@ def test_bes_estimate_matches_oracle(S, O, synth, ctx, cl, name, c):
     orr, ys = O.bes_run(og, O.compile_plan(k, e), c, 23, eps=0.05, confidence=0.95, reps_max=30)
     assert r.scheme == S.SCHEME_GS and r.colours == c
     assert r.n_samples == orr.reps and r.S1 == orr.S1 and r.S2 == orr.S2
-    assert r.estimate == orr.estimate and r.eps_hat == orr.eps_hat and r.converged == orr.converged
+    assert r.estimate == orr.estimate and r.converged == orr.converged
+    assert r.eps_hat == pytest.approx(orr.eps_hat, rel=1e-15, abs=0)
     S.sgpm_pattern_free(p)
 
 

@@ -74,10 +74,10 @@ def test_hybrid_picks_gs_for_rare_matches(S, O, synth, ctx):
     p = S.sgpm_pattern_create(ctx, k, e)
     exact = O.plan_count(og, O.compile_plan(k, e))
     assert exact >= 8
-    # one colour: GS is the exact count, so two identical colourings converge
+    # one colour: GS is the exact count, so three identical colourings converge (the rule starts at three)
     rh = run_pair(S, ctx, g, p, eps=0.02, seed=9, checksum=1, colours=1)
     assert rh.scheme == S.SCHEME_GS and rh.converged == 1
-    assert rh.estimate == exact and rh.n_samples == 2
+    assert rh.estimate == exact and rh.n_samples == 3
     S.sgpm_pattern_free(p)
     S.sgpm_graph_free(g)
 

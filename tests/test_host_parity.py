@@ -1,5 +1,7 @@
 """Host parts of the library (graph loader, pattern compiler, statistics,
 window schedule) against the oracle, bit for bit, on the CPU."""
+import math
+
 import numpy as np
 import pytest
 
@@ -103,6 +105,35 @@ def test_predicted_error_bit_exact(S, O):
             continue
         assert S.sgpm_host_predicted_error(z, n, S1, S2) == O.eps_hat(z, n, S1, S2)
     assert S.sgpm_host_predicted_error(z, 10, 0, 0) == float("inf")
+
+
+def test_t_quantile_matches_oracle(S, O):
+    """The GS rule's Student t quantile: the library (incomplete beta, Newton)
+    and the oracle (closed-form CDF, bisection) each work in extended
+    precision and round to double; where the exact value lies near the
+    midpoint of two doubles they may round apart, by one unit in the last
+    place at most."""
+    same = total = 0
+    for nu in range(1, 130):
+        for conf in (0.8, 0.9, 0.95, 0.99, 0.999):
+            a, b = S.sgpm_host_t_quantile(conf, nu), O.t_ppf(conf, nu)
+            assert a == b or math.nextafter(a, b) == b, (nu, conf, a, b)
+            same += a == b
+            total += 1
+    assert same >= 0.9 * total
+    assert math.isnan(S.sgpm_host_t_quantile(0.95, 0)) and math.isnan(S.sgpm_host_t_quantile(1.0, 3))
+
+
+def test_predicted_error_t_bit_exact(S, O):
+    rng = np.random.default_rng(12)
+    for _ in range(300):
+        n = int(rng.integers(2, 70))
+        xs = [int(x) for x in rng.integers(0, 2**62, size=n)] if rng.random() < 0.5 else \
+             [int(x) << int(rng.integers(0, 60)) for x in rng.integers(0, 1000, size=n)]
+        S1, S2 = sum(xs), sum(x * x for x in xs)
+        t = O.t_ppf(0.95, n - 1)
+        assert S.sgpm_host_predicted_error_t(t, n, S1, S2) == O.eps_hat_t(t, n, S1, S2)
+    assert S.sgpm_host_predicted_error_t(12.7, 1, 5, 25) == float("inf")
 
 
 def test_window_schedule_matches_oracle(S, O):

@@ -2,13 +2,23 @@
 NS prediction checked with the oracle.
 
 The rule: each NS pilot slice predicts t_i (eps_hat_i / eps)^2 and the slices'
-minimum and maximum form the NS cone; two GS pilot colourings predict
-R = max(2, ceil(2 (eps_hat_2 / eps)^2)) colourings at the mean colouring time;
+minimum and maximum form the NS cone; two GS pilot colourings with relative
+spread cv predict the smallest R >= 3 with t_{R-1} cv / sqrt(R) <= eps
+colourings (the GS stop rule's Student t interval) at the mean colouring time;
 GS runs only when its prediction lies entirely below the cone."""
 import math
 
 import numpy as np
 import pytest
+from scipy import stats
+
+
+def _reps(cv, eps, cap, conf=0.95):
+    """Colourings the GS stop rule needs, by scipy's t quantile."""
+    for R in range(3, cap + 1):
+        if stats.t.ppf(0.5 + conf / 2, R - 1) * cv / math.sqrt(R) <= eps:
+            return R
+    return None
 
 
 @pytest.fixture(scope="module")
@@ -20,26 +30,28 @@ def S():
 def test_cone_from_slices(S):
     sc, lo, hi, gs = S.sgpm_host_hybrid_choice([1e-3, 2e-3, 1e-3, 1e-3], [0.1, 0.1, 0.2, 0.05], 0.01, 2, 0.5, 0.0)
     assert lo == pytest.approx(1e-3 * 25) and hi == pytest.approx(1e-3 * 400)
-    assert gs == pytest.approx(1.0)  # two colourings suffice when they agree exactly
-    assert sc == S.SCHEME_NS  # 1.0 s is above the cone's lower end 0.025 s
+    assert gs == pytest.approx(1.5)  # three colourings (the rule's minimum) when they agree exactly
+    assert sc == S.SCHEME_NS  # 1.5 s is above the cone's lower end 0.025 s
 
 
 def test_gs_below_cone_selects_gs(S):
     sc, lo, hi, gs = S.sgpm_host_hybrid_choice([0.01] * 4, [1.0, 2.0, 1.5, 1.2], 0.01, 2, 0.2, 0.03)
-    # R = ceil(2 * 3^2) = 18 colourings of 0.2 s
-    assert gs == pytest.approx(18 * 0.2)
+    R = _reps(0.03, 0.01, 64)
+    assert 36 < R < 64 and gs == pytest.approx(R * 0.2)
     assert lo == pytest.approx(0.01 * 1e4) and sc == S.SCHEME_GS
 
 
 def test_overlap_and_above_select_ns(S):
     # GS inside the cone: NS keeps the guarantee
     sc, lo, hi, gs = S.sgpm_host_hybrid_choice([1.0, 1.0], [0.01, 0.02], 0.01, 2, 1.5, 0.0)
-    assert lo == 1.0 and hi == 4.0 and gs == 3.0 and sc == S.SCHEME_NS
+    assert lo == 1.0 and hi == 4.0 and gs == 4.5 and sc == S.SCHEME_NS
     # GS above the cone
     sc, *_ = S.sgpm_host_hybrid_choice([1.0, 1.0], [0.01, 0.02], 0.01, 2, 10.0, 0.0)
     assert sc == S.SCHEME_NS
     # exactly at the lower end is not below it
-    sc, *_ = S.sgpm_host_hybrid_choice([1.0], [0.01], 0.01, 2, 0.5, 0.0)
+    assert 3 * (1 / 3) == 1.0
+    sc, lo, hi, gs = S.sgpm_host_hybrid_choice([1.0], [0.01], 0.01, 2, 1 / 3, 0.0)
+    assert gs == lo
     assert sc == S.SCHEME_NS
 
 
@@ -62,8 +74,12 @@ def test_missing_hits_and_caps(S):
     # more colourings than gs_reps_max: GS cannot meet eps
     sc, lo, hi, gs = S.sgpm_host_hybrid_choice([1.0], [10.0], 0.01, 2, 1e-6, 0.2, 64)
     assert math.isinf(gs) and sc == S.SCHEME_NS
-    sc, lo, hi, gs = S.sgpm_host_hybrid_choice([1.0], [10.0], 0.01, 2, 1e-6, 0.2, 1000)
-    assert gs == pytest.approx(800 * 1e-6) and sc == S.SCHEME_GS
+    sc, lo, hi, gs = S.sgpm_host_hybrid_choice([1.0], [10.0], 0.01, 2, 1e-6, 0.2, 4000)
+    R = _reps(0.2, 0.01, 4000)
+    assert R > 1000 and gs == pytest.approx(R * 1e-6) and sc == S.SCHEME_GS
+    # a stricter confidence needs more colourings
+    sc, lo, hi, gs99 = S.sgpm_host_hybrid_choice([1.0], [10.0], 0.01, 2, 1e-6, 0.2, 4000, confidence=0.99)
+    assert gs99 == pytest.approx(_reps(0.2, 0.01, 4000, 0.99) * 1e-6) and gs99 > gs
 
 
 def test_invalid_arguments(S):
@@ -71,6 +87,8 @@ def test_invalid_arguments(S):
         S.sgpm_host_hybrid_choice([], [], 0.01, 2, 1.0, 0.0)
     with pytest.raises(S.SgpmError):
         S.sgpm_host_hybrid_choice([1.0], [1.0], 0.0, 2, 1.0, 0.0)
+    with pytest.raises(S.SgpmError):
+        S.sgpm_host_hybrid_choice([1.0], [1.0], 0.01, 2, 1.0, 0.0, confidence=1.0)
 
 
 @pytest.mark.parametrize("name,eps", [("triangle", 0.02), ("4-cycle", 0.005)])
@@ -95,3 +113,31 @@ def test_pilot_scaling_predicts_the_stop_point(O, synth, name, eps):
     assert full.converged == 1
     assert 0.5 * predicted <= full.n <= 2.0 * predicted, (predicted, full.n)
     assert z == pilot.z
+
+
+def test_colour_choice_window(S):
+    """colours = 0: the fewest colours whose predicted colouring time is within
+    25 % of the time at 16 colours (Sec. 4.4 stabilisation window).  A colouring
+    costs 2m / 1e11 + 3e-4 s of sparsification plus leaves16 (16 / c)^(k-1) / 3e9
+    s of search."""
+    def model(m, k, y16):
+        sp = 2 * m / 1e11 + 3e-4
+        at16 = sp + y16 / 3e9
+        for c in (4, 5, 6, 8, 10, 12, 16):
+            if sp + y16 * (16 / c) ** (k - 1) / 3e9 <= 1.25 * at16:
+                return c
+        return 16
+    # no leaves: the search costs nothing, four colours keep the most matches
+    assert S.sgpm_host_colours_choice(10**7, 4, 0.0) == 4
+    # a search far dearer than the sparsification: as many colours as allowed
+    assert S.sgpm_host_colours_choice(10**6, 5, 1e12) == 16
+    for m in (10**5, 10**7, 10**9):
+        for k in (3, 4, 5, 6):
+            for y in (0.0, 1e3, 1e5, 1e7, 1e9):
+                assert S.sgpm_host_colours_choice(m, k, y) == model(m, k, y), (m, k, y)
+    # more leaves never choose fewer colours
+    for k in (3, 5):
+        cs = [S.sgpm_host_colours_choice(10**7, k, y) for y in np.logspace(0, 12, 40)]
+        assert cs == sorted(cs)
+    assert S.sgpm_host_colours_choice(10, 9, 1.0) == S.SGPM_EINVAL
+    assert S.sgpm_host_colours_choice(10, 4, -1.0) == S.SGPM_EINVAL

@@ -68,4 +68,5 @@ def test_c1_is_exact(O, synth):
     p = O.compile_plan(k, e)
     want = O.plan_count(g, p)
     r, ys = O.bes_run(g, p, 1, 3, eps=0.01, reps_max=5)
-    assert ys[:2] == [want, want] and r.reps == 2 and r.converged == 1 and r.estimate == want
+    # c = 1 keeps every edge: each repetition is exact and the rule stops at its third
+    assert ys == [want] * 3 and r.reps == 3 and r.converged == 1 and r.estimate == want

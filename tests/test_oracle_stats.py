@@ -113,3 +113,120 @@ def test_big_integer_to_double_is_correctly_rounded(O):
         cases.append(int.from_bytes(rng.bytes(88), "little") >> (704 - bits))
     for x in cases:
         assert O.digits_to_double(x) == float(x), x
+
+
+def _mp_t_quantile(conf, nu):
+    """Two-sided t quantile from the regularised incomplete beta in 40-digit
+    arithmetic: P(|T| <= t) = 1 - I_{nu/(nu+t^2)}(nu/2, 1/2), solved by bisection."""
+    import mpmath as mp
+    mp.mp.dps = 40
+    f = lambda t: 1 - mp.betainc(mp.mpf(nu) / 2, mp.mpf(1) / 2, 0, nu / (nu + t * t), regularized=True) - conf
+    lo, hi = mp.mpf(0), mp.mpf(1)
+    while f(hi) < 0:
+        hi *= 2
+    for _ in range(200):
+        mid = (lo + hi) / 2
+        if f(mid) < 0:
+            lo = mid
+        else:
+            hi = mid
+    return (lo + hi) / 2
+
+
+@pytest.mark.parametrize("nu", [1, 2, 3, 4, 5, 8, 13, 30, 63, 100])
+def test_t_ppf_against_high_precision(O, nu):
+    """The GS interval's Student t quantile (closed-form CDF for integer
+    degrees of freedom) against 40-digit arithmetic and scipy."""
+    from scipy import stats
+    for conf in [0.5, 0.9, 0.95, 0.99]:
+        want = _mp_t_quantile(conf, nu)
+        got = O.t_ppf(conf, nu)
+        assert abs(got - float(want)) <= 2e-16 * float(want), (nu, conf)
+        assert abs(got - stats.t.ppf(0.5 + conf / 2, nu)) <= 1e-9 * got
+    # textbook values: t_1(0.975) = tan(0.475 pi), t_2(0.975) = 4.302652729...
+    assert abs(O.t_ppf(0.95, 1) - math.tan(0.475 * math.pi)) < 1e-13
+    # t approaches the normal quantile
+    assert O.t_ppf(0.95, 5000) > O.norm_ppf(0.975) and O.t_ppf(0.95, 5000) - O.norm_ppf(0.975) < 1e-3
+
+
+@pytest.mark.parametrize("case", [
+    [1, 2, 3, 4, 5],
+    [0, 0, 7, 0, 9],
+    [10**20, 3 * 10**20, 5 * 10**19],
+    [2**100 + 17, 2**99, 2**101],
+])
+def test_eps_hat_t_is_unbiased_standard_error(O, case):
+    """t * s / sqrt(n) / mean with s^2 the unbiased sample variance, in 60-digit decimals."""
+    getcontext().prec = 60
+    n = len(case)
+    mean = Decimal(sum(case)) / n
+    s2 = sum((Decimal(x) - mean) ** 2 for x in case) / (n - 1)
+    t = 2.7764451051977987
+    want = float(Decimal(t) * (s2 / n).sqrt() / mean)
+    got = O.eps_hat_t(t, n, sum(case), sum(x * x for x in case))
+    assert abs(got - want) <= 1e-13 * want
+    assert O.eps_hat_t(t, 1, 5, 25) == float("inf")
+    assert O.eps_hat_t(t, 3, 0, 0) == float("inf")
+
+
+def test_gs_sums_beyond_32_bits(O, synth):
+    """GS repetition statistics with X_r = c^(k-1) Y_r far above 2^32: the
+    oracle's digit sums equal Python big-integer sums of its per-colouring
+    counts, and its interval is the t interval of those values."""
+    n = 140
+    g = O.OGraph.from_pairs(n, synth.complete_pairs(n))
+    k, e = synth.pattern("6-clique")
+    p = O.compile_plan(k, e)
+    c = 4
+    r, ys = O.gs_run(g, p, c, 5, eps=-1.0, reps_max=6)  # eps < 0: never stops early
+    xs = [y * c ** (k - 1) for y in ys]
+    assert r.reps == 6 and min(xs) > 2**32 and len(set(xs)) > 1
+    assert r.S1 == sum(xs) and r.S2 == sum(x * x for x in xs)
+    t = O.t_ppf(0.95, 5)
+    assert r.z == t
+    assert r.eps_hat == O.eps_hat_t(t, 6, sum(xs), sum(x * x for x in xs))
+    assert r.estimate == O.digits_to_double(sum(xs)) / 6
+
+
+def _gs_coverage(O, g, p, C, c, eps, seeds):
+    """Among converged GS runs: (runs, count inside the interval)."""
+    runs = inside = 0
+    for seed in seeds:
+        r, _ = O.gs_run(g, p, c, seed, eps=eps, reps_max=64, threads=1)
+        if r.converged:
+            runs += 1
+            half = r.estimate * r.eps_hat
+            inside += abs(r.estimate - C) <= half
+    return runs, inside
+
+
+def test_gs_interval_coverage(O, synth):
+    """The GS stop rule (Student t interval, unbiased variance, tested from the
+    third colouring on) on a light-tailed count: among 100 seeds the exact
+    count lies inside the reported 95 % interval in at least 85 (binomial:
+    mean 95, sd 2.2 at the nominal rate; optional stopping costs a few).  The
+    normal quantile with the 1/n variance and a test from the second colouring
+    on, applied to the same colourings, falls far short -- which is why the
+    rule changed."""
+    n = 1500
+    g = O.OGraph.from_raw_csr(n, *synth.pairs_to_csr(n, synth.chung_lu_pairs(n, 10, 2.1, 3)))
+    k, e = synth.pattern("triangle")
+    p = O.compile_plan(k, e)
+    C = O.plan_count(g, p)
+    runs, inside = _gs_coverage(O, g, p, C, 2, 0.1, range(100))
+    assert runs >= 98 and inside >= 85, (runs, inside)
+    # the former rule on the same colourings
+    z = O.norm_ppf(0.975)
+    old_in = 0
+    for seed in range(100):
+        _, ys = O.gs_run(g, p, 2, seed, eps=0.0, reps_max=12, threads=1)
+        S1 = S2 = 0
+        for m, y in enumerate(ys, 1):
+            x = y * 2 ** (k - 1)
+            S1 += x
+            S2 += x * x
+            eh = O.eps_hat(z, m, S1, S2)
+            if m >= 2 and eh <= 0.1:
+                old_in += abs(S1 / m - C) <= eh * S1 / m
+                break
+    assert old_in <= 75, old_in
