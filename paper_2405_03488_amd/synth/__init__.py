@@ -156,6 +156,11 @@ PATTERNS = {
     "diamond": (4, [(0, 1), (1, 2), (2, 3), (3, 0), (0, 2)]),
     "house": (5, [(0, 1), (1, 2), (2, 3), (3, 0), (2, 4), (3, 4)]),
     "dumbbell": (6, [(0, 1), (1, 2), (0, 2), (3, 4), (4, 5), (3, 5), (2, 3)]),
+    "7-clique": (7, [(a, b) for a in range(7) for b in range(a + 1, 7)]),
+    "8-clique": (8, [(a, b) for a in range(8) for b in range(a + 1, 8)]),
+    "7-cycle": (7, [(a, (a + 1) % 7) for a in range(7)]),
+    "8-path": (8, [(a, a + 1) for a in range(7)]),
+    "wheel-7": (7, [(0, a) for a in range(1, 7)] + [(a, a % 6 + 1) for a in range(1, 7)]),
 }
 
 

@@ -1,7 +1,7 @@
-"""Persistent batched estimation: every query's result equals its solo run bit
-for bit (samples drawn, exact sums, hits, checksum, windows, stop point), the
-device's stop test agrees with the host arithmetic, and replays of the
-captured hipGraph with new seeds stay equal to solo runs."""
+"""Persistent batched estimation: every query's result equals the oracle's run
+and its solo run bit for bit (samples drawn, exact sums, hits, checksum,
+windows, stop point), the device's stop test agrees with the host arithmetic,
+and replays of the captured hipGraph with new seeds stay equal to solo runs."""
 import pytest
 
 pytestmark = pytest.mark.gpu
@@ -20,17 +20,24 @@ def ctx(S):
     S.sgpm_destroy(c)
 
 
+def graph_inputs(synth):
+    for n, pairs in [(3000, synth.chung_lu_pairs(3000, 12, 2.1, 1)), (1 << 14, synth.rmat_pairs(14, 16, seed=3)),
+                     (5000, synth.er_pairs(5000, 40000, 2))]:
+        yield n, synth.pairs_to_csr(n, pairs)
+
+
 @pytest.fixture(scope="module")
 def graphs(S, synth, ctx):
     print("building batch graphs", flush=True)
-    out = []
-    for n, pairs in [(3000, synth.chung_lu_pairs(3000, 12, 2.1, 1)), (1 << 14, synth.rmat_pairs(14, 16, seed=3)),
-                     (5000, synth.er_pairs(5000, 40000, 2))]:
-        off, nbr = synth.pairs_to_csr(n, pairs)
-        out.append(S.sgpm_graph_from_csr(ctx, n, off, nbr))
+    out = [S.sgpm_graph_from_csr(ctx, n, off, nbr) for n, (off, nbr) in graph_inputs(synth)]
     yield out
     for g in out:
         S.sgpm_graph_free(g)
+
+
+@pytest.fixture(scope="module")
+def ographs(O, synth):
+    return [O.OGraph.from_raw_csr(n, off, nbr) for n, (off, nbr) in graph_inputs(synth)]
 
 
 def same(a, b):
@@ -69,6 +76,36 @@ def test_batch_equals_solo(S, synth, ctx, graphs):
         rs, _ = S.sgpm_estimate(ctx, g, p, o)
         same(rb, rs)
         assert rb.tile >= 16
+    for q in qs:
+        S.sgpm_pattern_free(q[1])
+
+
+def test_batch_equals_oracle(S, O, synth, ctx, graphs, ographs):
+    """Every query of the persistent batch (strict queries with their own
+    windows and device-side stop test, fixed-n queries) against the oracle's
+    run at the same options: stop point, windows, exact sums, hits, checksum,
+    estimate and predicted error."""
+    qs = make_queries(S, synth, ctx, graphs, 100)
+    res = S.sgpm_estimate_batch(ctx, [q[0] for q in qs], [q[1] for q in qs], [q[2] for q in qs])
+    i = 0
+    for og in ographs:
+        for name, induced in MOTIFS:
+            g, p, o = qs[i]
+            rb = res[i]
+            op = O.compile_plan(*synth.pattern(name), induced)
+            if o.mode == S.MODE_FIXED_N:
+                oo = O.make_opts(fixed_n=o.fixed_n, seed=o.seed, tag=o.query_tag)
+            else:
+                oo = O.make_opts(eps=o.eps, confidence=o.confidence, seed=o.seed, tag=o.query_tag, n_min=o.n_min,
+                                 w_min=o.w_min, quantum=o.quantum, max_samples=o.max_samples,
+                                 growth=o.window_growth)
+            orr = O.run(og, op, oo)
+            print(f"query {i} {name} n={orr.n}", flush=True)
+            assert rb.n_samples == orr.n and rb.windows == orr.windows and rb.converged == orr.converged
+            assert rb.S1 == orr.S1 and rb.S2 == orr.S2 and rb.n_hits == orr.hits and rb.checksum == orr.checksum
+            assert rb.estimate == orr.estimate
+            assert rb.eps_hat == orr.eps_hat or (rb.eps_hat == float("inf") and orr.eps_hat == float("inf"))
+            i += 1
     for q in qs:
         S.sgpm_pattern_free(q[1])
 

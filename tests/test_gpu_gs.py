@@ -229,3 +229,33 @@ def test_bes_refuses_what_it_cannot_estimate(S, O, synth, ctx, cl):
         with pytest.raises(S.SgpmError):
             S.sgpm_estimate(ctx, g, p, S.sgpm_options_default(**{"gs_scheme": S.GS_BERNOULLI, **kw}))
     S.sgpm_pattern_free(p)
+
+
+def test_colour_choice(S, O, synth, ctx, cl):
+    """colours = 0: the library probes one colouring at 16 colours (repetition
+    0x3FFFFFFF), chooses c from its leaves by the rule sgpm_host_colours_choice
+    states, and the estimate equals the GS run at that c."""
+    g, og = cl
+    for name in ["triangle", "4-clique", "diamond"]:
+        k, e = synth.pattern(name)
+        p = S.sgpm_pattern_create(ctx, k, e)
+        sp = S.sgpm_gs_sparsify(ctx, g, 16, 23, 0x3FFFFFFF)
+        y16 = S.sgpm_exact_count(ctx, sp, p)
+        S.sgpm_graph_free(sp)
+        assert y16 == O.gs_count(og, O.compile_plan(k, e), 16, 23, 0x3FFFFFFF)
+        want = S.sgpm_host_colours_choice(og.m, k, float(y16))
+        assert 4 <= want <= 16
+        r, rc = S.sgpm_estimate(ctx, g, p, S.sgpm_options_default(mode=S.MODE_GS, colours=0, seed=23, eps=0.05,
+                                                                   gs_reps_max=20))
+        assert r.colours == want
+        r2, _ = S.sgpm_estimate(ctx, g, p, S.sgpm_options_default(mode=S.MODE_GS, colours=want, seed=23, eps=0.05,
+                                                                    gs_reps_max=20))
+        assert (r.n_samples, r.S1, r.S2, r.estimate) == (r2.n_samples, r2.S1, r2.S2, r2.estimate)
+        S.sgpm_pattern_free(p)
+    p = S.sgpm_pattern_create(ctx, *synth.pattern("triangle"))
+    for bad in (-1, 257):
+        for mode in (S.MODE_GS, S.MODE_HYBRID):
+            with pytest.raises(S.SgpmError) as ei:
+                S.sgpm_estimate(ctx, g, p, S.sgpm_options_default(mode=mode, colours=bad))
+            assert ei.value.status == S.SGPM_EINVAL
+    S.sgpm_pattern_free(p)

@@ -115,8 +115,27 @@ def cl(S, O, synth, ctx):
     S.sgpm_graph_free(g)
 
 
-@pytest.mark.parametrize("name", ["triangle", "4-clique", "4-cycle", "diamond", "5-clique", "house"])
+def learned_oracle_sums(O, og, op, table, seed, tag, N):
+    """(S1, S2, hits, checksum, records of the first 4096 ids) of the
+    oracle's learned sampler over ids [0, N)."""
+    S1 = S2 = hits = csum = 0
+    recs = []
+    for s in range(N):
+        rec, af = O.sample_learned(og, op, table, seed, tag, s)
+        if s < 4096:
+            recs.append(rec)
+        S1 += rec.alpha
+        S2 += rec.alpha * rec.alpha
+        hits += rec.hit
+        csum = (csum + O.rec_hash(rec)) % (1 << 64)
+    return S1, S2, hits, csum, recs
+
+
+@pytest.mark.parametrize("name", ["triangle", "4-clique", "4-cycle", "diamond", "5-clique", "house", "6-clique"])
 def test_learned_walks_match_oracle(S, O, synth, ctx, cl, name):
+    """Traced runs take the generic learned kernel, untraced ones (what the
+    estimates launch) the clique specialisation for cliques of 3 to 6
+    vertices; both equal the oracle's learned walks, sums and checksum."""
     g, og = cl
     k, e = synth.pattern(name)
     p = S.sgpm_pattern_create(ctx, k, e)
@@ -147,6 +166,58 @@ def test_learned_walks_match_oracle(S, O, synth, ctx, cl, name):
         csum = (csum + O.rec_hash(rec)) % (1 << 64)
     assert r.S1 == S1 and r.S2 == S2 and r.n_hits == hits and r.checksum == csum
     assert r.estimate == O.digits_to_double(S1) / N / 2 ** 52
+    o = S.sgpm_options_default(mode=S.MODE_FIXED_N, fixed_n=N, seed=21, checksum=1, proposal=model.value)
+    r, _ = S.sgpm_estimate(ctx, g, p, o)
+    assert r.S1 == S1 and r.S2 == S2 and r.n_hits == hits and r.checksum == csum
+    S.sgpm_model_free(model)
+    S.sgpm_pattern_free(p)
+
+
+@pytest.fixture(scope="module")
+def dense_big(S, O, synth, ctx):
+    """A dense core (ER on 2,000 vertices with 80 % of all pairs) whose vertex i
+    also has 3i neighbours among 3,000 others: candidate sets of a core edge
+    often exceed the 896-entry LDS list and span several degree buckets."""
+    n = 5000
+    rng = np.random.default_rng(5)
+    ext = [np.stack([np.full(3 * i, i), 2000 + rng.choice(3000, 3 * i, replace=False)], 1) for i in range(1, 1000)]
+    pairs = np.concatenate([synth.er_pairs(2000, 1600000, 7)] + ext).astype(np.int32)
+    off, nbr = synth.pairs_to_csr(n, pairs)
+    g = S.sgpm_graph_from_csr(ctx, n, off, nbr)
+    og = O.OGraph.from_raw_csr(n, off, nbr)
+    yield g, og
+    S.sgpm_graph_free(g)
+
+
+@pytest.mark.parametrize("name", ["4-clique", "5-clique", "diamond", "4-cycle"])
+def test_learned_candidate_list_overflow(S, O, synth, ctx, dense_big, name):
+    """Weighted steps whose candidate set exceeds the LDS list: the bucket
+    histogram is taken by rescanning the rows.  The oracle shows the case in
+    many samples; traced and untraced runs equal its learned sums."""
+    g, og = dense_big
+    k, e = synth.pattern(name)
+    p = S.sgpm_pattern_create(ctx, k, e)
+    op = O.compile_plan(k, e)
+    rng = np.random.default_rng(3)
+    table = rng.integers(1, 65536, size=(8, 32, 32, 32)).astype(np.uint16)
+    model = S.sgpm_model_from_tables(ctx, [p], table)
+    N = 12000 + 5
+    S1, S2, hits, csum, recs = learned_oracle_sums(O, og, op, table, 4, 3, N)
+    big = sum(1 for r in recs if max(r.size[2:k - 1]) > 896)
+    assert big >= len(recs) // 100, big
+    buf = S.trace_buffer(len(recs))
+    o = S.sgpm_options_default(mode=S.MODE_FIXED_N, fixed_n=N, seed=4, query_tag=3, checksum=1,
+                               proposal=model.value, trace_lo=0, trace_hi=len(recs),
+                               trace_buf=C.cast(buf, C.c_void_p).value)
+    r, _ = S.sgpm_estimate(ctx, g, p, o)
+    for a, b in zip(buf, recs):
+        st = 0xFF if b.hit else b.fail_step
+        assert (a.s, a.status, list(a.v), a.alpha) == (b.s, st, list(b.v), b.alpha), b.s
+    assert r.S1 == S1 and r.S2 == S2 and r.n_hits == hits and r.checksum == csum
+    o = S.sgpm_options_default(mode=S.MODE_FIXED_N, fixed_n=N, seed=4, query_tag=3, checksum=1,
+                               proposal=model.value)
+    r, _ = S.sgpm_estimate(ctx, g, p, o)
+    assert r.S1 == S1 and r.S2 == S2 and r.n_hits == hits and r.checksum == csum
     S.sgpm_model_free(model)
     S.sgpm_pattern_free(p)
 

@@ -157,8 +157,10 @@ def cl_graph(S, O, synth, ctx):
 @pytest.mark.parametrize("induced", [False, True])
 @pytest.mark.parametrize("name", ALL)
 def test_patterns_fixed_n(S, O, synth, ctx, cl_graph, name, induced):
-    """Every pattern, edge- and vertex-induced, a ragged sample count; lanes
-    1 and 16 must give the oracle's sums and checksum."""
+    """Every pattern, edge- and vertex-induced, a ragged sample count: lanes
+    1, 16 and 64 with a trace (64: the generic one-sample-per-wave kernel) and
+    64 without one (the kernel strict runs launch: the clique specialisation
+    for cliques of 3 to 6 vertices) must give the oracle's sums and checksum."""
     print(f"pattern {name} induced={induced}", flush=True)
     g, og = cl_graph
     k, e = synth.pattern(name)
@@ -166,15 +168,97 @@ def test_patterns_fixed_n(S, O, synth, ctx, cl_graph, name, induced):
     op = O.compile_plan(k, e, induced)
     N = 200000 + 123
     orr = O.run(og, op, O.make_opts(fixed_n=N, seed=11, tag=5))
-    for lanes in (1, 16):
+    recs = O.trace(og, op, 11, 5, N - 500, 500)
+    for lanes in (1, 16, 64):
         buf = S.trace_buffer(700)
         opts = S.sgpm_options_default(mode=S.MODE_FIXED_N, fixed_n=N, seed=11, query_tag=5, checksum=1,
                                       lanes_per_sample=lanes, trace_lo=N - 500, trace_hi=N + 200,
                                       trace_buf=addr(buf))
         r, _ = S.sgpm_estimate(ctx, g, p, opts)
+        assert r.lanes_per_sample == lanes
         check_run(S, O, r, orr)
-        check_trace(buf[:500], O.trace(og, op, 11, 5, N - 500, 500))
+        check_trace(buf[:500], recs)
         assert all(x.s == 0 and x.k == 0 for x in buf[500:])  # ids beyond the run are never written
+    opts = S.sgpm_options_default(mode=S.MODE_FIXED_N, fixed_n=N, seed=11, query_tag=5, checksum=1,
+                                  lanes_per_sample=64)
+    r, _ = S.sgpm_estimate(ctx, g, p, opts)
+    assert r.lanes_per_sample == 64
+    check_run(S, O, r, orr)
+    S.sgpm_pattern_free(p)
+
+
+@pytest.fixture(scope="module")
+def dense_small(S, O, synth, ctx):
+    print("building ER(300, 25000)", flush=True)
+    g, og = load(S, O, synth, ctx, 300, synth.er_pairs(300, 25000, 3))
+    yield g, og
+    S.sgpm_graph_free(g)
+
+
+@pytest.mark.parametrize("induced", [False, True])
+@pytest.mark.parametrize("name", ["7-clique", "8-clique", "7-cycle", "8-path", "wheel-7"])
+def test_seven_and_eight_vertex_patterns(S, O, synth, ctx, dense_small, name, induced):
+    """Patterns of 7 and 8 vertices (the largest the library accepts) on a
+    dense graph where they have hits: every lane width, traced and not, equals
+    the oracle's sums, hits and checksum, and the traced walks match."""
+    print(f"pattern {name} induced={induced}", flush=True)
+    g, og = dense_small
+    k, e = synth.pattern(name)
+    p = S.sgpm_pattern_create(ctx, k, e, induced)
+    op = O.compile_plan(k, e, induced)
+    N = 60000 + 7
+    orr = O.run(og, op, O.make_opts(fixed_n=N, seed=5, tag=2))
+    assert orr.hits > 10
+    recs = O.trace(og, op, 5, 2, 0, 400)
+    for lanes in (1, 4, 16, 64):
+        buf = S.trace_buffer(400)
+        opts = S.sgpm_options_default(mode=S.MODE_FIXED_N, fixed_n=N, seed=5, query_tag=2, checksum=1,
+                                      lanes_per_sample=lanes, trace_lo=0, trace_hi=400, trace_buf=addr(buf))
+        r, _ = S.sgpm_estimate(ctx, g, p, opts)
+        check_run(S, O, r, orr)
+        check_trace(buf, recs)
+        r, _ = S.sgpm_estimate(ctx, g, p, S.sgpm_options_default(mode=S.MODE_FIXED_N, fixed_n=N, seed=5,
+                                                                 query_tag=2, checksum=1, lanes_per_sample=lanes))
+        check_run(S, O, r, orr)
+    S.sgpm_pattern_free(p)
+
+
+@pytest.fixture(scope="module")
+def dense_big(S, O, synth, ctx):
+    """ER(2000, 1.6M): 80 % of all pairs, so an edge's common neighbours number
+    about 1,280 and a step's candidate set often exceeds the 896 entries the
+    one-sample-per-wave kernels keep in LDS."""
+    print("building ER(2000, 1600000)", flush=True)
+    g, og = load(S, O, synth, ctx, 2000, synth.er_pairs(2000, 1600000, 7))
+    yield g, og
+    S.sgpm_graph_free(g)
+
+
+@pytest.mark.parametrize("name", ["triangle", "4-clique", "diamond", "4-cycle"])
+def test_candidate_list_overflow(S, O, synth, ctx, dense_big, name):
+    """Candidate sets larger than the LDS list: the kernels count them fully
+    and select the drawn member by rescanning the rows.  The oracle shows the
+    case occurs in many samples; every width, traced and not, matches it."""
+    print(f"overflow {name}", flush=True)
+    g, og = dense_big
+    k, e = synth.pattern(name)
+    p = S.sgpm_pattern_create(ctx, k, e)
+    op = O.compile_plan(k, e)
+    N = 20000 + 3
+    recs = O.trace(og, op, 9, 1, 0, N)
+    big = sum(1 for r in recs if max(r.size[2:k]) > 896)
+    assert big >= N // 20, big
+    orr = O.run(og, op, O.make_opts(fixed_n=N, seed=9, tag=1))
+    for lanes in (1, 16, 64):
+        buf = S.trace_buffer(N)
+        opts = S.sgpm_options_default(mode=S.MODE_FIXED_N, fixed_n=N, seed=9, query_tag=1, checksum=1,
+                                      lanes_per_sample=lanes, trace_lo=0, trace_hi=N, trace_buf=addr(buf))
+        r, _ = S.sgpm_estimate(ctx, g, p, opts)
+        check_run(S, O, r, orr)
+        check_trace(buf, recs)
+    r, _ = S.sgpm_estimate(ctx, g, p, S.sgpm_options_default(mode=S.MODE_FIXED_N, fixed_n=N, seed=9, query_tag=1,
+                                                             checksum=1, lanes_per_sample=64))
+    check_run(S, O, r, orr)
     S.sgpm_pattern_free(p)
 
 
