@@ -9,7 +9,9 @@ resident on the device before timing starts.
 
 value   = verified samples/s over the timed steps (all samples drawn / wall time)
 roofline= the sampling kernel's algorithmic bytes (per-sample figure from the
-          instrumented kernel x samples) / its HIP-event time, against the HBM peak
+          instrumented kernel x samples: 8 per first edge, 16 per opened row and 4 per
+          entry of every row merged inside the step bounds) / its HIP-event time,
+          against the HBM peak
 cpu_baseline = the CPU oracle on a bounded sample of the same workload
 Every timed run is rerun by the CPU oracle after timing with the same
 options; stop point, exact sums and the checksum over all samples must match
@@ -369,6 +371,9 @@ def main():
                          "5-clique and diamond on R-MAT 20 colour-sparsified with c = 16 (seed 11, colouring 0)")
     ap.add_argument("--counters-run", action="store_true",
                     help="short run for hardware counters: one 256 MiB copy, then one 4M-sample window per query")
+    ap.add_argument("--counters-learned", action="store_true",
+                    help="with --counters-run: also train the MLP proposal and run one 4M-sample learned window "
+                         "per query")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding is a "
@@ -418,6 +423,14 @@ def main():
                                        lanes_per_sample=64)
             r, _ = S.sgpm_estimate(ctx, g, pats[q], o)
             log(f"{q}: {r.n_samples} samples, kernel {r.seconds_kernel * 1e3:.3f} ms over {r.launches} launch(es)")
+        if args.counters_learned:
+            model = S.sgpm_model_train(ctx, g, [pats[q] for q in queries])
+            for q in queries:
+                o = S.sgpm_options_default(mode=S.MODE_FIXED_N, fixed_n=4 << 20, seed=1000, checksum=1,
+                                           proposal=model.value)
+                r, _ = S.sgpm_estimate(ctx, g, pats[q], o)
+                log(f"{q} learned: {r.n_samples} samples, kernel {r.seconds_kernel * 1e3:.3f} ms")
+            S.sgpm_model_free(model)
         return
 
     def opts_for(q, seed, lanes):
@@ -450,6 +463,8 @@ def main():
     wall = t_end - t_begin
     total_samples = sum(x["r"].n_samples for x in runs)
     kernel_s = sum(x["r"].seconds_kernel for x in runs)
+    # device time with at least one sampling kernel running (estimates run one after another)
+    busy_s = sum(x["r"].seconds_kernel_busy for x in runs)
     launches = sum(x["r"].launches for x in runs)
 
     # algorithmic bytes per sample, from the instrumented kernel on step 0's samples
@@ -486,6 +501,7 @@ def main():
                     "windows": [int(r.windows) for r in rs],
                     "device_span_s": float(np.mean([r.seconds_sampling for r in rs])),
                     "kernel_s": float(np.mean([r.seconds_kernel for r in rs])),
+                    "kernel_busy_s": float(np.mean([r.seconds_kernel_busy for r in rs])),
                     "bytes_per_sample": bps[q]}
 
     # CPU leg: oracle baseline and verification of the timed runs
@@ -501,13 +517,16 @@ def main():
         # the exact sums and the checksum over all samples must be identical
         verified = True
         tv = time.perf_counter()
+        cpu_tte = {}
         for x in runs:
             k, e = synth.pattern(x["q"])
             op = O.compile_plan(k, e)
             so = x["opts"]
+            t_o = time.perf_counter()
             orr = O.run(og, op, O.make_opts(eps=so.eps, confidence=so.confidence, seed=so.seed, tag=so.query_tag,
                                             n_min=so.n_min, w_min=so.w_min, quantum=so.quantum,
                                             max_samples=so.max_samples, growth=so.window_growth))
+            cpu_tte.setdefault(x["q"], []).append(time.perf_counter() - t_o)
             r = x["r"]
             if (orr.n, orr.S1, orr.S2, orr.hits, orr.checksum) != (r.n_samples, r.S1, r.S2, r.n_hits, r.checksum):
                 verified = False
@@ -536,6 +555,11 @@ def main():
         cpu["single_core"] = {"value": N1 / dt1, "unit": "samples/s", "cores": 1,
                               "sample": f"fixed {N1} samples (seed 7), {dt1:.1f}s on 1 thread"}
         cpu["host"] = {"nproc": os.cpu_count(), "cpu_model": host_cpu_model()}
+        # the oracle's time to eps on the same windows (the verification reruns above:
+        # same seeds and window schedule, hence the same stop points as the GPU)
+        cpu["time_to_eps_s"] = {q: float(np.mean(v)) for q, v in cpu_tte.items()}
+        cpu["time_to_eps_runs"] = {q: len(v) for q, v in cpu_tte.items()}
+        cpu["time_to_eps_cores"] = O.nthreads()
         log(f"cpu oracle, one core: {N1 / dt1:.4g} samples/s ({N1} samples, {dt1:.1f}s)")
         # algorithmic bytes per sample (the measurement definition the roofline
         # uses), by the step at which the sample ended, from the oracle's records
@@ -545,14 +569,19 @@ def main():
             opq = O.compile_plan(kq, eq)
             ends = {}
             allb = []
+            minb = []
             for sid in range(20000):
                 rec = O.sample(og, opq, 1, 0, sid)
                 key = "hit" if rec.hit else f"ended at step {rec.fail_step}"
                 ends.setdefault(key, []).append(int(rec.bytes))
                 allb.append(int(rec.bytes))
+                minb.append(int(rec.bytes_min))
             a = np.array(allb, dtype=np.float64)
-            bdist[q] = {"samples": len(allb), "mean": float(a.mean()), "p50": float(np.percentile(a, 50)),
+            bdist[q] = {"definition": "8 first edge + 16 per opened row + 4 per entry of every merged row inside "
+                                      "the step bounds",
+                        "samples": len(allb), "mean": float(a.mean()), "p50": float(np.percentile(a, 50)),
                         "p90": float(np.percentile(a, 90)), "p99": float(np.percentile(a, 99)), "max": float(a.max()),
+                        "mean_smallest_row_only": float(np.mean(minb)),
                         "by_end": {k2: {"samples": len(v), "mean": float(np.mean(v))} for k2, v in sorted(ends.items())}}
         cpu_bytes = bdist
 
@@ -580,8 +609,12 @@ def main():
                      if (traffic and gather) else None,
                      "kernel": sorted({"ns_wave_kernel" if lanes[q] == 64 else f"ns_window_kernel<{lanes[q]}>"
                                        for q in queries}),
+                     "frac_smallest_row_bytes": (achieved / HBM_PEAK_GBS * sum(
+                         cpu_bytes[q]["mean_smallest_row_only"] / cpu_bytes[q]["mean"] for q in queries) / len(queries))
+                     if cpu_bytes else None,
                      "launches": launches,
                      "avg_launch_ms": kernel_s / max(1, launches) * 1e3,
+                     "kernel_busy_ms_per_step": busy_s / args.steps * 1e3,
                      "sampling_launches_before_timed": warm_launches,
                      "alg_bytes_per_launch": alg_bytes / max(1, launches),
                      "measured": probes},

@@ -210,6 +210,10 @@ typedef struct {
      * predicted GS time (+inf when GS cannot meet eps), and the pilots' wall time */
     double pred_ns_lo, pred_ns_hi, pred_gs;
     double seconds_pilot;
+    /* NS: device time during which at least one sampling kernel of the call ran
+     * (the union of their intervals; below seconds_kernel when windows queued
+     * ahead overlap on the second stream) */
+    double seconds_kernel_busy;
 } sgpm_result;
 
 /* Defaults: eps 0.01, confidence 0.95, seed 1, tag 0, strict NS, n_min = w_min =

@@ -410,6 +410,7 @@ sgpm_status ns_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_op
         if (it != c->ns_tuned.end()) lanes = it->second;
     }
     double dev_seconds = 0.0, kernel_seconds = 0.0;
+    std::vector<std::pair<float, float>> spans;  // sampling kernels' [start, end) in ms after e0
     int windows = 0, launches = 0;
     bool converged = false;
     sgpm_status status = SGPM_OK;
@@ -512,8 +513,11 @@ sgpm_status ns_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_op
         HIP_TRY(c, hipEventSynchronize(c->kev[3 * lastslot + 2]));
         for (size_t k = w.slot0; k <= lastslot; k++) {
             absorb(s, c->h_slots + k * SLOT_WORDS + 1);
-            float kms = 0;
+            float kms = 0, ka = 0, kb = 0;
             HIP_TRY(c, hipEventElapsedTime(&kms, c->kev[3 * k], c->kev[3 * k + 1]));
+            HIP_TRY(c, hipEventElapsedTime(&ka, e0, c->kev[3 * k]));
+            HIP_TRY(c, hipEventElapsedTime(&kb, e0, c->kev[3 * k + 1]));
+            spans.emplace_back(ka, kb);
             kernel_seconds += kms * 1e-3;
             launches++;
         }
@@ -551,6 +555,22 @@ sgpm_status ns_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_op
     res->lanes_per_sample = lanes ? lanes : 64;
     res->seconds_sampling = dev_seconds;
     res->seconds_kernel = kernel_seconds;
+    {
+        // union of the kernels' intervals (windows queued ahead overlap)
+        std::sort(spans.begin(), spans.end());
+        double busy = 0.0, a = -1.0, b = -1.0;
+        for (const auto& sp : spans) {
+            if (sp.first > b) {
+                if (b > a) busy += b - a;
+                a = sp.first;
+                b = sp.second;
+            } else if (sp.second > b) {
+                b = sp.second;
+            }
+        }
+        if (b > a) busy += b - a;
+        res->seconds_kernel_busy = busy * 1e-3;
+    }
     res->launches = launches;
     if (o.mode == SGPM_MODE_FIXED_N) converged = res->eps_hat <= o.eps;
     res->converged = converged ? 1 : 0;

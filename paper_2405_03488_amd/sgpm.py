@@ -61,7 +61,7 @@ class Result(C.Structure):
                 ("bytes", C.c_uint64), ("seconds_sampling", C.c_double), ("seconds_total", C.c_double),
                 ("seconds_kernel", C.c_double), ("tile", C.c_int32), ("weight_shift", C.c_int32),
                 ("reserved0", C.c_int32), ("pred_ns_lo", C.c_double), ("pred_ns_hi", C.c_double),
-                ("pred_gs", C.c_double), ("seconds_pilot", C.c_double)]
+                ("pred_gs", C.c_double), ("seconds_pilot", C.c_double), ("seconds_kernel_busy", C.c_double)]
 
     @property
     def S1(self) -> int:
