@@ -70,9 +70,9 @@ sgpm_graph::~sgpm_graph() {
     if (ctx)
         for (auto it = ctx->ns_tuned.begin(); it != ctx->ns_tuned.end();)
             it = std::get<0>(it->first) == (const void*)this ? ctx->ns_tuned.erase(it) : std::next(it);
-    if (!d_off && !d_nbr && !d_epair && !d_arow && !d_bthr) return;
+    if (!d_off && !d_nbr && !d_epair && !d_arow && !d_vb) return;
     if (ctx) (void)hipSetDevice(ctx->dev);
-    for (void* q : {(void*)d_off, (void*)d_nbr, (void*)d_epair, (void*)d_arow, (void*)d_bthr})
+    for (void* q : {(void*)d_off, (void*)d_nbr, (void*)d_epair, (void*)d_arow, (void*)d_vb})
         if (q) (void)hipFree(q);
 }
 
@@ -199,23 +199,26 @@ sgpm_status sgpm_graph_from_csr(sgpm_ctx_t c, int64_t n, const void* offsets, in
         HIP_TRY(c, hipMemcpy(g->d_epair, ep.data(), sizeof(int2) * (size_t)h.m, hipMemcpyHostToDevice));
         HIP_TRY(c, hipMemcpy(g->d_arow, arow.data(), sizeof(int32_t) * (size_t)(2 * h.m), hipMemcpyHostToDevice));
     }
-    // degree buckets b = floor(log2(1 + deg)) are non-increasing in the canonical id
+    // degree buckets b = floor(log2(1 + deg)) are non-increasing in the canonical id;
+    // the learned proposal reads a candidate's bucket from a byte per vertex
     g->degree_ordered = true;
     {
         int64_t cntb[32] = {0};
+        std::vector<uint8_t> vb((size_t)std::max<int64_t>(n, 1), 0);
         for (int64_t u = 0; u < n; u++) {
             const int64_t d = h.off[(size_t)u + 1] - h.off[(size_t)u];
             int b = 0;
             while (b < 31 && ((d + 1) >> (b + 1)) > 0) b++;
             cntb[b]++;
+            vb[(size_t)u] = (uint8_t)b;
         }
         int64_t above = 0;
         for (int b = 31; b >= 0; b--) {
             g->bthr[b] = (int32_t)above;  // vertices with bucket > b
             above += cntb[b];
         }
-        HIP_TRY(c, hipMalloc(&g->d_bthr, sizeof(int32_t) * 32));
-        HIP_TRY(c, hipMemcpy(g->d_bthr, g->bthr, sizeof(int32_t) * 32, hipMemcpyHostToDevice));
+        HIP_TRY(c, hipMalloc(&g->d_vb, vb.size()));
+        HIP_TRY(c, hipMemcpy(g->d_vb, vb.data(), vb.size(), hipMemcpyHostToDevice));
     }
     g->perm = std::move(h.perm);
     *out = g.release();

@@ -181,15 +181,25 @@ __device__ __forceinline__ bool member(const int32_t* __restrict__ R, int32_t rl
 // One NS-prune sample.  Returns 0xFF for a hit, else the failing position j.
 // For G > 1 all G lanes of a group call it with the same s.  `list` is the
 // group's LDS area of CAP words holding the current candidate set.
-// b(x) = #{t < 31 : x < thr[t]}; thr is non-increasing, so a binary search
-__device__ __forceinline__ int32_t bucket_of(const LearnArgs& la, int32_t x) {
-    int32_t lo = 0, hi = 31;
-    while (lo < hi) {
-        const int32_t mid = (lo + hi) >> 1;
-        if (x < la.thr[mid]) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
+// Degree bucket floor(log2(1 + d)), clipped to 31: of an embedded vertex from
+// its row length (already loaded), of a candidate from the graph's byte array.
+__device__ __forceinline__ int32_t bucket_of_degree(int32_t d) {
+    const int32_t b = 31 - (int32_t)__clz((uint32_t)d + 1u);
+    return b < 31 ? b : 31;
+}
+__device__ __forceinline__ int32_t bucket_of(const LearnArgs& la, int32_t x) { return (int32_t)la.vb[x]; }
+
+// Inclusive prefix sums over lanes 0-31 (two rows of 16 lanes): DPP shifts by
+// 1, 2, 4 and 8 within each row, then row 0's total broadcast into row 1.
+// Lanes 32-63 end with sums of their own rows (callers ignore them).  Every
+// lane of the wave must be active.
+__device__ __forceinline__ uint32_t scan32_dpp(uint32_t x) {
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, false);  // row_shr:1
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, false);  // row_shr:2
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, false);  // row_shr:4
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, false);  // row_shr:8
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false);  // row_bcast:15 into rows 1, 3
+    return x;
 }
 
 __device__ __forceinline__ uint64_t wave_incl_scan(uint64_t x) {
@@ -305,7 +315,7 @@ __device__ __forceinline__ uint32_t ns_sample(const DGraph& g, const Plan& p, ui
     const bool learned = (G == 64) && la != nullptr && la->table != nullptr;
     double af = (double)M;
     int32_t b0 = 0;
-    if (learned) b0 = hd ? hd->k0 : bucket_of(*la, v[0]);
+    if (learned) b0 = hd ? hd->k0 : bucket_of_degree(rl[0]);
     uint32_t opened = 0;
     int32_t prevcnt = -1;  // |S_{j-1}| when the whole set sits in `list`
 
@@ -326,10 +336,10 @@ __device__ __forceinline__ uint32_t ns_sample(const DGraph& g, const Plan& p, ui
         // candidates are scanned
         // (the last step picks uniformly: every candidate completes exactly one match)
         const bool weighted = learned && j + 1 < pk;
-        uint64_t wrow = 0;
+        uint32_t wrow = 0;
         if (weighted && lane < 32) {
-            const int32_t bp = (j == 2 && hd) ? hd->k1 : bucket_of(*la, v[j - 1]);
-            wrow = (uint64_t)la->table[(((size_t)j * 32 + (size_t)b0) * 32 + (size_t)bp) * 32 + lane];
+            const int32_t bp = (j == 2 && hd) ? hd->k1 : bucket_of_degree(rl[j - 1]);
+            wrow = (uint32_t)la->table[(((size_t)j * 32 + (size_t)b0) * 32 + (size_t)bp) * 32 + lane];
         }
         // smallest connected earlier row (lowest position on ties)
         int d = -1;
@@ -437,22 +447,19 @@ __device__ __forceinline__ uint32_t ns_sample(const DGraph& g, const Plan& p, ui
                 af = __dmul_rn(af, (double)cnt);
             } else if (weighted && cnt <= (uint32_t)CAP) {
                 // weighted bucket, then a uniform member of it: counts n_b <= CAP
-                // and n_b w_b < 2^26, so (n_b w_b) << 32 | n_b scans as one word
+                // and n_b w_b < 2^26, so both running sums fit 32 bits; bucket b
+                // sits in lane b and the sums are scanned with DPP row shifts
                 if (lane < 32) hist[lane] = 0;
                 for (uint32_t i = (uint32_t)lane; i < cnt; i += 64u) atomicAdd(&hist[bucket_of(*la, list[i])], 1u);
-                const uint64_t nb = lane < 32 ? (uint64_t)hist[lane] : 0ull;
-                const uint64_t w = wrow;
-                uint64_t pk = (nb * w) << 32 | nb;
-#pragma unroll
-                for (int o = 1; o < 32; o <<= 1) {
-                    const uint64_t y = __shfl_up(pk, (unsigned)o);
-                    if (lane >= o) pk += y;
-                }
-                const uint64_t cum = pk >> 32, cumn = pk & 0xFFFFFFFFull;
-                const uint64_t sigma = __shfl(cum, 31);
+                const uint32_t nb = lane < 32 ? hist[lane] : 0u;
+                const uint32_t w = (uint32_t)wrow;
+                const uint32_t cum = scan32_dpp(nb * w), cumn = scan32_dpp(nb);
+                const uint64_t sigma = (uint32_t)__builtin_amdgcn_readlane((int)cum, 31);
                 const uint64_t t = __umul64hi(sigma, draw_at(dr, seed, s, (uint32_t)j, tag));
-                const int bsel = __ffsll((unsigned long long)__ballot(lane < 32 && cum > t)) - 1;
-                const uint64_t nbs = __shfl(nb, bsel), wbs = __shfl(w, bsel), upto = __shfl(cumn, bsel);
+                const int bsel = __ffsll((unsigned long long)__ballot(lane < 32 && (uint64_t)cum > t)) - 1;
+                const uint64_t nbs = (uint32_t)__builtin_amdgcn_readlane((int)nb, bsel);
+                const uint64_t wbs = (uint32_t)__builtin_amdgcn_readlane((int)w, bsel);
+                const uint64_t upto = (uint32_t)__builtin_amdgcn_readlane((int)cumn, bsel);
                 const uint64_t inb = __umul64hi(nbs, draw_at(dr, seed, s, 16u + (uint32_t)j, tag));
                 idx = (uint32_t)((uint64_t)cnt - upto + inb);
                 af = __dmul_rn(af, __ddiv_rn((double)sigma, (double)wbs));
@@ -469,7 +476,7 @@ __device__ __forceinline__ uint32_t ns_sample(const DGraph& g, const Plan& p, ui
                     if (inm != gmask) break;
                 }
                 const uint64_t nb = lane < 32 ? (uint64_t)hist[lane] : 0ull;
-                const uint64_t w = wrow;
+                const uint64_t w = (uint64_t)wrow;
                 const uint64_t cum = wave_incl_scan(nb * w);
                 const uint64_t cumn = wave_incl_scan(nb);
                 const uint64_t sigma = __shfl(cum, 63);
@@ -565,7 +572,8 @@ __device__ __forceinline__ void prefetch_heads(const DGraph& g, bool oriented, c
         h4[1] = make_uint4((uint32_t)b0, (uint32_t)((uint64_t)b0 >> 32), (uint32_t)b1, (uint32_t)((uint64_t)b1 >> 32));
         if (la) {  // words 8-9: the buckets of the first edge's ends (learned proposal)
             uint2* k2 = reinterpret_cast<uint2*>(rec + lane * stride + 8);
-            k2[0] = make_uint2((uint32_t)bucket_of(*la, h0), (uint32_t)bucket_of(*la, h1));
+            k2[0] = make_uint2((uint32_t)bucket_of_degree((int32_t)(e0 - b0)),
+                               (uint32_t)bucket_of_degree((int32_t)(e1 - b1)));
         }
     }
     __builtin_amdgcn_wave_barrier();

@@ -196,14 +196,7 @@ __global__ __launch_bounds__(256, wave_occupancy(MODE, CLQ)) void ns_wave_kernel
     unsigned long long* wsum = s_wsum[wid];
     int32_t* list = s_list + wid * (LDS_WORDS / 4);
     if (lane < 16) wsum[lane] = 0ull;
-    // learned proposal: the bucket thresholds, searched once per candidate chunk, in LDS
-    __shared__ int32_t s_thr[32];
-    LearnArgs lal = la;
-    if (MODE == 1) {
-        if (threadIdx.x < 32) s_thr[threadIdx.x] = la.thr[threadIdx.x];
-        __syncthreads();
-        lal.thr = s_thr;
-    }
+    const LearnArgs lal = la;
     __builtin_amdgcn_wave_barrier();
     uint64_t ovf = 0;
     const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x >> 6);

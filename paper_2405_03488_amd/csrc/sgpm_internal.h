@@ -50,7 +50,7 @@ struct TraceArgs {
 // thr[b] = the number of vertices whose bucket exceeds b.
 struct LearnArgs {
     const uint16_t* table;  // [8][32][32][32] weights for the pattern, nullptr = uniform proposal
-    const int32_t* thr;     // [32] device array, thr[31] = 0
+    const uint8_t* vb;      // [n] bucket floor(log2(1 + degree)) of every vertex, clipped to 31
 };
 
 // Dynamic work distribution of the sampling kernels: NTK ticket counters,
@@ -216,8 +216,8 @@ struct sgpm_graph {
     sgpm_ctx* ctx = nullptr;
     int64_t n = 0, m = 0, maxdeg = 0;
     bool degree_ordered = false;  // canonical ids: degree non-increasing (bucket thresholds valid)
-    int32_t bthr[32] = {0};
-    int32_t* d_bthr = nullptr;
+    int32_t bthr[32] = {0};          // host: vertices with bucket > b (bucket thresholds in id order)
+    uint8_t* d_vb = nullptr;         // device: bucket of every vertex (canonical graphs)
     std::vector<int32_t> perm;
     int64_t* d_off = nullptr;
     int32_t* d_nbr = nullptr;
