@@ -98,6 +98,15 @@ def other_legs(S, ctx, g, pats, queries, eps):
         out["hybrid"][q] = {"scheme": "GS" if r.scheme == S.SCHEME_GS else "NS", "ns_cone_s": [r.pred_ns_lo,
                                                                                              r.pred_ns_hi],
                             "gs_pred_s": r.pred_gs, "pilot_s": r.seconds_pilot, "total_s": r.seconds_total}
+        # the paper's profiler and cost models choosing instead of the pilots
+        r, _ = S.sgpm_estimate(ctx, g, pats[q], S.sgpm_options_default(mode=S.MODE_HYBRID, eps=eps, seed=6,
+                                                                        hybrid_selector=S.HYBRID_COST_MODEL))
+        out.setdefault("hybrid_cost_model", {})[q] = {
+            "scheme": "GS" if r.scheme == S.SCHEME_GS else "NS", "ns_cone_s": [r.pred_ns_lo, r.pred_ns_hi],
+            "gs_pred_s": r.pred_gs, "pred_samples": r.pred_samples, "samples": int(r.n_samples),
+            "pred_over_actual_samples": r.pred_samples / r.n_samples if r.n_samples else None,
+            "profile_s": r.seconds_pilot, "total_s": r.seconds_total, "estimate": r.estimate,
+            "eps_hat": r.eps_hat}
     # the persistent batch: both queries x 4 seeds in one launch against the solo runs
     qs = [(q, 3000 + i) for q in queries for i in range(4)]
     bopts = [S.sgpm_options_default(eps=eps, seed=sd, query_tag=i, checksum=1) for i, (q, sd) in enumerate(qs)]
@@ -142,8 +151,15 @@ def learned_leg(S, ctx, g, pats, queries, eps, steps, lanes):
     model = S.sgpm_model_train(ctx, g, [pats[q] for q in queries])
     train_s = time.perf_counter() - t0
     info = S.sgpm_model_info(model)
+    # training work: 8 epochs over the tuples (whole minibatches of 2048 rows),
+    # forward + backward of the 16-64-64-1 network = 3 x 2 x 5,248 flops per row
+    rows = 8 * (info["tuples"] // 2048) * 2048
+    flops = rows * 3 * 2 * (16 * 64 + 64 * 64 + 64)
     out = {"train_s": train_s, "pilot_s": info["pilot_seconds"], "tuples": info["tuples"],
-           "loss_first": info["loss_first"], "loss_last": info["loss_last"], "queries": {}}
+           "loss_first": info["loss_first"], "loss_last": info["loss_last"],
+           "train_flops": flops, "train_tflops_per_s": flops / max(train_s - info["pilot_seconds"], 1e-9) / 1e12,
+           "train_mfma_frac_of_bf16_peak": flops / max(train_s - info["pilot_seconds"], 1e-9) / 2.5e15,
+           "queries": {}}
     for q in queries:
         # warm both paths (the learned one runs one sample per wave)
         for prop in (None, model):

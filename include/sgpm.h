@@ -180,7 +180,16 @@ typedef struct {
     int32_t sampler;         /* SGPM_SAMPLER_*: NS-prune (default) or NS-base; NS-base runs in the strict
                                 and fixed-n modes only, with the uniform proposal and no byte count */
     int32_t gs_scheme;       /* SGPM_GS_*: the sparsifier of SGPM_MODE_GS */
+    int32_t hybrid_selector; /* SGPM_HYBRID_*: how loose mode chooses between NS and GS */
 } sgpm_options;
+
+enum {
+    SGPM_HYBRID_PILOTS = 0,    /* timed NS and GS pilots predict both engines' times (default) */
+    SGPM_HYBRID_COST_MODEL = 1 /* the paper's profiler (10 % sparsified graph, NS-online to 50 % at 99 %,
+                                  Sec. 5.3) with the NS performance cone (Sec. 4.3) and the GS cost model
+                                  (Sec. 4.4); NS then runs with windows of 10 % of the predicted samples
+                                  (Sec. 5.4); see sgpm_host_cost_model */
+};
 
 typedef struct {
     double estimate;         /* mu = S1 / n (NS) or the mean of c^(k-1) Y over colourings (GS) */
@@ -214,6 +223,8 @@ typedef struct {
      * (the union of their intervals; below seconds_kernel when windows queued
      * ahead overlap on the second stream) */
     double seconds_kernel_busy;
+    /* loose mode with SGPM_HYBRID_COST_MODEL: the samples the profiler predicts NS needs */
+    double pred_samples;
 } sgpm_result;
 
 /* Defaults: eps 0.01, confidence 0.95, seed 1, tag 0, strict NS, n_min = w_min =
@@ -273,7 +284,9 @@ sgpm_status sgpm_bes_sparsify(sgpm_ctx_t ctx, sgpm_graph_t g, uint32_t inv_p, ui
 
 /* Train the MLP proposal on pilot NS samples of (g, patterns[0..np)) drawn with
  * tag 0x80000000 | i, using the library's BF16 MFMA forward and backward
- * kernels; train_cfg may be NULL for defaults (see sgpm_train_cfg). */
+ * kernels; train_cfg may be NULL for the defaults: 2^18 pilot samples per
+ * pattern, 8 epochs of Adam over minibatches of 2048 rows, learning rate 6e-3,
+ * seed 1 (fields left 0 take their default). */
 typedef struct {
     uint64_t pilot_samples;  /* per pattern */
     int32_t epochs;
@@ -366,25 +379,70 @@ double sgpm_host_predicted_error_t(double t, uint64_t n, const uint32_t* s1, int
  * the result is the smallest c of 4, 5, 6, 8, 10, 12, 16 predicted within 25 %
  * of the time at 16.  SGPM_EINVAL for m < 0, k outside [2, 8] or leaves16 < 0. */
 int sgpm_host_colours_choice(int64_t m, int k, double leaves16);
+/* Inputs and outputs of the loose-mode cost models (SGPM_HYBRID_COST_MODEL). */
+typedef struct {
+    double n, m;                 /* |V| and |E| (undirected) of G */
+    double triangles;            /* T, the triangle count of G (GS set-size model) */
+    double count;                /* estimated count of P on G (the profiler's, scaled) */
+    double eps, confidence, z;   /* target error bound, confidence, Phi^-1(1 - delta/2) */
+    int32_t gs_reps_max;         /* cap on colourings */
+    int32_t reserved;
+    double pilot_samples, pilot_seconds; /* NS pilot on G: samples and kernel seconds */
+    double rho_g;                /* hit rate of that pilot: rho(P, G) */
+    double prof_samples, prof_eps_hat, prof_z; /* profiler: NS-online on G' ended at N_o with eps_o, z_o */
+    double rho_sparse;           /* its hit rate: rho(P, G') */
+    double sparsify_seconds, sparsify_keep; /* one timed sparsification of G keeping a fraction of the edges */
+    double probe_colours, probe_search_seconds; /* one timed exact search of G colour-sparsified with c colours */
+} sgpm_cost_in;
+typedef struct {
+    double w_lo, w_hi;           /* NS work per sample (row entries): first break point, full walk */
+    double ns_samples;           /* N_s = N_o (eps_o / eps)^2 (z / z_o)^2 rho(P, G') / rho(P, G) */
+    double ns_lo, ns_hi;         /* NS cone: (seconds per unit of pilot work) x w_lo / w_hi x N_s */
+    double gs_seconds[7];        /* predicted GS time for 4, 5, 6, 8, 10, 12, 16 colours */
+    int32_t gs_reps[7];          /* colourings the GS stop rule needs (0: more than gs_reps_max) */
+    int32_t gs_colours;          /* the fastest colour count, 0 if none is feasible */
+    double gs_best;              /* its predicted time */
+    int32_t choice;              /* SGPM_SCHEME_GS when gs_best lies below ns_lo, else SGPM_SCHEME_NS */
+    int32_t reserved;
+} sgpm_cost_out;
+/* The loose-mode cost models on the host (Sec. 4.3, 4.4, 5.1, 5.3) for a
+ * pattern given as for sgpm_pattern_create.  NS: a row holds 2|E|/|V| entries;
+ * w_lo = 1 + rows_2 d, w_hi = 1 + sum_j rows_j d (rows_j: earlier positions a
+ * step merges).  GS at keep probability p = 1/c: preprocessing seconds per
+ * |E| (1 + p) from the timed sparsification; search work sum_j (prod_{t<j}
+ * i_t) rows_j 2|E|p/|V| with i_1 = p|E| first edges (2p|E| arcs for
+ * unoriented plans) and i_j = |V| p1 p2^(c_j - 1), halved for a bounded step,
+ * p1 = 2|E|p/|V|^2, p2 = min(1, 3T|V|/(2|E|^2)), c_j the step's pattern edges;
+ * seconds per unit from the timed search; colourings from the relative
+ * variance (c^(k-1) - 1) / count and the GS Student t stop rule.  Returns
+ * SGPM_OK, or the pattern's compile error. */
+int sgpm_host_cost_model(int k, int l, const int32_t* edges, int induced, const sgpm_cost_in* in, sgpm_cost_out* out);
 /* End of the window that starts at sample n_t under options o. */
 uint64_t sgpm_host_next_window(uint64_t n_t, const sgpm_options* o);
-/* Hybrid selection from pilot figures (loose mode, Sec. 5.1 and the NS cost
- * model of Sec. 4.3).  Pilot NS slice i took slice_seconds[i] and gave the
- * predicted error slice_eps_hat[i]; by the error equation the samples needed
- * scale with (eps_hat / eps)^2, so slice i predicts slice_seconds[i] *
- * (slice_eps_hat[i] / eps)^2 and the slices' min and max form the NS cone
- * (*ns_lo, *ns_hi; +inf for a slice without hits).  GS: gs_reps_run (1 or 2)
- * pilot colourings took gs_rep_seconds each on average; with two, gs_cv is the
- * relative standard deviation of one colouring's estimate (unbiased variance
- * over the squared mean) and GS needs the smallest R in [3, gs_reps_max] with
- * t_{R-1} gs_cv / sqrt(R) <= eps (t: two-sided Student t quantile at
- * `confidence`), +inf if there is none; with one, only the lower bound
- * 2 * gs_rep_seconds is known.  *gs_pred = R * gs_rep_seconds.  Returns
- * SGPM_SCHEME_GS when GS lies entirely below the cone, else SGPM_SCHEME_NS
- * (above or overlapping: NS keeps the guarantee); SGPM_EINVAL for bad inputs. */
-int sgpm_host_hybrid_choice(int slices, const double* slice_seconds, const double* slice_eps_hat, double eps,
-                            double confidence, int gs_reps_run, double gs_rep_seconds, double gs_cv, int gs_reps_max,
-                            double* ns_lo, double* ns_hi, double* gs_pred);
+/* The NS time cone of loose mode's pilot selector (Sec. 5.1 and the NS cost
+ * model of Sec. 4.3, measured): pilot slice i drew slice_n[i] samples in one
+ * launch of slice_seconds[i] and gave the predicted error slice_eps_hat[i].
+ * Launch time is fitted as t0 + n / rate by least squares over the slices (a
+ * fit with t0 < 0 or no positive rate falls back to t0 = 0 and the slices'
+ * mean rate).  By the error equation the samples needed scale with (eps_hat /
+ * eps)^2, so slice i predicts N_i = slice_n[i] (slice_eps_hat[i] / o->eps)^2
+ * samples taking N_i / rate + t0 x (windows of o's schedule up to N_i)
+ * seconds (+inf for a slice without hits); *lo, *hi = their min and max, *t0
+ * and *rate (nullable) the fit.  SGPM_EINVAL for bad arguments. */
+int sgpm_host_ns_cone(int slices, const double* slice_n, const double* slice_seconds, const double* slice_eps_hat,
+                      const sgpm_options* o, double* lo, double* hi, double* t0, double* rate);
+/* Hybrid selection (loose mode, Sec. 5.1) given the NS cone's lower end
+ * ns_lo.  GS: gs_reps_run (1 or 2) pilot colourings took gs_rep_seconds each
+ * on average; with two, gs_cv is the relative standard deviation of one
+ * colouring's estimate (unbiased variance over the squared mean) and GS needs
+ * the smallest R in [3, gs_reps_max] with t_{R-1} gs_cv / sqrt(R) <= eps (t:
+ * two-sided Student t quantile at `confidence`), +inf if there is none; with
+ * one, only the lower bound 2 * gs_rep_seconds is known.  *gs_pred = R *
+ * gs_rep_seconds.  Returns SGPM_SCHEME_GS when GS lies entirely below the
+ * cone, else SGPM_SCHEME_NS (above or overlapping: NS keeps the guarantee);
+ * SGPM_EINVAL for bad inputs. */
+int sgpm_host_hybrid_choice(double ns_lo, double eps, double confidence, int gs_reps_run, double gs_rep_seconds,
+                            double gs_cv, int gs_reps_max, double* gs_pred);
 
 #ifdef __cplusplus
 }

@@ -15,7 +15,7 @@ ARCH = os.environ.get("SGPM_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["api.cpp", "gs.cpp", "host_graph.cpp", "host_pattern.cpp", "host_stats.cpp", "ns_kernels.hip",
            "gs_kernels.hip", "probe_kernels.hip", "batch.cpp", "batch_kernels.hip",
-           "model.cpp", "mlp_kernels.hip", "hybrid.cpp"]
+           "model.cpp", "mlp_kernels.hip", "hybrid.cpp", "cost_model.cpp"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-ffp-contract=off", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

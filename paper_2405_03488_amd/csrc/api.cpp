@@ -403,6 +403,14 @@ sgpm_status ns_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_op
     HIP_TRY(c, ev.create());
     const hipEvent_t e0 = ev[0];  // start of the first window
     NsState s;
+    // a prefix of the estimation stream already drawn (the loose-mode pilot)
+    uint64_t prefix_n = 0;
+    if (ex && ex->prefix_n && o.mode != SGPM_MODE_FIXED_N && ex->prefix_n < next_window_end(0, o) && !ntr &&
+        !count_bytes) {
+        absorb(s, ex->prefix_sums);
+        prefix_n = ex->prefix_n;
+        s.n = prefix_n;
+    }
     int lanes = o.lanes_per_sample;
     // the learned proposal, pilot sizes and NS-base run one sample per wave
     if (learned || tr.sizes || o.sampler == SGPM_SAMPLER_BASE) lanes = 64;
@@ -412,9 +420,9 @@ sgpm_status ns_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_op
         auto it = c->ns_tuned.find(tune_key);
         if (it != c->ns_tuned.end()) lanes = it->second;
     }
-    double dev_seconds = 0.0, kernel_seconds = 0.0;
+    double dev_seconds = 0.0, kernel_seconds = prefix_n ? ex->prefix_kernel_s : 0.0;
     std::vector<std::pair<float, float>> spans;  // sampling kernels' [start, end) in ms after e0
-    int windows = 0, launches = 0;
+    int windows = 0, launches = prefix_n ? ex->prefix_launches : 0;
     bool converged = false;
     sgpm_status status = SGPM_OK;
     // Windows are decided in order, one at a time.  A launch ends with a tail
@@ -434,12 +442,15 @@ sgpm_status ns_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_op
     std::deque<Win> inflight;
     size_t depth = 1;
     const bool may_queue_ahead = o.mode != SGPM_MODE_FIXED_N && !ntr && !count_bytes;
-    uint64_t queued = 0;
+    uint64_t queued = prefix_n;
     size_t last_done = SIZE_MAX;
     HIP_TRY(c, hipEventRecord(e0, c->st));
     for (;;) {
         while (inflight.size() < depth) {
-            const uint64_t nx = o.mode == SGPM_MODE_FIXED_N ? o.fixed_n : next_window_end(queued, o);
+            // the window that holds sample `queued` (a prefix may end inside the first window)
+            // a prefix ends inside the first window, which then starts at the prefix's end
+            const uint64_t nx = o.mode == SGPM_MODE_FIXED_N ? o.fixed_n
+                                : next_window_end(queued == prefix_n ? 0 : queued, o);
             if (nx <= queued || (o.mode == SGPM_MODE_FIXED_N && queued > 0)) break;
             if (lanes == 0 && nx - queued >= (1ull << 19)) {
                 if (!inflight.empty()) break;  // tune once the queue has drained
@@ -595,7 +606,8 @@ sgpm_status ns_estimate_solo(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sg
 }
 
 sgpm_status ns_pilot(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_options& o, const LearnArgs& la,
-                     uint64_t n, int slices, double* seconds, double* eps_hat, double* mean) {
+                     int slices, const uint64_t* slice_end, double* seconds, double* eps_hat, double* mean,
+                     unsigned long long* sums_out) {
     HIP_TRY(c, hipSetDevice(c->dev));
     const double z = normal_quantile(1.0 - (1.0 - o.confidence) / 2.0);
     int lanes = o.lanes_per_sample;
@@ -605,18 +617,24 @@ sgpm_status ns_pilot(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_optio
         lanes = it != c->ns_tuned.end() ? it->second : 64;
     }
     const TraceArgs tr{nullptr, 0, 0, nullptr};
+    const uint64_t n = slice_end[slices - 1];
     for (int i = 0; i < slices; i++) {
-        const uint64_t a = n * (uint64_t)i / (uint64_t)slices, b = n * (uint64_t)(i + 1) / (uint64_t)slices;
-        sgpm_status st = enqueue_range(c, g, p, o, a, b, lanes, (size_t)i, tr, 0, la, n);
+        const uint64_t a = i ? slice_end[i - 1] : 0, b = slice_end[i];
+        sgpm_status st = enqueue_range(c, g, p, o, a, b, lanes, (size_t)i, tr, 0, la, b - a);
         if (st != SGPM_OK) return st;
     }
     HIP_TRY(c, hipStreamSynchronize(c->st));
     NsState all;
+    if (sums_out)
+        for (int w = 0; w < PF_N; w++) sums_out[w] = 0;
     for (int i = 0; i < slices; i++) {
-        const uint64_t a = n * (uint64_t)i / (uint64_t)slices, b = n * (uint64_t)(i + 1) / (uint64_t)slices;
+        const uint64_t a = i ? slice_end[i - 1] : 0, b = slice_end[i];
+        const unsigned long long* sl = c->h_slots + (size_t)i * SLOT_WORDS + 1;
         NsState s;
-        absorb(s, c->h_slots + (size_t)i * SLOT_WORDS + 1);
-        absorb(all, c->h_slots + (size_t)i * SLOT_WORDS + 1);
+        absorb(s, sl);
+        absorb(all, sl);
+        if (sums_out)
+            for (int w = 0; w < PF_N; w++) sums_out[w] += sl[w];
         s.n = b - a;
         float ms = 0;
         HIP_TRY(c, hipEventElapsedTime(&ms, c->kev[3 * (size_t)i], c->kev[3 * (size_t)i + 1]));
@@ -748,13 +766,18 @@ int sgpm_host_colours_choice(int64_t m, int k, double leaves16) {
     return (int)colours_from_probe(m, k, leaves16);
 }
 
-int sgpm_host_hybrid_choice(int slices, const double* slice_seconds, const double* slice_eps_hat, double eps,
-                            double confidence, int gs_reps_run, double gs_rep_seconds, double gs_cv, int gs_reps_max,
-                            double* ns_lo, double* ns_hi, double* gs_pred) {
-    if (slices < 1 || !slice_seconds || !slice_eps_hat || !(eps > 0) || !(confidence > 0 && confidence < 1))
+int sgpm_host_hybrid_choice(double ns_lo, double eps, double confidence, int gs_reps_run, double gs_rep_seconds,
+                            double gs_cv, int gs_reps_max, double* gs_pred) {
+    if (!(eps > 0) || !(confidence > 0 && confidence < 1)) return SGPM_EINVAL;
+    return hybrid_choice(ns_lo, eps, confidence, gs_reps_run, gs_rep_seconds, gs_cv, gs_reps_max, gs_pred);
+}
+
+int sgpm_host_ns_cone(int slices, const double* slice_n, const double* slice_seconds, const double* slice_eps_hat,
+                      const sgpm_options* o, double* lo, double* hi, double* t0, double* rate) {
+    if (slices < 1 || !slice_n || !slice_seconds || !slice_eps_hat || !o || !lo || !hi || !(o->eps > 0))
         return SGPM_EINVAL;
-    return hybrid_choice(slices, slice_seconds, slice_eps_hat, eps, confidence, gs_reps_run, gs_rep_seconds, gs_cv,
-                         gs_reps_max, ns_lo, ns_hi, gs_pred);
+    ns_cone(slices, slice_n, slice_seconds, slice_eps_hat, *o, lo, hi, t0, rate);
+    return SGPM_OK;
 }
 
 }  // extern "C"

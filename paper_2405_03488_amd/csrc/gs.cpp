@@ -53,7 +53,7 @@ enum GsSlot : size_t { GS_COL, GS_RSTART, GS_RLOW, GS_TK, GS_TL, GS_TKO, GS_TLO,
 
 // colours: c of colour sparsification, or (bes) the inverse keep probability
 sgpm_status sparsify(sgpm_ctx* c, sgpm_graph* g, uint32_t colours, uint64_t seed, uint32_t rep, sgpm_graph** out,
-                     bool bes = false) {
+                     bool bes) {
     if (colours < 1 || colours > 256) return fail(c, SGPM_EINVAL, "colours must be in [1, 256]");
     HIP_TRY(c, hipSetDevice(c->dev));
     const int64_t n = g->n;

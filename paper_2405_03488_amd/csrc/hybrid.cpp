@@ -9,10 +9,14 @@
 // confidence guarantee.  Its profiler and GS cost formulas are not usable as
 // printed, so both predictions here come from measurements on this device:
 //
-//  * NS: a pilot of P samples on a separate Philox stream (tag 0x80000000 | q),
-//    in S equal slices.  By the error equation (Sec. 4.1) the samples needed for
-//    eps scale as (eps_hat / eps)^2, so slice i predicts t_i (eps_hat_i / eps)^2
-//    with t_i its kernel time; the slices' minimum and maximum are the cone.
+//  * NS: a pilot of the estimation stream itself (tag q, sample ids [0, P) with
+//    P inside the first window) in four slices of P/8, P/8, P/4 and P/2
+//    samples, one launch each.  Their kernel times fit t0 + n / rate (the
+//    launch's fixed cost and the steady rate).  By the error equation (Sec.
+//    4.1) the samples needed for eps scale as (eps_hat / eps)^2, so slice i
+//    predicts N_i = n_i (eps_hat_i / eps)^2 samples taking N_i / rate plus t0
+//    per window of the schedule up to N_i; the slices' minimum and maximum are
+//    the cone.  When NS runs, the pilot's samples are its first ones.
 //  * GS: colourings 0 and 1 of the GS engine itself (timed end to end:
 //    sparsification and count).  Their relative spread (the unbiased standard
 //    deviation of one colouring's estimate over their mean, cv) gives the
@@ -28,9 +32,10 @@
 //    2m / (n c) below 16; the count kernel measures 1.4e9 to 3.7e9 there) and
 //    1e11 otherwise (long rows: 4.1e10 measured for the 4-clique on R-MAT 20).
 //
-// The engine then runs exactly as in its own mode with the same options (GS
-// reuses the two pilot colourings, which are its first two), so a hybrid result
-// equals the strict-NS or GS result bit for bit.
+// The engine then runs exactly as in its own mode with the same options (NS
+// continues the pilot's stream, GS reuses the two pilot colourings, which are
+// its first two), so a hybrid result equals the strict-NS or GS result bit for
+// bit.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -50,16 +55,53 @@ int gs_reps_needed(double cv, double eps, double confidence, int cap) {
     return 0;
 }
 
-int hybrid_choice(int slices, const double* slice_seconds, const double* slice_eps_hat, double eps, double confidence,
-                  int gs_reps_run, double gs_rep_seconds, double gs_cv, int gs_reps_max, double* ns_lo, double* ns_hi,
-                  double* gs_pred) {
-    double lo = INFINITY, hi = 0.0;
+void ns_cone(int slices, const double* slice_n, const double* seconds, const double* eps_hat, const sgpm_options& o,
+             double* lo, double* hi, double* t0_out, double* rate_out) {
+    // least-squares fit of t = t0 + n / rate; a fit without a positive rate or
+    // with a negative fixed cost falls back to the plain rate of all slices
+    double sn = 0, st = 0, snn = 0, snt = 0;
     for (int i = 0; i < slices; i++) {
-        const double r = slice_eps_hat[i] / eps;
-        const double t = std::isfinite(r) ? slice_seconds[i] * r * r : INFINITY;
-        lo = std::min(lo, t);
-        hi = std::max(hi, t);
+        sn += slice_n[i];
+        st += seconds[i];
+        snn += slice_n[i] * slice_n[i];
+        snt += slice_n[i] * seconds[i];
     }
+    const double den = slices * snn - sn * sn;
+    double slope = den > 0 ? (slices * snt - sn * st) / den : 0.0;
+    double t0 = slices > 0 ? (st - slope * sn) / slices : 0.0;
+    if (!(slope > 0) || !(t0 >= 0)) {
+        t0 = 0.0;
+        slope = sn > 0 ? st / sn : 0.0;
+    }
+    double l = INFINITY, h = 0.0;
+    for (int i = 0; i < slices; i++) {
+        const double r = eps_hat[i] / o.eps;
+        double t = INFINITY;
+        if (std::isfinite(r)) {
+            const double need = slice_n[i] * r * r;
+            // windows of the schedule up to `need` samples (at least one)
+            int w = 0;
+            uint64_t e = 0;
+            while (w < 100000) {
+                const uint64_t nx = next_window_end(e, o);
+                w++;
+                if ((double)nx >= need || nx <= e) break;
+                e = nx;
+            }
+            t = need * slope + t0 * w;
+        }
+        l = std::min(l, t);
+        h = std::max(h, t);
+    }
+    if (slices == 0) l = h = INFINITY;
+    *lo = l;
+    *hi = h;
+    if (t0_out) *t0_out = t0;
+    if (rate_out) *rate_out = slope > 0 ? 1.0 / slope : 0.0;
+}
+
+int hybrid_choice(double ns_lo, double eps, double confidence, int gs_reps_run, double gs_rep_seconds, double gs_cv,
+                  int gs_reps_max, double* gs_pred) {
     double gs = INFINITY;
     if (gs_reps_run >= 2) {
         const int need = gs_reps_needed(gs_cv, eps, confidence, gs_reps_max > 0 ? gs_reps_max : 64);
@@ -67,11 +109,9 @@ int hybrid_choice(int slices, const double* slice_seconds, const double* slice_e
     } else if (gs_reps_run == 1) {
         gs = 2.0 * gs_rep_seconds;  // a lower bound: GS needs two colourings at least
     }
-    if (ns_lo) *ns_lo = lo;
-    if (ns_hi) *ns_hi = hi;
     if (gs_pred) *gs_pred = gs;
     // GS entirely below the cone; a one-colouring bound never selects GS
-    return (gs_reps_run >= 2 && gs < lo) ? SGPM_SCHEME_GS : SGPM_SCHEME_NS;
+    return (gs_reps_run >= 2 && gs < ns_lo) ? SGPM_SCHEME_GS : SGPM_SCHEME_NS;
 }
 
 namespace {
@@ -106,6 +146,12 @@ double gs_pilot_cv(const GsPrefix& pre, const Plan& p, uint32_t col) {
 }  // namespace
 
 sgpm_status hybrid_estimate(sgpm_ctx* c, sgpm_graph* g, sgpm_pattern* pat, const sgpm_options& o, sgpm_result* res) {
+    if (o.hybrid_selector == SGPM_HYBRID_COST_MODEL) {
+        if (o.proposal) return fail(c, SGPM_EUNSUPPORTED, "the cost-model selector runs the uniform proposal");
+        if (o.colours < 0 || o.colours > 256) return fail(c, SGPM_EINVAL, "colours must be 0 (choose) or in [1, 256]");
+        return model_hybrid_estimate(c, g, pat, o, res);
+    }
+    if (o.hybrid_selector != SGPM_HYBRID_PILOTS) return fail(c, SGPM_EINVAL, "hybrid_selector");
     using clk = std::chrono::steady_clock;
     const auto t0 = clk::now();
     const Plan& p = pat->plan;
@@ -124,19 +170,27 @@ sgpm_status hybrid_estimate(sgpm_ctx* c, sgpm_graph* g, sgpm_pattern* pat, const
         if (st != SGPM_OK) return st;
     }
     if (M > 0) {
-        // NS pilot on its own stream of draws
+        // NS pilot: the first samples of the estimation stream, inside its first window
         constexpr int kSlices = 4;
         sgpm_options po = o;
-        po.query_tag = 0x80000000u | o.query_tag;
-        po.checksum = 0;
+        po.checksum = o.checksum;
         po.trace_lo = po.trace_hi = 0;
         po.trace_buf = nullptr;
-        const uint64_t n_pilot = std::max<uint64_t>(1ull << 16, o.n_min / 4);
-        double sec[kSlices], eh[kSlices], mu = 0.0;
-        sgpm_status st = ns_pilot(c, g, p, po, ex.la, n_pilot, kSlices, sec, eh, &mu);
+        const uint64_t first = next_window_end(0, o);
+        uint64_t n_pilot = std::max<uint64_t>(1ull << 16, o.n_min / 4);
+        if (n_pilot >= first) n_pilot = first / 2;
+        n_pilot = std::max<uint64_t>(8, n_pilot / 8 * 8);
+        const uint64_t ends[kSlices] = {n_pilot / 8, n_pilot / 4, n_pilot / 2, n_pilot};
+        double sn[kSlices], sec[kSlices], eh[kSlices], mu = 0.0;
+        for (int i = 0; i < kSlices; i++) sn[i] = (double)(ends[i] - (i ? ends[i - 1] : 0));
+        sgpm_status st = ns_pilot(c, g, p, po, ex.la, kSlices, ends, sec, eh, &mu, ex.prefix_sums);
         if (st != SGPM_OK) return st;
-        (void)hybrid_choice(kSlices, sec, eh, o.eps, o.confidence, 0, 0.0, 0.0, o.gs_reps_max, &ns_lo, &ns_hi,
-                            nullptr);
+        if (n_pilot < first) {
+            ex.prefix_n = n_pilot;
+            ex.prefix_launches = kSlices;
+            for (double x : sec) ex.prefix_kernel_s += x;
+        }
+        ns_cone(kSlices, sn, sec, eh, o, &ns_lo, &ns_hi, nullptr, nullptr);
         // lower bound of two colourings from the leaves they must reach
         double leaves = mu;
         for (int i = 0; i < p.k - 1; i++) leaves /= (double)col;
@@ -159,8 +213,7 @@ sgpm_status hybrid_estimate(sgpm_ctx* c, sgpm_graph* g, sgpm_pattern* pat, const
         } else {
             rep_seconds /= pre.n;
             const double cv = pre.n >= 2 ? gs_pilot_cv(pre, p, col) : INFINITY;
-            scheme = hybrid_choice(kSlices, sec, eh, o.eps, o.confidence, pre.n, rep_seconds, cv, o.gs_reps_max,
-                                   &ns_lo, &ns_hi, &gs_pred);
+            scheme = hybrid_choice(ns_lo, o.eps, o.confidence, pre.n, rep_seconds, cv, o.gs_reps_max, &gs_pred);
         }
     }
     const double pilot = std::chrono::duration<double>(clk::now() - t0).count();
@@ -172,7 +225,7 @@ sgpm_status hybrid_estimate(sgpm_ctx* c, sgpm_graph* g, sgpm_pattern* pat, const
     } else {
         sgpm_options no = o;
         no.mode = SGPM_MODE_STRICT_NS;
-        st = ns_estimate_solo(c, g, p, no, res, 0, o.proposal ? &ex : nullptr);
+        st = ns_estimate_solo(c, g, p, no, res, 0, &ex);
     }
     res->pred_ns_lo = ns_lo;
     res->pred_ns_hi = ns_hi;

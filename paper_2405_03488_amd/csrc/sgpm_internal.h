@@ -117,6 +117,13 @@ hipError_t launch_batch(const BatchQuery* q, BatchState* s, int nq, unsigned lon
 struct NsExtra {
     LearnArgs la;        // learned proposal (table nullptr = uniform)
     uint32_t* d_sizes;   // pilot traces: |S_j| per traced sample
+    // samples [0, prefix_n) of the estimation stream already drawn (the
+    // loose-mode pilot): their window sums, kernel seconds and launches; used
+    // by a strict run when prefix_n lies inside its first window
+    uint64_t prefix_n;
+    unsigned long long prefix_sums[PF_N];
+    double prefix_kernel_s;
+    int prefix_launches;
 };
 
 // MLP (mlp_kernels.hip)
@@ -271,12 +278,23 @@ sgpm_status ns_estimate_solo(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sg
 // (the caller sets the tag); per slice the kernel seconds and predicted error,
 // and the estimate of the count over the whole pilot
 sgpm_status ns_pilot(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_options& o, const LearnArgs& la,
-                     uint64_t n, int slices, double* seconds, double* eps_hat, double* mean);
+                     int slices, const uint64_t* slice_end, double* seconds, double* eps_hat, double* mean,
+                     unsigned long long* sums_out);
+// NS time cone from pilot slices (one launch each): launch time fitted as
+// t0 + n / rate over the slices; slice i predicts n_i (eps_hat_i / eps)^2
+// samples in N / rate + t0 x (windows of the schedule of o up to N) seconds
+void ns_cone(int slices, const double* slice_n, const double* seconds, const double* eps_hat, const sgpm_options& o,
+             double* lo, double* hi, double* t0_out, double* rate_out);
 sgpm_status learn_args_for(sgpm_ctx* c, sgpm_graph* g, sgpm_pattern* p, sgpm_model* m, LearnArgs* la);
 sgpm_status hybrid_estimate(sgpm_ctx* c, sgpm_graph* g, sgpm_pattern* p, const sgpm_options& o, sgpm_result* res);
-int hybrid_choice(int slices, const double* slice_seconds, const double* slice_eps_hat, double eps, double confidence,
-                  int gs_reps_run, double gs_rep_seconds, double gs_cv, int gs_reps_max, double* ns_lo, double* ns_hi,
-                  double* gs_pred);
+sgpm_status model_hybrid_estimate(sgpm_ctx* c, sgpm_graph* g, sgpm_pattern* p, const sgpm_options& o,
+                                  sgpm_result* res);
+void cost_model(const Plan& p, const sgpm_cost_in& in, sgpm_cost_out* out);
+sgpm_status sparsify(sgpm_ctx* c, sgpm_graph* g, uint32_t colours, uint64_t seed, uint32_t rep, sgpm_graph** out,
+                     bool bes = false);
+sgpm_status exact_count(sgpm_ctx* c, sgpm_graph* g, const Plan& p, unsigned __int128* out, double* seconds);
+int hybrid_choice(double ns_lo, double eps, double confidence, int gs_reps_run, double gs_rep_seconds, double gs_cv,
+                  int gs_reps_max, double* gs_pred);
 int gs_reps_needed(double cv, double eps, double confidence, int cap);
 // the GS stop rule tests its interval from the third sparsification on
 constexpr uint64_t kGsMinReps = 3;

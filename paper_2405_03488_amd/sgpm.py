@@ -29,6 +29,7 @@ SGPM_SYMMETRIZE = 0x4
 
 MODE_STRICT_NS, MODE_FIXED_N, MODE_GS, MODE_HYBRID = 0, 1, 2, 3
 SAMPLER_PRUNE, SAMPLER_BASE = 0, 1
+HYBRID_PILOTS, HYBRID_COST_MODEL = 0, 1
 GS_COLOUR, GS_BERNOULLI = 0, 1
 SCHEME_NS, SCHEME_GS, SCHEME_EXACT = 0, 1, 2
 
@@ -49,7 +50,7 @@ class Options(C.Structure):
                 ("colours", C.c_int32), ("gs_reps_max", C.c_int32), ("proposal", C.c_void_p),
                 ("lanes_per_sample", C.c_int32), ("checksum", C.c_int32), ("trace_lo", C.c_uint64),
                 ("trace_hi", C.c_uint64), ("trace_buf", C.c_void_p), ("sampler", C.c_int32),
-                ("gs_scheme", C.c_int32)]
+                ("gs_scheme", C.c_int32), ("hybrid_selector", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -61,7 +62,8 @@ class Result(C.Structure):
                 ("bytes", C.c_uint64), ("seconds_sampling", C.c_double), ("seconds_total", C.c_double),
                 ("seconds_kernel", C.c_double), ("tile", C.c_int32), ("weight_shift", C.c_int32),
                 ("reserved0", C.c_int32), ("pred_ns_lo", C.c_double), ("pred_ns_hi", C.c_double),
-                ("pred_gs", C.c_double), ("seconds_pilot", C.c_double), ("seconds_kernel_busy", C.c_double)]
+                ("pred_gs", C.c_double), ("seconds_pilot", C.c_double), ("seconds_kernel_busy", C.c_double),
+                ("pred_samples", C.c_double)]
 
     @property
     def S1(self) -> int:
@@ -70,6 +72,21 @@ class Result(C.Structure):
     @property
     def S2(self) -> int:
         return sum(int(d) << (32 * i) for i, d in enumerate(self.sumsq_digits))
+
+
+class CostIn(C.Structure):
+    _fields_ = [("n", C.c_double), ("m", C.c_double), ("triangles", C.c_double), ("count", C.c_double),
+                ("eps", C.c_double), ("confidence", C.c_double), ("z", C.c_double), ("gs_reps_max", C.c_int32),
+                ("reserved", C.c_int32), ("pilot_samples", C.c_double), ("pilot_seconds", C.c_double),
+                ("rho_g", C.c_double), ("prof_samples", C.c_double), ("prof_eps_hat", C.c_double),
+                ("prof_z", C.c_double), ("rho_sparse", C.c_double), ("sparsify_seconds", C.c_double),
+                ("sparsify_keep", C.c_double), ("probe_colours", C.c_double), ("probe_search_seconds", C.c_double)]
+
+
+class CostOut(C.Structure):
+    _fields_ = [("w_lo", C.c_double), ("w_hi", C.c_double), ("ns_samples", C.c_double), ("ns_lo", C.c_double),
+                ("ns_hi", C.c_double), ("gs_seconds", C.c_double * 7), ("gs_reps", C.c_int32 * 7),
+                ("gs_colours", C.c_int32), ("gs_best", C.c_double), ("choice", C.c_int32), ("reserved", C.c_int32)]
 
 
 class TrainCfg(C.Structure):
@@ -133,10 +150,12 @@ def lib():
             "sgpm_host_predicted_error": ([C.c_double, C.c_uint64, P, C.c_int, P, C.c_int], C.c_double),
             "sgpm_host_next_window": ([C.c_uint64, C.POINTER(Options)], C.c_uint64),
             "sgpm_host_t_quantile": ([C.c_double, C.c_int], C.c_double),
+            "sgpm_host_cost_model": ([C.c_int, C.c_int, P, C.c_int, C.POINTER(CostIn), C.POINTER(CostOut)], C.c_int),
             "sgpm_host_colours_choice": ([C.c_int64, C.c_int, C.c_double], C.c_int),
             "sgpm_host_predicted_error_t": ([C.c_double, C.c_uint64, P, C.c_int, P, C.c_int], C.c_double),
-            "sgpm_host_hybrid_choice": ([C.c_int, P, P, C.c_double, C.c_double, C.c_int, C.c_double, C.c_double,
-                                         C.c_int, P, P, P], C.c_int),
+            "sgpm_host_hybrid_choice": ([C.c_double, C.c_double, C.c_double, C.c_int, C.c_double, C.c_double,
+                                         C.c_int, P], C.c_int),
+            "sgpm_host_ns_cone": ([C.c_int, P, P, P, C.POINTER(Options), P, P, P, P], C.c_int),
         }
         for name, (args, res) in sig.items():
             if hasattr(L, name):
@@ -155,7 +174,8 @@ EXPORTED = ["sgpm_create", "sgpm_destroy", "sgpm_last_error", "sgpm_device_count
             "sgpm_model_from_tables", "sgpm_model_table", "sgpm_model_info", "sgpm_mlp_forward", "sgpm_mlp_grad",
             "sgpm_mlp_adam_steps",
             "sgpm_probe_copy", "sgpm_probe_gather", "sgpm_probe_mlp", "sgpm_host_canonicalise", "sgpm_host_plan", "sgpm_host_normal_quantile", "sgpm_host_predicted_error",
-            "sgpm_host_t_quantile", "sgpm_host_predicted_error_t", "sgpm_host_colours_choice", "sgpm_host_next_window", "sgpm_host_hybrid_choice"]
+            "sgpm_host_t_quantile", "sgpm_host_predicted_error_t", "sgpm_host_colours_choice", "sgpm_host_cost_model", "sgpm_host_next_window", "sgpm_host_hybrid_choice",
+            "sgpm_host_ns_cone"]
 
 
 class SgpmError(RuntimeError):
@@ -363,6 +383,15 @@ def sgpm_host_predicted_error_t(t, n, S1: int, S2: int):
     return float(lib().sgpm_host_predicted_error_t(t, n, d1.ctypes.data, 8, d2.ctypes.data, 12))
 
 
+def sgpm_host_cost_model(k, edges, cin: CostIn, induced=False) -> CostOut:
+    e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 2))
+    out = CostOut()
+    rc = lib().sgpm_host_cost_model(k, len(e), e.ctypes.data, int(bool(induced)), C.byref(cin), C.byref(out))
+    if rc != SGPM_OK:
+        raise SgpmError(rc, "cost model: pattern compile failed")
+    return out
+
+
 def sgpm_host_colours_choice(m, k, leaves16):
     return int(lib().sgpm_host_colours_choice(m, k, leaves16))
 
@@ -371,17 +400,27 @@ def sgpm_host_next_window(n_t, opts: Options):
     return int(lib().sgpm_host_next_window(n_t, C.byref(opts)))
 
 
-def sgpm_host_hybrid_choice(slice_seconds, slice_eps_hat, eps, gs_reps_run, gs_rep_seconds, gs_cv,
-                            gs_reps_max=64, confidence=0.95):
-    """(scheme, ns_lo, ns_hi, gs_pred) from pilot figures; see include/sgpm.h."""
-    sec = np.ascontiguousarray(slice_seconds, dtype=np.float64)
-    eh = np.ascontiguousarray(slice_eps_hat, dtype=np.float64)
-    lo, hi, gs = C.c_double(), C.c_double(), C.c_double()
-    rc = lib().sgpm_host_hybrid_choice(len(sec), sec.ctypes.data, eh.ctypes.data, eps, confidence, gs_reps_run,
-                                       gs_rep_seconds, gs_cv, gs_reps_max, C.byref(lo), C.byref(hi), C.byref(gs))
+def sgpm_host_hybrid_choice(ns_lo, eps, gs_reps_run, gs_rep_seconds, gs_cv, gs_reps_max=64, confidence=0.95):
+    """(scheme, gs_pred) from the NS cone's lower end and GS pilot figures; see include/sgpm.h."""
+    gs = C.c_double()
+    rc = lib().sgpm_host_hybrid_choice(ns_lo, eps, confidence, gs_reps_run, gs_rep_seconds, gs_cv, gs_reps_max,
+                                       C.byref(gs))
     if rc < 0:
         raise SgpmError(rc, "invalid hybrid pilot figures")
-    return rc, lo.value, hi.value, gs.value
+    return rc, gs.value
+
+
+def sgpm_host_ns_cone(slice_n, slice_seconds, slice_eps_hat, opts: Options):
+    """(lo, hi, t0, rate) of the NS time cone from pilot slices; see include/sgpm.h."""
+    n = np.ascontiguousarray(slice_n, dtype=np.float64)
+    sec = np.ascontiguousarray(slice_seconds, dtype=np.float64)
+    eh = np.ascontiguousarray(slice_eps_hat, dtype=np.float64)
+    lo, hi, t0, rate = C.c_double(), C.c_double(), C.c_double(), C.c_double()
+    rc = lib().sgpm_host_ns_cone(len(n), n.ctypes.data, sec.ctypes.data, eh.ctypes.data, C.byref(opts), C.byref(lo),
+                                 C.byref(hi), C.byref(t0), C.byref(rate))
+    if rc < 0:
+        raise SgpmError(rc, "invalid pilot slices")
+    return lo.value, hi.value, t0.value, rate.value
 
 
 def sgpm_probe_copy(ctx, nbytes, iters=10) -> float:

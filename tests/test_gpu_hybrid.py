@@ -6,6 +6,8 @@ Philox stream; the GS pilot colourings are the GS run's first two).  Two
 clear-cut cases check the choice itself: a common pattern on a power-law
 graph (NS), and a handful of planted 5-cliques in a large sparse graph, where
 NS pilots see almost no hits while one exact count is cheap (GS)."""
+import math
+
 import numpy as np
 import pytest
 
@@ -100,5 +102,58 @@ def test_hybrid_on_an_edgeless_graph(S, synth, ctx):
     p = S.sgpm_pattern_create(ctx, *synth.pattern("triangle"))
     r, _ = S.sgpm_estimate(ctx, g, p, S.sgpm_options_default(mode=S.MODE_HYBRID))
     assert r.scheme == S.SCHEME_NS and r.estimate == 0.0 and r.converged == 1
+    S.sgpm_pattern_free(p)
+    S.sgpm_graph_free(g)
+
+
+def windows_for(S, pred_samples, quantum):
+    q = quantum or 1
+    return max(q, math.ceil(0.1 * pred_samples / q) * q)
+
+
+@pytest.mark.parametrize("name", ["triangle", "4-clique", "diamond"])
+def test_cost_model_selector_runs_the_chosen_engine(S, O, synth, ctx, name):
+    """Loose mode with the paper's profiler and cost models: the result equals
+    the chosen engine run on its own -- NS with windows of 10 % of the
+    predicted samples (and the oracle's run with those windows), or GS at the
+    chosen colour count."""
+    n = 3000
+    off, nbr = synth.pairs_to_csr(n, synth.chung_lu_pairs(n, 12, 2.1, 8))
+    g = S.sgpm_graph_from_csr(ctx, n, off, nbr)
+    og = O.OGraph.from_raw_csr(n, off, nbr)
+    k, e = synth.pattern(name)
+    p = S.sgpm_pattern_create(ctx, k, e)
+    kw = dict(eps=0.05, seed=17, checksum=1, quantum=1 << 10)
+    rh, _ = S.sgpm_estimate(ctx, g, p, S.sgpm_options_default(mode=S.MODE_HYBRID,
+                                                              hybrid_selector=S.HYBRID_COST_MODEL, **kw))
+    assert rh.seconds_pilot > 0 and rh.pred_ns_lo <= rh.pred_ns_hi
+    if rh.scheme == S.SCHEME_NS:
+        w = windows_for(S, rh.pred_samples, kw["quantum"])
+        ro, _ = S.sgpm_estimate(ctx, g, p, S.sgpm_options_default(n_min=w, w_min=w, window_growth=0.0, **kw))
+        same(rh, ro)
+        orr = O.run(og, O.compile_plan(k, e), O.make_opts(eps=0.05, seed=17, n_min=w, w_min=w, growth=0.0,
+                                                           quantum=kw["quantum"]))
+        assert (rh.n_samples, rh.S1, rh.S2, rh.checksum) == (orr.n, orr.S1, orr.S2, orr.checksum)
+    else:
+        ro, _ = S.sgpm_estimate(ctx, g, p, S.sgpm_options_default(mode=S.MODE_GS, colours=rh.colours, **kw))
+        same(rh, ro)
+    S.sgpm_pattern_free(p)
+    S.sgpm_graph_free(g)
+
+
+def test_cost_model_selector_picks_gs_for_rare_matches(S, O, synth, ctx):
+    """A few planted 5-cliques in a large sparse graph: NS pilots find no hit,
+    so NS cannot be predicted and GS runs; one colour makes it exact."""
+    n = 200000
+    pairs = planted(synth, n, 200000, 8, 5, 11)
+    off, nbr = synth.pairs_to_csr(n, pairs)
+    g = S.sgpm_graph_from_csr(ctx, n, off, nbr)
+    og = O.OGraph.from_raw_csr(n, off, nbr)
+    k, e = synth.pattern("5-clique")
+    p = S.sgpm_pattern_create(ctx, k, e)
+    exact = O.plan_count(og, O.compile_plan(k, e))
+    rh, _ = S.sgpm_estimate(ctx, g, p, S.sgpm_options_default(mode=S.MODE_HYBRID, hybrid_selector=S.HYBRID_COST_MODEL,
+                                                              eps=0.02, seed=9, colours=1))
+    assert rh.scheme == S.SCHEME_GS and rh.estimate == exact and rh.converged == 1
     S.sgpm_pattern_free(p)
     S.sgpm_graph_free(g)

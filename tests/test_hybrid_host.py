@@ -1,8 +1,9 @@
 """Loose-mode selection rule (Sec. 5.1) on the host, and the premise of its
 NS prediction checked with the oracle.
 
-The rule: each NS pilot slice predicts t_i (eps_hat_i / eps)^2 and the slices'
-minimum and maximum form the NS cone; two GS pilot colourings with relative
+The rule: pilot slices of different sizes fit each launch's time as t0 + n/rate;
+slice i predicts N_i = n_i (eps_hat_i / eps)^2 samples, taking N_i / rate plus t0
+per window up to N_i, and the slices' minimum and maximum form the NS cone; two GS pilot colourings with relative
 spread cv predict the smallest R >= 3 with t_{R-1} cv / sqrt(R) <= eps
 colourings (the GS stop rule's Student t interval) at the mean colouring time;
 GS runs only when its prediction lies entirely below the cone."""
@@ -27,68 +28,88 @@ def S():
     return sgpm
 
 
-def test_cone_from_slices(S):
-    sc, lo, hi, gs = S.sgpm_host_hybrid_choice([1e-3, 2e-3, 1e-3, 1e-3], [0.1, 0.1, 0.2, 0.05], 0.01, 2, 0.5, 0.0)
-    assert lo == pytest.approx(1e-3 * 25) and hi == pytest.approx(1e-3 * 400)
-    assert gs == pytest.approx(1.5)  # three colourings (the rule's minimum) when they agree exactly
-    assert sc == S.SCHEME_NS  # 1.5 s is above the cone's lower end 0.025 s
+def test_cone_fit_and_windows(S, O):
+    """Slices of 1/8, 1/8, 1/4, 1/2 of the pilot: times t0 + n/rate exactly,
+    so the fit recovers t0 and rate; slice i predicts N_i = n_i (e_i/eps)^2
+    samples in N_i / rate + t0 per window of the schedule up to N_i."""
+    o = S.sgpm_options_default(n_min=1 << 16, w_min=1 << 15, quantum=1 << 10, window_growth=0.1)
+    n = [8192, 8192, 16384, 32768]
+    t0, rate = 5e-5, 1e9
+    sec = [t0 + x / rate for x in n]
+    eh = [0.05, 0.04, 0.045, 0.03]
+    lo, hi, ft0, frate = S.sgpm_host_ns_cone(n, sec, eh, o)
+    assert ft0 == pytest.approx(t0, rel=1e-9) and frate == pytest.approx(rate, rel=1e-9)
+    oo = O.make_opts(n_min=1 << 16, w_min=1 << 15, quantum=1 << 10, growth=0.1)
+    preds = []
+    for ni, ei in zip(n, eh):
+        need = ni * (ei / 0.01) ** 2
+        w, e = 0, 0
+        while True:
+            nx = O.window_next(e, oo)
+            w += 1
+            if nx >= need or nx <= e:
+                break
+            e = nx
+        preds.append(need / rate + t0 * w)
+    assert lo == pytest.approx(min(preds), rel=1e-12) and hi == pytest.approx(max(preds), rel=1e-12)
 
 
-def test_gs_below_cone_selects_gs(S):
-    sc, lo, hi, gs = S.sgpm_host_hybrid_choice([0.01] * 4, [1.0, 2.0, 1.5, 1.2], 0.01, 2, 0.2, 0.03)
+def test_cone_fallback_and_missing_hits(S):
+    o = S.sgpm_options_default(n_min=1 << 16, w_min=1 << 16, quantum=1 << 10)
+    # times falling with size: no positive rate in the fit -> the slices' mean rate, t0 = 0
+    lo, hi, t0, rate = S.sgpm_host_ns_cone([1000, 2000], [2e-3, 1e-3], [0.1, 0.1], o)
+    assert t0 == 0.0 and rate == pytest.approx(3000 / 3e-3)
+    # a slice without hits makes the upper end infinite; all without: the lower end too
+    inf = float("inf")
+    lo, hi, *_ = S.sgpm_host_ns_cone([1000, 2000], [1e-4, 2e-4], [0.1, inf], o)
+    assert math.isfinite(lo) and math.isinf(hi)
+    lo, hi, *_ = S.sgpm_host_ns_cone([1000, 2000], [1e-4, 2e-4], [inf, inf], o)
+    assert math.isinf(lo) and math.isinf(hi)
+    with pytest.raises(S.SgpmError):
+        S.sgpm_host_ns_cone([], [], [], o)
+
+
+def test_gs_prediction_and_choice(S):
+    # three colourings (the rule's minimum) when they agree exactly
+    sc, gs = S.sgpm_host_hybrid_choice(0.025, 0.01, 2, 0.5, 0.0)
+    assert gs == pytest.approx(1.5) and sc == S.SCHEME_NS  # 1.5 s is above the cone's lower end
+    sc, gs = S.sgpm_host_hybrid_choice(100.0, 0.01, 2, 0.2, 0.03)
     R = _reps(0.03, 0.01, 64)
-    assert 36 < R < 64 and gs == pytest.approx(R * 0.2)
-    assert lo == pytest.approx(0.01 * 1e4) and sc == S.SCHEME_GS
-
-
-def test_overlap_and_above_select_ns(S):
-    # GS inside the cone: NS keeps the guarantee
-    sc, lo, hi, gs = S.sgpm_host_hybrid_choice([1.0, 1.0], [0.01, 0.02], 0.01, 2, 1.5, 0.0)
-    assert lo == 1.0 and hi == 4.0 and gs == 4.5 and sc == S.SCHEME_NS
-    # GS above the cone
-    sc, *_ = S.sgpm_host_hybrid_choice([1.0, 1.0], [0.01, 0.02], 0.01, 2, 10.0, 0.0)
-    assert sc == S.SCHEME_NS
+    assert 36 < R < 64 and gs == pytest.approx(R * 0.2) and sc == S.SCHEME_GS
     # exactly at the lower end is not below it
-    assert 3 * (1 / 3) == 1.0
-    sc, lo, hi, gs = S.sgpm_host_hybrid_choice([1.0], [0.01], 0.01, 2, 1 / 3, 0.0)
-    assert gs == lo
-    assert sc == S.SCHEME_NS
+    sc, gs = S.sgpm_host_hybrid_choice(1.0, 0.01, 2, 1 / 3, 0.0)
+    assert gs == 1.0 and sc == S.SCHEME_NS
 
 
 def test_one_colouring_never_selects_gs(S):
-    sc, lo, hi, gs = S.sgpm_host_hybrid_choice([1.0], [1.0], 0.01, 1, 1e-9, float("nan"))
+    sc, gs = S.sgpm_host_hybrid_choice(1.0, 0.01, 1, 1e-9, float("nan"))
     assert gs == pytest.approx(2e-9) and sc == S.SCHEME_NS
 
 
 def test_missing_hits_and_caps(S):
     inf = float("inf")
-    # no NS pilot hits anywhere: the cone is unbounded, a finite GS wins
-    sc, lo, hi, gs = S.sgpm_host_hybrid_choice([1e-3] * 4, [inf] * 4, 0.01, 2, 5.0, 0.0)
-    assert math.isinf(lo) and math.isinf(hi) and sc == S.SCHEME_GS
+    # no NS pilot hits: the cone is unbounded, a finite GS wins
+    sc, gs = S.sgpm_host_hybrid_choice(inf, 0.01, 2, 5.0, 0.0)
+    assert sc == S.SCHEME_GS
     # GS colourings all zero as well: nothing can be predicted, NS runs
-    sc, lo, hi, gs = S.sgpm_host_hybrid_choice([1e-3] * 4, [inf] * 4, 0.01, 2, 5.0, inf)
+    sc, gs = S.sgpm_host_hybrid_choice(inf, 0.01, 2, 5.0, inf)
     assert math.isinf(gs) and sc == S.SCHEME_NS
-    # some slices without hits: the cone's upper end is unbounded
-    sc, lo, hi, gs = S.sgpm_host_hybrid_choice([1e-3, 1e-3], [0.5, inf], 0.01, 2, 5.0, 0.0)
-    assert lo == pytest.approx(2.5) and math.isinf(hi)
     # more colourings than gs_reps_max: GS cannot meet eps
-    sc, lo, hi, gs = S.sgpm_host_hybrid_choice([1.0], [10.0], 0.01, 2, 1e-6, 0.2, 64)
+    sc, gs = S.sgpm_host_hybrid_choice(1000.0, 0.01, 2, 1e-6, 0.2, 64)
     assert math.isinf(gs) and sc == S.SCHEME_NS
-    sc, lo, hi, gs = S.sgpm_host_hybrid_choice([1.0], [10.0], 0.01, 2, 1e-6, 0.2, 4000)
+    sc, gs = S.sgpm_host_hybrid_choice(1000.0, 0.01, 2, 1e-6, 0.2, 4000)
     R = _reps(0.2, 0.01, 4000)
     assert R > 1000 and gs == pytest.approx(R * 1e-6) and sc == S.SCHEME_GS
     # a stricter confidence needs more colourings
-    sc, lo, hi, gs99 = S.sgpm_host_hybrid_choice([1.0], [10.0], 0.01, 2, 1e-6, 0.2, 4000, confidence=0.99)
+    sc, gs99 = S.sgpm_host_hybrid_choice(1000.0, 0.01, 2, 1e-6, 0.2, 4000, confidence=0.99)
     assert gs99 == pytest.approx(_reps(0.2, 0.01, 4000, 0.99) * 1e-6) and gs99 > gs
 
 
 def test_invalid_arguments(S):
     with pytest.raises(S.SgpmError):
-        S.sgpm_host_hybrid_choice([], [], 0.01, 2, 1.0, 0.0)
+        S.sgpm_host_hybrid_choice(1.0, 0.0, 2, 1.0, 0.0)
     with pytest.raises(S.SgpmError):
-        S.sgpm_host_hybrid_choice([1.0], [1.0], 0.0, 2, 1.0, 0.0)
-    with pytest.raises(S.SgpmError):
-        S.sgpm_host_hybrid_choice([1.0], [1.0], 0.01, 2, 1.0, 0.0, confidence=1.0)
+        S.sgpm_host_hybrid_choice(1.0, 0.01, 2, 1.0, 0.0, confidence=1.0)
 
 
 @pytest.mark.parametrize("name,eps", [("triangle", 0.02), ("4-cycle", 0.005)])
