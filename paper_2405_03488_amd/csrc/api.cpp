@@ -65,11 +65,14 @@ int largest_grid(sgpm_ctx* c) {
 }  // namespace
 
 sgpm_graph::~sgpm_graph() {
-    // lane counts tuned for this graph must not carry over to a later graph
-    // that happens to get the same address
-    if (ctx)
+    // lane counts and tiles tuned for this graph must not carry over to a
+    // later graph that happens to get the same address
+    if (ctx) {
         for (auto it = ctx->ns_tuned.begin(); it != ctx->ns_tuned.end();)
             it = std::get<0>(it->first) == (const void*)this ? ctx->ns_tuned.erase(it) : std::next(it);
+        for (auto it = ctx->tuned.begin(); it != ctx->tuned.end();)
+            it = std::get<0>(it->first) == (const void*)this ? ctx->tuned.erase(it) : std::next(it);
+    }
     if (!d_off && !d_nbr && !d_epair && !d_arow && !d_vb) return;
     if (ctx) (void)hipSetDevice(ctx->dev);
     for (void* q : {(void*)d_off, (void*)d_nbr, (void*)d_epair, (void*)d_arow, (void*)d_vb})

@@ -1,6 +1,8 @@
 // Batched estimation: many (graph, pattern) NS queries in one persistent,
-// hipGraph-captured launch, one sample per wave at a time, with an autotuner
-// that sizes each query's tickets from timed pilot samples.
+// hipGraph-captured launch, each query sampled with its own lane count (one
+// sample per wave, or groups of 16, 4 or 1 lanes per sample), with an
+// autotuner that picks each query's lane count and ticket size from timed
+// pilot samples.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -16,34 +18,75 @@ namespace sgpm {
 
 namespace {
 
-// Tile autotuner: time 2^18 pilot samples of the query (Philox tag
-// 0x80000000 | tag, so they never overlap estimation samples) and size the
-// query's tickets to about 200 us of wave time, so uneven queries hand out
-// tickets of similar cost and the persistent grid drains evenly.
-sgpm_status autotune_tile(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_options& o, int* tile) {
+// Autotuner: pick a query's lanes per sample and its ticket size from timed
+// pilot samples (Philox tag 0x80000000 | tag, so they never overlap estimation
+// samples).  Lane counts: the caller's lanes_per_sample if set, else the count
+// the solo estimate chose for this (graph, plan) if it ran, else candidates
+// from wide to narrow (64, 16, 4, 1), two timed rounds each (the first launch
+// of a kernel pays for its code and cold caches), a narrower count tried only
+// while narrowing paid off.  The tile (samples per ticket) is sized to about
+// 400 us of wave time at the chosen count, so uneven queries hand out tickets
+// of similar cost and the persistent grid drains evenly: for G lanes per sample
+// a wave holds 64/G samples at once, so its samples per lane are tile / (64/G).
+sgpm_status autotune_query(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_options& o, int* lanes_out,
+                           int* tile) {
     sgpm_options po = o;
     po.mode = SGPM_MODE_FIXED_N;
-    po.fixed_n = 1 << 18;
     po.query_tag = 0x80000000u | (o.query_tag & 0x7FFFFFFFu);
-    po.lanes_per_sample = 64;
     po.checksum = 0;
     po.trace_buf = nullptr;
     po.trace_lo = po.trace_hi = 0;
-    sgpm_result r;
-    sgpm_status st = ns_estimate_solo(c, g, p, po, &r, 0);
-    if (st != SGPM_OK && st != SGPM_NOT_CONVERGED) return st;
-    const bool clq = wave_uses_clique_kernel(p, TraceArgs{}, LearnArgs{}, 0);
-    const double waves = (double)c->cus * (double)(clq ? ns_clique_blocks_per_cu() : ns_blocks_per_cu(64)) * 4.0;
-    const double wave_time_per_sample = r.seconds_kernel * waves / (double)po.fixed_n;
+    int cand[4] = {64, 16, 4, 1};
+    int ncand = 4;
+    if (o.lanes_per_sample) {
+        cand[0] = o.lanes_per_sample;
+        ncand = 1;
+    } else {
+        auto it = c->ns_tuned.find(std::make_tuple((const void*)g, std::string((const char*)&p, sizeof(Plan))));
+        if (it != c->ns_tuned.end()) {
+            cand[0] = it->second;
+            ncand = 1;
+        }
+    }
+    double best[4] = {0, 0, 0, 0};
+    int ntry = ncand == 1 ? 1 : 2;  // candidates in play
+    for (int round = 0; round < 2; round++)
+        for (int ci = 0; ci < ntry; ci++) {
+            po.lanes_per_sample = cand[ci];
+            po.fixed_n = cand[ci] == 64 ? (1u << 18) : (1u << 17);
+            sgpm_result r;
+            sgpm_status st = ns_estimate_solo(c, g, p, po, &r, 0);
+            if (st != SGPM_OK && st != SGPM_NOT_CONVERGED) return st;
+            const double per = r.seconds_kernel / (double)po.fixed_n;
+            if (std::getenv("SGPM_DEBUG"))
+                std::fprintf(stderr, "sgpm batch autotune: lanes=%d %.4g s per sample\n", cand[ci], per);
+            if (round == 0 || per < best[ci]) best[ci] = per;
+            // the narrower count won its first run: the next one is tried too
+            if (round == 0 && ci >= 1 && ci + 1 == ntry && ntry < ncand && best[ci] < best[ci - 1]) ntry++;
+        }
+    int bi = 0;
+    for (int ci = 1; ci < ntry; ci++)
+        if (best[ci] < best[bi]) bi = ci;
+    const int L = cand[bi];
+    const bool clq = L == 64 && wave_uses_clique_kernel(p, TraceArgs{}, LearnArgs{}, 0);
+    const double waves = (double)c->cus * (double)(clq ? ns_clique_blocks_per_cu() : ns_blocks_per_cu(L)) * 4.0;
+    const double wave_time_per_sample = best[bi] * waves;
 #ifndef SGPM_TILE_US
-#define SGPM_TILE_US 200
+#define SGPM_TILE_US 400
 #endif
-    double t = wave_time_per_sample > 0 ? SGPM_TILE_US * 1e-6 / wave_time_per_sample : 1024.0;
-    int tl = 16;
-    while (tl < 1024 && tl * 2 <= 1.5 * t) tl *= 2;  // the power of two nearest t
+    // at least 16 samples (a sample per wave: one group of the draw and
+    // first-edge prefetch; smaller tiles were slower even for queries whose
+    // samples take a wave a millisecond on hub rows) and a round of the
+    // wave's lane groups
+    const int per_round = 64 / L;  // samples a wave holds at once
+    const int tmin = std::max(16, per_round), tmax = std::max(1024, 256 * per_round);
+    double t = wave_time_per_sample > 0 ? SGPM_TILE_US * 1e-6 / wave_time_per_sample : (double)tmax;
+    int tl = tmin;
+    while (tl < tmax && tl * 2 <= 1.5 * t) tl *= 2;  // the power of two nearest t
     *tile = tl;
+    *lanes_out = L;
     if (std::getenv("SGPM_DEBUG"))
-        std::fprintf(stderr, "sgpm batch autotune: %.3g us wave time per sample -> tile %d\n",
+        std::fprintf(stderr, "sgpm batch autotune: lanes %d, %.3g us wave time per sample -> tile %d\n", L,
                      wave_time_per_sample * 1e6, tl);
     return SGPM_OK;
 }
@@ -66,6 +109,8 @@ sgpm_status batch_estimate(sgpm_ctx* c, int nq, const sgpm_graph_t* graphs, cons
             return fail(c, SGPM_EUNSUPPORTED, "batch queries must be NS (strict or fixed-n)");
         if (o.trace_buf || o.proposal) return fail(c, SGPM_EUNSUPPORTED, "batch queries take no trace or proposal");
         if (o.sampler != SGPM_SAMPLER_PRUNE) return fail(c, SGPM_EUNSUPPORTED, "batch queries use NS-prune");
+        const int l = o.lanes_per_sample;
+        if (!(l == 0 || l == 1 || l == 4 || l == 16 || l == 64)) return fail(c, SGPM_EINVAL, "lanes_per_sample");
         if (!(o.eps > 0) || !(o.confidence > 0 && o.confidence < 1)) return fail(c, SGPM_EINVAL, "eps/confidence");
         if (o.mode == SGPM_MODE_FIXED_N && o.fixed_n == 0) return fail(c, SGPM_EINVAL, "fixed_n = 0");
         // every window must hold a tile, or its query would never complete
@@ -105,18 +150,20 @@ sgpm_status batch_estimate(sgpm_ctx* c, int nq, const sgpm_graph_t* graphs, cons
         Q.eps = o.eps;
         Q.z = normal_quantile(1.0 - (1.0 - o.confidence) / 2.0);
         const uint64_t M = p.oriented ? (uint64_t)g->m : 2ull * (uint64_t)g->m;
-        int tile = 64;
+        int tile = 64, lanes = o.lanes_per_sample ? o.lanes_per_sample : 64;
         if (M > 0) {
-            auto key = std::make_tuple((const void*)g, std::string((const char*)&p, sizeof(Plan)));
+            auto key = std::make_tuple((const void*)g, std::string((const char*)&p, sizeof(Plan)), o.lanes_per_sample);
             auto it = c->tuned.find(key);
-            if (it != c->tuned.end()) tile = it->second;
-            else {
-                sgpm_status st = autotune_tile(c, g, p, o, &tile);
+            if (it != c->tuned.end()) {
+                lanes = it->second.first;
+                tile = it->second.second;
+            } else {
+                sgpm_status st = autotune_query(c, g, p, o, &lanes, &tile);
                 if (st != SGPM_OK) return st;
-                c->tuned[key] = tile;
+                c->tuned[key] = std::make_pair(lanes, tile);
             }
         }
-        Q.lanes = 64;
+        Q.lanes = lanes;
         Q.tile = tile;
         Q.window_cap = window_cap;
         if (M == 0) {
@@ -131,11 +178,15 @@ sgpm_status batch_estimate(sgpm_ctx* c, int nq, const sgpm_graph_t* graphs, cons
     int kmax = 2;
     for (int i = 0; i < nq; i++) kmax = std::max(kmax, patterns[i]->plan.k);
     kmax = batch_kmax(kmax);
-    // every query a clique of at most 6 vertices: tiles run the clique sampler
-    bool clq = kmax <= 6;
+    // some query with fewer than 64 lanes per sample: the build with the
+    // lane-group samplers; else, every query a clique of at most 6 vertices:
+    // tiles run the clique sampler
+    bool grp = false;
+    for (int i = 0; i < nq; i++) grp = grp || hq[(size_t)i].lanes != 64;
+    bool clq = kmax <= 6 && !grp;
     for (int i = 0; i < nq; i++)
         clq = clq && plan_is_clique(patterns[i]->plan) && patterns[i]->plan.k >= 3 && patterns[i]->plan.k <= kmax;
-    if (c->batch_nq != nq || c->batch_kmax != kmax || c->batch_clq != clq) {
+    if (c->batch_nq != nq || c->batch_kmax != kmax || c->batch_clq != clq || c->batch_grp != grp) {
         if (c->batch_exec) (void)hipGraphExecDestroy(c->batch_exec);
         if (c->batch_graph) (void)hipGraphDestroy(c->batch_graph);
         c->batch_exec = nullptr;
@@ -147,7 +198,7 @@ sgpm_status batch_estimate(sgpm_ctx* c, int nq, const sgpm_graph_t* graphs, cons
         HIP_TRY(c, hipMalloc(&c->d_bq, total));
         HIP_TRY(c, hipHostMalloc(&c->h_bq, total, hipHostMallocDefault));
         if (!c->batch_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->batch_stream, hipStreamNonBlocking));
-        const int blocks = c->cus * batch_blocks_per_cu(kmax, clq);
+        const int blocks = c->cus * batch_blocks_per_cu(kmax, clq, grp);
         char* d = (char*)c->d_bq;
         char* h = (char*)c->h_bq;
         BatchQuery* dq = (BatchQuery*)d;
@@ -155,13 +206,14 @@ sgpm_status batch_estimate(sgpm_ctx* c, int nq, const sgpm_graph_t* graphs, cons
         unsigned long long* dact = (unsigned long long*)(d + qbytes + sbytes);
         HIP_TRY(c, hipStreamBeginCapture(c->batch_stream, hipStreamCaptureModeThreadLocal));
         HIP_TRY(c, hipMemcpyAsync(d, h, qbytes + sbytes + 8, hipMemcpyHostToDevice, c->batch_stream));
-        HIP_TRY(c, launch_batch(dq, ds, nq, dact, blocks, kmax, clq, c->batch_stream));
+        HIP_TRY(c, launch_batch(dq, ds, nq, dact, blocks, kmax, clq, grp, c->batch_stream));
         HIP_TRY(c, hipMemcpyAsync(h + qbytes, d + qbytes, sbytes, hipMemcpyDeviceToHost, c->batch_stream));
         HIP_TRY(c, hipStreamEndCapture(c->batch_stream, &c->batch_graph));
         HIP_TRY(c, hipGraphInstantiate(&c->batch_exec, c->batch_graph, nullptr, nullptr, 0));
         c->batch_nq = nq;
         c->batch_kmax = kmax;
         c->batch_clq = clq;
+        c->batch_grp = grp;
     }
     char* h = (char*)c->h_bq;
     std::memcpy(h, hq.data(), qbytes);

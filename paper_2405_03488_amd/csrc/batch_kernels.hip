@@ -198,12 +198,17 @@ __device__ __attribute__((noinline)) void complete_window(const BatchQuery& Q, B
     }
 }
 
+// A wave's sums of one (query, window) are held in LDS as the window columns'
+// layout (PF_S1.. 32-bit digit columns of S1, PF_S2.. of S2, PF_HITS,
+// PF_CSUM); every sample adds normalised digits (each below 2^32), so a
+// column of a window below 2^32 samples cannot wrap.
+//
 // One tile of samples, one sample per wave at a time, in groups of up to 16
 // as in the window kernel: the group's Philox draws are evaluated in parallel
 // lanes and read back with readlane, each sample leaves a record in LDS, and
-// lane q of the group epilogue hashes record q and adds the digit columns of X
-// and X^2 to the wave's LDS sums (0-3 digits of S1, 4-11 columns of S2, 12
-// checksum, 14 hits), which the caller adds to the query's window columns.
+// lane q of the group epilogue hashes record q and adds the digits of X and of
+// X^2 to the wave's LDS sums, which the caller adds to the query's window
+// columns.
 constexpr int BGMAX = 16, BREC = 16;
 
 // CLQ: the query is the KMAX-clique (its compiled plan is the clique's), and the
@@ -258,7 +263,7 @@ __device__ __forceinline__ void run_tile(const BatchQuery& Q, uint64_t s0, uint6
                 if (i < K) h = fmix64(h ^ (uint64_t)r[i]);
             h = fmix64(h ^ ((uint64_t)d[1] << 32 | d[0]));
             h = fmix64(h ^ ((uint64_t)d[3] << 32 | d[2]));
-            atomicAdd(&wsum[12], (unsigned long long)h);
+            atomicAdd(&wsum[PF_CSUM], (unsigned long long)h);
             if (st == 0xFFu) {
                 uint64_t c2[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
@@ -269,15 +274,87 @@ __device__ __forceinline__ void run_tile(const BatchQuery& Q, uint64_t s0, uint6
                         c2[a + e] += pr & 0xFFFFFFFFull;
                         if (a + e + 1 < 8) c2[a + e + 1] += pr >> 32;
                     }
+                // X^2 < 2^256: the columns normalise into 8 digits
+                uint64_t cy = 0;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) atomicAdd(&wsum[i], (unsigned long long)d[i]);
+                for (int i = 0; i < 8; ++i) {
+                    const uint64_t t = c2[i] + cy;
+                    c2[i] = t & 0xFFFFFFFFull;
+                    cy = t >> 32;
+                }
 #pragma unroll
-                for (int i = 0; i < 8; ++i) atomicAdd(&wsum[4 + i], (unsigned long long)c2[i]);
-                atomicAdd(&wsum[14], 1ull);
+                for (int i = 0; i < 4; ++i) atomicAdd(&wsum[PF_S1 + i], (unsigned long long)d[i]);
+#pragma unroll
+                for (int i = 0; i < 8; ++i) atomicAdd(&wsum[PF_S2 + i], (unsigned long long)c2[i]);
+                atomicAdd(&wsum[PF_HITS], 1ull);
             }
         }
         __builtin_amdgcn_wave_barrier();
     }
+}
+
+// One tile with G lanes per sample (G = 1, 4, 16), as in the solo window
+// kernel: group q of the wave takes samples s0 + q, s0 + q + 64/G, ...; its
+// leader keeps the exact sums of its samples, and at the tile's end the wave
+// adds their 32-bit digits into its LDS sums.
+template <int G, int KMAX>
+__device__ __forceinline__ void run_tile_g(const BatchQuery& Q, uint64_t s0, uint64_t s1, int32_t* list,
+                                           unsigned long long* wsum, uint64_t& ovf) {
+    const int lane = (int)(threadIdx.x & 63);
+    const bool leader = (lane & (G - 1)) == 0;
+    constexpr int CAP = LDS_WORDS / (256 / G);
+    int32_t* glist = list + (lane / G) * CAP;
+    Acc a;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) a.s1[i] = 0;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) a.s2[i] = 0;
+    a.hits = a.csum = 0;
+    for (uint64_t base = s0; base < s1; base += (uint64_t)(64 / G)) {
+        const uint64_t s = base + (uint64_t)(lane / G);
+        if (s >= s1) break;  // the whole group leaves together
+        int32_t v[8];
+        uint64_t alo, ahi, b = 0, ov = 0;
+        const uint32_t st = ns_sample<G, KMAX>(Q.g, Q.p, Q.seed, Q.tag, s, v, alo, ahi, ov, b, false, glist);
+        ovf |= ov;
+        if (!leader) continue;
+        if (st != 0xFFu) {
+            alo = 0;
+            ahi = 0;
+        } else {
+            a.hits += 1;
+            acc_add(a, alo, ahi);
+        }
+        uint64_t h = fmix64(s ^ 0x9E3779B97F4A7C15ull);
+        h = fmix64(h ^ (uint64_t)st);
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            if (i < Q.p.k) h = fmix64(h ^ (uint64_t)(uint32_t)v[i]);
+        h = fmix64(h ^ alo);
+        h = fmix64(h ^ ahi);
+        a.csum += h;
+    }
+    // the leaders' exact sums as digit columns, summed over the wave
+    unsigned long long f[PF_N];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        f[PF_S1 + 2 * i] = a.s1[i] & 0xFFFFFFFFull;
+        f[PF_S1 + 2 * i + 1] = a.s1[i] >> 32;
+    }
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        f[PF_S2 + 2 * i] = a.s2[i] & 0xFFFFFFFFull;
+        f[PF_S2 + 2 * i + 1] = a.s2[i] >> 32;
+    }
+    f[PF_HITS] = a.hits;
+    f[PF_CSUM] = a.csum;
+#pragma unroll
+    for (int i = 0; i < PF_N; ++i) {
+        if (i == PF_BYTES || i == PF_OVF) continue;
+        const unsigned long long x = wave_sum(f[i]);
+        if (lane == 0) wsum[i] += x;
+    }
+    __builtin_amdgcn_wave_barrier();
 }
 
 #ifndef SGPM_BATCH_IDLE_SLEEP
@@ -289,7 +366,21 @@ __device__ __forceinline__ void run_tile(const BatchQuery& Q, uint64_t s0, uint6
 // blocks per CU the kernel is compiled for: the most at which the sampling
 // loops of that pattern bound keep every value in registers (the all-clique
 // build inlines one sampler per clique size, so it needs more of them)
-constexpr int batch_occupancy(int kmax, bool clq) { return clq ? (kmax == 4 ? 6 : 5) : kmax <= 5 ? 6 : kmax == 6 ? 5 : 4; }
+// (a build with the lane-group samplers holds a walk per lane in vector
+// registers, as the solo window kernel does, and runs at its occupancy)
+#ifndef SGPM_BATCH_OCC_CLQ
+#define SGPM_BATCH_OCC_CLQ 0  // > 0: waves per SIMD of the all-clique builds
+#endif
+#ifndef SGPM_BATCH_OCC_GEN
+#define SGPM_BATCH_OCC_GEN 0  // > 0: waves per SIMD of the generic builds
+#endif
+// (all-clique builds for 4 and 5 vertices: 7 waves per SIMD with a few vector
+// spills beat 5 without, 10.9 against 12.5 ms for four 4-clique and four
+// 5-clique queries to 1 % on R-MAT 20)
+constexpr int batch_occupancy(int kmax, bool clq, bool grp) {
+    return grp ? 3 : clq ? (SGPM_BATCH_OCC_CLQ > 0 ? SGPM_BATCH_OCC_CLQ : kmax == 4 || kmax == 5 ? 7 : 5)
+                       : SGPM_BATCH_OCC_GEN > 0 ? SGPM_BATCH_OCC_GEN : kmax <= 5 ? 6 : kmax == 6 ? 5 : 4;
+}
 
 // a tile of a k-clique query (3 <= k <= KMAX) with the sampler compiled for k
 template <int KMAX>
@@ -312,14 +403,12 @@ __device__ __forceinline__ void flush_held(const BatchQuery* queries, BatchState
     const int lane = (int)(threadIdx.x & 63);
     BatchState& S = states[hq];
     unsigned long long* win = S.win[blockIdx.x & 7];
-    if (lane < 15) {
+    if (lane < PF_N && lane != PF_BYTES && lane != PF_OVF) {
         const unsigned long long val = wsum[lane];
         wsum[lane] = 0ull;
-        const int field = lane < 4 ? PF_S1 + lane : lane < 12 ? PF_S2 + (lane - 4) : lane == 12 ? PF_CSUM
-                        : lane == 14 ? PF_HITS : -1;
-        if (field >= 0 && val) atomicAdd(&win[field], val);
+        if (val) atomicAdd(&win[lane], val);
     }
-    if (lane == 15 && hovf) atomicAdd(&win[PF_OVF], (unsigned long long)hovf);
+    if (lane == PF_OVF && hovf) atomicAdd(&win[PF_OVF], (unsigned long long)hovf);
     __builtin_amdgcn_wave_barrier();
     // release only: the sums above before the count below
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -334,7 +423,9 @@ __device__ __forceinline__ void flush_held(const BatchQuery* queries, BatchState
 
 // KMAX: the largest pattern size of the batch (the sampler is compiled for it).
 // ALLCLQ: every query is a clique of at most KMAX vertices, and each tile runs
-// the clique sampler compiled for its query's size.
+// the clique sampler compiled for its query's size.  GRP: some query samples
+// with 1, 4 or 16 lanes per sample (its BatchQuery::lanes), and each tile runs
+// the sampler of its query's lane count.
 //
 // Scheduling: a wave takes tiles from the query it served last while that
 // query's window has tiles left, trying its own XCD's counter first and the
@@ -344,16 +435,16 @@ __device__ __forceinline__ void flush_held(const BatchQuery* queries, BatchState
 // wave keeps its sums in LDS until it moves to another (query, window) or finds
 // no tile; a window cannot complete while a wave holds part of it, so every
 // wave holding sums of a finished window flushes at its next poll.
-template <int KMAX, bool ALLCLQ>
-__global__ __launch_bounds__(256, batch_occupancy(KMAX, ALLCLQ)) void batch_kernel(const BatchQuery* __restrict__ queries, BatchState* __restrict__ states,
+template <int KMAX, bool ALLCLQ, bool GRP>
+__global__ __launch_bounds__(256, batch_occupancy(KMAX, ALLCLQ, GRP)) void batch_kernel(const BatchQuery* __restrict__ queries, BatchState* __restrict__ states,
                                                     int nq, unsigned long long* __restrict__ active) {
     const int lane = (int)(threadIdx.x & 63);
     const int wid = (int)(threadIdx.x >> 6);
     __shared__ int32_t s_list[LDS_WORDS];
     __shared__ __align__(16) uint32_t s_rec[4][BGMAX * BREC];
-    __shared__ unsigned long long s_wsum[4][16];
+    __shared__ unsigned long long s_wsum[4][PF_N];
     unsigned long long* wsum = s_wsum[wid];
-    if (lane < 16) wsum[lane] = 0ull;
+    if (lane < PF_N) wsum[lane] = 0ull;
     __builtin_amdgcn_wave_barrier();
     const int wave = rfl((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
     const int xc = (int)(blockIdx.x & 7);
@@ -426,10 +517,18 @@ __global__ __launch_bounds__(256, batch_occupancy(KMAX, ALLCLQ)) void batch_kern
         const uint64_t T = (uint64_t)Q.tile;
         const uint64_t s0 = cws + t * T, s1 = min(s0 + T, cwe);
         uint64_t ovf = 0;
-        if constexpr (ALLCLQ)
-            clique_tile<KMAX>(Q.p.k, Q, s0, s1, s_list + wid * (LDS_WORDS / 4), s_rec[wid], wsum, ovf);
-        else
-            run_tile<KMAX, false>(Q, s0, s1, s_list + wid * (LDS_WORDS / 4), s_rec[wid], wsum, ovf);
+        int32_t* const wl = s_list + wid * (LDS_WORDS / 4);
+        if constexpr (GRP) {
+            const int lanes = rfl(Q.lanes);
+            if (lanes == 1) run_tile_g<1, KMAX>(Q, s0, s1, wl, wsum, ovf);
+            else if (lanes == 4) run_tile_g<4, KMAX>(Q, s0, s1, wl, wsum, ovf);
+            else if (lanes == 16) run_tile_g<16, KMAX>(Q, s0, s1, wl, wsum, ovf);
+            else run_tile<KMAX, false>(Q, s0, s1, wl, s_rec[wid], wsum, ovf);
+        } else if constexpr (ALLCLQ) {
+            clique_tile<KMAX>(Q.p.k, Q, s0, s1, wl, s_rec[wid], wsum, ovf);
+        } else {
+            run_tile<KMAX, false>(Q, s0, s1, wl, s_rec[wid], wsum, ovf);
+        }
         hq = q;
         hw = w;
         hws = cws;
@@ -444,33 +543,42 @@ __global__ __launch_bounds__(256, batch_occupancy(KMAX, ALLCLQ)) void batch_kern
 // the compiled bound for a batch whose largest pattern has k vertices
 int batch_kmax(int k) { return k <= 3 ? 3 : k <= 6 ? k : 8; }
 
-int batch_blocks_per_cu(int kmax, bool clq) {
+int batch_blocks_per_cu(int kmax, bool clq, bool grp) {
     int nb = 0;
     hipError_t e = hipErrorInvalidValue;
-#define SGPM_BATCH_OCC(KK, CC) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_kernel<KK, CC>, 256, 0)
+#define SGPM_BATCH_OCC(KK, CC, GG) \
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_kernel<KK, CC, GG>, 256, 0)
+#define SGPM_BATCH_OCC3(KK) \
+    if (grp) SGPM_BATCH_OCC(KK, false, true); else if (clq) SGPM_BATCH_OCC(KK, true, false); \
+    else SGPM_BATCH_OCC(KK, false, false)
     switch (batch_kmax(kmax)) {
-        case 3: if (clq) SGPM_BATCH_OCC(3, true); else SGPM_BATCH_OCC(3, false); break;
-        case 4: if (clq) SGPM_BATCH_OCC(4, true); else SGPM_BATCH_OCC(4, false); break;
-        case 5: if (clq) SGPM_BATCH_OCC(5, true); else SGPM_BATCH_OCC(5, false); break;
-        case 6: if (clq) SGPM_BATCH_OCC(6, true); else SGPM_BATCH_OCC(6, false); break;
-        default: SGPM_BATCH_OCC(8, false); break;
+        case 3: SGPM_BATCH_OCC3(3); break;
+        case 4: SGPM_BATCH_OCC3(4); break;
+        case 5: SGPM_BATCH_OCC3(5); break;
+        case 6: SGPM_BATCH_OCC3(6); break;
+        default: if (grp) SGPM_BATCH_OCC(8, false, true); else SGPM_BATCH_OCC(8, false, false); break;
     }
+#undef SGPM_BATCH_OCC3
 #undef SGPM_BATCH_OCC
     if (e != hipSuccess || nb < 1) nb = 1;
     return nb;
 }
 
 hipError_t launch_batch(const BatchQuery* q, BatchState* s, int nq, unsigned long long* active, int blocks,
-                        int kmax, bool clq, hipStream_t st) {
-#define SGPM_BATCH_LAUNCH(KK, CC) \
-    hipLaunchKernelGGL((batch_kernel<KK, CC>), dim3((unsigned)blocks), dim3(256), 0, st, q, s, nq, active)
+                        int kmax, bool clq, bool grp, hipStream_t st) {
+#define SGPM_BATCH_LAUNCH(KK, CC, GG) \
+    hipLaunchKernelGGL((batch_kernel<KK, CC, GG>), dim3((unsigned)blocks), dim3(256), 0, st, q, s, nq, active)
+#define SGPM_BATCH_LAUNCH3(KK) \
+    if (grp) SGPM_BATCH_LAUNCH(KK, false, true); else if (clq) SGPM_BATCH_LAUNCH(KK, true, false); \
+    else SGPM_BATCH_LAUNCH(KK, false, false)
     switch (batch_kmax(kmax)) {
-        case 3: if (clq) SGPM_BATCH_LAUNCH(3, true); else SGPM_BATCH_LAUNCH(3, false); break;
-        case 4: if (clq) SGPM_BATCH_LAUNCH(4, true); else SGPM_BATCH_LAUNCH(4, false); break;
-        case 5: if (clq) SGPM_BATCH_LAUNCH(5, true); else SGPM_BATCH_LAUNCH(5, false); break;
-        case 6: if (clq) SGPM_BATCH_LAUNCH(6, true); else SGPM_BATCH_LAUNCH(6, false); break;
-        default: SGPM_BATCH_LAUNCH(8, false); break;
+        case 3: SGPM_BATCH_LAUNCH3(3); break;
+        case 4: SGPM_BATCH_LAUNCH3(4); break;
+        case 5: SGPM_BATCH_LAUNCH3(5); break;
+        case 6: SGPM_BATCH_LAUNCH3(6); break;
+        default: if (grp) SGPM_BATCH_LAUNCH(8, false, true); else SGPM_BATCH_LAUNCH(8, false, false); break;
     }
+#undef SGPM_BATCH_LAUNCH3
 #undef SGPM_BATCH_LAUNCH
     return hipGetLastError();
 }

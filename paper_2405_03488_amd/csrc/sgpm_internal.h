@@ -84,7 +84,7 @@ struct BatchQuery {
     Plan p;
     uint64_t seed;
     uint32_t tag;
-    int32_t lanes;  // 16 or 64
+    int32_t lanes;  // lanes per sample: 1, 4, 16 or 64
     int32_t mode;   // SGPM_MODE_STRICT_NS or SGPM_MODE_FIXED_N
     int32_t tile;   // samples per ticket
     int32_t window_cap;  // first window index that would hold >= 2^32 samples
@@ -109,10 +109,10 @@ struct BatchState {
     double eps_hat;
     uint64_t n;
 };
-int batch_blocks_per_cu(int kmax, bool clq);
+int batch_blocks_per_cu(int kmax, bool clq, bool grp);
 int batch_kmax(int k);
 hipError_t launch_batch(const BatchQuery* q, BatchState* s, int nq, unsigned long long* active, int blocks,
-                        int kmax, bool clq, hipStream_t st);
+                        int kmax, bool clq, bool grp, hipStream_t st);
 
 struct NsExtra {
     LearnArgs la;        // learned proposal (table nullptr = uniform)
@@ -202,11 +202,13 @@ struct sgpm_ctx {
     size_t nslots = 0;
     std::vector<hipEvent_t> kev;             // start/stop events around each sampling kernel
     // batch: autotuned lanes per (graph, plan), device/pinned tables, captured graph
-    std::map<std::tuple<const void*, std::string>, int> tuned;     // batch tile per (graph, plan)
+    // batch (lanes per sample, tile) per (graph, plan, requested lanes)
+    std::map<std::tuple<const void*, std::string, int>, std::pair<int, int>> tuned;
     std::map<std::tuple<const void*, std::string>, int> ns_tuned;  // solo lanes per sample per (graph, plan)
     int batch_nq = 0;
     int batch_kmax = 0;
     bool batch_clq = false;
+    bool batch_grp = false;
     void* d_bq = nullptr;
     void* h_bq = nullptr;
     hipStream_t batch_stream = nullptr;

@@ -75,18 +75,12 @@ def test_batch_equals_solo(S, synth, ctx, graphs):
     for (g, p, o), rb in zip(qs, res):
         rs, _ = S.sgpm_estimate(ctx, g, p, o)
         same(rb, rs)
-        assert rb.tile >= 16
+        assert rb.tile >= 16 and rb.tile & (rb.tile - 1) == 0
     for q in qs:
         S.sgpm_pattern_free(q[1])
 
 
-def test_batch_equals_oracle(S, O, synth, ctx, graphs, ographs):
-    """Every query of the persistent batch (strict queries with their own
-    windows and device-side stop test, fixed-n queries) against the oracle's
-    run at the same options: stop point, windows, exact sums, hits, checksum,
-    estimate and predicted error."""
-    qs = make_queries(S, synth, ctx, graphs, 100)
-    res = S.sgpm_estimate_batch(ctx, [q[0] for q in qs], [q[1] for q in qs], [q[2] for q in qs])
+def check_against_oracle(S, O, synth, ographs, qs, res):
     i = 0
     for og in ographs:
         for name, induced in MOTIFS:
@@ -100,14 +94,67 @@ def test_batch_equals_oracle(S, O, synth, ctx, graphs, ographs):
                                  w_min=o.w_min, quantum=o.quantum, max_samples=o.max_samples,
                                  growth=o.window_growth)
             orr = O.run(og, op, oo)
-            print(f"query {i} {name} n={orr.n}", flush=True)
+            print(f"query {i} {name} lanes={rb.lanes_per_sample} tile={rb.tile} n={orr.n}", flush=True)
             assert rb.n_samples == orr.n and rb.windows == orr.windows and rb.converged == orr.converged
             assert rb.S1 == orr.S1 and rb.S2 == orr.S2 and rb.n_hits == orr.hits and rb.checksum == orr.checksum
             assert rb.estimate == orr.estimate
             assert rb.eps_hat == orr.eps_hat or (rb.eps_hat == float("inf") and orr.eps_hat == float("inf"))
             i += 1
+
+
+def test_batch_equals_oracle(S, O, synth, ctx, graphs, ographs):
+    """Every query of the persistent batch (strict queries with their own
+    windows and device-side stop test, fixed-n queries) against the oracle's
+    run at the same options: stop point, windows, exact sums, hits, checksum,
+    estimate and predicted error."""
+    qs = make_queries(S, synth, ctx, graphs, 100)
+    res = S.sgpm_estimate_batch(ctx, [q[0] for q in qs], [q[1] for q in qs], [q[2] for q in qs])
+    check_against_oracle(S, O, synth, ographs, qs, res)
     for q in qs:
         S.sgpm_pattern_free(q[1])
+
+
+@pytest.mark.parametrize("lanes", [(1, 4, 16, 64), (16, 4), (1,)])
+def test_batch_lane_groups_equal_oracle(S, O, synth, ctx, graphs, ographs, lanes):
+    """Queries pinned to 1, 4, 16 or 64 lanes per sample (the build with the
+    lane-group samplers; strict and fixed-n, ragged last tiles) against the
+    oracle, and each query reports the lane count it ran."""
+    qs = make_queries(S, synth, ctx, graphs, 700)
+    for i, (_, _, o) in enumerate(qs):
+        o.lanes_per_sample = lanes[i % len(lanes)]
+    res = S.sgpm_estimate_batch(ctx, [q[0] for q in qs], [q[1] for q in qs], [q[2] for q in qs])
+    for (_, _, o), rb in zip(qs, res):
+        assert rb.lanes_per_sample == o.lanes_per_sample
+        assert rb.tile % (64 // rb.lanes_per_sample) == 0
+    check_against_oracle(S, O, synth, ographs, qs, res)
+    for q in qs:
+        S.sgpm_pattern_free(q[1])
+
+
+def test_batch_autotuned_lanes(S, synth, ctx, graphs):
+    """lanes_per_sample = 0: the autotuner picks each query's lane count from
+    timed pilots (a count the solo estimate chose is reused); every result
+    still equals its solo run at the lane count the solo run picks."""
+    qs = make_queries(S, synth, ctx, graphs, 1300)
+    res = S.sgpm_estimate_batch(ctx, [q[0] for q in qs], [q[1] for q in qs], [q[2] for q in qs])
+    picked = [rb.lanes_per_sample for rb in res]
+    print("batch lanes picked:", picked, flush=True)
+    assert all(l in (1, 4, 16, 64) for l in picked)
+    for (g, p, o), rb in zip(qs, res):
+        rs, _ = S.sgpm_estimate(ctx, g, p, o)
+        same(rb, rs)
+    for q in qs:
+        S.sgpm_pattern_free(q[1])
+
+
+def test_batch_rejects_bad_lanes(S, synth, ctx, graphs):
+    k, e = synth.pattern("triangle")
+    p = S.sgpm_pattern_create(ctx, k, e)
+    o = S.sgpm_options_default(eps=0.05, lanes_per_sample=8)
+    with pytest.raises(S.SgpmError) as ei:
+        S.sgpm_estimate_batch(ctx, [graphs[0]], [p], [o])
+    assert ei.value.status == S.SGPM_EINVAL
+    S.sgpm_pattern_free(p)
 
 
 def test_batch_replay_new_seeds(S, synth, ctx, graphs):
