@@ -189,6 +189,20 @@ def learned_leg(S, ctx, g, pats, queries, eps, steps, lanes):
     return out
 
 
+def learned_c4_leg(S, synth, ctx, eps, steps):
+    """The learned-vs-uniform comparison at the scale its figure is quoted on:
+    R-MAT 24 (edge factor 16), 5-clique, same seeds and windows for both."""
+    g, gi = load_graph(S, synth, ctx, "rmat24", 1 << 24, lambda: synth.rmat_pairs(24, 16, 0.57, 0.19, 0.19, seed=1))
+    pats = {"5-clique": S.sgpm_pattern_create(ctx, *synth.pattern("5-clique"))}
+    r, _ = S.sgpm_estimate(ctx, g, pats["5-clique"], S.sgpm_options_default(eps=eps, seed=700))
+    lanes = {"5-clique": int(r.lanes_per_sample)}
+    out = learned_leg(S, ctx, g, pats, ["5-clique"], eps, steps, lanes)
+    out["graph"] = gi
+    S.sgpm_pattern_free(pats["5-clique"])
+    S.sgpm_graph_free(g)
+    return out
+
+
 def host_cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -376,6 +390,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-probes", action="store_true", help="skip the measured copy/gather rooflines")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-uniform leg")
+    ap.add_argument("--no-c4", action="store_true", help="skip the R-MAT 24 learned-vs-uniform leg")
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "coverage"],
                     help="c1: ER triangle throughput; "
                          "c2 (default): R-MAT 20 4-/5-clique, the benchmark line; c3: 24 motif queries on three "
@@ -496,6 +511,7 @@ def main():
 
     learned = None if args.no_learned else learned_leg(S, ctx, g, pats, queries, args.eps, args.steps, lanes)
     other = None if args.no_learned else other_legs(S, ctx, g, pats, queries, args.eps)
+    c4 = None if args.no_learned or args.no_c4 else learned_c4_leg(S, synth, ctx, args.eps, max(3, args.steps))
 
     probes = None
     if not args.no_probes:
@@ -637,6 +653,7 @@ def main():
         "cpu_baseline": cpu,
         "bytes_per_sample": cpu_bytes,
         "learned_vs_uniform": learned,
+        "learned_vs_uniform_c4": c4,
         "gs_hybrid_mlp": other,
     }
     print(json.dumps(line), flush=True)

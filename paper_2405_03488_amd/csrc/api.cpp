@@ -73,9 +73,9 @@ sgpm_graph::~sgpm_graph() {
         for (auto it = ctx->tuned.begin(); it != ctx->tuned.end();)
             it = std::get<0>(it->first) == (const void*)this ? ctx->tuned.erase(it) : std::next(it);
     }
-    if (!d_off && !d_nbr && !d_epair && !d_arow && !d_vb) return;
+    if (!d_off && !d_nbr && !d_epair && !d_arow && !d_vb && !d_bthr) return;
     if (ctx) (void)hipSetDevice(ctx->dev);
-    for (void* q : {(void*)d_off, (void*)d_nbr, (void*)d_epair, (void*)d_arow, (void*)d_vb})
+    for (void* q : {(void*)d_off, (void*)d_nbr, (void*)d_epair, (void*)d_arow, (void*)d_vb, (void*)d_bthr})
         if (q) (void)hipFree(q);
 }
 
@@ -203,7 +203,9 @@ sgpm_status sgpm_graph_from_csr(sgpm_ctx_t c, int64_t n, const void* offsets, in
         HIP_TRY(c, hipMemcpy(g->d_arow, arow.data(), sizeof(int32_t) * (size_t)(2 * h.m), hipMemcpyHostToDevice));
     }
     // degree buckets b = floor(log2(1 + deg)) are non-increasing in the canonical id;
-    // the learned proposal reads a candidate's bucket from a byte per vertex
+    // the learned proposal counts a sorted candidate set's buckets by searching
+    // it for the first id of each bucket, and reads single candidates' buckets
+    // from a byte per vertex
     g->degree_ordered = true;
     {
         int64_t cntb[32] = {0};
@@ -222,6 +224,8 @@ sgpm_status sgpm_graph_from_csr(sgpm_ctx_t c, int64_t n, const void* offsets, in
         }
         HIP_TRY(c, hipMalloc(&g->d_vb, vb.size()));
         HIP_TRY(c, hipMemcpy(g->d_vb, vb.data(), vb.size(), hipMemcpyHostToDevice));
+        HIP_TRY(c, hipMalloc(&g->d_bthr, sizeof(g->bthr)));
+        HIP_TRY(c, hipMemcpy(g->d_bthr, g->bthr, sizeof(g->bthr), hipMemcpyHostToDevice));
     }
     g->perm = std::move(h.perm);
     *out = g.release();
@@ -376,7 +380,7 @@ void fill_result(sgpm_result* r, const NsState& s, double z, int shift) {
 
 sgpm_status ns_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_options& o, sgpm_result* res,
                         int count_bytes, const NsExtra* ex = nullptr) {
-    LearnArgs la{nullptr, nullptr};
+    LearnArgs la{nullptr, nullptr, nullptr, 0};
     if (ex) la = ex->la;
     const bool learned = la.table != nullptr;
     auto t_start = std::chrono::steady_clock::now();

@@ -73,12 +73,14 @@ sgpm_status upload_tables(sgpm_ctx* c, sgpm_model* m) {
 }  // namespace
 
 sgpm_status learn_args_for(sgpm_ctx* c, sgpm_graph* g, sgpm_pattern* p, sgpm_model* m, LearnArgs* la) {
-    if (!g->degree_ordered || !g->d_vb)
+    if (!g->degree_ordered || !g->d_vb || !g->d_bthr)
         return fail(c, SGPM_EUNSUPPORTED, "the learned proposal needs a degree-ordered (canonical) graph");
     for (int i = 0; i < m->np; i++)
         if (same_plan(m->plans[(size_t)i], p->plan)) {
             la->table = m->d_tables + (size_t)i * TABLE;
             la->vb = g->d_vb;
+            la->thr = g->d_bthr;
+            la->lane_thr = 0;
             return SGPM_OK;
         }
     return fail(c, SGPM_EINVAL, "the proposal model has no table for this pattern");

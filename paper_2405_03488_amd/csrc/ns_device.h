@@ -433,36 +433,49 @@ __device__ __forceinline__ uint32_t ns_sample(const DGraph& g, const Plan& p, ui
 
         uint32_t idx = 0;
         if constexpr (G == 64) {
-            // learned proposal with every candidate in one bucket (buckets follow
-            // the id order, so the first and the last candidate decide): the
-            // weighted choice reduces to a uniform member drawn with draw 16+j
-            // and the factor sum / w_b is exactly |S_j|
-            const bool one_bucket =
-                weighted && cnt <= (uint32_t)CAP && bucket_of(*la, uni<G>(list[0])) == bucket_of(*la, uni<G>(list[cnt - 1]));
             if (learned && !weighted) {
                 idx = (uint32_t)__umul64hi((uint64_t)cnt, draw_at(dr, seed, s, (uint32_t)j, tag));
                 af = __dmul_rn(af, (double)cnt);
-            } else if (one_bucket) {
-                idx = (uint32_t)__umul64hi((uint64_t)cnt, draw_at(dr, seed, s, 16u + (uint32_t)j, tag));
-                af = __dmul_rn(af, (double)cnt);
             } else if (weighted && cnt <= (uint32_t)CAP) {
-                // weighted bucket, then a uniform member of it: counts n_b <= CAP
-                // and n_b w_b < 2^26, so both running sums fit 32 bits; bucket b
-                // sits in lane b and the sums are scanned with DPP row shifts
-                if (lane < 32) hist[lane] = 0;
-                for (uint32_t i = (uint32_t)lane; i < cnt; i += 64u) atomicAdd(&hist[bucket_of(*la, list[i])], 1u);
-                const uint32_t nb = lane < 32 ? hist[lane] : 0u;
-                const uint32_t w = (uint32_t)wrow;
-                const uint32_t cum = scan32_dpp(nb * w), cumn = scan32_dpp(nb);
-                const uint64_t sigma = (uint32_t)__builtin_amdgcn_readlane((int)cum, 31);
-                const uint64_t t = __umul64hi(sigma, draw_at(dr, seed, s, (uint32_t)j, tag));
-                const int bsel = __ffsll((unsigned long long)__ballot(lane < 32 && (uint64_t)cum > t)) - 1;
-                const uint64_t nbs = (uint32_t)__builtin_amdgcn_readlane((int)nb, bsel);
-                const uint64_t wbs = (uint32_t)__builtin_amdgcn_readlane((int)w, bsel);
-                const uint64_t upto = (uint32_t)__builtin_amdgcn_readlane((int)cumn, bsel);
-                const uint64_t inb = __umul64hi(nbs, draw_at(dr, seed, s, 16u + (uint32_t)j, tag));
-                idx = (uint32_t)((uint64_t)cnt - upto + inb);
-                af = __dmul_rn(af, __ddiv_rn((double)sigma, (double)wbs));
+                // Bucket counts from the list's order: buckets do not increase
+                // with the id, so in the ascending list each bucket is one run.
+                // Lane b < 32 finds the first candidate of bucket <= b by a
+                // binary search for the first id of those buckets (lane_thr),
+                // and n_b is its distance to lane b-1's position.
+                int32_t lo = 0;
+                if (lane < 32) {
+                    int32_t hi = (int32_t)cnt;
+                    const int32_t thr = la->lane_thr;
+                    while (lo < hi) {
+                        const int32_t mid = (lo + hi) >> 1;
+                        if (list[mid] < thr) lo = mid + 1;
+                        else hi = mid;
+                    }
+                }
+                const int32_t before = __shfl(lo, lane - 1);
+                const uint32_t nb = lane < 32 ? (uint32_t)((lane == 0 ? (int32_t)cnt : before) - lo) : 0u;
+                if (__popcll(__ballot(nb != 0u)) == 1) {
+                    // every candidate in one bucket: the weighted choice reduces to
+                    // a uniform member drawn with draw 16+j, and the factor
+                    // sum / w_b is exactly |S_j|
+                    idx = (uint32_t)__umul64hi((uint64_t)cnt, draw_at(dr, seed, s, 16u + (uint32_t)j, tag));
+                    af = __dmul_rn(af, (double)cnt);
+                } else {
+                    // weighted bucket, then a uniform member of it: counts n_b <= CAP
+                    // and n_b w_b < 2^26, so both running sums fit 32 bits; bucket b
+                    // sits in lane b and the sums are scanned with DPP row shifts
+                    const uint32_t w = (uint32_t)wrow;
+                    const uint32_t cum = scan32_dpp(nb * w), cumn = scan32_dpp(nb);
+                    const uint64_t sigma = (uint32_t)__builtin_amdgcn_readlane((int)cum, 31);
+                    const uint64_t t = __umul64hi(sigma, draw_at(dr, seed, s, (uint32_t)j, tag));
+                    const int bsel = __ffsll((unsigned long long)__ballot(lane < 32 && (uint64_t)cum > t)) - 1;
+                    const uint64_t nbs = (uint32_t)__builtin_amdgcn_readlane((int)nb, bsel);
+                    const uint64_t wbs = (uint32_t)__builtin_amdgcn_readlane((int)w, bsel);
+                    const uint64_t upto = (uint32_t)__builtin_amdgcn_readlane((int)cumn, bsel);
+                    const uint64_t inb = __umul64hi(nbs, draw_at(dr, seed, s, 16u + (uint32_t)j, tag));
+                    idx = (uint32_t)((uint64_t)cnt - upto + inb);
+                    af = __dmul_rn(af, __ddiv_rn((double)sigma, (double)wbs));
+                }
             } else if (weighted) {
                 // the same when the set overflowed the list: histogram by rescanning
                 if (lane < 32) hist[lane] = 0;

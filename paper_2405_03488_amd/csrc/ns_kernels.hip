@@ -196,7 +196,9 @@ __global__ __launch_bounds__(256, wave_occupancy(MODE, CLQ)) void ns_wave_kernel
     unsigned long long* wsum = s_wsum[wid];
     int32_t* list = s_list + wid * (LDS_WORDS / 4);
     if (lane < 16) wsum[lane] = 0ull;
-    const LearnArgs lal = la;
+    // the learned proposal's bucket thresholds, one per lane, held for the launch
+    LearnArgs lal = la;
+    lal.lane_thr = (MODE == 1 && la.thr && lane < 32) ? la.thr[lane] : 0;
     __builtin_amdgcn_wave_barrier();
     uint64_t ovf = 0;
     const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x >> 6);

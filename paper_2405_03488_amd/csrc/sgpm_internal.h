@@ -51,6 +51,8 @@ struct TraceArgs {
 struct LearnArgs {
     const uint16_t* table;  // [8][32][32][32] weights for the pattern, nullptr = uniform proposal
     const uint8_t* vb;      // [n] bucket floor(log2(1 + degree)) of every vertex, clipped to 31
+    const int32_t* thr;     // [32] first id of the buckets <= b (buckets do not increase with the id)
+    int32_t lane_thr;       // in the kernel: thr[lane] for lanes < 32
 };
 
 // Dynamic work distribution of the sampling kernels: NTK ticket counters,
@@ -227,6 +229,7 @@ struct sgpm_graph {
     bool degree_ordered = false;  // canonical ids: degree non-increasing (bucket thresholds valid)
     int32_t bthr[32] = {0};          // host: vertices with bucket > b (bucket thresholds in id order)
     uint8_t* d_vb = nullptr;         // device: bucket of every vertex (canonical graphs)
+    int32_t* d_bthr = nullptr;       // device: bthr
     std::vector<int32_t> perm;
     int64_t* d_off = nullptr;
     int32_t* d_nbr = nullptr;
