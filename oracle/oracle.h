@@ -139,6 +139,8 @@ int32_t orc_bucket(const orc_graph* g, int64_t v);
 void orc_ns_sample_learned(const orc_graph* g, const orc_plan* p, const uint16_t* table, uint64_t seed,
                            uint32_t tag, uint64_t s, const uint64_t* draws, orc_rec* r, double* alpha_f);
 double orc_bf16(double x);
+void orc_learned_features(int pattern, int j, int b0, int bp, int bc, float* x);
+void orc_learned_table(const float* params, int pattern, int k, int bf16, uint16_t* out);
 int orc_mlp_nparams(void);
 double orc_mlp(const float* params, const float* X, const float* y, int64_t N, int bf16, double* s_out,
                double* grads);

@@ -131,6 +131,10 @@ def lib():
         L.orc_bf16.argtypes = [C.c_double]
         L.orc_bf16.restype = C.c_double
         L.orc_mlp_nparams.restype = C.c_int
+        L.orc_learned_table.argtypes = [P, C.c_int, C.c_int, C.c_int, P]
+        L.orc_learned_table.restype = None
+        L.orc_learned_features.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, P]
+        L.orc_learned_features.restype = None
         L.orc_mlp.argtypes = [P, P, P, C.c_int64, C.c_int, P, P]
         L.orc_mlp.restype = C.c_double
         L.orc_digits_to_double.argtypes = [P, C.c_int]
@@ -511,6 +515,22 @@ def sample_learned(g: OGraph, p: Plan, table, seed, tag, s, draws=None):
 
 def bf16(x: float) -> float:
     return float(lib().orc_bf16(x))
+
+
+def learned_table(params, pattern, k, bf16=True):
+    """The learned proposal's uint16 table [8][32][32][32] for pattern slot
+    `pattern` of a k-vertex pattern, from the network's parameters."""
+    P = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+    assert P.size == mlp_nparams()
+    out = np.zeros((8, 32, 32, 32), dtype=np.uint16)
+    lib().orc_learned_table(P.ctypes.data, int(pattern), int(k), 1 if bf16 else 0, out.ctypes.data)
+    return out
+
+
+def learned_features(pattern, j, b0, bp, bc):
+    x = np.zeros(16, dtype=np.float32)
+    lib().orc_learned_features(int(pattern), int(j), int(b0), int(bp), int(bc), x.ctypes.data)
+    return x
 
 
 def mlp_nparams() -> int:

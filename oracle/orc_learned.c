@@ -192,3 +192,49 @@ double orc_mlp(const float* params, const float* X, const float* y, int64_t N, i
 }
 
 #undef RB
+
+/* ------------------------------------------------------------------ table */
+/* The learned proposal's weight table (a project extension; the paper's
+ * lemma of Sec. 4.2 only asks for positive weights).  Cell (j, b0, bp, bc):
+ * step j, degree buckets of v0, of v_{j-1} and of the candidate.  Its features
+ * are, in order: bc/16, b0/16, bp/16, j/8, (bc-bp)/16, (bc-b0)/16, 1, the
+ * one-hot pattern index (8 slots), 0; its score is the network on them.  The
+ * 32 weights of a row (j, b0, bp) are 2^(score - row maximum + 15) rounded to
+ * nearest and held in [1, 65535]; steps outside 2 .. k-2 hold 1 (step k-1, the
+ * last, picks uniformly).  bf16 as in orc_mlp. */
+void orc_learned_features(int pattern, int j, int b0, int bp, int bc, float* x) {
+    x[0] = (float)bc / 16.f;
+    x[1] = (float)b0 / 16.f;
+    x[2] = (float)bp / 16.f;
+    x[3] = (float)j / 8.f;
+    x[4] = (float)(bc - bp) / 16.f;
+    x[5] = (float)(bc - b0) / 16.f;
+    x[6] = 1.f;
+    for (int i = 0; i < 8; i++) x[7 + i] = i == pattern ? 1.f : 0.f;
+    x[15] = 0.f;
+}
+
+void orc_learned_table(const float* params, int pattern, int k, int bf16, uint16_t* out) {
+    float x[32 * NIN];
+    double s[32];
+    for (int j = 0; j < 8; j++)
+        for (int b0 = 0; b0 < 32; b0++)
+            for (int bp = 0; bp < 32; bp++) {
+                uint16_t* row = out + (((size_t)j * 32 + (size_t)b0) * 32 + (size_t)bp) * 32;
+                if (j < 2 || j > k - 2) {
+                    for (int bc = 0; bc < 32; bc++) row[bc] = 1;
+                    continue;
+                }
+                for (int bc = 0; bc < 32; bc++) orc_learned_features(pattern, j, b0, bp, bc, x + bc * NIN);
+                orc_mlp(params, x, NULL, 32, bf16, s, NULL);
+                double mx = s[0];
+                for (int bc = 1; bc < 32; bc++)
+                    if (s[bc] > mx) mx = s[bc];
+                for (int bc = 0; bc < 32; bc++) {
+                    double w = nearbyint(exp2(s[bc] - mx + 15.0));
+                    if (w < 1.0) w = 1.0;
+                    if (w > 65535.0) w = 65535.0;
+                    row[bc] = (uint16_t)w;
+                }
+            }
+}

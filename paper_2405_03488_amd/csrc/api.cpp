@@ -27,8 +27,9 @@ sgpm_status ensure_scratch(sgpm_ctx* c, size_t blocks, size_t slots) {
         if (c->d_partials2) (void)hipFree(c->d_partials2);
         c->d_partials = c->d_partials2 = nullptr;
         c->partial_blocks = 0;
-        HIP_TRY(c, hipMalloc(&c->d_partials, blocks * PF_N * sizeof(unsigned long long)));
-        HIP_TRY(c, hipMalloc(&c->d_partials2, blocks * PF_N * sizeof(unsigned long long)));
+        // a partial per block and per finish group of the block
+        HIP_TRY(c, hipMalloc(&c->d_partials, (blocks + FIN_MAX_GROUPS) * PF_N * sizeof(unsigned long long)));
+        HIP_TRY(c, hipMalloc(&c->d_partials2, (blocks + FIN_MAX_GROUPS) * PF_N * sizeof(unsigned long long)));
         c->partial_blocks = blocks;
     }
     if (!c->st2) HIP_TRY(c, hipStreamCreateWithFlags(&c->st2, hipStreamNonBlocking));
@@ -45,7 +46,11 @@ sgpm_status ensure_scratch(sgpm_ctx* c, size_t blocks, size_t slots) {
         HIP_TRY(c, hipHostMalloc(&c->h_slots, want * SLOT_WORDS * sizeof(unsigned long long),
                                  hipHostMallocMapped | hipHostMallocCoherent));
         HIP_TRY(c, hipHostGetDevicePointer((void**)&c->dh_slots, c->h_slots, 0));
-        HIP_TRY(c, hipMalloc(&c->d_tickets, want * NTK * TK_STRIDE * sizeof(unsigned long long)));
+        // per slot: the ticket counters and the launch's finish counts, zero
+        // between launches (each launch's last block clears them)
+        HIP_TRY(c, hipMalloc(&c->d_tickets, want * SLOT_TK_WORDS * sizeof(unsigned long long)));
+        HIP_TRY(c, hipMemsetAsync(c->d_tickets, 0, want * SLOT_TK_WORDS * sizeof(unsigned long long), c->st));
+        HIP_TRY(c, hipStreamSynchronize(c->st));
         c->nslots = want;
     }
     return SGPM_OK;
@@ -337,25 +342,24 @@ sgpm_status enqueue_range(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_
     }
     const uint64_t per_wave = (uint64_t)(64 / lanes) * (uint64_t)cfg.spl;
     const uint64_t tickets = (s1 - s0 + per_wave - 1) / per_wave;
-    const uint64_t max_blocks = (tickets + 3) / 4;
+    const uint64_t max_blocks = std::min<uint64_t>((tickets + 3) / 4, (uint64_t)FIN_GROUP * FIN_MAX_GROUPS);
     if ((uint64_t)cfg.blocks > max_blocks) cfg.blocks = (int)std::max<uint64_t>(1, max_blocks);
     // partials sized for the largest grid once, so no buffer in flight is freed
     sgpm_status st = ensure_scratch(c, (size_t)largest_grid(c), slot + 1);
     if (st != SGPM_OK) return st;
     hipStream_t sq = second_stream ? c->st2 : c->st;
     unsigned long long* parts = second_stream ? c->d_partials2 : c->d_partials;
-    unsigned long long* tk = c->d_tickets + slot * NTK * TK_STRIDE;
-    HIP_TRY(c, launch_fill_u64(tk, (uint64_t)NTK * TK_STRIDE, 0ull, sq));
+    unsigned long long* tk = c->d_tickets + slot * SLOT_TK_WORDS;
     while (c->kev.size() < 3 * (slot + 1)) {
         hipEvent_t ev;
         HIP_TRY(c, hipEventCreate(&ev));
         c->kev.push_back(ev);
     }
     HIP_TRY(c, hipEventRecord(c->kev[3 * slot], sq));
-    HIP_TRY(c, launch_ns_window(g->view(), p, o.seed, o.query_tag, s0, s1, cfg, tk, parts, o.checksum, count_bytes,
-                                tr, la, sq));
+    // the launch's last block adds the block partials into the slot's host-mapped words
+    HIP_TRY(c, launch_ns_window(g->view(), p, o.seed, o.query_tag, s0, s1, cfg, tk, parts,
+                                c->dh_slots + slot * SLOT_WORDS + 1, o.checksum, count_bytes, tr, la, sq));
     HIP_TRY(c, hipEventRecord(c->kev[3 * slot + 1], sq));
-    HIP_TRY(c, launch_reduce_partials(parts, cfg.blocks, c->dh_slots + slot * SLOT_WORDS + 1, sq));
     HIP_TRY(c, hipEventRecord(c->kev[3 * slot + 2], sq));
     return SGPM_OK;
 }

@@ -23,21 +23,86 @@
 //
 // Sums: each lane accumulates X into a 192-bit and X^2 into a 320-bit integer;
 // the block turns them into 32-bit digits, adds, normalises and writes a
-// 20-word partial; a second kernel adds the partials.  Integer addition makes
-// the result independent of the schedule.
+// 20-word partial; the launch's last block adds the partials.  Integer
+// addition makes the result independent of the schedule.
 #include "ns_device.h"
 
 namespace sgpm {
 
+// Sum of `nrows` 20-word rows (nrows <= 64) into out[0..PF_N) by the block:
+// thread t < 240 adds column t % 20 of rows t / 20, t / 20 + 12, ... (at most
+// six independent loads), then 20 threads add the 12 part sums.  `red` holds
+// 240 words of LDS.
+__device__ __forceinline__ void sum_rows(const unsigned long long* rows, int nrows, unsigned long long* out,
+                                         unsigned long long* red) {
+    const int t = (int)threadIdx.x;
+    if (t < 240) {
+        const int col = t % PF_N;
+        unsigned long long a = 0;
+        for (int r = t / PF_N; r < nrows; r += 240 / PF_N) a += rows[(size_t)r * PF_N + col];
+        red[t] = a;
+    }
+    __syncthreads();
+    if (t < PF_N) {
+        unsigned long long a = 0;
+        for (int k = 0; k < 240 / PF_N; ++k) a += red[k * PF_N + t];
+        out[t] = a;
+    }
+    __syncthreads();
+}
+
+// End of a sampling launch, after this block's partial (20 words at
+// partials[blockIdx.x]) is written: the partials are added in a two-level
+// tree.  Blocks finish in groups of FIN_GROUP; the last block of a group to
+// finish adds the group's partials into a group partial (after the launch's
+// block partials), and the last group to finish adds the group partials into
+// `out` (host-mapped, 20 words) and clears the ticket counters and the finish
+// counts, so the next launch on this slot starts from zero.  Each finish count
+// is taken after a release fence, and its last taker fences (acquire) before
+// reading: the blocks run on different XCDs, whose L2s are not coherent.
+// `ticket`: NTK counters TK_STRIDE words apart, then the counts FIN_STRIDE
+// words apart (index 0: the groups, 1 + g: group g).  `red`: 240 words of LDS.
+__device__ __forceinline__ void fold_launch(unsigned long long* partials, unsigned long long* ticket,
+                                            unsigned long long* out, unsigned long long* red, int* flag) {
+    unsigned long long* fin = ticket + (size_t)NTK * TK_STRIDE;
+    const int nb = (int)gridDim.x, ng = (nb + FIN_GROUP - 1) / FIN_GROUP, gi = (int)blockIdx.x / FIN_GROUP;
+    const int gsize = min(FIN_GROUP, nb - gi * FIN_GROUP);
+    unsigned long long* gpart = partials + (size_t)nb * PF_N;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned long long old = atomicAdd(fin + (size_t)(1 + gi) * FIN_STRIDE, 1ull);
+        *flag = old + 1ull == (unsigned long long)gsize ? 1 : 0;
+    }
+    __syncthreads();
+    if (!*flag) return;
+    __threadfence();
+    sum_rows(partials + (size_t)gi * FIN_GROUP * PF_N, gsize, gpart + (size_t)gi * PF_N, red);
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned long long old = atomicAdd(fin, 1ull);
+        *flag = old + 1ull == (unsigned long long)ng ? 1 : 0;
+    }
+    __syncthreads();
+    if (!*flag) return;
+    __threadfence();
+    sum_rows(gpart, ng, out, red);
+    const int t = (int)threadIdx.x;
+    if (t < NTK) ticket[(size_t)t * TK_STRIDE] = 0ull;
+    else if (t < NTK + 1 + ng) fin[(size_t)(t - NTK) * FIN_STRIDE] = 0ull;
+    __threadfence_system();  // `out` is host memory read after the stream's next event
+}
+
 template <int G>
 __global__ __launch_bounds__(256) void ns_window_kernel(DGraph g, Plan p, uint64_t seed, uint32_t tag, uint64_t s0,
                                                         uint64_t s1, int spl, unsigned long long* __restrict__ ticket,
-                                                        unsigned long long* __restrict__ partials, int checksum,
+                                                        unsigned long long* __restrict__ partials,
+                                                        unsigned long long* __restrict__ out, int checksum,
                                                         int count_bytes, TraceArgs tr) {
     const int lane = (int)(threadIdx.x & 63);
     const bool leader = (lane & (G - 1)) == 0;
     const uint64_t per_wave = (uint64_t)(64 / G) * (uint64_t)spl;
-    __shared__ int32_t s_list[LDS_WORDS];
+    __shared__ __align__(16) int32_t s_list[LDS_WORDS];
     int32_t* list = s_list + (threadIdx.x / G) * (LDS_WORDS / (256 / G));
     Acc a;
 #pragma unroll
@@ -46,19 +111,11 @@ __global__ __launch_bounds__(256) void ns_window_kernel(DGraph g, Plan p, uint64
     for (int i = 0; i < 5; ++i) a.s2[i] = 0;
     a.hits = a.csum = a.bytes = a.ovf = 0;
 
-    // ticket == nullptr: static interleaving, wave w takes tickets w, w + W, ...
-    const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x >> 6);
-    uint64_t tstat = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const uint64_t ntickets = (s1 - s0 + per_wave - 1) / per_wave;
     int tk_cur = (int)(blockIdx.x % NTK), tk_left = NTK;
     for (;;) {
         uint64_t t = 0;
-        if (ticket) {
-            if (!next_ticket(ticket, ntickets, tk_cur, tk_left, t)) break;
-        } else {
-            t = tstat;
-            tstat += nwaves;
-        }
+        if (!next_ticket(ticket, ntickets, tk_cur, tk_left, t)) break;
         const uint64_t base = s0 + t * per_wave;
         if (base >= s1) break;
         for (int q = 0; q < spl; ++q) {
@@ -148,6 +205,8 @@ __global__ __launch_bounds__(256) void ns_window_kernel(DGraph g, Plan p, uint64
         unsigned long long* dst = partials + (size_t)blockIdx.x * PF_N;
         for (int i = 0; i < PF_N; ++i) dst[i] = o[i];
     }
+    __shared__ int s_last;
+    fold_launch(partials, ticket, out, reinterpret_cast<unsigned long long*>(s_list), &s_last);
 }
 
 // One sample per wave, samples handled in groups of up to GMAX per wave:
@@ -180,14 +239,15 @@ __device__ __forceinline__ uint32_t draw_of_slot(int t) {
 template <int MODE, int K, bool CLQ>
 __global__ __launch_bounds__(256, wave_occupancy(MODE, CLQ)) void ns_wave_kernel(DGraph g, Plan p, uint64_t seed, uint32_t tag, uint64_t s0,
                                                       uint64_t s1, int spl, unsigned long long* __restrict__ ticket,
-                                                      unsigned long long* __restrict__ partials, int checksum,
+                                                      unsigned long long* __restrict__ partials,
+                                                      unsigned long long* __restrict__ out, int checksum,
                                                       int count_bytes, TraceArgs tr, LearnArgs la) {
     constexpr int G = 64;
     constexpr int D = (K - 1) + (MODE == 1 && K > 3 ? K - 3 : 0);  // draws per sample
     constexpr int GS = (64 / D) < GMAX ? (64 / D) : GMAX;
     const int lane = (int)(threadIdx.x & 63);
     const int wid = (int)(threadIdx.x >> 6);
-    __shared__ int32_t s_list[LDS_WORDS];
+    __shared__ __align__(16) int32_t s_list[LDS_WORDS];
     __shared__ uint32_t s_hist[4][32];
     __shared__ __align__(16) uint32_t s_rec[4][GMAX * REC];
     __shared__ unsigned long long s_wsum[4][16];
@@ -202,7 +262,7 @@ __global__ __launch_bounds__(256, wave_occupancy(MODE, CLQ)) void ns_wave_kernel
     __builtin_amdgcn_wave_barrier();
     uint64_t ovf = 0;
     const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x >> 6);
-    uint64_t tstat = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const uint64_t tstat = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const uint64_t ntickets = (s1 - s0 + (uint64_t)spl - 1) / (uint64_t)spl;
     int tk_cur = (int)(blockIdx.x % NTK), tk_left = NTK;
     // tickets 0 .. nwaves-1 go to the waves by index, without an atomic (the
@@ -212,18 +272,13 @@ __global__ __launch_bounds__(256, wave_occupancy(MODE, CLQ)) void ns_wave_kernel
     const uint64_t ndyn = ntickets > nwaves ? ntickets - nwaves : 0;
     for (;;) {
         uint64_t tt = 0;
-        if (ticket) {
-            if (first) {
-                first = false;
-                tt = tstat;
-            } else {
-                uint64_t td = 0;
-                if (ndyn == 0 || !next_ticket(ticket, ndyn, tk_cur, tk_left, td)) break;
-                tt = nwaves + td;
-            }
-        } else {
+        if (first) {
+            first = false;
             tt = tstat;
-            tstat += nwaves;
+        } else {
+            uint64_t td = 0;
+            if (ndyn == 0 || !next_ticket(ticket, ndyn, tk_cur, tk_left, td)) break;
+            tt = nwaves + td;
         }
         const uint64_t base = s0 + tt * (uint64_t)spl;
         if (base >= s1) break;
@@ -360,29 +415,8 @@ __global__ __launch_bounds__(256, wave_occupancy(MODE, CLQ)) void ns_wave_kernel
         unsigned long long* dst = partials + (size_t)blockIdx.x * PF_N;
         for (int i = 0; i < PF_N; ++i) dst[i] = o[i];
     }
-}
-
-__global__ __launch_bounds__(256) void reduce_partials_kernel(const unsigned long long* __restrict__ partials,
-                                                              int nblocks, unsigned long long* __restrict__ out) {
-    unsigned long long acc[PF_N];
-#pragma unroll
-    for (int i = 0; i < PF_N; ++i) acc[i] = 0;
-    for (int b = (int)threadIdx.x; b < nblocks; b += (int)blockDim.x)
-#pragma unroll
-        for (int i = 0; i < PF_N; ++i) acc[i] += partials[(size_t)b * PF_N + i];
-    __shared__ unsigned long long red[4][PF_N];
-    const int lane = (int)(threadIdx.x & 63), w = (int)(threadIdx.x >> 6);
-#pragma unroll
-    for (int i = 0; i < PF_N; ++i) {
-        const unsigned long long x = wave_sum(acc[i]);
-        if (lane == 0) red[w][i] = x;
-    }
-    __syncthreads();
-    if (threadIdx.x < PF_N) {
-        const int i = (int)threadIdx.x;
-        out[i] = red[0][i] + red[1][i] + red[2][i] + red[3][i];
-    }
-    __threadfence_system();  // `out` may be host memory read after the stream's next event
+    __shared__ int s_last;
+    fold_launch(partials, ticket, out, reinterpret_cast<unsigned long long*>(s_list), &s_last);
 }
 
 __global__ void fill_u64_kernel(unsigned long long* p, uint64_t n, unsigned long long v) {
@@ -421,7 +455,7 @@ bool wave_uses_clique_kernel(const Plan& p, const TraceArgs& tr, const LearnArgs
 
 template <int MODE>
 hipError_t launch_wave_mode(const DGraph& g, const Plan& p, uint64_t seed, uint32_t tag, uint64_t s0, uint64_t s1,
-                            const LaunchCfg& cfg, unsigned long long* ticket, unsigned long long* partials,
+                            const LaunchCfg& cfg, unsigned long long* ticket, unsigned long long* partials, unsigned long long* out,
                             int checksum, int count_bytes, const TraceArgs& tr, const LearnArgs& la, hipStream_t st) {
     const dim3 grid((unsigned)cfg.blocks), block(256);
     const bool clq = MODE < 2 && wave_uses_clique_kernel(p, tr, la, count_bytes);
@@ -429,10 +463,10 @@ hipError_t launch_wave_mode(const DGraph& g, const Plan& p, uint64_t seed, uint3
     case KK:                                                                                                      \
         if (MODE < 2 && clq && KK >= 3 && KK <= 6)                                                                \
             hipLaunchKernelGGL((ns_wave_kernel<MODE, KK, MODE < 2 && KK >= 3 && KK <= 6>), grid, block, 0, st, g, p, \
-                               seed, tag, s0, s1, cfg.spl, ticket, partials, checksum, count_bytes, tr, la);      \
+                               seed, tag, s0, s1, cfg.spl, ticket, partials, out, checksum, count_bytes, tr, la); \
         else                                                                                                      \
             hipLaunchKernelGGL((ns_wave_kernel<MODE, KK, false>), grid, block, 0, st, g, p, seed, tag, s0, s1,    \
-                               cfg.spl, ticket, partials, checksum, count_bytes, tr, la);                         \
+                               cfg.spl, ticket, partials, out, checksum, count_bytes, tr, la);                    \
         break;
     switch (p.k) {
         SGPM_WAVE_CASE(2)
@@ -450,16 +484,16 @@ hipError_t launch_wave_mode(const DGraph& g, const Plan& p, uint64_t seed, uint3
 }
 
 hipError_t launch_wave(const DGraph& g, const Plan& p, uint64_t seed, uint32_t tag, uint64_t s0, uint64_t s1,
-                       const LaunchCfg& cfg, unsigned long long* ticket, unsigned long long* partials, int checksum,
+                       const LaunchCfg& cfg, unsigned long long* ticket, unsigned long long* partials, unsigned long long* out, int checksum,
                        int count_bytes, const TraceArgs& tr, const LearnArgs& la, hipStream_t st) {
-    if (cfg.base) return launch_wave_mode<3>(g, p, seed, tag, s0, s1, cfg, ticket, partials, checksum, 0, tr, la, st);
-    if (la.table) return launch_wave_mode<1>(g, p, seed, tag, s0, s1, cfg, ticket, partials, checksum, count_bytes, tr, la, st);
-    if (tr.sizes) return launch_wave_mode<2>(g, p, seed, tag, s0, s1, cfg, ticket, partials, checksum, count_bytes, tr, la, st);
-    return launch_wave_mode<0>(g, p, seed, tag, s0, s1, cfg, ticket, partials, checksum, count_bytes, tr, la, st);
+    if (cfg.base) return launch_wave_mode<3>(g, p, seed, tag, s0, s1, cfg, ticket, partials, out, checksum, 0, tr, la, st);
+    if (la.table) return launch_wave_mode<1>(g, p, seed, tag, s0, s1, cfg, ticket, partials, out, checksum, count_bytes, tr, la, st);
+    if (tr.sizes) return launch_wave_mode<2>(g, p, seed, tag, s0, s1, cfg, ticket, partials, out, checksum, count_bytes, tr, la, st);
+    return launch_wave_mode<0>(g, p, seed, tag, s0, s1, cfg, ticket, partials, out, checksum, count_bytes, tr, la, st);
 }
 
 hipError_t launch_ns_window(const DGraph& g, const Plan& p, uint64_t seed, uint32_t tag, uint64_t s0, uint64_t s1,
-                            const LaunchCfg& cfg, unsigned long long* ticket, unsigned long long* partials,
+                            const LaunchCfg& cfg, unsigned long long* ticket, unsigned long long* partials, unsigned long long* out,
                             int checksum, int count_bytes, const TraceArgs& tr, const LearnArgs& la,
                             hipStream_t st) {
     const dim3 grid((unsigned)cfg.blocks), block(256);
@@ -467,18 +501,18 @@ hipError_t launch_ns_window(const DGraph& g, const Plan& p, uint64_t seed, uint3
     switch (cfg.lanes) {
         case 1:
             hipLaunchKernelGGL(ns_window_kernel<1>, grid, block, 0, st, g, p, seed, tag, s0, s1, cfg.spl, ticket,
-                               partials, checksum, count_bytes, tr);
+                               partials, out, checksum, count_bytes, tr);
             break;
         case 4:
             hipLaunchKernelGGL(ns_window_kernel<4>, grid, block, 0, st, g, p, seed, tag, s0, s1, cfg.spl, ticket,
-                               partials, checksum, count_bytes, tr);
+                               partials, out, checksum, count_bytes, tr);
             break;
         case 16:
             hipLaunchKernelGGL(ns_window_kernel<16>, grid, block, 0, st, g, p, seed, tag, s0, s1, cfg.spl, ticket,
-                               partials, checksum, count_bytes, tr);
+                               partials, out, checksum, count_bytes, tr);
             break;
         case 64:
-            return launch_wave(g, p, seed, tag, s0, s1, cfg, ticket, partials, checksum, count_bytes, tr, la, st);
+            return launch_wave(g, p, seed, tag, s0, s1, cfg, ticket, partials, out, checksum, count_bytes, tr, la, st);
             break;
         default:
             return hipErrorInvalidValue;
@@ -516,10 +550,5 @@ int ns_blocks_per_cu(int lanes) {
     return nb;
 }
 
-hipError_t launch_reduce_partials(const unsigned long long* partials, int nblocks, unsigned long long* out20,
-                                  hipStream_t st) {
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(256), 0, st, partials, nblocks, out20);
-    return hipGetLastError();
-}
 
 }  // namespace sgpm

@@ -59,6 +59,13 @@ struct LearnArgs {
 // TK_STRIDE words apart, counter x handing out tickets x, x + NTK, ...
 constexpr int NTK = 8;
 constexpr int TK_STRIDE = 32;
+// The launch's finish counts (after the ticket counters of a slot): blocks
+// finish in groups of FIN_GROUP, one count per group and one over the groups,
+// each in a 128-byte line of its own.
+constexpr int FIN_GROUP = 64;
+constexpr int FIN_MAX_GROUPS = 32;  // so a launch has at most 2048 blocks
+constexpr int FIN_STRIDE = 16;
+constexpr size_t SLOT_TK_WORDS = (size_t)NTK * TK_STRIDE + (size_t)(1 + FIN_MAX_GROUPS) * FIN_STRIDE;
 
 struct LaunchCfg {
     int lanes;     // lanes cooperating on one sample: 1, 4, 16, 64
@@ -68,12 +75,15 @@ struct LaunchCfg {
 };
 
 // kernels (ns_kernels.hip)
+// One sampling launch over [s0, s1) of at most FIN_GROUP * FIN_MAX_GROUPS
+// blocks: ticket = SLOT_TK_WORDS words (NTK counters TK_STRIDE words apart,
+// then the finish counts), zero before the launch and left zero by it;
+// partials = one 20-word partial per block and per finish group; out = the
+// launch's 20-word sums (PF_* layout), written by its last block.
 hipError_t launch_ns_window(const DGraph& g, const Plan& p, uint64_t seed, uint32_t tag, uint64_t s0, uint64_t s1,
                             const LaunchCfg& cfg, unsigned long long* ticket, unsigned long long* partials,
-                            int checksum, int count_bytes, const TraceArgs& tr, const LearnArgs& la,
-                            hipStream_t st);
-hipError_t launch_reduce_partials(const unsigned long long* partials, int nblocks, unsigned long long* out20,
-                                  hipStream_t st);
+                            unsigned long long* out, int checksum, int count_bytes, const TraceArgs& tr,
+                            const LearnArgs& la, hipStream_t st);
 int ns_blocks_per_cu(int lanes);
 int ns_clique_blocks_per_cu();  // the uniform clique kernels (compiled for more blocks)
 bool plan_is_clique(const Plan& p);
@@ -200,7 +210,7 @@ struct sgpm_ctx {
     hipStream_t st2 = nullptr;  // a window queued ahead runs here, beside the one on st
     unsigned long long* h_slots = nullptr;   // pinned host slots: per launch its 20 sums (32 words a slot)
     unsigned long long* dh_slots = nullptr;  // the same memory as seen from the device
-    unsigned long long* d_tickets = nullptr; // per launch: NTK ticket counters, TK_STRIDE words apart
+    unsigned long long* d_tickets = nullptr; // per slot: SLOT_TK_WORDS words of ticket counters and finish counts
     size_t nslots = 0;
     std::vector<hipEvent_t> kev;             // start/stop events around each sampling kernel
     // batch: autotuned lanes per (graph, plan), device/pinned tables, captured graph

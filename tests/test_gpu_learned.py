@@ -256,6 +256,22 @@ def test_trained_proposal_is_unbiased_and_reduces_variance(S, O, synth, ctx, rma
         assert abs(rl.estimate - C_exact) < 4 * sig
         # the trained proposal lowers the predicted error at the same sample count
         assert rl.eps_hat < ru.eps_hat
+    # the tables the estimates used, against the oracle's quantisation of the
+    # same network (BF16 operands as on the device, FP64 accumulation): the
+    # device accumulates in FP32, so a score can differ in its last bits and a
+    # weight near a rounding boundary by one unit; a flipped BF16 rounding of a
+    # hidden activation moves a row's scores by up to ~1e-3, a weight by <0.1 %
+    for i, nm in enumerate(names):
+        k, _ = synth.pattern(nm)
+        dev = S.sgpm_model_table(model, i).astype(np.int64)
+        orc = O.learned_table(info["params"], i, k).astype(np.int64)
+        diff = np.abs(dev - orc)
+        same = float(np.mean(diff == 0))
+        print(nm, "table entries equal to the oracle's:", same, "max |diff|", int(diff.max()), flush=True)
+        assert same >= 0.99
+        assert (diff <= np.maximum(1, orc // 500)).all()
+        # steps outside 2..k-2 are uniform in both
+        assert (dev[:2] == 1).all() and (dev[k - 1:] == 1).all()
     S.sgpm_model_free(model)
     for p in pats:
         S.sgpm_pattern_free(p)

@@ -140,3 +140,80 @@ def test_mlp_forward_matches_numpy(O):
     s = h2 @ w3 + b3
     _, got, _ = O.mlp(params, X, bf16=False)
     assert np.allclose(got, s, rtol=1e-12, atol=1e-12)
+
+
+# --- the learned table from the network (oracle's orc_learned_table) ---------
+# Networks that read chosen features through one hidden unit:
+# s = 16 * relu(sum_i w_i x_i + bias), every weight exact in BF16, so each
+# cell's score is a small integer and every table entry is a known power of two.
+
+def _reader(O, weights, bias=0.0):
+    nh, nin = 64, 16
+    P = np.zeros(O.mlp_nparams(), dtype=np.float32)
+    W1, b1 = 0, nin * nh
+    W2 = b1 + nh
+    w3 = W2 + nh * nh + nh
+    for i, w in weights.items():
+        P[W1 + i * nh + 0] = w
+    P[b1 + 0] = bias
+    P[W2 + 0 * nh + 0] = 1.0
+    P[w3 + 0] = 16.0
+    return P
+
+
+def _quant(scores):
+    mx = max(scores)
+    return [max(1, min(65535, int(round(2.0 ** (s - mx + 15))))) for s in scores]
+
+
+def _check_rows(tab, k, score):
+    """score(j, b0, bp, bc) -> expected score; rows of steps 2..k-2 only."""
+    for j in range(8):
+        for b0 in (0, 5, 31):
+            for bp in (0, 7, 31):
+                row = tab[j, b0, bp]
+                if j < 2 or j > k - 2:
+                    assert (row == 1).all(), (j, b0, bp)
+                    continue
+                want = _quant([score(j, b0, bp, bc) for bc in range(32)])
+                assert list(row) == want, (j, b0, bp, list(row), want)
+
+
+def test_table_constant_network(O):
+    P = np.zeros(O.mlp_nparams(), dtype=np.float32)
+    P[-1] = 3.0  # the output bias only
+    for k in (3, 4, 5, 8):
+        tab = O.learned_table(P, 0, k)
+        _check_rows(tab, k, lambda j, b0, bp, bc: 3.0)
+
+
+def test_table_reads_the_candidate_bucket(O):
+    tab = O.learned_table(_reader(O, {0: 1.0}), 2, 5)
+    _check_rows(tab, 5, lambda j, b0, bp, bc: bc)
+    # the row maximum holds 2^15, buckets 16 and more below it halve per bucket
+    assert tab[2, 3, 4, 31] == 32768 and tab[2, 3, 4, 30] == 16384 and tab[2, 3, 4, 10] == 1
+
+
+def test_table_reads_bucket_differences(O):
+    # candidate minus v_{j-1}: directly, and through the separate features
+    for w in ({4: 1.0}, {0: 1.0, 2: -1.0}):
+        _check_rows(O.learned_table(_reader(O, w), 0, 6), 6, lambda j, b0, bp, bc: max(0, bc - bp))
+    # candidate minus v0
+    for w in ({5: 1.0}, {0: 1.0, 1: -1.0}):
+        _check_rows(O.learned_table(_reader(O, w), 0, 6), 6, lambda j, b0, bp, bc: max(0, bc - b0))
+
+
+def test_table_reads_step_and_pattern(O):
+    # the step: j/8 weighted 8 with bias -2.5 shifts step 2 below step 3
+    tab = O.learned_table(_reader(O, {0: 1.0, 3: 8.0}, -2.5), 0, 5)
+    _check_rows(tab, 5, lambda j, b0, bp, bc: max(0.0, bc + 16 * (j - 2.5)))
+    assert tab[2, 0, 0, 7] == 1 and tab[3, 0, 0, 7] == 1 and tab[3, 0, 0, 31] == 32768
+    # the pattern slot: only the model's own slot opens the candidate ramp
+    for q in range(8):
+        P = _reader(O, {0: 1.0, 7 + q: 4.0}, -3.0)
+        for pat in (0, 3, 7):
+            tab = O.learned_table(P, pat, 4)
+            if pat == q:
+                _check_rows(tab, 4, lambda j, b0, bp, bc: bc + 16)
+            else:
+                _check_rows(tab, 4, lambda j, b0, bp, bc: 0.0)
