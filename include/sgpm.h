@@ -244,14 +244,24 @@ sgpm_status sgpm_estimate(sgpm_ctx_t ctx, sgpm_graph_t g, sgpm_pattern_t p, cons
 
 /* sgpm_estimate in the NS modes with result.bytes filled: the algorithmic bytes
  * of every sample (8 for the first edge, 16 per earlier vertex whose row a step
- * reads, 4 per entry of the smallest connected row inside the step's bounds).
- * Uses an instrumented build of the sampling kernel; for measurement. */
+ * reads, 4 per entry of every row the step merges -- its connected rows and,
+ * vertex-induced, its disconnected rows -- inside the step's bounds; Sec. 4.2
+ * set operations, Sec. 4.3 work per sample).  Uses an instrumented build of the
+ * sampling kernel; for measurement. */
 sgpm_status sgpm_estimate_counted(sgpm_ctx_t ctx, sgpm_graph_t g, sgpm_pattern_t p, const sgpm_options* o,
                                   sgpm_result* res);
 
-/* Estimate nq queries (graphs[i], patterns[i], opts[i]) in one persistent
- * launch; each query keeps its own windows and stop rule and its result equals
- * the solo sgpm_estimate result bit for bit (NS modes only). */
+/* Estimate nq queries (graphs[i], patterns[i], opts[i]) in one persistent,
+ * hipGraph-captured launch; each query keeps its own windows and stop rule
+ * (Sec. 4.1 NS-online, with the window barrier of Sec. 5.4 taken on the device)
+ * and its result equals the solo sgpm_estimate result bit for bit.  Queries are
+ * NS-prune, strict or fixed-n, uniform proposal, no trace (else EUNSUPPORTED).
+ * Per query an autotuner picks the lanes per sample (opts[i].lanes_per_sample,
+ * or the solo estimate's choice for that graph and pattern, or timed pilot
+ * samples on the query's pilot stream at 64, 16, 4, 1) and the tile of samples
+ * per ticket; result.lanes_per_sample and result.tile report them.  Graphs,
+ * patterns and options stay owned by the caller; res[nq] is filled.  EINVAL on
+ * bad arguments (nq <= 0, null handles, lanes not in {0, 1, 4, 16, 64}). */
 sgpm_status sgpm_estimate_batch(sgpm_ctx_t ctx, int nq, const sgpm_graph_t* graphs,
                                 const sgpm_pattern_t* patterns, const sgpm_options* opts, sgpm_result* res);
 
