@@ -95,6 +95,15 @@ __device__ __forceinline__ int32_t uni(int32_t x) {
     if constexpr (G == 64) return rfl(x);
     else return x;
 }
+// The value of v in lane `src` (an absolute lane of the wave).  One sample per
+// wave (G = 64): src is wave-uniform and the value comes back by readlane,
+// with no LDS round trip; a group of G < 64 lanes uses a lane permute.
+template <int G>
+__device__ __forceinline__ int32_t from_lane(int32_t v, int src) {
+    if constexpr (G == 64) return __builtin_amdgcn_readlane(v, src);
+    else return __shfl(v, src);
+}
+
 // candidate lists per block (14 KB): with the records and sums, eight
 // one-sample-per-wave blocks fit a CU's 160 KB of LDS
 constexpr int LDS_WORDS = 3584;
@@ -136,14 +145,19 @@ __device__ __forceinline__ bool member(const int32_t* __restrict__ R, int32_t rl
         bool found = false, pending = act;
         int32_t b = (c + gl < rl) ? R[c + gl] : BIG;
         for (;;) {
-            const int32_t bmax = uni<G>(__shfl(b, gbase + G - 1));
-            int pos = 0;
+            const int32_t bmax = uni<G>(from_lane<G>(b, gbase + G - 1));
+            // binary search of x in the window through lane permutes, the
+            // position kept as the permute's byte address (lane * 4); a
+            // position of G (every entry below x) reads another lane, and the
+            // test below ignores it
+            int pb = gbase * 4;
 #pragma unroll
             for (int st = G / 2; st >= 1; st >>= 1) {
-                const int32_t bv = __shfl(b, gbase + pos + st - 1);
-                if (bv < x) pos += st;
+                const int32_t bv = __builtin_amdgcn_ds_bpermute(pb + (st - 1) * 4, b);
+                pb += bv < x ? st * 4 : 0;
             }
-            const int32_t bq = __shfl(b, gbase + (pos < G ? pos : G - 1));
+            const int pos = (pb >> 2) - gbase;
+            const int32_t bq = __builtin_amdgcn_ds_bpermute(pb, b);
             const bool res = pending && x <= bmax;
             if (res) found = pos < G && bq == x;
             pending = pending && !res;
@@ -154,7 +168,7 @@ __device__ __forceinline__ bool member(const int32_t* __restrict__ R, int32_t rl
             }
             const bool below = group_ballot<G>(res, gmask) == 0;  // the window lies below every pending x
             c += G;
-            const int32_t xmin = below && rl - c > 8 * G ? uni<G>(__shfl(x, __ffsll((unsigned long long)pend) - 1)) : 0;
+            const int32_t xmin = below && rl - c > 8 * G ? uni<G>(from_lane<G>(x, __ffsll((unsigned long long)pend) - 1)) : 0;
             if (below && rl - c > 8 * G && uni<G>(R[c + 8 * G - 1]) < xmin) {
                 // more than 8 windows from the smallest pending x: a G-ary search
                 // for the first entry >= it, each round probing G evenly spaced
@@ -402,7 +416,7 @@ __device__ __forceinline__ uint32_t ns_sample(const DGraph& g, const Plan& p, ui
             for (int i = 0; i < j; ++i)
                 if (excl >> i & 1) ok = ok && (x != v[i]);
             if (inm == 0) return false;
-            const int32_t xmax = uni<G>(__shfl(x, gbase + (int)__popcll(inm) - 1));
+            const int32_t xmax = uni<G>(from_lane<G>(x, gbase + (int)__popcll(inm) - 1));
 #pragma unroll
             for (int i = 0; i < j; ++i) {
                 if (need >> i & 1) {
@@ -522,7 +536,7 @@ __device__ __forceinline__ uint32_t ns_sample(const DGraph& g, const Plan& p, ui
                 const uint32_t c = (uint32_t)__popcll(okm);
                 if (seen + c > idx) {
                     for (uint32_t t = idx - seen; t > 0; --t) okm &= okm - 1ull;
-                    pick = uni<G>(__shfl(x, __ffsll((unsigned long long)okm) - 1));
+                    pick = uni<G>(from_lane<G>(x, __ffsll((unsigned long long)okm) - 1));
                     break;
                 }
                 seen += c;
