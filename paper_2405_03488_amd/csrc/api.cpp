@@ -414,12 +414,16 @@ sgpm_status ns_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_op
     HIP_TRY(c, ev.create());
     const hipEvent_t e0 = ev[0];  // start of the first window
     NsState s;
-    // a prefix of the estimation stream already drawn (the loose-mode pilot)
+    // a prefix of the estimation stream already drawn (the loose-mode pilot):
+    // part of the first window, or the whole of it (then its stop test runs
+    // below, before any launch)
     uint64_t prefix_n = 0;
-    if (ex && ex->prefix_n && o.mode != SGPM_MODE_FIXED_N && ex->prefix_n < next_window_end(0, o) && !ntr &&
+    bool prefix_window = false;
+    if (ex && ex->prefix_n && o.mode != SGPM_MODE_FIXED_N && ex->prefix_n <= next_window_end(0, o) && !ntr &&
         !count_bytes) {
         absorb(s, ex->prefix_sums);
         prefix_n = ex->prefix_n;
+        prefix_window = prefix_n == next_window_end(0, o);
         s.n = prefix_n;
     }
     int lanes = o.lanes_per_sample;
@@ -456,12 +460,30 @@ sgpm_status ns_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_op
     uint64_t queued = prefix_n;
     size_t last_done = SIZE_MAX;
     HIP_TRY(c, hipEventRecord(e0, c->st));
-    for (;;) {
+    // the stop test of a first window the prefix completed, as after any window
+    bool done_early = false;
+    if (prefix_window) {
+        windows = 1;
+        const double eh = predicted_error(z, s.n, s.S1, s.S2);
+        if (s.ovf) {
+            status = SGPM_EOVERFLOW;
+            done_early = true;
+        } else if (eh <= o.eps) {
+            converged = true;
+            done_early = true;
+        } else if (o.max_samples && s.n >= o.max_samples) {
+            done_early = true;
+        } else if (may_queue_ahead && std::isfinite(eh) && eh > 0) {
+            const double r = eh / o.eps, need = (double)s.n * r * r;
+            if (need > 1.1 * (double)next_window_end(s.n, o)) depth = 2;
+        }
+    }
+    for (; !done_early;) {
         while (inflight.size() < depth) {
             // the window that holds sample `queued` (a prefix may end inside the first window)
             // a prefix ends inside the first window, which then starts at the prefix's end
             const uint64_t nx = o.mode == SGPM_MODE_FIXED_N ? o.fixed_n
-                                : next_window_end(queued == prefix_n ? 0 : queued, o);
+                                : next_window_end(queued == prefix_n && !prefix_window ? 0 : queued, o);
             if (nx <= queued || (o.mode == SGPM_MODE_FIXED_N && queued > 0)) break;
             if (lanes == 0 && nx - queued >= (1ull << 19)) {
                 if (!inflight.empty()) break;  // tune once the queue has drained
@@ -594,7 +616,8 @@ sgpm_status ns_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_op
             }
         }
         if (b > a) busy += b - a;
-        res->seconds_kernel_busy = busy * 1e-3;
+        // a prefix's launches ran before e0, one after another
+        res->seconds_kernel_busy = busy * 1e-3 + (prefix_n ? ex->prefix_kernel_s : 0.0);
     }
     res->launches = launches;
     if (o.mode == SGPM_MODE_FIXED_N) converged = res->eps_hat <= o.eps;

@@ -9,14 +9,14 @@
 // confidence guarantee.  Its profiler and GS cost formulas are not usable as
 // printed, so both predictions here come from measurements on this device:
 //
-//  * NS: a pilot of the estimation stream itself (tag q, sample ids [0, P) with
-//    P inside the first window) in four slices of P/8, P/8, P/4 and P/2
-//    samples, one launch each.  Their kernel times fit t0 + n / rate (the
-//    launch's fixed cost and the steady rate).  By the error equation (Sec.
-//    4.1) the samples needed for eps scale as (eps_hat / eps)^2, so slice i
-//    predicts N_i = n_i (eps_hat_i / eps)^2 samples taking N_i / rate plus t0
-//    per window of the schedule up to N_i; the slices' minimum and maximum are
-//    the cone.  When NS runs, the pilot's samples are its first ones.
+//  * NS: a pilot of the estimation stream itself (tag q): its first window,
+//    in two slices (the first quarter and the rest), one launch each.  Their
+//    kernel times fit t0 + n / rate (the launch's fixed cost and the steady
+//    rate).  By the error equation (Sec. 4.1) the samples needed for eps scale
+//    as (eps_hat / eps)^2, so slice i predicts N_i = n_i (eps_hat_i / eps)^2
+//    samples taking N_i / rate plus t0 per window of the schedule up to N_i;
+//    the slices' minimum and maximum are the cone.  When NS runs, the pilot is
+//    its first window (its stop test is the first one the estimate applies).
 //  * GS: colourings 0 and 1 of the GS engine itself (timed end to end:
 //    sparsification and count).  Their relative spread (the unbiased standard
 //    deviation of one colouring's estimate over their mean, cv) gives the
@@ -170,27 +170,23 @@ sgpm_status hybrid_estimate(sgpm_ctx* c, sgpm_graph* g, sgpm_pattern* pat, const
         if (st != SGPM_OK) return st;
     }
     if (M > 0) {
-        // NS pilot: the first samples of the estimation stream, inside its first window
-        constexpr int kSlices = 4;
+        // NS pilot: the estimation stream's first window, in two slices (its
+        // first quarter and the rest); when NS is chosen the window is done
         sgpm_options po = o;
         po.checksum = o.checksum;
         po.trace_lo = po.trace_hi = 0;
         po.trace_buf = nullptr;
         const uint64_t first = next_window_end(0, o);
-        uint64_t n_pilot = std::max<uint64_t>(1ull << 16, o.n_min / 4);
-        if (n_pilot >= first) n_pilot = first / 2;
-        n_pilot = std::max<uint64_t>(8, n_pilot / 8 * 8);
-        const uint64_t ends[kSlices] = {n_pilot / 8, n_pilot / 4, n_pilot / 2, n_pilot};
-        double sn[kSlices], sec[kSlices], eh[kSlices], mu = 0.0;
-        for (int i = 0; i < kSlices; i++) sn[i] = (double)(ends[i] - (i ? ends[i - 1] : 0));
-        sgpm_status st = ns_pilot(c, g, p, po, ex.la, kSlices, ends, sec, eh, &mu, ex.prefix_sums);
+        const int slices = first >= 8 ? 2 : 1;
+        const uint64_t ends[2] = {slices == 2 ? first / 4 : first, first};
+        double sn[2], sec[2], eh[2], mu = 0.0;
+        for (int i = 0; i < slices; i++) sn[i] = (double)(ends[i] - (i ? ends[i - 1] : 0));
+        sgpm_status st = ns_pilot(c, g, p, po, ex.la, slices, ends, sec, eh, &mu, ex.prefix_sums);
         if (st != SGPM_OK) return st;
-        if (n_pilot < first) {
-            ex.prefix_n = n_pilot;
-            ex.prefix_launches = kSlices;
-            for (double x : sec) ex.prefix_kernel_s += x;
-        }
-        ns_cone(kSlices, sn, sec, eh, o, &ns_lo, &ns_hi, nullptr, nullptr);
+        ex.prefix_n = first;
+        ex.prefix_launches = slices;
+        for (int i = 0; i < slices; i++) ex.prefix_kernel_s += sec[i];
+        ns_cone(slices, sn, sec, eh, o, &ns_lo, &ns_hi, nullptr, nullptr);
         // lower bound of two colourings from the leaves they must reach
         double leaves = mu;
         for (int i = 0; i < p.k - 1; i++) leaves /= (double)col;

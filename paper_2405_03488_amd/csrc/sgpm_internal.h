@@ -131,7 +131,7 @@ struct NsExtra {
     uint32_t* d_sizes;   // pilot traces: |S_j| per traced sample
     // samples [0, prefix_n) of the estimation stream already drawn (the
     // loose-mode pilot): their window sums, kernel seconds and launches; used
-    // by a strict run when prefix_n lies inside its first window
+    // by a strict run when prefix_n lies inside its first window or ends it
     uint64_t prefix_n;
     unsigned long long prefix_sums[PF_N];
     double prefix_kernel_s;
