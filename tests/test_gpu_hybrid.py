@@ -57,6 +57,47 @@ def test_hybrid_picks_ns_for_a_common_pattern(S, synth, ctx):
     S.sgpm_graph_free(g)
 
 
+@pytest.mark.parametrize("case", ["stops_in_pilot", "max_samples_first", "tiny_first", "many_windows"])
+def test_pilot_window_ends(S, O, synth, ctx, case):
+    """The NS pilot is the estimate's first window: when NS is chosen the
+    estimate applies that window's stop test before any launch of its own.
+    Whether the run stops there (eps reached, max_samples reached) or goes on
+    (tiny first windows, many windows), the hybrid result equals strict NS and
+    the oracle's run bit for bit."""
+    n = 20000
+    off, nbr = synth.pairs_to_csr(n, synth.chung_lu_pairs(n, 16, 2.1, 4))
+    g = S.sgpm_graph_from_csr(ctx, n, off, nbr)
+    og = O.OGraph.from_raw_csr(n, off, nbr)
+    k, e = synth.pattern("triangle")
+    p = S.sgpm_pattern_create(ctx, k, e)
+    kw = {"stops_in_pilot": dict(eps=0.2, n_min=1 << 16, w_min=1 << 14, quantum=1),
+          "max_samples_first": dict(eps=1e-4, n_min=1 << 15, w_min=1 << 14, quantum=1, max_samples=1 << 15),
+          "tiny_first": dict(eps=0.03, n_min=5, w_min=1 << 12, quantum=1),
+          "many_windows": dict(eps=0.01, n_min=1 << 12, w_min=1 << 12, quantum=1 << 8)}[case]
+    kw.update(seed=21, checksum=1, colours=2)
+    rh = run_pair(S, ctx, g, p, **kw)
+    if case in ("stops_in_pilot", "max_samples_first"):
+        assert rh.scheme == S.SCHEME_NS  # one window of NS against two colourings
+    elif rh.scheme == S.SCHEME_GS:
+        # the pilots chose GS (equal to the GS mode's run, checked above)
+        S.sgpm_pattern_free(p)
+        S.sgpm_graph_free(g)
+        return
+    oo = O.make_opts(eps=kw["eps"], confidence=0.95, seed=21, tag=0, n_min=kw["n_min"], w_min=kw["w_min"],
+                     quantum=kw["quantum"], max_samples=kw.get("max_samples", 1 << 40))
+    orr = O.run(og, O.compile_plan(k, e), oo)
+    assert rh.n_samples == orr.n and rh.windows == orr.windows and rh.converged == orr.converged
+    assert rh.S1 == orr.S1 and rh.S2 == orr.S2 and rh.checksum == orr.checksum
+    if case == "stops_in_pilot":
+        assert rh.windows == 1 and rh.converged == 1
+    if case == "max_samples_first":
+        assert rh.windows == 1 and rh.converged == 0 and rh.n_samples == 1 << 15
+    if case == "many_windows":
+        assert rh.windows > 3
+    S.sgpm_pattern_free(p)
+    S.sgpm_graph_free(g)
+
+
 def planted(synth, n, m, cliques, k, seed):
     rng = np.random.default_rng(seed)
     pairs = [synth.er_pairs(n, m, seed)]
