@@ -620,6 +620,22 @@ def main():
                         "mean_smallest_row_only": float(np.mean(minb)),
                         "by_end": {k2: {"samples": len(v), "mean": float(np.mean(v))} for k2, v in sorted(ends.items())}}
         cpu_bytes = bdist
+        # the GS exact count's algorithmic bytes (every node of the search tree)
+        # on the GS leg's two colourings, from the oracle, against the count
+        # kernels' time in that leg
+        if other is not None and other.get("gs"):
+            gsr = {}
+            for q in queries:
+                kq, eq = synth.pattern(q)
+                opq = O.compile_plan(kq, eq)
+                t0 = time.perf_counter()
+                gb = sum(O.gs_count_bytes(og, opq, 16, 5, r) for r in range(int(other["gs"][q]["colourings"])))
+                kt = other["gs"][q]["count_kernel_s"]
+                gsr[q] = {"alg_bytes": gb, "count_kernel_s": kt, "achieved_GBs": gb / kt / 1e9 if kt > 0 else None,
+                          "frac_of_hbm_peak": gb / kt / 1e9 / HBM_PEAK_GBS if kt > 0 else None,
+                          "oracle_s": time.perf_counter() - t0}
+                log(f"gs count {q}: {gb} algorithmic bytes in {kt * 1e3:.2f} ms of count kernels")
+            other["gs_count_roofline"] = gsr
 
     value = total_samples / wall
     traffic = measured_traffic(runs, launches)

@@ -92,6 +92,11 @@ int orc_automorphisms(int k, int l, const int32_t* edges);
 void orc_brute_count(const orc_graph* g, int k, int l, const int32_t* edges, int induced,
                      uint64_t* injective_maps, uint64_t* count);
 void orc_plan_count(const orc_graph* g, const orc_plan* p, int nthreads, uint64_t* lo, uint64_t* hi);
+uint64_t orc_plan_count_bytes(const orc_graph* g, const orc_plan* p, int nthreads);
+uint64_t orc_step_bytes(const orc_graph* g, const orc_plan* p, int j, const int32_t* v, uint32_t* opened,
+                        uint64_t* min_b);
+uint64_t orc_gs_count_bytes(const orc_graph* g, const orc_plan* p, uint32_t c, uint64_t seed, uint32_t rep,
+                            int nthreads);
 
 uint64_t orc_candidates(const orc_graph* g, const orc_plan* p, int j, const int32_t* v, int32_t* out);
 void orc_ns_sample(const orc_graph* g, const orc_plan* p, uint64_t seed, uint32_t tag, uint64_t s,

@@ -122,6 +122,10 @@ def lib():
         L.orc_gs_colour.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_int64]
         L.orc_gs_colour.restype = C.c_int32
         L.orc_gs_sparsify.argtypes = [G, P, G]
+        L.orc_plan_count_bytes.argtypes = [G, PL, C.c_int]
+        L.orc_plan_count_bytes.restype = C.c_uint64
+        L.orc_gs_count_bytes.argtypes = [G, PL, C.c_uint32, C.c_uint64, C.c_uint32, C.c_int]
+        L.orc_gs_count_bytes.restype = C.c_uint64
         L.orc_gs_count.argtypes = [G, PL, C.c_uint32, C.c_uint64, C.c_uint32, C.c_int,
                                    C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
         L.orc_bucket.argtypes = [G, C.c_int64]
@@ -409,6 +413,16 @@ def gs_sparsify(g: OGraph, colour) -> OGraph:
     if rc != 0:
         raise ValueError("oracle sparsify failed")
     return OGraph(out)
+
+
+def plan_count_bytes(g: OGraph, p: Plan, threads=None) -> int:
+    """Algorithmic bytes of the exact search over g (every node of the search tree)."""
+    return int(lib().orc_plan_count_bytes(g.ref(), C.byref(p), threads or nthreads()))
+
+
+def gs_count_bytes(g: OGraph, p: Plan, c, seed, rep, threads=None) -> int:
+    """Algorithmic bytes of the exact search on colouring `rep` of the colour scheme."""
+    return int(lib().orc_gs_count_bytes(g.ref(), C.byref(p), c, seed, rep, threads or nthreads()))
 
 
 def gs_count(g: OGraph, p: Plan, c, seed, rep, threads=None) -> int:

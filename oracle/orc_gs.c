@@ -55,6 +55,19 @@ void orc_gs_count(const orc_graph* g, const orc_plan* p, uint32_t c, uint64_t se
     free(colour);
 }
 
+/* the exact search's algorithmic bytes on colouring rep of the colour scheme */
+uint64_t orc_gs_count_bytes(const orc_graph* g, const orc_plan* p, uint32_t c, uint64_t seed, uint32_t rep,
+                            int nthreads) {
+    int32_t* colour = (int32_t*)malloc(sizeof(int32_t) * (size_t)(g->n ? g->n : 1));
+    for (int64_t v = 0; v < g->n; v++) colour[v] = orc_gs_colour(seed, rep, c, v);
+    orc_graph sp;
+    orc_gs_sparsify(g, colour, &sp);
+    uint64_t b = orc_plan_count_bytes(&sp, p, nthreads);
+    orc_graph_free(&sp);
+    free(colour);
+    return b;
+}
+
 /* Bernoulli edge sparsification (Sec. 2.2, the edge-sparsification algorithm
  * and the GS trade-off section): every edge is kept independently with
  * probability p = 1/c, so a match with l pattern edges survives with

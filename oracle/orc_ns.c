@@ -140,8 +140,8 @@ uint64_t orc_candidates(const orc_graph* g, const orc_plan* p, int j, const int3
  * one.  *min_b receives the same sum with only the smallest connected row's
  * entries counted (a lower bound: what a scan of the shortest row alone must
  * read). */
-static uint64_t step_bytes(const orc_graph* g, const orc_plan* p, int j, const int32_t* v, uint32_t* opened,
-                           uint64_t* min_b) {
+uint64_t orc_step_bytes(const orc_graph* g, const orc_plan* p, int j, const int32_t* v, uint32_t* opened,
+                        uint64_t* min_b) {
     int64_t lo = -1, hi = g->n;
     for (int i = 0; i < j; i++) {
         if (p->upper[j] >> i & 1) { if (v[i] < hi) hi = v[i]; }
@@ -188,7 +188,7 @@ void orc_ns_sample(const orc_graph* g, const orc_plan* p, uint64_t seed, uint32_
     unsigned __int128 alpha = M;
     int32_t* buf = NULL;
     for (int j = 2; j < p->k; j++) {
-        r->bytes += step_bytes(g, p, j, r->v, &opened, &r->bytes_min);
+        r->bytes += orc_step_bytes(g, p, j, r->v, &opened, &r->bytes_min);
         uint64_t cnt = orc_candidates(g, p, j, r->v, NULL);
         r->size[j] = cnt;
         if (cnt == 0) {

@@ -259,3 +259,72 @@ void orc_plan_count(const orc_graph* g, const orc_plan* p, int nthreads, uint64_
     *lo = (uint64_t)total;
     *hi = (uint64_t)(total >> 64);
 }
+
+/* Algorithmic bytes of the exact search (Sec. 4.4 nested loops; the work
+ * measure of the GS cost model): the search tree's node at level j (a partial
+ * match v_0..v_{j-1}) forms S_j, reading what one NS step reads from the same
+ * partial match (orc_step_bytes: 16 per row first merged at this level of the
+ * path, 4 per entry of every merged row inside the level's bounds); the sum
+ * runs over every node of every level 2..k-1. */
+typedef struct {
+    const orc_graph* g; const orc_plan* p; uint64_t e0, e1; uint64_t bytes;
+} pb_job;
+
+static uint64_t pb_rec(const orc_graph* g, const orc_plan* p, int j, int32_t* v, uint32_t opened, int32_t* buf,
+                       size_t stride) {
+    uint64_t unused = 0;
+    uint64_t b = orc_step_bytes(g, p, j, v, &opened, &unused);
+    int32_t* mine = buf + (size_t)j * stride;
+    uint64_t cnt = orc_candidates(g, p, j, v, mine);
+    if (j == p->k - 1) return b;
+    for (uint64_t i = 0; i < cnt; i++) {
+        v[j] = mine[i];
+        b += pb_rec(g, p, j + 1, v, opened, buf, stride);
+    }
+    return b;
+}
+
+static void* pb_worker(void* arg) {
+    pb_job* J = (pb_job*)arg;
+    const orc_graph* g = J->g;
+    const orc_plan* p = J->p;
+    int64_t maxdeg = 0;
+    for (int64_t u = 0; u < g->n; u++)
+        if (g->off[u + 1] - g->off[u] > maxdeg) maxdeg = g->off[u + 1] - g->off[u];
+    size_t stride = (size_t)maxdeg + 1;
+    int32_t* buf = (int32_t*)malloc(sizeof(int32_t) * 8 * stride);
+    int32_t v[8];
+    J->bytes = 0;
+    for (uint64_t e = J->e0; e < J->e1; e++) {
+        if (p->oriented) { v[0] = g->esrc[e]; v[1] = g->edst[e]; }
+        else { v[0] = g->arow[e]; v[1] = g->nbr[e]; }
+        J->bytes += 8;  /* the first edge */
+        if (p->k > 2) J->bytes += pb_rec(g, p, 2, v, 0u, buf, stride);
+    }
+    free(buf);
+    return NULL;
+}
+
+uint64_t orc_plan_count_bytes(const orc_graph* g, const orc_plan* p, int nthreads) {
+    uint64_t M = p->oriented ? (uint64_t)g->m : 2 * (uint64_t)g->m;
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 64) nthreads = 64;
+    pthread_t th[64];
+    pb_job jobs[64];
+    uint64_t total = 0;
+    int nblocks = nthreads * 64;
+    for (int base = 0; base < nblocks; base += nthreads) {
+        for (int t = 0; t < nthreads; t++) {
+            int b = base + t;
+            jobs[t].g = g; jobs[t].p = p;
+            jobs[t].e0 = M * (uint64_t)b / (uint64_t)nblocks;
+            jobs[t].e1 = M * (uint64_t)(b + 1) / (uint64_t)nblocks;
+            pthread_create(&th[t], NULL, pb_worker, &jobs[t]);
+        }
+        for (int t = 0; t < nthreads; t++) {
+            pthread_join(th[t], NULL);
+            total += jobs[t].bytes;
+        }
+    }
+    return total;
+}

@@ -106,3 +106,73 @@ def test_bucket_is_floor_log2_one_plus_degree(O, synth):
     # buckets never increase along the degree-descending relabel
     b = [O.bucket(g, v) for v in range(n)]
     assert all(b[i] >= b[i + 1] for i in range(n - 1))
+
+
+def _python_tree_bytes(g, plan):
+    """Algorithmic bytes of the exact search, from the definition: every node
+    of the nested loops (a partial match v_0..v_{j-1} at level j) reads 16 per
+    row first merged at level j along its path and 4 per entry of each merged
+    row inside the level's bounds; 8 per first edge.  Candidates by Python sets."""
+    off, nbr = g.off, g.nbr
+    rows = {u: set(nbr[off[u]:off[u + 1]].tolist()) for u in range(len(off) - 1)}
+    k = plan.k
+    first_merge = {}
+    for j in range(2, k):
+        for i in _bits(plan.connect[j]) + _bits(plan.disconnect[j]):
+            first_merge.setdefault(i, j)
+            first_merge[i] = min(first_merge[i], j)
+
+    def node(j, v):
+        lo, hi = -1, math.inf
+        for i in _bits(plan.upper[j]):
+            hi = min(hi, v[i])
+        for i in _bits(plan.lower[j]):
+            lo = max(lo, v[i])
+        merged = sorted(set(_bits(plan.connect[j])) | set(_bits(plan.disconnect[j])))
+        b = sum(16 for i in merged if first_merge[i] == j)
+        b += sum(4 * sum(1 for x in rows[v[i]] if lo < x < hi) for i in merged)
+        cand = None
+        for i in _bits(plan.connect[j]):
+            cand = set(rows[v[i]]) if cand is None else cand & rows[v[i]]
+        for i in _bits(plan.disconnect[j]):
+            cand -= rows[v[i]]
+        cand = sorted(x for x in cand if lo < x < hi and x not in v[:j])
+        if j == k - 1:
+            return b
+        return b + sum(node(j + 1, v[:j] + [x]) for x in cand)
+
+    total = 0
+    n = len(off) - 1
+    for u in range(n):
+        for w in sorted(rows[u]):
+            if plan.oriented and not w < u:
+                continue
+            total += 8
+            if k > 2:
+                total += node(2, [u, w])
+    return total
+
+
+@pytest.mark.parametrize("induced", [False, True])
+@pytest.mark.parametrize("name", ["triangle", "wedge", "4-clique", "4-cycle", "3-star", "diamond", "5-cycle",
+                                  "house", "5-clique"])
+def test_exact_search_bytes_recomputed(O, synth, name, induced):
+    """The exact count's algorithmic bytes (every node of the search tree)
+    against the definition recomputed with Python sets."""
+    n = 120
+    g = O.OGraph.from_raw_csr(n, *synth.pairs_to_csr(n, synth.chung_lu_pairs(n, 8, 2.1, 7)))
+    k, e = synth.pattern(name)
+    p = O.compile_plan(k, e, induced)
+    assert O.plan_count_bytes(g, p, threads=3) == _python_tree_bytes(g, p)
+
+
+def test_exact_search_bytes_closed_form_complete_graph(O, synth):
+    """Triangle on K_n: the first edges are the pairs v0 > v1, each node reads
+    both rows below v1 (v1 entries each) after opening them: sum over v1 of
+    (n - 1 - v1) * (8 + 32 + 8 v1)."""
+    n = 25
+    g = O.OGraph.from_pairs(n, synth.complete_pairs(n))
+    k, e = synth.pattern("triangle")
+    p = O.compile_plan(k, e)
+    want = sum((n - 1 - v1) * (8 + 32 + 8 * v1) for v1 in range(n))
+    assert O.plan_count_bytes(g, p) == want
