@@ -305,7 +305,8 @@ def workload_c4(S, synth, args):
 def workload_c5(S, synth, args):
     """R-MAT 26 (edge factor 16, about a billion edges, int64 offsets): 6-clique,
     5-cycle and diamond (edge-induced) in loose mode, where pilots choose
-    between NS-prune and colour sparsification with 16 colours."""
+    between NS-prune and colour sparsification with 16 colours; then strict NS
+    with the learned proposal against uniform on the same seeds."""
     ctx = S.sgpm_create(0)
     g, gi = load_graph(S, synth, ctx, "rmat26", 1 << 26, lambda: synth.rmat_pairs(26, 16, 0.57, 0.19, 0.19, seed=1))
     out = {"metric": "C5 loose-mode estimates on R-MAT 26", "graph": gi, "eps": args.eps, "queries": {}}
@@ -320,6 +321,23 @@ def workload_c5(S, synth, args):
                              "pilot_s": r.seconds_pilot, "total_s": r.seconds_total,
                              "lanes": r.lanes_per_sample}
         log(f"c5 {q}: {out['queries'][q]}")
+    # learned proposal on the NS path: one model for the three patterns, then
+    # strict NS with the uniform and the learned proposal on the same seeds
+    pats = [S.sgpm_pattern_create(ctx, *synth.pattern(q)) for q in ("6-clique", "5-cycle", "diamond")]
+    t0 = time.perf_counter()
+    model = S.sgpm_model_train(ctx, g, pats)
+    out["learned"] = {"train_s": time.perf_counter() - t0, "tuples": S.sgpm_model_info(model)["tuples"], "runs": {}}
+    for q, p in zip(("6-clique", "5-cycle", "diamond"), pats):
+        row = {}
+        for name, prop in (("uniform", None), ("learned", model.value)):
+            r, _ = S.sgpm_estimate(ctx, g, p, S.sgpm_options_default(eps=args.eps, seed=9, proposal=prop, checksum=1,
+                                                                     max_samples=1 << 30))
+            row[name] = {"n": int(r.n_samples), "time_s": r.seconds_total, "estimate": r.estimate,
+                         "eps_hat": r.eps_hat, "converged": int(r.converged)}
+        row["time_ratio_learned_over_uniform"] = row["learned"]["time_s"] / row["uniform"]["time_s"]
+        out["learned"]["runs"][q] = row
+        log(f"c5 learned vs uniform {q}: {row}")
+    S.sgpm_model_free(model)
     return out
 
 
