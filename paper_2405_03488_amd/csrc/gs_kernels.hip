@@ -346,9 +346,9 @@ struct Lanes {
         if constexpr (G == 64) return b;
         else return (b >> base) & full;
     }
-    // x of the group's lane i
+    // x of the group's lane i (a whole wave: i is uniform, read by readlane)
     __device__ __forceinline__ int32_t at(int32_t x, int i) const {
-        if constexpr (G == 64) return grfl(__shfl(x, i));
+        if constexpr (G == 64) return __builtin_amdgcn_readlane(x, i);
         else return __shfl(x, base + i);
     }
 };
@@ -363,13 +363,15 @@ __device__ __forceinline__ bool grp_member(const int32_t* __restrict__ R, int32_
     for (;;) {
         const int32_t b = (c + ln.sub < rl) ? R[c + ln.sub] : GBIG;
         const int32_t bmax = ln.at(b, G - 1);
-        int pos = 0;  // entries of the window below x, at most G - 1
+        // entries of the window below x (at most G - 1), kept as the lane
+        // permute's byte address of the group's lane base + pos
+        int pb = ln.base * 4;
 #pragma unroll
         for (int st = G / 2; st >= 1; st >>= 1) {
-            const int32_t bv = __shfl(b, ln.base + pos + st - 1);
-            if (bv < x) pos += st;
+            const int32_t bv = __builtin_amdgcn_ds_bpermute(pb + (st - 1) * 4, b);
+            pb += bv < x ? st * 4 : 0;
         }
-        const int32_t bq = __shfl(b, ln.base + pos);
+        const int32_t bq = __builtin_amdgcn_ds_bpermute(pb, b);
         const bool res = pending && x <= bmax;
         if (res) found = bq == x;
         pending = pending && !res;
