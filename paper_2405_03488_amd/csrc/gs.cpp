@@ -41,7 +41,7 @@ sgpm_status gs_scratch(sgpm_ctx* c, size_t i, size_t bytes, void** out) {
     return SGPM_OK;
 }
 
-enum GsSlot : size_t { GS_COL, GS_RSTART, GS_RLOW, GS_TK, GS_TL, GS_TKO, GS_TLO, GS_SCAN, GS_EOFF, GS_PART, GS_CELL };
+enum GsSlot : size_t { GS_COL, GS_RSTART, GS_RLOW, GS_TK, GS_TL, GS_TKO, GS_TLO, GS_SCAN, GS_EOFF, GS_PART, GS_CELL, GS_OVF };
 
 #define GS_SCRATCH(ctx, slot, bytes, ptr)                                        \
     do {                                                                         \
@@ -134,36 +134,75 @@ int exact_group(const sgpm_graph* g, const Plan& p) {
     return plan_is_clique(p) && p.k == 4 ? 16 : 64;
 }
 
-// exact count of the plan's tuples on g (the leaves of the pruned search tree)
+// exact count of the plan's tuples on g (the leaves of the pruned search tree).
+// The 4-, 5- and 6-clique on oriented first edges take the bitmap count (one
+// wave per first edge; first edges whose candidate set exceeds 64 go to the
+// general search through a list), unless SGPM_EXACT_GROUP fixes the general
+// search's width; the rest take the general search.
 sgpm_status exact_count(sgpm_ctx* c, sgpm_graph* g, const Plan& p, unsigned __int128* out, double* seconds) {
     HIP_TRY(c, hipSetDevice(c->dev));
     const uint64_t nfirst = p.oriented ? (uint64_t)g->m : 2ull * (uint64_t)g->m;
     *out = 0;
     if (seconds) *seconds = 0.0;
     if (nfirst == 0) return SGPM_OK;
-    const int group = exact_group(g, p);
-    const int blocks = c->cus * exact_blocks_per_cu(group);
-    const uint64_t groups = (uint64_t)blocks * 4 * (uint64_t)(64 / group);
-    // about 32 tickets per group; at least 4 edges each for narrow groups, so
-    // the one ticket counter is not the limit on a graph of short rows
-    const int per_ticket =
-        (int)std::min<uint64_t>(4096, std::max<uint64_t>(group == 64 ? 1 : 4, nfirst / (groups * 32)));
-    unsigned long long *part = nullptr, *d = nullptr;  // d: ticket, spare, low sum, high sum
-    GS_SCRATCH(c, GS_PART, sizeof(unsigned long long) * 2 * (size_t)blocks, part);
-    GS_SCRATCH(c, GS_CELL, sizeof(unsigned long long) * 4, d);
-    HIP_TRY(c, launch_fill_u64(d, 4, 0ull, c->st));
+    const bool bitmap = plan_is_clique(p) && p.oriented && p.k >= 4 && p.k <= 6 && nfirst <= (1ull << 28) &&
+                        !std::getenv("SGPM_EXACT_GROUP");
+    int group = exact_group(g, p);
+    unsigned long long *part = nullptr, *d = nullptr;  // d: ticket, overflow count, 2 sums, ticket, spare, 2 sums
+    uint32_t* ovf = nullptr;
+    const int maxblocks = c->cus * std::max(exact_blocks_per_cu(64), bitmap ? clique_bitmap_blocks_per_cu(p.k) : 1);
+    GS_SCRATCH(c, GS_PART, sizeof(unsigned long long) * 2 * (size_t)std::max(maxblocks, c->cus * exact_blocks_per_cu(group)), part);
+    GS_SCRATCH(c, GS_CELL, sizeof(unsigned long long) * 8, d);
+    HIP_TRY(c, launch_fill_u64(d, 8, 0ull, c->st));
     ScopedEvents<2> ev;
     HIP_TRY(c, ev.create());
     HIP_TRY(c, hipEventRecord(ev.e[0], c->st));
-    HIP_TRY(c, launch_exact_count(g->view(), p, nfirst, group, blocks, per_ticket, d, part, d + 2, c->st));
+    // Ticket plans.  Every ticket is one atomic on one counter, and those
+    // serialise at about 12 ns per wave-wide atomic on this device, so a
+    // kernel of T tickets takes at least 12 T ns.  The general search: about
+    // 32 tickets per wave (over the wave's groups), starting at one edge (four
+    // for narrow groups) and growing linearly, since the search below a first
+    // edge costs the most on the high-degree rows at the front of the edge
+    // order.  The bitmap count (even, short work per edge): about 8 tickets
+    // per wave of at least 32 edges each.
+    auto general_plan = [&](int grp, int blocks, uint64_t nf) {
+        const uint64_t T = (uint64_t)blocks * 4 * 32, base = grp == 64 ? 1 : 4;
+        if (nf <= base * T || nf >= (1ull << 32)) return TicketPlan{std::max<uint64_t>(base, nf / T), 0};
+        return TicketPlan{base, std::max<uint64_t>(1, T * T / (2 * (nf - base * T)))};
+    };
+    auto bitmap_plan = [&](int blocks, uint64_t nf) {
+        return TicketPlan{std::max<uint64_t>(32, nf / ((uint64_t)blocks * 4 * 8)), 0};
+    };
+    uint64_t rest = 0;  // first edges left to the general search (bitmap count)
+    if (bitmap) {
+        GS_SCRATCH(c, GS_OVF, sizeof(uint32_t) * (size_t)nfirst, ovf);
+        const int blocks = c->cus * clique_bitmap_blocks_per_cu(p.k);
+        HIP_TRY(c, launch_clique_bitmap(g->view(), p.k, nfirst, blocks, bitmap_plan(blocks, nfirst), d, part,
+                                        d + 2, ovf, d + 1, c->st));
+        unsigned long long nov = 0;
+        HIP_TRY(c, hipMemcpyAsync(&nov, d + 1, sizeof(nov), hipMemcpyDeviceToHost, c->st));
+        HIP_TRY(c, hipStreamSynchronize(c->st));
+        rest = nov;
+        group = 64;
+    }
+    if (!bitmap || rest > 0) {
+        const uint64_t nf = bitmap ? rest : nfirst;
+        const int blocks = c->cus * exact_blocks_per_cu(group);
+        HIP_TRY(c, launch_exact_count(g->view(), p, nf, group, blocks, general_plan(group, blocks, nf), d + 4, part,
+                                      d + 6, bitmap ? ovf : nullptr, c->st));
+    }
     HIP_TRY(c, hipEventRecord(ev.e[1], c->st));
+    unsigned long long four[4];
+    HIP_TRY(c, hipMemcpyAsync(four, d + 2, sizeof(four), hipMemcpyDeviceToHost, c->st));
     unsigned long long two[2];
-    HIP_TRY(c, hipMemcpyAsync(two, d + 2, sizeof(two), hipMemcpyDeviceToHost, c->st));
+    HIP_TRY(c, hipMemcpyAsync(two, d + 6, sizeof(two), hipMemcpyDeviceToHost, c->st));
     HIP_TRY(c, hipStreamSynchronize(c->st));
     float ms = 0;
     (void)hipEventElapsedTime(&ms, ev.e[0], ev.e[1]);
     if (seconds) *seconds = ms * 1e-3;
-    *out = (unsigned __int128)two[0] + ((unsigned __int128)two[1] << 32);
+    // low and high 32-bit halves of the two searches' sums
+    *out = (unsigned __int128)four[0] + ((unsigned __int128)four[1] << 32) + (unsigned __int128)two[0] +
+           ((unsigned __int128)two[1] << 32);
     return SGPM_OK;
 }
 

@@ -480,9 +480,10 @@ __device__ __forceinline__ void init_level(const DGraph& g, const PackedPlan& p,
 }
 
 template <int G>
-__global__ __launch_bounds__(256) void exact_count_kernel(DGraph g, PackedPlan p, uint64_t nfirst, int per_ticket,
+__global__ __launch_bounds__(256) void exact_count_kernel(DGraph g, PackedPlan p, uint64_t nfirst, TicketPlan tp,
                                                           unsigned long long* __restrict__ ticket,
-                                                          unsigned long long* __restrict__ partials) {
+                                                          unsigned long long* __restrict__ partials,
+                                                          const uint32_t* __restrict__ elist) {
     constexpr int NG = 64 / G;  // groups per wave
     const int lane = (int)(threadIdx.x & 63), w = (int)(threadIdx.x >> 6);
     const int grp = lane / G;
@@ -495,10 +496,13 @@ __global__ __launch_bounds__(256) void exact_count_kernel(DGraph g, PackedPlan p
         unsigned long long t = 0;
         if (ln.sub == 0) t = atomicAdd(ticket, 1ull);
         t = __shfl(t, ln.base);
-        const uint64_t e0 = (uint64_t)t * (uint64_t)per_ticket;
+        if (t >= nfirst) break;
+        const uint64_t e0 = ticket_start(tp, t);
         if (e0 >= nfirst) break;
-        const uint64_t e1 = e0 + (uint64_t)per_ticket < nfirst ? e0 + (uint64_t)per_ticket : nfirst;
-        for (uint64_t e = e0; e < e1; ++e) {
+        const uint64_t e1 = min(ticket_start(tp, t + 1), nfirst);
+        for (uint64_t ei = e0; ei < e1; ++ei) {
+            // first edge ei, or the ei-th of a list of first edges
+            const uint64_t e = elist ? (uint64_t)elist[ei] : ei;
             int32_t v0, v1;
             if (p.oriented) {
                 const int2 pr = g.epair[e];
@@ -585,6 +589,135 @@ __global__ __launch_bounds__(256) void exact_count_kernel(DGraph g, PackedPlan p
     }
 }
 
+// Clique counts (k = 4, 5, 6) by bitmaps over the first edge's candidate set.
+// The k-clique plan orders v0 > v1 > ... > v_{k-1}, every later vertex adjacent
+// to all earlier ones, so with S = N(v0) ∩ N(v1) ∩ [0, v1) in ascending order
+// the tuples through the first edge (v0, v1) are the (k-2)-cliques of the graph
+// induced on S, each once in descending order.  One wave per first edge: S
+// goes to LDS (at most 64 members; a first edge with a larger S is appended to
+// `overflow` for the general search); a window merge of S against the row of
+// its member a gives the bitmap M[a] of the members below a adjacent to it;
+// the count is sum_a |M[a]| (k = 4), sum_a sum_{b in M[a]} |M[a] & M[b]|
+// (k = 5), or one more level (k = 6).  Levels beyond the third cost popcounts
+// instead of row merges.
+constexpr int CLQ_SET = 64;
+
+template <int KC>
+__global__ __launch_bounds__(256) void clique_bitmap_kernel(DGraph g, uint64_t nfirst, TicketPlan tp,
+                                                            unsigned long long* __restrict__ ticket,
+                                                            unsigned long long* __restrict__ partials,
+                                                            uint32_t* __restrict__ overflow,
+                                                            unsigned long long* __restrict__ noverflow) {
+    const int lane = (int)(threadIdx.x & 63), w = (int)(threadIdx.x >> 6);
+    const Lanes<64> ln{lane, 0};
+    __shared__ int32_t s_set[4][CLQ_SET];
+    __shared__ unsigned long long s_mask[4][CLQ_SET];
+    int32_t* S = s_set[w];
+    unsigned long long* M = s_mask[w];
+    unsigned long long total = 0;  // per lane
+    for (;;) {
+        unsigned long long t = 0;
+        if (lane == 0) t = atomicAdd(ticket, 1ull);
+        t = ((unsigned long long)(uint32_t)grfl((int32_t)(__shfl(t, 0) >> 32)) << 32) |
+            (uint32_t)grfl((int32_t)__shfl(t, 0));
+        if (t >= nfirst) break;
+        const uint64_t e0 = ticket_start(tp, t);
+        if (e0 >= nfirst) break;
+        const uint64_t e1 = min(ticket_start(tp, t + 1), nfirst);
+        for (uint64_t e = e0; e < e1; ++e) {
+            const int2 pr = g.epair[e];
+            const int32_t v0 = grfl(pr.x), v1 = grfl(pr.y);
+            const int64_t b0 = g.off[v0], b1 = g.off[v1];
+            const int32_t l0 = (int32_t)(g.off[v0 + 1] - b0), l1 = (int32_t)(g.off[v1 + 1] - b1);
+            // S: the shorter row's entries below v1 that the other row holds
+            const bool d0 = l0 <= l1;
+            const int32_t* dp = g.nbr + (d0 ? b0 : b1);
+            const int32_t* op = g.nbr + (d0 ? b1 : b0);
+            const int32_t dl = d0 ? l0 : l1, ol = d0 ? l1 : l0;
+            int32_t s = 0, cur = 0;
+            bool over = false;
+            for (int32_t base = 0; base < dl; base += 64) {
+                const int32_t x = base + lane < dl ? dp[base + lane] : GBIG;
+                const bool act = x < v1;
+                const unsigned long long inm = __ballot(act);  // a prefix of the wave
+                if (inm == 0) break;
+                const int32_t xmax = ln.at(x, (int)__popcll(inm) - 1);
+                const bool f = grp_member<64>(op, ol, cur, x, act, xmax, ln);
+                const unsigned long long okm = __ballot(act && f);
+                const int c = (int)__popcll(okm);
+                if (s + c > CLQ_SET) {
+                    over = true;
+                    break;
+                }
+                if (act && f) S[s + (int)__popcll(okm & ((1ull << lane) - 1ull))] = x;
+                s += c;
+                if (inm != ~0ull) break;
+            }
+            if (over) {
+                if (lane == 0) overflow[atomicAdd(noverflow, 1ull)] = (uint32_t)e;
+                continue;
+            }
+            if (s < KC - 2) continue;
+            __builtin_amdgcn_wave_barrier();
+            const int32_t xs = lane < s ? S[lane] : GBIG;  // ascending over the lanes
+            // lane ia: M[ia] = members below S[ia] adjacent to it
+            unsigned long long mine = 0;
+            for (int ia = 1; ia < s; ++ia) {
+                const int32_t a = ln.at(xs, ia);
+                const int64_t ba = g.off[a];
+                const int32_t la = (int32_t)(g.off[a + 1] - ba);
+                int32_t ca = 0;
+                const bool act = lane < ia;
+                const bool f = grp_member<64>(g.nbr + ba, la, ca, xs, act, ln.at(xs, ia - 1), ln);
+                const unsigned long long m = __ballot(act && f);
+                if (lane == ia) mine = m;
+            }
+            M[lane] = mine;
+            __builtin_amdgcn_wave_barrier();
+            unsigned long long cnt = 0;
+            if constexpr (KC == 4) {
+                cnt = (unsigned long long)__popcll(mine);
+            } else {
+                unsigned long long m = mine;
+                while (m) {
+                    const int b = __ffsll((unsigned long long)m) - 1;
+                    m &= m - 1ull;
+                    const unsigned long long m2 = mine & M[b];
+                    if constexpr (KC == 5) {
+                        cnt += (unsigned long long)__popcll(m2);
+                    } else {
+                        unsigned long long r = m2;
+                        while (r) {
+                            const int c3 = __ffsll((unsigned long long)r) - 1;
+                            r &= r - 1ull;
+                            cnt += (unsigned long long)__popcll(m2 & M[c3]);
+                        }
+                    }
+                }
+            }
+            total += cnt;
+            __builtin_amdgcn_wave_barrier();  // S and M are rewritten by the next first edge
+        }
+    }
+    // block sum as the general count's: two 32-bit halves per block
+    unsigned long long lo = total & 0xFFFFFFFFull, hi = total >> 32;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        lo += __shfl_xor(lo, o);
+        hi += __shfl_xor(hi, o);
+    }
+    __shared__ unsigned long long red[4][2];
+    if (lane == 0) {
+        red[w][0] = lo;
+        red[w][1] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = red[0][0] + red[1][0] + red[2][0] + red[3][0];
+        partials[2 * blockIdx.x + 1] = red[0][1] + red[1][1] + red[2][1] + red[3][1];
+    }
+}
+
 __global__ void sum_pairs_kernel(const unsigned long long* __restrict__ partials, int nblocks,
                                  unsigned long long* __restrict__ out2) {
     __shared__ unsigned long long a[256], b[256];
@@ -668,9 +801,9 @@ hipError_t exclusive_scan(const int64_t* in, int64_t n, int64_t* out, int64_t* s
     return hipGetLastError();
 }
 
-hipError_t launch_exact_count(const DGraph& g, const Plan& p, uint64_t nfirst, int group, int blocks, int per_ticket,
+hipError_t launch_exact_count(const DGraph& g, const Plan& p, uint64_t nfirst, int group, int blocks, TicketPlan tp,
                               unsigned long long* ticket, unsigned long long* partials, unsigned long long* out2,
-                              hipStream_t st) {
+                              const uint32_t* elist, hipStream_t st) {
     PackedPlan pp{};
     for (int j = 0; j < 8; ++j) {
         pp.connect |= (uint64_t)p.connect[j] << (8 * j);
@@ -681,20 +814,49 @@ hipError_t launch_exact_count(const DGraph& g, const Plan& p, uint64_t nfirst, i
     pp.k = p.k;
     pp.oriented = p.oriented;
     if (group == 8)
-        hipLaunchKernelGGL(exact_count_kernel<8>, dim3((unsigned)blocks), dim3(256), 0, st, g, pp, nfirst, per_ticket,
-                           ticket, partials);
+        hipLaunchKernelGGL(exact_count_kernel<8>, dim3((unsigned)blocks), dim3(256), 0, st, g, pp, nfirst, tp,
+                           ticket, partials, elist);
     else if (group == 16)
-        hipLaunchKernelGGL(exact_count_kernel<16>, dim3((unsigned)blocks), dim3(256), 0, st, g, pp, nfirst, per_ticket,
-                           ticket, partials);
+        hipLaunchKernelGGL(exact_count_kernel<16>, dim3((unsigned)blocks), dim3(256), 0, st, g, pp, nfirst, tp,
+                           ticket, partials, elist);
     else if (group == 64)
-        hipLaunchKernelGGL(exact_count_kernel<64>, dim3((unsigned)blocks), dim3(256), 0, st, g, pp, nfirst, per_ticket,
-                           ticket, partials);
+        hipLaunchKernelGGL(exact_count_kernel<64>, dim3((unsigned)blocks), dim3(256), 0, st, g, pp, nfirst, tp,
+                           ticket, partials, elist);
     else
         return hipErrorInvalidValue;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(sum_pairs_kernel, dim3(1), dim3(256), 0, st, partials, blocks, out2);
     return hipGetLastError();
+}
+
+hipError_t launch_clique_bitmap(const DGraph& g, int k, uint64_t nfirst, int blocks, TicketPlan tp,
+                                unsigned long long* ticket, unsigned long long* partials, unsigned long long* out2,
+                                uint32_t* overflow, unsigned long long* noverflow, hipStream_t st) {
+    if (k == 4)
+        hipLaunchKernelGGL(clique_bitmap_kernel<4>, dim3((unsigned)blocks), dim3(256), 0, st, g, nfirst, tp,
+                           ticket, partials, overflow, noverflow);
+    else if (k == 5)
+        hipLaunchKernelGGL(clique_bitmap_kernel<5>, dim3((unsigned)blocks), dim3(256), 0, st, g, nfirst, tp,
+                           ticket, partials, overflow, noverflow);
+    else if (k == 6)
+        hipLaunchKernelGGL(clique_bitmap_kernel<6>, dim3((unsigned)blocks), dim3(256), 0, st, g, nfirst, tp,
+                           ticket, partials, overflow, noverflow);
+    else
+        return hipErrorInvalidValue;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(sum_pairs_kernel, dim3(1), dim3(256), 0, st, partials, blocks, out2);
+    return hipGetLastError();
+}
+
+int clique_bitmap_blocks_per_cu(int k) {
+    int nb = 0;
+    hipError_t e = k == 4   ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, clique_bitmap_kernel<4>, 256, 0)
+                   : k == 5 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, clique_bitmap_kernel<5>, 256, 0)
+                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, clique_bitmap_kernel<6>, 256, 0);
+    if (e != hipSuccess || nb < 1) nb = 2;
+    return nb;
 }
 
 int exact_blocks_per_cu(int group) {

@@ -28,9 +28,10 @@
 //    colouring's search reaches about C / c^(k-1) leaves, and two colourings at
 //    an optimistic rate taking at least the cone's lower end rule GS out without
 //    running it (a large graph's exact count can take minutes).  The rate is
-//    1e10 leaves per second when the sparsified graph is sparse (mean degree
-//    2m / (n c) below 16; the count kernel measures 1.4e9 to 3.7e9 there) and
-//    1e11 otherwise (long rows: 4.1e10 measured for the 4-clique on R-MAT 20).
+//    1e11 leaves per second when the sparsified graph is sparse (mean degree
+//    2m / (n c) below 16; the count kernels measure 2e9 to 3e10 there, the
+//    clique bitmaps up to 9e10) and 1e12 otherwise (long rows: 5e10 measured
+//    for the 4-clique on the whole R-MAT 20 graph).
 //
 // The engine then runs exactly as in its own mode with the same options (NS
 // continues the pilot's stream, GS reuses the two pilot colourings, which are
@@ -191,7 +192,7 @@ sgpm_status hybrid_estimate(sgpm_ctx* c, sgpm_graph* g, sgpm_pattern* pat, const
         double leaves = mu;
         for (int i = 0; i < p.k - 1; i++) leaves /= (double)col;
         const double sparse_deg = g->n > 0 ? 2.0 * (double)g->m / ((double)g->n * (double)col) : 0.0;
-        const double gs_floor = 2.0 * leaves / (sparse_deg < 16.0 ? 1e10 : 1e11);
+        const double gs_floor = 2.0 * leaves / (sparse_deg < 16.0 ? 1e11 : 1e12);
         // GS pilot: the GS engine's first colourings, timed end to end
         double rep_seconds = 0.0;
         for (int r = 0; r < 2 && gs_floor < ns_lo; r++) {

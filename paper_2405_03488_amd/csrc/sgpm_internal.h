@@ -185,11 +185,31 @@ hipError_t gs_arc_write(const DGraph& g, const uint8_t* col, uint32_t c, uint64_
 int64_t scan_scratch_words(int64_t n);
 hipError_t exclusive_scan(const int64_t* in, int64_t n, int64_t* out, int64_t* scratch, hipStream_t st);
 hipError_t max_degree(const int64_t* off, int64_t n, unsigned long long* out, hipStream_t st);
-// group: lanes per first edge (8, 16 or 64)
-hipError_t launch_exact_count(const DGraph& g, const Plan& p, uint64_t nfirst, int group, int blocks, int per_ticket,
+// Work split of the count kernels: a wave (or lane group) takes ticket t from
+// one counter and counts first edges [ticket_start(t), ticket_start(t + 1)).
+// Ticket t holds base + floor(t / growth) edges roughly (growth 0: base
+// each), so with growth the first tickets, over the highest-degree rows that
+// lead the edge order, are short while the count of tickets (one atomic each
+// on the shared counter) stays bounded.  growth > 0 needs nfirst < 2^32.
+struct TicketPlan {
+    uint64_t base, growth;
+};
+__host__ __device__ inline uint64_t ticket_start(const TicketPlan& tp, uint64_t t) {
+    return t * tp.base + (tp.growth ? (t * (t - 1) / 2) / tp.growth : 0);
+}
+// group: lanes per first edge (8, 16 or 64); elist: nullptr for first edges
+// [0, nfirst), else nfirst entries of first-edge ids
+hipError_t launch_exact_count(const DGraph& g, const Plan& p, uint64_t nfirst, int group, int blocks, TicketPlan tp,
                               unsigned long long* ticket, unsigned long long* partials, unsigned long long* out2,
-                              hipStream_t st);
+                              const uint32_t* elist, hipStream_t st);
 int exact_blocks_per_cu(int group);
+// the k-clique (k = 4, 5, 6; oriented first edges) by bitmaps over each first
+// edge's candidate set of at most 64; first edges with larger sets are appended
+// to overflow (count in *noverflow, both zero before the launch)
+hipError_t launch_clique_bitmap(const DGraph& g, int k, uint64_t nfirst, int blocks, TicketPlan tp,
+                                unsigned long long* ticket, unsigned long long* partials, unsigned long long* out2,
+                                uint32_t* overflow, unsigned long long* noverflow, hipStream_t st);
+int clique_bitmap_blocks_per_cu(int k);
 // probes (probe_kernels.hip)
 hipError_t probe_copy(const void* in, void* out, uint64_t bytes, int blocks, hipStream_t st);
 hipError_t probe_gather(const int32_t* a, uint64_t words, int seg_bytes, int rounds, int blocks, uint64_t seed,

@@ -97,6 +97,30 @@ def test_exact_count_closed_forms(S, O, synth, ctx):
     S.sgpm_graph_free(g)
 
 
+@pytest.mark.parametrize("kk", [4, 5, 6])
+def test_exact_clique_dense_neighbourhoods(S, O, synth, ctx, kk):
+    """Cliques where the common lower neighbourhood of an edge passes 64 (the
+    edges the bitmap search hands to the generic search) next to edges where
+    it does not: K_90 against C(90, k), and a dense core (100 vertices, edge
+    probability 0.7) inside a power-law graph against the oracle."""
+    import math
+    print(f"dense clique k={kk}", flush=True)
+    k, e = synth.pattern(f"{kk}-clique")
+    p = S.sgpm_pattern_create(ctx, k, e)
+    g, _ = load(S, O, synth, ctx, 90, synth.complete_pairs(90))
+    assert S.sgpm_exact_count(ctx, g, p) == math.comb(90, kk)
+    S.sgpm_graph_free(g)
+    rng = np.random.default_rng(31)
+    core = synth.complete_pairs(100)
+    core = core[rng.random(len(core)) < 0.7]
+    n = 3000
+    pairs = np.concatenate([core, synth.chung_lu_pairs(n, 8, 2.1, 7)])
+    g, og = load(S, O, synth, ctx, n, pairs)
+    assert S.sgpm_exact_count(ctx, g, p) == O.plan_count(og, O.compile_plan(k, e))
+    S.sgpm_graph_free(g)
+    S.sgpm_pattern_free(p)
+
+
 @pytest.mark.parametrize("name,c", [("triangle", 4), ("4-cycle", 3), ("diamond", 2)])
 def test_gs_estimate_matches_oracle(S, O, synth, ctx, cl, name, c):
     g, og = cl
