@@ -447,7 +447,7 @@ int sgpm_host_ns_cone(int slices, const double* slice_n, const double* slice_sec
  * colouring's estimate (unbiased variance over the squared mean) and GS needs
  * the smallest R in [3, gs_reps_max] with t_{R-1} gs_cv / sqrt(R) <= eps (t:
  * two-sided Student t quantile at `confidence`), +inf if there is none; with
- * one, only the lower bound 2 * gs_rep_seconds is known.  *gs_pred = R *
+ * one, only the lower bound 3 * gs_rep_seconds (the rule's minimum) is known.  *gs_pred = R *
  * gs_rep_seconds.  Returns SGPM_SCHEME_GS when GS lies entirely below the
  * cone, else SGPM_SCHEME_NS (above or overlapping: NS keeps the guarantee);
  * SGPM_EINVAL for bad inputs. */

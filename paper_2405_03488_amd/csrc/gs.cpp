@@ -233,9 +233,11 @@ sgpm_status gs_rep(sgpm_ctx* c, sgpm_graph* g, const Plan& p, uint32_t colours, 
 // the graph, the pattern and the seed, so runs repeat exactly.
 constexpr uint32_t kColourProbeRep = 0x3FFFFFFFu;
 
+double gs_sparsify_model_s(int64_t m) { return 2.0 * (double)m / 1e11 + 3e-4; }
+
 uint32_t colours_from_probe(int64_t m, int k, double leaves16) {
     static const uint32_t cands[] = {4, 5, 6, 8, 10, 12, 16};
-    const double t_sp = 2.0 * (double)m / 1e11 + 3e-4;
+    const double t_sp = gs_sparsify_model_s(m);
     const double at16 = t_sp + leaves16 / 3e9;
     for (uint32_t cc : cands)
         if (t_sp + leaves16 * std::pow(16.0 / (double)cc, (double)(k - 1)) / 3e9 <= 1.25 * at16) return cc;

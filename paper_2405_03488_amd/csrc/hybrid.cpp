@@ -22,12 +22,15 @@
 //    deviation of one colouring's estimate over their mean, cv) gives the
 //    colourings needed under the GS stop rule: the smallest R >= 3 with
 //    t_{R-1} cv / sqrt(R) <= eps (t the two-sided Student t quantile), and the
-//    prediction is R times the mean colouring time.  When one colouring already takes half the
-//    cone's lower end GS cannot lie below it and the second is skipped.  Before
+//    prediction is R times the mean colouring time.  When one colouring already takes a third
+//    of the cone's lower end GS cannot lie below it and the second is skipped.  Before
 //    any colouring, the NS pilot's estimate C bounds GS from below: one
-//    colouring's search reaches about C / c^(k-1) leaves, and two colourings at
-//    an optimistic rate taking at least the cone's lower end rule GS out without
-//    running it (a large graph's exact count can take minutes).  The rate is
+//    colouring's search reaches about C / c^(k-1) leaves, and three colourings
+//    (each its sparsification at the modelled device rate the colour choice
+//    uses, plus its leaves at an optimistic rate) taking at least the cone's
+//    lower end rule GS out without running it (a large graph's exact count can
+//    take minutes; a small one's colouring is mostly its sparsification).  The
+//    rate is
 //    1e11 leaves per second when the sparsified graph is sparse (mean degree
 //    2m / (n c) below 16; the count kernels measure 2e9 to 3e10 there, the
 //    clique bitmaps up to 9e10) and 1e12 otherwise (long rows: 5e10 measured
@@ -108,7 +111,7 @@ int hybrid_choice(double ns_lo, double eps, double confidence, int gs_reps_run, 
         const int need = gs_reps_needed(gs_cv, eps, confidence, gs_reps_max > 0 ? gs_reps_max : 64);
         if (need > 0) gs = need * gs_rep_seconds;
     } else if (gs_reps_run == 1) {
-        gs = 2.0 * gs_rep_seconds;  // a lower bound: GS needs two colourings at least
+        gs = (double)kGsMinReps * gs_rep_seconds;  // a lower bound: the stop rule starts at three colourings
     }
     if (gs_pred) *gs_pred = gs;
     // GS entirely below the cone; a one-colouring bound never selects GS
@@ -188,11 +191,12 @@ sgpm_status hybrid_estimate(sgpm_ctx* c, sgpm_graph* g, sgpm_pattern* pat, const
         ex.prefix_launches = slices;
         for (int i = 0; i < slices; i++) ex.prefix_kernel_s += sec[i];
         ns_cone(slices, sn, sec, eh, o, &ns_lo, &ns_hi, nullptr, nullptr);
-        // lower bound of two colourings from the leaves they must reach
+        // lower bound of the three colourings the GS stop rule needs at least
         double leaves = mu;
         for (int i = 0; i < p.k - 1; i++) leaves /= (double)col;
         const double sparse_deg = g->n > 0 ? 2.0 * (double)g->m / ((double)g->n * (double)col) : 0.0;
-        const double gs_floor = 2.0 * leaves / (sparse_deg < 16.0 ? 1e11 : 1e12);
+        const double gs_floor = (double)kGsMinReps *
+                                (gs_sparsify_model_s(g->m) + leaves / (sparse_deg < 16.0 ? 1e11 : 1e12));
         // GS pilot: the GS engine's first colourings, timed end to end
         double rep_seconds = 0.0;
         for (int r = 0; r < 2 && gs_floor < ns_lo; r++) {
@@ -203,7 +207,7 @@ sgpm_status hybrid_estimate(sgpm_ctx* c, sgpm_graph* g, sgpm_pattern* pat, const
             pre.dev_seconds += dev;
             pre.n = r + 1;
             rep_seconds += std::chrono::duration<double>(clk::now() - a).count();
-            if (r == 0 && 2.0 * rep_seconds >= ns_lo) break;  // GS cannot lie below the cone
+            if (r == 0 && (double)kGsMinReps * rep_seconds >= ns_lo) break;  // GS cannot lie below the cone
         }
         if (pre.n == 0) {
             gs_pred = gs_floor;  // a lower bound; GS was not run

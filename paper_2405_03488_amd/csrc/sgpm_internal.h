@@ -303,6 +303,9 @@ struct GsPrefix {              // colourings 0..n-1 already counted (hybrid pilo
 };
 sgpm_status gs_rep(sgpm_ctx* c, sgpm_graph* g, const Plan& p, uint32_t colours, uint64_t seed, uint32_t rep,
                    unsigned __int128* y, double* dev_seconds, bool bes = false);
+// modelled seconds of one colour sparsification of a graph of m edges (two
+// passes over the 2m arcs at the measured 1e11 arcs/s, plus 0.3 ms of launches)
+double gs_sparsify_model_s(int64_t m);
 uint32_t colours_from_probe(int64_t m, int k, double leaves16);
 sgpm_status gs_resolve_colours(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_options& o, uint32_t* col);
 sgpm_status gs_estimate(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const sgpm_options& o, sgpm_result* res,

@@ -83,7 +83,7 @@ def test_gs_prediction_and_choice(S):
 
 def test_one_colouring_never_selects_gs(S):
     sc, gs = S.sgpm_host_hybrid_choice(1.0, 0.01, 1, 1e-9, float("nan"))
-    assert gs == pytest.approx(2e-9) and sc == S.SCHEME_NS
+    assert gs == pytest.approx(3e-9) and sc == S.SCHEME_NS  # the stop rule's three colourings
 
 
 def test_missing_hits_and_caps(S):
