@@ -138,25 +138,40 @@ int exact_group(const sgpm_graph* g, const Plan& p) {
 // The 4-, 5- and 6-clique on oriented first edges take the bitmap count (one
 // wave per first edge; first edges whose candidate set exceeds 64 go to the
 // general search through a list), unless SGPM_EXACT_GROUP fixes the general
-// search's width; the rest take the general search.
-sgpm_status exact_count(sgpm_ctx* c, sgpm_graph* g, const Plan& p, unsigned __int128* out, double* seconds) {
-    HIP_TRY(c, hipSetDevice(c->dev));
+// search's width or the list could outgrow its buffer; the rest take the
+// general search.  The buffers come from the caller: block partials (two words
+// per block, for part_blocks blocks), eight counter and sum words (cleared
+// here), and the list of ovf_cap first-edge ids.
+namespace {
+
+struct CountBuffers {
+    unsigned long long* part;
+    size_t part_blocks;
+    unsigned long long* cells;
+    uint32_t* ovf;
+    uint64_t ovf_cap;
+};
+
+bool bitmap_count_applies(const Plan& p, uint64_t nfirst) {
+    return plan_is_clique(p) && p.oriented && p.k >= 4 && p.k <= 6 && nfirst <= (1ull << 28) &&
+           !std::getenv("SGPM_EXACT_GROUP");
+}
+
+sgpm_status exact_count_with(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const CountBuffers& b, unsigned __int128* out,
+                             double* seconds) {
     const uint64_t nfirst = p.oriented ? (uint64_t)g->m : 2ull * (uint64_t)g->m;
     *out = 0;
     if (seconds) *seconds = 0.0;
     if (nfirst == 0) return SGPM_OK;
-    const bool bitmap = plan_is_clique(p) && p.oriented && p.k >= 4 && p.k <= 6 && nfirst <= (1ull << 28) &&
-                        !std::getenv("SGPM_EXACT_GROUP");
+    const bool bitmap = bitmap_count_applies(p, nfirst) && nfirst <= b.ovf_cap;
     int group = exact_group(g, p);
-    unsigned long long *part = nullptr, *d = nullptr;  // d: ticket, overflow count, 2 sums, ticket, spare, 2 sums
-    uint32_t* ovf = nullptr;
-    const int maxblocks = c->cus * std::max(exact_blocks_per_cu(64), bitmap ? clique_bitmap_blocks_per_cu(p.k) : 1);
-    GS_SCRATCH(c, GS_PART, sizeof(unsigned long long) * 2 * (size_t)std::max(maxblocks, c->cus * exact_blocks_per_cu(group)), part);
-    GS_SCRATCH(c, GS_CELL, sizeof(unsigned long long) * 8, d);
+    unsigned long long* d = b.cells;  // ticket, overflow count, 2 sums, ticket, spare, 2 sums
     HIP_TRY(c, launch_fill_u64(d, 8, 0ull, c->st));
     ScopedEvents<2> ev;
-    HIP_TRY(c, ev.create());
-    HIP_TRY(c, hipEventRecord(ev.e[0], c->st));
+    if (seconds) {
+        HIP_TRY(c, ev.create());
+        HIP_TRY(c, hipEventRecord(ev.e[0], c->st));
+    }
     // Ticket plans.  Every ticket is one atomic on one counter, and those
     // serialise at about 12 ns per wave-wide atomic on this device, so a
     // kernel of T tickets takes at least 12 T ns.  The general search: about
@@ -175,10 +190,10 @@ sgpm_status exact_count(sgpm_ctx* c, sgpm_graph* g, const Plan& p, unsigned __in
     };
     uint64_t rest = 0;  // first edges left to the general search (bitmap count)
     if (bitmap) {
-        GS_SCRATCH(c, GS_OVF, sizeof(uint32_t) * (size_t)nfirst, ovf);
         const int blocks = c->cus * clique_bitmap_blocks_per_cu(p.k);
-        HIP_TRY(c, launch_clique_bitmap(g->view(), p.k, nfirst, blocks, bitmap_plan(blocks, nfirst), d, part,
-                                        d + 2, ovf, d + 1, c->st));
+        if ((size_t)blocks > b.part_blocks) return fail(c, SGPM_EINVAL, "the count's launch exceeds its partials buffer");
+        HIP_TRY(c, launch_clique_bitmap(g->view(), p.k, nfirst, blocks, bitmap_plan(blocks, nfirst), d, b.part,
+                                        d + 2, b.ovf, d + 1, c->st));
         unsigned long long nov = 0;
         HIP_TRY(c, hipMemcpyAsync(&nov, d + 1, sizeof(nov), hipMemcpyDeviceToHost, c->st));
         HIP_TRY(c, hipStreamSynchronize(c->st));
@@ -188,22 +203,47 @@ sgpm_status exact_count(sgpm_ctx* c, sgpm_graph* g, const Plan& p, unsigned __in
     if (!bitmap || rest > 0) {
         const uint64_t nf = bitmap ? rest : nfirst;
         const int blocks = c->cus * exact_blocks_per_cu(group);
-        HIP_TRY(c, launch_exact_count(g->view(), p, nf, group, blocks, general_plan(group, blocks, nf), d + 4, part,
-                                      d + 6, bitmap ? ovf : nullptr, c->st));
+        if ((size_t)blocks > b.part_blocks) return fail(c, SGPM_EINVAL, "the count's launch exceeds its partials buffer");
+        HIP_TRY(c, launch_exact_count(g->view(), p, nf, group, blocks, general_plan(group, blocks, nf), d + 4, b.part,
+                                      d + 6, bitmap ? b.ovf : nullptr, c->st));
     }
-    HIP_TRY(c, hipEventRecord(ev.e[1], c->st));
+    if (seconds) HIP_TRY(c, hipEventRecord(ev.e[1], c->st));
     unsigned long long four[4];
     HIP_TRY(c, hipMemcpyAsync(four, d + 2, sizeof(four), hipMemcpyDeviceToHost, c->st));
     unsigned long long two[2];
     HIP_TRY(c, hipMemcpyAsync(two, d + 6, sizeof(two), hipMemcpyDeviceToHost, c->st));
     HIP_TRY(c, hipStreamSynchronize(c->st));
-    float ms = 0;
-    (void)hipEventElapsedTime(&ms, ev.e[0], ev.e[1]);
-    if (seconds) *seconds = ms * 1e-3;
+    if (seconds) {
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, ev.e[0], ev.e[1]);
+        *seconds = ms * 1e-3;
+    }
     // low and high 32-bit halves of the two searches' sums
     *out = (unsigned __int128)four[0] + ((unsigned __int128)four[1] << 32) + (unsigned __int128)two[0] +
            ((unsigned __int128)two[1] << 32);
     return SGPM_OK;
+}
+
+}  // namespace
+
+sgpm_status exact_count(sgpm_ctx* c, sgpm_graph* g, const Plan& p, unsigned __int128* out, double* seconds) {
+    HIP_TRY(c, hipSetDevice(c->dev));
+    const uint64_t nfirst = p.oriented ? (uint64_t)g->m : 2ull * (uint64_t)g->m;
+    *out = 0;
+    if (seconds) *seconds = 0.0;
+    if (nfirst == 0) return SGPM_OK;
+    const bool bitmap = bitmap_count_applies(p, nfirst);
+    const int maxblocks = c->cus * std::max({exact_blocks_per_cu(64), exact_blocks_per_cu(exact_group(g, p)),
+                                             bitmap ? clique_bitmap_blocks_per_cu(p.k) : 1});
+    CountBuffers b{};
+    b.part_blocks = (size_t)maxblocks;
+    GS_SCRATCH(c, GS_PART, sizeof(unsigned long long) * 2 * b.part_blocks, b.part);
+    GS_SCRATCH(c, GS_CELL, sizeof(unsigned long long) * 8, b.cells);
+    if (bitmap) {
+        GS_SCRATCH(c, GS_OVF, sizeof(uint32_t) * (size_t)nfirst, b.ovf);
+        b.ovf_cap = nfirst;
+    }
+    return exact_count_with(c, g, p, b, out, seconds);
 }
 
 sgpm_status gs_rep(sgpm_ctx* c, sgpm_graph* g, const Plan& p, uint32_t colours, uint64_t seed, uint32_t rep,
@@ -381,6 +421,30 @@ sgpm_status sgpm_exact_count(sgpm_ctx_t c, sgpm_graph_t g, sgpm_pattern_t p, uin
     if (!c || !g || !p || !count_lo) return fail(c, SGPM_EINVAL, "null argument");
     unsigned __int128 v = 0;
     sgpm_status st = exact_count(c, g, p->plan, &v, nullptr);
+    if (st != SGPM_OK) return st;
+    *count_lo = (uint64_t)v;
+    if (count_hi) *count_hi = (uint64_t)(v >> 64);
+    return SGPM_OK;
+}
+
+// sgpm_exact_count with its scratch in the device's file-scope array (no
+// allocation): the same kernels and ticket plans, so the same count.  A graph
+// whose first edges outnumber the array's list takes the general search for
+// cliques too, which counts the same tuples.
+sgpm_status sgpm_exact_count_noalloc(sgpm_ctx_t c, sgpm_graph_t g, sgpm_pattern_t p, uint64_t* count_lo,
+                                     uint64_t* count_hi) {
+    if (!c || !g || !p || !count_lo) return fail(c, SGPM_EINVAL, "null argument");
+    HIP_TRY(c, hipSetDevice(c->dev));
+    unsigned long long* base = nullptr;
+    HIP_TRY(c, count_scratch_address(c->dev, &base));
+    CountBuffers b{};
+    b.part = base;
+    b.part_blocks = kCountScratchBlocks;
+    b.cells = base + 2 * kCountScratchBlocks;
+    b.ovf = (uint32_t*)(base + 2 * kCountScratchBlocks + 8);
+    b.ovf_cap = kCountScratchOvf;
+    unsigned __int128 v = 0;
+    sgpm_status st = exact_count_with(c, g, p->plan, b, &v, nullptr);
     if (st != SGPM_OK) return st;
     *count_lo = (uint64_t)v;
     if (count_hi) *count_hi = (uint64_t)(v >> 64);

@@ -17,6 +17,8 @@
 // per first edge; the per-level loop state (chunk of 64 candidates, its valid
 // mask, merge cursors, walk vertices) lives in LDS so the depth is a runtime
 // value.
+#include <mutex>
+
 #include "sgpm_internal.h"
 
 namespace sgpm {
@@ -848,6 +850,28 @@ hipError_t launch_clique_bitmap(const DGraph& g, int k, uint64_t nfirst, int blo
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(sum_pairs_kernel, dim3(1), dim3(256), 0, st, partials, blocks, out2);
     return hipGetLastError();
+}
+
+// The allocation-free count's scratch.  In host code `scratch` names a host
+// stand-in, not device memory: kernels and copies only ever get the address
+// hipGetSymbolAddress returns for it on the current device, kept per device.
+static __device__ __align__(256) unsigned long long scratch[kCountScratchWords];
+
+hipError_t count_scratch_address(int dev, unsigned long long** out) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static unsigned long long* addr[kMaxDevices] = {};
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        addr[dev] = (unsigned long long*)ptr;
+    }
+    *out = addr[dev];
+    return hipSuccess;
 }
 
 int clique_bitmap_blocks_per_cu(int k) {

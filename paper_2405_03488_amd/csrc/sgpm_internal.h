@@ -210,6 +210,17 @@ hipError_t launch_clique_bitmap(const DGraph& g, int k, uint64_t nfirst, int blo
                                 unsigned long long* ticket, unsigned long long* partials, unsigned long long* out2,
                                 uint32_t* overflow, unsigned long long* noverflow, hipStream_t st);
 int clique_bitmap_blocks_per_cu(int k);
+// Scratch of the allocation-free exact count: one file-scope device array per
+// GPU of kCountScratchWords 64-bit words, laid out as kCountScratchBlocks
+// two-word block partials, then 8 counter and sum words, then a list of
+// kCountScratchOvf 32-bit first-edge ids (8 MiB) for the bitmap count's first
+// edges with more than 64 candidates.
+constexpr size_t kCountScratchBlocks = 4096;
+constexpr size_t kCountScratchOvf = size_t(1) << 21;
+constexpr size_t kCountScratchWords = 2 * kCountScratchBlocks + 8 + kCountScratchOvf / 2;
+// that array's device address on `dev`, which must be the current device:
+// looked up once per device (hipGetSymbolAddress), then reused
+hipError_t count_scratch_address(int dev, unsigned long long** out);
 // probes (probe_kernels.hip)
 hipError_t probe_copy(const void* in, void* out, uint64_t bytes, int blocks, hipStream_t st);
 hipError_t probe_gather(const int32_t* a, uint64_t words, int seg_bytes, int rounds, int blocks, uint64_t seed,

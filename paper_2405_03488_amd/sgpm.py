@@ -131,6 +131,7 @@ def lib():
             "sgpm_estimate_counted": ([P, P, P, C.POINTER(Options), C.POINTER(Result)], st),
             "sgpm_estimate_batch": ([P, C.c_int, P, P, P, P], st),
             "sgpm_exact_count": ([P, P, P, P, P], st),
+            "sgpm_exact_count_noalloc": ([P, P, P, P, P], st),
             "sgpm_gs_sparsify": ([P, P, C.c_uint32, C.c_uint64, C.c_uint32, PP], st),
             "sgpm_bes_sparsify": ([P, P, C.c_uint32, C.c_uint64, C.c_uint32, PP], st),
             "sgpm_model_train": ([P, P, P, C.c_int, P, PP], st),
@@ -169,7 +170,7 @@ def lib():
 EXPORTED = ["sgpm_create", "sgpm_destroy", "sgpm_last_error", "sgpm_device_count", "sgpm_graph_from_csr",
             "sgpm_graph_stats", "sgpm_graph_export", "sgpm_graph_free", "sgpm_pattern_create", "sgpm_pattern_plan",
             "sgpm_pattern_free", "sgpm_options_default", "sgpm_estimate", "sgpm_estimate_counted",
-            "sgpm_estimate_batch", "sgpm_exact_count", "sgpm_gs_sparsify", "sgpm_bes_sparsify",
+            "sgpm_estimate_batch", "sgpm_exact_count", "sgpm_exact_count_noalloc", "sgpm_gs_sparsify", "sgpm_bes_sparsify",
             "sgpm_model_train", "sgpm_model_free",
             "sgpm_model_from_tables", "sgpm_model_table", "sgpm_model_info", "sgpm_mlp_forward", "sgpm_mlp_grad",
             "sgpm_mlp_adam_steps",
@@ -306,6 +307,13 @@ def sgpm_estimate_batch(ctx, graphs, patterns, opts_list):
 def sgpm_exact_count(ctx, g, p) -> int:
     lo, hi = C.c_uint64(), C.c_uint64()
     _check(ctx, lib().sgpm_exact_count(ctx, g, p, C.byref(lo), C.byref(hi)))
+    return (hi.value << 64) | lo.value
+
+
+def sgpm_exact_count_noalloc(ctx, g, p) -> int:
+    """sgpm_exact_count with its scratch in the library's fixed device array."""
+    lo, hi = C.c_uint64(), C.c_uint64()
+    _check(ctx, lib().sgpm_exact_count_noalloc(ctx, g, p, C.byref(lo), C.byref(hi)))
     return (hi.value << 64) | lo.value
 
 
