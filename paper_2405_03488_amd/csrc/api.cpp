@@ -78,7 +78,7 @@ sgpm_graph::~sgpm_graph() {
         for (auto it = ctx->tuned.begin(); it != ctx->tuned.end();)
             it = std::get<0>(it->first) == (const void*)this ? ctx->tuned.erase(it) : std::next(it);
     }
-    if (!d_off && !d_nbr && !d_epair && !d_arow && !d_vb && !d_bthr) return;
+    if (borrowed || (!d_off && !d_nbr && !d_epair && !d_arow && !d_vb && !d_bthr)) return;
     if (ctx) (void)hipSetDevice(ctx->dev);
     for (void* q : {(void*)d_off, (void*)d_nbr, (void*)d_epair, (void*)d_arow, (void*)d_vb, (void*)d_bthr})
         if (q) (void)hipFree(q);

@@ -41,7 +41,10 @@ sgpm_status gs_scratch(sgpm_ctx* c, size_t i, size_t bytes, void** out) {
     return SGPM_OK;
 }
 
-enum GsSlot : size_t { GS_COL, GS_RSTART, GS_RLOW, GS_TK, GS_TL, GS_TKO, GS_TLO, GS_SCAN, GS_EOFF, GS_PART, GS_CELL, GS_OVF };
+enum GsSlot : size_t {
+    GS_COL, GS_RSTART, GS_RLOW, GS_TK, GS_TL, GS_TKO, GS_TLO, GS_SCAN, GS_EOFF, GS_PART, GS_CELL, GS_OVF,
+    GS_SP_OFF, GS_SP_NBR, GS_SP_AROW, GS_SP_EPAIR  // a sparsified graph that lives only for one colouring
+};
 
 #define GS_SCRATCH(ctx, slot, bytes, ptr)                                        \
     do {                                                                         \
@@ -53,7 +56,7 @@ enum GsSlot : size_t { GS_COL, GS_RSTART, GS_RLOW, GS_TK, GS_TL, GS_TKO, GS_TLO,
 
 // colours: c of colour sparsification, or (bes) the inverse keep probability
 sgpm_status sparsify(sgpm_ctx* c, sgpm_graph* g, uint32_t colours, uint64_t seed, uint32_t rep, sgpm_graph** out,
-                     bool bes) {
+                     bool bes, bool scratch_graph) {
     if (colours < 1 || colours > 256) return fail(c, SGPM_EINVAL, "colours must be in [1, 256]");
     HIP_TRY(c, hipSetDevice(c->dev));
     const int64_t n = g->n;
@@ -75,8 +78,12 @@ sgpm_status sparsify(sgpm_ctx* c, sgpm_graph* g, uint32_t colours, uint64_t seed
     auto h = std::make_unique<sgpm_graph>();
     h->ctx = c;
     h->n = n;
-    h->perm = g->perm;
-    HIP_TRY(c, hipMalloc(&h->d_off, sizeof(int64_t) * (size_t)(n + 1)));
+    if (!scratch_graph) h->perm = g->perm;  // ids map back only for graphs handed to the caller
+    h->borrowed = scratch_graph;
+    if (scratch_graph)
+        GS_SCRATCH(c, GS_SP_OFF, sizeof(int64_t) * (size_t)(n + 1), h->d_off);
+    else
+        HIP_TRY(c, hipMalloc(&h->d_off, sizeof(int64_t) * (size_t)(n + 1)));
     const DGraph dg = g->view();
     const uint8_t* colp = bes ? nullptr : col;
     if (!bes) HIP_TRY(c, gs_colours(n, colours, seed, rep, col, c->st));
@@ -95,11 +102,23 @@ sgpm_status sparsify(sgpm_ctx* c, sgpm_graph* g, uint32_t colours, uint64_t seed
     }
     if (arcs != 2 * edges) return fail(c, SGPM_EHIP, "internal: sparsified graph is not symmetric");
     h->m = edges;
-    HIP_TRY(c, hipMalloc(&h->d_nbr, sizeof(int32_t) * (size_t)std::max<int64_t>(arcs, 1)));
-    HIP_TRY(c, hipMalloc(&h->d_arow, sizeof(int32_t) * (size_t)std::max<int64_t>(arcs, 1)));
-    HIP_TRY(c, hipMalloc(&h->d_epair, sizeof(int2) * (size_t)std::max<int64_t>(edges, 1)));
+    const size_t arc_bytes = sizeof(int32_t) * (size_t)std::max<int64_t>(arcs, 1);
+    const size_t edge_bytes = sizeof(int2) * (size_t)std::max<int64_t>(edges, 1);
+    if (scratch_graph) {
+        GS_SCRATCH(c, GS_SP_NBR, arc_bytes, h->d_nbr);
+        GS_SCRATCH(c, GS_SP_AROW, arc_bytes, h->d_arow);
+        GS_SCRATCH(c, GS_SP_EPAIR, edge_bytes, h->d_epair);
+    } else {
+        HIP_TRY(c, hipMalloc(&h->d_nbr, arc_bytes));
+        HIP_TRY(c, hipMalloc(&h->d_arow, arc_bytes));
+        HIP_TRY(c, hipMalloc(&h->d_epair, edge_bytes));
+    }
     HIP_TRY(c, gs_arc_write(dg, colp, colours, seed, rep, tko, tlo, h->d_nbr, h->d_arow,
                             h->d_epair, rstart, rlow, h->d_off, d_eoff, c->st));
+    if (scratch_graph) {  // the count does not use the max degree
+        *out = h.release();
+        return SGPM_OK;
+    }
     unsigned long long* d_md = (unsigned long long*)rstart;  // reuse as the max-degree cell
     HIP_TRY(c, launch_fill_u64(d_md, 1, 0ull, c->st));
     HIP_TRY(c, max_degree(h->d_off, n, d_md, c->st));
@@ -249,7 +268,7 @@ sgpm_status exact_count(sgpm_ctx* c, sgpm_graph* g, const Plan& p, unsigned __in
 sgpm_status gs_rep(sgpm_ctx* c, sgpm_graph* g, const Plan& p, uint32_t colours, uint64_t seed, uint32_t rep,
                    unsigned __int128* y, double* dev_seconds, bool bes) {
     sgpm_graph* sp = nullptr;
-    sgpm_status st = sparsify(c, g, colours, seed, rep, &sp, bes);
+    sgpm_status st = sparsify(c, g, colours, seed, rep, &sp, bes, true);
     if (st != SGPM_OK) return st;
     st = exact_count(c, sp, p, y, dev_seconds);
     sgpm_graph_free(sp);
@@ -286,7 +305,7 @@ uint32_t colours_from_probe(int64_t m, int k, double leaves16) {
 
 sgpm_status gs_choose_colours(sgpm_ctx* c, sgpm_graph* g, const Plan& p, uint64_t seed, uint32_t* out) {
     sgpm_graph* sp = nullptr;
-    sgpm_status st = sparsify(c, g, 16, seed, kColourProbeRep, &sp);
+    sgpm_status st = sparsify(c, g, 16, seed, kColourProbeRep, &sp, false, true);
     if (st != SGPM_OK) return st;
     unsigned __int128 y = 0;
     st = exact_count(c, sp, p, &y, nullptr);

@@ -276,6 +276,7 @@ struct sgpm_graph {
     int32_t* d_nbr = nullptr;
     int2* d_epair = nullptr;
     int32_t* d_arow = nullptr;
+    bool borrowed = false;  // the device arrays are the context's GS scratch: not freed here
     sgpm::DGraph view() const { return sgpm::DGraph{d_off, d_nbr, d_epair, d_arow, n, m}; }
     sgpm_graph() = default;
     sgpm_graph(const sgpm_graph&) = delete;
@@ -339,8 +340,11 @@ sgpm_status hybrid_estimate(sgpm_ctx* c, sgpm_graph* g, sgpm_pattern* p, const s
 sgpm_status model_hybrid_estimate(sgpm_ctx* c, sgpm_graph* g, sgpm_pattern* p, const sgpm_options& o,
                                   sgpm_result* res);
 void cost_model(const Plan& p, const sgpm_cost_in& in, sgpm_cost_out* out);
+// scratch_graph: the sparsified graph's arrays are the context's GS scratch
+// (grown, never freed per call) and its max degree is not computed; the handle
+// must be freed before the next such call on the context
 sgpm_status sparsify(sgpm_ctx* c, sgpm_graph* g, uint32_t colours, uint64_t seed, uint32_t rep, sgpm_graph** out,
-                     bool bes = false);
+                     bool bes = false, bool scratch_graph = false);
 sgpm_status exact_count(sgpm_ctx* c, sgpm_graph* g, const Plan& p, unsigned __int128* out, double* seconds);
 int hybrid_choice(double ns_lo, double eps, double confidence, int gs_reps_run, double gs_rep_seconds, double gs_cv,
                   int gs_reps_max, double* gs_pred);
