@@ -157,10 +157,21 @@ int exact_group(const sgpm_graph* g, const Plan& p) {
 // The 4-, 5- and 6-clique on oriented first edges take the bitmap count (one
 // wave per first edge; first edges whose candidate set exceeds 64 go to the
 // general search through a list), unless SGPM_EXACT_GROUP fixes the general
-// search's width or the list could outgrow its buffer; the rest take the
-// general search.  The buffers come from the caller: block partials (two words
-// per block, for part_blocks blocks), eight counter and sum words (cleared
-// here), and the list of ovf_cap first-edge ids.
+// search's width or the list could outgrow its buffer.  The diamond takes the
+// sum over edges of C(t_e, 2) (t_e the edge's common neighbours: each diamond
+// once, through the edge its two triangles share), less 6 per 4-clique when
+// vertex-induced (a 4-clique holds six diamonds), under the same SGPM_EXACT_GROUP
+// exception.  The rest take the general search.  The buffers come from the
+// caller: block partials (two words per block, for part_blocks blocks),
+// kCountCells counter and sum words (cleared here), and the list of ovf_cap
+// first-edge ids.
+bool plan_is_diamond(const Plan& p) {
+    if (p.k != 4) return false;
+    int edges = 0;
+    for (int j = 1; j < 4; j++) edges += __builtin_popcount((unsigned)p.connect[j]);
+    return edges == 5;
+}
+
 namespace {
 
 struct CountBuffers {
@@ -170,6 +181,17 @@ struct CountBuffers {
     uint32_t* ovf;
     uint64_t ovf_cap;
 };
+
+const Plan& clique4_plan() {
+    static const Plan plan = [] {
+        const int32_t e[12] = {0, 1, 0, 2, 0, 3, 1, 2, 1, 3, 2, 3};
+        Plan q{};
+        std::string err;
+        (void)compile_pattern(4, 6, e, 0, q, err);
+        return q;
+    }();
+    return plan;
+}
 
 bool bitmap_count_applies(const Plan& p, uint64_t nfirst) {
     return plan_is_clique(p) && p.oriented && p.k >= 4 && p.k <= 6 && nfirst <= (1ull << 28) &&
@@ -183,8 +205,11 @@ sgpm_status exact_count_with(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const Co
     if (seconds) *seconds = 0.0;
     if (nfirst == 0) return SGPM_OK;
     const bool bitmap = bitmap_count_applies(p, nfirst) && nfirst <= b.ovf_cap;
+    const bool diamond = plan_is_diamond(p) && !std::getenv("SGPM_EXACT_GROUP");
     int group = exact_group(g, p);
-    unsigned long long* d = b.cells;  // ticket, overflow count, 2 sums, ticket, spare, 2 sums
+    // cells: ticket, overflow count, 2 sums, ticket, spare, 2 sums; words 8 on
+    // are the induced diamond's 4-clique count's
+    unsigned long long* d = b.cells;
     HIP_TRY(c, launch_fill_u64(d, 8, 0ull, c->st));
     ScopedEvents<2> ev;
     if (seconds) {
@@ -207,6 +232,33 @@ sgpm_status exact_count_with(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const Co
     auto bitmap_plan = [&](int blocks, uint64_t nf) {
         return TicketPlan{std::max<uint64_t>(32, nf / ((uint64_t)blocks * 4 * 8)), 0};
     };
+    if (diamond) {
+        const int grp = 2.0 * (double)g->m >= 16.0 * (double)g->n ? 64 : 8;
+        const int blocks = c->cus * edge_pairs_blocks_per_cu(grp);
+        if ((size_t)blocks > b.part_blocks) return fail(c, SGPM_EINVAL, "the count's launch exceeds its partials buffer");
+        HIP_TRY(c, launch_edge_pairs(g->view(), grp, blocks, general_plan(grp, blocks, (uint64_t)g->m), d, b.part,
+                                     d + 2, c->st));
+        unsigned __int128 k4 = 0;
+        if (p.induced) {
+            CountBuffers bk = b;
+            bk.cells = b.cells + 8;
+            sgpm_status st = exact_count_with(c, g, clique4_plan(), bk, &k4, nullptr);
+            if (st != SGPM_OK) return st;
+        }
+        if (seconds) HIP_TRY(c, hipEventRecord(ev.e[1], c->st));
+        unsigned long long two[2];
+        HIP_TRY(c, hipMemcpyAsync(two, d + 2, sizeof(two), hipMemcpyDeviceToHost, c->st));
+        HIP_TRY(c, hipStreamSynchronize(c->st));
+        if (seconds) {
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, ev.e[0], ev.e[1]);
+            *seconds = ms * 1e-3;
+        }
+        const unsigned __int128 pairs = (unsigned __int128)two[0] + ((unsigned __int128)two[1] << 32);
+        if (pairs < 6 * k4) return fail(c, SGPM_EHIP, "internal: induced diamond count below zero");
+        *out = pairs - 6 * k4;
+        return SGPM_OK;
+    }
     uint64_t rest = 0;  // first edges left to the general search (bitmap count)
     if (bitmap) {
         const int blocks = c->cus * clique_bitmap_blocks_per_cu(p.k);
@@ -252,15 +304,19 @@ sgpm_status exact_count(sgpm_ctx* c, sgpm_graph* g, const Plan& p, unsigned __in
     if (seconds) *seconds = 0.0;
     if (nfirst == 0) return SGPM_OK;
     const bool bitmap = bitmap_count_applies(p, nfirst);
+    const bool diamond = plan_is_diamond(p);
     const int maxblocks = c->cus * std::max({exact_blocks_per_cu(64), exact_blocks_per_cu(exact_group(g, p)),
-                                             bitmap ? clique_bitmap_blocks_per_cu(p.k) : 1});
+                                             bitmap || diamond ? clique_bitmap_blocks_per_cu(4) : 1,
+                                             diamond ? exact_blocks_per_cu(16) : 1,
+                                             diamond ? std::max(edge_pairs_blocks_per_cu(8), edge_pairs_blocks_per_cu(64)) : 1});
     CountBuffers b{};
     b.part_blocks = (size_t)maxblocks;
     GS_SCRATCH(c, GS_PART, sizeof(unsigned long long) * 2 * b.part_blocks, b.part);
-    GS_SCRATCH(c, GS_CELL, sizeof(unsigned long long) * 8, b.cells);
-    if (bitmap) {
-        GS_SCRATCH(c, GS_OVF, sizeof(uint32_t) * (size_t)nfirst, b.ovf);
-        b.ovf_cap = nfirst;
+    GS_SCRATCH(c, GS_CELL, sizeof(unsigned long long) * kCountCells, b.cells);
+    if (bitmap || (diamond && p.induced)) {  // the induced diamond counts 4-cliques over the m oriented edges
+        const uint64_t cap = std::max<uint64_t>(nfirst, (uint64_t)g->m);
+        GS_SCRATCH(c, GS_OVF, sizeof(uint32_t) * (size_t)std::max<uint64_t>(cap, 1), b.ovf);
+        b.ovf_cap = cap;
     }
     return exact_count_with(c, g, p, b, out, seconds);
 }
@@ -460,7 +516,7 @@ sgpm_status sgpm_exact_count_noalloc(sgpm_ctx_t c, sgpm_graph_t g, sgpm_pattern_
     b.part = base;
     b.part_blocks = kCountScratchBlocks;
     b.cells = base + 2 * kCountScratchBlocks;
-    b.ovf = (uint32_t*)(base + 2 * kCountScratchBlocks + 8);
+    b.ovf = (uint32_t*)(base + 2 * kCountScratchBlocks + kCountCells);
     b.ovf_cap = kCountScratchOvf;
     unsigned __int128 v = 0;
     sgpm_status st = exact_count_with(c, g, p->plan, b, &v, nullptr);

@@ -720,6 +720,68 @@ __global__ __launch_bounds__(256) void clique_bitmap_kernel(DGraph g, uint64_t n
     }
 }
 
+// Common-neighbour pairs of every edge, for the diamond (K4 minus one edge).
+// Its two degree-3 vertices span the one edge both of its triangles share, and
+// its other two vertices are common neighbours of that edge's endpoints, so the
+// diamonds are the pairs of common neighbours of the edges: sum over edges of
+// C(t_e, 2), t_e = |N(u) n N(w)|, each diamond once.  G lanes per edge (edges
+// in the oriented list, each once): the shorter row, G entries at a time, is
+// merged against the longer by the window search.
+template <int G>
+__global__ __launch_bounds__(256) void edge_pairs_kernel(DGraph g, TicketPlan tp,
+                                                         unsigned long long* __restrict__ ticket,
+                                                         unsigned long long* __restrict__ partials) {
+    const int lane = (int)(threadIdx.x & 63), w = (int)(threadIdx.x >> 6);
+    const Lanes<G> ln{lane % G, (lane / G) * G};
+    const uint64_t nfirst = (uint64_t)g.m;
+    unsigned long long total = 0;  // uniform over the group
+    for (;;) {
+        unsigned long long t = 0;
+        if (ln.sub == 0) t = atomicAdd(ticket, 1ull);
+        t = __shfl(t, ln.base);
+        if (t >= nfirst) break;
+        const uint64_t e0 = ticket_start(tp, t);
+        if (e0 >= nfirst) break;
+        const uint64_t e1 = min(ticket_start(tp, t + 1), nfirst);
+        for (uint64_t e = e0; e < e1; ++e) {
+            const int2 pr = g.epair[e];
+            const int64_t b0 = g.off[pr.x], b1 = g.off[pr.y];
+            const int32_t l0 = (int32_t)(g.off[pr.x + 1] - b0), l1 = (int32_t)(g.off[pr.y + 1] - b1);
+            const bool d0 = l0 <= l1;
+            const int32_t* dp = g.nbr + (d0 ? b0 : b1);
+            const int32_t* op = g.nbr + (d0 ? b1 : b0);
+            const int32_t dl = d0 ? l0 : l1, ol = d0 ? l1 : l0;
+            int32_t cur = 0;
+            unsigned long long tc = 0;
+            for (int32_t base = 0; base < dl; base += G) {
+                const bool act = base + ln.sub < dl;
+                const int32_t x = act ? dp[base + ln.sub] : GBIG;
+                const int32_t xmax = ln.at(x, min(G, dl - base) - 1);
+                const bool f = grp_member<G>(op, ol, cur, x, act, xmax, ln);
+                tc += (unsigned long long)__popcll(ln.ballot(act && f));
+            }
+            total += tc * (tc - 1ull) / 2ull;  // 0 for tc = 0 in unsigned arithmetic
+        }
+    }
+    // block sum in two 32-bit halves; one lane per group carries the group's total
+    unsigned long long lo = ln.sub == 0 ? (total & 0xFFFFFFFFull) : 0ull, hi = ln.sub == 0 ? (total >> 32) : 0ull;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        lo += __shfl_xor(lo, o);
+        hi += __shfl_xor(hi, o);
+    }
+    __shared__ unsigned long long red[4][2];
+    if (lane == 0) {
+        red[w][0] = lo;
+        red[w][1] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = red[0][0] + red[1][0] + red[2][0] + red[3][0];
+        partials[2 * blockIdx.x + 1] = red[0][1] + red[1][1] + red[2][1] + red[3][1];
+    }
+}
+
 __global__ void sum_pairs_kernel(const unsigned long long* __restrict__ partials, int nblocks,
                                  unsigned long long* __restrict__ out2) {
     __shared__ unsigned long long a[256], b[256];
@@ -850,6 +912,28 @@ hipError_t launch_clique_bitmap(const DGraph& g, int k, uint64_t nfirst, int blo
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(sum_pairs_kernel, dim3(1), dim3(256), 0, st, partials, blocks, out2);
     return hipGetLastError();
+}
+
+hipError_t launch_edge_pairs(const DGraph& g, int group, int blocks, TicketPlan tp, unsigned long long* ticket,
+                             unsigned long long* partials, unsigned long long* out2, hipStream_t st) {
+    if (group == 8)
+        hipLaunchKernelGGL(edge_pairs_kernel<8>, dim3((unsigned)blocks), dim3(256), 0, st, g, tp, ticket, partials);
+    else if (group == 64)
+        hipLaunchKernelGGL(edge_pairs_kernel<64>, dim3((unsigned)blocks), dim3(256), 0, st, g, tp, ticket, partials);
+    else
+        return hipErrorInvalidValue;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(sum_pairs_kernel, dim3(1), dim3(256), 0, st, partials, blocks, out2);
+    return hipGetLastError();
+}
+
+int edge_pairs_blocks_per_cu(int group) {
+    int nb = 0;
+    hipError_t e = group == 8 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, edge_pairs_kernel<8>, 256, 0)
+                              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, edge_pairs_kernel<64>, 256, 0);
+    if (e != hipSuccess || nb < 1) nb = 2;
+    return nb;
 }
 
 // The allocation-free count's scratch.  In host code `scratch` names a host

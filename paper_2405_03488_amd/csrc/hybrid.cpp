@@ -29,8 +29,8 @@
 //    (each its sparsification at the modelled device rate the colour choice
 //    uses, plus its leaves at an optimistic rate) taking at least the cone's
 //    lower end rule GS out without running it (a large graph's exact count can
-//    take minutes; a small one's colouring is mostly its sparsification).  The
-//    rate is
+//    take minutes; a small one's colouring is mostly its sparsification; the
+//    diamond, counted by an edge scan, adds no leaf term).  The rate is
 //    1e11 leaves per second when the sparsified graph is sparse (mean degree
 //    2m / (n c) below 16; the count kernels measure 2e9 to 3e10 there, the
 //    clique bitmaps up to 9e10) and 1e12 otherwise (long rows: 5e10 measured
@@ -195,8 +195,9 @@ sgpm_status hybrid_estimate(sgpm_ctx* c, sgpm_graph* g, sgpm_pattern* pat, const
         double leaves = mu;
         for (int i = 0; i < p.k - 1; i++) leaves /= (double)col;
         const double sparse_deg = g->n > 0 ? 2.0 * (double)g->m / ((double)g->n * (double)col) : 0.0;
-        const double gs_floor = (double)kGsMinReps *
-                                (gs_sparsify_model_s(g->m) + leaves / (sparse_deg < 16.0 ? 1e11 : 1e12));
+        // (the diamond's count scans edges instead of reaching its leaves)
+        const double search = plan_is_diamond(p) ? 0.0 : leaves / (sparse_deg < 16.0 ? 1e11 : 1e12);
+        const double gs_floor = (double)kGsMinReps * (gs_sparsify_model_s(g->m) + search);
         // GS pilot: the GS engine's first colourings, timed end to end
         double rep_seconds = 0.0;
         for (int r = 0; r < 2 && gs_floor < ns_lo; r++) {

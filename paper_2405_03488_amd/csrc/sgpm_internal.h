@@ -210,14 +210,21 @@ hipError_t launch_clique_bitmap(const DGraph& g, int k, uint64_t nfirst, int blo
                                 unsigned long long* ticket, unsigned long long* partials, unsigned long long* out2,
                                 uint32_t* overflow, unsigned long long* noverflow, hipStream_t st);
 int clique_bitmap_blocks_per_cu(int k);
+// diamond: sum over the oriented edges of C(t_e, 2), t_e the edge's common
+// neighbours, with group (8 or 64) lanes per edge; out2 receives the low and
+// high 32-bit halves' sums
+hipError_t launch_edge_pairs(const DGraph& g, int group, int blocks, TicketPlan tp, unsigned long long* ticket,
+                             unsigned long long* partials, unsigned long long* out2, hipStream_t st);
+int edge_pairs_blocks_per_cu(int group);
 // Scratch of the allocation-free exact count: one file-scope device array per
 // GPU of kCountScratchWords 64-bit words, laid out as kCountScratchBlocks
-// two-word block partials, then 8 counter and sum words, then a list of
+// two-word block partials, then kCountCells counter and sum words, then a list of
 // kCountScratchOvf 32-bit first-edge ids (8 MiB) for the bitmap count's first
 // edges with more than 64 candidates.
 constexpr size_t kCountScratchBlocks = 4096;
 constexpr size_t kCountScratchOvf = size_t(1) << 21;
-constexpr size_t kCountScratchWords = 2 * kCountScratchBlocks + 8 + kCountScratchOvf / 2;
+constexpr size_t kCountCells = 16;
+constexpr size_t kCountScratchWords = 2 * kCountScratchBlocks + kCountCells + kCountScratchOvf / 2;
 // that array's device address on `dev`, which must be the current device:
 // looked up once per device (hipGetSymbolAddress), then reused
 hipError_t count_scratch_address(int dev, unsigned long long** out);
@@ -346,6 +353,9 @@ void cost_model(const Plan& p, const sgpm_cost_in& in, sgpm_cost_out* out);
 sgpm_status sparsify(sgpm_ctx* c, sgpm_graph* g, uint32_t colours, uint64_t seed, uint32_t rep, sgpm_graph** out,
                      bool bes = false, bool scratch_graph = false);
 sgpm_status exact_count(sgpm_ctx* c, sgpm_graph* g, const Plan& p, unsigned __int128* out, double* seconds);
+// a 4-vertex pattern of five edges (K4 less one edge): its exact count is the
+// per-edge common-neighbour pairs, an edge scan, not a search over its leaves
+bool plan_is_diamond(const Plan& p);
 int hybrid_choice(double ns_lo, double eps, double confidence, int gs_reps_run, double gs_rep_seconds, double gs_cv,
                   int gs_reps_max, double* gs_pred);
 int gs_reps_needed(double cv, double eps, double confidence, int cap);

@@ -121,6 +121,29 @@ def test_exact_clique_dense_neighbourhoods(S, O, synth, ctx, kk):
     S.sgpm_pattern_free(p)
 
 
+@pytest.mark.parametrize("induced", [False, True])
+def test_exact_diamond_by_edge_pairs(S, O, synth, ctx, induced):
+    """The diamond counted as pairs of common neighbours per edge (less 6 per
+    4-clique when vertex-induced): K_90 against 6 C(90, 4) and 0, and a dense
+    core inside a power-law graph (4-cliques through the overflow list)
+    against the oracle's search."""
+    import math
+    print(f"diamond induced={induced}", flush=True)
+    k, e = synth.pattern("diamond")
+    p = S.sgpm_pattern_create(ctx, k, e, induced)
+    g, _ = load(S, O, synth, ctx, 90, synth.complete_pairs(90))
+    assert S.sgpm_exact_count(ctx, g, p) == (0 if induced else 6 * math.comb(90, 4))
+    S.sgpm_graph_free(g)
+    rng = np.random.default_rng(31)
+    core = synth.complete_pairs(100)
+    core = core[rng.random(len(core)) < 0.7]
+    pairs = np.concatenate([core, synth.chung_lu_pairs(3000, 8, 2.1, 7)])
+    g, og = load(S, O, synth, ctx, 3000, pairs)
+    assert S.sgpm_exact_count(ctx, g, p) == O.plan_count(og, O.compile_plan(k, e, induced))
+    S.sgpm_graph_free(g)
+    S.sgpm_pattern_free(p)
+
+
 @pytest.mark.parametrize("name,c", [("triangle", 4), ("4-cycle", 3), ("diamond", 2)])
 def test_gs_estimate_matches_oracle(S, O, synth, ctx, cl, name, c):
     g, og = cl
