@@ -115,7 +115,8 @@ sgpm_status sparsify(sgpm_ctx* c, sgpm_graph* g, uint32_t colours, uint64_t seed
     }
     HIP_TRY(c, gs_arc_write(dg, colp, colours, seed, rep, tko, tlo, h->d_nbr, h->d_arow,
                             h->d_epair, rstart, rlow, h->d_off, d_eoff, c->st));
-    if (scratch_graph) {  // the count does not use the max degree
+    if (scratch_graph) {  // not measured: an arc survives with about 1/c, so about the max degree / c
+        h->maxdeg = g->maxdeg / (int64_t)colours;
         *out = h.release();
         return SGPM_OK;
     }
@@ -233,7 +234,11 @@ sgpm_status exact_count_with(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const Co
         return TicketPlan{std::max<uint64_t>(32, nf / ((uint64_t)blocks * 4 * 8)), 0};
     };
     if (diamond) {
-        const int grp = 2.0 * (double)g->m >= 16.0 * (double)g->n ? 64 : 8;
+        // 8 lanes per edge unless some rows are long (hubs), where 64 pay:
+        // R-MAT 20 at c = 16 (max degree 3,983) 1.2 ms at 8 lanes, 3.3 at 64;
+        // R-MAT 20 at c = 4 (about 16K) 15.7 and 5.2; R-MAT 24 at c = 16
+        // (about 25K) 51 and 15.7
+        const int grp = (2.0 * (double)g->m >= 16.0 * (double)g->n || g->maxdeg >= 8192) ? 64 : 8;
         const int blocks = c->cus * edge_pairs_blocks_per_cu(grp);
         if ((size_t)blocks > b.part_blocks) return fail(c, SGPM_EINVAL, "the count's launch exceeds its partials buffer");
         HIP_TRY(c, launch_edge_pairs(g->view(), grp, blocks, general_plan(grp, blocks, (uint64_t)g->m), d, b.part,

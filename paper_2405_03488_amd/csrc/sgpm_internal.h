@@ -348,8 +348,9 @@ sgpm_status model_hybrid_estimate(sgpm_ctx* c, sgpm_graph* g, sgpm_pattern* p, c
                                   sgpm_result* res);
 void cost_model(const Plan& p, const sgpm_cost_in& in, sgpm_cost_out* out);
 // scratch_graph: the sparsified graph's arrays are the context's GS scratch
-// (grown, never freed per call) and its max degree is not computed; the handle
-// must be freed before the next such call on the context
+// (grown, never freed per call) and its max degree is not measured but taken
+// as the source's over c; the handle must be freed before
+// the next such call on the context
 sgpm_status sparsify(sgpm_ctx* c, sgpm_graph* g, uint32_t colours, uint64_t seed, uint32_t rep, sgpm_graph** out,
                      bool bes = false, bool scratch_graph = false);
 sgpm_status exact_count(sgpm_ctx* c, sgpm_graph* g, const Plan& p, unsigned __int128* out, double* seconds);

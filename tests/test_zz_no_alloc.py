@@ -66,13 +66,14 @@ def test_noalloc_equals_exact_count_shrinking_inputs(S, synth, ctx):
 
 def test_noalloc_past_the_overflow_list(S, synth, ctx):
     """R-MAT 18 (about 4M first edges, more than the array's 2^21-entry list):
-    the allocation-free call counts cliques by the general search, the other by
-    bitmaps; then a smaller graph on the same array."""
+    the allocation-free call counts cliques by the general search, the other
+    by bitmaps (the diamond by edge pairs on both); then a smaller graph on the
+    same array."""
     n = 1 << 18
     print("noalloc rmat18", flush=True)
     g = load(S, synth, ctx, n, synth.rmat_pairs(18, 16, seed=3))
     assert S.sgpm_graph_stats(g)[1] > (1 << 21)
-    for name in ["4-clique", "triangle"]:
+    for name in ["4-clique", "triangle", "diamond"]:
         print(f"noalloc rmat18 {name}", flush=True)
         a, b = both(S, synth, ctx, g, name)
         assert a == b, (name, a, b)
