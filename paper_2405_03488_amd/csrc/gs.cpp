@@ -150,7 +150,13 @@ int exact_group(const sgpm_graph* g, const Plan& p) {
         if (v == 8 || v == 16 || v == 64) return v;
     }
     if (2.0 * (double)g->m >= 16.0 * (double)g->n) return 64;
-    if (p.k == 3) return plan_is_clique(p) ? 8 : 16;  // one counted level per first edge
+    // hub rows (max degree 8,192 or more) take the next width up: triangle /
+    // wedge ms at 8, 16, 64 lanes, R-MAT 20 at c = 4 (max degree 16K): 1.50 /
+    // 8.29, 1.40 / 7.08, 2.90 / 6.51; R-MAT 24 at c = 4 (102K): 54.6 / 486,
+    // 44.9 / 377, 41.1 / 275; R-MAT 20 at c = 16 (4K): 0.49 / 1.56, 0.82 /
+    // 1.15, 2.88 / 2.89
+    const bool hubs = g->maxdeg >= 8192;
+    if (p.k == 3) return plan_is_clique(p) ? (hubs ? 16 : 8) : (hubs ? 64 : 16);  // one counted level per first edge
     return plan_is_clique(p) && p.k == 4 ? 16 : 64;
 }
 
