@@ -214,10 +214,11 @@ sgpm_status exact_count_with(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const Co
     const bool bitmap = bitmap_count_applies(p, nfirst) && nfirst <= b.ovf_cap;
     const bool diamond = plan_is_diamond(p) && !std::getenv("SGPM_EXACT_GROUP");
     int group = exact_group(g, p);
-    // cells: ticket, overflow count, 2 sums, ticket, spare, 2 sums; words 8 on
-    // are the induced diamond's 4-clique count's
+    // cells, three passes of ticket, count or spare, 2 sums: the 64-member
+    // bitmaps (0-3), the 128-member bitmaps (4-7), the general search (8-11);
+    // words 16 on are the induced diamond's 4-clique count's
     unsigned long long* d = b.cells;
-    HIP_TRY(c, launch_fill_u64(d, 8, 0ull, c->st));
+    HIP_TRY(c, launch_fill_u64(d, 12, 0ull, c->st));
     ScopedEvents<2> ev;
     if (seconds) {
         HIP_TRY(c, ev.create());
@@ -252,7 +253,7 @@ sgpm_status exact_count_with(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const Co
         unsigned __int128 k4 = 0;
         if (p.induced) {
             CountBuffers bk = b;
-            bk.cells = b.cells + 8;
+            bk.cells = b.cells + 16;
             sgpm_status st = exact_count_with(c, g, clique4_plan(), bk, &k4, nullptr);
             if (st != SGPM_OK) return st;
         }
@@ -270,7 +271,11 @@ sgpm_status exact_count_with(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const Co
         *out = pairs - 6 * k4;
         return SGPM_OK;
     }
+    // Bitmap passes: candidate sets of up to 64 members, then the first pass's
+    // list of larger sets at up to 128 members when the second list fits after
+    // the first; what is left goes to the general search.
     uint64_t rest = 0;  // first edges left to the general search (bitmap count)
+    const uint32_t* rest_list = nullptr;
     if (bitmap) {
         const int blocks = c->cus * clique_bitmap_blocks_per_cu(p.k);
         if ((size_t)blocks > b.part_blocks) return fail(c, SGPM_EINVAL, "the count's launch exceeds its partials buffer");
@@ -280,29 +285,41 @@ sgpm_status exact_count_with(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const Co
         HIP_TRY(c, hipMemcpyAsync(&nov, d + 1, sizeof(nov), hipMemcpyDeviceToHost, c->st));
         HIP_TRY(c, hipStreamSynchronize(c->st));
         rest = nov;
+        rest_list = b.ovf;
+        if (nov > 0 && 2 * nov <= b.ovf_cap) {
+            const int blocks2 = c->cus * clique_bitmap128_blocks_per_cu(p.k);
+            if ((size_t)blocks2 > b.part_blocks)
+                return fail(c, SGPM_EINVAL, "the count's launch exceeds its partials buffer");
+            HIP_TRY(c, launch_clique_bitmap128(g->view(), p.k, b.ovf, nov, blocks2, general_plan(64, blocks2, nov),
+                                               d + 4, b.part, d + 6, b.ovf + nov, d + 5, c->st));
+            unsigned long long nov2 = 0;
+            HIP_TRY(c, hipMemcpyAsync(&nov2, d + 5, sizeof(nov2), hipMemcpyDeviceToHost, c->st));
+            HIP_TRY(c, hipStreamSynchronize(c->st));
+            rest = nov2;
+            rest_list = b.ovf + nov;
+        }
         group = 64;
     }
     if (!bitmap || rest > 0) {
         const uint64_t nf = bitmap ? rest : nfirst;
         const int blocks = c->cus * exact_blocks_per_cu(group);
         if ((size_t)blocks > b.part_blocks) return fail(c, SGPM_EINVAL, "the count's launch exceeds its partials buffer");
-        HIP_TRY(c, launch_exact_count(g->view(), p, nf, group, blocks, general_plan(group, blocks, nf), d + 4, b.part,
-                                      d + 6, bitmap ? b.ovf : nullptr, c->st));
+        HIP_TRY(c, launch_exact_count(g->view(), p, nf, group, blocks, general_plan(group, blocks, nf), d + 8, b.part,
+                                      d + 10, bitmap ? rest_list : nullptr, c->st));
     }
     if (seconds) HIP_TRY(c, hipEventRecord(ev.e[1], c->st));
-    unsigned long long four[4];
-    HIP_TRY(c, hipMemcpyAsync(four, d + 2, sizeof(four), hipMemcpyDeviceToHost, c->st));
-    unsigned long long two[2];
-    HIP_TRY(c, hipMemcpyAsync(two, d + 6, sizeof(two), hipMemcpyDeviceToHost, c->st));
+    unsigned long long sums[12];
+    HIP_TRY(c, hipMemcpyAsync(sums, d, sizeof(sums), hipMemcpyDeviceToHost, c->st));
     HIP_TRY(c, hipStreamSynchronize(c->st));
     if (seconds) {
         float ms = 0;
         (void)hipEventElapsedTime(&ms, ev.e[0], ev.e[1]);
         *seconds = ms * 1e-3;
     }
-    // low and high 32-bit halves of the two searches' sums
-    *out = (unsigned __int128)four[0] + ((unsigned __int128)four[1] << 32) + (unsigned __int128)two[0] +
-           ((unsigned __int128)two[1] << 32);
+    // low and high 32-bit halves of the three passes' sums
+    unsigned __int128 total = 0;
+    for (int q = 2; q < 12; q += 4) total += (unsigned __int128)sums[q] + ((unsigned __int128)sums[q + 1] << 32);
+    *out = total;
     return SGPM_OK;
 }
 
@@ -318,6 +335,8 @@ sgpm_status exact_count(sgpm_ctx* c, sgpm_graph* g, const Plan& p, unsigned __in
     const bool diamond = plan_is_diamond(p);
     const int maxblocks = c->cus * std::max({exact_blocks_per_cu(64), exact_blocks_per_cu(exact_group(g, p)),
                                              bitmap || diamond ? clique_bitmap_blocks_per_cu(4) : 1,
+                                             bitmap ? std::max(clique_bitmap_blocks_per_cu(p.k), clique_bitmap128_blocks_per_cu(p.k)) : 1,
+                                             diamond ? clique_bitmap128_blocks_per_cu(4) : 1,
                                              diamond ? exact_blocks_per_cu(16) : 1,
                                              diamond ? std::max(edge_pairs_blocks_per_cu(8), edge_pairs_blocks_per_cu(64)) : 1});
     CountBuffers b{};
@@ -325,7 +344,8 @@ sgpm_status exact_count(sgpm_ctx* c, sgpm_graph* g, const Plan& p, unsigned __in
     GS_SCRATCH(c, GS_PART, sizeof(unsigned long long) * 2 * b.part_blocks, b.part);
     GS_SCRATCH(c, GS_CELL, sizeof(unsigned long long) * kCountCells, b.cells);
     if (bitmap || (diamond && p.induced)) {  // the induced diamond counts 4-cliques over the m oriented edges
-        const uint64_t cap = std::max<uint64_t>(nfirst, (uint64_t)g->m);
+        // room for the first bitmap pass's list and, after it, the second's
+        const uint64_t cap = 2 * std::max<uint64_t>(nfirst, (uint64_t)g->m);
         GS_SCRATCH(c, GS_OVF, sizeof(uint32_t) * (size_t)std::max<uint64_t>(cap, 1), b.ovf);
         b.ovf_cap = cap;
     }

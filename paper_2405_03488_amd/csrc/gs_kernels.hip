@@ -720,6 +720,160 @@ __global__ __launch_bounds__(256) void clique_bitmap_kernel(DGraph g, uint64_t n
     }
 }
 
+// The same count for first edges whose candidate set S holds 65 to 128
+// members (the 64-member kernel's overflow list): S in two halves of 64 lanes,
+// each member's adjacency inside S as a two-word mask, one merge of the row of
+// member a against both halves (ascending, so the merge cursor carries from
+// the first half into the second).  A set past 128 members is appended to
+// `overflow` for the general search.
+constexpr int CLQ_SET2 = 128;
+
+template <int KC>
+__global__ __launch_bounds__(256) void clique_bitmap128_kernel(DGraph g, const uint32_t* __restrict__ elist,
+                                                               uint64_t nlist, TicketPlan tp,
+                                                               unsigned long long* __restrict__ ticket,
+                                                               unsigned long long* __restrict__ partials,
+                                                               uint32_t* __restrict__ overflow,
+                                                               unsigned long long* __restrict__ noverflow) {
+    const int lane = (int)(threadIdx.x & 63), w = (int)(threadIdx.x >> 6);
+    const Lanes<64> ln{lane, 0};
+    __shared__ int32_t s_set[4][CLQ_SET2];
+    __shared__ unsigned long long s_m0[4][CLQ_SET2], s_m1[4][CLQ_SET2];
+    int32_t* S = s_set[w];
+    unsigned long long* M0 = s_m0[w];
+    unsigned long long* M1 = s_m1[w];
+    unsigned long long total = 0;  // per lane
+    for (;;) {
+        unsigned long long t = 0;
+        if (lane == 0) t = atomicAdd(ticket, 1ull);
+        t = ((unsigned long long)(uint32_t)grfl((int32_t)(__shfl(t, 0) >> 32)) << 32) |
+            (uint32_t)grfl((int32_t)__shfl(t, 0));
+        if (t >= nlist) break;
+        const uint64_t e0 = ticket_start(tp, t);
+        if (e0 >= nlist) break;
+        const uint64_t e1 = min(ticket_start(tp, t + 1), nlist);
+        for (uint64_t ei = e0; ei < e1; ++ei) {
+            const uint32_t e = (uint32_t)grfl((int32_t)elist[ei]);
+            const int2 pr = g.epair[e];
+            const int32_t v0 = grfl(pr.x), v1 = grfl(pr.y);
+            const int64_t b0 = g.off[v0], b1 = g.off[v1];
+            const int32_t l0 = (int32_t)(g.off[v0 + 1] - b0), l1 = (int32_t)(g.off[v1 + 1] - b1);
+            const bool d0 = l0 <= l1;
+            const int32_t* dp = g.nbr + (d0 ? b0 : b1);
+            const int32_t* op = g.nbr + (d0 ? b1 : b0);
+            const int32_t dl = d0 ? l0 : l1, ol = d0 ? l1 : l0;
+            int32_t s = 0, cur = 0;
+            bool over = false;
+            for (int32_t base = 0; base < dl; base += 64) {
+                const int32_t x = base + lane < dl ? dp[base + lane] : GBIG;
+                const bool act = x < v1;
+                const unsigned long long inm = __ballot(act);  // a prefix of the wave
+                if (inm == 0) break;
+                const int32_t xmax = ln.at(x, (int)__popcll(inm) - 1);
+                const bool f = grp_member<64>(op, ol, cur, x, act, xmax, ln);
+                const unsigned long long okm = __ballot(act && f);
+                const int c = (int)__popcll(okm);
+                if (s + c > CLQ_SET2) {
+                    over = true;
+                    break;
+                }
+                if (act && f) S[s + (int)__popcll(okm & ((1ull << lane) - 1ull))] = x;
+                s += c;
+                if (inm != ~0ull) break;
+            }
+            if (over) {
+                if (lane == 0) overflow[atomicAdd(noverflow, 1ull)] = e;
+                continue;
+            }
+            if (s < KC - 2) continue;
+            __builtin_amdgcn_wave_barrier();
+            // ascending over lane and then over 64 + lane
+            const int32_t xs0 = lane < s ? S[lane] : GBIG, xs1 = 64 + lane < s ? S[64 + lane] : GBIG;
+            // member lane: (lo0, lo1), member 64 + lane: (hi0, hi1)
+            unsigned long long lo0 = 0, lo1 = 0, hi0 = 0, hi1 = 0;
+            for (int ia = 1; ia < s; ++ia) {
+                const int32_t a = ia < 64 ? ln.at(xs0, ia) : ln.at(xs1, ia - 64);
+                const int64_t ba = g.off[a];
+                const int32_t la = (int32_t)(g.off[a + 1] - ba);
+                int32_t ca = 0;
+                const int n0 = ia < 64 ? ia : 64;  // members below a in the first half
+                const bool act0 = lane < n0;
+                const bool f0 = grp_member<64>(g.nbr + ba, la, ca, xs0, act0, ln.at(xs0, n0 - 1), ln);
+                const unsigned long long m0 = __ballot(act0 && f0);
+                unsigned long long m1 = 0;
+                if (ia > 64) {
+                    const bool act1 = lane < ia - 64;
+                    const bool f1 = grp_member<64>(g.nbr + ba, la, ca, xs1, act1, ln.at(xs1, ia - 65), ln);
+                    m1 = __ballot(act1 && f1);
+                }
+                if (ia < 64) {
+                    if (lane == ia) {
+                        lo0 = m0;
+                        lo1 = m1;
+                    }
+                } else if (lane == ia - 64) {
+                    hi0 = m0;
+                    hi1 = m1;
+                }
+            }
+            M0[lane] = lo0;
+            M1[lane] = lo1;
+            M0[64 + lane] = hi0;
+            M1[64 + lane] = hi1;
+            __builtin_amdgcn_wave_barrier();
+            unsigned long long cnt = 0;
+#pragma unroll
+            for (int half = 0; half < 2; ++half) {
+                const unsigned long long a0 = half ? hi0 : lo0, a1 = half ? hi1 : lo1;
+                if constexpr (KC == 4) {
+                    cnt += (unsigned long long)(__popcll(a0) + __popcll(a1));
+                } else {
+#pragma unroll
+                    for (int wd = 0; wd < 2; ++wd) {
+                        unsigned long long m = wd ? a1 : a0;
+                        while (m) {
+                            const int b = (__ffsll((unsigned long long)m) - 1) + 64 * wd;
+                            m &= m - 1ull;
+                            const unsigned long long c0 = a0 & M0[b], c1 = a1 & M1[b];
+                            if constexpr (KC == 5) {
+                                cnt += (unsigned long long)(__popcll(c0) + __popcll(c1));
+                            } else {
+#pragma unroll
+                                for (int wd2 = 0; wd2 < 2; ++wd2) {
+                                    unsigned long long r = wd2 ? c1 : c0;
+                                    while (r) {
+                                        const int c3 = (__ffsll((unsigned long long)r) - 1) + 64 * wd2;
+                                        r &= r - 1ull;
+                                        cnt += (unsigned long long)(__popcll(c0 & M0[c3]) + __popcll(c1 & M1[c3]));
+                                    }
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+            total += cnt;
+            __builtin_amdgcn_wave_barrier();  // S and the masks are rewritten by the next first edge
+        }
+    }
+    unsigned long long lo = total & 0xFFFFFFFFull, hi = total >> 32;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        lo += __shfl_xor(lo, o);
+        hi += __shfl_xor(hi, o);
+    }
+    __shared__ unsigned long long red[4][2];
+    if (lane == 0) {
+        red[w][0] = lo;
+        red[w][1] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = red[0][0] + red[1][0] + red[2][0] + red[3][0];
+        partials[2 * blockIdx.x + 1] = red[0][1] + red[1][1] + red[2][1] + red[3][1];
+    }
+}
+
 // Common-neighbour pairs of every edge, for the diamond (K4 minus one edge).
 // Its two degree-3 vertices span the one edge both of its triangles share, and
 // its other two vertices are common neighbours of that edge's endpoints, so the
@@ -912,6 +1066,36 @@ hipError_t launch_clique_bitmap(const DGraph& g, int k, uint64_t nfirst, int blo
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(sum_pairs_kernel, dim3(1), dim3(256), 0, st, partials, blocks, out2);
     return hipGetLastError();
+}
+
+hipError_t launch_clique_bitmap128(const DGraph& g, int k, const uint32_t* elist, uint64_t nlist, int blocks,
+                                   TicketPlan tp, unsigned long long* ticket, unsigned long long* partials,
+                                   unsigned long long* out2, uint32_t* overflow, unsigned long long* noverflow,
+                                   hipStream_t st) {
+    if (k == 4)
+        hipLaunchKernelGGL(clique_bitmap128_kernel<4>, dim3((unsigned)blocks), dim3(256), 0, st, g, elist, nlist, tp,
+                           ticket, partials, overflow, noverflow);
+    else if (k == 5)
+        hipLaunchKernelGGL(clique_bitmap128_kernel<5>, dim3((unsigned)blocks), dim3(256), 0, st, g, elist, nlist, tp,
+                           ticket, partials, overflow, noverflow);
+    else if (k == 6)
+        hipLaunchKernelGGL(clique_bitmap128_kernel<6>, dim3((unsigned)blocks), dim3(256), 0, st, g, elist, nlist, tp,
+                           ticket, partials, overflow, noverflow);
+    else
+        return hipErrorInvalidValue;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(sum_pairs_kernel, dim3(1), dim3(256), 0, st, partials, blocks, out2);
+    return hipGetLastError();
+}
+
+int clique_bitmap128_blocks_per_cu(int k) {
+    int nb = 0;
+    hipError_t e = k == 4   ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, clique_bitmap128_kernel<4>, 256, 0)
+                   : k == 5 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, clique_bitmap128_kernel<5>, 256, 0)
+                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, clique_bitmap128_kernel<6>, 256, 0);
+    if (e != hipSuccess || nb < 1) nb = 2;
+    return nb;
 }
 
 hipError_t launch_edge_pairs(const DGraph& g, int group, int blocks, TicketPlan tp, unsigned long long* ticket,

@@ -210,6 +210,13 @@ hipError_t launch_clique_bitmap(const DGraph& g, int k, uint64_t nfirst, int blo
                                 unsigned long long* ticket, unsigned long long* partials, unsigned long long* out2,
                                 uint32_t* overflow, unsigned long long* noverflow, hipStream_t st);
 int clique_bitmap_blocks_per_cu(int k);
+// the same for the nlist first edges elist[] whose candidate sets hold up to
+// 128 members (two-word masks); larger sets go to overflow
+hipError_t launch_clique_bitmap128(const DGraph& g, int k, const uint32_t* elist, uint64_t nlist, int blocks,
+                                   TicketPlan tp, unsigned long long* ticket, unsigned long long* partials,
+                                   unsigned long long* out2, uint32_t* overflow, unsigned long long* noverflow,
+                                   hipStream_t st);
+int clique_bitmap128_blocks_per_cu(int k);
 // diamond: sum over the oriented edges of C(t_e, 2), t_e the edge's common
 // neighbours, with group (8 or 64) lanes per edge; out2 receives the low and
 // high 32-bit halves' sums
@@ -223,7 +230,7 @@ int edge_pairs_blocks_per_cu(int group);
 // edges with more than 64 candidates.
 constexpr size_t kCountScratchBlocks = 4096;
 constexpr size_t kCountScratchOvf = size_t(1) << 21;
-constexpr size_t kCountCells = 16;
+constexpr size_t kCountCells = 32;
 constexpr size_t kCountScratchWords = 2 * kCountScratchBlocks + kCountCells + kCountScratchOvf / 2;
 // that array's device address on `dev`, which must be the current device:
 // looked up once per device (hipGetSymbolAddress), then reused

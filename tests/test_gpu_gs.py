@@ -100,16 +100,19 @@ def test_exact_count_closed_forms(S, O, synth, ctx):
 @pytest.mark.parametrize("kk", [4, 5, 6])
 def test_exact_clique_dense_neighbourhoods(S, O, synth, ctx, kk):
     """Cliques where the common lower neighbourhood of an edge passes 64 (the
-    edges the bitmap search hands to the generic search) next to edges where
-    it does not: K_90 against C(90, k), and a dense core (100 vertices, edge
-    probability 0.7) inside a power-law graph against the oracle."""
+    first bitmap pass's list, counted by 128-member bitmaps) or 128 (the second
+    pass's list, counted by the general search), next to edges where it does
+    not: K_90, and K_140 (K_132 for the 6-clique, whose general search grows
+    fast), against C(n, k); a dense core (100 vertices, edge probability 0.7)
+    inside a power-law graph against the oracle."""
     import math
     print(f"dense clique k={kk}", flush=True)
     k, e = synth.pattern(f"{kk}-clique")
     p = S.sgpm_pattern_create(ctx, k, e)
-    g, _ = load(S, O, synth, ctx, 90, synth.complete_pairs(90))
-    assert S.sgpm_exact_count(ctx, g, p) == math.comb(90, kk)
-    S.sgpm_graph_free(g)
+    for n in (90, 132 if kk == 6 else 140):
+        g, _ = load(S, O, synth, ctx, n, synth.complete_pairs(n))
+        assert S.sgpm_exact_count(ctx, g, p) == math.comb(n, kk)
+        S.sgpm_graph_free(g)
     rng = np.random.default_rng(31)
     core = synth.complete_pairs(100)
     core = core[rng.random(len(core)) < 0.7]
