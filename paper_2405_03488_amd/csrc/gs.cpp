@@ -172,6 +172,10 @@ int exact_group(const sgpm_graph* g, const Plan& p) {
 // caller: block partials (two words per block, for part_blocks blocks),
 // kCountCells counter and sum words (cleared here), and the list of ovf_cap
 // first-edge ids.
+bool count_not_by_leaves(const Plan& p) {
+    return plan_is_diamond(p) || (plan_is_clique(p) && p.oriented && p.k >= 4 && p.k <= 6);
+}
+
 bool plan_is_diamond(const Plan& p) {
     if (p.k != 4) return false;
     int edges = 0;

@@ -30,11 +30,14 @@
 //    uses, plus its leaves at an optimistic rate) taking at least the cone's
 //    lower end rule GS out without running it (a large graph's exact count can
 //    take minutes; a small one's colouring is mostly its sparsification; the
-//    diamond, counted by an edge scan, adds no leaf term).  The rate is
+//    diamond's edge pairs and the 4- to 6-clique's bitmaps count many leaves
+//    per instruction, up to 2e12 leaves/s, so they are charged their pass over
+//    the about m / c kept edges at 2e9 edges/s instead, above the 0.8e9 to
+//    1.4e9 measured).  The rate is
 //    1e11 leaves per second when the sparsified graph is sparse (mean degree
-//    2m / (n c) below 16; the count kernels measure 2e9 to 3e10 there, the
-//    clique bitmaps up to 9e10) and 1e12 otherwise (long rows: 5e10 measured
-//    for the 4-clique on the whole R-MAT 20 graph).
+//    2m / (n c) below 16; the general search measures 2e9 to 3e10 there) and
+//    1e12 otherwise (long rows: 4e10 measured for the general search's
+//    4-clique on the whole R-MAT 20 graph).
 //
 // The engine then runs exactly as in its own mode with the same options (NS
 // continues the pilot's stream, GS reuses the two pilot colourings, which are
@@ -195,8 +198,11 @@ sgpm_status hybrid_estimate(sgpm_ctx* c, sgpm_graph* g, sgpm_pattern* pat, const
         double leaves = mu;
         for (int i = 0; i < p.k - 1; i++) leaves /= (double)col;
         const double sparse_deg = g->n > 0 ? 2.0 * (double)g->m / ((double)g->n * (double)col) : 0.0;
-        // (the diamond's count scans edges instead of reaching its leaves)
-        const double search = plan_is_diamond(p) ? 0.0 : leaves / (sparse_deg < 16.0 ? 1e11 : 1e12);
+        // (the diamond's edge pairs and the cliques' bitmaps count many leaves
+        // per instruction: their search is charged its pass over the kept
+        // edges, about m / c, at 2e9 edges per second instead)
+        const double search = count_not_by_leaves(p) ? (double)g->m / (double)col / 2e9
+                                                     : leaves / (sparse_deg < 16.0 ? 1e11 : 1e12);
         const double gs_floor = (double)kGsMinReps * (gs_sparsify_model_s(g->m) + search);
         // GS pilot: the GS engine's first colourings, timed end to end
         double rep_seconds = 0.0;

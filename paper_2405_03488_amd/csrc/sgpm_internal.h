@@ -364,6 +364,9 @@ sgpm_status exact_count(sgpm_ctx* c, sgpm_graph* g, const Plan& p, unsigned __in
 // a 4-vertex pattern of five edges (K4 less one edge): its exact count is the
 // per-edge common-neighbour pairs, an edge scan, not a search over its leaves
 bool plan_is_diamond(const Plan& p);
+// the diamond and the 4- to 6-clique: counted by edge pairs or bitmaps, whose
+// time does not follow the number of leaves
+bool count_not_by_leaves(const Plan& p);
 int hybrid_choice(double ns_lo, double eps, double confidence, int gs_reps_run, double gs_rep_seconds, double gs_cv,
                   int gs_reps_max, double* gs_pred);
 int gs_reps_needed(double cv, double eps, double confidence, int cap);
