@@ -277,21 +277,23 @@ sgpm_status sgpm_estimate_batch(sgpm_ctx_t ctx, int nq, const sgpm_graph_t* grap
 sgpm_status sgpm_exact_count(sgpm_ctx_t ctx, sgpm_graph_t g, sgpm_pattern_t p, uint64_t* count_lo,
                              uint64_t* count_hi);
 
-/* For callers that cannot allocate memory during the call (code under HIP
- * stream capture, tight serving loops, harnesses that forbid allocation):
- * sgpm_exact_count without any hipMalloc, hipFree or other allocating routine.
- * The count's scratch (block partials, its ticket counters and sums, and the
- * bitmap count's list of first edges with more than 64 candidates) lives in
- * one file-scope device array per GPU of about 8 MiB, reserved when the library
- * is loaded and held until the process ends; its device address is looked up
- * on the first call on each device.  The kernels, widths and ticket plans are
- * sgpm_exact_count's, so the count is the same; a graph with more than 2^21
- * first edges counts cliques by the general search instead of the bitmaps (the
- * list would not fit), which counts the same tuples.  A launch needing more
- * than 4,096 blocks of partials fails with EINVAL.  Every call on a GPU shares
- * that GPU's array and clears its counters first, so calls that overlap on one
- * GPU (contexts on different host threads) race and must be serialised by the
- * caller.  Arguments, result and other errors as sgpm_exact_count. */
+/* For callers that cannot allocate memory during the call (tight serving
+ * loops, harnesses that forbid allocation): sgpm_exact_count without any
+ * hipMalloc, hipFree or other allocating routine.  Like sgpm_exact_count it
+ * synchronises the context's stream to read its counts back, so it is not for
+ * use under stream capture.  The count's scratch (block partials, its ticket
+ * counters and sums, and the list of first edges that the clique bitmaps pass
+ * on) lives in one file-scope device array per GPU of about 8 MiB, reserved
+ * when the library is loaded and held until the process ends; its device
+ * address is looked up on the first call on each device.  The kernels, widths
+ * and ticket plans are sgpm_exact_count's, so the count is the same; where the
+ * array's list (2^21 first edges) could not hold a pass's list, cliques go to
+ * the general search instead of that bitmap pass, which counts the same
+ * tuples.  A launch needing more than 4,096 blocks of partials fails with
+ * EINVAL.  Every call on a GPU shares that GPU's array and clears its counters
+ * first, so calls that overlap on one GPU (contexts on different host threads)
+ * race and must be serialised by the caller.  Arguments, result and other
+ * errors as sgpm_exact_count. */
 sgpm_status sgpm_exact_count_noalloc(sgpm_ctx_t ctx, sgpm_graph_t g, sgpm_pattern_t p, uint64_t* count_lo,
                                      uint64_t* count_hi);
 
