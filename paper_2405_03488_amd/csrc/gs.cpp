@@ -162,25 +162,44 @@ int exact_group(const sgpm_graph* g, const Plan& p) {
 
 // exact count of the plan's tuples on g (the leaves of the pruned search tree).
 // The 4-, 5- and 6-clique on oriented first edges take the bitmap count (one
-// wave per first edge; first edges whose candidate set exceeds 64 go to the
-// general search through a list), unless SGPM_EXACT_GROUP fixes the general
-// search's width or the list could outgrow its buffer.  The diamond takes the
-// sum over edges of C(t_e, 2) (t_e the edge's common neighbours: each diamond
-// once, through the edge its two triangles share), less 6 per 4-clique when
-// vertex-induced (a 4-clique holds six diamonds), under the same SGPM_EXACT_GROUP
-// exception.  The rest take the general search.  The buffers come from the
-// caller: block partials (two words per block, for part_blocks blocks),
-// kCountCells counter and sum words (cleared here), and the list of ovf_cap
-// first-edge ids.
-bool count_not_by_leaves(const Plan& p) {
-    return plan_is_diamond(p) || (plan_is_clique(p) && p.oriented && p.k >= 4 && p.k <= 6);
+// wave per first edge; first edges whose candidate set exceeds 64, then 128,
+// go on through lists), unless SGPM_EXACT_GROUP fixes the general search's
+// width or a list could outgrow its buffer.  Four 4-vertex patterns and the
+// wedge have closed forms over edges (edge_shape), counted by one pass of
+// per-edge terms, under the same SGPM_EXACT_GROUP exception.  The rest take
+// the general search.  The buffers come from the caller: block partials (two
+// words per slot, part_blocks slots), kCountCells counter and sum words
+// (cleared here), and the list of ovf_cap first-edge ids.
+
+// The patterns counted from per-edge terms (t the edge's common neighbours,
+// du and dw its endpoints' degrees, K4 the 4-cliques), by identities the
+// oracle's counts are pinned against:
+//   wedge          sum (du + dw - 2) / 2;  vertex-induced: sum (du + dw - 2 - 2t) / 2
+//   3-star         sum (C(du - 1, 2) + C(dw - 1, 2)) / 3;  induced: that - tt + 2 dia - 4 K4
+//   4-path         sum ((du - 1)(dw - 1) - t);  (induced: needs the 4-cycles, not here)
+//   tailed triangle tt = sum t (du + dw - 4) / 2;  induced: tt - 4 dia + 12 K4
+//   diamond        dia = sum C(t, 2);  induced: dia - 6 K4
+int edge_shape(const Plan& p) {
+    if (p.k != 3 && p.k != 4) return SHAPE_NONE;
+    int deg[4] = {0, 0, 0, 0}, edges = 0;
+    for (int j = 1; j < p.k; j++)
+        for (int i = 0; i < j; i++)
+            if (p.connect[j] >> i & 1) {
+                deg[i]++;
+                deg[j]++;
+                edges++;
+            }
+    std::sort(deg, deg + p.k);
+    if (p.k == 3) return edges == 2 ? SHAPE_WEDGE : SHAPE_NONE;
+    if (edges == 3 && deg[3] == 3) return SHAPE_STAR3;
+    if (edges == 3 && deg[3] == 2) return p.induced ? SHAPE_NONE : SHAPE_PATH4;
+    if (edges == 4 && deg[3] == 3) return SHAPE_TAILED;
+    if (edges == 5) return SHAPE_DIAMOND;
+    return SHAPE_NONE;
 }
 
-bool plan_is_diamond(const Plan& p) {
-    if (p.k != 4) return false;
-    int edges = 0;
-    for (int j = 1; j < 4; j++) edges += __builtin_popcount((unsigned)p.connect[j]);
-    return edges == 5;
+bool count_not_by_leaves(const Plan& p) {
+    return edge_shape(p) != SHAPE_NONE || (plan_is_clique(p) && p.oriented && p.k >= 4 && p.k <= 6);
 }
 
 namespace {
@@ -216,11 +235,11 @@ sgpm_status exact_count_with(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const Co
     if (seconds) *seconds = 0.0;
     if (nfirst == 0) return SGPM_OK;
     const bool bitmap = bitmap_count_applies(p, nfirst) && nfirst <= b.ovf_cap;
-    const bool diamond = plan_is_diamond(p) && !std::getenv("SGPM_EXACT_GROUP");
+    const int shape = std::getenv("SGPM_EXACT_GROUP") ? (int)SHAPE_NONE : edge_shape(p);
     int group = exact_group(g, p);
     // cells, three passes of ticket, count or spare, 2 sums: the 64-member
     // bitmaps (0-3), the 128-member bitmaps (4-7), the general search (8-11);
-    // words 16 on are the induced diamond's 4-clique count's
+    // words 16 on are the 4-clique count's of an induced pattern with a closed form
     unsigned long long* d = b.cells;
     HIP_TRY(c, launch_fill_u64(d, 12, 0ull, c->st));
     ScopedEvents<2> ev;
@@ -244,35 +263,64 @@ sgpm_status exact_count_with(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const Co
     auto bitmap_plan = [&](int blocks, uint64_t nf) {
         return TicketPlan{std::max<uint64_t>(32, nf / ((uint64_t)blocks * 4 * 8)), 0};
     };
-    if (diamond) {
+    if (shape != SHAPE_NONE) {
+        // terms: ET 0 diamond, 1 tailed, 2 4-path, 3 3-star, 4 wedge, 5 induced wedge
+        int sel[3] = {-1, -1, -1};
+        const bool ind = p.induced != 0;
+        switch (shape) {
+            case SHAPE_WEDGE: sel[0] = ind ? 5 : 4; break;
+            case SHAPE_STAR3: sel[0] = 3; if (ind) { sel[1] = 1; sel[2] = 0; } break;
+            case SHAPE_PATH4: sel[0] = 2; break;
+            case SHAPE_TAILED: sel[0] = 1; if (ind) sel[1] = 0; break;
+            default: sel[0] = 0; break;  // diamond
+        }
+        const bool need_t = !((shape == SHAPE_WEDGE || shape == SHAPE_STAR3) && !ind);
+        const bool need_k4 = ind && (shape == SHAPE_STAR3 || shape == SHAPE_TAILED || shape == SHAPE_DIAMOND);
         // 8 lanes per edge unless some rows are long (hubs), where 64 pay:
-        // R-MAT 20 at c = 16 (max degree 3,983) 1.2 ms at 8 lanes, 3.3 at 64;
-        // R-MAT 20 at c = 4 (about 16K) 15.7 and 5.2; R-MAT 24 at c = 16
-        // (about 25K) 51 and 15.7
+        // diamond, R-MAT 20 at c = 16 (max degree 3,983) 1.2 ms at 8 lanes, 3.3
+        // at 64; R-MAT 20 at c = 4 (about 16K) 15.7 and 5.2; R-MAT 24 at c = 16
+        // (about 25K) 51 and 15.7.  Six partial words per block: at most a
+        // third of the partials slots.
         const int grp = (2.0 * (double)g->m >= 16.0 * (double)g->n || g->maxdeg >= 8192) ? 64 : 8;
-        const int blocks = c->cus * edge_pairs_blocks_per_cu(grp);
-        if ((size_t)blocks > b.part_blocks) return fail(c, SGPM_EINVAL, "the count's launch exceeds its partials buffer");
-        HIP_TRY(c, launch_edge_pairs(g->view(), grp, blocks, general_plan(grp, blocks, (uint64_t)g->m), d, b.part,
-                                     d + 2, c->st));
+        const int blocks =
+            (int)std::min<size_t>((size_t)c->cus * (size_t)edge_terms_blocks_per_cu(grp, need_t), b.part_blocks / 3);
+        if (blocks < 1) return fail(c, SGPM_EINVAL, "the count's launch exceeds its partials buffer");
+        HIP_TRY(c, launch_edge_terms(g->view(), grp, need_t, blocks, general_plan(grp, blocks, (uint64_t)g->m), sel,
+                                     d, b.part, d + 4, c->st));
         unsigned __int128 k4 = 0;
-        if (p.induced) {
+        if (need_k4) {
             CountBuffers bk = b;
             bk.cells = b.cells + 16;
             sgpm_status st = exact_count_with(c, g, clique4_plan(), bk, &k4, nullptr);
             if (st != SGPM_OK) return st;
         }
         if (seconds) HIP_TRY(c, hipEventRecord(ev.e[1], c->st));
-        unsigned long long two[2];
-        HIP_TRY(c, hipMemcpyAsync(two, d + 2, sizeof(two), hipMemcpyDeviceToHost, c->st));
+        unsigned long long six[6];
+        HIP_TRY(c, hipMemcpyAsync(six, d + 4, sizeof(six), hipMemcpyDeviceToHost, c->st));
         HIP_TRY(c, hipStreamSynchronize(c->st));
         if (seconds) {
             float ms = 0;
             (void)hipEventElapsedTime(&ms, ev.e[0], ev.e[1]);
             *seconds = ms * 1e-3;
         }
-        const unsigned __int128 pairs = (unsigned __int128)two[0] + ((unsigned __int128)two[1] << 32);
-        if (pairs < 6 * k4) return fail(c, SGPM_EHIP, "internal: induced diamond count below zero");
-        *out = pairs - 6 * k4;
+        __int128 S[3];
+        for (int q = 0; q < 3; q++) S[q] = (__int128)six[2 * q] + ((__int128)six[2 * q + 1] << 32);
+        const __int128 K4 = (__int128)k4;
+        __int128 v = -1;
+        bool exact = true;  // the divisions are exact by the identities
+        auto div = [&](__int128 x, int q) {
+            if (x % q != 0) exact = false;
+            return x / q;
+        };
+        switch (shape) {
+            case SHAPE_WEDGE: v = div(S[0], 2); break;
+            case SHAPE_STAR3: v = ind ? div(S[0], 3) - div(S[1], 2) + 2 * S[2] - 4 * K4 : div(S[0], 3); break;
+            case SHAPE_PATH4: v = S[0]; break;
+            case SHAPE_TAILED: v = ind ? div(S[0], 2) - 4 * S[1] + 12 * K4 : div(S[0], 2); break;
+            default: v = ind ? S[0] - 6 * K4 : S[0]; break;
+        }
+        if (!exact || v < 0) return fail(c, SGPM_EHIP, "internal: per-edge terms do not give a count");
+        *out = (unsigned __int128)v;
         return SGPM_OK;
     }
     // Bitmap passes: candidate sets of up to 64 members, then the first pass's
@@ -336,15 +384,21 @@ sgpm_status exact_count(sgpm_ctx* c, sgpm_graph* g, const Plan& p, unsigned __in
     if (seconds) *seconds = 0.0;
     if (nfirst == 0) return SGPM_OK;
     const bool bitmap = bitmap_count_applies(p, nfirst);
-    const bool diamond = plan_is_diamond(p);
+    const int shape = edge_shape(p);
+    const bool diamond = shape != SHAPE_NONE;  // a closed form over edges (its 4-cliques when induced)
     const int maxblocks = c->cus * std::max({exact_blocks_per_cu(64), exact_blocks_per_cu(exact_group(g, p)),
                                              bitmap || diamond ? clique_bitmap_blocks_per_cu(4) : 1,
                                              bitmap ? std::max(clique_bitmap_blocks_per_cu(p.k), clique_bitmap128_blocks_per_cu(p.k)) : 1,
                                              diamond ? clique_bitmap128_blocks_per_cu(4) : 1,
                                              diamond ? exact_blocks_per_cu(16) : 1,
-                                             diamond ? std::max(edge_pairs_blocks_per_cu(8), edge_pairs_blocks_per_cu(64)) : 1});
+                                             1});
+    // the per-edge terms take three slots per block
+    const int term_blocks = diamond ? c->cus * std::max({edge_terms_blocks_per_cu(8, true),
+                                                         edge_terms_blocks_per_cu(64, true),
+                                                         edge_terms_blocks_per_cu(64, false)})
+                                    : 0;
     CountBuffers b{};
-    b.part_blocks = (size_t)maxblocks;
+    b.part_blocks = std::max((size_t)maxblocks, 3 * (size_t)term_blocks);
     GS_SCRATCH(c, GS_PART, sizeof(unsigned long long) * 2 * b.part_blocks, b.part);
     GS_SCRATCH(c, GS_CELL, sizeof(unsigned long long) * kCountCells, b.cells);
     if (bitmap || (diamond && p.induced)) {  // the induced diamond counts 4-cliques over the m oriented edges

@@ -874,65 +874,123 @@ __global__ __launch_bounds__(256) void clique_bitmap128_kernel(DGraph g, const u
     }
 }
 
-// Common-neighbour pairs of every edge, for the diamond (K4 minus one edge).
-// Its two degree-3 vertices span the one edge both of its triangles share, and
-// its other two vertices are common neighbours of that edge's endpoints, so the
-// diamonds are the pairs of common neighbours of the edges: sum over edges of
-// C(t_e, 2), t_e = |N(u) n N(w)|, each diamond once.  G lanes per edge (edges
-// in the oriented list, each once): the shorter row, G entries at a time, is
-// merged against the longer by the window search.
-template <int G>
-__global__ __launch_bounds__(256) void edge_pairs_kernel(DGraph g, TicketPlan tp,
+// Per-edge terms of the 4-vertex counts that have closed forms over edges
+// (each identity is one the oracle's counts are pinned against): with t the
+// edge's common neighbours and du, dw its endpoints' degrees, the oriented
+// edge list (each edge once) gives
+//   ET_DIAMOND  C(t, 2)                      diamonds (one middle edge each)
+//   ET_TAILED   t (du + dw - 4)              twice the tailed triangles
+//   ET_PATH4    (du - 1)(dw - 1) - t         4-paths (by their middle edge)
+//   ET_STAR3    C(du - 1, 2) + C(dw - 1, 2)  three times the 3-stars
+//   ET_WEDGE    du + dw - 2                  twice the wedges
+//   ET_IWEDGE   du + dw - 2 - 2t             twice the induced wedges
+// Every term is below 2^63.  The launch sums the terms sel[0..2] (-1: none);
+// a lane adds each term's low and high 32-bit halves separately and every
+// block writes its six sums to partials[6 block ..].  With NEED_T the G lanes
+// of a group intersect the edge's rows (the shorter row, G entries at a time,
+// merged against the longer by the window search); without it (degree terms
+// only) every lane takes its own edges.
+enum { ET_DIAMOND, ET_TAILED, ET_PATH4, ET_STAR3, ET_WEDGE, ET_IWEDGE };
+
+__device__ __forceinline__ unsigned long long edge_term(int q, unsigned long long t, unsigned long long du,
+                                                        unsigned long long dw) {
+    switch (q) {
+        case ET_DIAMOND: return t * (t - 1ull) / 2ull;  // 0 for t = 0 in unsigned arithmetic
+        case ET_TAILED: return t == 0ull ? 0ull : t * (du + dw - 4ull);  // t >= 1: du, dw >= 2
+        case ET_PATH4: return (du - 1ull) * (dw - 1ull) - t;
+        case ET_STAR3:
+            return (du >= 3ull ? (du - 1ull) * (du - 2ull) / 2ull : 0ull) +
+                   (dw >= 3ull ? (dw - 1ull) * (dw - 2ull) / 2ull : 0ull);
+        case ET_WEDGE: return du + dw - 2ull;
+        case ET_IWEDGE: return du + dw - 2ull - 2ull * t;
+        default: return 0ull;
+    }
+}
+
+template <int G, bool NEED_T>
+__global__ __launch_bounds__(256) void edge_terms_kernel(DGraph g, TicketPlan tp, int sel0, int sel1, int sel2,
                                                          unsigned long long* __restrict__ ticket,
                                                          unsigned long long* __restrict__ partials) {
     const int lane = (int)(threadIdx.x & 63), w = (int)(threadIdx.x >> 6);
     const Lanes<G> ln{lane % G, (lane / G) * G};
-    const uint64_t nfirst = (uint64_t)g.m;
-    unsigned long long total = 0;  // uniform over the group
-    for (;;) {
-        unsigned long long t = 0;
-        if (ln.sub == 0) t = atomicAdd(ticket, 1ull);
-        t = __shfl(t, ln.base);
-        if (t >= nfirst) break;
-        const uint64_t e0 = ticket_start(tp, t);
-        if (e0 >= nfirst) break;
-        const uint64_t e1 = min(ticket_start(tp, t + 1), nfirst);
-        for (uint64_t e = e0; e < e1; ++e) {
+    const uint64_t nedges = (uint64_t)g.m;
+    const int sel[3] = {sel0, sel1, sel2};
+    unsigned long long acc[6] = {0ull, 0ull, 0ull, 0ull, 0ull, 0ull};  // (low, high) per selected term
+    auto add = [&](unsigned long long t, unsigned long long du, unsigned long long dw) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const unsigned long long v = edge_term(sel[k], t, du, dw);
+            acc[2 * k] += v & 0xFFFFFFFFull;
+            acc[2 * k + 1] += v >> 32;
+        }
+    };
+    if constexpr (!NEED_T) {
+        for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nedges;
+             e += (uint64_t)gridDim.x * blockDim.x) {
             const int2 pr = g.epair[e];
-            const int64_t b0 = g.off[pr.x], b1 = g.off[pr.y];
-            const int32_t l0 = (int32_t)(g.off[pr.x + 1] - b0), l1 = (int32_t)(g.off[pr.y + 1] - b1);
-            const bool d0 = l0 <= l1;
-            const int32_t* dp = g.nbr + (d0 ? b0 : b1);
-            const int32_t* op = g.nbr + (d0 ? b1 : b0);
-            const int32_t dl = d0 ? l0 : l1, ol = d0 ? l1 : l0;
-            int32_t cur = 0;
-            unsigned long long tc = 0;
-            for (int32_t base = 0; base < dl; base += G) {
-                const bool act = base + ln.sub < dl;
-                const int32_t x = act ? dp[base + ln.sub] : GBIG;
-                const int32_t xmax = ln.at(x, min(G, dl - base) - 1);
-                const bool f = grp_member<G>(op, ol, cur, x, act, xmax, ln);
-                tc += (unsigned long long)__popcll(ln.ballot(act && f));
+            add(0ull, (unsigned long long)(g.off[pr.x + 1] - g.off[pr.x]),
+                (unsigned long long)(g.off[pr.y + 1] - g.off[pr.y]));
+        }
+    } else {
+        for (;;) {
+            unsigned long long t = 0;
+            if (ln.sub == 0) t = atomicAdd(ticket, 1ull);
+            t = __shfl(t, ln.base);
+            if (t >= nedges) break;
+            const uint64_t e0 = ticket_start(tp, t);
+            if (e0 >= nedges) break;
+            const uint64_t e1 = min(ticket_start(tp, t + 1), nedges);
+            for (uint64_t e = e0; e < e1; ++e) {
+                const int2 pr = g.epair[e];
+                const int64_t b0 = g.off[pr.x], b1 = g.off[pr.y];
+                const int32_t l0 = (int32_t)(g.off[pr.x + 1] - b0), l1 = (int32_t)(g.off[pr.y + 1] - b1);
+                const bool d0 = l0 <= l1;
+                const int32_t* dp = g.nbr + (d0 ? b0 : b1);
+                const int32_t* op = g.nbr + (d0 ? b1 : b0);
+                const int32_t dl = d0 ? l0 : l1, ol = d0 ? l1 : l0;
+                int32_t cur = 0;
+                unsigned long long tc = 0;
+                for (int32_t base = 0; base < dl; base += G) {
+                    const bool act = base + ln.sub < dl;
+                    const int32_t x = act ? dp[base + ln.sub] : GBIG;
+                    const int32_t xmax = ln.at(x, min(G, dl - base) - 1);
+                    const bool f = grp_member<G>(op, ol, cur, x, act, xmax, ln);
+                    tc += (unsigned long long)__popcll(ln.ballot(act && f));
+                }
+                // every lane of the group holds the same values; its first adds them
+                if (ln.sub == 0) add(tc, (unsigned long long)l0, (unsigned long long)l1);
             }
-            total += tc * (tc - 1ull) / 2ull;  // 0 for tc = 0 in unsigned arithmetic
         }
     }
-    // block sum in two 32-bit halves; one lane per group carries the group's total
-    unsigned long long lo = ln.sub == 0 ? (total & 0xFFFFFFFFull) : 0ull, hi = ln.sub == 0 ? (total >> 32) : 0ull;
+    __shared__ unsigned long long red[4][6];
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        lo += __shfl_xor(lo, o);
-        hi += __shfl_xor(hi, o);
-    }
-    __shared__ unsigned long long red[4][2];
-    if (lane == 0) {
-        red[w][0] = lo;
-        red[w][1] = hi;
+    for (int k = 0; k < 6; ++k) {
+        unsigned long long a = acc[k];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
+        if (lane == 0) red[w][k] = a;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        partials[2 * blockIdx.x] = red[0][0] + red[1][0] + red[2][0] + red[3][0];
-        partials[2 * blockIdx.x + 1] = red[0][1] + red[1][1] + red[2][1] + red[3][1];
+    if (threadIdx.x < 6)
+        partials[6 * (size_t)blockIdx.x + threadIdx.x] =
+            red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+}
+
+// out[k] = sum over the blocks of partials[6 block + k], k < 6
+__global__ void sum_six_kernel(const unsigned long long* __restrict__ partials, int nblocks,
+                               unsigned long long* __restrict__ out) {
+    __shared__ unsigned long long a[6][256];
+    unsigned long long s[6] = {0ull, 0ull, 0ull, 0ull, 0ull, 0ull};
+    for (int i = (int)threadIdx.x; i < nblocks; i += (int)blockDim.x)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) s[k] += partials[6 * (size_t)i + k];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) a[k][threadIdx.x] = s[k];
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        unsigned long long t = 0;
+        for (int i = 0; i < 256; ++i) t += a[threadIdx.x][i];
+        out[threadIdx.x] = t;
     }
 }
 
@@ -1098,24 +1156,31 @@ int clique_bitmap128_blocks_per_cu(int k) {
     return nb;
 }
 
-hipError_t launch_edge_pairs(const DGraph& g, int group, int blocks, TicketPlan tp, unsigned long long* ticket,
-                             unsigned long long* partials, unsigned long long* out2, hipStream_t st) {
-    if (group == 8)
-        hipLaunchKernelGGL(edge_pairs_kernel<8>, dim3((unsigned)blocks), dim3(256), 0, st, g, tp, ticket, partials);
+hipError_t launch_edge_terms(const DGraph& g, int group, bool need_t, int blocks, TicketPlan tp, const int sel[3],
+                             unsigned long long* ticket, unsigned long long* partials, unsigned long long* out6,
+                             hipStream_t st) {
+    if (!need_t)
+        hipLaunchKernelGGL((edge_terms_kernel<64, false>), dim3((unsigned)blocks), dim3(256), 0, st, g, tp, sel[0],
+                           sel[1], sel[2], ticket, partials);
+    else if (group == 8)
+        hipLaunchKernelGGL((edge_terms_kernel<8, true>), dim3((unsigned)blocks), dim3(256), 0, st, g, tp, sel[0],
+                           sel[1], sel[2], ticket, partials);
     else if (group == 64)
-        hipLaunchKernelGGL(edge_pairs_kernel<64>, dim3((unsigned)blocks), dim3(256), 0, st, g, tp, ticket, partials);
+        hipLaunchKernelGGL((edge_terms_kernel<64, true>), dim3((unsigned)blocks), dim3(256), 0, st, g, tp, sel[0],
+                           sel[1], sel[2], ticket, partials);
     else
         return hipErrorInvalidValue;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(sum_pairs_kernel, dim3(1), dim3(256), 0, st, partials, blocks, out2);
+    hipLaunchKernelGGL(sum_six_kernel, dim3(1), dim3(256), 0, st, partials, blocks, out6);
     return hipGetLastError();
 }
 
-int edge_pairs_blocks_per_cu(int group) {
+int edge_terms_blocks_per_cu(int group, bool need_t) {
     int nb = 0;
-    hipError_t e = group == 8 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, edge_pairs_kernel<8>, 256, 0)
-                              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, edge_pairs_kernel<64>, 256, 0);
+    hipError_t e = !need_t       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, edge_terms_kernel<64, false>, 256, 0)
+                   : group == 8 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, edge_terms_kernel<8, true>, 256, 0)
+                                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, edge_terms_kernel<64, true>, 256, 0);
     if (e != hipSuccess || nb < 1) nb = 2;
     return nb;
 }

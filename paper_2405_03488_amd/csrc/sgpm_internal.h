@@ -217,12 +217,18 @@ hipError_t launch_clique_bitmap128(const DGraph& g, int k, const uint32_t* elist
                                    unsigned long long* out2, uint32_t* overflow, unsigned long long* noverflow,
                                    hipStream_t st);
 int clique_bitmap128_blocks_per_cu(int k);
-// diamond: sum over the oriented edges of C(t_e, 2), t_e the edge's common
-// neighbours, with group (8 or 64) lanes per edge; out2 receives the low and
-// high 32-bit halves' sums
-hipError_t launch_edge_pairs(const DGraph& g, int group, int blocks, TicketPlan tp, unsigned long long* ticket,
-                             unsigned long long* partials, unsigned long long* out2, hipStream_t st);
-int edge_pairs_blocks_per_cu(int group);
+// Closed-form 4-vertex counts over edges: for every oriented edge (common
+// neighbours t, endpoint degrees du, dw) the terms sel[0..2] of
+//   0 C(t, 2), 1 t (du + dw - 4), 2 (du - 1)(dw - 1) - t,
+//   3 C(du - 1, 2) + C(dw - 1, 2), 4 du + dw - 2, 5 du + dw - 2 - 2t
+// (-1: none) are summed; out6[2k], out6[2k + 1] receive term k's low and high
+// 32-bit halves' sums.  need_t: the terms use t (group 8 or 64 lanes per
+// edge intersect the rows); else one lane per edge.  partials: 6 words per
+// block.
+hipError_t launch_edge_terms(const DGraph& g, int group, bool need_t, int blocks, TicketPlan tp, const int sel[3],
+                             unsigned long long* ticket, unsigned long long* partials, unsigned long long* out6,
+                             hipStream_t st);
+int edge_terms_blocks_per_cu(int group, bool need_t);
 // Scratch of the allocation-free exact count: one file-scope device array per
 // GPU of kCountScratchWords 64-bit words, laid out as kCountScratchBlocks
 // two-word block partials, then kCountCells counter and sum words, then a list of
@@ -361,11 +367,12 @@ void cost_model(const Plan& p, const sgpm_cost_in& in, sgpm_cost_out* out);
 sgpm_status sparsify(sgpm_ctx* c, sgpm_graph* g, uint32_t colours, uint64_t seed, uint32_t rep, sgpm_graph** out,
                      bool bes = false, bool scratch_graph = false);
 sgpm_status exact_count(sgpm_ctx* c, sgpm_graph* g, const Plan& p, unsigned __int128* out, double* seconds);
-// a 4-vertex pattern of five edges (K4 less one edge): its exact count is the
-// per-edge common-neighbour pairs, an edge scan, not a search over its leaves
-bool plan_is_diamond(const Plan& p);
-// the diamond and the 4- to 6-clique: counted by edge pairs or bitmaps, whose
-// time does not follow the number of leaves
+// patterns whose exact count is a closed form over per-edge terms (common
+// neighbours and degrees of the edge's endpoints), by edge_shape
+enum EdgeShape { SHAPE_NONE, SHAPE_WEDGE, SHAPE_STAR3, SHAPE_PATH4, SHAPE_TAILED, SHAPE_DIAMOND };
+int edge_shape(const Plan& p);
+// the edge-shaped patterns and the 4- to 6-clique: counted from per-edge terms
+// or by bitmaps, whose time does not follow the number of leaves
 bool count_not_by_leaves(const Plan& p);
 int hybrid_choice(double ns_lo, double eps, double confidence, int gs_reps_run, double gs_rep_seconds, double gs_cv,
                   int gs_reps_max, double* gs_pred);
