@@ -30,8 +30,9 @@
 //    uses, plus its leaves at an optimistic rate) taking at least the cone's
 //    lower end rule GS out without running it (a large graph's exact count can
 //    take minutes; a small one's colouring is mostly its sparsification; the
-//    diamond's edge pairs and the 4- to 6-clique's bitmaps count many leaves
-//    per instruction, up to 2e12 leaves/s, so they are charged their pass over
+//    per-edge closed forms (wedge, 3-star, 4-path, tailed triangle, diamond)
+//    and the 4- to 6-clique's bitmaps count many leaves per instruction, up
+//    to 2e12 leaves/s and more, so they are charged their pass over
 //    the about m / c kept edges at 2e9 edges/s instead, above the 0.8e9 to
 //    1.4e9 measured).  The rate is
 //    1e11 leaves per second when the sparsified graph is sparse (mean degree
@@ -198,7 +199,7 @@ sgpm_status hybrid_estimate(sgpm_ctx* c, sgpm_graph* g, sgpm_pattern* pat, const
         double leaves = mu;
         for (int i = 0; i < p.k - 1; i++) leaves /= (double)col;
         const double sparse_deg = g->n > 0 ? 2.0 * (double)g->m / ((double)g->n * (double)col) : 0.0;
-        // (the diamond's edge pairs and the cliques' bitmaps count many leaves
+        // (the per-edge closed forms and the cliques' bitmaps count many leaves
         // per instruction: their search is charged its pass over the kept
         // edges, about m / c, at 2e9 edges per second instead)
         const double search = count_not_by_leaves(p) ? (double)g->m / (double)col / 2e9
