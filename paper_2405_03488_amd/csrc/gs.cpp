@@ -385,15 +385,15 @@ sgpm_status exact_count(sgpm_ctx* c, sgpm_graph* g, const Plan& p, unsigned __in
     if (nfirst == 0) return SGPM_OK;
     const bool bitmap = bitmap_count_applies(p, nfirst);
     const int shape = edge_shape(p);
-    const bool diamond = shape != SHAPE_NONE;  // a closed form over edges (its 4-cliques when induced)
+    const bool closed = shape != SHAPE_NONE;  // a closed form over edges (its 4-cliques when induced)
     const int maxblocks = c->cus * std::max({exact_blocks_per_cu(64), exact_blocks_per_cu(exact_group(g, p)),
-                                             bitmap || diamond ? clique_bitmap_blocks_per_cu(4) : 1,
+                                             bitmap || closed ? clique_bitmap_blocks_per_cu(4) : 1,
                                              bitmap ? std::max(clique_bitmap_blocks_per_cu(p.k), clique_bitmap128_blocks_per_cu(p.k)) : 1,
-                                             diamond ? clique_bitmap128_blocks_per_cu(4) : 1,
-                                             diamond ? exact_blocks_per_cu(16) : 1,
+                                             closed ? clique_bitmap128_blocks_per_cu(4) : 1,
+                                             closed ? exact_blocks_per_cu(16) : 1,
                                              1});
     // the per-edge terms take three slots per block
-    const int term_blocks = diamond ? c->cus * std::max({edge_terms_blocks_per_cu(8, true),
+    const int term_blocks = closed ? c->cus * std::max({edge_terms_blocks_per_cu(8, true),
                                                          edge_terms_blocks_per_cu(64, true),
                                                          edge_terms_blocks_per_cu(64, false)})
                                     : 0;
@@ -401,7 +401,7 @@ sgpm_status exact_count(sgpm_ctx* c, sgpm_graph* g, const Plan& p, unsigned __in
     b.part_blocks = std::max((size_t)maxblocks, 3 * (size_t)term_blocks);
     GS_SCRATCH(c, GS_PART, sizeof(unsigned long long) * 2 * b.part_blocks, b.part);
     GS_SCRATCH(c, GS_CELL, sizeof(unsigned long long) * kCountCells, b.cells);
-    if (bitmap || (diamond && p.induced)) {  // the induced diamond counts 4-cliques over the m oriented edges
+    if (bitmap || (closed && p.induced)) {  // an induced closed form counts 4-cliques over the m oriented edges
         // room for the first bitmap pass's list and, after it, the second's
         const uint64_t cap = 2 * std::max<uint64_t>(nfirst, (uint64_t)g->m);
         GS_SCRATCH(c, GS_OVF, sizeof(uint32_t) * (size_t)std::max<uint64_t>(cap, 1), b.ovf);
