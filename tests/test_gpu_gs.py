@@ -147,6 +147,22 @@ def test_exact_diamond_by_edge_pairs(S, O, synth, ctx, induced):
     S.sgpm_pattern_free(p)
 
 
+@pytest.mark.parametrize("induced", [False, True])
+def test_closed_forms_at_wave_width(S, O, synth, ctx, induced):
+    """The per-edge closed forms at 64 lanes per edge (a graph of mean degree
+    16 or more: ER(400, 4000)) against the oracle's search, for the wedge,
+    3-star, 4-path, tailed triangle and diamond."""
+    print(f"closed forms 64 lanes induced={induced}", flush=True)
+    g, og = load(S, O, synth, ctx, 400, synth.er_pairs(400, 4000, 9))
+    assert 2 * S.sgpm_graph_stats(g)[1] >= 16 * 400
+    for name in ["wedge", "3-star", "4-path", "tailed-triangle", "diamond"]:
+        k, e = synth.pattern(name)
+        p = S.sgpm_pattern_create(ctx, k, e, induced)
+        assert S.sgpm_exact_count(ctx, g, p) == O.plan_count(og, O.compile_plan(k, e, induced)), name
+        S.sgpm_pattern_free(p)
+    S.sgpm_graph_free(g)
+
+
 @pytest.mark.parametrize("name,c", [("triangle", 4), ("4-cycle", 3), ("diamond", 2)])
 def test_gs_estimate_matches_oracle(S, O, synth, ctx, cl, name, c):
     g, og = cl
