@@ -179,6 +179,9 @@ int exact_group(const sgpm_graph* g, const Plan& p) {
 //   4-path         sum ((du - 1)(dw - 1) - t);  (induced: needs the 4-cycles, not here)
 //   tailed triangle tt = sum t (du + dw - 4) / 2;  induced: tt - 4 dia + 12 K4
 //   diamond        dia = sum C(t, 2);  induced: dia - 6 K4
+// With the 4-cycles C4 from the general search, also
+//   induced 4-path   sum ((du - 1)(dw - 1) - t) - 2 tt - 4 C4 + 6 dia - 12 K4
+//   induced 4-cycle  C4 - dia + 3 K4
 int edge_shape(const Plan& p) {
     if (p.k != 3 && p.k != 4) return SHAPE_NONE;
     int deg[4] = {0, 0, 0, 0}, edges = 0;
@@ -192,14 +195,17 @@ int edge_shape(const Plan& p) {
     std::sort(deg, deg + p.k);
     if (p.k == 3) return edges == 2 ? SHAPE_WEDGE : SHAPE_NONE;
     if (edges == 3 && deg[3] == 3) return SHAPE_STAR3;
-    if (edges == 3 && deg[3] == 2) return p.induced ? SHAPE_NONE : SHAPE_PATH4;
+    if (edges == 3 && deg[3] == 2) return p.induced ? SHAPE_IPATH4 : SHAPE_PATH4;
     if (edges == 4 && deg[3] == 3) return SHAPE_TAILED;
+    if (edges == 4 && deg[3] == 2) return p.induced ? SHAPE_ICYCLE4 : SHAPE_NONE;
     if (edges == 5) return SHAPE_DIAMOND;
     return SHAPE_NONE;
 }
 
 bool count_not_by_leaves(const Plan& p) {
-    return edge_shape(p) != SHAPE_NONE || (plan_is_clique(p) && p.oriented && p.k >= 4 && p.k <= 6);
+    const int sh = edge_shape(p);  // the induced 4-path and 4-cycle search the 4-cycles
+    return (sh != SHAPE_NONE && sh != SHAPE_IPATH4 && sh != SHAPE_ICYCLE4) ||
+           (plan_is_clique(p) && p.oriented && p.k >= 4 && p.k <= 6);
 }
 
 namespace {
@@ -223,6 +229,17 @@ const Plan& clique4_plan() {
     return plan;
 }
 
+const Plan& cycle4_plan() {
+    static const Plan plan = [] {
+        const int32_t e[8] = {0, 1, 1, 2, 2, 3, 3, 0};
+        Plan q{};
+        std::string err;
+        (void)compile_pattern(4, 4, e, 0, q, err);
+        return q;
+    }();
+    return plan;
+}
+
 bool bitmap_count_applies(const Plan& p, uint64_t nfirst) {
     return plan_is_clique(p) && p.oriented && p.k >= 4 && p.k <= 6 && nfirst <= (1ull << 28) &&
            !std::getenv("SGPM_EXACT_GROUP");
@@ -239,7 +256,8 @@ sgpm_status exact_count_with(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const Co
     int group = exact_group(g, p);
     // cells, three passes of ticket, count or spare, 2 sums: the 64-member
     // bitmaps (0-3), the 128-member bitmaps (4-7), the general search (8-11);
-    // words 16 on are the 4-clique count's of an induced pattern with a closed form
+    // words 16 on are the 4-clique count's of an induced pattern with a closed form,
+    // words 32 on the 4-cycle count's
     unsigned long long* d = b.cells;
     HIP_TRY(c, launch_fill_u64(d, 12, 0ull, c->st));
     ScopedEvents<2> ev;
@@ -272,10 +290,12 @@ sgpm_status exact_count_with(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const Co
             case SHAPE_STAR3: sel[0] = 3; if (ind) { sel[1] = 1; sel[2] = 0; } break;
             case SHAPE_PATH4: sel[0] = 2; break;
             case SHAPE_TAILED: sel[0] = 1; if (ind) sel[1] = 0; break;
-            default: sel[0] = 0; break;  // diamond
+            case SHAPE_IPATH4: sel[0] = 2; sel[1] = 1; sel[2] = 0; break;
+            default: sel[0] = 0; break;  // diamond, induced 4-cycle
         }
         const bool need_t = !((shape == SHAPE_WEDGE || shape == SHAPE_STAR3) && !ind);
-        const bool need_k4 = ind && (shape == SHAPE_STAR3 || shape == SHAPE_TAILED || shape == SHAPE_DIAMOND);
+        const bool need_k4 = ind && shape != SHAPE_WEDGE;
+        const bool need_c4 = shape == SHAPE_IPATH4 || shape == SHAPE_ICYCLE4;
         // 8 lanes per edge unless some rows are long (hubs), where 64 pay:
         // diamond, R-MAT 20 at c = 16 (max degree 3,983) 1.2 ms at 8 lanes, 3.3
         // at 64; R-MAT 20 at c = 4 (about 16K) 15.7 and 5.2; R-MAT 24 at c = 16
@@ -287,11 +307,17 @@ sgpm_status exact_count_with(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const Co
         if (blocks < 1) return fail(c, SGPM_EINVAL, "the count's launch exceeds its partials buffer");
         HIP_TRY(c, launch_edge_terms(g->view(), grp, need_t, blocks, general_plan(grp, blocks, (uint64_t)g->m), sel,
                                      d, b.part, d + 4, c->st));
-        unsigned __int128 k4 = 0;
+        unsigned __int128 k4 = 0, c4 = 0;
         if (need_k4) {
             CountBuffers bk = b;
             bk.cells = b.cells + 16;
             sgpm_status st = exact_count_with(c, g, clique4_plan(), bk, &k4, nullptr);
+            if (st != SGPM_OK) return st;
+        }
+        if (need_c4) {  // the 4-cycles by the general search (cells 32 on)
+            CountBuffers bc = b;
+            bc.cells = b.cells + 32;
+            sgpm_status st = exact_count_with(c, g, cycle4_plan(), bc, &c4, nullptr);
             if (st != SGPM_OK) return st;
         }
         if (seconds) HIP_TRY(c, hipEventRecord(ev.e[1], c->st));
@@ -305,7 +331,7 @@ sgpm_status exact_count_with(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const Co
         }
         __int128 S[3];
         for (int q = 0; q < 3; q++) S[q] = (__int128)six[2 * q] + ((__int128)six[2 * q + 1] << 32);
-        const __int128 K4 = (__int128)k4;
+        const __int128 K4 = (__int128)k4, C4 = (__int128)c4;
         __int128 v = -1;
         bool exact = true;  // the divisions are exact by the identities
         auto div = [&](__int128 x, int q) {
@@ -317,6 +343,8 @@ sgpm_status exact_count_with(sgpm_ctx* c, sgpm_graph* g, const Plan& p, const Co
             case SHAPE_STAR3: v = ind ? div(S[0], 3) - div(S[1], 2) + 2 * S[2] - 4 * K4 : div(S[0], 3); break;
             case SHAPE_PATH4: v = S[0]; break;
             case SHAPE_TAILED: v = ind ? div(S[0], 2) - 4 * S[1] + 12 * K4 : div(S[0], 2); break;
+            case SHAPE_IPATH4: v = S[0] - S[1] - 4 * C4 + 6 * S[2] - 12 * K4; break;  // S[1] = 2 tt
+            case SHAPE_ICYCLE4: v = C4 - S[0] + 3 * K4; break;
             default: v = ind ? S[0] - 6 * K4 : S[0]; break;
         }
         if (!exact || v < 0) return fail(c, SGPM_EHIP, "internal: per-edge terms do not give a count");

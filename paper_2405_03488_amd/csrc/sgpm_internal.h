@@ -236,7 +236,7 @@ int edge_terms_blocks_per_cu(int group, bool need_t);
 // edges with more than 64 candidates.
 constexpr size_t kCountScratchBlocks = 4096;
 constexpr size_t kCountScratchOvf = size_t(1) << 21;
-constexpr size_t kCountCells = 32;
+constexpr size_t kCountCells = 48;
 constexpr size_t kCountScratchWords = 2 * kCountScratchBlocks + kCountCells + kCountScratchOvf / 2;
 // that array's device address on `dev`, which must be the current device:
 // looked up once per device (hipGetSymbolAddress), then reused
@@ -368,8 +368,9 @@ sgpm_status sparsify(sgpm_ctx* c, sgpm_graph* g, uint32_t colours, uint64_t seed
                      bool bes = false, bool scratch_graph = false);
 sgpm_status exact_count(sgpm_ctx* c, sgpm_graph* g, const Plan& p, unsigned __int128* out, double* seconds);
 // patterns whose exact count is a closed form over per-edge terms (common
-// neighbours and degrees of the edge's endpoints), by edge_shape
-enum EdgeShape { SHAPE_NONE, SHAPE_WEDGE, SHAPE_STAR3, SHAPE_PATH4, SHAPE_TAILED, SHAPE_DIAMOND };
+// neighbours and degrees of the edge's endpoints), by edge_shape; the
+// vertex-induced 4-path and 4-cycle also take the 4-cycles' general search
+enum EdgeShape { SHAPE_NONE, SHAPE_WEDGE, SHAPE_STAR3, SHAPE_PATH4, SHAPE_TAILED, SHAPE_DIAMOND, SHAPE_IPATH4, SHAPE_ICYCLE4 };
 int edge_shape(const Plan& p);
 // the edge-shaped patterns and the 4- to 6-clique: counted from per-edge terms
 // or by bitmaps, whose time does not follow the number of leaves

@@ -151,11 +151,12 @@ def test_exact_diamond_by_edge_pairs(S, O, synth, ctx, induced):
 def test_closed_forms_at_wave_width(S, O, synth, ctx, induced):
     """The per-edge closed forms at 64 lanes per edge (a graph of mean degree
     16 or more: ER(400, 4000)) against the oracle's search, for the wedge,
-    3-star, 4-path, tailed triangle and diamond."""
+    3-star, 4-path, tailed triangle and diamond, and the vertex-induced 4-path
+    and 4-cycle through the 4-cycles' search."""
     print(f"closed forms 64 lanes induced={induced}", flush=True)
     g, og = load(S, O, synth, ctx, 400, synth.er_pairs(400, 4000, 9))
     assert 2 * S.sgpm_graph_stats(g)[1] >= 16 * 400
-    for name in ["wedge", "3-star", "4-path", "tailed-triangle", "diamond"]:
+    for name in ["wedge", "3-star", "4-path", "tailed-triangle", "diamond", "4-cycle"]:
         k, e = synth.pattern(name)
         p = S.sgpm_pattern_create(ctx, k, e, induced)
         assert S.sgpm_exact_count(ctx, g, p) == O.plan_count(og, O.compile_plan(k, e, induced)), name
