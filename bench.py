@@ -89,7 +89,7 @@ def other_legs(S, ctx, g, pats, queries, eps):
         r, _ = S.sgpm_estimate(ctx, g, pats[q], S.sgpm_options_default(mode=S.MODE_GS, eps=eps, colours=16,
                                                                         gs_reps_max=2, seed=5))
         out["gs"][q] = {"colourings": int(r.n_samples), "estimate": r.estimate, "wall_s": time.perf_counter() - t0,
-                        "count_kernel_s": r.seconds_kernel}
+                        "count_kernel_s": r.seconds_kernel, "S1": int(r.S1)}
         t0 = time.perf_counter()
         r, _ = S.sgpm_estimate(ctx, g, pats[q], S.sgpm_options_default(mode=S.MODE_GS, eps=eps, colours=16,
                                                                         gs_reps_max=2, seed=5,
@@ -647,12 +647,17 @@ def main():
                 kq, eq = synth.pattern(q)
                 opq = O.compile_plan(kq, eq)
                 t0 = time.perf_counter()
-                gb = sum(O.gs_count_bytes(og, opq, 16, 5, r) for r in range(int(other["gs"][q]["colourings"])))
+                reps = range(int(other["gs"][q]["colourings"]))
+                gb = sum(O.gs_count_bytes(og, opq, 16, 5, r) for r in reps)
+                # the same colourings counted by the oracle: S1 = sum of 16^(k-1) Y_r
+                s1 = sum(O.gs_count(og, opq, 16, 5, r) * 16 ** (kq - 1) for r in reps)
                 kt = other["gs"][q]["count_kernel_s"]
                 gsr[q] = {"alg_bytes": gb, "count_kernel_s": kt, "achieved_GBs": gb / kt / 1e9 if kt > 0 else None,
                           "frac_of_hbm_peak": gb / kt / 1e9 / HBM_PEAK_GBS if kt > 0 else None,
+                          "counts_equal_oracle": s1 == other["gs"][q]["S1"],
                           "oracle_s": time.perf_counter() - t0}
-                log(f"gs count {q}: {gb} algorithmic bytes in {kt * 1e3:.2f} ms of count kernels")
+                log(f"gs count {q}: {gb} algorithmic bytes in {kt * 1e3:.2f} ms of count kernels; "
+                    f"sums equal the oracle's: {s1 == other['gs'][q]['S1']}")
             other["gs_count_roofline"] = gsr
 
     value = total_samples / wall
