@@ -271,9 +271,15 @@ sgpm_status sgpm_estimate_batch(sgpm_ctx_t ctx, int nq, const sgpm_graph_t* grap
  * graph) on the unsparsified graph, which is colour sparsification with one
  * colour.  The count is (count_hi << 64) | count_lo (count_hi nullable).
  * Errors: EINVAL (null ctx, graph, pattern or count_lo), EHIP.
- * The search runs 8, 16 or 64 lanes per first edge, chosen from the pattern and
- * the graph's mean degree; the environment variable SGPM_EXACT_GROUP (8, 16 or
- * 64) fixes it.  The count does not depend on the width. */
+ * The same count is reached three ways: the 4-, 5- and 6-clique by bitmaps
+ * over each first edge's common lower neighbourhood; the wedge, 3-star,
+ * 4-path, tailed triangle and diamond (edge- and vertex-induced; the induced
+ * 4-path and 4-cycle with the 4-cycles' search) by closed forms over per-edge
+ * common-neighbour counts and degrees; every other pattern by the search, at
+ * 8, 16 or 64 lanes per first edge chosen from the pattern and the graph's
+ * mean and maximum degree.  The environment variable SGPM_EXACT_GROUP (8, 16
+ * or 64) sends every pattern to the search at that width.  The count does not
+ * depend on the way or the width. */
 sgpm_status sgpm_exact_count(sgpm_ctx_t ctx, sgpm_graph_t g, sgpm_pattern_t p, uint64_t* count_lo,
                              uint64_t* count_hi);
 
