@@ -164,6 +164,26 @@ def test_closed_forms_at_wave_width(S, O, synth, ctx, induced):
     S.sgpm_graph_free(g)
 
 
+def test_closed_forms_degenerate_graphs(S, O, synth, ctx):
+    """Degree-1 endpoints, edges without common neighbours and graphs without
+    edges: a star K_{1,50} (C(50, 3) 3-stars and C(50, 2) wedges, edge- and
+    vertex-induced, and nothing else), one edge, and 20 isolated vertices."""
+    import math
+    star = np.array([(0, i) for i in range(1, 51)], dtype=np.int32)
+    want_star = {"wedge": math.comb(50, 2), "3-star": math.comb(50, 3), "4-path": 0, "tailed-triangle": 0,
+                 "diamond": 0, "4-cycle": 0}
+    for n, pairs, want in [(51, star, want_star), (2, np.array([(0, 1)], dtype=np.int32), None),
+                           (20, np.zeros((0, 2), dtype=np.int32), None)]:
+        g, _ = load(S, O, synth, ctx, n, pairs)
+        for name in ["wedge", "3-star", "4-path", "tailed-triangle", "diamond", "4-cycle"]:
+            for induced in (False, True):
+                p = S.sgpm_pattern_create(ctx, *synth.pattern(name), induced)
+                got = S.sgpm_exact_count(ctx, g, p)
+                assert got == (want[name] if want else 0), (n, name, induced, got)
+                S.sgpm_pattern_free(p)
+        S.sgpm_graph_free(g)
+
+
 @pytest.mark.parametrize("name,c", [("triangle", 4), ("4-cycle", 3), ("diamond", 2)])
 def test_gs_estimate_matches_oracle(S, O, synth, ctx, cl, name, c):
     g, og = cl
