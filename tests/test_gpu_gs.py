@@ -167,15 +167,16 @@ def test_closed_forms_at_wave_width(S, O, synth, ctx, induced):
 def test_closed_forms_degenerate_graphs(S, O, synth, ctx):
     """Degree-1 endpoints, edges without common neighbours and graphs without
     edges: a star K_{1,50} (C(50, 3) 3-stars and C(50, 2) wedges, edge- and
-    vertex-induced, and nothing else), one edge, and 20 isolated vertices."""
+    vertex-induced, and nothing else), one edge, and 20 isolated vertices; the
+    clique bitmaps on the same graphs (no cliques)."""
     import math
     star = np.array([(0, i) for i in range(1, 51)], dtype=np.int32)
     want_star = {"wedge": math.comb(50, 2), "3-star": math.comb(50, 3), "4-path": 0, "tailed-triangle": 0,
-                 "diamond": 0, "4-cycle": 0}
+                 "diamond": 0, "4-cycle": 0, "4-clique": 0, "5-clique": 0, "6-clique": 0}
     for n, pairs, want in [(51, star, want_star), (2, np.array([(0, 1)], dtype=np.int32), None),
                            (20, np.zeros((0, 2), dtype=np.int32), None)]:
         g, _ = load(S, O, synth, ctx, n, pairs)
-        for name in ["wedge", "3-star", "4-path", "tailed-triangle", "diamond", "4-cycle"]:
+        for name in want_star:
             for induced in (False, True):
                 p = S.sgpm_pattern_create(ctx, *synth.pattern(name), induced)
                 got = S.sgpm_exact_count(ctx, g, p)
