@@ -91,8 +91,7 @@ sgpm_status sparsify(sgpm_ctx* c, sgpm_graph* g, uint32_t colours, uint64_t seed
     int64_t arcs = 0, edges = 0;
     if (nt > 0) {
         HIP_TRY(c, gs_arc_counts(dg, colp, colours, seed, rep, tk, tl, c->st));
-        HIP_TRY(c, exclusive_scan(tk, nt, tko, scan, c->st));
-        HIP_TRY(c, exclusive_scan(tl, nt, tlo, scan, c->st));
+        HIP_TRY(c, exclusive_scan_pair(tk, tl, nt, tko, tlo, scan, c->st));
         HIP_TRY(c, hipMemcpyAsync(&arcs, tko + nt, sizeof(int64_t), hipMemcpyDeviceToHost, c->st));
         HIP_TRY(c, hipMemcpyAsync(&edges, tlo + nt, sizeof(int64_t), hipMemcpyDeviceToHost, c->st));
         HIP_TRY(c, hipStreamSynchronize(c->st));

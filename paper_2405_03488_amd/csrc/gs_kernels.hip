@@ -331,6 +331,47 @@ __global__ __launch_bounds__(256) void scan_finish(const int64_t* __restrict__ i
     }
 }
 
+// Exclusive scans of two arrays of n <= SCAN_PAIR_MAX entries by one block
+// (out[n] = the total): thread i sums a contiguous run of each array, the
+// run sums are scanned across the block, then every run is written out.
+constexpr int64_t SCAN_PAIR_MAX = 1 << 16;
+
+__global__ __launch_bounds__(1024) void scan_pair_kernel(const int64_t* __restrict__ a, const int64_t* __restrict__ b,
+                                                         int64_t n, int64_t* __restrict__ oa, int64_t* __restrict__ ob) {
+    __shared__ int64_t pa[1024], pb[1024];
+    const int64_t per = (n + 1023) / 1024;
+    const int64_t i0 = (int64_t)threadIdx.x * per, i1 = i0 + per < n ? i0 + per : n;
+    int64_t sa = 0, sb = 0;
+    for (int64_t i = i0; i < i1; ++i) {
+        sa += a[i];
+        sb += b[i];
+    }
+    pa[threadIdx.x] = sa;
+    pb[threadIdx.x] = sb;
+    __syncthreads();
+    // Hillis-Steele inclusive scan of the run sums
+    for (int st = 1; st < 1024; st <<= 1) {
+        const int64_t xa = (int)threadIdx.x >= st ? pa[threadIdx.x - st] : 0;
+        const int64_t xb = (int)threadIdx.x >= st ? pb[threadIdx.x - st] : 0;
+        __syncthreads();
+        pa[threadIdx.x] += xa;
+        pb[threadIdx.x] += xb;
+        __syncthreads();
+    }
+    int64_t ra = pa[threadIdx.x] - sa, rb = pb[threadIdx.x] - sb;
+    for (int64_t i = i0; i < i1; ++i) {
+        const int64_t va = a[i], vb = b[i];
+        oa[i] = ra;
+        ob[i] = rb;
+        ra += va;
+        rb += vb;
+    }
+    if (threadIdx.x == 1023) {
+        oa[n] = pa[1023];
+        ob[n] = pb[1023];
+    }
+}
+
 // ------------------------------------------------------------------ exact count
 __device__ __forceinline__ int32_t grfl(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 
@@ -1067,6 +1108,16 @@ hipError_t max_degree(const int64_t* off, int64_t n, unsigned long long* out, hi
 }
 
 int64_t scan_scratch_words(int64_t n) { return (n + SCAN_TILE - 1) / SCAN_TILE + 1; }
+
+hipError_t exclusive_scan_pair(const int64_t* a, const int64_t* b, int64_t n, int64_t* oa, int64_t* ob,
+                               int64_t* scratch, hipStream_t st) {
+    if (n > SCAN_PAIR_MAX) {
+        hipError_t e = exclusive_scan(a, n, oa, scratch, st);
+        return e != hipSuccess ? e : exclusive_scan(b, n, ob, scratch, st);
+    }
+    hipLaunchKernelGGL(scan_pair_kernel, dim3(1), dim3(1024), 0, st, a, b, n, oa, ob);
+    return hipGetLastError();
+}
 
 hipError_t exclusive_scan(const int64_t* in, int64_t n, int64_t* out, int64_t* scratch, hipStream_t st) {
     const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;

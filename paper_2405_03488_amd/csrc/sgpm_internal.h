@@ -184,6 +184,10 @@ hipError_t gs_arc_write(const DGraph& g, const uint8_t* col, uint32_t c, uint64_
                         int64_t* rstart, int64_t* rlow, int64_t* noff, int64_t* neoff, hipStream_t st);
 int64_t scan_scratch_words(int64_t n);
 hipError_t exclusive_scan(const int64_t* in, int64_t n, int64_t* out, int64_t* scratch, hipStream_t st);
+// exclusive scans of a and b (n entries each, totals at oa[n], ob[n]); one
+// block for n up to 65,536, else exclusive_scan twice
+hipError_t exclusive_scan_pair(const int64_t* a, const int64_t* b, int64_t n, int64_t* oa, int64_t* ob,
+                               int64_t* scratch, hipStream_t st);
 hipError_t max_degree(const int64_t* off, int64_t n, unsigned long long* out, hipStream_t st);
 // Work split of the count kernels: a wave (or lane group) takes ticket t from
 // one counter and counts first edges [ticket_start(t), ticket_start(t + 1)).
